@@ -1,0 +1,342 @@
+"""Oracle for the BBC large-k IVF query path (arxiv 2604.01960).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's
+CPU-baseline leg use this package.  It shares no code with the GPU library
+(``paper_2604_01960_amd``) and never imports it.
+
+The arithmetic lives in ``oracle.c`` (plain C, canonical float32 order, see
+its header); this module only marshals numpy arrays through ctypes and
+composes the index build from the C steps.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+from typing import Dict, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+CFLAGS = ["-O2", "-ffp-contract=off", "-fno-fast-math", "-fopenmp", "-fPIC", "-shared",
+          "-std=c11", "-Wall", "-Wno-unknown-pragmas"]
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c into liboracle.so (gcc, canonical float flags)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+                build()
+            L = C.CDLL(_LIB_PATH)
+            vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
+            L.orc_canon_l2.restype = f32
+            L.orc_canon_l2.argtypes = [vp, vp, i32]
+            L.orc_canon_ip.restype = f32
+            L.orc_canon_ip.argtypes = [vp, vp, i32]
+            L.orc_canon_l2_batch.argtypes = [vp, vp, i64, i32, vp]
+            L.orc_topk_sort.argtypes = [vp, vp, i64, i64, vp, vp]
+            L.orc_update.restype = i32
+            L.orc_update.argtypes = [vp, i32, i64]
+            L.orc_cell_of.restype = i32
+            L.orc_cell_of.argtypes = [f32, f32, f32]
+            L.orc_codebook.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
+            L.orc_bucket_of.restype = i32
+            L.orc_bucket_of.argtypes = [f32, f32, f32, vp]
+            L.orc_collect_bbc.argtypes = [vp, vp, vp, i32, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_probe.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp, vp]
+            L.orc_pq_lut.argtypes = [vp, vp, i32, i32, i32, vp, vp]
+            L.orc_pq_key.restype = f32
+            L.orc_pq_key.argtypes = [vp, vp, i32, i32]
+            L.orc_pq_keys.argtypes = [vp, vp, i64, i32, i32, vp]
+            L.orc_kmeans_assign.argtypes = [vp, vp, i64, i32, vp, i32, vp]
+            L.orc_kmeans_update.argtypes = [vp, vp, i64, i32, vp, i32, vp]
+            L.orc_kmeans_train.argtypes = [vp, i32, vp, i64, vp, i32, i32, vp]
+            L.orc_pq_train.argtypes = [vp, i64, i32, i32, i32, vp, i32, vp]
+            L.orc_pq_encode.argtypes = [vp, i64, i32, i32, i32, vp, vp]
+            L.orc_residuals.argtypes = [vp, vp, i64, i32, vp, vp, vp]
+            L.orc_search_pq.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, i32, vp, vp, i32,
+                                        vp, i64, vp, vp, f64, vp, vp, vp, vp,
+                                        vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_exact_knn64.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp]
+            L.orc_num_threads.restype = C.c_int
+            _lib = L
+    return _lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _i64(a):
+    return np.ascontiguousarray(a, dtype=np.int64)
+
+
+def _i32(a):
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+def _check(rc: int, what: str):
+    if rc != 0:
+        raise RuntimeError(f"oracle {what} failed with status {rc}")
+
+
+def num_threads() -> int:
+    return int(lib().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# canonical arithmetic
+# --------------------------------------------------------------------------
+
+def canon_l2(a, b) -> np.float32:
+    a, b = _f32(a), _f32(b)
+    return np.float32(lib().orc_canon_l2(_p(a), _p(b), a.shape[0]))
+
+
+def canon_ip(a, b) -> np.float32:
+    a, b = _f32(a), _f32(b)
+    return np.float32(lib().orc_canon_ip(_p(a), _p(b), a.shape[0]))
+
+
+def canon_l2_batch(q, x) -> np.ndarray:
+    q, x = _f32(q), _f32(x)
+    out = np.empty(x.shape[0], dtype=np.float32)
+    lib().orc_canon_l2_batch(_p(q), _p(x), x.shape[0], x.shape[1], _p(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# collector
+# --------------------------------------------------------------------------
+
+def topk_sort(keys, ids, kc):
+    """First kc of (key, id) ascending."""
+    keys, ids = _f32(keys), _i64(ids)
+    kc = min(int(kc), keys.shape[0])
+    ok = np.empty(kc, np.float32)
+    oi = np.empty(kc, np.int64)
+    _check(lib().orc_topk_sort(_p(keys), _p(ids), keys.shape[0], kc, _p(ok), _p(oi)), "topk_sort")
+    return ok, oi
+
+
+def update(counts, k) -> int:
+    """Threshold bucket: first bucket where the running count reaches k (m if never)."""
+    c = _i64(counts)
+    return int(lib().orc_update(_p(c), c.shape[0], int(k)))
+
+
+def cell_of(key, dmin, delta) -> int:
+    return int(lib().orc_cell_of(float(np.float32(key)), float(np.float32(dmin)), float(np.float32(delta))))
+
+
+def bucket_of(key, dmin, delta, mp) -> int:
+    mp = np.ascontiguousarray(mp, dtype=np.uint8)
+    return int(lib().orc_bucket_of(float(np.float32(key)), float(np.float32(dmin)), float(np.float32(delta)),
+                                   _p(mp)))
+
+
+def codebook(sample_keys, sample_ids, kc, m):
+    sk, si = _f32(sample_keys), _i64(sample_ids)
+    dmin = np.zeros(1, np.float32)
+    delta = np.zeros(1, np.float32)
+    mp = np.zeros(256, np.uint8)
+    _check(lib().orc_codebook(_p(sk), _p(si), sk.shape[0], int(kc), int(m), _p(dmin), _p(delta), _p(mp)),
+           "codebook")
+    return dmin[0], delta[0], mp
+
+
+def collect_bbc(keys, ids, grp_off, kc, m, nsample=8) -> Dict[str, object]:
+    """Result-buffer workflow over objects grouped by probed list (nearest first)."""
+    keys, ids, grp_off = _f32(keys), _i64(ids), _i64(grp_off)
+    ngrp = grp_off.shape[0] - 1
+    kc = min(int(kc), int(grp_off[-1]))
+    dmin = np.zeros(1, np.float32)
+    delta = np.zeros(1, np.float32)
+    mp = np.zeros(256, np.uint8)
+    tau = np.zeros(1, np.int32)
+    s = np.zeros(1, np.int64)
+    ck = np.empty(max(kc, 1), np.float32)
+    ci = np.empty(max(kc, 1), np.int64)
+    counts = np.zeros(m, np.int64)
+    _check(lib().orc_collect_bbc(_p(keys), _p(ids), _p(grp_off), ngrp, kc, int(m), int(nsample),
+                                 _p(dmin), _p(delta), _p(mp), _p(tau), _p(s), _p(ck), _p(ci), _p(counts)),
+           "collect_bbc")
+    return dict(dmin=dmin[0], delta=delta[0], map=mp, tau=int(tau[0]), s=int(s[0]),
+                cand_keys=ck[:kc], cand_ids=ci[:kc], counts=counts, kc=kc)
+
+
+# --------------------------------------------------------------------------
+# probe / PQ
+# --------------------------------------------------------------------------
+
+def probe(queries, centroids, nprobe, metric=0):
+    q, c = _f32(queries), _f32(centroids)
+    nq = q.shape[0]
+    npb = _i32(np.broadcast_to(np.asarray(nprobe), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(npb)
+    lists = np.empty(off[-1], np.int32)
+    keys = np.empty(off[-1], np.float32)
+    _check(lib().orc_probe(_p(q), nq, q.shape[1], _p(c), c.shape[0], int(metric), _p(npb), _p(off),
+                           _p(lists), _p(keys)), "probe")
+    return lists, keys, off
+
+
+def pq_lut(q, centroid, codebook_arr, M, ksub):
+    q, c, cb = _f32(q), _f32(centroid), _f32(codebook_arr)
+    lut = np.empty((M, ksub), np.float32)
+    lib().orc_pq_lut(_p(q), _p(c), q.shape[0], M, ksub, _p(cb), _p(lut))
+    return lut
+
+
+def pq_keys(lut, codes):
+    """Estimated keys of the rows of codes [n, M] against one table."""
+    lut = _f32(lut)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    M, ksub = lut.shape
+    out = np.empty(codes.shape[0], np.float32)
+    lib().orc_pq_keys(_p(lut), _p(codes), codes.shape[0], M, ksub, _p(out))
+    return out
+
+
+# --------------------------------------------------------------------------
+# index build
+# --------------------------------------------------------------------------
+
+def kmeans_assign(x, c, rows=None):
+    x, c = _f32(x), _f32(c)
+    rows_a = None if rows is None else _i64(rows)
+    n = x.shape[0] if rows is None else rows_a.shape[0]
+    out = np.empty(n, np.int32)
+    lib().orc_kmeans_assign(_p(x), _p(rows_a), n, x.shape[1], _p(c), c.shape[0], _p(out))
+    return out
+
+
+def kmeans_train(x, train_rows, init_pos, nc, iters):
+    x = _f32(x)
+    tr, ip = _i64(train_rows), _i64(init_pos)
+    c = np.empty((nc, x.shape[1]), np.float32)
+    _check(lib().orc_kmeans_train(_p(x), x.shape[1], _p(tr), tr.shape[0], _p(ip), nc, iters, _p(c)),
+           "kmeans_train")
+    return c
+
+
+def residuals(x, rows, c, assign_all):
+    x, c, a = _f32(x), _f32(c), _i32(assign_all)
+    rows_a = None if rows is None else _i64(rows)
+    n = x.shape[0] if rows is None else rows_a.shape[0]
+    out = np.empty((n, x.shape[1]), np.float32)
+    lib().orc_residuals(_p(x), _p(rows_a), n, x.shape[1], _p(c), _p(a), _p(out))
+    return out
+
+
+def pq_train(resid, M, ksub, init_pos, iters):
+    r = _f32(resid)
+    ip = _i64(init_pos)
+    cb = np.empty((M, ksub, r.shape[1] // M), np.float32)
+    _check(lib().orc_pq_train(_p(r), r.shape[0], r.shape[1], M, ksub, _p(ip), iters, _p(cb)), "pq_train")
+    return cb
+
+
+def pq_encode(resid, codebook_arr):
+    r, cb = _f32(resid), _f32(codebook_arr)
+    M, ksub, _ = cb.shape
+    codes = np.empty((r.shape[0], M), np.uint8)
+    lib().orc_pq_encode(_p(r), r.shape[0], r.shape[1], M, ksub, _p(cb), _p(codes))
+    return codes
+
+
+def build_ivf_pq(x, nlist, M, bits, train_rows, init_pos, pq_rows, pq_init, iters=10):
+    """IVF k-means + residual PQ.  Random draws (training rows, seeds) are inputs.
+
+    Returns the index as numpy arrays: lists hold their rows in ascending row
+    order; codes are list-ordered, one code per byte."""
+    x = _f32(x)
+    n, d = x.shape
+    if d % M:
+        raise ValueError("d must be a multiple of M")
+    ksub = 1 << bits
+    cent = kmeans_train(x, train_rows, init_pos, nlist, iters)
+    assign = kmeans_assign(x, cent)
+    order = np.argsort(assign, kind="stable").astype(np.int64)
+    counts = np.bincount(assign, minlength=nlist)
+    list_off = np.zeros(nlist + 1, np.int64)
+    list_off[1:] = np.cumsum(counts)
+    pr = _i64(pq_rows)
+    cb = pq_train(residuals(x, pr, cent, assign), M, ksub, pq_init, iters)
+    codes = pq_encode(residuals(x, order, cent, assign), cb)
+    return dict(kind="pq", n=n, d=d, nlist=nlist, M=M, ksub=ksub, bits=bits, metric=0,
+                centroids=cent, assign=assign, list_off=list_off, list_ids=order,
+                codes=codes, codebook=cb, base=x)
+
+
+# --------------------------------------------------------------------------
+# search
+# --------------------------------------------------------------------------
+
+def search_pq(index, queries, k, nprobe, ratio, debug=False):
+    """Full PQ query path.  Returns dict(ids, dists, counts, off[, debug...])."""
+    q = _f32(queries)
+    nq = q.shape[0]
+    kk = _i32(np.broadcast_to(np.asarray(k), (nq,)))
+    npb = _i32(np.broadcast_to(np.asarray(nprobe), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    ids = np.empty(off[-1], np.int64)
+    dists = np.empty(off[-1], np.float32)
+    counts = np.empty(nq, np.int32)
+    res = dict(ids=ids, dists=dists, counts=counts, off=off)
+    pl = pk = poff = ns = nc = ck = ci = coff = None
+    if debug:
+        poff = np.zeros(nq + 1, np.int64)
+        poff[1:] = np.cumsum(npb)
+        pl = np.empty(poff[-1], np.int32)
+        pk = np.empty(poff[-1], np.float32)
+        ns = np.empty(nq, np.int64)
+        nc = np.empty(nq, np.int64)
+        kcmax = np.ceil(float(ratio) * kk.astype(np.float64)).astype(np.int64)
+        coff = np.zeros(nq + 1, np.int64)
+        coff[1:] = np.cumsum(kcmax)
+        ck = np.empty(coff[-1], np.float32)
+        ci = np.empty(coff[-1], np.int64)
+        res.update(probe_lists=pl, probe_keys=pk, probe_off=poff, n_scanned=ns, n_cand=nc,
+                   cand_keys=ck, cand_ids=ci, cand_off=coff)
+    ix = index
+    _check(lib().orc_search_pq(
+        ix["n"], ix["d"], ix["nlist"], _p(_f32(ix["centroids"])), _p(_i64(ix["list_off"])),
+        _p(_i64(ix["list_ids"])), _p(np.ascontiguousarray(ix["codes"], np.uint8)), ix["M"], ix["ksub"],
+        _p(_f32(ix["codebook"])), _p(_f32(ix["base"])), ix["metric"],
+        _p(q), nq, _p(kk), _p(npb), float(ratio), _p(off), _p(ids), _p(dists), _p(counts),
+        _p(pl), _p(pk), _p(poff), _p(ns), _p(nc), _p(ck), _p(ci), _p(coff)), "search_pq")
+    return res
+
+
+def exact_knn64(base, queries, k, metric=0):
+    """Exact k nearest over all rows in float64, ties by smaller row id."""
+    b, q = _f32(base), _f32(queries)
+    nq = q.shape[0]
+    ids = np.empty((nq, k), np.int64)
+    dists = np.empty((nq, k), np.float64)
+    _check(lib().orc_exact_knn64(_p(b), b.shape[0], b.shape[1], _p(q), nq, int(k), int(metric),
+                                 _p(ids), _p(dists)), "exact_knn64")
+    return ids, dists

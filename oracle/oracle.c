@@ -1,0 +1,695 @@
+/*
+ * Oracle for the large-k IVF query path with a bucket-based result collector
+ * (BBC, arxiv 2604.01960).  TEST INFRASTRUCTURE ONLY: the tests, the smoke
+ * check and the CPU-baseline leg of the benchmark call it; the product path
+ * never does.  It shares no source with the GPU library.
+ *
+ * Plain and slow on purpose: every step is a direct loop, selection is a full
+ * qsort by (key, id), and there is no blocking or fusion.  OpenMP runs
+ * independent queries (or independent rows of the index build) in parallel;
+ * inside one query everything is sequential.
+ *
+ * Arithmetic is IEEE binary32 with round-to-nearest-even, no contraction
+ * (built with -ffp-contract=off, no fast-math), in the fixed operation order
+ * below.  The GPU path implements the same order independently; that is what
+ * makes bit-exact ids possible when thousands of neighbours sit within a
+ * relative distance band of 1e-6 of each other.
+ *
+ *   canon_l2(a,b): vectors padded with zeros to a multiple of 256; 4-element
+ *     chunk c goes to virtual lane c%64 at step c/64; each lane starts at +0
+ *     and for each step and element e=0..3 does  t=(a-b); t=t*t; acc=acc+t;
+ *     lanes are combined by acc[l] = acc[l] + acc[l+off] for off=32,16,..,1.
+ *   canon_ip: same with t = a*b.
+ *   PQ table entry: r = q - c (once per element), then sequentially over the
+ *     sub-vector elements  t = r - C; t = t*t; acc = acc + t.
+ *   PQ key: acc = +0; acc = acc + LUT[m][code_m] for m = 0..M-1.
+ *   Total order: (key, id) with numeric key comparison, ties by smaller id.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <float.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_OK 0
+#define ORC_EINVAL (-1)
+#define ORC_ENOMEM (-2)
+
+#define NLANES 64
+#define KM_SPLIT_UP (1.0f + 1.0f / 1024.0f)
+#define KM_SPLIT_DOWN (1.0f - 1.0f / 1024.0f)
+#define NCELLS 256
+
+/* ------------------------------------------------------------------------ */
+/* Canonical distances                                                       */
+/* ------------------------------------------------------------------------ */
+
+float orc_canon_l2(const float* a, const float* b, int32_t d) {
+  float acc[NLANES];
+  for (int l = 0; l < NLANES; ++l) acc[l] = 0.0f;
+  int nchunk = (d + 3) / 4;
+  for (int c = 0; c < nchunk; ++c) {
+    int lane = c % NLANES;
+    for (int e = 0; e < 4; ++e) {
+      int i = 4 * c + e;
+      float av = i < d ? a[i] : 0.0f;
+      float bv = i < d ? b[i] : 0.0f;
+      float t = av - bv;
+      t = t * t;
+      acc[lane] = acc[lane] + t;
+    }
+  }
+  for (int off = NLANES / 2; off >= 1; off /= 2)
+    for (int l = 0; l < off; ++l) acc[l] = acc[l] + acc[l + off];
+  return acc[0];
+}
+
+float orc_canon_ip(const float* a, const float* b, int32_t d) {
+  float acc[NLANES];
+  for (int l = 0; l < NLANES; ++l) acc[l] = 0.0f;
+  int nchunk = (d + 3) / 4;
+  for (int c = 0; c < nchunk; ++c) {
+    int lane = c % NLANES;
+    for (int e = 0; e < 4; ++e) {
+      int i = 4 * c + e;
+      float av = i < d ? a[i] : 0.0f;
+      float bv = i < d ? b[i] : 0.0f;
+      float t = av * bv;
+      acc[lane] = acc[lane] + t;
+    }
+  }
+  for (int off = NLANES / 2; off >= 1; off /= 2)
+    for (int l = 0; l < off; ++l) acc[l] = acc[l] + acc[l + off];
+  return acc[0];
+}
+
+/* Sequential squared distance over a short sub-vector (PQ sub-spaces). */
+static float seq_l2(const float* a, const float* b, int32_t n) {
+  float acc = 0.0f;
+  for (int e = 0; e < n; ++e) {
+    float t = a[e] - b[e];
+    t = t * t;
+    acc = acc + t;
+  }
+  return acc;
+}
+
+void orc_canon_l2_batch(const float* q, const float* x, int64_t n, int32_t d, float* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_canon_l2(q, x + i * (int64_t)d, d);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total order on (key, id)                                                  */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { float key; int32_t pad; int64_t id; } kv_t;
+
+static int kv_cmp(const void* pa, const void* pb) {
+  const kv_t* a = (const kv_t*)pa;
+  const kv_t* b = (const kv_t*)pb;
+  if (a->key < b->key) return -1;
+  if (a->key > b->key) return 1;
+  if (a->id < b->id) return -1;
+  if (a->id > b->id) return 1;
+  return 0;
+}
+
+typedef struct { double key; int64_t id; } kv64_t;
+
+static int kv64_cmp(const void* pa, const void* pb) {
+  const kv64_t* a = (const kv64_t*)pa;
+  const kv64_t* b = (const kv64_t*)pb;
+  if (a->key < b->key) return -1;
+  if (a->key > b->key) return 1;
+  if (a->id < b->id) return -1;
+  if (a->id > b->id) return 1;
+  return 0;
+}
+
+/* First kc of (key, id) ascending: the definition of what the collector must
+ * return (exact top-kc of the estimated keys). */
+int orc_topk_sort(const float* keys, const int64_t* ids, int64_t n, int64_t kc,
+                  float* out_keys, int64_t* out_ids) {
+  if (kc > n) kc = n;
+  kv_t* v = (kv_t*)malloc(sizeof(kv_t) * (size_t)(n > 0 ? n : 1));
+  if (!v) return ORC_ENOMEM;
+  for (int64_t i = 0; i < n; ++i) { v[i].key = keys[i]; v[i].pad = 0; v[i].id = ids[i]; }
+  qsort(v, (size_t)n, sizeof(kv_t), kv_cmp);
+  for (int64_t i = 0; i < kc; ++i) { out_keys[i] = v[i].key; out_ids[i] = v[i].id; }
+  free(v);
+  return ORC_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Result buffer (bucket-based collector)                                    */
+/* ------------------------------------------------------------------------ */
+
+/* Update: walk buckets in order accumulating their sizes; the threshold
+ * bucket is the first one at which the running total reaches k.  Returns m
+ * (standing for "infinity": accept everything) when the total is below k. */
+int32_t orc_update(const int64_t* counts, int32_t m, int64_t k) {
+  int64_t s = 0;
+  for (int32_t i = 0; i < m; ++i) {
+    s += counts[i];
+    if (s >= k) return i;
+  }
+  return m;
+}
+
+/* Equal-width cell of a key (the floor/clamp of the bucket-id equation). */
+static inline int32_t cell_of(float key, float dmin, float delta) {
+  float t = (key - dmin) / delta;
+  if (t < 0.0f) return 0;
+  if (t >= 255.0f) return 255;
+  return (int32_t)t;
+}
+
+int32_t orc_cell_of(float key, float dmin, float delta) { return cell_of(key, dmin, delta); }
+
+/* Codebook from a sample of estimated keys (the keys of the nearest probed
+ * lists): d_min and d_max are the extremes of the sample's top-kc keys, the
+ * range is cut into 256 equal-width cells, and the cells are mapped onto m
+ * buckets of (about) equal depth with respect to the sample's top-kc keys:
+ * map[e] = min(m-1, floor(m * C_<e / T)) with C_<e the number of those keys
+ * in cells before e and T their count. */
+int orc_codebook(const float* sample_keys, const int64_t* sample_ids, int64_t ns, int64_t kc,
+                 int32_t m, float* dmin_out, float* delta_out, uint8_t* map_out) {
+  if (m < 1 || m > 256) return ORC_EINVAL;
+  int64_t t = kc < ns ? kc : ns;
+  if (t <= 0) {
+    *dmin_out = 0.0f;
+    *delta_out = 1.0f;
+    for (int e = 0; e < NCELLS; ++e) map_out[e] = 0;
+    return ORC_OK;
+  }
+  float* tk = (float*)malloc(sizeof(float) * (size_t)t);
+  int64_t* ti = (int64_t*)malloc(sizeof(int64_t) * (size_t)t);
+  if (!tk || !ti) { free(tk); free(ti); return ORC_ENOMEM; }
+  int rc = orc_topk_sort(sample_keys, sample_ids, ns, t, tk, ti);
+  if (rc) { free(tk); free(ti); return rc; }
+  float dmin = tk[0];
+  float dmax = tk[t - 1];
+  float delta = (dmax - dmin) / 256.0f;
+  if (!(delta > 0.0f)) delta = 1.0f;
+  int64_t hist[NCELLS];
+  for (int e = 0; e < NCELLS; ++e) hist[e] = 0;
+  for (int64_t i = 0; i < t; ++i) hist[cell_of(tk[i], dmin, delta)] += 1;
+  int64_t below = 0;
+  for (int e = 0; e < NCELLS; ++e) {
+    int64_t b = ((int64_t)m * below) / t;
+    map_out[e] = (uint8_t)(b < m - 1 ? b : m - 1);
+    below += hist[e];
+  }
+  *dmin_out = dmin;
+  *delta_out = delta;
+  free(tk);
+  free(ti);
+  return ORC_OK;
+}
+
+int32_t orc_bucket_of(float key, float dmin, float delta, const uint8_t* map) {
+  return map[cell_of(key, dmin, delta)];
+}
+
+/* The result-buffer workflow (Push / Update / Collect) over objects that
+ * arrive grouped by probed list, nearest list first.  The threshold bucket is
+ * refreshed once per list.  Returns the collected candidates (kc of them,
+ * buckets below the threshold in arrival order, then the top-s of the
+ * threshold bucket by (key, id)), the codebook, the final threshold bucket
+ * and s, and the full per-bucket histogram of all keys. */
+int orc_collect_bbc(const float* keys, const int64_t* ids, const int64_t* grp_off, int32_t ngrp,
+                    int64_t kc, int32_t m, int32_t nsample,
+                    float* dmin_out, float* delta_out, uint8_t* map_out,
+                    int32_t* tau_out, int64_t* s_out,
+                    float* cand_keys, int64_t* cand_ids, int64_t* counts_full) {
+  int64_t total = grp_off[ngrp];
+  if (kc > total) kc = total;
+  int32_t ns_grp = nsample < ngrp ? nsample : ngrp;
+  int64_t ns = grp_off[ns_grp];
+  int rc = orc_codebook(keys, ids, ns, kc, m, dmin_out, delta_out, map_out);
+  if (rc) return rc;
+  float dmin = *dmin_out, delta = *delta_out;
+
+  /* buckets: per-bucket linear buffers of (key, id) */
+  int64_t* cap = (int64_t*)calloc((size_t)m, sizeof(int64_t));
+  int64_t* cnt = (int64_t*)calloc((size_t)m, sizeof(int64_t));
+  kv_t** buf = (kv_t**)calloc((size_t)m, sizeof(kv_t*));
+  if (!cap || !cnt || !buf) { free(cap); free(cnt); free(buf); return ORC_ENOMEM; }
+  for (int i = 0; i < m; ++i) counts_full[i] = 0;
+
+  int32_t tau = m; /* infinity */
+  for (int32_t g = 0; g < ngrp; ++g) {
+    for (int64_t i = grp_off[g]; i < grp_off[g + 1]; ++i) {
+      int32_t a = map_out[cell_of(keys[i], dmin, delta)];
+      counts_full[a] += 1;
+      if (a <= tau) { /* Push */
+        if (cnt[a] == cap[a]) {
+          int64_t nc = cap[a] ? 2 * cap[a] : 64;
+          kv_t* nb = (kv_t*)realloc(buf[a], sizeof(kv_t) * (size_t)nc);
+          if (!nb) { rc = ORC_ENOMEM; goto done; }
+          buf[a] = nb;
+          cap[a] = nc;
+        }
+        buf[a][cnt[a]].key = keys[i];
+        buf[a][cnt[a]].pad = 0;
+        buf[a][cnt[a]].id = ids[i];
+        cnt[a] += 1;
+      }
+    }
+    tau = orc_update(cnt, m, kc); /* Update once per list */
+  }
+  {
+    int64_t nres = 0;
+    int32_t upto = tau < m ? tau : m;
+    for (int32_t b = 0; b < upto; ++b)
+      for (int64_t j = 0; j < cnt[b]; ++j) {
+        cand_keys[nres] = buf[b][j].key;
+        cand_ids[nres] = buf[b][j].id;
+        ++nres;
+      }
+    int64_t s = kc - nres;
+    if (tau < m && s > 0) {
+      qsort(buf[tau], (size_t)cnt[tau], sizeof(kv_t), kv_cmp);
+      for (int64_t j = 0; j < s; ++j) {
+        cand_keys[nres] = buf[tau][j].key;
+        cand_ids[nres] = buf[tau][j].id;
+        ++nres;
+      }
+    }
+    *tau_out = tau;
+    *s_out = s;
+  }
+done:
+  for (int i = 0; i < m; ++i) free(buf[i]);
+  free(buf);
+  free(cap);
+  free(cnt);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* IVF probe                                                                 */
+/* ------------------------------------------------------------------------ */
+
+/* Probe key of list j: canonical squared L2 to its centroid, or the negated
+ * canonical inner product for the inner-product metric. */
+static float probe_key(const float* q, const float* c, int32_t d, int32_t metric) {
+  return metric == 0 ? orc_canon_l2(q, c, d) : -orc_canon_ip(q, c, d);
+}
+
+/* The nprobe lists with the smallest (key, list id), in that order. */
+static int probe_one(const float* q, const float* centroids, int32_t nlist, int32_t d,
+                     int32_t metric, int32_t nprobe, int32_t* out_lists, float* out_keys) {
+  kv_t* v = (kv_t*)malloc(sizeof(kv_t) * (size_t)nlist);
+  if (!v) return ORC_ENOMEM;
+  for (int32_t j = 0; j < nlist; ++j) {
+    v[j].key = probe_key(q, centroids + (int64_t)j * d, d, metric);
+    v[j].pad = 0;
+    v[j].id = j;
+  }
+  qsort(v, (size_t)nlist, sizeof(kv_t), kv_cmp);
+  for (int32_t i = 0; i < nprobe; ++i) {
+    out_lists[i] = (int32_t)v[i].id;
+    if (out_keys) out_keys[i] = v[i].key;
+  }
+  free(v);
+  return ORC_OK;
+}
+
+/* Batched probe; out arrays are ragged by probe_off (nq+1 prefix of nprobe). */
+int orc_probe(const float* queries, int64_t nq, int32_t d, const float* centroids, int32_t nlist,
+              int32_t metric, const int32_t* nprobe, const int64_t* probe_off,
+              int32_t* out_lists, float* out_keys) {
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t qi = 0; qi < nq; ++qi) {
+    int rc = probe_one(queries + qi * d, centroids, nlist, d, metric, nprobe[qi],
+                       out_lists + probe_off[qi], out_keys ? out_keys + probe_off[qi] : NULL);
+    if (rc) {
+#pragma omp critical
+      err = rc;
+    }
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* PQ: tables and estimated keys                                             */
+/* ------------------------------------------------------------------------ */
+
+/* Residual table for one (query, list): lut[m][b] over ksub codewords. */
+void orc_pq_lut(const float* q, const float* centroid, int32_t d, int32_t M, int32_t ksub,
+                const float* codebook, float* lut) {
+  int32_t dsub = d / M;
+  float* r = (float*)malloc(sizeof(float) * (size_t)d);
+  for (int i = 0; i < d; ++i) r[i] = q[i] - centroid[i];
+  for (int32_t m = 0; m < M; ++m)
+    for (int32_t b = 0; b < ksub; ++b)
+      lut[(int64_t)m * ksub + b] =
+          seq_l2(r + m * dsub, codebook + ((int64_t)m * ksub + b) * dsub, dsub);
+  free(r);
+}
+
+float orc_pq_key(const float* lut, const uint8_t* code, int32_t M, int32_t ksub) {
+  float acc = 0.0f;
+  for (int32_t m = 0; m < M; ++m) acc = acc + lut[(int64_t)m * ksub + code[m]];
+  return acc;
+}
+
+void orc_pq_keys(const float* lut, const uint8_t* codes, int64_t n, int32_t M, int32_t ksub,
+                 float* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_pq_key(lut, codes + i * M, M, ksub);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Index build: IVF k-means and PQ                                           */
+/* ------------------------------------------------------------------------ */
+
+/* Nearest centroid by canonical squared L2, ties to the smaller list id. */
+void orc_kmeans_assign(const float* x, const int64_t* rows, int64_t n, int32_t d,
+                       const float* c, int32_t nc, int32_t* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const float* xi = x + (rows ? rows[i] : i) * (int64_t)d;
+    int32_t best = 0;
+    float bk = orc_canon_l2(xi, c, d);
+    for (int32_t j = 1; j < nc; ++j) {
+      float kj = orc_canon_l2(xi, c + (int64_t)j * d, d);
+      if (kj < bk) { bk = kj; best = j; }
+    }
+    out[i] = best;
+  }
+}
+
+/* Centroid = mean of its members: float64 sum over members in the given row
+ * order, divided by the member count in float64, rounded once to float32.
+ * Empty clusters are refilled by splitting the largest one (see below). */
+int orc_kmeans_update(const float* x, const int64_t* rows, int64_t n, int32_t d,
+                      const int32_t* assign, int32_t nc, float* c) {
+  double* sum = (double*)calloc((size_t)nc * d, sizeof(double));
+  int64_t* cnt = (int64_t*)calloc((size_t)nc, sizeof(int64_t));
+  if (!sum || !cnt) { free(sum); free(cnt); return ORC_ENOMEM; }
+  for (int64_t i = 0; i < n; ++i) {
+    const float* xi = x + (rows ? rows[i] : i) * (int64_t)d;
+    double* s = sum + (int64_t)assign[i] * d;
+    for (int e = 0; e < d; ++e) s[e] = s[e] + (double)xi[e];
+    cnt[assign[i]] += 1;
+  }
+  for (int32_t j = 0; j < nc; ++j) {
+    if (cnt[j] == 0) continue;
+    for (int e = 0; e < d; ++e)
+      c[(int64_t)j * d + e] = (float)(sum[(int64_t)j * d + e] / (double)cnt[j]);
+  }
+  /* Empty clusters, in ascending id order, each split the currently largest
+   * cluster (ties to the smaller id): the two centroids become the largest
+   * one scaled by (1 + eps) and (1 - eps) on alternating elements, and the
+   * member count is shared between them (floor half to the empty one). */
+  for (int32_t e = 0; e < nc; ++e) {
+    if (cnt[e] != 0) continue;
+    int32_t big = 0;
+    for (int32_t j = 1; j < nc; ++j)
+      if (cnt[j] > cnt[big]) big = j;
+    if (cnt[big] < 2) break;
+    float* ce = c + (int64_t)e * d;
+    float* cb = c + (int64_t)big * d;
+    for (int i = 0; i < d; ++i) {
+      float v = cb[i];
+      if (i % 2 == 0) { ce[i] = v * KM_SPLIT_UP; cb[i] = v * KM_SPLIT_DOWN; }
+      else            { ce[i] = v * KM_SPLIT_DOWN; cb[i] = v * KM_SPLIT_UP; }
+    }
+    cnt[e] = cnt[big] / 2;
+    cnt[big] -= cnt[e];
+  }
+  free(sum);
+  free(cnt);
+  return ORC_OK;
+}
+
+/* Lloyd iterations on the training rows, seeded by the rows at init_pos. */
+int orc_kmeans_train(const float* x, int32_t d, const int64_t* train_rows, int64_t ntrain,
+                     const int64_t* init_pos, int32_t nc, int32_t iters, float* c) {
+  for (int32_t j = 0; j < nc; ++j)
+    memcpy(c + (int64_t)j * d, x + train_rows[init_pos[j]] * (int64_t)d, sizeof(float) * d);
+  int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)ntrain);
+  if (!a) return ORC_ENOMEM;
+  for (int32_t it = 0; it < iters; ++it) {
+    orc_kmeans_assign(x, train_rows, ntrain, d, c, nc, a);
+    int rc = orc_kmeans_update(x, train_rows, ntrain, d, a, nc, c);
+    if (rc) { free(a); return rc; }
+  }
+  free(a);
+  return ORC_OK;
+}
+
+/* Per-sub-space k-means on residual sub-vectors: resid is [n][d] (already
+ * the residuals of the training rows, in ascending row order). */
+int orc_pq_train(const float* resid, int64_t n, int32_t d, int32_t M, int32_t ksub,
+                 const int64_t* init_pos, int32_t iters, float* codebook) {
+  int32_t dsub = d / M;
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int32_t m = 0; m < M; ++m) {
+    float* cb = codebook + (int64_t)m * ksub * dsub;
+    float* sub = (float*)malloc(sizeof(float) * (size_t)n * dsub);
+    int32_t* a = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    double* sum = (double*)malloc(sizeof(double) * (size_t)ksub * dsub);
+    int64_t* cnt = (int64_t*)malloc(sizeof(int64_t) * (size_t)ksub);
+    if (!sub || !a || !sum || !cnt) {
+#pragma omp critical
+      err = ORC_ENOMEM;
+      free(sub); free(a); free(sum); free(cnt);
+      continue;
+    }
+    for (int64_t i = 0; i < n; ++i)
+      memcpy(sub + i * dsub, resid + i * (int64_t)d + (int64_t)m * dsub, sizeof(float) * dsub);
+    for (int32_t b = 0; b < ksub; ++b)
+      memcpy(cb + (int64_t)b * dsub, sub + init_pos[(int64_t)m * ksub + b] * dsub, sizeof(float) * dsub);
+    for (int32_t it = 0; it < iters; ++it) {
+      for (int64_t i = 0; i < n; ++i) {
+        int32_t best = 0;
+        float bk = seq_l2(sub + i * dsub, cb, dsub);
+        for (int32_t b = 1; b < ksub; ++b) {
+          float kb = seq_l2(sub + i * dsub, cb + (int64_t)b * dsub, dsub);
+          if (kb < bk) { bk = kb; best = b; }
+        }
+        a[i] = best;
+      }
+      for (int64_t z = 0; z < (int64_t)ksub * dsub; ++z) sum[z] = 0.0;
+      for (int32_t b = 0; b < ksub; ++b) cnt[b] = 0;
+      for (int64_t i = 0; i < n; ++i) {
+        for (int e = 0; e < dsub; ++e) sum[(int64_t)a[i] * dsub + e] += (double)sub[i * dsub + e];
+        cnt[a[i]] += 1;
+      }
+      for (int32_t b = 0; b < ksub; ++b) {
+        if (cnt[b] == 0) continue;
+        for (int e = 0; e < dsub; ++e)
+          cb[(int64_t)b * dsub + e] = (float)(sum[(int64_t)b * dsub + e] / (double)cnt[b]);
+      }
+    }
+    free(sub); free(a); free(sum); free(cnt);
+  }
+  return err;
+}
+
+/* Code of each residual: per sub-space, the nearest codeword (sequential
+ * sub-vector distance), ties to the smaller codeword index. */
+void orc_pq_encode(const float* resid, int64_t n, int32_t d, int32_t M, int32_t ksub,
+                   const float* codebook, uint8_t* codes) {
+  int32_t dsub = d / M;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int32_t m = 0; m < M; ++m) {
+      const float* r = resid + i * (int64_t)d + (int64_t)m * dsub;
+      const float* cb = codebook + (int64_t)m * ksub * dsub;
+      int32_t best = 0;
+      float bk = seq_l2(r, cb, dsub);
+      for (int32_t b = 1; b < ksub; ++b) {
+        float kb = seq_l2(r, cb + (int64_t)b * dsub, dsub);
+        if (kb < bk) { bk = kb; best = b; }
+      }
+      codes[i * M + m] = (uint8_t)best;
+    }
+  }
+}
+
+/* Residuals x[row] - c[assign[row]] for the given rows (elementwise float32). */
+void orc_residuals(const float* x, const int64_t* rows, int64_t n, int32_t d,
+                   const float* c, const int32_t* assign_all, float* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t row = rows ? rows[i] : i;
+    const float* xi = x + row * (int64_t)d;
+    const float* ci = c + (int64_t)assign_all[row] * d;
+    for (int e = 0; e < d; ++e) out[i * (int64_t)d + e] = xi[e] - ci[e];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Search, PQ flavour (probe -> tables and keys -> collect -> re-rank)       */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int64_t n; int32_t d; int32_t nlist;
+  const float* centroids;      /* [nlist][d] */
+  const int64_t* list_off;     /* [nlist+1] */
+  const int64_t* list_ids;     /* [n] original row of each list slot */
+  const uint8_t* codes;        /* [n][M], list order, one code per byte */
+  int32_t M; int32_t ksub;
+  const float* codebook;       /* [M][ksub][d/M] */
+  const float* base;           /* [n][d] original row order */
+  int32_t metric;              /* 0 = L2 (PQ path supports L2 only) */
+} orc_pq_index;
+
+/* Optional per-query intermediate outputs (any pointer may be NULL). */
+typedef struct {
+  int32_t* probe_lists;   /* ragged by probe_off */
+  float* probe_keys;      /* ragged by probe_off */
+  const int64_t* probe_off;
+  int64_t* n_scanned;     /* [nq] S */
+  int64_t* n_cand;        /* [nq] K_c */
+  float* cand_keys;       /* ragged by cand_off: the K_c candidates, (key,id) ascending */
+  int64_t* cand_ids;
+  const int64_t* cand_off;
+} orc_pq_debug;
+
+static int search_pq_one(const orc_pq_index* ix, const float* q, int32_t k, int32_t nprobe,
+                         double ratio, int64_t* out_ids, float* out_dists, int32_t* out_count,
+                         const orc_pq_debug* dbg, int64_t qi) {
+  const int32_t d = ix->d;
+  int32_t* lists = (int32_t*)malloc(sizeof(int32_t) * (size_t)nprobe);
+  float* lkeys = (float*)malloc(sizeof(float) * (size_t)nprobe);
+  float* lut = (float*)malloc(sizeof(float) * (size_t)ix->M * ix->ksub);
+  if (!lists || !lkeys || !lut) { free(lists); free(lkeys); free(lut); return ORC_ENOMEM; }
+  int rc = probe_one(q, ix->centroids, ix->nlist, d, ix->metric, nprobe, lists, lkeys);
+  if (rc) { free(lists); free(lkeys); free(lut); return rc; }
+  if (dbg && dbg->probe_lists)
+    for (int32_t i = 0; i < nprobe; ++i) dbg->probe_lists[dbg->probe_off[qi] + i] = lists[i];
+  if (dbg && dbg->probe_keys)
+    for (int32_t i = 0; i < nprobe; ++i) dbg->probe_keys[dbg->probe_off[qi] + i] = lkeys[i];
+
+  int64_t S = 0;
+  for (int32_t i = 0; i < nprobe; ++i) S += ix->list_off[lists[i] + 1] - ix->list_off[lists[i]];
+  kv_t* est = (kv_t*)malloc(sizeof(kv_t) * (size_t)(S > 0 ? S : 1));
+  if (!est) { free(lists); free(lkeys); free(lut); return ORC_ENOMEM; }
+  int64_t w = 0;
+  for (int32_t i = 0; i < nprobe; ++i) {
+    int32_t j = lists[i];
+    orc_pq_lut(q, ix->centroids + (int64_t)j * d, d, ix->M, ix->ksub, ix->codebook, lut);
+    for (int64_t p = ix->list_off[j]; p < ix->list_off[j + 1]; ++p) {
+      est[w].key = orc_pq_key(lut, ix->codes + p * ix->M, ix->M, ix->ksub);
+      est[w].pad = 0;
+      est[w].id = ix->list_ids[p];
+      ++w;
+    }
+  }
+  int64_t kc = (int64_t)ceil(ratio * (double)k);
+  if (kc > S) kc = S;
+  qsort(est, (size_t)S, sizeof(kv_t), kv_cmp);
+  if (dbg && dbg->n_scanned) dbg->n_scanned[qi] = S;
+  if (dbg && dbg->n_cand) dbg->n_cand[qi] = kc;
+  if (dbg && dbg->cand_keys)
+    for (int64_t i = 0; i < kc; ++i) {
+      dbg->cand_keys[dbg->cand_off[qi] + i] = est[i].key;
+      dbg->cand_ids[dbg->cand_off[qi] + i] = est[i].id;
+    }
+
+  /* exact re-rank of the kc candidates */
+  for (int64_t i = 0; i < kc; ++i) {
+    const float* x = ix->base + est[i].id * (int64_t)d;
+    est[i].key = ix->metric == 0 ? orc_canon_l2(q, x, d) : -orc_canon_ip(q, x, d);
+  }
+  qsort(est, (size_t)kc, sizeof(kv_t), kv_cmp);
+  int64_t cnt = kc < k ? kc : k;
+  for (int64_t i = 0; i < k; ++i) {
+    if (i < cnt) {
+      out_ids[i] = est[i].id;
+      out_dists[i] = ix->metric == 0 ? est[i].key : -est[i].key;
+    } else {
+      out_ids[i] = -1;
+      out_dists[i] = ix->metric == 0 ? INFINITY : -INFINITY;
+    }
+  }
+  *out_count = (int32_t)cnt;
+  free(est);
+  free(lists);
+  free(lkeys);
+  free(lut);
+  return ORC_OK;
+}
+
+int orc_search_pq(int64_t n, int32_t d, int32_t nlist, const float* centroids,
+                  const int64_t* list_off, const int64_t* list_ids, const uint8_t* codes,
+                  int32_t M, int32_t ksub, const float* codebook, const float* base, int32_t metric,
+                  const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                  double ratio, const int64_t* out_off, int64_t* out_ids, float* out_dists,
+                  int32_t* out_counts,
+                  int32_t* dbg_probe_lists, float* dbg_probe_keys, const int64_t* dbg_probe_off,
+                  int64_t* dbg_n_scanned, int64_t* dbg_n_cand,
+                  float* dbg_cand_keys, int64_t* dbg_cand_ids, const int64_t* dbg_cand_off) {
+  orc_pq_index ix = {n, d, nlist, centroids, list_off, list_ids, codes, M, ksub, codebook, base, metric};
+  orc_pq_debug dbg = {dbg_probe_lists, dbg_probe_keys, dbg_probe_off, dbg_n_scanned, dbg_n_cand,
+                      dbg_cand_keys, dbg_cand_ids, dbg_cand_off};
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t qi = 0; qi < nq; ++qi) {
+    int rc = search_pq_one(&ix, queries + qi * d, k[qi], nprobe[qi], ratio,
+                           out_ids + out_off[qi], out_dists + out_off[qi], out_counts + qi,
+                           &dbg, qi);
+    if (rc) {
+#pragma omp critical
+      err = rc;
+    }
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ground truth: exact float64 k nearest over all rows                       */
+/* ------------------------------------------------------------------------ */
+
+int orc_exact_knn64(const float* base, int64_t n, int32_t d, const float* queries, int64_t nq,
+                    int32_t k, int32_t metric, int64_t* out_ids, double* out_dists) {
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t qi = 0; qi < nq; ++qi) {
+    kv64_t* v = (kv64_t*)malloc(sizeof(kv64_t) * (size_t)n);
+    if (!v) {
+#pragma omp critical
+      err = ORC_ENOMEM;
+      continue;
+    }
+    const float* q = queries + qi * d;
+    for (int64_t i = 0; i < n; ++i) {
+      const float* x = base + i * (int64_t)d;
+      double acc = 0.0;
+      if (metric == 0) {
+        for (int e = 0; e < d; ++e) { double t = (double)x[e] - (double)q[e]; acc += t * t; }
+      } else {
+        for (int e = 0; e < d; ++e) acc += (double)x[e] * (double)q[e];
+        acc = -acc;
+      }
+      v[i].key = acc;
+      v[i].id = i;
+    }
+    qsort(v, (size_t)n, sizeof(kv64_t), kv64_cmp);
+    int32_t kk = k < n ? k : (int32_t)n;
+    for (int32_t i = 0; i < k; ++i) {
+      out_ids[qi * k + i] = i < kk ? v[i].id : -1;
+      out_dists[qi * k + i] = i < kk ? (metric == 0 ? v[i].key : -v[i].key) : NAN;
+    }
+    free(v);
+  }
+  return err;
+}
+
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
