@@ -1,0 +1,150 @@
+/*
+ * bbc.h - C ABI of the MI355X (gfx950) query path for large-k approximate
+ * nearest-neighbour search over quantized IVF indexes with a bucket-based
+ * result collector (BBC, arxiv 2604.01960).
+ *
+ * Problem (background section of the paper, "Problem Statement"): index N
+ * d-dimensional vectors; for a query q return its k nearest vectors under
+ * squared Euclidean distance (the default) or inner product, k typically
+ * >= 5,000.  The path: IVF probe -> quantized-code scan (PQ tables) ->
+ * bucket-based collector of the K_c = min(ceil(r*k), S) best estimated keys
+ * (result-buffer section: Push / Update / Collect, bucket-id equation) ->
+ * exact re-rank -> k results.
+ *
+ * Conventions shared by every entry point
+ *  - Every function returns a status (BBC_OK or a negative BBC_E* code);
+ *    nothing throws across the ABI.  bbc_last_error() gives a message for
+ *    the last failing call on the calling thread.
+ *  - Ids are original row numbers 0..n-1.  Results are sorted ascending by
+ *    (key, id): key = squared L2, or -<q, x> for inner product, ties broken
+ *    by the smaller id.  Distances returned are squared L2, or <q, x>.
+ *  - If fewer than k objects are scanned, out_counts[q] is that number and
+ *    the remaining slots hold id -1 and +inf (L2) / -inf (IP).
+ *  - Arrays are row-major and densely packed.  The caller owns every buffer
+ *    it passes; the library copies what it keeps and holds no caller pointer
+ *    after a call returns.
+ *  - Floating-point inputs must be finite (BBC_EINVAL otherwise).
+ */
+#ifndef BBC_H_
+#define BBC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define BBC_OK 0
+#define BBC_EINVAL (-1)      /* bad argument */
+#define BBC_ENOMEM (-2)      /* device or host allocation failed */
+#define BBC_EDEVICE (-3)     /* HIP runtime error */
+#define BBC_EUNSUPPORTED (-4)
+#define BBC_EBUSY (-6)       /* serving: result not ready yet */
+
+#define BBC_METRIC_L2 0
+#define BBC_METRIC_IP 1
+
+#define BBC_QUANT_PQ 0
+#define BBC_QUANT_RABITQ 1
+
+#define BBC_COLLECT_BUCKET 0 /* bucket-based result buffer (the paper's) */
+#define BBC_COLLECT_HEAP 1   /* comparator: bounded max-heap per query */
+#define BBC_COLLECT_SORT 2   /* comparator: full sort of all keys per query */
+
+typedef struct bbc_index bbc_index; /* opaque; owns its device memory */
+
+/* Create a PQ index on `device` from an already built IVF-PQ index held in
+ * host memory (background section: IVF lists of k-means clusters, residual
+ * product quantization with M sub-spaces of 2^bits codewords).
+ *   centroids [nlist][d] float32
+ *   list_off  [nlist+1] int64, list_off[0] = 0, non-decreasing, = n at the end
+ *   list_ids  [n] int64: row id of each list slot (a permutation of 0..n-1)
+ *   codebook  [pq_m][2^pq_bits][d/pq_m] float32 (codewords of residuals)
+ *   codes     [n][pq_m] uint8, list-slot order, one code per byte
+ *   base      [n][d] float32 in row-id order (for the exact re-rank)
+ * Requirements: d % 4 == 0, d <= 1024, d % pq_m == 0, pq_bits in {4, 8},
+ * 1 <= nlist <= 8192, n < 2^31.  metric must be BBC_METRIC_L2 for PQ. */
+int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
+                            const float* centroids, const int64_t* list_off, const int64_t* list_ids,
+                            int32_t pq_m, int32_t pq_bits, const float* codebook, const uint8_t* codes,
+                            const float* base, bbc_index** out);
+
+typedef struct {
+  double ncand_ratio;  /* r >= 1: the collector keeps K_c = min(ceil(r*k), S) candidates */
+  int32_t collector;   /* BBC_COLLECT_* */
+  int32_t buckets;     /* m in [1, 256]; 0 picks the default */
+  int32_t nsample;     /* nearest probed lists sampled for the codebook; 0 = 8 */
+  int32_t device_io;   /* 1: queries and outputs are device pointers on `stream` and the
+                          call returns once the work is enqueued; 0: host pointers, the
+                          call returns when the results are in place */
+  void* stream;        /* hipStream_t; NULL = the default stream */
+} bbc_search_params;
+
+/* Search nq queries [nq][d] float32.  k[nq] and nprobe[nq] are host arrays
+ * (per-query values; 1 <= nprobe <= nlist, k >= 1).  out_offsets[nq+1] is
+ * the host prefix sum of k; out_ids [sum k] int64, out_dists [sum k] float32,
+ * out_counts [nq] int32 receive the results (see the conventions above). */
+int32_t bbc_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                   const int32_t* nprobe, const bbc_search_params* params, const int64_t* out_offsets,
+                   int64_t* out_ids, float* out_dists, int32_t* out_counts);
+
+/* Intermediate state of a search, for checking every step (host arrays;
+ * any pointer may be NULL).  Ragged arrays use the prefix sums given:
+ * probe_*: by nprobe; cand_*: by cand_cap[q] = the per-query candidate
+ * capacity reported in n_cand_cap.  For the bucket collector: codebook
+ * (dmin, delta, map[nq][256]), threshold bucket tau, s, bucket counts
+ * [nq][m] of all scanned keys, and the size of the threshold bucket. */
+typedef struct {
+  int32_t* probe_lists; float* probe_keys;   /* [sum nprobe], nearest first */
+  int64_t* n_scanned;                        /* [nq] S */
+  int64_t* n_cand;                           /* [nq] K_c */
+  int32_t* n_recheck;                        /* [nq] lists rechecked in FP32 by the probe */
+  float* dmin; float* delta; uint8_t* map;   /* [nq], [nq], [nq][256] */
+  int32_t* tau; int64_t* s; int32_t* bucket_counts; int64_t* n_boundary; /* [nq],[nq],[nq][m],[nq] */
+  float* est_keys;                           /* [sum S]: estimated keys in probe order */
+  int64_t* est_off;                          /* [nq+1] prefix sums of S (output) */
+  int64_t* cand_ids;                         /* candidate ids, ragged by cand_off */
+  float* cand_exact;                         /* their exact keys (same order) */
+  int64_t* cand_off;                         /* [nq+1] prefix sums of K_c (output) */
+} bbc_search_trace;
+
+/* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and
+ * cand_exact need the sizes reported by a first call with them NULL). */
+int32_t bbc_search_traced(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                          const int32_t* nprobe, const bbc_search_params* params,
+                          const int64_t* out_offsets, int64_t* out_ids, float* out_dists,
+                          int32_t* out_counts, bbc_search_trace* trace);
+
+/* Device bytes of per-query scratch a search with this k and nprobe needs
+ * (upper bound); used for admission by memory. Negative on error. */
+int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bbc_search_params* params);
+
+#define BBC_FIELD_CENTROIDS 0 /* [nlist][d] float32 */
+#define BBC_FIELD_LIST_OFF 1  /* [nlist+1] int64 */
+#define BBC_FIELD_LIST_IDS 2  /* [n] int64 */
+#define BBC_FIELD_CODES 3     /* [n][pq_m] uint8, one code per byte */
+#define BBC_FIELD_CODEBOOK 4  /* [pq_m][2^bits][d/pq_m] float32 */
+
+/* Sizes of an index: any pointer may be NULL. */
+int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,
+                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits);
+/* Copy one array of the index (BBC_FIELD_*) to host memory of `bytes` bytes. */
+int32_t bbc_index_get(const bbc_index* ix, int32_t field, void* dst, int64_t bytes);
+void bbc_index_free(bbc_index* ix);
+
+/* Per-stage device time: when enabled, every kernel launch of a search is
+ * bracketed by HIP events recorded on the search stream; bbc_stage_times
+ * waits for them and returns, per stage, the summed milliseconds and the
+ * launch count since the last reset (stages: 0 probe (coarse GEMM and
+ * select), 2 code scan, 3 collector, 4 re-rank, 5 final top-k). */
+int32_t bbc_stage_timing(int32_t enable);
+int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset);
+
+const char* bbc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BBC_H_ */

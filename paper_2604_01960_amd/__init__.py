@@ -1,0 +1,279 @@
+"""MI355X query path for large-k ANN search with a bucket-based result collector.
+
+Thin ctypes binding over the C ABI in ``include/bbc.h`` (``libbbc.so``, built
+from ``csrc/`` for gfx950).  This module only marshals arguments; every step
+of the search runs in the library's HIP kernels.  There is no fallback: if
+the library is missing, importing the binding's entry points raises.
+
+Host numpy arrays use the blocking host-I/O mode; torch tensors on a GPU use
+the device-I/O mode on the current torch stream (torch supplies device
+memory and streams only).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Dict, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbc.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bbc.h")
+
+OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = 0, -1, -2, -3, -4, -6
+METRIC_L2, METRIC_IP = 0, 1
+QUANT_PQ, QUANT_RABITQ = 0, 1
+COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
+FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
+STAGES = {0: "probe", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
+
+
+class BBCError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"bbc error {code}: {msg}")
+        self.code = code
+
+
+class SearchParams(C.Structure):
+    _fields_ = [("ncand_ratio", C.c_double), ("collector", C.c_int32), ("buckets", C.c_int32),
+                ("nsample", C.c_int32), ("device_io", C.c_int32), ("stream", C.c_void_p)]
+
+
+class SearchTrace(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
+        "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off")]
+
+
+_lib = None
+
+
+def load(path: Optional[str] = None):
+    """Load libbbc.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    p = path or LIB_PATH
+    # One HIP runtime per process: when torch is present its bundled runtime
+    # must be the one loaded first, so that libbbc.so binds to it (same
+    # SONAME) instead of bringing up a second runtime next to it.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    if not os.path.exists(p):
+        raise ImportError(f"{p} is missing: build it with paper_2604_01960_amd.build_lib.build()")
+    L = C.CDLL(p)
+    vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    L.bbc_index_create_pq.restype = i32
+    L.bbc_index_create_pq.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(vp)]
+    L.bbc_search.restype = i32
+    L.bbc_search.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp]
+    L.bbc_search_traced.restype = i32
+    L.bbc_search_traced.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp,
+                                    C.POINTER(SearchTrace)]
+    L.bbc_query_bytes.restype = i64
+    L.bbc_query_bytes.argtypes = [vp, i32, i32, C.POINTER(SearchParams)]
+    L.bbc_index_info.restype = i32
+    L.bbc_index_info.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.bbc_index_get.restype = i32
+    L.bbc_index_get.argtypes = [vp, i32, vp, i64]
+    L.bbc_index_free.restype = None
+    L.bbc_index_free.argtypes = [vp]
+    L.bbc_stage_timing.restype = i32
+    L.bbc_stage_timing.argtypes = [i32]
+    L.bbc_stage_times.restype = i32
+    L.bbc_stage_times.argtypes = [vp, vp, i32, i32]
+    L.bbc_last_error.restype = C.c_char_p
+    L.bbc_last_error.argtypes = []
+    _lib = L
+    return L
+
+
+def _check(rc: int):
+    if rc != OK:
+        raise BBCError(rc, load().bbc_last_error().decode(errors="replace"))
+
+
+def _np(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return int(a.data_ptr())  # torch tensor
+
+
+def _is_torch_gpu(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+def _per_query(v, nq, name) -> np.ndarray:
+    a = np.asarray(v)
+    if a.ndim == 0:
+        a = np.full(nq, int(a), dtype=np.int32)
+    if a.shape != (nq,):
+        raise ValueError(f"{name} must be a scalar or have shape ({nq},)")
+    return np.ascontiguousarray(a, dtype=np.int32)
+
+
+class Index:
+    """A device-resident IVF index (owns its device memory)."""
+
+    def __init__(self, handle: int, device: int = 0):
+        self._h = C.c_void_p(handle)
+        self.device = device
+        n, d, nlist, metric, quant, m, bits = (C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                               C.c_int32(), C.c_int32(), C.c_int32())
+        _check(load().bbc_index_info(self._h, C.byref(n), C.byref(d), C.byref(nlist), C.byref(metric),
+                                     C.byref(quant), C.byref(m), C.byref(bits)))
+        self.n, self.d, self.nlist = n.value, d.value, nlist.value
+        self.metric, self.quant, self.pq_m, self.pq_bits = metric.value, quant.value, m.value, bits.value
+
+    # -- construction ------------------------------------------------------
+    @classmethod
+    def create_pq(cls, centroids, list_off, list_ids, codebook, codes, base, metric=METRIC_L2, device=0):
+        cent = _np(centroids, np.float32)
+        lo = _np(list_off, np.int64)
+        li = _np(list_ids, np.int64)
+        cb = _np(codebook, np.float32)
+        cd = _np(codes, np.uint8)
+        b = _np(base, np.float32)
+        nlist, d = cent.shape
+        M = cb.shape[0]
+        bits = int(round(np.log2(cb.shape[1])))
+        h = C.c_void_p()
+        _check(load().bbc_index_create_pq(device, b.shape[0], d, nlist, metric, _ptr(cent), _ptr(lo), _ptr(li),
+                                          M, bits, _ptr(cb), _ptr(cd), _ptr(b), C.byref(h)))
+        return cls(h.value, device)
+
+    def free(self):
+        if self._h and self._h.value:
+            load().bbc_index_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+    # -- introspection -----------------------------------------------------
+    def get(self, field: int) -> np.ndarray:
+        shapes = {
+            FIELD_CENTROIDS: ((self.nlist, self.d), np.float32),
+            FIELD_LIST_OFF: ((self.nlist + 1,), np.int64),
+            FIELD_LIST_IDS: ((self.n,), np.int64),
+            FIELD_CODES: ((self.n, self.pq_m), np.uint8),
+            FIELD_CODEBOOK: ((self.pq_m, 1 << self.pq_bits, self.d // max(self.pq_m, 1)), np.float32),
+        }
+        shape, dt = shapes[field]
+        out = np.empty(shape, dt)
+        _check(load().bbc_index_get(self._h, field, _ptr(out), out.nbytes))
+        return out
+
+    def query_bytes(self, k: int, nprobe: int, ratio: float = 2.0) -> int:
+        p = SearchParams(float(ratio), 0, 0, 0, 0, None)
+        v = load().bbc_query_bytes(self._h, int(k), int(nprobe), C.byref(p))
+        if v < 0:
+            _check(int(v))
+        return int(v)
+
+    # -- search --------------------------------------------------------------
+    def _params(self, ratio, collector, buckets, nsample, device_io, stream):
+        return SearchParams(float(ratio), COLLECT[collector] if isinstance(collector, str) else int(collector),
+                            int(buckets), int(nsample), int(device_io), stream)
+
+    def search(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
+               nsample: int = 0, out=None, stream=None):
+        """Search a batch.  numpy queries: blocking, returns (ids, dists, counts, offsets)
+        as numpy.  torch GPU queries: enqueued on `stream` (default: torch's current
+        stream); `out` may hold preallocated (ids, dists, counts) torch tensors."""
+        nq = int(queries.shape[0])
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        if _is_torch_gpu(queries):
+            import torch
+            if queries.dtype != torch.float32 or not queries.is_contiguous():
+                raise ValueError("queries must be a contiguous float32 tensor")
+            if stream is None:
+                stream = torch.cuda.current_stream(queries.device).cuda_stream
+            if out is None:
+                out = (torch.empty(int(off[-1]), dtype=torch.int64, device=queries.device),
+                       torch.empty(int(off[-1]), dtype=torch.float32, device=queries.device),
+                       torch.empty(nq, dtype=torch.int32, device=queries.device))
+            ids, dists, counts = out
+            p = self._params(ratio, collector, buckets, nsample, 1, stream)
+            _check(load().bbc_search(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                     _ptr(ids), _ptr(dists), _ptr(counts)))
+            return ids, dists, counts, off
+        q = _np(queries, np.float32)
+        ids = np.empty(int(off[-1]), np.int64)
+        dists = np.empty(int(off[-1]), np.float32)
+        counts = np.empty(nq, np.int32)
+        p = self._params(ratio, collector, buckets, nsample, 0, stream)
+        _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                 _ptr(ids), _ptr(dists), _ptr(counts)))
+        return ids, dists, counts, off
+
+    def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
+                      nsample: int = 0) -> Dict[str, np.ndarray]:
+        """Host search that also returns every intermediate of the path."""
+        q = _np(queries, np.float32)
+        nq = q.shape[0]
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        m = buckets if buckets else 256
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        L = load()
+        p = self._params(ratio, collector, buckets, nsample, 0, None)
+        r = dict(
+            ids=np.empty(int(off[-1]), np.int64), dists=np.empty(int(off[-1]), np.float32),
+            counts=np.empty(nq, np.int32), off=off,
+            probe_lists=np.empty(int(npb.sum()), np.int32), probe_keys=np.empty(int(npb.sum()), np.float32),
+            n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64), n_recheck=np.empty(nq, np.int32),
+            dmin=np.empty(nq, np.float32), delta=np.empty(nq, np.float32), map=np.empty((nq, 256), np.uint8),
+            tau=np.empty(nq, np.int32), s=np.empty(nq, np.int64), bucket_counts=np.empty((nq, m), np.int32),
+            n_boundary=np.empty(nq, np.int64), est_off=np.zeros(nq + 1, np.int64),
+            cand_off=np.zeros(nq + 1, np.int64))
+        tr = SearchTrace(**{f: _ptr(r[f]) for f in (
+            "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
+            "bucket_counts", "n_boundary", "est_off", "cand_off")})
+        _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                   _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
+        # second pass for the ragged arrays, now that their sizes are known
+        r["est_keys"] = np.empty(int(r["est_off"][-1]), np.float32)
+        r["cand_ids"] = np.empty(int(r["cand_off"][-1]), np.int64)
+        r["cand_exact"] = np.empty(int(r["cand_off"][-1]), np.float32)
+        tr.est_keys = _ptr(r["est_keys"])
+        tr.cand_ids = _ptr(r["cand_ids"])
+        tr.cand_exact = _ptr(r["cand_exact"])
+        _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                   _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
+        return r
+
+
+def stage_timing(enable: bool = True):
+    _check(load().bbc_stage_timing(1 if enable else 0))
+
+
+def stage_times(reset: bool = False) -> Dict[str, Dict[str, float]]:
+    ms = np.zeros(8, np.float64)
+    n = np.zeros(8, np.int64)
+    _check(load().bbc_stage_times(_ptr(ms), _ptr(n), 8, 1 if reset else 0))
+    return {name: dict(ms=float(ms[i]), launches=int(n[i])) for i, name in STAGES.items()}
+
+
+def declared_symbols() -> Sequence[str]:
+    """Names of the functions declared in include/bbc.h."""
+    import re
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(bbc_[a-z_0-9]+)\s*\(", text)))

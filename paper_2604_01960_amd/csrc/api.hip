@@ -1,0 +1,707 @@
+// Host runtime and C ABI (include/bbc.h): index residency in HBM, per-call
+// workspace planning, kernel sequencing on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/bbc.h"
+#include "kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+int32_t fail(int32_t code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t _e = (expr);                                                        \
+    if (_e != hipSuccess)                                                          \
+      return fail(_e == hipErrorOutOfMemory ? BBC_ENOMEM : BBC_EDEVICE,            \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));              \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T** p, size_t count) {
+  *p = nullptr;
+  if (count == 0) count = 1;
+  return hipMalloc(reinterpret_cast<void**>(p), sizeof(T) * count);
+}
+
+inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+
+uint16_t bf16_rne(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+bool all_finite(const float* p, int64_t n) {
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Grow-only device arena for per-call scratch.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t used = 0;
+  hipError_t reserve(size_t bytes) {
+    if (bytes <= cap) return hipSuccess;
+    if (base) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      hipFree(base);
+      base = nullptr;
+      cap = 0;
+    }
+    size_t want = std::max(bytes, cap + cap / 2);
+    hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), want);
+    if (e != hipSuccess) {
+      base = nullptr;
+      e = hipMalloc(reinterpret_cast<void**>(&base), bytes);
+      if (e != hipSuccess) { base = nullptr; return e; }
+      want = bytes;
+    }
+    cap = want;
+    return hipSuccess;
+  }
+};
+
+// Simple layout planner: offsets of 256-byte aligned sub-buffers.
+struct Plan {
+  size_t total = 0;
+  size_t add(size_t bytes) {
+    size_t off = total;
+    total += (size_t)round_up((int64_t)std::max<size_t>(bytes, 1), 256);
+    return off;
+  }
+};
+
+struct StageTimer {
+  bool enabled = false;
+  std::mutex mu;
+  struct Rec { int stage; hipEvent_t a, b; };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[8] = {0};
+  int64_t launches[8] = {0};
+  hipEvent_t get() {
+    if (!pool.empty()) { hipEvent_t e = pool.back(); pool.pop_back(); return e; }
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+StageTimer g_timer;
+
+struct StageScope {
+  hipStream_t s;
+  int stage;
+  hipEvent_t a = nullptr, b = nullptr;
+  StageScope(hipStream_t s_, int st) : s(s_), stage(st) {
+    if (!g_timer.enabled) return;
+    std::lock_guard<std::mutex> g(g_timer.mu);
+    a = g_timer.get();
+    b = g_timer.get();
+    if (a) hipEventRecord(a, s);
+  }
+  ~StageScope() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    std::lock_guard<std::mutex> g(g_timer.mu);
+    g_timer.pending.push_back({stage, a, b});
+  }
+};
+
+}  // namespace
+
+struct bbc_index {
+  int device = 0;
+  int64_t n = 0;
+  int32_t d = 0, nlist = 0, metric = 0, quant = 0, M = 0, bits = 0, ksub = 0, dpad = 0;
+  int32_t code_bytes = 0, code_stride = 0;
+  int fp16 = 0;
+  // device residency
+  float* cent = nullptr;
+  uint16_t* cent_bf16 = nullptr;
+  float* cent_norm2 = nullptr;
+  float* cent_norm = nullptr;
+  int64_t* list_off = nullptr;
+  int32_t* list_ids = nullptr;
+  int32_t* pos_of_id = nullptr;
+  uint8_t* codes = nullptr;
+  float* codebook = nullptr;
+  void* vectors = nullptr;  // list-slot order
+  // host metadata
+  std::vector<int64_t> h_list_off;
+  std::vector<int64_t> h_maxS;  // h_maxS[p] = sum of the p largest list sizes
+  int max_lds = 65536;
+  // per-call state
+  Arena arena;
+  char* pinned = nullptr;
+  size_t pinned_cap = 0;
+  hipEvent_t meta_done = nullptr;
+  std::mutex mu;
+};
+
+namespace {
+
+int32_t set_device(int dev) {
+  int cnt = 0;
+  HIP_TRY(hipGetDeviceCount(&cnt));
+  if (dev < 0 || dev >= cnt) return fail(BBC_EINVAL, "device index out of range");
+  HIP_TRY(hipSetDevice(dev));
+  return BBC_OK;
+}
+
+void index_release(bbc_index* ix) {
+  if (!ix) return;
+  hipSetDevice(ix->device);
+  hipDeviceSynchronize();
+  hipFree(ix->cent); hipFree(ix->cent_bf16); hipFree(ix->cent_norm2); hipFree(ix->cent_norm);
+  hipFree(ix->list_off); hipFree(ix->list_ids); hipFree(ix->pos_of_id); hipFree(ix->codes);
+  hipFree(ix->codebook); hipFree(ix->vectors);
+  if (ix->arena.base) hipFree(ix->arena.base);
+  if (ix->pinned) hipHostFree(ix->pinned);
+  if (ix->meta_done) hipEventDestroy(ix->meta_done);
+  delete ix;
+}
+
+int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* list_off,
+                          const int64_t* list_ids) {
+  const int64_t n = ix->n;
+  const int32_t d = ix->d, nlist = ix->nlist;
+  ix->dpad = (int32_t)round_up(d, 32);
+  std::vector<uint16_t> cb16((size_t)nlist * ix->dpad, 0);
+  std::vector<float> cn2(nlist), cn(nlist);
+  for (int32_t j = 0; j < nlist; ++j) {
+    float s = 0.0f;
+    for (int32_t e = 0; e < d; ++e) {
+      float v = centroids[(int64_t)j * d + e];
+      cb16[(size_t)j * ix->dpad + e] = bf16_rne(v);
+      s = s + v * v;
+    }
+    cn2[j] = s;
+    cn[j] = std::sqrt(s);
+  }
+  std::vector<int32_t> ids32(n), pos(n, -1);
+  for (int64_t p = 0; p < n; ++p) {
+    int64_t id = list_ids[p];
+    if (id < 0 || id >= n || pos[id] != -1) return fail(BBC_EINVAL, "list_ids is not a permutation of 0..n-1");
+    pos[id] = (int32_t)p;
+    ids32[p] = (int32_t)id;
+  }
+  HIP_TRY(dalloc(&ix->cent, (size_t)nlist * d));
+  HIP_TRY(dalloc(&ix->cent_bf16, cb16.size()));
+  HIP_TRY(dalloc(&ix->cent_norm2, nlist));
+  HIP_TRY(dalloc(&ix->cent_norm, nlist));
+  HIP_TRY(dalloc(&ix->list_off, nlist + 1));
+  HIP_TRY(dalloc(&ix->list_ids, n));
+  HIP_TRY(dalloc(&ix->pos_of_id, n));
+  HIP_TRY(hipMemcpy(ix->cent, centroids, sizeof(float) * nlist * d, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->cent_bf16, cb16.data(), sizeof(uint16_t) * cb16.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->cent_norm2, cn2.data(), sizeof(float) * nlist, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->cent_norm, cn.data(), sizeof(float) * nlist, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->list_off, list_off, sizeof(int64_t) * (nlist + 1), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->list_ids, ids32.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(ix->pos_of_id, pos.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  ix->h_list_off.assign(list_off, list_off + nlist + 1);
+  std::vector<int64_t> sizes(nlist);
+  for (int32_t j = 0; j < nlist; ++j) sizes[j] = list_off[j + 1] - list_off[j];
+  std::sort(sizes.begin(), sizes.end(), std::greater<int64_t>());
+  ix->h_maxS.assign(nlist + 1, 0);
+  for (int32_t j = 0; j < nlist; ++j) ix->h_maxS[j + 1] = ix->h_maxS[j] + sizes[j];
+  int lds = 0;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) == hipSuccess && lds > 0)
+    ix->max_lds = lds;
+  HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
+  return BBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* bbc_last_error(void) { return g_err.c_str(); }
+
+int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
+                            const float* centroids, const int64_t* list_off, const int64_t* list_ids,
+                            int32_t pq_m, int32_t pq_bits, const float* codebook, const uint8_t* codes,
+                            const float* base, bbc_index** out) {
+  if (!out) return fail(BBC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!centroids || !list_off || !list_ids || !codebook || !codes || !base)
+    return fail(BBC_EINVAL, "NULL array");
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(BBC_EINVAL, "n must be in [1, 2^31)");
+  if (d < 4 || d > 1024 || d % 4) return fail(BBC_EINVAL, "d must be a multiple of 4 in [4, 1024]");
+  if (nlist < 1 || nlist > 8192) return fail(BBC_EINVAL, "nlist must be in [1, 8192]");
+  if (metric != BBC_METRIC_L2) return fail(BBC_EUNSUPPORTED, "the PQ path supports the L2 metric only");
+  if (pq_bits != 4 && pq_bits != 8) return fail(BBC_EINVAL, "pq_bits must be 4 or 8");
+  if (pq_m < 1 || d % pq_m) return fail(BBC_EINVAL, "pq_m must divide d");
+  if (list_off[0] != 0 || list_off[nlist] != n) return fail(BBC_EINVAL, "list_off must run from 0 to n");
+  for (int32_t j = 0; j < nlist; ++j)
+    if (list_off[j + 1] < list_off[j]) return fail(BBC_EINVAL, "list_off must be non-decreasing");
+  const int32_t ksub = 1 << pq_bits;
+  const int32_t dsub = d / pq_m;
+  if (!all_finite(centroids, (int64_t)nlist * d) || !all_finite(base, n * d) ||
+      !all_finite(codebook, (int64_t)pq_m * ksub * dsub))
+    return fail(BBC_EINVAL, "non-finite value in the index arrays");
+  for (int64_t i = 0; i < n * pq_m; ++i)
+    if (codes[i] >= ksub) return fail(BBC_EINVAL, "code out of range for pq_bits");
+  int32_t rc = set_device(device);
+  if (rc) return rc;
+  bbc_index* ix = new bbc_index();
+  ix->device = device;
+  ix->n = n; ix->d = d; ix->nlist = nlist; ix->metric = metric; ix->quant = BBC_QUANT_PQ;
+  ix->M = pq_m; ix->bits = pq_bits; ix->ksub = ksub;
+  ix->code_bytes = pq_bits == 8 ? pq_m : (pq_m + 1) / 2;
+  ix->code_stride = (int32_t)round_up(ix->code_bytes, 16);
+  rc = upload_ivf_common(ix, centroids, list_off, list_ids);
+  if (rc) { index_release(ix); return rc; }
+  // codes, re-strided (and nibble-packed for 4 bits: low nibble = even sub-space)
+  std::vector<uint8_t> packed((size_t)n * ix->code_stride, 0);
+  for (int64_t p = 0; p < n; ++p) {
+    uint8_t* row = packed.data() + (size_t)p * ix->code_stride;
+    const uint8_t* src = codes + p * pq_m;
+    if (pq_bits == 8) {
+      std::memcpy(row, src, pq_m);
+    } else {
+      for (int32_t m = 0; m < pq_m; ++m) row[m / 2] |= (uint8_t)((src[m] & 15) << (4 * (m & 1)));
+    }
+  }
+  // base vectors in list-slot order
+  std::vector<float> vec((size_t)n * d);
+  for (int64_t p = 0; p < n; ++p) std::memcpy(vec.data() + (size_t)p * d, base + list_ids[p] * d, sizeof(float) * d);
+  auto up = [&]() -> int32_t {
+    HIP_TRY(dalloc(&ix->codes, packed.size()));
+    HIP_TRY(hipMemcpy(ix->codes, packed.data(), packed.size(), hipMemcpyHostToDevice));
+    HIP_TRY(dalloc(&ix->codebook, (size_t)pq_m * ksub * dsub));
+    HIP_TRY(hipMemcpy(ix->codebook, codebook, sizeof(float) * pq_m * ksub * dsub, hipMemcpyHostToDevice));
+    float* v = nullptr;
+    HIP_TRY(dalloc(&v, vec.size()));
+    ix->vectors = v;
+    HIP_TRY(hipMemcpy(v, vec.data(), sizeof(float) * vec.size(), hipMemcpyHostToDevice));
+    return BBC_OK;
+  };
+  rc = up();
+  if (rc) { index_release(ix); return rc; }
+  *out = ix;
+  return BBC_OK;
+}
+
+int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,
+                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits) {
+  if (!ix) return fail(BBC_EINVAL, "index is NULL");
+  if (n) *n = ix->n;
+  if (d) *d = ix->d;
+  if (nlist) *nlist = ix->nlist;
+  if (metric) *metric = ix->metric;
+  if (quant) *quant = ix->quant;
+  if (pq_m) *pq_m = ix->M;
+  if (pq_bits) *pq_bits = ix->bits;
+  return BBC_OK;
+}
+
+int32_t bbc_index_get(const bbc_index* ix, int32_t field, void* dst, int64_t bytes) {
+  if (!ix || !dst) return fail(BBC_EINVAL, "NULL argument");
+  int32_t rc = set_device(ix->device);
+  if (rc) return rc;
+  const int64_t n = ix->n;
+  switch (field) {
+    case BBC_FIELD_CENTROIDS: {
+      int64_t need = sizeof(float) * (int64_t)ix->nlist * ix->d;
+      if (bytes != need) return fail(BBC_EINVAL, "wrong size for centroids");
+      HIP_TRY(hipMemcpy(dst, ix->cent, need, hipMemcpyDeviceToHost));
+      return BBC_OK;
+    }
+    case BBC_FIELD_LIST_OFF: {
+      int64_t need = sizeof(int64_t) * (ix->nlist + 1);
+      if (bytes != need) return fail(BBC_EINVAL, "wrong size for list_off");
+      std::memcpy(dst, ix->h_list_off.data(), need);
+      return BBC_OK;
+    }
+    case BBC_FIELD_LIST_IDS: {
+      if (bytes != (int64_t)sizeof(int64_t) * n) return fail(BBC_EINVAL, "wrong size for list_ids");
+      std::vector<int32_t> t(n);
+      HIP_TRY(hipMemcpy(t.data(), ix->list_ids, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+      int64_t* o = static_cast<int64_t*>(dst);
+      for (int64_t i = 0; i < n; ++i) o[i] = t[i];
+      return BBC_OK;
+    }
+    case BBC_FIELD_CODES: {
+      if (ix->quant != BBC_QUANT_PQ) return fail(BBC_EUNSUPPORTED, "not a PQ index");
+      if (bytes != n * ix->M) return fail(BBC_EINVAL, "wrong size for codes");
+      std::vector<uint8_t> t((size_t)n * ix->code_stride);
+      HIP_TRY(hipMemcpy(t.data(), ix->codes, t.size(), hipMemcpyDeviceToHost));
+      uint8_t* o = static_cast<uint8_t*>(dst);
+      for (int64_t p = 0; p < n; ++p)
+        for (int32_t m = 0; m < ix->M; ++m) {
+          uint8_t b = ix->bits == 8 ? t[(size_t)p * ix->code_stride + m]
+                                    : (uint8_t)((t[(size_t)p * ix->code_stride + m / 2] >> (4 * (m & 1))) & 15);
+          o[p * ix->M + m] = b;
+        }
+      return BBC_OK;
+    }
+    case BBC_FIELD_CODEBOOK: {
+      if (ix->quant != BBC_QUANT_PQ) return fail(BBC_EUNSUPPORTED, "not a PQ index");
+      int64_t need = sizeof(float) * (int64_t)ix->M * ix->ksub * (ix->d / ix->M);
+      if (bytes != need) return fail(BBC_EINVAL, "wrong size for codebook");
+      HIP_TRY(hipMemcpy(dst, ix->codebook, need, hipMemcpyDeviceToHost));
+      return BBC_OK;
+    }
+    default:
+      return fail(BBC_EINVAL, "unknown field");
+  }
+}
+
+void bbc_index_free(bbc_index* ix) { index_release(ix); }
+
+int32_t bbc_stage_timing(int32_t enable) {
+  g_timer.enabled = enable != 0;
+  return BBC_OK;
+}
+
+int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset) {
+  std::lock_guard<std::mutex> g(g_timer.mu);
+  for (auto& r : g_timer.pending) {
+    hipError_t e = hipEventSynchronize(r.b);
+    if (e != hipSuccess) return fail(BBC_EDEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+    float t = 0.f;
+    hipEventElapsedTime(&t, r.a, r.b);
+    if (r.stage >= 0 && r.stage < 8) { g_timer.ms[r.stage] += t; g_timer.launches[r.stage] += 1; }
+    g_timer.pool.push_back(r.a);
+    g_timer.pool.push_back(r.b);
+  }
+  g_timer.pending.clear();
+  for (int i = 0; i < nstages && i < 8; ++i) {
+    if (ms) ms[i] = g_timer.ms[i];
+    if (launches) launches[i] = g_timer.launches[i];
+  }
+  if (reset) {
+    for (int i = 0; i < 8; ++i) { g_timer.ms[i] = 0; g_timer.launches[i] = 0; }
+  }
+  return BBC_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// search
+// ---------------------------------------------------------------------------
+namespace {
+
+struct Layout {
+  // offsets into the arena
+  size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
+      cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts,
+      t_nb;
+};
+
+int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                        const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off) {
+  if (!ix) return fail(BBC_EINVAL, "index is NULL");
+  if (!p) return fail(BBC_EINVAL, "params is NULL");
+  if (nq < 0) return fail(BBC_EINVAL, "nq < 0");
+  if (nq == 0) return BBC_OK;
+  if (!queries || !k || !nprobe || !out_off) return fail(BBC_EINVAL, "NULL argument");
+  if (!(p->ncand_ratio >= 1.0) || !std::isfinite(p->ncand_ratio)) return fail(BBC_EINVAL, "ncand_ratio must be >= 1");
+  if (p->buckets < 0 || p->buckets > 256) return fail(BBC_EINVAL, "buckets must be in [0, 256]");
+  if (p->nsample < 0) return fail(BBC_EINVAL, "nsample must be >= 0");
+  if (p->collector != BBC_COLLECT_BUCKET) return fail(BBC_EUNSUPPORTED, "collector not available");
+  if (out_off[0] != 0) return fail(BBC_EINVAL, "out_offsets[0] must be 0");
+  for (int64_t i = 0; i < nq; ++i) {
+    if (k[i] < 1) return fail(BBC_EINVAL, "k must be >= 1");
+    if (nprobe[i] < 1 || nprobe[i] > ix->nlist) return fail(BBC_EINVAL, "nprobe must be in [1, nlist]");
+    if (out_off[i + 1] - out_off[i] != k[i]) return fail(BBC_EINVAL, "out_offsets must be the prefix sums of k");
+  }
+  if (!p->device_io && !all_finite(queries, nq * ix->d)) return fail(BBC_EINVAL, "non-finite query value");
+  return BBC_OK;
+}
+
+int64_t kc_cap_of(const bbc_index* ix, int32_t k, int32_t np, double r) {
+  int64_t t = (int64_t)std::ceil(r * (double)k);
+  return std::min(t, ix->h_maxS[np]);
+}
+
+int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                   const bbc_search_params* p, const int64_t* out_off, int64_t* out_ids, float* out_dists,
+                   int32_t* out_counts, bbc_search_trace* tr) {
+  int32_t rc = validate_search(ix, queries, nq, k, nprobe, p, out_off);
+  if (rc || nq == 0) return rc;
+  rc = set_device(ix->device);
+  if (rc) return rc;
+  std::lock_guard<std::mutex> guard(ix->mu);
+  hipStream_t s = static_cast<hipStream_t>(p->stream);
+  const bool host_io = p->device_io == 0;
+  const int m = p->buckets ? p->buckets : 256;
+  const int nsample = p->nsample ? p->nsample : 8;
+  const int d = ix->d;
+  const bool tracing = tr != nullptr;
+
+  // host-side metadata: per query k, nprobe, and prefix offsets
+  std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq);
+  int64_t max_kc = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    probe_off[i + 1] = probe_off[i] + nprobe[i];
+    key_off[i + 1] = key_off[i] + ix->h_maxS[nprobe[i]];
+    int64_t cap = kc_cap_of(ix, k[i], nprobe[i], p->ncand_ratio);
+    kc_target[i] = (int64_t)std::ceil(p->ncand_ratio * (double)k[i]);
+    cand_off[i + 1] = cand_off[i] + cap;
+    max_kc = std::max(max_kc, cap);
+  }
+  const int64_t npairs = probe_off[nq];
+  const int64_t nkeys = key_off[nq];
+  const int64_t ncand = cand_off[nq];
+  const int64_t nout = out_off[nq];
+
+  // metadata block: k i32[nq] | nprobe i32[nq] | probe_off i64 | key_off i64 | kc_target i64 | cand_off i64 | out_off i64
+  Plan mp;
+  size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),
+         m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1));
+  Plan pl;
+  Layout L{};
+  L.meta = pl.add(mp.total);
+  L.q = host_io ? pl.add(sizeof(float) * nq * d) : 0;
+  L.dprime = pl.add(sizeof(float) * nq * ix->nlist);
+  L.probe_lists = pl.add(4 * npairs);
+  L.probe_keys = pl.add(4 * npairs);
+  L.rank_off = pl.add(8 * npairs);
+  L.n_scanned = pl.add(8 * nq);
+  L.n_recheck = pl.add(4 * nq);
+  L.keys = pl.add(4 * nkeys);
+  L.cand_pos = pl.add(4 * ncand);
+  L.cand_packed = pl.add(8 * ncand);
+  L.n_cand = pl.add(8 * nq);
+  if (host_io) {
+    L.out_ids = pl.add(8 * nout);
+    L.out_dists = pl.add(4 * nout);
+    L.out_counts = pl.add(4 * nq);
+  }
+  if (tracing) {
+    L.t_dmin = pl.add(4 * nq); L.t_delta = pl.add(4 * nq); L.t_map = pl.add(256 * nq);
+    L.t_tau = pl.add(4 * nq); L.t_s = pl.add(8 * nq); L.t_counts = pl.add(4 * nq * m); L.t_nb = pl.add(8 * nq);
+  }
+  HIP_TRY(ix->arena.reserve(pl.total));
+  char* A = ix->arena.base;
+
+  // stage metadata through pinned memory (wait for the previous call's copy)
+  if (ix->pinned_cap < mp.total) {
+    HIP_TRY(hipEventSynchronize(ix->meta_done));
+    if (ix->pinned) hipHostFree(ix->pinned);
+    ix->pinned = nullptr;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ix->pinned), mp.total * 2));
+    ix->pinned_cap = mp.total * 2;
+  } else {
+    HIP_TRY(hipEventSynchronize(ix->meta_done));
+  }
+  char* H = ix->pinned;
+  std::memcpy(H + m_k, k, 4 * nq);
+  std::memcpy(H + m_np, nprobe, 4 * nq);
+  std::memcpy(H + m_po, probe_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_ko, key_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_kt, kc_target.data(), 8 * nq);
+  std::memcpy(H + m_co, cand_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
+  char* M = A + L.meta;
+  HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ix->meta_done, s));
+  const float* dq = queries;
+  if (host_io) {
+    HIP_TRY(hipMemcpyAsync(A + L.q, queries, sizeof(float) * nq * d, hipMemcpyHostToDevice, s));
+    dq = reinterpret_cast<const float*>(A + L.q);
+  }
+  const int32_t* d_k = reinterpret_cast<const int32_t*>(M + m_k);
+  const int32_t* d_np = reinterpret_cast<const int32_t*>(M + m_np);
+  const int64_t* d_po = reinterpret_cast<const int64_t*>(M + m_po);
+  const int64_t* d_ko = reinterpret_cast<const int64_t*>(M + m_ko);
+  const int64_t* d_kt = reinterpret_cast<const int64_t*>(M + m_kt);
+  const int64_t* d_co = reinterpret_cast<const int64_t*>(M + m_co);
+  const int64_t* d_oo = reinterpret_cast<const int64_t*>(M + m_oo);
+  int64_t* d_oid = host_io ? reinterpret_cast<int64_t*>(A + L.out_ids) : out_ids;
+  float* d_odist = host_io ? reinterpret_cast<float*>(A + L.out_dists) : out_dists;
+  int32_t* d_ocnt = host_io ? reinterpret_cast<int32_t*>(A + L.out_counts) : out_counts;
+
+  bbc::ProbeArgs pa{};
+  pa.q = dq; pa.nq = nq; pa.d = d; pa.cent = ix->cent; pa.cent_bf16 = ix->cent_bf16; pa.dpad = ix->dpad;
+  pa.cent_norm2 = ix->cent_norm2; pa.cent_norm = ix->cent_norm; pa.nlist = ix->nlist; pa.metric = ix->metric;
+  pa.nprobe = d_np; pa.probe_off = d_po; pa.list_off = ix->list_off;
+  pa.dprime = reinterpret_cast<float*>(A + L.dprime);
+  pa.probe_lists = reinterpret_cast<int32_t*>(A + L.probe_lists);
+  pa.probe_keys = reinterpret_cast<float*>(A + L.probe_keys);
+  pa.rank_off = reinterpret_cast<int64_t*>(A + L.rank_off);
+  pa.n_scanned = reinterpret_cast<int64_t*>(A + L.n_scanned);
+  pa.n_recheck = reinterpret_cast<int32_t*>(A + L.n_recheck);
+  {
+    StageScope st(s, 0);  // both probe kernels are timed together as stages 0+1
+    HIP_TRY(bbc::launch_probe(pa, s));
+  }
+
+  bbc::PqScanArgs sa{};
+  sa.q = dq; sa.nq = nq; sa.d = d; sa.cent = ix->cent; sa.M = ix->M; sa.bits = ix->bits;
+  sa.codebook = ix->codebook; sa.codes = ix->codes; sa.code_stride = ix->code_stride;
+  sa.list_off = ix->list_off; sa.probe_off = d_po; sa.probe_lists = pa.probe_lists; sa.rank_off = pa.rank_off;
+  sa.key_off = d_ko; sa.keys = reinterpret_cast<float*>(A + L.keys); sa.rank_begin = 0; sa.rank_end = 1 << 30;
+  {
+    StageScope st(s, 2);
+    HIP_TRY(bbc::launch_pq_scan(sa, npairs, s));
+  }
+
+  const int bcap = 8192;
+  bbc::CollectArgs ca{};
+  ca.nq = nq; ca.keys = sa.keys; ca.key_off = d_ko; ca.n_scanned = pa.n_scanned; ca.nprobe = d_np;
+  ca.probe_off = d_po; ca.probe_lists = pa.probe_lists; ca.rank_off = pa.rank_off; ca.list_off = ix->list_off;
+  ca.list_ids = ix->list_ids; ca.pos_of_id = ix->pos_of_id; ca.kc_target = d_kt; ca.cand_off = d_co; ca.m = m;
+  ca.nsample = nsample; ca.bcap = bcap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
+  ca.n_cand = reinterpret_cast<int64_t*>(A + L.n_cand);
+  if (tracing) {
+    ca.t_dmin = reinterpret_cast<float*>(A + L.t_dmin); ca.t_delta = reinterpret_cast<float*>(A + L.t_delta);
+    ca.t_map = reinterpret_cast<uint8_t*>(A + L.t_map); ca.t_tau = reinterpret_cast<int32_t*>(A + L.t_tau);
+    ca.t_s = reinterpret_cast<int64_t*>(A + L.t_s); ca.t_counts = reinterpret_cast<int32_t*>(A + L.t_counts);
+    ca.t_nboundary = reinterpret_cast<int64_t*>(A + L.t_nb);
+  }
+  {
+    StageScope st(s, 3);
+    HIP_TRY(bbc::launch_collect_bucket(ca, s));
+  }
+
+  bbc::RerankArgs ra{};
+  ra.q = dq; ra.nq = nq; ra.d = d; ra.metric = ix->metric; ra.vectors = ix->vectors; ra.fp16 = ix->fp16;
+  ra.list_ids = ix->list_ids; ra.cand_pos = ca.cand_pos; ra.cand_off = d_co; ra.n_cand = ca.n_cand;
+  ra.cand_packed = reinterpret_cast<uint64_t*>(A + L.cand_packed);
+  {
+    StageScope st(s, 4);
+    HIP_TRY(bbc::launch_rerank(ra, max_kc, s));
+  }
+
+  // trace copies of the exact candidate keys happen before the final step
+  // reuses the candidate buffer as merge scratch
+  std::vector<uint64_t> cand_packed_h;
+  std::vector<uint32_t> cand_pos_h;
+  std::vector<int64_t> n_cand_h(nq);
+  if (tracing && (tr->cand_ids || tr->cand_exact || tr->cand_off)) {
+    cand_packed_h.resize(ncand);
+    HIP_TRY(hipMemcpyAsync(cand_packed_h.data(), ra.cand_packed, 8 * ncand, hipMemcpyDeviceToHost, s));
+  }
+
+  int run = 8192;
+  if (ix->max_lds >= (int)(16384 * sizeof(uint64_t) + 4096)) run = 16384;
+  bbc::FinalArgs fa{};
+  fa.nq = nq; fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
+  fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
+  fa.run = run;
+  {
+    StageScope st(s, 5);
+    HIP_TRY(bbc::launch_final_topk(fa, s));
+  }
+
+  if (host_io) {
+    HIP_TRY(hipMemcpyAsync(out_ids, d_oid, 8 * nout, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out_dists, d_odist, 4 * nout, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out_counts, d_ocnt, 4 * nq, hipMemcpyDeviceToHost, s));
+  }
+  if (tracing) {
+    auto cp = [&](void* dst, size_t off, size_t bytes) -> int32_t {
+      if (dst) HIP_TRY(hipMemcpyAsync(dst, A + off, bytes, hipMemcpyDeviceToHost, s));
+      return BBC_OK;
+    };
+    if ((rc = cp(tr->probe_lists, L.probe_lists, 4 * npairs))) return rc;
+    if ((rc = cp(tr->probe_keys, L.probe_keys, 4 * npairs))) return rc;
+    if ((rc = cp(tr->n_recheck, L.n_recheck, 4 * nq))) return rc;
+    if ((rc = cp(tr->dmin, L.t_dmin, 4 * nq))) return rc;
+    if ((rc = cp(tr->delta, L.t_delta, 4 * nq))) return rc;
+    if ((rc = cp(tr->map, L.t_map, 256 * nq))) return rc;
+    if ((rc = cp(tr->tau, L.t_tau, 4 * nq))) return rc;
+    if ((rc = cp(tr->s, L.t_s, 8 * nq))) return rc;
+    if ((rc = cp(tr->bucket_counts, L.t_counts, 4 * nq * m))) return rc;
+    if ((rc = cp(tr->n_boundary, L.t_nb, 8 * nq))) return rc;
+    std::vector<int64_t> nsc(nq);
+    HIP_TRY(hipMemcpyAsync(nsc.data(), A + L.n_scanned, 8 * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(n_cand_h.data(), A + L.n_cand, 8 * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (tr->n_scanned) std::memcpy(tr->n_scanned, nsc.data(), 8 * nq);
+    if (tr->n_cand) std::memcpy(tr->n_cand, n_cand_h.data(), 8 * nq);
+    if (tr->est_off) {
+      tr->est_off[0] = 0;
+      for (int64_t i = 0; i < nq; ++i) tr->est_off[i + 1] = tr->est_off[i] + nsc[i];
+    }
+    if (tr->est_keys) {
+      std::vector<float> kk(nkeys);
+      HIP_TRY(hipMemcpy(kk.data(), A + L.keys, 4 * nkeys, hipMemcpyDeviceToHost));
+      int64_t w = 0;
+      for (int64_t i = 0; i < nq; ++i) {
+        std::memcpy(tr->est_keys + w, kk.data() + key_off[i], 4 * nsc[i]);
+        w += nsc[i];
+      }
+    }
+    if (tr->cand_off) {
+      tr->cand_off[0] = 0;
+      for (int64_t i = 0; i < nq; ++i) tr->cand_off[i + 1] = tr->cand_off[i] + n_cand_h[i];
+    }
+    if (tr->cand_ids || tr->cand_exact) {
+      int64_t w = 0;
+      for (int64_t i = 0; i < nq; ++i) {
+        for (int64_t j = 0; j < n_cand_h[i]; ++j) {
+          uint64_t v = cand_packed_h[cand_off[i] + j];
+          uint32_t kb = (uint32_t)(v >> 32);
+          uint32_t fb = (kb & 0x80000000u) ? (kb & 0x7fffffffu) : ~kb;
+          float key;
+          std::memcpy(&key, &fb, 4);
+          if (tr->cand_ids) tr->cand_ids[w] = (int64_t)(v & 0xffffffffu);
+          if (tr->cand_exact) tr->cand_exact[w] = key;
+          ++w;
+        }
+      }
+    }
+  }
+  if (host_io) HIP_TRY(hipStreamSynchronize(s));
+  return BBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bbc_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                   const int32_t* nprobe, const bbc_search_params* params, const int64_t* out_offsets,
+                   int64_t* out_ids, float* out_dists, int32_t* out_counts) {
+  return run_search(const_cast<bbc_index*>(ix), queries, nq, k, nprobe, params, out_offsets, out_ids,
+                    out_dists, out_counts, nullptr);
+}
+
+int32_t bbc_search_traced(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                          const int32_t* nprobe, const bbc_search_params* params,
+                          const int64_t* out_offsets, int64_t* out_ids, float* out_dists,
+                          int32_t* out_counts, bbc_search_trace* trace) {
+  if (!params || params->device_io) return fail(BBC_EINVAL, "traced search needs host I/O");
+  if (!trace) return fail(BBC_EINVAL, "trace is NULL");
+  return run_search(const_cast<bbc_index*>(ix), queries, nq, k, nprobe, params, out_offsets, out_ids,
+                    out_dists, out_counts, trace);
+}
+
+int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bbc_search_params* p) {
+  if (!ix || !p || k < 1 || nprobe < 1 || nprobe > ix->nlist || !(p->ncand_ratio >= 1.0))
+    return fail(BBC_EINVAL, "bad argument");
+  int64_t kc = kc_cap_of(ix, k, nprobe, p->ncand_ratio);
+  int64_t bytes = 0;
+  bytes += 4 * (int64_t)ix->d + 4 * (int64_t)ix->nlist;     // query, coarse scores
+  bytes += 16 * (int64_t)nprobe;                            // probe lists, keys, rank offsets
+  bytes += 4 * ix->h_maxS[nprobe];                          // estimated keys
+  bytes += 12 * kc;                                         // candidate slots + packed exact keys
+  bytes += 12 * (int64_t)k + 64;                            // outputs + per-query scalars
+  return bytes;
+}
+
+}  // extern "C"

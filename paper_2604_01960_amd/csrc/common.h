@@ -1,0 +1,201 @@
+// Shared device helpers for the BBC query path on gfx950 (CDNA4, wave64).
+//
+// Canonical float32 arithmetic: the library is compiled with
+// -ffp-contract=off (no FMA contraction), IEEE division/sqrt, no fast-math.
+// Distances follow one fixed operation order (below) so that results are
+// reproducible bit for bit by any implementation of the same order:
+//   * a vector is padded with zeros to a multiple of 256 elements and cut into
+//     4-element chunks; chunk c belongs to lane c % 64 at step c / 64;
+//   * each lane starts at +0 and, step by step and element by element, adds
+//     t = (a - b) * (a - b)   [L2]   or   t = a * b   [inner product];
+//   * lanes are combined as acc[l] = acc[l] + acc[l + off], off = 32 .. 1.
+// Lanes that only ever see padding hold +0, and adding +0 to a partial sum
+// that is never -0 is exact, so a row of at most 32 chunks can be reduced on
+// 32 lanes (off = 16 .. 1) with the same result.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define BBC_WAVE 64
+#define BBC_NCELLS 256          // equal-width cells of the bucket codebook
+#define BBC_MAX_BUCKETS 256     // m <= 256: the cell->bucket map is one byte
+
+namespace bbc {
+
+// Key order used everywhere: numeric key (-0 == +0), ties to the smaller id.
+// The 32-bit image below is monotone in the key; -0 is first made +0.
+__device__ __forceinline__ uint32_t key_bits(float f) {
+  f = f + 0.0f;  // -0 -> +0, every other value unchanged
+  uint32_t u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float bits_key(uint32_t u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+__device__ __forceinline__ uint64_t pack_key_id(float key, uint32_t id) {
+  return ((uint64_t)key_bits(key) << 32) | (uint64_t)id;
+}
+__device__ __forceinline__ float packed_key(uint64_t p) { return bits_key((uint32_t)(p >> 32)); }
+__device__ __forceinline__ uint32_t packed_id(uint64_t p) { return (uint32_t)(p & 0xffffffffu); }
+
+// Equal-width cell of a key: clamp(floor((key - dmin) / delta), 0, 255).
+__device__ __forceinline__ int cell_of(float key, float dmin, float delta) {
+  float t = (key - dmin) / delta;
+  if (t < 0.0f) return 0;
+  if (t >= 255.0f) return 255;
+  return (int)t;
+}
+
+// Lane combination of the canonical order on a full wave (off = 32 .. 1).
+__device__ __forceinline__ float canon_reduce64(float acc) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) acc = acc + __shfl_xor(acc, off);
+  return acc;
+}
+// Same on each 32-lane half of a wave (rows of at most 32 chunks).
+__device__ __forceinline__ float canon_reduce32(float acc) {
+#pragma unroll
+  for (int off = 16; off >= 1; off >>= 1) acc = acc + __shfl_xor(acc, off);
+  return acc;
+}
+
+__device__ __forceinline__ float chunk_l2(float4 a, float4 b, float acc) {
+  float t;
+  t = a.x - b.x; t = t * t; acc = acc + t;
+  t = a.y - b.y; t = t * t; acc = acc + t;
+  t = a.z - b.z; t = t * t; acc = acc + t;
+  t = a.w - b.w; t = t * t; acc = acc + t;
+  return acc;
+}
+__device__ __forceinline__ float chunk_ip(float4 a, float4 b, float acc) {
+  float t;
+  t = a.x * b.x; acc = acc + t;
+  t = a.y * b.y; acc = acc + t;
+  t = a.z * b.z; acc = acc + t;
+  t = a.w * b.w; acc = acc + t;
+  return acc;
+}
+
+// Canonical L2 / IP of two float rows (d a multiple of 4, 16-byte aligned)
+// computed by one full wave; every lane returns the result.
+__device__ __forceinline__ float wave_canon(const float* __restrict__ a, const float* __restrict__ b,
+                                            int d, bool ip) {
+  const int lane = threadIdx.x & 63;
+  const int nchunk = d >> 2;
+  float acc = 0.0f;
+  for (int c = lane; c < nchunk; c += 64) {
+    float4 av = reinterpret_cast<const float4*>(a)[c];
+    float4 bv = reinterpret_cast<const float4*>(b)[c];
+    acc = ip ? chunk_ip(av, bv, acc) : chunk_l2(av, bv, acc);
+  }
+  return canon_reduce64(acc);
+}
+
+// Block-wide helpers ------------------------------------------------------
+
+template <int NT>
+__device__ __forceinline__ uint32_t block_sum_u32(uint32_t v, uint32_t* red) {
+  // red: LDS scratch of NT/64 entries
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) s += red[i];
+  __syncthreads();
+  return s;
+}
+
+// Bitonic sort of n (power of two) 64-bit values in LDS, ascending, by a
+// block of NT threads.
+template <int NT>
+__device__ void lds_bitonic_sort(uint64_t* v, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < (n >> 1); t += NT) {
+        int lo = 2 * t - (t & (stride - 1));
+        int hi = lo + stride;
+        bool up = ((lo & size) == 0);
+        uint64_t a = v[lo], b = v[hi];
+        if ((a > b) == up) { v[lo] = b; v[hi] = a; }
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Radix select over a block: value of the element of rank r (0-based,
+// ascending) among n 32-bit values produced by get(i).  hist: 256 LDS words;
+// bc: 2 LDS words for broadcast.
+template <int NT, typename Get>
+__device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
+  uint32_t prefix = 0, mask = 0;
+  for (int shift = 24; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
+      uint32_t v = get(i);
+      if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t rr = r;
+      uint32_t dg = 0;
+      for (; dg < 255; ++dg) {
+        if (rr < (int64_t)hist[dg]) break;
+        rr -= hist[dg];
+      }
+      bc[0] = dg;
+      bc[1] = (uint32_t)rr;
+    }
+    __syncthreads();
+    prefix |= bc[0] << shift;
+    mask |= 255u << shift;
+    r = bc[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+// 64-bit variant over the elements for which get(i, v) returns true.
+template <int NT, typename Get>
+__device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
+  uint64_t prefix = 0, mask = 0;
+  for (int shift = 56; shift >= 0; shift -= 8) {
+    for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < n; i += NT) {
+      uint64_t v;
+      if (get(i, v) && (v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t rr = r;
+      uint32_t dg = 0;
+      for (; dg < 255; ++dg) {
+        if (rr < (int64_t)hist[dg]) break;
+        rr -= hist[dg];
+      }
+      bc[0] = dg;
+      bc[1] = (uint32_t)rr;
+    }
+    __syncthreads();
+    prefix |= (uint64_t)bc[0] << shift;
+    mask |= 255ull << shift;
+    r = bc[1];
+    __syncthreads();
+  }
+  return prefix;
+}
+
+__host__ __device__ __forceinline__ int next_pow2(int x) {
+  int p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+}  // namespace bbc

@@ -1,0 +1,73 @@
+"""Shared test helpers: seeded oracle-built indexes and per-step expected
+values computed by the oracle only."""
+from __future__ import annotations
+
+import functools
+
+import numpy as np
+
+import oracle
+import synth
+
+
+@functools.lru_cache(maxsize=8)
+def oracle_pq_index(base_name: str, n: int, nlist: int, M: int, bits: int, nq: int, d: int = 0,
+                    iters: int = 10):
+    """Index built by the oracle from a scaled-down seeded workload."""
+    w = synth.workload(base_name)
+    kw = dict(pq_m=M, pq_bits=bits)
+    if d:
+        kw["d"] = d
+    if n == w.n and nlist == w.nlist and nq == w.nq:
+        w = synth.workload(base_name, **kw)
+    else:
+        w = synth.small_workload(base_name, n=n, nlist=nlist, nq=nq, **kw)
+    x = synth.base_vectors(w)
+    q = synth.query_vectors(w)
+    tr, ip = synth.kmeans_draws(w.n, w.nlist, w.train_per_list * w.nlist, 0)
+    pr, pi = synth.pq_draws(w.n, M, 1 << bits, w.pq_train, 0)
+    ix = oracle.build_ivf_pq(x, w.nlist, M, bits, tr, ip, pr, pi, iters)
+    return w, ix, q
+
+
+def make_gpu_index(bbc, ix):
+    return bbc.Index.create_pq(ix["centroids"], ix["list_off"], ix["list_ids"], ix["codebook"], ix["codes"],
+                               ix["base"])
+
+
+def expected_steps(ix, q, k, nprobe, ratio, m, nsample):
+    """Per query, everything the GPU trace reports, from the oracle alone."""
+    nq = q.shape[0]
+    kk = np.broadcast_to(np.asarray(k), (nq,)).astype(np.int64)
+    npb = np.broadcast_to(np.asarray(nprobe), (nq,)).astype(np.int64)
+    res = oracle.search_pq(ix, q, kk, npb, ratio, debug=True)
+    out = []
+    for i in range(nq):
+        lists = res["probe_lists"][res["probe_off"][i]:res["probe_off"][i + 1]]
+        keys, ids, sizes = [], [], []
+        for j in lists:
+            lut = oracle.pq_lut(q[i], ix["centroids"][j], ix["codebook"], ix["M"], ix["ksub"])
+            sl = slice(ix["list_off"][j], ix["list_off"][j + 1])
+            keys.append(oracle.pq_keys(lut, ix["codes"][sl]))
+            ids.append(ix["list_ids"][sl])
+            sizes.append(sl.stop - sl.start)
+        keys = np.concatenate(keys) if keys else np.zeros(0, np.float32)
+        ids = np.concatenate(ids) if ids else np.zeros(0, np.int64)
+        goff = np.zeros(len(lists) + 1, np.int64)
+        goff[1:] = np.cumsum(sizes)
+        kc_t = int(np.ceil(ratio * float(kk[i])))
+        col = oracle.collect_bbc(keys, ids, goff, kc_t, m, nsample) if len(keys) else None
+        kc = int(res["n_cand"][i])
+        cand = res["cand_ids"][res["cand_off"][i]:res["cand_off"][i] + kc]
+        exact = np.array([oracle.canon_l2(q[i], ix["base"][c]) for c in cand], np.float32)
+        s = slice(res["off"][i], res["off"][i + 1])
+        out.append(dict(probe_lists=lists, probe_keys=res["probe_keys"][res["probe_off"][i]:res["probe_off"][i + 1]],
+                        est_keys=keys, est_ids=ids, n_scanned=int(res["n_scanned"][i]), n_cand=kc,
+                        collect=col, cand_ids=cand, cand_exact=exact, ids=res["ids"][s], dists=res["dists"][s],
+                        count=int(res["counts"][i])))
+    return out
+
+
+def sort_pairs(ids, keys):
+    o = np.lexsort((ids, keys))
+    return ids[o], keys[o]

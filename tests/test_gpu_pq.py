@@ -1,0 +1,131 @@
+"""GPU parity of the PQ query path against the oracle, step by step, through
+the C ABI (probe, estimated keys, codebook, histogram and threshold bucket,
+candidate set, exact keys, final ids and distances)."""
+import numpy as np
+import pytest
+
+from helpers import expected_steps, make_gpu_index, oracle_pq_index, sort_pairs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    import paper_2604_01960_amd as b
+    b.load()
+    return b
+
+
+def _check_trace(tr, exp, q_index_slice, m):
+    nq = len(exp)
+    for i in range(nq):
+        e = exp[i]
+        ps = slice(int(np.sum([len(x["probe_lists"]) for x in exp[:i]])),
+                   int(np.sum([len(x["probe_lists"]) for x in exp[:i + 1]])))
+        np.testing.assert_array_equal(tr["probe_lists"][ps], e["probe_lists"], err_msg=f"probe q{i}")
+        np.testing.assert_array_equal(tr["probe_keys"][ps], e["probe_keys"], err_msg=f"probe keys q{i}")
+        assert tr["n_scanned"][i] == e["n_scanned"]
+        es = slice(tr["est_off"][i], tr["est_off"][i + 1])
+        np.testing.assert_array_equal(tr["est_keys"][es], e["est_keys"], err_msg=f"estimated keys q{i}")
+        assert tr["n_cand"][i] == e["n_cand"]
+        col = e["collect"]
+        if col is not None and e["n_cand"] > 0:
+            assert tr["dmin"][i] == col["dmin"] and tr["delta"][i] == col["delta"], f"codebook q{i}"
+            np.testing.assert_array_equal(tr["map"][i], col["map"], err_msg=f"map q{i}")
+            np.testing.assert_array_equal(tr["bucket_counts"][i][:m], col["counts"], err_msg=f"counts q{i}")
+            assert tr["tau"][i] == col["tau"] and tr["s"][i] == col["s"], f"tau/s q{i}"
+        cs = slice(tr["cand_off"][i], tr["cand_off"][i + 1])
+        gi, gk = sort_pairs(tr["cand_ids"][cs], tr["cand_exact"][cs])
+        ei, ek = sort_pairs(e["cand_ids"], e["cand_exact"])
+        np.testing.assert_array_equal(gi, ei, err_msg=f"candidates q{i}")
+        np.testing.assert_array_equal(gk, ek, err_msg=f"exact keys q{i}")
+        os_ = slice(tr["off"][i], tr["off"][i + 1])
+        assert tr["counts"][i] == e["count"]
+        np.testing.assert_array_equal(tr["ids"][os_], e["ids"], err_msg=f"ids q{i}")
+        np.testing.assert_array_equal(tr["dists"][os_], e["dists"], err_msg=f"dists q{i}")
+
+
+@pytest.mark.parametrize("cfg", [
+    # (base workload, n, nlist, M, bits, d, nq, k, nprobe, ratio, m, nsample)
+    ("ivfpq_100k_d128", 20000, 64, 16, 8, 0, 12, 300, 12, 2.0, 64, 8),
+    ("ivfpq_1m_d128", 24000, 60, 32, 8, 0, 10, 700, 9, 1.5, 256, 3),
+    ("ivfpq4_10m_d96", 20000, 50, 48, 4, 0, 10, 400, 10, 2.5, 80, 8),
+])
+def test_every_step_matches_oracle(bbc, cfg):
+    base, n, nlist, M, bits, d, nq, k, nprobe, ratio, m, ns = cfg
+    w, ix, q = oracle_pq_index(base, n, nlist, M, bits, nq, d)
+    print(f"[case] {base} n={n} nlist={nlist} M={M} bits={bits} k={k} nprobe={nprobe} r={ratio} m={m}", flush=True)
+    g = make_gpu_index(bbc, ix)
+    tr = g.search_traced(q, k, nprobe, ratio=ratio, buckets=m, nsample=ns)
+    exp = expected_steps(ix, q, k, nprobe, ratio, m, ns)
+    _check_trace(tr, exp, None, m)
+
+
+def test_uneven_and_edge_cases(bbc):
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 12000, 40, 16, 8, 14)
+    print("[case] uneven/edge n=12000 nlist=40", flush=True)
+    g = make_gpu_index(bbc, ix)
+    sizes = np.diff(ix["list_off"])
+    k = np.array([1, 5, 300, 2000, 12000, 50, 7, 999, 20000, 64, 3, 1000, 250, 4000], np.int32)
+    npb = np.array([1, 40, 3, 7, 40, 2, 1, 11, 40, 5, 39, 1, 13, 4], np.int32)
+    for ratio in (1.0, 1.7):
+        for m in (1, 2, 256):
+            tr = g.search_traced(q, k, npb, ratio=ratio, buckets=m, nsample=2)
+            exp = expected_steps(ix, q, k, npb, ratio, m, 2)
+            _check_trace(tr, exp, None, m)
+    # k larger than everything scanned pads with -1 / +inf
+    ids, dists, counts, off = g.search(q[:1], 5000, 1, ratio=1.0)
+    s = int(sizes[tr["probe_lists"][0]]) if False else int(counts[0])
+    assert np.all(ids[s:] == -1) and np.all(np.isinf(dists[s:]))
+
+
+def test_ties_on_integer_data(bbc):
+    """Integer vectors: exact keys tie massively; ids must still match."""
+    import oracle
+    rng = np.random.default_rng(21)
+    n, d, nlist, M = 5000, 16, 10, 4
+    x = rng.integers(0, 3, (n, d)).astype(np.float32)
+    cent = rng.integers(0, 3, (nlist, d)).astype(np.float32)
+    a = oracle.kmeans_assign(x, cent)
+    order = np.argsort(a, kind="stable").astype(np.int64)
+    off = np.zeros(nlist + 1, np.int64)
+    off[1:] = np.cumsum(np.bincount(a, minlength=nlist))
+    cb = rng.integers(-1, 2, (M, 16, d // M)).astype(np.float32)
+    codes = oracle.pq_encode(oracle.residuals(x, order, cent, a), cb)
+    ix = dict(kind="pq", n=n, d=d, nlist=nlist, M=M, ksub=16, bits=4, metric=0, centroids=cent, assign=a,
+              list_off=off, list_ids=order, codes=codes, codebook=cb, base=x)
+    q = rng.integers(0, 3, (6, d)).astype(np.float32)
+    print("[case] integer ties", flush=True)
+    g = make_gpu_index(bbc, ix)
+    tr = g.search_traced(q, 700, 4, ratio=2.0, buckets=16, nsample=2)
+    exp = expected_steps(ix, q, 700, 4, 2.0, 16, 2)
+    _check_trace(tr, exp, None, 16)
+
+
+def test_full_100k_config_bit_exact(bbc):
+    """The 100k x 128 / IVF256 / PQ16x8 workload: all 100 queries, k=5000, nprobe=32."""
+    import oracle
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 100_000, 256, 16, 8, 100)
+    print("[case] full 100k config", flush=True)
+    g = make_gpu_index(bbc, ix)
+    ids, dists, counts, off = g.search(q, 5000, 32, ratio=2.0)
+    ref = oracle.search_pq(ix, q, 5000, 32, 2.0)
+    np.testing.assert_array_equal(counts, ref["counts"])
+    np.testing.assert_array_equal(ids, ref["ids"])
+    np.testing.assert_array_equal(dists, ref["dists"])
+
+
+def test_repeat_and_device_io(bbc):
+    import torch
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 20000, 64, 16, 8, 12)
+    g = make_gpu_index(bbc, ix)
+    a = g.search(q, 300, 12, ratio=2.0)
+    b = g.search(q, 300, 12, ratio=2.0)
+    for x, y in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(x, y)
+    qt = torch.from_numpy(q).cuda()
+    ids, dists, counts, off = g.search(qt, 300, 12, ratio=2.0)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ids.cpu().numpy(), a[0])
+    np.testing.assert_array_equal(dists.cpu().numpy(), a[1])
+    np.testing.assert_array_equal(counts.cpu().numpy(), a[2])
