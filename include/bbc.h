@@ -70,6 +70,30 @@ int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist,
                             int32_t pq_m, int32_t pq_bits, const float* codebook, const uint8_t* codes,
                             const float* base, bbc_index** out);
 
+/* Build an index on `device` from base [n][d] float32 (row-id order):
+ * IVF k-means (kmeans_iters Lloyd rounds on the training rows, then every
+ * row assigned to its nearest centroid; empty clusters split the largest
+ * one), then residual PQ trained on the PQ rows.  The random draws are
+ * inputs: train_rows [n_train] ascending rows, init_pos [nlist] distinct
+ * positions in train_rows seeding the centroids, pq_rows [n_pq] ascending
+ * rows, pq_init [pq_m][2^pq_bits] distinct positions in pq_rows seeding
+ * each sub-space codebook.  Assignment uses canonical float32 squared L2
+ * with ties to the smaller id; centroid and codeword means are float64 sums
+ * in row order rounded once.  d/pq_m <= 16. */
+typedef struct {
+  int32_t nlist;
+  int32_t kmeans_iters;
+  int32_t metric;   /* BBC_METRIC_L2 */
+  int32_t quant;    /* BBC_QUANT_PQ */
+  int32_t pq_m;
+  int32_t pq_bits;  /* 4 or 8 */
+  const int64_t* train_rows; int64_t n_train; const int64_t* init_pos;
+  const int64_t* pq_rows; int64_t n_pq; const int64_t* pq_init;
+} bbc_build_params;
+
+int32_t bbc_build_index(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* params,
+                        bbc_index** out);
+
 typedef struct {
   double ncand_ratio;  /* r >= 1: the collector keeps K_c = min(ceil(r*k), S) candidates */
   int32_t collector;   /* BBC_COLLECT_* */

@@ -40,6 +40,13 @@ class SearchParams(C.Structure):
                 ("nsample", C.c_int32), ("device_io", C.c_int32), ("stream", C.c_void_p)]
 
 
+class BuildParams(C.Structure):
+    _fields_ = [("nlist", C.c_int32), ("kmeans_iters", C.c_int32), ("metric", C.c_int32), ("quant", C.c_int32),
+                ("pq_m", C.c_int32), ("pq_bits", C.c_int32),
+                ("train_rows", C.c_void_p), ("n_train", C.c_int64), ("init_pos", C.c_void_p),
+                ("pq_rows", C.c_void_p), ("n_pq", C.c_int64), ("pq_init", C.c_void_p)]
+
+
 class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
@@ -68,6 +75,8 @@ def load(path: Optional[str] = None):
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.bbc_index_create_pq.restype = i32
     L.bbc_index_create_pq.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(vp)]
+    L.bbc_build_index.restype = i32
+    L.bbc_build_index.argtypes = [i32, vp, i64, i32, C.POINTER(BuildParams), C.POINTER(vp)]
     L.bbc_search.restype = i32
     L.bbc_search.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.bbc_search_traced.restype = i32
@@ -151,6 +160,18 @@ class Index:
                                           M, bits, _ptr(cb), _ptr(cd), _ptr(b), C.byref(h)))
         return cls(h.value, device)
 
+    @classmethod
+    def build_pq(cls, base, nlist, pq_m, pq_bits, train_rows, init_pos, pq_rows, pq_init, iters=10, device=0):
+        """Build an IVF-PQ index on the GPU from base vectors and the random draws."""
+        b = _np(base, np.float32)
+        tr, ip = _np(train_rows, np.int64), _np(init_pos, np.int64)
+        pr, pi = _np(pq_rows, np.int64), _np(pq_init, np.int64)
+        p = BuildParams(int(nlist), int(iters), METRIC_L2, QUANT_PQ, int(pq_m), int(pq_bits),
+                        _ptr(tr), tr.shape[0], _ptr(ip), _ptr(pr), pr.shape[0], _ptr(pi))
+        h = C.c_void_p()
+        _check(load().bbc_build_index(device, _ptr(b), b.shape[0], b.shape[1], C.byref(p), C.byref(h)))
+        return cls(h.value, device)
+
     def free(self):
         if self._h and self._h.value:
             load().bbc_index_free(self._h)
@@ -221,6 +242,26 @@ class Index:
         _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                  _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
+
+    def search_counts(self, queries, k, nprobe, ratio: float = 2.0, buckets: int = 0, nsample: int = 0):
+        """Host search returning only per-query sizes: S, K_c, rechecked lists,
+        threshold-bucket size."""
+        q = _np(queries, np.float32)
+        nq = q.shape[0]
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        r = dict(n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64), n_recheck=np.empty(nq, np.int32),
+                 n_boundary=np.empty(nq, np.int64))
+        ids = np.empty(int(off[-1]), np.int64)
+        dists = np.empty(int(off[-1]), np.float32)
+        counts = np.empty(nq, np.int32)
+        tr = SearchTrace(**{f: _ptr(v) for f, v in r.items()})
+        p = self._params(ratio, "bucket", buckets, nsample, 0, None)
+        _check(load().bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                        _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
+        return r
 
     def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
                       nsample: int = 0) -> Dict[str, np.ndarray]:

@@ -23,6 +23,12 @@ int32_t fail(int32_t code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+int32_t bbc::set_error(int32_t code, const std::string& msg) { return fail(code, msg); }
+
+namespace {
+
 #define HIP_TRY(expr)                                                              \
   do {                                                                             \
     hipError_t _e = (expr);                                                        \
@@ -236,6 +242,14 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
 extern "C" {
 
 const char* bbc_last_error(void) { return g_err.c_str(); }
+
+int32_t bbc_build_index(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
+                        bbc_index** out) {
+  if (!p) return fail(BBC_EINVAL, "params is NULL");
+  if (p->quant != BBC_QUANT_PQ) return fail(BBC_EUNSUPPORTED, "quantizer not available in this build");
+  if (p->metric != BBC_METRIC_L2) return fail(BBC_EUNSUPPORTED, "the PQ path supports the L2 metric only");
+  return bbc::build_index_pq(device, base, n, d, p, out);
+}
 
 int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
                             const float* centroids, const int64_t* list_off, const int64_t* list_ids,

@@ -4,7 +4,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
+#include "../../include/bbc.h"
+
 namespace bbc {
+
+// Records the message of a failing call (bbc_last_error) and returns code.
+int32_t set_error(int32_t code, const std::string& msg);
+
+int32_t build_index_pq(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
+                       bbc_index** out);
 
 struct ProbeArgs {
   const float* q; int64_t nq; int d;
