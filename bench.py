@@ -188,10 +188,11 @@ def main():
     for k in ks:
         c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"])
         sizes[k] = dict(S=int(c["n_scanned"].sum()), Kc=int(c["n_cand"].sum()),
-                        recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()))
+                        recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()),
+                        sample_lists_mean=float(c["n_sample_lists"].mean()),
+                        survivors_mean=float(c["n_survivors"].mean()))
     d = w.d
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2
-    launches_per_step = len(ks)
     algo = {
         # re-rank: a d*4-byte row plus its 4-byte slot per candidate
         "rerank": sum(sizes[k]["Kc"] for k in ks) * (4 * d + 4),
@@ -205,8 +206,9 @@ def main():
         if st["launches"] == 0:
             continue
         avg_ms = st["ms"] / st["launches"]
-        bytes_per_launch = algo[name] / launches_per_step
-        gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        bytes_total = algo[name] * args.steps
+        bytes_per_launch = bytes_total / st["launches"]
+        gbs = bytes_total / (st["ms"] * 1e-3) / 1e9
         entry = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
                  "algorithmic_bytes_per_launch": int(bytes_per_launch)}

@@ -98,7 +98,8 @@ typedef struct {
   double ncand_ratio;  /* r >= 1: the collector keeps K_c = min(ceil(r*k), S) candidates */
   int32_t collector;   /* BBC_COLLECT_* */
   int32_t buckets;     /* m in [1, 256]; 0 picks the default */
-  int32_t nsample;     /* nearest probed lists sampled for the codebook; 0 = 8 */
+  int32_t nsample;     /* codebook sample: at least this many nearest probed lists (0 = 8), */
+  int32_t sample_factor; /* ... extended until they hold sample_factor * K_c keys (0 = 2) */
   int32_t device_io;   /* 1: queries and outputs are device pointers on `stream` and the
                           call returns once the work is enqueued; 0: host pointers, the
                           call returns when the results are in place */
@@ -131,6 +132,8 @@ typedef struct {
   int64_t* cand_ids;                         /* candidate ids, ragged by cand_off */
   float* cand_exact;                         /* their exact keys (same order) */
   int64_t* cand_off;                         /* [nq+1] prefix sums of K_c (output) */
+  int32_t* n_sample_lists;                   /* [nq] probed lists in the codebook sample */
+  int64_t* n_survivors;                      /* [nq] keys kept by the relaxed-threshold filter */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and

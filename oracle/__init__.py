@@ -62,7 +62,7 @@ def lib():
             L.orc_codebook.argtypes = [vp, vp, i64, i64, i32, vp, vp, vp]
             L.orc_bucket_of.restype = i32
             L.orc_bucket_of.argtypes = [f32, f32, f32, vp]
-            L.orc_collect_bbc.argtypes = [vp, vp, vp, i32, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_collect_bbc.argtypes = [vp, vp, vp, i32, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_probe.argtypes = [vp, i64, i32, vp, i32, i32, vp, vp, vp, vp]
             L.orc_pq_lut.argtypes = [vp, vp, i32, i32, i32, vp, vp]
             L.orc_pq_key.restype = f32
@@ -165,7 +165,7 @@ def codebook(sample_keys, sample_ids, kc, m):
     return dmin[0], delta[0], mp
 
 
-def collect_bbc(keys, ids, grp_off, kc, m, nsample=8) -> Dict[str, object]:
+def collect_bbc(keys, ids, grp_off, kc, m, nsample=8, sample_factor=2) -> Dict[str, object]:
     """Result-buffer workflow over objects grouped by probed list (nearest first)."""
     keys, ids, grp_off = _f32(keys), _i64(ids), _i64(grp_off)
     ngrp = grp_off.shape[0] - 1
@@ -178,7 +178,7 @@ def collect_bbc(keys, ids, grp_off, kc, m, nsample=8) -> Dict[str, object]:
     ck = np.empty(max(kc, 1), np.float32)
     ci = np.empty(max(kc, 1), np.int64)
     counts = np.zeros(m, np.int64)
-    _check(lib().orc_collect_bbc(_p(keys), _p(ids), _p(grp_off), ngrp, kc, int(m), int(nsample),
+    _check(lib().orc_collect_bbc(_p(keys), _p(ids), _p(grp_off), ngrp, kc, int(m), int(nsample), int(sample_factor),
                                  _p(dmin), _p(delta), _p(mp), _p(tau), _p(s), _p(ck), _p(ci), _p(counts)),
            "collect_bbc")
     return dict(dmin=dmin[0], delta=delta[0], map=mp, tau=int(tau[0]), s=int(s[0]),

@@ -216,19 +216,26 @@ int32_t orc_bucket_of(float key, float dmin, float delta, const uint8_t* map) {
 }
 
 /* The result-buffer workflow (Push / Update / Collect) over objects that
- * arrive grouped by probed list, nearest list first.  The threshold bucket is
+ * arrive grouped by probed list, nearest list first.  The codebook sample is
+ * the nearest lists: at least nsample of them, extended list by list until
+ * the sample holds sample_factor * kc keys (the sample's kc-th key then
+ * bounds the result).  The threshold bucket is
  * refreshed once per list.  Returns the collected candidates (kc of them,
  * buckets below the threshold in arrival order, then the top-s of the
  * threshold bucket by (key, id)), the codebook, the final threshold bucket
  * and s, and the full per-bucket histogram of all keys. */
 int orc_collect_bbc(const float* keys, const int64_t* ids, const int64_t* grp_off, int32_t ngrp,
-                    int64_t kc, int32_t m, int32_t nsample,
+                    int64_t kc, int32_t m, int32_t nsample, int32_t sample_factor,
                     float* dmin_out, float* delta_out, uint8_t* map_out,
                     int32_t* tau_out, int64_t* s_out,
                     float* cand_keys, int64_t* cand_ids, int64_t* counts_full) {
   int64_t total = grp_off[ngrp];
   if (kc > total) kc = total;
+  /* the sample: the nearest lists, at least nsample of them and then more
+   * until they hold sample_factor * kc keys (so that d_max, the sample's
+   * kc-th key, lies beyond the kc-th key of the whole scan) */
   int32_t ns_grp = nsample < ngrp ? nsample : ngrp;
+  while (ns_grp < ngrp && grp_off[ns_grp] < (int64_t)sample_factor * kc) ++ns_grp;
   int64_t ns = grp_off[ns_grp];
   int rc = orc_codebook(keys, ids, ns, kc, m, dmin_out, delta_out, map_out);
   if (rc) return rc;

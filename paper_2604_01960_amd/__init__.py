@@ -37,7 +37,8 @@ class BBCError(RuntimeError):
 
 class SearchParams(C.Structure):
     _fields_ = [("ncand_ratio", C.c_double), ("collector", C.c_int32), ("buckets", C.c_int32),
-                ("nsample", C.c_int32), ("device_io", C.c_int32), ("stream", C.c_void_p)]
+                ("nsample", C.c_int32), ("sample_factor", C.c_int32), ("device_io", C.c_int32),
+                ("stream", C.c_void_p)]
 
 
 class BuildParams(C.Structure):
@@ -50,7 +51,8 @@ class BuildParams(C.Structure):
 class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
-        "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off")]
+        "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off",
+        "n_sample_lists", "n_survivors")]
 
 
 _lib = None
@@ -198,16 +200,16 @@ class Index:
         return out
 
     def query_bytes(self, k: int, nprobe: int, ratio: float = 2.0) -> int:
-        p = SearchParams(float(ratio), 0, 0, 0, 0, None)
+        p = SearchParams(float(ratio), 0, 0, 0, 0, 0, None)
         v = load().bbc_query_bytes(self._h, int(k), int(nprobe), C.byref(p))
         if v < 0:
             _check(int(v))
         return int(v)
 
     # -- search --------------------------------------------------------------
-    def _params(self, ratio, collector, buckets, nsample, device_io, stream):
+    def _params(self, ratio, collector, buckets, nsample, device_io, stream, sample_factor=0):
         return SearchParams(float(ratio), COLLECT[collector] if isinstance(collector, str) else int(collector),
-                            int(buckets), int(nsample), int(device_io), stream)
+                            int(buckets), int(nsample), int(sample_factor), int(device_io), stream)
 
     def search(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
                nsample: int = 0, out=None, stream=None):
@@ -253,7 +255,8 @@ class Index:
         off = np.zeros(nq + 1, np.int64)
         off[1:] = np.cumsum(kk)
         r = dict(n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64), n_recheck=np.empty(nq, np.int32),
-                 n_boundary=np.empty(nq, np.int64))
+                 n_boundary=np.empty(nq, np.int64), n_sample_lists=np.empty(nq, np.int32),
+                 n_survivors=np.empty(nq, np.int64))
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)

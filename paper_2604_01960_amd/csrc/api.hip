@@ -155,6 +155,9 @@ struct bbc_index {
   std::vector<int64_t> h_list_off;
   std::vector<int64_t> h_maxS;  // h_maxS[p] = sum of the p largest list sizes
   int max_lds = 65536;
+  int num_cu = 256;
+  int nxcd = 8;
+  int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -233,6 +236,15 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   int lds = 0;
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) == hipSuccess && lds > 0)
     ix->max_lds = lds;
+  int v = 0;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, ix->device) == hipSuccess && v > 0)
+    ix->num_cu = v;
+  if (hipDeviceGetAttribute(&v, hipDeviceAttributeNumberOfXccs, ix->device) == hipSuccess && v > 0)
+    ix->nxcd = v;
+  if (const char* sv = std::getenv("BBC_SCAN_VARIANT")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 2) ix->scan_variant = x;
+  }
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
   return BBC_OK;
 }
@@ -419,6 +431,7 @@ namespace {
 
 struct Layout {
   // offsets into the arena
+  size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts,
       t_nb;
@@ -434,6 +447,7 @@ int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, c
   if (!(p->ncand_ratio >= 1.0) || !std::isfinite(p->ncand_ratio)) return fail(BBC_EINVAL, "ncand_ratio must be >= 1");
   if (p->buckets < 0 || p->buckets > 256) return fail(BBC_EINVAL, "buckets must be in [0, 256]");
   if (p->nsample < 0) return fail(BBC_EINVAL, "nsample must be >= 0");
+  if (p->sample_factor < 0 || p->sample_factor > 64) return fail(BBC_EINVAL, "sample_factor must be in [0, 64]");
   if (p->collector != BBC_COLLECT_BUCKET) return fail(BBC_EUNSUPPORTED, "collector not available");
   if (out_off[0] != 0) return fail(BBC_EINVAL, "out_offsets[0] must be 0");
   for (int64_t i = 0; i < nq; ++i) {
@@ -462,16 +476,25 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const bool host_io = p->device_io == 0;
   const int m = p->buckets ? p->buckets : 256;
   const int nsample = p->nsample ? p->nsample : 8;
+  const int sample_factor = p->sample_factor ? p->sample_factor : 2;
   const int d = ix->d;
   const bool tracing = tr != nullptr;
 
   // host-side metadata: per query k, nprobe, and prefix offsets
-  std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq);
+  std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq),
+      sample_off(nq + 1, 0), surv_off(nq + 1, 0);
   int64_t max_kc = 0;
+  const int64_t max_list = ix->h_maxS[1];
   for (int64_t i = 0; i < nq; ++i) {
     probe_off[i + 1] = probe_off[i] + nprobe[i];
-    key_off[i + 1] = key_off[i] + ix->h_maxS[nprobe[i]];
     int64_t cap = kc_cap_of(ix, k[i], nprobe[i], p->ncand_ratio);
+    // the sample stops at the first list that brings it to K_c keys
+    const int64_t scap = std::min(ix->h_maxS[nprobe[i]],
+                                  std::max(ix->h_maxS[std::min(nsample, nprobe[i])],
+                                           (int64_t)sample_factor * cap + max_list));
+    sample_off[i + 1] = sample_off[i] + scap;
+    surv_off[i + 1] = surv_off[i] + ix->h_maxS[nprobe[i]];
+    key_off[i + 1] = key_off[i] + (tracing ? ix->h_maxS[nprobe[i]] : 0);
     kc_target[i] = (int64_t)std::ceil(p->ncand_ratio * (double)k[i]);
     cand_off[i + 1] = cand_off[i] + cap;
     max_kc = std::max(max_kc, cap);
@@ -481,10 +504,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const int64_t ncand = cand_off[nq];
   const int64_t nout = out_off[nq];
 
-  // metadata block: k i32[nq] | nprobe i32[nq] | probe_off i64 | key_off i64 | kc_target i64 | cand_off i64 | out_off i64
+  // metadata block (one upload): k, nprobe, then the prefix arrays
   Plan mp;
   size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),
-         m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1));
+         m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)),
+         m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1));
   Plan pl;
   Layout L{};
   L.meta = pl.add(mp.total);
@@ -495,7 +519,19 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.rank_off = pl.add(8 * npairs);
   L.n_scanned = pl.add(8 * nq);
   L.n_recheck = pl.add(4 * nq);
-  L.keys = pl.add(4 * nkeys);
+  L.nsample_q = pl.add(4 * nq);
+  L.keys = tracing ? pl.add(4 * nkeys) : 0;
+  L.sample_keys = pl.add(4 * sample_off[nq]);
+  L.surv_key = pl.add(4 * surv_off[nq]);
+  L.surv_pos = pl.add(4 * surv_off[nq]);
+  L.pair_nsurv = pl.add(4 * npairs);
+  L.surv_bucket = pl.add(surv_off[nq]);
+  L.surv_total = pl.add(4 * nq);
+  L.n_rejected = pl.add(4 * nq);
+  L.books = pl.add(sizeof(bbc::QueryBook) * nq);
+  L.pair_cnt = pl.add(4 * 2 * (size_t)ix->nlist);
+  L.sorted_pairs = pl.add(4 * bbc::pair_slots(npairs, ix->nlist));
+  L.pair_split = pl.add(8);
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
@@ -529,6 +565,8 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::memcpy(H + m_kt, kc_target.data(), 8 * nq);
   std::memcpy(H + m_co, cand_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
+  std::memcpy(H + m_so, sample_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_vo, surv_off.data(), 8 * (nq + 1));
   char* M = A + L.meta;
   HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
   HIP_TRY(hipEventRecord(ix->meta_done, s));
@@ -544,6 +582,8 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const int64_t* d_kt = reinterpret_cast<const int64_t*>(M + m_kt);
   const int64_t* d_co = reinterpret_cast<const int64_t*>(M + m_co);
   const int64_t* d_oo = reinterpret_cast<const int64_t*>(M + m_oo);
+  const int64_t* d_so = reinterpret_cast<const int64_t*>(M + m_so);
+  const int64_t* d_vo = reinterpret_cast<const int64_t*>(M + m_vo);
   int64_t* d_oid = host_io ? reinterpret_cast<int64_t*>(A + L.out_ids) : out_ids;
   float* d_odist = host_io ? reinterpret_cast<float*>(A + L.out_dists) : out_dists;
   int32_t* d_ocnt = host_io ? reinterpret_cast<int32_t*>(A + L.out_counts) : out_counts;
@@ -558,33 +598,70 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   pa.rank_off = reinterpret_cast<int64_t*>(A + L.rank_off);
   pa.n_scanned = reinterpret_cast<int64_t*>(A + L.n_scanned);
   pa.n_recheck = reinterpret_cast<int32_t*>(A + L.n_recheck);
+  pa.kc_target = d_kt; pa.nsample = nsample; pa.sample_factor = sample_factor;
+  pa.nsample_q = reinterpret_cast<int32_t*>(A + L.nsample_q);
   {
-    StageScope st(s, 0);  // both probe kernels are timed together as stages 0+1
+    StageScope st(s, 0);  // coarse GEMM and probe select
     HIP_TRY(bbc::launch_probe(pa, s));
   }
+
+  const int bcap = 4096;
+  bbc::QueryBook* books = reinterpret_cast<bbc::QueryBook*>(A + L.books);
+  float* surv_key = reinterpret_cast<float*>(A + L.surv_key);
+  uint32_t* surv_pos = reinterpret_cast<uint32_t*>(A + L.surv_pos);
+  uint32_t* pair_nsurv = reinterpret_cast<uint32_t*>(A + L.pair_nsurv);
+  uint32_t* n_rejected = reinterpret_cast<uint32_t*>(A + L.n_rejected);
+  float* sample_keys = reinterpret_cast<float*>(A + L.sample_keys);
 
   bbc::PqScanArgs sa{};
   sa.q = dq; sa.nq = nq; sa.d = d; sa.cent = ix->cent; sa.M = ix->M; sa.bits = ix->bits;
   sa.codebook = ix->codebook; sa.codes = ix->codes; sa.code_stride = ix->code_stride;
   sa.list_off = ix->list_off; sa.probe_off = d_po; sa.probe_lists = pa.probe_lists; sa.rank_off = pa.rank_off;
-  sa.key_off = d_ko; sa.keys = reinterpret_cast<float*>(A + L.keys); sa.rank_begin = 0; sa.rank_end = 1 << 30;
-  {
-    StageScope st(s, 2);
-    HIP_TRY(bbc::launch_pq_scan(sa, npairs, s));
-  }
+  sa.key_off = d_ko;
+  sa.nlist = ix->nlist; sa.npairs = npairs; sa.num_cu = ix->num_cu; sa.nxcd = ix->nxcd;
+  sa.scan_variant = ix->scan_variant;
+  sa.pair_cnt = reinterpret_cast<uint32_t*>(A + L.pair_cnt);
+  sa.sorted_pairs = reinterpret_cast<uint32_t*>(A + L.sorted_pairs);
+  sa.pair_split = reinterpret_cast<uint32_t*>(A + L.pair_split);
+  sa.nsample_q = pa.nsample_q; sa.sample_keys = sample_keys; sa.sample_off = d_so; sa.books = books;
+  sa.surv_key = surv_key; sa.surv_pos = surv_pos; sa.surv_off = d_vo; sa.pair_nsurv = pair_nsurv;
+  sa.n_rejected = n_rejected;
+  sa.trace_keys = tracing ? reinterpret_cast<float*>(A + L.keys) : nullptr;
 
-  const int bcap = 8192;
   bbc::CollectArgs ca{};
-  ca.nq = nq; ca.keys = sa.keys; ca.key_off = d_ko; ca.n_scanned = pa.n_scanned; ca.nprobe = d_np;
+  ca.nq = nq; ca.n_scanned = pa.n_scanned; ca.nprobe = d_np;
   ca.probe_off = d_po; ca.probe_lists = pa.probe_lists; ca.rank_off = pa.rank_off; ca.list_off = ix->list_off;
   ca.list_ids = ix->list_ids; ca.pos_of_id = ix->pos_of_id; ca.kc_target = d_kt; ca.cand_off = d_co; ca.m = m;
-  ca.nsample = nsample; ca.bcap = bcap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
+  ca.nsample_q = pa.nsample_q; ca.bcap = bcap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
   ca.n_cand = reinterpret_cast<int64_t*>(A + L.n_cand);
+  ca.sample_keys = sample_keys; ca.sample_off = d_so; ca.books = books;
+  ca.surv_key = surv_key; ca.surv_pos = surv_pos; ca.surv_off = d_vo; ca.pair_nsurv = pair_nsurv;
+  ca.surv_total = reinterpret_cast<uint32_t*>(A + L.surv_total);
+  ca.surv_bucket = reinterpret_cast<uint8_t*>(A + L.surv_bucket);
+  ca.n_rejected = n_rejected;
   if (tracing) {
     ca.t_dmin = reinterpret_cast<float*>(A + L.t_dmin); ca.t_delta = reinterpret_cast<float*>(A + L.t_delta);
     ca.t_map = reinterpret_cast<uint8_t*>(A + L.t_map); ca.t_tau = reinterpret_cast<int32_t*>(A + L.t_tau);
     ca.t_s = reinterpret_cast<int64_t*>(A + L.t_s); ca.t_counts = reinterpret_cast<int32_t*>(A + L.t_counts);
     ca.t_nboundary = reinterpret_cast<int64_t*>(A + L.t_nb);
+  }
+
+  // scan of the sample lists, codebook, scan of the rest through the filter,
+  // then the collector over the survivors
+  {
+    StageScope st(s, 2);
+    HIP_TRY(bbc::launch_pair_sort(sa, s));
+    sa.mode = 0;
+    HIP_TRY(bbc::launch_pq_scan(sa, s));
+  }
+  {
+    StageScope st(s, 3);
+    HIP_TRY(bbc::launch_codebook(ca, s));
+  }
+  {
+    StageScope st(s, 2);
+    sa.mode = 1;
+    HIP_TRY(bbc::launch_pq_scan(sa, s));
   }
   {
     StageScope st(s, 3);
@@ -610,8 +687,9 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     HIP_TRY(hipMemcpyAsync(cand_packed_h.data(), ra.cand_packed, 8 * ncand, hipMemcpyDeviceToHost, s));
   }
 
-  int run = 8192;
-  if (ix->max_lds >= (int)(16384 * sizeof(uint64_t) + 4096)) run = 16384;
+  // final top-k LDS: `run` packed items (dynamic) + ~18 KB of static tables
+  int run = 1024;
+  while ((int64_t)(2 * run) * 8 + 20480 <= ix->max_lds && run < 16384) run *= 2;
   bbc::FinalArgs fa{};
   fa.nq = nq; fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
@@ -641,12 +719,17 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     if ((rc = cp(tr->s, L.t_s, 8 * nq))) return rc;
     if ((rc = cp(tr->bucket_counts, L.t_counts, 4 * nq * m))) return rc;
     if ((rc = cp(tr->n_boundary, L.t_nb, 8 * nq))) return rc;
+    if ((rc = cp(tr->n_sample_lists, L.nsample_q, 4 * nq))) return rc;
+    std::vector<uint32_t> nsurv(nq);
+    HIP_TRY(hipMemcpyAsync(nsurv.data(), A + L.surv_total, 4 * nq, hipMemcpyDeviceToHost, s));
     std::vector<int64_t> nsc(nq);
     HIP_TRY(hipMemcpyAsync(nsc.data(), A + L.n_scanned, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(n_cand_h.data(), A + L.n_cand, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (tr->n_scanned) std::memcpy(tr->n_scanned, nsc.data(), 8 * nq);
     if (tr->n_cand) std::memcpy(tr->n_cand, n_cand_h.data(), 8 * nq);
+    if (tr->n_survivors)
+      for (int64_t i = 0; i < nq; ++i) tr->n_survivors[i] = nsurv[i];
     if (tr->est_off) {
       tr->est_off[0] = 0;
       for (int64_t i = 0; i < nq; ++i) tr->est_off[i + 1] = tr->est_off[i] + nsc[i];

@@ -165,7 +165,7 @@ struct Assigner {
       a.cent_norm2 = cn2.p; a.cent_norm = cn.p; a.nlist = nlist; a.metric = 0;
       a.nprobe = nprobe.p; a.probe_off = probe_off.p; a.list_off = list_off.p;
       a.dprime = dprime.p; a.probe_lists = lists.p; a.probe_keys = pkeys.p; a.rank_off = rank_off.p;
-      a.n_scanned = nsc.p; a.n_recheck = nullptr;
+      a.n_scanned = nsc.p; a.n_recheck = nullptr; a.kc_target = nullptr; a.nsample_q = nullptr;
       BTRY(bbc::launch_probe(a, 0));
       BTRY(hipMemcpy(out + r0, lists.p, 4 * nr, hipMemcpyDeviceToHost));
     }

@@ -2,31 +2,38 @@
 // paper: Push / Update / Collect, the codebook from a sample of the nearest
 // clusters, and the bucket-id equation).
 //
-// One block of 1024 threads per query, over the query's estimated keys
-// (already in the key scratch, in probe order):
-//  1. Codebook.  The sample is the keys of the first nsample probed lists.
-//     T = min(K_c, |sample|); d_min / d_max are the smallest and the T-th
-//     smallest sample key; delta = (d_max - d_min) / 256 (1 if that is not
-//     positive); the 256 equal-width cells are mapped onto m buckets of equal
-//     depth w.r.t. the sample's T smallest keys:
-//     map[e] = min(m-1, floor(m * C_<e / T)).
-//  2. Histogram.  bucket(key) = map[clamp(floor((key - d_min)/delta),0,255)],
-//     counted in LDS over all S keys.
-//  3. Update.  tau = first bucket whose running count reaches K_c;
-//     s = K_c - (count below tau).  Because the per-list cadence of the
-//     paper only ever lowers tau, the final tau of the once-per-list Update
-//     equals the tau of the full histogram.
-//  4. Collect.  Every object of a bucket below tau is a candidate; the
-//     threshold bucket's objects are sorted by (key, id) in LDS and its
-//     first s are added.  A threshold bucket larger than the LDS buffer is
-//     resolved by an exact 64-bit radix select over its members instead.
-// The result is exactly the K_c smallest (key, id): the definition of the
-// collector's output.  Slots are taken by LDS atomics, so the order of
-// candidates in the buffer is arbitrary; the set is not.
+// The path runs in two kernels here, one block of 1024 threads per query:
+//  * codebook_kernel, after the scan of the first nsample probed lists (the
+//    sample).  T = min(K_c, |sample|); d_min / d_max are the smallest and the
+//    T-th smallest sample key; delta = (d_max - d_min) / 256 (1 if that is
+//    not positive); the 256 equal-width cells are mapped onto m buckets of
+//    equal depth w.r.t. the sample's T smallest keys:
+//    map[e] = min(m-1, floor(m * C_<e / T)).  When the sample already holds
+//    K_c keys, d_max is a relaxed threshold: at least K_c scanned keys are
+//    <= d_max, so no key above it can be a candidate, and every key above it
+//    falls in the last cell.  Such keys are only counted (the "Push" of the
+//    paper rejects them); the others are appended to the query's survivor
+//    list as (key, list slot).  The sample's own keys go through the same
+//    filter here; the remaining lists go through it in the scan kernel.
+//  * collect_bucket_kernel over the survivors.  Histogram with
+//    bucket(key) = map[clamp(floor((key - d_min)/delta), 0, 255)] (the
+//    rejected keys are added to the last cell's bucket, so the counts are
+//    those of all scanned keys); Update: tau = first bucket whose running
+//    count reaches K_c, s = K_c - (count below tau); Collect: every survivor
+//    of a bucket below tau, plus the first s of bucket tau by (key, id),
+//    sorted in LDS (an exact radix select when they do not fit).
+// Because the per-list cadence of the paper only ever lowers tau, the tau of
+// the full histogram equals the final tau of the once-per-list Update, and
+// the result is exactly the K_c smallest (key, id).  Candidate slots come
+// from LDS atomics, so their order is arbitrary; the set is not.
 #include "common.h"
 #include "kernels.h"
 
 namespace bbc {
+
+constexpr int COLLECT_RANKCAP = 2048;
+constexpr int COLLECT_CHUNKCAP = 4096;  // 64-survivor chunks mapped to their run by an LDS table
+constexpr int COLLECT_UNROLL = 4;       // chunks a wave has in flight
 
 __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restrict__ rank_off,
                                                const int32_t* __restrict__ lists,
@@ -39,12 +46,9 @@ __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restr
   return list_off[lists[lo]] + (i - rank_off[lo]);
 }
 
-__global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
+__global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
   constexpr int NT = 1024;
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* bbuf = reinterpret_cast<uint64_t*>(smem);  // [bcap], bcap a power of two
   __shared__ uint32_t hist[256];
-  __shared__ uint32_t counts[BBC_MAX_BUCKETS];
   __shared__ uint8_t cmap[256];
   __shared__ uint32_t bc[8];
   __shared__ float fbc[2];
@@ -57,25 +61,33 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int64_t po = a.probe_off[qi];
   const int64_t* rank_off = a.rank_off + po;
   const int32_t* lists = a.probe_lists + po;
-  const float* keys = a.keys + a.key_off[qi];
+  const float* keys = a.sample_keys + a.sample_off[qi];
   const int m = a.m;
-  if (kc <= 0) {
-    if (threadIdx.x == 0) {
-      a.n_cand[qi] = 0;
-      if (a.t_tau) { a.t_tau[qi] = -1; a.t_s[qi] = 0; a.t_dmin[qi] = 0.f; a.t_delta[qi] = 1.f; }
-    }
-    if (a.t_map) for (int e = threadIdx.x; e < 256; e += NT) a.t_map[qi * 256 + e] = 0;
-    if (a.t_counts) for (int b = threadIdx.x; b < m; b += NT) a.t_counts[qi * m + b] = 0;
-    return;
-  }
+  QueryBook* book = a.books + qi;
 
-  // ---- 1. codebook from the sample ------------------------------------
-  const int nsr = a.nsample < np ? a.nsample : np;
+  const int nsr = a.nsample_q[qi];
   const int64_t Ts = nsr < np ? rank_off[nsr] : S;
+  __shared__ int32_t s_rbeg[COLLECT_RANKCAP];
+  __shared__ int32_t s_lbeg[COLLECT_RANKCAP];
+  const bool lds_ranks = nsr <= COLLECT_RANKCAP;
+  if (lds_ranks)
+    for (int r = threadIdx.x; r < nsr; r += NT) {
+      s_rbeg[r] = (int32_t)rank_off[r];
+      s_lbeg[r] = (int32_t)a.list_off[lists[r]];
+    }
+  auto pos_of = [&](int64_t i) -> int64_t {
+    if (!lds_ranks) return slot_to_pos(i, rank_off, lists, a.list_off, nsr);
+    int lo = 0, hi = nsr - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (s_rbeg[mid] <= i) lo = mid; else hi = mid - 1;
+    }
+    return (int64_t)s_lbeg[lo] + (i - s_rbeg[lo]);
+  };
   const int64_t T = kc < Ts ? kc : Ts;
+  uint32_t dmax_b = 0;
   if (T > 0) {
-    uint32_t dmax_b = block_radix_select32<NT>([&](int64_t i) { return key_bits(keys[i]); }, Ts, T - 1,
-                                               hist, bc);
+    dmax_b = block_radix_select32<NT>([&](int64_t i) { return key_bits(keys[i]); }, Ts, T - 1, hist, bc);
     if (threadIdx.x == 0) bc[4] = 0xffffffffu;
     __syncthreads();
     uint32_t mn = 0xffffffffu;
@@ -88,9 +100,10 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     const float dmax = bits_key(dmax_b);
     float delta = (dmax - dmin) / 256.0f;
     if (!(delta > 0.0f)) delta = 1.0f;
-    for (int64_t i = threadIdx.x; i < Ts; i += NT) {
-      float k = keys[i];
-      if (key_bits(k) < dmax_b) atomicAdd(&hist[cell_of(k, dmin, delta)], 1u);
+    for (int64_t base = 0; base < Ts; base += NT) {
+      const int64_t i = base + threadIdx.x;
+      const float k = i < Ts ? keys[i] : 0.0f;
+      wave_hist_add(hist, (uint32_t)cell_of(k, dmin, delta), i < Ts && key_bits(k) < dmax_b);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -105,22 +118,206 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
       }
       fbc[0] = dmin;
       fbc[1] = delta;
+      // reject above d_max only when the sample alone holds K_c keys and the
+      // cells are proper (then every key above d_max is in cell 255)
+      bc[5] = (Ts >= kc && dmax > dmin) ? 1u : 0u;
     }
   } else if (threadIdx.x == 0) {
     for (int e = 0; e < 256; ++e) cmap[e] = 0;
     fbc[0] = 0.0f;
     fbc[1] = 1.0f;
+    bc[5] = 0u;
   }
+  if (threadIdx.x == 0) { bc[6] = 0; bc[7] = 0; }
+  __syncthreads();
+  const uint32_t prune = bc[5];
+  for (int e = threadIdx.x; e < 256; e += NT) book->map[e] = cmap[e];
+  if (threadIdx.x == 0) {
+    book->dmin = fbc[0];
+    book->delta = fbc[1];
+    book->dmax_bits = dmax_b;
+    book->prune = prune;
+  }
+  // the sample's keys through the relaxed-threshold filter
+  float* skey = a.surv_key + a.surv_off[qi];
+  uint32_t* spos = a.surv_pos + a.surv_off[qi];
+  uint32_t n_rej = 0;
+  for (int64_t i = threadIdx.x; i < Ts; i += NT) {
+    const float k = keys[i];
+    const bool keep = !prune || key_bits(k) <= dmax_b;
+    const uint32_t slot = wave_slot(keep, &bc[6]);
+    if (keep) {
+      skey[slot] = k;
+      spos[slot] = (uint32_t)pos_of(i);
+    } else {
+      ++n_rej;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) n_rej += __shfl_xor(n_rej, off);
+  if ((threadIdx.x & 63) == 0 && n_rej) atomicAdd(&bc[7], n_rej);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a.n_rejected[qi] = bc[7];
+    a.pair_nsurv[po] = bc[6];  // the sample's survivors form rank 0's run
+  }
+  for (int r = 1 + threadIdx.x; r < nsr; r += NT) a.pair_nsurv[po + r] = 0;
+}
+
+__global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
+  constexpr int NT = 1024;
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* bbuf = reinterpret_cast<uint64_t*>(smem);  // [bcap], bcap a power of two
+  __shared__ uint32_t s_pref[COLLECT_RANKCAP + 1];
+  __shared__ uint32_t s_rbeg[COLLECT_RANKCAP];
+  __shared__ uint32_t s_nsurv[COLLECT_RANKCAP];
+  __shared__ uint16_t s_crank[COLLECT_CHUNKCAP];
+  __shared__ uint32_t hist[256];
+  __shared__ uint32_t counts[BBC_MAX_BUCKETS];
+  __shared__ uint8_t cmap[256];
+  __shared__ uint32_t bc[8];
+
+  const int64_t qi = blockIdx.x;
+  const int64_t S = a.n_scanned[qi];
+  int64_t kc = a.kc_target[qi];
+  if (kc > S) kc = S;
+  const int m = a.m;
+  const QueryBook* book = a.books + qi;
+  if (kc <= 0) {
+    if (threadIdx.x == 0) {
+      a.n_cand[qi] = 0;
+      if (a.t_tau) { a.t_tau[qi] = -1; a.t_s[qi] = 0; a.t_dmin[qi] = 0.f; a.t_delta[qi] = 1.f; a.t_nboundary[qi] = 0; }
+      if (a.surv_total) a.surv_total[qi] = 0;
+    }
+    if (a.t_map) for (int e = threadIdx.x; e < 256; e += NT) a.t_map[qi * 256 + e] = 0;
+    if (a.t_counts) for (int b = threadIdx.x; b < m; b += NT) a.t_counts[qi * m + b] = 0;
+    return;
+  }
+  for (int e = threadIdx.x; e < 256; e += NT) cmap[e] = book->map[e];
   for (int b = threadIdx.x; b < m; b += NT) counts[b] = 0;
+  if (threadIdx.x == 0) bc[4] = 0;
   __syncthreads();
-  const float dmin = fbc[0], delta = fbc[1];
+  const float dmin = book->dmin, delta = book->delta;
+  const int np = a.nprobe[qi];
+  const int64_t po = a.probe_off[qi];
+  const int64_t* rank_off = a.rank_off + po;
+  const uint32_t* nsurv = a.pair_nsurv + po;
+  const float* skey = a.surv_key + a.surv_off[qi];
+  const uint32_t* spos = a.surv_pos + a.surv_off[qi];
+  uint8_t* sbkt = a.surv_bucket + a.surv_off[qi];
+  // Survivors sit in per-rank runs [rank_off[r], rank_off[r] + nsurv[r]).
+  // The runs are cut into 64-element chunks (an LDS prefix of chunk counts,
+  // and a chunk -> run table when it fits); a wave takes COLLECT_UNROLL
+  // consecutive chunks at a time and issues all their loads before using
+  // them.  Probes wider than the LDS tables walk the runs one by one.
+  const bool flat = np <= COLLECT_RANKCAP;
+  if (flat && threadIdx.x < 64) {
+    const int lane = threadIdx.x;
+    uint32_t carry = 0;
+    for (int base = 0; base < np; base += 64) {
+      const int r = base + lane;
+      const uint32_t ns = r < np ? nsurv[r] : 0u;
+      const uint32_t v = (ns + 63u) / 64u;
+      uint32_t incl = v;
+      for (int off = 1; off < 64; off <<= 1) {
+        uint32_t o = __shfl_up(incl, off);
+        if (lane >= off) incl += o;
+      }
+      if (r < np) {
+        s_pref[r] = carry + incl - v;
+        s_rbeg[r] = (uint32_t)rank_off[r];
+        s_nsurv[r] = ns;
+      }
+      carry += __shfl(incl, 63);
+    }
+    if (lane == 0) s_pref[np] = carry;
+  }
+  __syncthreads();
+  const uint32_t nchunks = flat ? s_pref[np] : 0u;
+  const bool table = flat && nchunks <= (uint32_t)COLLECT_CHUNKCAP;
+  if (table)
+    for (int r = threadIdx.x; r < np; r += NT)
+      for (uint32_t ch = s_pref[r]; ch < s_pref[r + 1]; ++ch) s_crank[ch] = (uint16_t)r;
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  constexpr int U = COLLECT_UNROLL;
+  constexpr int NW = NT / 64;
+  // For every survivor: v = load(active, slot), then use(active, slot, v); the
+  // trip counts are wave-uniform (use() may take wave-wide collectives).
+  auto for_each_wave = [&](auto load, auto use) {
+    using V = decltype(load(false, (int64_t)0));
+    if (flat) {
+      for (uint32_t c0 = (uint32_t)wv * U; c0 < nchunks; c0 += NW * U) {
+        bool act[U];
+        int64_t idx[U];
+        V v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const uint32_t ch = c0 + u;
+          act[u] = false;
+          idx[u] = 0;
+          if (ch < nchunks) {
+            int r;
+            if (table) {
+              r = s_crank[ch];
+            } else {
+              int lo = 0, hi = np - 1;
+              while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_pref[mid] <= ch) lo = mid; else hi = mid - 1;
+              }
+              r = lo;
+            }
+            const uint32_t e = (ch - s_pref[r]) * 64u + lane;
+            act[u] = e < s_nsurv[r];
+            idx[u] = (int64_t)s_rbeg[r] + e;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = load(act[u], idx[u]);
+#pragma unroll
+        for (int u = 0; u < U; ++u) use(act[u], idx[u], v[u]);
+      }
+    } else {
+      for (int r = 0; r < np; ++r) {
+        const int64_t rb = rank_off[r];
+        const int64_t rn = nsurv[r];
+        for (int64_t base = 0; base < rn; base += NT) {
+          const bool act = base + threadIdx.x < rn;
+          const int64_t i = rb + base + threadIdx.x;
+          use(act, i, load(act, i));
+        }
+      }
+    }
+  };
+  auto for_each = [&](auto fn) {
+    for_each_wave([&](bool act, int64_t i) { return 0; },
+                  [&](bool act, int64_t i, int) { if (act) fn(i); });
+  };
 
-  // ---- 2. histogram of all keys ----------------------------------------
-  for (int64_t i = threadIdx.x; i < S; i += NT)
-    atomicAdd(&counts[cmap[cell_of(keys[i], dmin, delta)]], 1u);
+  // ---- histogram (rejected keys all sit in the last cell); each survivor's
+  // bucket is kept for the collection pass --------------------------------
+  {
+    uint32_t n_last = 0, n_all = 0;
+    for_each_wave([&](bool act, int64_t i) { return act ? skey[i] : 0.0f; },
+                  [&](bool act, int64_t i, float key) {
+                    const int c = act ? cell_of(key, dmin, delta) : 255;
+                    const uint32_t b = cmap[c];
+                    if (act) sbkt[i] = (uint8_t)b;
+                    n_all += act;
+                    n_last += act && c == 255;
+                    wave_hist_add(counts, b, act && c != 255);
+                  });
+    for (int off = 32; off >= 1; off >>= 1) {
+      n_last += __shfl_xor(n_last, off);
+      n_all += __shfl_xor(n_all, off);
+    }
+    if (lane == 0 && n_last) atomicAdd(&counts[cmap[255]], n_last);
+    if (lane == 0 && n_all) atomicAdd(&bc[4], n_all);
+    if (threadIdx.x == 0 && a.n_rejected[qi]) atomicAdd(&counts[cmap[255]], (uint32_t)a.n_rejected[qi]);
+  }
   __syncthreads();
 
-  // ---- 3. Update: threshold bucket and s ---------------------------------
+  // ---- Update: threshold bucket and s ---------------------------------------
   if (threadIdx.x == 0) {
     int64_t cum = 0;
     int tau = m - 1;
@@ -132,6 +329,7 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     bc[1] = (uint32_t)cum;      // objects strictly below tau
     bc[2] = 0;                  // candidate slot counter
     bc[3] = 0;                  // boundary slot counter
+    if (a.surv_total) a.surv_total[qi] = bc[4];
   }
   __syncthreads();
   const int tau = (int)bc[0];
@@ -140,21 +338,14 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int bcap = a.bcap;
   uint32_t* cand = a.cand_pos + a.cand_off[qi];
 
-  // ---- 4. Collect -----------------------------------------------------------
-  for (int64_t i = threadIdx.x; i < S; i += NT) {
-    float k = keys[i];
-    int b = cmap[cell_of(k, dmin, delta)];
-    if (b < tau) {
-      uint32_t slot = atomicAdd(&bc[2], 1u);
-      cand[slot] = (uint32_t)slot_to_pos(i, rank_off, lists, a.list_off, np);
-    } else if (b == tau) {
-      uint32_t bs = atomicAdd(&bc[3], 1u);
-      if ((int)bs < bcap) {
-        int64_t pos = slot_to_pos(i, rank_off, lists, a.list_off, np);
-        bbuf[bs] = pack_key_id(k, (uint32_t)a.list_ids[pos]);
-      }
-    }
-  }
+  // ---- Collect -----------------------------------------------------------------
+  for_each_wave([&](bool act, int64_t i) { return act ? (int)sbkt[i] : m; },
+                [&](bool act, int64_t i, int b) {
+                  const uint32_t slot = wave_slot(b < tau, &bc[2]);
+                  if (b < tau) cand[slot] = spos[i];
+                  const uint32_t bs = wave_slot(b == tau, &bc[3]);
+                  if (b == tau && (int)bs < bcap) bbuf[bs] = pack_key_id(skey[i], (uint32_t)a.list_ids[spos[i]]);
+                });
   __syncthreads();
   const int64_t nb = bc[3];
   if (nb <= bcap) {
@@ -165,24 +356,45 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     for (int64_t r = threadIdx.x; r < s; r += NT)
       cand[nbelow + r] = (uint32_t)a.pos_of_id[packed_id(bbuf[r])];
   } else {
-    // exact selection of the s smallest (key, id) of the threshold bucket
+    // exact selection of the s smallest (key, id) of the threshold bucket:
+    // 64-bit radix select over its members, then one pass to collect them
     auto get = [&](int64_t i, uint64_t& v) -> bool {
-      float k = keys[i];
-      if (cmap[cell_of(k, dmin, delta)] != tau) return false;
-      int64_t pos = slot_to_pos(i, rank_off, lists, a.list_off, np);
-      v = pack_key_id(k, (uint32_t)a.list_ids[pos]);
+      if ((int)sbkt[i] != tau) return false;
+      v = pack_key_id(skey[i], (uint32_t)a.list_ids[spos[i]]);
       return true;
     };
-    uint64_t thr = block_radix_select64<NT>(get, S, s - 1, hist, bc + 4);
+    uint64_t prefix = 0, mask = 0;
+    int64_t rr = s - 1;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+      for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
+      __syncthreads();
+      for_each([&](int64_t i) {
+        uint64_t v;
+        if (get(i, v) && (v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+      });
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int64_t q = rr;
+        uint32_t dg = 0;
+        for (; dg < 255; ++dg) {
+          if (q < (int64_t)hist[dg]) break;
+          q -= hist[dg];
+        }
+        bc[5] = dg;
+        bc[6] = (uint32_t)q;
+      }
+      __syncthreads();
+      prefix |= (uint64_t)bc[5] << shift;
+      mask |= 255ull << shift;
+      rr = bc[6];
+      __syncthreads();
+    }
     if (threadIdx.x == 0) bc[3] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < S; i += NT) {
+    for_each([&](int64_t i) {
       uint64_t v;
-      if (get(i, v) && v <= thr) {
-        uint32_t slot = atomicAdd(&bc[3], 1u);
-        cand[nbelow + slot] = (uint32_t)slot_to_pos(i, rank_off, lists, a.list_off, np);
-      }
-    }
+      if (get(i, v) && v <= prefix) cand[nbelow + atomicAdd(&bc[3], 1u)] = spos[i];
+    });
   }
   if (threadIdx.x == 0) {
     a.n_cand[qi] = kc;
@@ -196,6 +408,12 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   }
   if (a.t_map) for (int e = threadIdx.x; e < 256; e += NT) a.t_map[qi * 256 + e] = cmap[e];
   if (a.t_counts) for (int b = threadIdx.x; b < m; b += NT) a.t_counts[qi * m + b] = (int32_t)counts[b];
+}
+
+hipError_t launch_codebook(const CollectArgs& a, hipStream_t s) {
+  if (a.nq <= 0) return hipSuccess;
+  hipLaunchKernelGGL(codebook_kernel, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s) {

@@ -128,6 +128,34 @@ __device__ void lds_bitonic_sort(uint64_t* v, int n) {
   __syncthreads();
 }
 
+// Values that are equal on every lane, moved to scalar registers (the
+// compiler cannot prove uniformity of values loaded through vector loads).
+__device__ __forceinline__ uint32_t uniform(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int32_t uniform(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uniform(int64_t v) {
+  const uint32_t lo = uniform((uint32_t)v), hi = uniform((uint32_t)((uint64_t)v >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+template <class T>
+__device__ __forceinline__ T* uniform(T* p) {
+  return reinterpret_cast<T*>(uniform((int64_t)reinterpret_cast<uintptr_t>(p)));
+}
+
+// hist[bin] += 1 for every active lane with valid set.  Lanes that share the
+// first valid lane's bin are counted with one ballot and one atomic (keys of
+// one query are concentrated, so most lanes of a wave often share a bin);
+// the others add their own.
+__device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t bin, bool valid) {
+  const uint64_t act = __ballot(valid);
+  if (!act) return;
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  const uint32_t lb = __shfl(bin, leader);
+  const uint64_t same = __ballot(valid && bin == lb);
+  if (lane == leader) atomicAdd(&hist[lb], (uint32_t)__popcll(same));
+  else if (valid && bin != lb) atomicAdd(&hist[bin], 1u);
+}
+
 // Radix select over a block: value of the element of rank r (0-based,
 // ascending) among n 32-bit values produced by get(i).  hist: 256 LDS words;
 // bc: 2 LDS words for broadcast.
@@ -137,9 +165,10 @@ __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += NT) {
-      uint32_t v = get(i);
-      if ((v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+    for (int64_t base = 0; base < n; base += NT) {  // wave-uniform trip count
+      const int64_t i = base + threadIdx.x;
+      const uint32_t v = i < n ? get(i) : 0u;
+      wave_hist_add(hist, (v >> shift) & 255u, i < n && (v & mask) == prefix);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -168,9 +197,11 @@ __device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < n; i += NT) {
-      uint64_t v;
-      if (get(i, v) && (v & mask) == prefix) atomicAdd(&hist[(v >> shift) & 255u], 1u);
+    for (int64_t base = 0; base < n; base += NT) {  // wave-uniform trip count
+      const int64_t i = base + threadIdx.x;
+      uint64_t v = 0;
+      const bool ok = i < n && get(i, v) && (v & mask) == prefix;
+      wave_hist_add(hist, (uint32_t)((v >> shift) & 255u), ok);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -190,6 +221,18 @@ __device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t
     __syncthreads();
   }
   return prefix;
+}
+
+// Slot of this lane among the active lanes of its wave that set `take`, from
+// one atomic per wave on *counter (LDS or global memory).
+__device__ __forceinline__ uint32_t wave_slot(bool take, uint32_t* counter) {
+  const uint64_t mask = __ballot(take);
+  const int lane = threadIdx.x & 63;
+  const int leader = __ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader < 0 ? 0 : leader);
+  return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
 __host__ __device__ __forceinline__ int next_pow2(int x) {

@@ -23,29 +23,66 @@ struct ProbeArgs {
   const int32_t* nprobe; const int64_t* probe_off; const int64_t* list_off;
   float* dprime; int32_t* probe_lists; float* probe_keys; int64_t* rank_off; int64_t* n_scanned;
   int32_t* n_recheck;
+  // codebook sample size: the nearest lists, at least `nsample`, extended
+  // until they hold sample_factor * kc_target keys (all probed lists if they
+  // never do)
+  const int64_t* kc_target; int nsample; int sample_factor; int32_t* nsample_q;
 };
 hipError_t launch_probe(const ProbeArgs& a, hipStream_t s);
 size_t probe_select_lds(int nlist);
+
+// Per-query collector codebook (written by the codebook kernel).
+struct QueryBook {
+  float dmin;
+  float delta;
+  uint32_t dmax_bits;  // key image of d_max
+  uint32_t prune;      // 1: keys above d_max are rejected at the scan
+  uint8_t map[256];    // equal-width cell -> bucket
+};
 
 struct PqScanArgs {
   const float* q; int64_t nq; int d; const float* cent;
   int M; int bits; const float* codebook; const uint8_t* codes; int code_stride;
   const int64_t* list_off; const int64_t* probe_off; const int32_t* probe_lists;
-  const int64_t* rank_off; const int64_t* key_off; float* keys;
-  int rank_begin; int rank_end;
+  const int64_t* rank_off; const int64_t* key_off;
+  int nlist; int64_t npairs; int num_cu; int nxcd;
+  uint32_t* pair_cnt;       // [2*nlist] scratch
+  uint32_t* sorted_pairs;   // [npairs] scratch: sample pairs then the rest, each grouped by list
+  // pairs scanned by this launch: sorted_pairs[0, split) for mode 0 and
+  // [split, total) for mode 1, with pair_split = {split, total} (bins padded
+  // to SCAN_GROUP entries with NO_PAIR)
+  uint32_t* pair_split;
+  int mode;                 // 0: sample lists -> sample_keys by slot; 1: the rest -> filter + survivors
+  const int32_t* nsample_q; // per-query sample size (probe ranks below it are the sample)
+  float* sample_keys; const int64_t* sample_off;
+  const QueryBook* books;
+  // survivors: pair p of query q writes its kept keys, compacted, from slot
+  // surv_off[q] + rank_off[p] on and their number to pair_nsurv[p]
+  float* surv_key; uint32_t* surv_pos; const int64_t* surv_off; uint32_t* pair_nsurv; uint32_t* n_rejected;
+  float* trace_keys;        // optional: every key by slot (key_off regions)
+  int scan_variant;         // grouped-scan block geometry: 0 (512 threads, 2 codes each), 1 (512, 1), 2 (1024, 1)
 };
-hipError_t launch_pq_scan(const PqScanArgs& a, int64_t npairs, hipStream_t s);
+constexpr int SCAN_GROUP = 4;  // queries of one list scanned together
+int64_t pair_slots(int64_t npairs, int nlist);  // sorted_pairs capacity
+// Counting sort of the (query, rank) pairs by (rank >= nsample, list).
+hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s);
+hipError_t launch_pq_scan(const PqScanArgs& a, hipStream_t s);
 
 struct CollectArgs {
   int64_t nq; const float* keys; const int64_t* key_off; const int64_t* n_scanned;
   const int32_t* nprobe; const int64_t* probe_off; const int32_t* probe_lists; const int64_t* rank_off;
   const int64_t* list_off; const int32_t* list_ids; const int32_t* pos_of_id;
-  const int64_t* kc_target; const int64_t* cand_off; int m; int nsample; int bcap;
+  const int64_t* kc_target; const int64_t* cand_off; int m; const int32_t* nsample_q; int bcap;
   uint32_t* cand_pos; int64_t* n_cand;
+  const float* sample_keys; const int64_t* sample_off; QueryBook* books;
+  float* surv_key; uint32_t* surv_pos; const int64_t* surv_off; uint32_t* pair_nsurv; uint32_t* n_rejected;
+  uint32_t* surv_total;     // [nq] survivors per query (written by the collector)
+  uint8_t* surv_bucket;     // bucket of each survivor (collector scratch, same slots as surv_key)
   // trace outputs (all null when tracing is off)
   float* t_dmin; float* t_delta; uint8_t* t_map; int32_t* t_tau; int64_t* t_s; int32_t* t_counts;
   int64_t* t_nboundary;
 };
+hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s);
 
 struct RerankArgs {

@@ -2,16 +2,30 @@
 // precompute query-to-codeword distances and sum them per code; IVF+PQ uses
 // residual codes, one table per (query, probed list)).
 //
-// One block per (query, probe rank).  The block builds the residual table
-// LUT[m][b] = sum_e ((q_e - c_e) - C_m[b][e])^2 in LDS (r = q - c once per
-// element, then sequentially over the sub-vector elements, unfused), and
-// then every thread walks its objects' codes and sums LUT[m][code_m] for
-// m = 0..M-1 in order, starting from +0.  Keys go to the per-query key
-// scratch in probe order, so the keys of the nearest lists come first.
+// Table entry LUT[m][b] = sum_e ((q_e - c_e) - C_m[b][e])^2 with r = q - c
+// computed once per element and the sum taken sequentially over the
+// sub-vector (unfused); key = sum_m LUT[m][code_m] in order from +0.  Keys go
+// to the per-query key scratch in probe order, nearest list first.
+//
+// Scheduling.  The (query, probe rank) pairs are first counting-sorted by
+// (phase, list): the codebook-sample lists of every query first, then the
+// rest; each bin is padded to a multiple of SCAN_GROUP.  A persistent block
+// then takes SCAN_GROUP pairs of one list at a time -- up to four queries
+// probing the same list -- and builds their four tables side by side in LDS
+// ([m][code][query]): every code byte is extracted once and one 16-byte LDS
+// read yields the four queries' entries, each query keeping its own ordered
+// sum.  Each XCD walks one contiguous slice of the sorted groups (workgroups
+// are dispatched round-robin over the XCDs), so the queries of a list are
+// served while its codes sit in that XCD's L2.  Thread t builds table
+// entries t, t+1024, ... reading their codewords from L2.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
 namespace bbc {
+
+constexpr uint32_t NO_PAIR = 0xffffffffu;
 
 __device__ __forceinline__ int64_t find_query(const int64_t* __restrict__ off, int64_t nq, int64_t p) {
   // largest qi with off[qi] <= p (off is non-decreasing, off[0] = 0)
@@ -23,7 +37,329 @@ __device__ __forceinline__ int64_t find_query(const int64_t* __restrict__ off, i
   return lo;
 }
 
-template <int BITS>
+// ---- pair sort by list --------------------------------------------------------
+__global__ void zero_u32_kernel(uint32_t* __restrict__ p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+__device__ __forceinline__ int pair_bin(const PqScanArgs& a, int64_t p) {
+  const int64_t qi = find_query(a.probe_off, a.nq, p);
+  const int rank = (int)(p - a.probe_off[qi]);
+  return (rank >= a.nsample_q[qi] ? a.nlist : 0) + a.probe_lists[p];
+}
+
+__global__ void pair_count_kernel(PqScanArgs a) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npairs; p += (int64_t)gridDim.x * blockDim.x)
+    atomicAdd(&a.pair_cnt[pair_bin(a, p)], 1u);
+}
+
+// In place: per-bin counts -> exclusive prefix of the counts rounded up to a
+// multiple of SCAN_GROUP (one block).  Also records the start of the second
+// phase (bin nlist) and the padded total in split[0], split[1].
+__global__ __launch_bounds__(1024) void pair_offsets_kernel(uint32_t* __restrict__ cnt_fill, int nbins, int nlist,
+                                                            uint32_t* __restrict__ split) {
+  __shared__ uint32_t carry_s;
+  __shared__ uint32_t wsum[16];
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int base = 0; base < nbins; base += 1024) {
+    const int j = base + threadIdx.x;
+    uint32_t v = j < nbins ? (cnt_fill[j] + SCAN_GROUP - 1) / SCAN_GROUP * SCAN_GROUP : 0u;
+    uint32_t incl = v;
+    for (int off = 1; off < 64; off <<= 1) {
+      uint32_t o = __shfl_up(incl, off);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    uint32_t before = carry_s;
+    for (int i = 0; i < w; ++i) before += wsum[i];
+    if (j < nbins) cnt_fill[j] = before + incl - v;
+    if (j == nlist) split[0] = before + incl - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry_s = before + incl;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) split[1] = carry_s;
+}
+
+__global__ void pair_scatter_kernel(PqScanArgs a) {
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npairs; p += (int64_t)gridDim.x * blockDim.x) {
+    uint32_t slot = atomicAdd(&a.pair_cnt[pair_bin(a, p)], 1u);
+    a.sorted_pairs[slot] = (uint32_t)p;
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// Block-wide stream compaction for G output streams at once: every thread
+// of the block calls step() with the keep flags of its O elements
+// (keep[o * G + g]); each kept element gets the next slot of its stream, in
+// (wave, element, lane) order within a call and call order across calls.  One
+// barrier per call; the per-wave counts are double buffered so consecutive
+// calls need no second barrier.
+template <int G, int NT, int O = 1>
+struct BlockCompactor {
+  uint32_t total[G];
+  int parity;
+  __device__ __forceinline__ void reset() {
+#pragma unroll
+    for (int g = 0; g < G; ++g) total[g] = 0;
+    parity = 0;
+  }
+  __device__ __forceinline__ void step(const bool* keep, uint32_t* slot, uint32_t (*wc)[G][NT / 64]) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t below = (1ull << lane) - 1ull;
+    uint64_t mask[O][G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      uint32_t n = 0;
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        mask[o][g] = __ballot(keep[o * G + g]);
+        n += (uint32_t)__popcll(mask[o][g]);
+      }
+      if (lane == 0) wc[parity][g][w] = n;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      uint32_t off = total[g], sum = 0;
+#pragma unroll
+      for (int ww = 0; ww < NT / 64; ++ww) {
+        const uint32_t c = wc[parity][g][ww];
+        if (ww < w) off += c;
+        sum += c;
+      }
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        slot[o * G + g] = off + (uint32_t)__popcll(mask[o][g] & below);
+        off += (uint32_t)__popcll(mask[o][g]);
+      }
+      total[g] += sum;
+    }
+    parity ^= 1;
+  }
+};
+
+// Per-query output of one scanned pair.  Phase 0 (sample lists) writes every
+// key by slot; phase 1 keeps the keys at or below the query's relaxed
+// threshold (all keys when the query does not reject) and writes them,
+// compacted, with their list slot.
+struct PairOut {
+  float* sample_out;
+  float* skey;
+  uint32_t* spos;
+  float* trace_out;
+  uint32_t prune, dmax_bits;
+  __device__ __forceinline__ void init(const PqScanArgs& a, int mode, int64_t qi, int64_t p) {
+    const int64_t ro = uniform(a.rank_off[p]);
+    trace_out = a.trace_keys ? uniform(a.trace_keys + a.key_off[qi] + ro) : nullptr;
+    if (mode == 0) {
+      sample_out = uniform(a.sample_keys + a.sample_off[qi] + ro);
+      prune = 0;
+      dmax_bits = 0;
+    } else {
+      const QueryBook* b = a.books + qi;
+      prune = uniform(b->prune);
+      dmax_bits = uniform(b->dmax_bits);
+      const int64_t so = uniform(a.surv_off[qi]) + ro;
+      skey = a.surv_key + so;
+      spos = a.surv_pos + so;
+    }
+  }
+  __device__ __forceinline__ bool keep(float key) const { return !prune || key_bits(key) <= dmax_bits; }
+};
+
+// ---- persistent grouped scan ----------------------------------------------------
+// One block per CU walks the (list, 4 queries) groups of its XCD's slice.  Per
+// group: the 4 residuals go to LDS, the 4 distance tables are built into one
+// table of float4 rows (entry e holds e's value for the 4 queries, so one LDS
+// read serves all 4), then each thread scans O codes of the list per pass,
+// interleaved, to keep more table reads in flight per wave.  Block geometries
+// (threads NT, codes per thread O) are compiled as variants: (512, 2), the
+// default, (512, 1) and (1024, 1).
+template <int MODE, int BITS, int M, int DSUB, int NT, int O>
+__global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
+  constexpr int G = SCAN_GROUP;
+  constexpr int KSUB = 1 << BITS;
+  constexpr int NENT = M * KSUB;
+  constexpr int EPT = (NENT + NT - 1) / NT;   // table entries owned by each thread
+  constexpr bool REGCB = EPT * DSUB <= 64;    // owned codewords held in registers
+  constexpr int D = M * DSUB;
+  constexpr int CODE_BYTES = BITS == 8 ? M : (M + 1) / 2;
+  constexpr int NVEC = (CODE_BYTES + 15) / 16;
+  static_assert(G == 4, "the table rows are float4");
+  extern __shared__ __align__(16) float4 lut4[];   // [NENT]: entry e for the group's 4 queries
+  __shared__ __align__(16) float res[G][D];
+  __shared__ uint32_t wcnt[2][G][NT / 64];
+
+  // the codebook is the same for every group: the owned codewords are loaded once
+  float creg[REGCB ? EPT : 1][DSUB];
+  if constexpr (REGCB) {
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * NT;
+#pragma unroll
+      for (int t = 0; t < DSUB; ++t) creg[i][t] = e < NENT ? a.codebook[e * DSUB + t] : 0.0f;
+    }
+  }
+
+  const int64_t split = a.pair_split[0], total = a.pair_split[1];
+  const int64_t cbeg = (MODE == 0 ? 0 : split) / G;
+  const int64_t cend = (MODE == 0 ? split : total) / G;
+  const int nx = a.nxcd;
+  const int xcd = blockIdx.x % nx;
+  const int64_t wid = blockIdx.x / nx;
+  const int64_t nw = gridDim.x / nx;
+  const int64_t span = cend - cbeg;
+  const int64_t lo = cbeg + span * xcd / nx;
+  const int64_t hi = cbeg + span * (xcd + 1) / nx;
+  for (int64_t c = lo + wid; c < hi; c += nw) {
+    uint32_t pp[G];
+    int64_t qq[G];
+    bool valid[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      pp[g] = uniform(a.sorted_pairs[c * G + g]);
+      valid[g] = pp[g] != NO_PAIR;
+      qq[g] = valid[g] ? uniform(find_query(a.probe_off, a.nq, pp[g])) : 0;
+    }
+    const int j = uniform(a.probe_lists[pp[0]]);  // the first pair of a group is always real
+    const float* cv = a.cent + (int64_t)j * D;
+    __syncthreads();  // the previous group is done with res and the tables
+    for (int idx = threadIdx.x; idx < G * D; idx += NT) {
+      const int g = idx / D, e = idx % D;
+      float r = 0.0f;
+      if (g == 0) r = a.q[qq[0] * D + e] - cv[e];
+      else if (g == 1 && valid[1]) r = a.q[qq[1] * D + e] - cv[e];
+      else if (g == 2 && valid[2]) r = a.q[qq[2] * D + e] - cv[e];
+      else if (g == 3 && valid[3]) r = a.q[qq[3] * D + e] - cv[e];
+      res[g][e] = r;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+      const int e = threadIdx.x + i * NT;
+      if (e < NENT) {
+        const int m = e / KSUB;
+        float cw[DSUB];
+#pragma unroll
+        for (int t = 0; t < DSUB; ++t) {
+          if constexpr (REGCB) cw[t] = creg[i][t];
+          else cw[t] = a.codebook[e * DSUB + t];
+        }
+        float out[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+          float acc = 0.0f;
+#pragma unroll
+          for (int t = 0; t < DSUB; ++t) {
+            float u = res[g][m * DSUB + t] - cw[t];
+            u = u * u;
+            acc = acc + u;
+          }
+          out[g] = acc;
+        }
+        lut4[e] = make_float4(out[0], out[1], out[2], out[3]);
+      }
+      asm volatile("" ::: "memory");  // one entry's LDS reads at a time
+    }
+    __syncthreads();
+    const int64_t lbeg = uniform(a.list_off[j]);
+    const int64_t nobj = uniform(a.list_off[j + 1]) - lbeg;
+    PairOut out[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      if (valid[g]) out[g].init(a, MODE, qq[g], pp[g]);
+    BlockCompactor<G, NT, O> comp;
+    comp.reset();
+    const uint8_t* codes = a.codes + lbeg * (NVEC * 16);
+    // block-uniform trip count: every thread takes part in the compaction
+    for (int64_t base = 0; base < nobj; base += NT * O) {
+      bool active[O];
+      uint32_t w[O][NVEC * 4];
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        const int64_t i = base + o * NT + threadIdx.x;
+        active[o] = i < nobj;
+        const uint4* row = reinterpret_cast<const uint4*>(codes + (active[o] ? i : 0) * (NVEC * 16));
+#pragma unroll
+        for (int cc = 0; cc < NVEC; ++cc) {
+          uint4 v = active[o] ? row[cc] : make_uint4(0u, 0u, 0u, 0u);
+          w[o][4 * cc + 0] = v.x; w[o][4 * cc + 1] = v.y; w[o][4 * cc + 2] = v.z; w[o][4 * cc + 3] = v.w;
+        }
+      }
+      float acc[O][G];
+#pragma unroll
+      for (int o = 0; o < O; ++o)
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc[o][g] = 0.0f;
+      if (active[0])  // waves past the end of the list skip the table reads
+#pragma unroll
+      for (int m = 0; m < M; ++m) {
+        // bounds the table reads in flight: nothing moves across this fence
+        if (m % (4 / O) == 0 && m) asm volatile("" ::: "memory");
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+          uint32_t code;
+          if (BITS == 8) code = (w[o][m >> 2] >> (8 * (m & 3))) & 0xffu;
+          else code = (w[o][m >> 3] >> (4 * (m & 7))) & 0xfu;
+          const float4 v = lut4[m * KSUB + code];
+          acc[o][0] = acc[o][0] + v.x;
+          acc[o][1] = acc[o][1] + v.y;
+          acc[o][2] = acc[o][2] + v.z;
+          acc[o][3] = acc[o][3] + v.w;
+        }
+      }
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        const int64_t i = base + o * NT + threadIdx.x;
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+          if (valid[g] && active[o] && out[g].trace_out) out[g].trace_out[i] = acc[o][g];
+        if (MODE == 0) {
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            if (valid[g] && active[o]) out[g].sample_out[i] = acc[o][g];
+        }
+      }
+      if (MODE == 1) {
+        bool keep[O * G];
+        uint32_t slot[O * G];
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+#pragma unroll
+          for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && out[g].keep(acc[o][g]);
+        comp.step(keep, slot, wcnt);
+#pragma unroll
+        for (int o = 0; o < O; ++o) {
+          const int64_t i = base + o * NT + threadIdx.x;
+#pragma unroll
+          for (int g = 0; g < G; ++g)
+            if (keep[o * G + g]) {
+              out[g].skey[slot[o * G + g]] = acc[o][g];
+              out[g].spos[slot[o * G + g]] = (uint32_t)(lbeg + i);
+            }
+        }
+      }
+    }
+    if (MODE == 1 && threadIdx.x == 0) {
+#pragma unroll
+      for (int g = 0; g < G; ++g)
+        if (valid[g]) {
+          a.pair_nsurv[pp[g]] = comp.total[g];
+          if (nobj > comp.total[g]) atomicAdd(a.n_rejected + qq[g], (uint32_t)(nobj - comp.total[g]));
+        }
+    }
+  }
+}
+
+// ---- generic fallback: one block per pair, table from the global codebook -----
+template <int MODE, int BITS>
 __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   constexpr int NT = 256;
   constexpr int KSUB = 1 << BITS;
@@ -31,10 +367,13 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   float* lut = reinterpret_cast<float*>(smem);              // [M][KSUB]
   float* res = lut + a.M * KSUB;                            // [d]
 
-  const int64_t p = blockIdx.x;
+  const int64_t split = a.pair_split[0];
+  const int64_t it = (MODE == 0 ? 0 : split) + blockIdx.x;
+  if (it >= (MODE == 0 ? split : (int64_t)a.pair_split[1])) return;
+  const uint32_t pv = a.sorted_pairs[it];
+  if (pv == NO_PAIR) return;
+  const int64_t p = pv;
   const int64_t qi = find_query(a.probe_off, a.nq, p);
-  const int rank = (int)(p - a.probe_off[qi]);
-  if (rank < a.rank_begin || rank >= a.rank_end) return;
   const int j = a.probe_lists[p];
   const float* qv = a.q + qi * a.d;
   const float* cv = a.cent + (int64_t)j * a.d;
@@ -57,14 +396,20 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   __syncthreads();
   const int64_t lbeg = a.list_off[j];
   const int64_t nobj = a.list_off[j + 1] - lbeg;
-  float* out = a.keys + a.key_off[qi] + a.rank_off[p];
+  PairOut out;
+  out.init(a, MODE, qi, p);
+  __shared__ uint32_t wcnt[2][1][NT / 64];
+  BlockCompactor<1, NT> comp;
+  comp.reset();
   const int stride = a.code_stride;  // bytes per code row, multiple of 16
   const uint8_t* codes = a.codes + lbeg * stride;
-  for (int64_t i = threadIdx.x; i < nobj; i += NT) {
-    const uint4* row = reinterpret_cast<const uint4*>(codes + i * stride);
+  for (int64_t base = 0; base < nobj; base += NT) {
+    const int64_t i = base + threadIdx.x;
+    const bool active = i < nobj;
+    const uint4* row = reinterpret_cast<const uint4*>(codes + (active ? i : 0) * stride);
     float key = 0.0f;
     int m = 0;
-    for (int c = 0; c < stride / 16 && m < a.M; ++c) {
+    for (int c = 0; active && c < stride / 16 && m < a.M; ++c) {
       uint4 v = row[c];
       uint32_t wds[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -81,17 +426,78 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
         }
       }
     }
-    out[i] = key;
+    if (active && out.trace_out) out.trace_out[i] = key;
+    if (MODE == 0) {
+      if (active) out.sample_out[i] = key;
+    } else {
+      bool keep[1] = {active && out.keep(key)};
+      uint32_t slot[1];
+      comp.step(keep, slot, wcnt);
+      if (keep[0]) {
+        out.skey[slot[0]] = key;
+        out.spos[slot[0]] = (uint32_t)(lbeg + i);
+      }
+    }
+  }
+  if (MODE == 1 && threadIdx.x == 0) {
+    a.pair_nsurv[p] = comp.total[0];
+    if (nobj > comp.total[0]) atomicAdd(a.n_rejected + qi, (uint32_t)(nobj - comp.total[0]));
   }
 }
 
-hipError_t launch_pq_scan(const PqScanArgs& a, int64_t npairs, hipStream_t s) {
-  if (npairs <= 0) return hipSuccess;
-  size_t lds = sizeof(float) * ((size_t)a.M * (1 << a.bits) + a.d);
-  if (a.bits == 8)
-    hipLaunchKernelGGL(pq_scan_kernel<8>, dim3((unsigned)npairs), dim3(256), lds, s, a);
+template <int BITS, int M, int DSUB, int NT, int O>
+static void launch_grouped(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
+  if (a.mode == 0)
+    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O>), dim3(blocks), dim3(NT), lds, s, a);
   else
-    hipLaunchKernelGGL(pq_scan_kernel<4>, dim3((unsigned)npairs), dim3(256), lds, s, a);
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O>), dim3(blocks), dim3(NT), lds, s, a);
+}
+
+template <int BITS, int M, int DSUB>
+static bool try_grouped(const PqScanArgs& a, hipStream_t s) {
+  if (a.bits != BITS || a.M != M || a.d != M * DSUB) return false;
+  int blocks = (a.num_cu / a.nxcd) * a.nxcd;
+  if (blocks < a.nxcd) blocks = a.nxcd;
+  const size_t lds = sizeof(float4) * (size_t)M * (1 << BITS);
+  switch (a.scan_variant) {
+    case 1: launch_grouped<BITS, M, DSUB, 512, 1>(a, blocks, lds, s); break;
+    case 2: launch_grouped<BITS, M, DSUB, 1024, 1>(a, blocks, lds, s); break;
+    default: launch_grouped<BITS, M, DSUB, 512, 2>(a, blocks, lds, s); break;
+  }
+  return true;
+}
+
+int64_t pair_slots(int64_t npairs, int nlist) { return npairs + 2 * (int64_t)nlist * (SCAN_GROUP - 1); }
+
+hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  const int nb = 2 * a.nlist;
+  const int64_t slots = pair_slots(a.npairs, a.nlist);
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.pair_cnt, (int64_t)nb);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((slots + 255) / 256, 4096)), dim3(256), 0, s,
+                     a.sorted_pairs, slots, NO_PAIR);
+  const unsigned g = (unsigned)std::min<int64_t>((a.npairs + 255) / 256, 4096);
+  hipLaunchKernelGGL(pair_count_kernel, dim3(g), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, a.pair_split);
+  hipLaunchKernelGGL(pair_scatter_kernel, dim3(g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_pq_scan(const PqScanArgs& a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  if (try_grouped<8, 32, 4>(a, s) || try_grouped<8, 16, 8>(a, s) || try_grouped<4, 48, 2>(a, s) ||
+      try_grouped<4, 32, 4>(a, s))
+    return hipGetLastError();
+  // generic shapes: one block per padded slot of either phase
+  const int64_t n = pair_slots(a.npairs, a.nlist);
+  size_t lds = sizeof(float) * ((size_t)a.M * (1 << a.bits) + a.d);
+  if (a.bits == 8) {
+    if (a.mode == 0) hipLaunchKernelGGL((pq_scan_kernel<0, 8>), dim3((unsigned)n), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((pq_scan_kernel<1, 8>), dim3((unsigned)n), dim3(256), lds, s, a);
+  } else {
+    if (a.mode == 0) hipLaunchKernelGGL((pq_scan_kernel<0, 4>), dim3((unsigned)n), dim3(256), lds, s, a);
+    else hipLaunchKernelGGL((pq_scan_kernel<1, 4>), dim3((unsigned)n), dim3(256), lds, s, a);
+  }
   return hipGetLastError();
 }
 

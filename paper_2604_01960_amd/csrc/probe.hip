@@ -91,7 +91,8 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
     const int32_t* __restrict__ nprobe, const int64_t* __restrict__ probe_off,
     const int64_t* __restrict__ list_off, int32_t* __restrict__ probe_lists,
     float* __restrict__ probe_keys, int64_t* __restrict__ rank_off, int64_t* __restrict__ n_scanned,
-    int32_t* __restrict__ n_recheck) {
+    int32_t* __restrict__ n_recheck, const int64_t* __restrict__ kc_target, int nsample, int sample_factor,
+    int32_t* __restrict__ nsample_q) {
   constexpr int NT = 256;
   extern __shared__ __align__(16) unsigned char smem[];
   const int P = next_pow2(nlist);
@@ -179,6 +180,32 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
       n_scanned[qi] = carry;
       if (n_recheck) n_recheck[qi] = nr;
     }
+    if (nsample_q) {
+      // sample size: first rank r >= min(nsample, np) whose preceding lists
+      // hold sample_factor * kc_target keys; np when no such rank exists
+      const int nsr = nsample < np ? nsample : np;
+      const int64_t kt = (int64_t)sample_factor * kc_target[qi];
+      int ns = np;
+      int64_t cum = 0;
+      for (int base = 0; base < np && ns == np; base += 64) {
+        int r = base + lane;
+        int64_t sz = 0;
+        if (r < np) {
+          int j = (int)packed_id(cand[r]);
+          sz = list_off[j + 1] - list_off[j];
+        }
+        int64_t incl = sz;
+        for (int off = 1; off < 64; off <<= 1) {
+          int64_t o = __shfl_up(incl, off);
+          if (lane >= off) incl += o;
+        }
+        const int64_t excl = cum + incl - sz;
+        const uint64_t hit = __ballot(r < np && r >= nsr && excl >= kt);
+        if (hit) ns = base + __ffsll((unsigned long long)hit) - 1;
+        cum += __shfl(incl, 63);
+      }
+      if (lane == 0) nsample_q[qi] = ns;
+    }
   }
 }
 
@@ -191,7 +218,8 @@ hipError_t launch_probe(const ProbeArgs& a, hipStream_t s) {
   size_t lds = sizeof(uint64_t) * next_pow2(a.nlist) + sizeof(uint32_t) * a.nlist;
   hipLaunchKernelGGL(probe_select_kernel, dim3((unsigned)a.nq), dim3(256), lds, s, a.q, a.nq, a.d,
                      a.cent, a.cent_norm, a.dprime, a.nlist, a.metric, a.nprobe, a.probe_off,
-                     a.list_off, a.probe_lists, a.probe_keys, a.rank_off, a.n_scanned, a.n_recheck);
+                     a.list_off, a.probe_lists, a.probe_keys, a.rank_off, a.n_scanned, a.n_recheck,
+                     a.kc_target, a.nsample, a.sample_factor, a.nsample_q);
   return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ def make_gpu_index(bbc, ix):
                                ix["base"])
 
 
-def expected_steps(ix, q, k, nprobe, ratio, m, nsample):
+def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2):
     """Per query, everything the GPU trace reports, from the oracle alone."""
     nq = q.shape[0]
     kk = np.broadcast_to(np.asarray(k), (nq,)).astype(np.int64)
@@ -56,7 +56,7 @@ def expected_steps(ix, q, k, nprobe, ratio, m, nsample):
         goff = np.zeros(len(lists) + 1, np.int64)
         goff[1:] = np.cumsum(sizes)
         kc_t = int(np.ceil(ratio * float(kk[i])))
-        col = oracle.collect_bbc(keys, ids, goff, kc_t, m, nsample) if len(keys) else None
+        col = oracle.collect_bbc(keys, ids, goff, kc_t, m, nsample, sample_factor) if len(keys) else None
         kc = int(res["n_cand"][i])
         cand = res["cand_ids"][res["cand_off"][i]:res["cand_off"][i] + kc]
         exact = np.array([oracle.canon_l2(q[i], ix["base"][c]) for c in cand], np.float32)

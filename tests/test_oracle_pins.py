@@ -140,10 +140,11 @@ def test_collect_invariant_under_codebook():
     ref = None
     for m in (1, 3, 17, 256):
         for ns in (1, 2, 7, 20):
-            got = np.sort(oracle.collect_bbc(keys, ids, off, kc, m, ns)["cand_ids"])
-            if ref is None:
-                ref = got
-            np.testing.assert_array_equal(got, ref)
+            for sf in (1, 2, 3):
+                got = np.sort(oracle.collect_bbc(keys, ids, off, kc, m, ns, sf)["cand_ids"])
+                if ref is None:
+                    ref = got
+                np.testing.assert_array_equal(got, ref)
 
 
 def test_codebook_equal_depth():
