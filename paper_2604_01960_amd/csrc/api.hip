@@ -687,13 +687,20 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     HIP_TRY(hipMemcpyAsync(cand_packed_h.data(), ra.cand_packed, 8 * ncand, hipMemcpyDeviceToHost, s));
   }
 
-  // final top-k LDS: `run` packed items (dynamic) + ~18 KB of static tables
-  int run = 1024;
-  while ((int64_t)(2 * run) * 8 + 20480 <= ix->max_lds && run < 16384) run *= 2;
+  // final top-k LDS: `cap` packed items (dynamic; the largest min(k, K_c) of
+  // the batch when it fits) + the kernel's static tables
+  int64_t max_cnt = 1;
+  for (int64_t i = 0; i < nq; ++i) max_cnt = std::max(max_cnt, std::min<int64_t>(k[i], cand_off[i + 1] - cand_off[i]));
+  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
+  const int cap = (int)std::min(max_cnt, cap_max);
+  int run = 1;
+  while (2 * run <= cap) run *= 2;
   bbc::FinalArgs fa{};
   fa.nq = nq; fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
+  fa.cap = cap;
   fa.run = run;
+  fa.max_kc = max_kc;
   {
     StageScope st(s, 5);
     HIP_TRY(bbc::launch_final_topk(fa, s));

@@ -50,7 +50,7 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
   constexpr int NT = 1024;
   __shared__ uint32_t hist[256];
   __shared__ uint8_t cmap[256];
-  __shared__ uint32_t bc[8];
+  __shared__ __align__(8) uint32_t bc[8];
   __shared__ float fbc[2];
 
   const int64_t qi = blockIdx.x;
@@ -106,21 +106,36 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
       wave_hist_add(hist, (uint32_t)cell_of(k, dmin, delta), i < Ts && key_bits(k) < dmax_b);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t below = 0;
-      for (int e = 0; e < 256; ++e) below += hist[e];
-      hist[cell_of(dmax, dmin, delta)] += (uint32_t)(T - below);
-      below = 0;
-      for (int e = 0; e < 256; ++e) {
-        int64_t b = ((int64_t)m * below) / T;
-        cmap[e] = (uint8_t)(b < m - 1 ? b : m - 1);
-        below += hist[e];
+    if (threadIdx.x < 64) {
+      // cell counts of the sample's T smallest keys: the keys below d_max as
+      // counted, plus (T - their number) copies of d_max in d_max's cell;
+      // map[e] = min(m - 1, floor(m * C_<e / T)), one wave, 4 cells per lane
+      const int lane = threadIdx.x;
+      uint32_t h[4], sum = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        h[j] = hist[4 * lane + j];
+        sum += h[j];
       }
-      fbc[0] = dmin;
-      fbc[1] = delta;
-      // reject above d_max only when the sample alone holds K_c keys and the
-      // cells are proper (then every key above d_max is in cell 255)
-      bc[5] = (Ts >= kc && dmax > dmin) ? 1u : 0u;
+      const uint32_t incl = wave_incl_scan(sum);
+      const int64_t below_dmax = __shfl(incl, 63);
+      const int cmax = cell_of(dmax, dmin, delta);
+      int64_t below = incl - sum;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int e = 4 * lane + j;
+        const int64_t be = below + (e > cmax ? T - below_dmax : 0);
+        const int64_t b = ((int64_t)m * be) / T;
+        cmap[e] = (uint8_t)(b < m - 1 ? b : m - 1);
+        below += h[j];
+      }
+      if (lane == 0) {
+        fbc[0] = dmin;
+        fbc[1] = delta;
+        // reject above d_max only when the sample alone holds K_c keys and the
+        // cells are proper (then every key above d_max is in cell 255)
+        bc[5] = (Ts >= kc && dmax > dmin) ? 1u : 0u;
+      }
     }
   } else if (threadIdx.x == 0) {
     for (int e = 0; e < 256; ++e) cmap[e] = 0;
@@ -174,7 +189,8 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   __shared__ uint32_t hist[256];
   __shared__ uint32_t counts[BBC_MAX_BUCKETS];
   __shared__ uint8_t cmap[256];
-  __shared__ uint32_t bc[8];
+  __shared__ __align__(8) uint32_t bc[8];
+  __shared__ int64_t s_rem;
 
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
@@ -241,15 +257,14 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int U = COLLECT_UNROLL;
   constexpr int NW = NT / 64;
-  // For every survivor: v = load(active, slot), then use(active, slot, v); the
-  // trip counts are wave-uniform (use() may take wave-wide collectives).
-  auto for_each_wave = [&](auto load, auto use) {
-    using V = decltype(load(false, (int64_t)0));
+  // Batches of up to U elements per lane: batch(n, act, idx) gets the slots
+  // idx[0, n) (with their active flags) of this lane; n and the number of
+  // calls are wave-uniform (batch() may take wave-wide collectives).
+  auto for_each_batch = [&](auto batch) {
     if (flat) {
       for (uint32_t c0 = (uint32_t)wv * U; c0 < nchunks; c0 += NW * U) {
         bool act[U];
         int64_t idx[U];
-        V v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint32_t ch = c0 + u;
@@ -272,22 +287,35 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
             idx[u] = (int64_t)s_rbeg[r] + e;
           }
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = load(act[u], idx[u]);
-#pragma unroll
-        for (int u = 0; u < U; ++u) use(act[u], idx[u], v[u]);
+        batch(act, idx);
       }
     } else {
       for (int r = 0; r < np; ++r) {
         const int64_t rb = rank_off[r];
         const int64_t rn = nsurv[r];
         for (int64_t base = 0; base < rn; base += NT) {
-          const bool act = base + threadIdx.x < rn;
-          const int64_t i = rb + base + threadIdx.x;
-          use(act, i, load(act, i));
+          bool act[U];
+          int64_t idx[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            act[u] = u == 0 && base + threadIdx.x < rn;
+            idx[u] = rb + base + threadIdx.x;
+          }
+          batch(act, idx);
         }
       }
     }
+  };
+  // For every survivor: v = load(active, slot), then use(active, slot, v).
+  auto for_each_wave = [&](auto load, auto use) {
+    using V = decltype(load(false, (int64_t)0));
+    for_each_batch([&](const bool* act, const int64_t* idx) {
+      V v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) v[u] = load(act[u], idx[u]);
+#pragma unroll
+      for (int u = 0; u < U; ++u) use(act[u], idx[u], v[u]);
+    });
   };
   auto for_each = [&](auto fn) {
     for_each_wave([&](bool act, int64_t i) { return 0; },
@@ -318,34 +346,55 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   __syncthreads();
 
   // ---- Update: threshold bucket and s ---------------------------------------
-  if (threadIdx.x == 0) {
-    int64_t cum = 0;
-    int tau = m - 1;
-    for (int b = 0; b < m; ++b) {
-      if (cum + (int64_t)counts[b] >= kc) { tau = b; break; }
-      cum += counts[b];
-    }
-    bc[0] = (uint32_t)tau;
-    bc[1] = (uint32_t)cum;      // objects strictly below tau
+  // tau: the first bucket whose running count reaches kc, i.e. the bucket
+  // holding rank kc - 1; s_rem = kc - 1 minus the count below tau
+  if (threadIdx.x < 64) wave_find_rank(counts, m, kc - 1, &bc[0], &s_rem);
+  if (threadIdx.x == 64) {
     bc[2] = 0;                  // candidate slot counter
     bc[3] = 0;                  // boundary slot counter
     if (a.surv_total) a.surv_total[qi] = bc[4];
   }
   __syncthreads();
   const int tau = (int)bc[0];
-  const int64_t nbelow = bc[1];
+  const int64_t nbelow = kc - 1 - s_rem;  // objects strictly below tau
   const int64_t s = kc - nbelow;
   const int bcap = a.bcap;
   uint32_t* cand = a.cand_pos + a.cand_off[qi];
 
   // ---- Collect -----------------------------------------------------------------
-  for_each_wave([&](bool act, int64_t i) { return act ? (int)sbkt[i] : m; },
-                [&](bool act, int64_t i, int b) {
-                  const uint32_t slot = wave_slot(b < tau, &bc[2]);
-                  if (b < tau) cand[slot] = spos[i];
-                  const uint32_t bs = wave_slot(b == tau, &bc[3]);
-                  if (b == tau && (int)bs < bcap) bbuf[bs] = pack_key_id(skey[i], (uint32_t)a.list_ids[spos[i]]);
-                });
+  // one atomic per counter for a lane's whole batch
+  for_each_batch([&](const bool* act, const int64_t* idx) {
+    int b[U];
+    uint64_t mc[U], mb[U];
+    uint32_t nc = 0, nbd = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) b[u] = act[u] ? (int)sbkt[idx[u]] : m;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      mc[u] = __ballot(b[u] < tau);
+      mb[u] = __ballot(b[u] == tau);
+      nc += (uint32_t)__popcll(mc[u]);
+      nbd += (uint32_t)__popcll(mb[u]);
+    }
+    uint32_t basec = 0, baseb = 0;
+    if (lane == 0) {
+      if (nc) basec = atomicAdd(&bc[2], nc);
+      if (nbd) baseb = atomicAdd(&bc[3], nbd);
+    }
+    basec = __shfl(basec, 0);
+    baseb = __shfl(baseb, 0);
+    const uint64_t lt = (1ull << lane) - 1ull;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (b[u] < tau) cand[basec + (uint32_t)__popcll(mc[u] & lt)] = spos[idx[u]];
+      if (b[u] == tau) {
+        const uint32_t bs = baseb + (uint32_t)__popcll(mb[u] & lt);
+        if ((int)bs < bcap) bbuf[bs] = pack_key_id(skey[idx[u]], (uint32_t)a.list_ids[spos[idx[u]]]);
+      }
+      basec += (uint32_t)__popcll(mc[u]);
+      baseb += (uint32_t)__popcll(mb[u]);
+    }
+  });
   __syncthreads();
   const int64_t nb = bc[3];
   if (nb <= bcap) {

@@ -141,6 +141,51 @@ __device__ __forceinline__ T* uniform(T* p) {
   return reinterpret_cast<T*>(uniform((int64_t)reinterpret_cast<uintptr_t>(p)));
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave.
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) {
+    const uint32_t o = __shfl_up(v, off);
+    if (lane >= off) v += o;
+  }
+  return v;
+}
+
+// Run by one whole wave: the bin holding rank rr (0-based, ascending) of a
+// histogram hist[0, nb), nb <= 256: the first bin dg whose running count
+// exceeds rr, and rem = rr minus the count below dg.  When the running count
+// never exceeds rr, dg = nb - 1 (rem still relative to that bin).  The lane
+// that finds the bin writes dg and rem (LDS words) for the block.
+__device__ __forceinline__ void wave_find_rank(const uint32_t* hist, int nb, int64_t rr, uint32_t* dg_out,
+                                               int64_t* rem_out) {
+  const int lane = threadIdx.x & 63;
+  uint32_t h[4], sum = 0;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int e = 4 * lane + j;
+    h[j] = e < nb ? hist[e] : 0u;
+    sum += h[j];
+  }
+  const uint32_t incl = wave_incl_scan(sum);
+  const uint64_t hit = __ballot((int64_t)incl > rr);
+  const int last = (nb - 1) >> 2;
+  int L = hit ? __ffsll((unsigned long long)hit) - 1 : last;
+  if (L > last) L = last;
+  if (lane == L) {
+    int64_t rem = rr - (int64_t)(incl - sum);
+    int dg = 4 * L;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      dg = 4 * L + j;
+      if (dg >= nb - 1 || rem < (int64_t)h[j]) break;
+      rem -= h[j];
+    }
+    *dg_out = (uint32_t)dg;
+    *rem_out = rem;
+  }
+}
+
 // hist[bin] += 1 for every active lane with valid set.  Lanes that share the
 // first valid lane's bin are counted with one ballot and one atomic (keys of
 // one query are concentrated, so most lanes of a wave often share a bin);
@@ -158,7 +203,7 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t bin, bool
 
 // Radix select over a block: value of the element of rank r (0-based,
 // ascending) among n 32-bit values produced by get(i).  hist: 256 LDS words;
-// bc: 2 LDS words for broadcast.
+// bc: 4 LDS words for broadcast, 8-byte aligned.
 template <int NT, typename Get>
 __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
   uint32_t prefix = 0, mask = 0;
@@ -171,20 +216,11 @@ __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t
       wave_hist_add(hist, (v >> shift) & 255u, i < n && (v & mask) == prefix);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t rr = r;
-      uint32_t dg = 0;
-      for (; dg < 255; ++dg) {
-        if (rr < (int64_t)hist[dg]) break;
-        rr -= hist[dg];
-      }
-      bc[0] = dg;
-      bc[1] = (uint32_t)rr;
-    }
+    if (threadIdx.x < 64) wave_find_rank(hist, 256, r, &bc[0], reinterpret_cast<int64_t*>(bc + 2));
     __syncthreads();
     prefix |= bc[0] << shift;
     mask |= 255u << shift;
-    r = bc[1];
+    r = *reinterpret_cast<const int64_t*>(bc + 2);
     __syncthreads();
   }
   return prefix;
@@ -204,20 +240,11 @@ __device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t
       wave_hist_add(hist, (uint32_t)((v >> shift) & 255u), ok);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      int64_t rr = r;
-      uint32_t dg = 0;
-      for (; dg < 255; ++dg) {
-        if (rr < (int64_t)hist[dg]) break;
-        rr -= hist[dg];
-      }
-      bc[0] = dg;
-      bc[1] = (uint32_t)rr;
-    }
+    if (threadIdx.x < 64) wave_find_rank(hist, 256, r, &bc[0], reinterpret_cast<int64_t*>(bc + 2));
     __syncthreads();
     prefix |= (uint64_t)bc[0] << shift;
     mask |= 255ull << shift;
-    r = bc[1];
+    r = *reinterpret_cast<const int64_t*>(bc + 2);
     __syncthreads();
   }
   return prefix;

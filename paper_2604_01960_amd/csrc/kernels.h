@@ -94,8 +94,12 @@ hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 
 struct FinalArgs {
   int64_t nq; const int32_t* k; const int64_t* n_cand; const int64_t* cand_off; uint64_t* cand_packed;
-  const int64_t* out_off; int64_t* out_ids; float* out_dists; int32_t* out_counts; int metric; int run;
+  const int64_t* out_off; int64_t* out_ids; float* out_dists; int32_t* out_counts; int metric;
+  int cap;                  // packed items in the dynamic LDS buffer (queries with min(k, K_c) <= cap use the binned path)
+  int run;                  // largest power of two <= cap: LDS sort run of the global sort
+  int64_t max_kc;           // largest K_c of the batch (selects the register-resident variant)
 };
+constexpr int FINAL_STATIC_LDS = 21000;  // bytes of static LDS of the final top-k kernel (upper bound)
 hipError_t launch_final_topk(const FinalArgs& a, hipStream_t s);
 
 }  // namespace bbc

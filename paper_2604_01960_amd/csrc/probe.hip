@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem);
   uint32_t* sel = reinterpret_cast<uint32_t*>(smem + sizeof(uint64_t) * P);
   __shared__ uint32_t hist[256];
-  __shared__ uint32_t bc[4];
+  __shared__ __align__(8) uint32_t bc[4];
   __shared__ uint32_t red[NT / 64];
   __shared__ float qn_s[2];
 
