@@ -30,11 +30,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+CSRC = os.path.join(ROOT, "paper_2604_01960_amd", "csrc")
+PROFILES = os.path.join(ROOT, "profiles")
+KERNEL_SCAN = "pq_scan_grouped<1, ...> (scan through the relaxed threshold)"
+KERNEL_SAMPLE = "pq_scan_grouped<0, ...> (scan of the codebook sample lists)"
 METRIC = "QPS at recall@k=0.95, k=5000-10000, bucket vs heap collector; p99 ms"
 
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def measured_traffic(workload, stage, sources):
+    """HBM bytes per launch from the committed counter record of this kernel
+    and workload, or None when there is none or the kernel's sources have
+    changed since the counters were taken."""
+    from paper_2604_01960_amd import profiling
+    path = os.path.join(PROFILES, f"hbm_traffic_{stage}_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = profiling.read_traffic(path)
+    except ValueError:
+        return None
+    if rec.get("sources_sha256") != profiling.sources_sha256(sources):
+        return None
+    return int(rec["traffic_bytes"])
 
 
 def recall_at_k(ids, off, gt, k):
@@ -70,15 +91,28 @@ def main():
     ap.add_argument("--ratio", type=str, default="", help="fixed r per k, e.g. 2,2 (skips the sweep)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-queries", type=int, default=3000)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES bytes (3 times) for counter calibration")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not supported "
-              "by this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}); multi-GPU runs are not supported",
+              file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
+
+    if args.copy_calibration:
+        # an elementwise kernel that reads and writes BYTES bytes once each
+        n = args.copy_calibration // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": 4 * n, "kernel": "elementwise mul"}), flush=True)
+        return
 
     import paper_2604_01960_amd as bbc
     import synth
@@ -102,10 +136,14 @@ def main():
 
     # ---- recall operating point ---------------------------------------------
     rq = q[: args.recall_queries]
-    x64 = torch.from_numpy(x).to(dev, torch.float64)
-    gt = ground_truth(torch, x64, rq, max(ks))
-    del x64
-    torch.cuda.empty_cache()
+    gt = None
+    if args.recall_queries > 0:
+        x64 = torch.from_numpy(x).to(dev, torch.float64)
+        gt = ground_truth(torch, x64, rq, max(ks))
+        del x64
+        torch.cuda.empty_cache()
+    elif not (args.nprobe and args.ratio):
+        raise SystemExit("--recall-queries 0 needs a fixed operating point (--nprobe and --ratio)")
     nprobe_grid = [64, 96, 128, 160, 192, 256]
     ratio_grid = [1.25, 1.5, 1.75, 2.0, 2.5, 3.0, 4.0]
     qd = torch.from_numpy(q).to(dev)
@@ -114,8 +152,11 @@ def main():
     op = {}
     for ki, k in enumerate(ks):
         if fixed_np and fixed_r:
-            ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki])
-            op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=recall_at_k(ids, off, gt, k))
+            rec = None
+            if gt is not None:
+                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki])
+                rec = recall_at_k(ids, off, gt, k)
+            op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=rec)
             continue
         cands = []
         for npb in nprobe_grid:
@@ -179,7 +220,8 @@ def main():
     per_k = {}
     for k in ks:
         arr = np.array(lat[k])
-        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], recall=round(op[k]["recall"], 4),
+        rec = op[k]["recall"]
+        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], recall=None if rec is None else round(rec, 4),
                              qps=round(nq / (arr.mean() / 1e3), 1), batch_ms_p50=round(float(np.percentile(arr, 50)), 3),
                              batch_ms_p99=round(float(np.percentile(arr, 99)), 3))
 
@@ -188,32 +230,40 @@ def main():
     for k in ks:
         c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"])
         sizes[k] = dict(S=int(c["n_scanned"].sum()), Kc=int(c["n_cand"].sum()),
+                        sample_keys=int(c["n_sample_keys"].sum()),
                         recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()),
                         sample_lists_mean=float(c["n_sample_lists"].mean()),
                         survivors_mean=float(c["n_survivors"].mean()))
     d = w.d
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2
+    # algorithmic bytes per step of the kernels that dominate their stage
     algo = {
+        # scan of the non-sample lists: one code row per scanned object
+        "scan": sum(sizes[k]["S"] - sizes[k]["sample_keys"] for k in ks) * code_bytes,
+        # scan of the codebook sample lists
+        "sample_scan": sum(sizes[k]["sample_keys"] for k in ks) * code_bytes,
         # re-rank: a d*4-byte row plus its 4-byte slot per candidate
         "rerank": sum(sizes[k]["Kc"] for k in ks) * (4 * d + 4),
-        # scan: one code row per scanned object
-        "scan": sum(sizes[k]["S"] for k in ks) * code_bytes,
     }
-    dominant = max(stages, key=lambda s: stages[s]["ms"])
-    roof = None
-    for name in ("rerank", "scan"):
+    kernels = {"scan": (KERNEL_SCAN, [os.path.join(CSRC, f) for f in ("pq_scan.hip", "common.h", "kernels.h")]),
+               "rerank": ("rerank_half_kernel", [os.path.join(CSRC, f) for f in ("rerank.hip", "common.h", "kernels.h")]),
+               "sample_scan": (KERNEL_SAMPLE, [os.path.join(CSRC, f) for f in ("pq_scan.hip", "common.h", "kernels.h")])}
+    entries = {}
+    for name in algo:
         st = stages[name]
         if st["launches"] == 0:
             continue
         avg_ms = st["ms"] / st["launches"]
         bytes_total = algo[name] * args.steps
         bytes_per_launch = bytes_total / st["launches"]
-        gbs = bytes_total / (st["ms"] * 1e-3) / 1e9
-        entry = {"kernel": name, "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                 "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None, "avg_launch_ms": round(avg_ms, 4),
-                 "algorithmic_bytes_per_launch": int(bytes_per_launch)}
-        if roof is None or name == dominant:
-            roof = entry
+        gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        entries[name] = {"kernel": kernels[name][0], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": measured_traffic(w.name, name, kernels[name][1]),
+                         "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bytes_per_launch)}
+    dominant = max(entries, key=lambda s: stages[s]["ms"])
+    roof = entries[dominant]
+    others = {n: e for n, e in entries.items() if n != dominant}
     stage_ms = {s: round(v["ms"] / max(1, args.steps), 4) for s, v in stages.items()}
 
     # ---- oracle CPU baseline ----------------------------------------------------
@@ -247,6 +297,7 @@ def main():
         "stage_ms_per_step": stage_ms,
         "sizes": sizes,
         "roofline": roof,
+        "roofline_other_kernels": others,
         "cpu_baseline": cpu,
         "build_s": round(build_s, 2),
     }

@@ -134,6 +134,7 @@ typedef struct {
   int64_t* cand_off;                         /* [nq+1] prefix sums of K_c (output) */
   int32_t* n_sample_lists;                   /* [nq] probed lists in the codebook sample */
   int64_t* n_survivors;                      /* [nq] keys kept by the relaxed-threshold filter */
+  int64_t* n_sample_keys;                    /* [nq] keys in the codebook sample lists */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and
@@ -164,7 +165,10 @@ void bbc_index_free(bbc_index* ix);
  * bracketed by HIP events recorded on the search stream; bbc_stage_times
  * waits for them and returns, per stage, the summed milliseconds and the
  * launch count since the last reset (stages: 0 probe (coarse GEMM and
- * select), 2 code scan, 3 collector, 4 re-rank, 5 final top-k). */
+ * select), 1 pair sort and scan of the codebook sample lists, 2 scan of the
+ * remaining lists through the relaxed threshold (one kernel launch per
+ * search), 3 collector (codebook and bucket collection), 4 re-rank, 5 final
+ * top-k). */
 int32_t bbc_stage_timing(int32_t enable);
 int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset);
 

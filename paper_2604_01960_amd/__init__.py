@@ -26,7 +26,7 @@ METRIC_L2, METRIC_IP = 0, 1
 QUANT_PQ, QUANT_RABITQ = 0, 1
 COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
 FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
-STAGES = {0: "probe", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
+STAGES = {0: "probe", 1: "sample_scan", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
 
 
 class BBCError(RuntimeError):
@@ -52,7 +52,7 @@ class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
         "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off",
-        "n_sample_lists", "n_survivors")]
+        "n_sample_lists", "n_survivors", "n_sample_keys")]
 
 
 _lib = None
@@ -256,7 +256,7 @@ class Index:
         off[1:] = np.cumsum(kk)
         r = dict(n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64), n_recheck=np.empty(nq, np.int32),
                  n_boundary=np.empty(nq, np.int64), n_sample_lists=np.empty(nq, np.int32),
-                 n_survivors=np.empty(nq, np.int64))
+                 n_survivors=np.empty(nq, np.int64), n_sample_keys=np.empty(nq, np.int64))
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)

@@ -433,7 +433,7 @@ struct Layout {
   // offsets into the arena
   size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
-      cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts,
+      cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb;
 };
 
@@ -542,7 +542,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   }
   if (tracing) {
     L.t_dmin = pl.add(4 * nq); L.t_delta = pl.add(4 * nq); L.t_map = pl.add(256 * nq);
-    L.t_tau = pl.add(4 * nq); L.t_s = pl.add(8 * nq); L.t_counts = pl.add(4 * nq * m); L.t_nb = pl.add(8 * nq);
+    L.t_tau = pl.add(4 * nq); L.t_s = pl.add(8 * nq); L.t_counts = pl.add(4 * nq * m); L.t_nb = pl.add(8 * nq); L.t_nsk = pl.add(8 * nq);
   }
   HIP_TRY(ix->arena.reserve(pl.total));
   char* A = ix->arena.base;
@@ -644,12 +644,13 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     ca.t_map = reinterpret_cast<uint8_t*>(A + L.t_map); ca.t_tau = reinterpret_cast<int32_t*>(A + L.t_tau);
     ca.t_s = reinterpret_cast<int64_t*>(A + L.t_s); ca.t_counts = reinterpret_cast<int32_t*>(A + L.t_counts);
     ca.t_nboundary = reinterpret_cast<int64_t*>(A + L.t_nb);
+    ca.t_nsample_keys = reinterpret_cast<int64_t*>(A + L.t_nsk);
   }
 
   // scan of the sample lists, codebook, scan of the rest through the filter,
   // then the collector over the survivors
   {
-    StageScope st(s, 2);
+    StageScope st(s, 1);
     HIP_TRY(bbc::launch_pair_sort(sa, s));
     sa.mode = 0;
     HIP_TRY(bbc::launch_pq_scan(sa, s));
@@ -727,6 +728,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     if ((rc = cp(tr->bucket_counts, L.t_counts, 4 * nq * m))) return rc;
     if ((rc = cp(tr->n_boundary, L.t_nb, 8 * nq))) return rc;
     if ((rc = cp(tr->n_sample_lists, L.nsample_q, 4 * nq))) return rc;
+    if ((rc = cp(tr->n_sample_keys, L.t_nsk, 8 * nq))) return rc;
     std::vector<uint32_t> nsurv(nq);
     HIP_TRY(hipMemcpyAsync(nsurv.data(), A + L.surv_total, 4 * nq, hipMemcpyDeviceToHost, s));
     std::vector<int64_t> nsc(nq);

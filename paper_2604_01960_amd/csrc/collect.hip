@@ -84,6 +84,7 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
     }
     return (int64_t)s_lbeg[lo] + (i - s_rbeg[lo]);
   };
+  if (a.t_nsample_keys && threadIdx.x == 0) a.t_nsample_keys[qi] = Ts;
   const int64_t T = kc < Ts ? kc : Ts;
   uint32_t dmax_b = 0;
   if (T > 0) {

@@ -81,6 +81,7 @@ struct CollectArgs {
   // trace outputs (all null when tracing is off)
   float* t_dmin; float* t_delta; uint8_t* t_map; int32_t* t_tau; int64_t* t_s; int32_t* t_counts;
   int64_t* t_nboundary;
+  int64_t* t_nsample_keys;  // keys in the codebook sample (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s);
