@@ -91,6 +91,7 @@ def main():
     ap.add_argument("--ratio", type=str, default="", help="fixed r per k, e.g. 2,2 (skips the sweep)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-queries", type=int, default=3000)
+    ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (3 times) for counter calibration")
     args = ap.parse_args()
@@ -225,6 +226,35 @@ def main():
                              qps=round(nq / (arr.mean() / 1e3), 1), batch_ms_p50=round(float(np.percentile(arr, 50)), 3),
                              batch_ms_p99=round(float(np.percentile(arr, 99)), 3))
 
+    # ---- collector comparison: same batch, same operating point ---------------
+    collectors = {}
+    if not args.no_compare:
+        for k in ks:
+            res_k = {}
+            ref = None
+            for col in ("bucket", "heap", "sort"):
+                o = (torch.empty_like(outs[k][0]), torch.empty_like(outs[k][1]), torch.empty_like(outs[k][2]))
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o)
+                torch.cuda.synchronize()
+                bbc.stage_times(reset=True)
+                bbc.stage_timing(True)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o)
+                e1.record()
+                torch.cuda.synchronize()
+                bbc.stage_timing(False)
+                st = bbc.stage_times(reset=True)
+                if ref is None:
+                    ref = o
+                same = bool(torch.equal(o[0], ref[0]) and torch.equal(o[1], ref[1]) and torch.equal(o[2], ref[2]))
+                scan_ms = st["sample_scan"]["ms"] + st["scan"]["ms"]
+                res_k[col] = dict(batch_ms=round(e0.elapsed_time(e1), 3), collector_ms=round(st["collect"]["ms"], 3),
+                                  scan_ms=round(scan_ms, 3), qps=round(nq / (e0.elapsed_time(e1) / 1e3), 1),
+                                  identical_to_bucket=same)
+                log(f"k={k} collector {col}: {res_k[col]}")
+            collectors[str(k)] = res_k
+
     # ---- sizes for the algorithmic byte counts ---------------------------------
     sizes = {}
     for k in ks:
@@ -295,6 +325,7 @@ def main():
                        "p99": round(float(np.percentile(sum(lat.values(), []), 99)), 3),
                        "what": "device time of one 10,000-query batch"},
         "stage_ms_per_step": stage_ms,
+        "collectors": collectors,
         "sizes": sizes,
         "roofline": roof,
         "roofline_other_kernels": others,

@@ -48,9 +48,20 @@ extern "C" {
 #define BBC_QUANT_PQ 0
 #define BBC_QUANT_RABITQ 1
 
-#define BBC_COLLECT_BUCKET 0 /* bucket-based result buffer (the paper's) */
-#define BBC_COLLECT_HEAP 1   /* comparator: bounded max-heap per query */
-#define BBC_COLLECT_SORT 2   /* comparator: full sort of all keys per query */
+/* Result collectors (result-collector background and Algorithm 1).  All
+ * three return the same candidates, the K_c smallest estimated (key, id);
+ * they differ in how they find them:
+ *  BUCKET  the bucket-based result buffer: codebook from the nearest lists,
+ *          keys above its d_max dropped during the scan, one histogram of
+ *          the rest, all buckets below the threshold bucket plus the best s
+ *          of the threshold bucket;
+ *  HEAP    comparator: every scanned key offered to a bounded max-heap of
+ *          K_c (key, id) per query (one wave per query, 64-ary heap);
+ *  SORT    comparator: exact selection over every scanned key (radix
+ *          select of the K_c-th key, ties by id). */
+#define BBC_COLLECT_BUCKET 0
+#define BBC_COLLECT_HEAP 1
+#define BBC_COLLECT_SORT 2
 
 typedef struct bbc_index bbc_index; /* opaque; owns its device memory */
 
@@ -119,7 +130,9 @@ int32_t bbc_search(const bbc_index* ix, const float* queries, int64_t nq, const 
  * probe_*: by nprobe; cand_*: by cand_cap[q] = the per-query candidate
  * capacity reported in n_cand_cap.  For the bucket collector: codebook
  * (dmin, delta, map[nq][256]), threshold bucket tau, s, bucket counts
- * [nq][m] of all scanned keys, and the size of the threshold bucket. */
+ * [nq][m] of all scanned keys, and the size of the threshold bucket; the
+ * heap and sort collectors leave these fields (and n_sample_lists,
+ * n_survivors, n_sample_keys) untouched. */
 typedef struct {
   int32_t* probe_lists; float* probe_keys;   /* [sum nprobe], nearest first */
   int64_t* n_scanned;                        /* [nq] S */

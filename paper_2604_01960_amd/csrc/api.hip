@@ -448,7 +448,8 @@ int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, c
   if (p->buckets < 0 || p->buckets > 256) return fail(BBC_EINVAL, "buckets must be in [0, 256]");
   if (p->nsample < 0) return fail(BBC_EINVAL, "nsample must be >= 0");
   if (p->sample_factor < 0 || p->sample_factor > 64) return fail(BBC_EINVAL, "sample_factor must be in [0, 64]");
-  if (p->collector != BBC_COLLECT_BUCKET) return fail(BBC_EUNSUPPORTED, "collector not available");
+  if (p->collector != BBC_COLLECT_BUCKET && p->collector != BBC_COLLECT_HEAP && p->collector != BBC_COLLECT_SORT)
+    return fail(BBC_EINVAL, "unknown collector");
   if (out_off[0] != 0) return fail(BBC_EINVAL, "out_offsets[0] must be 0");
   for (int64_t i = 0; i < nq; ++i) {
     if (k[i] < 1) return fail(BBC_EINVAL, "k must be >= 1");
@@ -479,6 +480,9 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const int sample_factor = p->sample_factor ? p->sample_factor : 2;
   const int d = ix->d;
   const bool tracing = tr != nullptr;
+  // the comparator collectors read every scanned key: all probed lists form
+  // the "sample" phase and no key is filtered
+  const bool bucket = p->collector == BBC_COLLECT_BUCKET;
 
   // host-side metadata: per query k, nprobe, and prefix offsets
   std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq),
@@ -489,11 +493,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     probe_off[i + 1] = probe_off[i] + nprobe[i];
     int64_t cap = kc_cap_of(ix, k[i], nprobe[i], p->ncand_ratio);
     // the sample stops at the first list that brings it to K_c keys
-    const int64_t scap = std::min(ix->h_maxS[nprobe[i]],
-                                  std::max(ix->h_maxS[std::min(nsample, nprobe[i])],
-                                           (int64_t)sample_factor * cap + max_list));
+    const int64_t scap = !bucket ? ix->h_maxS[nprobe[i]]
+                                 : std::min(ix->h_maxS[nprobe[i]],
+                                            std::max(ix->h_maxS[std::min(nsample, nprobe[i])],
+                                                     (int64_t)sample_factor * cap + max_list));
     sample_off[i + 1] = sample_off[i] + scap;
-    surv_off[i + 1] = surv_off[i] + ix->h_maxS[nprobe[i]];
+    surv_off[i + 1] = surv_off[i] + (bucket ? ix->h_maxS[nprobe[i]] : 0);
     key_off[i + 1] = key_off[i] + (tracing ? ix->h_maxS[nprobe[i]] : 0);
     kc_target[i] = (int64_t)std::ceil(p->ncand_ratio * (double)k[i]);
     cand_off[i + 1] = cand_off[i] + cap;
@@ -598,7 +603,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   pa.rank_off = reinterpret_cast<int64_t*>(A + L.rank_off);
   pa.n_scanned = reinterpret_cast<int64_t*>(A + L.n_scanned);
   pa.n_recheck = reinterpret_cast<int32_t*>(A + L.n_recheck);
-  pa.kc_target = d_kt; pa.nsample = nsample; pa.sample_factor = sample_factor;
+  pa.kc_target = d_kt; pa.nsample = bucket ? nsample : ix->nlist; pa.sample_factor = sample_factor;
   pa.nsample_q = reinterpret_cast<int32_t*>(A + L.nsample_q);
   {
     StageScope st(s, 0);  // coarse GEMM and probe select
@@ -655,18 +660,30 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     sa.mode = 0;
     HIP_TRY(bbc::launch_pq_scan(sa, s));
   }
-  {
+  if (bucket) {
+    {
+      StageScope st(s, 3);
+      HIP_TRY(bbc::launch_codebook(ca, s));
+    }
+    {
+      StageScope st(s, 2);
+      sa.mode = 1;
+      HIP_TRY(bbc::launch_pq_scan(sa, s));
+    }
+    {
+      StageScope st(s, 3);
+      HIP_TRY(bbc::launch_collect_bucket(ca, s));
+    }
+  } else {
+    bbc::CompareArgs xa{};
+    xa.nq = nq; xa.n_scanned = pa.n_scanned; xa.kc_target = d_kt; xa.nprobe = d_np; xa.probe_off = d_po;
+    xa.rank_off = pa.rank_off; xa.probe_lists = pa.probe_lists; xa.list_off = ix->list_off;
+    xa.list_ids = ix->list_ids; xa.pos_of_id = ix->pos_of_id;
+    xa.keys = reinterpret_cast<const float*>(A + L.sample_keys); xa.key_off = d_so;
+    xa.cand_off = d_co; xa.cand_pos = ca.cand_pos; xa.n_cand = ca.n_cand;
+    xa.heap = reinterpret_cast<uint64_t*>(A + L.cand_packed);
     StageScope st(s, 3);
-    HIP_TRY(bbc::launch_codebook(ca, s));
-  }
-  {
-    StageScope st(s, 2);
-    sa.mode = 1;
-    HIP_TRY(bbc::launch_pq_scan(sa, s));
-  }
-  {
-    StageScope st(s, 3);
-    HIP_TRY(bbc::launch_collect_bucket(ca, s));
+    HIP_TRY(bbc::launch_compare_collect(xa, p->collector, s));
   }
 
   bbc::RerankArgs ra{};
@@ -720,24 +737,26 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     if ((rc = cp(tr->probe_lists, L.probe_lists, 4 * npairs))) return rc;
     if ((rc = cp(tr->probe_keys, L.probe_keys, 4 * npairs))) return rc;
     if ((rc = cp(tr->n_recheck, L.n_recheck, 4 * nq))) return rc;
-    if ((rc = cp(tr->dmin, L.t_dmin, 4 * nq))) return rc;
-    if ((rc = cp(tr->delta, L.t_delta, 4 * nq))) return rc;
-    if ((rc = cp(tr->map, L.t_map, 256 * nq))) return rc;
-    if ((rc = cp(tr->tau, L.t_tau, 4 * nq))) return rc;
-    if ((rc = cp(tr->s, L.t_s, 8 * nq))) return rc;
-    if ((rc = cp(tr->bucket_counts, L.t_counts, 4 * nq * m))) return rc;
-    if ((rc = cp(tr->n_boundary, L.t_nb, 8 * nq))) return rc;
-    if ((rc = cp(tr->n_sample_lists, L.nsample_q, 4 * nq))) return rc;
-    if ((rc = cp(tr->n_sample_keys, L.t_nsk, 8 * nq))) return rc;
-    std::vector<uint32_t> nsurv(nq);
-    HIP_TRY(hipMemcpyAsync(nsurv.data(), A + L.surv_total, 4 * nq, hipMemcpyDeviceToHost, s));
+    std::vector<uint32_t> nsurv(nq, 0);
+    if (bucket) {  // the bucket collector's own intermediates
+      if ((rc = cp(tr->dmin, L.t_dmin, 4 * nq))) return rc;
+      if ((rc = cp(tr->delta, L.t_delta, 4 * nq))) return rc;
+      if ((rc = cp(tr->map, L.t_map, 256 * nq))) return rc;
+      if ((rc = cp(tr->tau, L.t_tau, 4 * nq))) return rc;
+      if ((rc = cp(tr->s, L.t_s, 8 * nq))) return rc;
+      if ((rc = cp(tr->bucket_counts, L.t_counts, 4 * nq * m))) return rc;
+      if ((rc = cp(tr->n_boundary, L.t_nb, 8 * nq))) return rc;
+      if ((rc = cp(tr->n_sample_lists, L.nsample_q, 4 * nq))) return rc;
+      if ((rc = cp(tr->n_sample_keys, L.t_nsk, 8 * nq))) return rc;
+      HIP_TRY(hipMemcpyAsync(nsurv.data(), A + L.surv_total, 4 * nq, hipMemcpyDeviceToHost, s));
+    }
     std::vector<int64_t> nsc(nq);
     HIP_TRY(hipMemcpyAsync(nsc.data(), A + L.n_scanned, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(n_cand_h.data(), A + L.n_cand, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (tr->n_scanned) std::memcpy(tr->n_scanned, nsc.data(), 8 * nq);
     if (tr->n_cand) std::memcpy(tr->n_cand, n_cand_h.data(), 8 * nq);
-    if (tr->n_survivors)
+    if (tr->n_survivors && bucket)
       for (int64_t i = 0; i < nq; ++i) tr->n_survivors[i] = nsurv[i];
     if (tr->est_off) {
       tr->est_off[0] = 0;

@@ -1,0 +1,230 @@
+// Comparator collectors: the same K_c candidates as the bucket collector
+// (the K_c smallest estimated (key, id) of the scanned objects), found the
+// ways the paper compares against (result-collector background: a bounded
+// max-heap, and selection by sorting).  Both read every scanned key, written
+// by slot by the scan with every probed list in the "sample" phase.
+//
+//  - sort: exact selection by a 32-bit radix select of the K_c-th key image
+//    over all S keys, then a compaction pass; ties on the threshold key are
+//    cut by id with a second radix select over the tied ids;
+//  - heap: one wave per query keeps a 64-ary max-heap of packed (key, id)
+//    of size K_c in global memory.  Its first K_c keys are heapified; every
+//    later key below the heap's top replaces the top and sifts down (each
+//    level: the 64 children are read by the 64 lanes and reduced).
+#include "common.h"
+#include "kernels.h"
+
+namespace bbc {
+
+namespace {
+
+constexpr int CMP_RANKCAP = 2048;      // probe ranks held in LDS (sort collector)
+constexpr int CMP_RANKCAP_HEAP = 256;  // (heap collector: small blocks, many per CU)
+
+// slot -> list slot (position) of the probed object, through LDS copies of
+// the query's rank offsets and list starts when they fit
+struct SlotMap {
+  const int64_t* rank_off;  // [np] slot offset of each probe rank
+  const int32_t* lists;     // [np] list of each probe rank
+  const int64_t* list_off;
+  int np;
+  const int32_t* s_rbeg;  // LDS copies (lds = true)
+  const int32_t* s_lbeg;
+  bool lds;
+  __device__ int64_t pos(int64_t slot) const {
+    int lo = 0, hi = np - 1;
+    if (lds) {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rbeg[mid] <= slot) lo = mid; else hi = mid - 1;
+      }
+      return (int64_t)s_lbeg[lo] + (slot - s_rbeg[lo]);
+    }
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rank_off[mid] <= slot) lo = mid; else hi = mid - 1;
+    }
+    return list_off[lists[lo]] + (slot - rank_off[lo]);
+  }
+};
+
+template <int NT, int CAP>
+__device__ SlotMap load_slot_map(const CompareArgs& a, int64_t qi, int32_t* s_rbeg, int32_t* s_lbeg) {
+  SlotMap sm;
+  const int64_t po = a.probe_off[qi];
+  sm.rank_off = a.rank_off + po;
+  sm.lists = a.probe_lists + po;
+  sm.list_off = a.list_off;
+  sm.np = a.nprobe[qi];
+  sm.lds = sm.np <= CAP && a.rank_off[po + sm.np - 1] < 0x7fffffff;
+  sm.s_rbeg = s_rbeg;
+  sm.s_lbeg = s_lbeg;
+  if (sm.lds)
+    for (int r = threadIdx.x; r < sm.np; r += NT) {
+      s_rbeg[r] = (int32_t)sm.rank_off[r];
+      s_lbeg[r] = (int32_t)sm.list_off[sm.lists[r]];
+    }
+  __syncthreads();
+  return sm;
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(1024) void sort_collect_kernel(CompareArgs a) {
+  constexpr int NT = 1024;
+  __shared__ int32_t s_rbeg[CMP_RANKCAP];
+  __shared__ int32_t s_lbeg[CMP_RANKCAP];
+  __shared__ uint32_t hist[256];
+  __shared__ __align__(8) uint32_t bc[8];
+
+  const int64_t qi = blockIdx.x;
+  const int64_t S = a.n_scanned[qi];
+  int64_t kc = a.kc_target[qi];
+  if (kc > S) kc = S;
+  if (threadIdx.x == 0) a.n_cand[qi] = kc > 0 ? kc : 0;
+  if (kc <= 0) return;
+  const SlotMap sm = load_slot_map<NT, CMP_RANKCAP>(a, qi, s_rbeg, s_lbeg);
+  const float* keys = a.keys + a.key_off[qi];
+  uint32_t* cand = a.cand_pos + a.cand_off[qi];
+  if (kc == S) {
+    for (int64_t i = threadIdx.x; i < S; i += NT) cand[i] = (uint32_t)sm.pos(i);
+    return;
+  }
+  const uint32_t T = block_radix_select32<NT>([&](int64_t i) { return key_bits(keys[i]); }, S, kc - 1, hist, bc);
+  // every key below T is a candidate
+  if (threadIdx.x == 0) { bc[4] = 0; bc[5] = 0; }
+  __syncthreads();
+  for (int64_t base = 0; base < S; base += NT) {  // wave-uniform trip count
+    const int64_t i = base + threadIdx.x;
+    const uint32_t kb = i < S ? key_bits(keys[i]) : 0xffffffffu;
+    const bool take = i < S && kb < T;
+    const uint32_t slot = wave_slot(take, &bc[4]);
+    if (take) cand[slot] = (uint32_t)sm.pos(i);
+    const uint64_t tie = __ballot(i < S && kb == T);
+    if ((threadIdx.x & 63) == 0 && tie) atomicAdd(&bc[5], (uint32_t)__popcll(tie));
+  }
+  __syncthreads();
+  const int64_t nless = bc[4];
+  const int64_t need = kc - nless;   // >= 1 of the keys equal to T
+  const int64_t nties = bc[5];
+  uint32_t id_thr = 0xffffffffu;     // all ties when they are exactly `need`
+  if (nties > need) {
+    // the `need` smallest ids among the ties (ids are distinct)
+    id_thr = (uint32_t)block_radix_select64<NT>(
+        [&](int64_t i, uint64_t& v) -> bool {
+          if (key_bits(keys[i]) != T) return false;
+          v = (uint64_t)(uint32_t)a.list_ids[sm.pos(i)];
+          return true;
+        },
+        S, need - 1, hist, bc);
+  }
+  if (threadIdx.x == 0) bc[6] = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < S; base += NT) {
+    const int64_t i = base + threadIdx.x;
+    bool take = false;
+    int64_t p = 0;
+    if (i < S && key_bits(keys[i]) == T) {
+      p = sm.pos(i);
+      take = (uint32_t)a.list_ids[p] <= id_thr;
+    }
+    const uint32_t slot = wave_slot(take, &bc[6]);
+    if (take) cand[nless + slot] = (uint32_t)p;
+  }
+}
+
+namespace {
+
+// heap storage in global memory, read past the L1 so that every lane of the
+// wave sees the stores of the others
+__device__ __forceinline__ uint64_t hload(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void hstore(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave: sift v down from node i of the 64-ary max-heap h[0, n).
+__device__ void heap_sift_down(uint64_t* h, int64_t n, int64_t i, uint64_t v) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const int64_t c0 = 64 * i + 1;
+    if (c0 >= n) break;
+    const int64_t cj = c0 + lane;
+    const bool ok = cj < n;
+    const uint64_t cv = ok ? hload(h + cj) : 0ull;
+    uint64_t mx = cv;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t o = __shfl_xor(mx, off);
+      mx = o > mx ? o : mx;
+    }
+    if (mx <= v) break;
+    const uint64_t at = __ballot(ok && cv == mx);
+    const int j = __ffsll((unsigned long long)at) - 1;
+    if (lane == 0) hstore(h + i, mx);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    i = c0 + j;
+  }
+  if (lane == 0) hstore(h + i, v);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+}  // namespace
+
+__global__ __launch_bounds__(64) void heap_collect_kernel(CompareArgs a) {
+  constexpr int NT = 64;
+  __shared__ int32_t s_rbeg[CMP_RANKCAP_HEAP];
+  __shared__ int32_t s_lbeg[CMP_RANKCAP_HEAP];
+  const int lane = threadIdx.x;
+
+  const int64_t qi = blockIdx.x;
+  const int64_t S = a.n_scanned[qi];
+  int64_t kc = a.kc_target[qi];
+  if (kc > S) kc = S;
+  if (lane == 0) a.n_cand[qi] = kc > 0 ? kc : 0;
+  if (kc <= 0) return;
+  const SlotMap sm = load_slot_map<NT, CMP_RANKCAP_HEAP>(a, qi, s_rbeg, s_lbeg);
+  const float* keys = a.keys + a.key_off[qi];
+  uint32_t* cand = a.cand_pos + a.cand_off[qi];
+  if (kc == S) {
+    for (int64_t i = lane; i < S; i += NT) cand[i] = (uint32_t)sm.pos(i);
+    return;
+  }
+  uint64_t* h = a.heap + a.cand_off[qi];
+  auto packed = [&](int64_t i) -> uint64_t {
+    return pack_key_id(keys[i], (uint32_t)a.list_ids[sm.pos(i)]);
+  };
+  // the first kc keys, then heapify bottom-up
+  for (int64_t i = lane; i < kc; i += NT) hstore(h + i, packed(i));
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  for (int64_t node = (kc - 2) / 64; node >= 0; --node) heap_sift_down(h, kc, node, hload(h + node));
+  uint64_t top = hload(h);
+  for (int64_t base = kc; base < S; base += NT) {
+    const int64_t i = base + lane;
+    uint64_t v = ~0ull;
+    // key filter first: only keys not above the top's key need their id
+    if (i < S && key_bits(keys[i]) <= (uint32_t)(top >> 32)) v = packed(i);
+    uint64_t mask = __ballot(v < top);
+    while (mask) {
+      const int j = __ffsll((unsigned long long)mask) - 1;
+      mask &= mask - 1;
+      const uint64_t x = __shfl(v, j);
+      if (x < top) {  // the top only decreases
+        heap_sift_down(h, kc, 0, x);
+        top = hload(h);
+      }
+    }
+  }
+  for (int64_t i = lane; i < kc; i += NT) cand[i] = (uint32_t)a.pos_of_id[packed_id(hload(h + i))];
+}
+
+hipError_t launch_compare_collect(const CompareArgs& a, int collector, hipStream_t s) {
+  if (a.nq <= 0) return hipSuccess;
+  if (collector == 1)
+    hipLaunchKernelGGL(heap_collect_kernel, dim3((unsigned)a.nq), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(sort_collect_kernel, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bbc

@@ -100,6 +100,18 @@ struct FinalArgs {
   int run;                  // largest power of two <= cap: LDS sort run of the global sort
   int64_t max_kc;           // largest K_c of the batch (selects the register-resident variant)
 };
+// ---- comparator collectors (heap, sort) over every scanned key ----------------
+struct CompareArgs {
+  int64_t nq; const int64_t* n_scanned; const int64_t* kc_target; const int32_t* nprobe; const int64_t* probe_off;
+  const int64_t* rank_off; const int32_t* probe_lists; const int64_t* list_off; const int32_t* list_ids;
+  const int32_t* pos_of_id;
+  const float* keys; const int64_t* key_off;   // every scanned key of query q at keys[key_off[q] + slot]
+  const int64_t* cand_off; uint32_t* cand_pos; int64_t* n_cand;
+  uint64_t* heap;                              // [sum K_c] heap storage (heap collector)
+};
+// collector: 1 heap, 2 sort
+hipError_t launch_compare_collect(const CompareArgs& a, int collector, hipStream_t s);
+
 constexpr int FINAL_STATIC_LDS = 21000;  // bytes of static LDS of the final top-k kernel (upper bound)
 hipError_t launch_final_topk(const FinalArgs& a, hipStream_t s);
 

@@ -71,3 +71,35 @@ def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2):
 def sort_pairs(ids, keys):
     o = np.lexsort((ids, keys))
     return ids[o], keys[o]
+
+
+def check_trace(tr, exp, m, bucket=True):
+    """Every step of a traced GPU search against the oracle's expectation
+    (the bucket collector's codebook, counts and threshold only when
+    `bucket`)."""
+    nq = len(exp)
+    for i in range(nq):
+        e = exp[i]
+        ps = slice(int(np.sum([len(x["probe_lists"]) for x in exp[:i]])),
+                   int(np.sum([len(x["probe_lists"]) for x in exp[:i + 1]])))
+        np.testing.assert_array_equal(tr["probe_lists"][ps], e["probe_lists"], err_msg=f"probe q{i}")
+        np.testing.assert_array_equal(tr["probe_keys"][ps], e["probe_keys"], err_msg=f"probe keys q{i}")
+        assert tr["n_scanned"][i] == e["n_scanned"]
+        es = slice(tr["est_off"][i], tr["est_off"][i + 1])
+        np.testing.assert_array_equal(tr["est_keys"][es], e["est_keys"], err_msg=f"estimated keys q{i}")
+        assert tr["n_cand"][i] == e["n_cand"]
+        col = e["collect"]
+        if bucket and col is not None and e["n_cand"] > 0:
+            assert tr["dmin"][i] == col["dmin"] and tr["delta"][i] == col["delta"], f"codebook q{i}"
+            np.testing.assert_array_equal(tr["map"][i], col["map"], err_msg=f"map q{i}")
+            np.testing.assert_array_equal(tr["bucket_counts"][i][:m], col["counts"], err_msg=f"counts q{i}")
+            assert tr["tau"][i] == col["tau"] and tr["s"][i] == col["s"], f"tau/s q{i}"
+        cs = slice(tr["cand_off"][i], tr["cand_off"][i + 1])
+        gi, gk = sort_pairs(tr["cand_ids"][cs], tr["cand_exact"][cs])
+        ei, ek = sort_pairs(e["cand_ids"], e["cand_exact"])
+        np.testing.assert_array_equal(gi, ei, err_msg=f"candidates q{i}")
+        np.testing.assert_array_equal(gk, ek, err_msg=f"exact keys q{i}")
+        os_ = slice(tr["off"][i], tr["off"][i + 1])
+        assert tr["counts"][i] == e["count"]
+        np.testing.assert_array_equal(tr["ids"][os_], e["ids"], err_msg=f"ids q{i}")
+        np.testing.assert_array_equal(tr["dists"][os_], e["dists"], err_msg=f"dists q{i}")

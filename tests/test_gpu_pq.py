@@ -4,7 +4,7 @@ candidate set, exact keys, final ids and distances)."""
 import numpy as np
 import pytest
 
-from helpers import expected_steps, make_gpu_index, oracle_pq_index, sort_pairs
+from helpers import check_trace, expected_steps, make_gpu_index, oracle_pq_index
 
 pytestmark = pytest.mark.gpu
 
@@ -14,35 +14,6 @@ def bbc():
     import paper_2604_01960_amd as b
     b.load()
     return b
-
-
-def _check_trace(tr, exp, q_index_slice, m):
-    nq = len(exp)
-    for i in range(nq):
-        e = exp[i]
-        ps = slice(int(np.sum([len(x["probe_lists"]) for x in exp[:i]])),
-                   int(np.sum([len(x["probe_lists"]) for x in exp[:i + 1]])))
-        np.testing.assert_array_equal(tr["probe_lists"][ps], e["probe_lists"], err_msg=f"probe q{i}")
-        np.testing.assert_array_equal(tr["probe_keys"][ps], e["probe_keys"], err_msg=f"probe keys q{i}")
-        assert tr["n_scanned"][i] == e["n_scanned"]
-        es = slice(tr["est_off"][i], tr["est_off"][i + 1])
-        np.testing.assert_array_equal(tr["est_keys"][es], e["est_keys"], err_msg=f"estimated keys q{i}")
-        assert tr["n_cand"][i] == e["n_cand"]
-        col = e["collect"]
-        if col is not None and e["n_cand"] > 0:
-            assert tr["dmin"][i] == col["dmin"] and tr["delta"][i] == col["delta"], f"codebook q{i}"
-            np.testing.assert_array_equal(tr["map"][i], col["map"], err_msg=f"map q{i}")
-            np.testing.assert_array_equal(tr["bucket_counts"][i][:m], col["counts"], err_msg=f"counts q{i}")
-            assert tr["tau"][i] == col["tau"] and tr["s"][i] == col["s"], f"tau/s q{i}"
-        cs = slice(tr["cand_off"][i], tr["cand_off"][i + 1])
-        gi, gk = sort_pairs(tr["cand_ids"][cs], tr["cand_exact"][cs])
-        ei, ek = sort_pairs(e["cand_ids"], e["cand_exact"])
-        np.testing.assert_array_equal(gi, ei, err_msg=f"candidates q{i}")
-        np.testing.assert_array_equal(gk, ek, err_msg=f"exact keys q{i}")
-        os_ = slice(tr["off"][i], tr["off"][i + 1])
-        assert tr["counts"][i] == e["count"]
-        np.testing.assert_array_equal(tr["ids"][os_], e["ids"], err_msg=f"ids q{i}")
-        np.testing.assert_array_equal(tr["dists"][os_], e["dists"], err_msg=f"dists q{i}")
 
 
 @pytest.mark.parametrize("cfg", [
@@ -58,7 +29,7 @@ def test_every_step_matches_oracle(bbc, cfg):
     g = make_gpu_index(bbc, ix)
     tr = g.search_traced(q, k, nprobe, ratio=ratio, buckets=m, nsample=ns)
     exp = expected_steps(ix, q, k, nprobe, ratio, m, ns)
-    _check_trace(tr, exp, None, m)
+    check_trace(tr, exp, m)
 
 
 def test_uneven_and_edge_cases(bbc):
@@ -72,7 +43,7 @@ def test_uneven_and_edge_cases(bbc):
         for m in (1, 2, 256):
             tr = g.search_traced(q, k, npb, ratio=ratio, buckets=m, nsample=2)
             exp = expected_steps(ix, q, k, npb, ratio, m, 2)
-            _check_trace(tr, exp, None, m)
+            check_trace(tr, exp, m)
     # k larger than everything scanned pads with -1 / +inf
     ids, dists, counts, off = g.search(q[:1], 5000, 1, ratio=1.0)
     s = int(sizes[tr["probe_lists"][0]]) if False else int(counts[0])
@@ -99,7 +70,7 @@ def test_ties_on_integer_data(bbc):
     g = make_gpu_index(bbc, ix)
     tr = g.search_traced(q, 700, 4, ratio=2.0, buckets=16, nsample=2)
     exp = expected_steps(ix, q, 700, 4, 2.0, 16, 2)
-    _check_trace(tr, exp, None, 16)
+    check_trace(tr, exp, 16)
 
 
 def test_full_100k_config_bit_exact(bbc):
