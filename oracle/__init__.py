@@ -78,6 +78,13 @@ def lib():
                                         vp, i64, vp, vp, f64, vp, vp, vp, vp,
                                         vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_exact_knn64.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp]
+            L.orc_rotate.argtypes = [vp, i32, vp, i64, vp]
+            L.orc_rabitq_encode.argtypes = [vp, vp, vp, i32, vp, i32, vp, vp, vp]
+            L.orc_rabitq_prep.argtypes = [vp, i32, vp, vp]
+            L.orc_rabitq_bounds.argtypes = [vp, vp, i64, i32, vp, vp, i32, f32, f32, f32, vp, vp, vp]
+            L.orc_search_rabitq.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, f32,
+                                            vp, i64, vp, vp, vp, vp, vp, vp,
+                                            vp, vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_num_threads.restype = C.c_int
             _lib = L
     return _lib
@@ -288,6 +295,123 @@ def build_ivf_pq(x, nlist, M, bits, train_rows, init_pos, pq_rows, pq_init, iter
     return dict(kind="pq", n=n, d=d, nlist=nlist, M=M, ksub=ksub, bits=bits, metric=0,
                 centroids=cent, assign=assign, list_off=list_off, list_ids=order,
                 codes=codes, codebook=cb, base=x)
+
+
+# --------------------------------------------------------------------------
+# RaBitQ (rotation, codes, query quantization, bounds)
+# --------------------------------------------------------------------------
+
+RABITQ_EPS0 = 1.9   # the cited method's default confidence parameter
+
+
+def rotate(P, v):
+    """y = P^T v for each row v (sequential float32 sums, see oracle.c)."""
+    P = _f32(P)
+    v = _f32(np.atleast_2d(v))
+    D = P.shape[0]
+    y = np.empty_like(v)
+    lib().orc_rotate(_p(P), D, _p(v), v.shape[0], _p(y))
+    return y
+
+
+def rabitq_encode(x, list_ids, list_off, centroids, P):
+    """Codes [n][D/32] uint32 and factors [n][4] (nr, f, g, popcount) of the
+    objects in list-slot order."""
+    x = _f32(x)
+    n, D = x.shape
+    nlist = len(list_off) - 1
+    codes = np.empty((n, D // 32), np.uint32)
+    fac = np.empty((n, 4), np.float32)
+    _check(lib().orc_rabitq_encode(_p(x), _p(_i64(list_ids)), _p(_i64(list_off)), nlist, _p(_f32(centroids)),
+                                   D, _p(_f32(P)), _p(codes), _p(fac)), "rabitq_encode")
+    return codes, fac
+
+
+def rabitq_prep(y):
+    """Quantized query side of one rotated vector: planes [4][D/32] and
+    scal = (vl, delta, c1, c2, c3, c4)."""
+    y = _f32(y)
+    D = y.shape[0]
+    planes = np.empty((4, D // 32), np.uint32)
+    scal = np.empty(6, np.float32)
+    lib().orc_rabitq_prep(_p(y), D, _p(planes), _p(scal))
+    return planes, scal
+
+
+def rabitq_bounds(codes, factors, planes, scal, metric, a, qn=0.0, eps0=RABITQ_EPS0):
+    """(key, lb, ub) of the objects for one prepared query side."""
+    codes = np.ascontiguousarray(codes, np.uint32)
+    factors = _f32(factors)
+    n = codes.shape[0]
+    D = codes.shape[1] * 32
+    key = np.empty(n, np.float32)
+    lb = np.empty(n, np.float32)
+    ub = np.empty(n, np.float32)
+    lib().orc_rabitq_bounds(_p(codes), _p(factors), n, D, _p(np.ascontiguousarray(planes, np.uint32)),
+                            _p(_f32(scal)), int(metric), float(a), float(qn), float(eps0), _p(key), _p(lb), _p(ub))
+    return key, lb, ub
+
+
+def build_ivf_rabitq(x, nlist, train_rows, init_pos, P, iters=10, metric=0):
+    """IVF k-means + RaBitQ codes of the residuals.  The rotation P and the
+    k-means draws are inputs.  Base rows may be float16 (converted exactly)."""
+    xf = _f32(x)
+    n, d = xf.shape
+    if d % 64:
+        raise ValueError("RaBitQ needs d to be a multiple of 64")
+    cent = kmeans_train(xf, train_rows, init_pos, nlist, iters)
+    assign = kmeans_assign(xf, cent)
+    order = np.argsort(assign, kind="stable").astype(np.int64)
+    counts = np.bincount(assign, minlength=nlist)
+    list_off = np.zeros(nlist + 1, np.int64)
+    list_off[1:] = np.cumsum(counts)
+    codes, fac = rabitq_encode(xf, order, list_off, cent, P)
+    return dict(kind="rabitq", n=n, d=d, nlist=nlist, metric=int(metric), centroids=cent,
+                rot_centroids=rotate(P, cent), P=_f32(P), assign=assign, list_off=list_off, list_ids=order,
+                codes=codes, factors=fac, base=xf, fp16=(np.asarray(x).dtype == np.float16))
+
+
+def search_rabitq(index, queries, k, nprobe, eps0=RABITQ_EPS0, debug=False):
+    """Full RaBitQ query path with the bounded re-rank.  Returns dict(ids,
+    dists, counts, off[, probe_*, n_scanned, est_key / est_lb / est_ub (by
+    scanned slot, probe order), est_off, n_visited])."""
+    q = _f32(queries)
+    nq = q.shape[0]
+    kk = _i32(np.broadcast_to(np.asarray(k), (nq,)))
+    npb = _i32(np.broadcast_to(np.asarray(nprobe), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    res = dict(ids=np.empty(off[-1], np.int64), dists=np.empty(off[-1], np.float32),
+               counts=np.empty(nq, np.int32), off=off)
+    ix = index
+    dbg = [None] * 9
+    if debug:
+        poff = np.zeros(nq + 1, np.int64)
+        poff[1:] = np.cumsum(npb)
+        pl = np.empty(poff[-1], np.int32)
+        pk = np.empty(poff[-1], np.float32)
+        # scanned sizes first (probe only), then the per-object arrays
+        sizes = np.diff(ix["list_off"])
+        _check(lib().orc_probe(_p(q), nq, ix["d"], _p(_f32(ix["centroids"])), ix["nlist"], ix["metric"],
+                               _p(npb), _p(poff), _p(pl), _p(pk)), "probe")
+        ns = np.array([sizes[pl[poff[i]:poff[i + 1]]].sum() for i in range(nq)], np.int64)
+        eoff = np.zeros(nq + 1, np.int64)
+        eoff[1:] = np.cumsum(ns)
+        ek = np.empty(eoff[-1], np.float32)
+        el = np.empty(eoff[-1], np.float32)
+        eu = np.empty(eoff[-1], np.float32)
+        nv = np.empty(nq, np.int64)
+        nsc = np.empty(nq, np.int64)
+        dbg = [pl, pk, poff, nsc, ek, el, eu, eoff, nv]
+        res.update(probe_lists=pl, probe_keys=pk, probe_off=poff, n_scanned=nsc, est_key=ek, est_lb=el,
+                   est_ub=eu, est_off=eoff, n_visited=nv)
+    _check(lib().orc_search_rabitq(
+        ix["n"], ix["d"], ix["nlist"], _p(_f32(ix["centroids"])), _p(_f32(ix["rot_centroids"])),
+        _p(_f32(ix["P"])), _p(_i64(ix["list_off"])), _p(_i64(ix["list_ids"])),
+        _p(np.ascontiguousarray(ix["codes"], np.uint32)), _p(_f32(ix["factors"])), _p(_f32(ix["base"])),
+        ix["metric"], float(eps0), _p(q), nq, _p(kk), _p(npb), _p(off), _p(res["ids"]), _p(res["dists"]),
+        _p(res["counts"]), *[_p(a) for a in dbg]), "search_rabitq")
+    return res
 
 
 # --------------------------------------------------------------------------

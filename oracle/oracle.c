@@ -655,6 +655,386 @@ int orc_search_pq(int64_t n, int32_t d, int32_t nlist, const float* centroids,
 }
 
 /* ------------------------------------------------------------------------ */
+/* RaBitQ codes and bounds (the bounded quantizer the paper integrates with, */
+/* cited in the background and Algorithms 2-3), in the fixed FP32 order:     */
+/*                                                                          */
+/*   rotation: y = P^T v, y_i = sum over e = 0..D-1 of (P[e][i] * v[e]),      */
+/*     product rounded, then added, sequentially from +0;                    */
+/*   code of object x in list j: r = x - c_j, y = P^T r, bit i = (y_i > 0);  */
+/*     nr = sqrt(canon_l2(x, c_j)); s1 = sum_i |y_i| (sequential);          */
+/*     <o_bar, o> = s1 / (nr * sqrt(D)), clamped to <= 1 (1 when nr = 0,    */
+/*     with all bits 0); f = 1 / <o_bar, o>;                                 */
+/*     g = sqrt(1 - <o_bar,o>^2) / <o_bar,o>; pc = popcount of the code;     */
+/*   query side, per (query, list) for L2 (y = P^T q - P^T c_j) or once per  */
+/*     query for IP (y = P^T q): vl = min y, vu = max y,                     */
+/*     delta = (vu - vl) * fl(1/15); u_i = clamp(floor((y_i - vl) / delta   */
+/*     + 0.5), 0, 15) (0 when delta = 0); four bit planes of u;             */
+/*     c1 = 2 delta / sqrt(D), c2 = 2 vl / sqrt(D),                          */
+/*     c3 = (delta / sqrt(D)) * sum_i u_i, c4 = sqrt(D) * vl;                */
+/*   per object: ip = sum_b 2^b popcount(code & plane_b) (integer);         */
+/*     est = (((c1 * ip + c2 * pc) - c3) - c4) * f;                          */
+/*     L2: key = (nr*nr + nq2) - (2 nr) * est, with nq2 = canon_l2(q, c_j);  */
+/*         err = (((2 nr) * sqrt(nq2)) * g) * epsc;                          */
+/*     IP: key = -(ipc + nr * est), ipc = canon_ip(q, c_j);                  */
+/*         err = ((nr * sqrt(canon_ip(q, q))) * g) * epsc;                   */
+/*     epsc = eps0 / sqrt(D - 1); lb = key - err; ub = key + err.            */
+/* ------------------------------------------------------------------------ */
+
+void orc_rotate(const float* P, int32_t D, const float* v, int64_t n, float* y) {
+#pragma omp parallel for schedule(static)
+  for (int64_t r = 0; r < n; ++r) {
+    const float* vv = v + r * D;
+    float* yy = y + r * D;
+    for (int32_t i = 0; i < D; ++i) {
+      float acc = 0.0f;
+      for (int32_t e = 0; e < D; ++e) {
+        float t = P[(int64_t)e * D + i] * vv[e];
+        acc = acc + t;
+      }
+      yy[i] = acc;
+    }
+  }
+}
+
+/* Codes [n][D/32] (bit i of object p at word i/32, bit i%32) and factors
+ * [n][4] = (nr, f, g, pc) of the objects in list-slot order. */
+int orc_rabitq_encode(const float* x, const int64_t* list_ids, const int64_t* list_off, int32_t nlist,
+                      const float* centroids, int32_t D, const float* P, uint32_t* codes, float* factors) {
+  if (D % 64) return ORC_EINVAL;
+  const int32_t W = D / 32;
+  const float sD = sqrtf((float)D);
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int32_t j = 0; j < nlist; ++j) {
+    float* r = (float*)malloc(sizeof(float) * (size_t)D * 2);
+    if (!r) {
+#pragma omp critical
+      err = ORC_ENOMEM;
+      continue;
+    }
+    float* y = r + D;
+    const float* c = centroids + (int64_t)j * D;
+    for (int64_t p = list_off[j]; p < list_off[j + 1]; ++p) {
+      const float* xv = x + list_ids[p] * (int64_t)D;
+      for (int32_t e = 0; e < D; ++e) r[e] = xv[e] - c[e];
+      for (int32_t i = 0; i < D; ++i) {
+        float acc = 0.0f;
+        for (int32_t e = 0; e < D; ++e) {
+          float t = P[(int64_t)e * D + i] * r[e];
+          acc = acc + t;
+        }
+        y[i] = acc;
+      }
+      const float nr = sqrtf(orc_canon_l2(xv, c, D));
+      uint32_t* code = codes + p * W;
+      float* fac = factors + p * 4;
+      for (int32_t w = 0; w < W; ++w) code[w] = 0u;
+      if (nr == 0.0f) {
+        fac[0] = 0.0f; fac[1] = 1.0f; fac[2] = 0.0f; fac[3] = 0.0f;
+        continue;
+      }
+      float s1 = 0.0f;
+      uint32_t pc = 0;
+      for (int32_t i = 0; i < D; ++i) {
+        s1 = s1 + fabsf(y[i]);
+        if (y[i] > 0.0f) { code[i / 32] |= 1u << (i % 32); ++pc; }
+      }
+      float den = nr * sD;
+      float ipoo = s1 / den;
+      if (ipoo > 1.0f) ipoo = 1.0f;
+      float g = ipoo * ipoo;
+      g = 1.0f - g;
+      g = sqrtf(g);
+      g = g / ipoo;
+      fac[0] = nr;
+      fac[1] = 1.0f / ipoo;
+      fac[2] = g;
+      fac[3] = (float)pc;
+    }
+    free(r);
+  }
+  return err;
+}
+
+/* Query-side quantization of one rotated vector y[D]: planes [4][D/32] and
+ * scal = (vl, delta, c1, c2, c3, c4). */
+void orc_rabitq_prep(const float* y, int32_t D, uint32_t* planes, float* scal) {
+  const int32_t W = D / 32;
+  float vl = y[0], vu = y[0];
+  for (int32_t i = 1; i < D; ++i) {
+    if (y[i] < vl) vl = y[i];
+    if (y[i] > vu) vu = y[i];
+  }
+  const float inv15 = 1.0f / 15.0f;
+  float delta = vu - vl;
+  delta = delta * inv15;
+  for (int32_t b = 0; b < 4 * W; ++b) planes[b] = 0u;
+  int32_t sum_u = 0;
+  for (int32_t i = 0; i < D; ++i) {
+    int32_t u = 0;
+    if (delta > 0.0f) {
+      float t = y[i] - vl;
+      t = t / delta;
+      t = t + 0.5f;
+      t = floorf(t);
+      u = t < 0.0f ? 0 : (t > 15.0f ? 15 : (int32_t)t);
+    }
+    sum_u += u;
+    for (int32_t b = 0; b < 4; ++b)
+      if ((u >> b) & 1) planes[b * W + i / 32] |= 1u << (i % 32);
+  }
+  const float sD = sqrtf((float)D);
+  float c1 = 2.0f * delta;
+  c1 = c1 / sD;
+  float c2 = 2.0f * vl;
+  c2 = c2 / sD;
+  float c3 = delta / sD;
+  c3 = c3 * (float)sum_u;
+  float c4 = sD * vl;
+  scal[0] = vl; scal[1] = delta; scal[2] = c1; scal[3] = c2; scal[4] = c3; scal[5] = c4;
+}
+
+static inline int32_t popc32(uint32_t v) {
+  int32_t c = 0;
+  while (v) { v &= v - 1u; ++c; }
+  return c;
+}
+
+/* Estimated inner product term est for one object (before the metric). */
+static float rabitq_est(const uint32_t* code, const float* fac, const uint32_t* planes, const float* scal,
+                        int32_t W) {
+  int64_t ip = 0;
+  for (int32_t b = 0; b < 4; ++b) {
+    int64_t c = 0;
+    for (int32_t w = 0; w < W; ++w) c += popc32(code[w] & planes[b * W + w]);
+    ip += c << b;
+  }
+  float est = scal[2] * (float)ip;
+  float t = scal[3] * fac[3];
+  est = est + t;
+  est = est - scal[4];
+  est = est - scal[5];
+  est = est * fac[1];
+  return est;
+}
+
+/* key, lb, ub of n objects (codes/factors of consecutive slots) for one
+ * prepared query side.  L2: a = nq2 (canon_l2(q, c_j)); IP: a = ipc
+ * (canon_ip(q, c_j)) and qn = sqrt(canon_ip(q, q)). */
+void orc_rabitq_bounds(const uint32_t* codes, const float* factors, int64_t n, int32_t D, const uint32_t* planes,
+                       const float* scal, int32_t metric, float a, float qn, float eps0, float* key,
+                       float* lb, float* ub) {
+  const int32_t W = D / 32;
+  const float epsc = eps0 / sqrtf((float)(D - 1));
+  const float nq = sqrtf(a);
+  for (int64_t p = 0; p < n; ++p) {
+    const float* fac = factors + p * 4;
+    const float nr = fac[0];
+    const float est = rabitq_est(codes + p * W, fac, planes, scal, W);
+    float kk, e;
+    if (metric == 0) {
+      float t = nr * nr;
+      t = t + a;
+      float u = 2.0f * nr;
+      u = u * est;
+      kk = t - u;
+      e = 2.0f * nr;
+      e = e * nq;
+      e = e * fac[2];
+      e = e * epsc;
+    } else {
+      float v = nr * est;
+      v = a + v;
+      kk = -v;
+      e = nr * qn;
+      e = e * fac[2];
+      e = e * epsc;
+    }
+    key[p] = kk;
+    lb[p] = kk - e;
+    ub[p] = kk + e;
+  }
+}
+
+typedef struct {
+  int64_t n; int32_t d; int32_t nlist;
+  const float* centroids;      /* [nlist][d] */
+  const float* rot_centroids;  /* [nlist][d] = P^T c_j (orc_rotate) */
+  const float* P;              /* [d][d] */
+  const int64_t* list_off;
+  const int64_t* list_ids;
+  const uint32_t* codes;       /* [n][d/32], list order */
+  const float* factors;        /* [n][4], list order */
+  const float* base;           /* [n][d] original row order (fp32) */
+  int32_t metric;
+  float eps0;
+} orc_rabitq_index;
+
+/* binary max-heap of (key, id) */
+static void heap_down(kv_t* h, int64_t n, int64_t i) {
+  while (1) {
+    int64_t l = 2 * i + 1, r = l + 1, m = i;
+    if (l < n && kv_cmp(&h[l], &h[m]) > 0) m = l;
+    if (r < n && kv_cmp(&h[r], &h[m]) > 0) m = r;
+    if (m == i) return;
+    kv_t t = h[i]; h[i] = h[m]; h[m] = t;
+    i = m;
+  }
+}
+static void heap_up(kv_t* h, int64_t i) {
+  while (i > 0) {
+    int64_t p = (i - 1) / 2;
+    if (kv_cmp(&h[i], &h[p]) <= 0) return;
+    kv_t t = h[i]; h[i] = h[p]; h[p] = t;
+    i = p;
+  }
+}
+
+/* The bounded re-rank: objects in ascending (lb, id); walking them with R =
+ * the best k by (exact key, id) so far, stop before object t when R holds k
+ * objects and lb_t > the k-th exact key of R (equality does not stop);
+ * otherwise compute t's exact key and offer it to R.  Returns the number of
+ * exact keys computed; R (unsorted) in res[0, *nres). */
+static int64_t bounded_walk(const kv_t* order, int64_t S, int64_t k, const float* q, const orc_rabitq_index* ix,
+                            kv_t* res, int64_t* nres) {
+  int64_t nr = 0, t = 0;
+  for (; t < S; ++t) {
+    if (nr == k && order[t].key > res[0].key) break;
+    const float* x = ix->base + order[t].id * (int64_t)ix->d;
+    kv_t e;
+    e.key = ix->metric == 0 ? orc_canon_l2(q, x, ix->d) : -orc_canon_ip(q, x, ix->d);
+    e.pad = 0;
+    e.id = order[t].id;
+    if (nr < k) {
+      res[nr] = e;
+      heap_up(res, nr);
+      ++nr;
+    } else if (kv_cmp(&e, &res[0]) < 0) {
+      res[0] = e;
+      heap_down(res, nr, 0);
+    }
+  }
+  *nres = nr;
+  return t;
+}
+
+typedef struct {
+  int32_t* probe_lists; float* probe_keys; const int64_t* probe_off;
+  int64_t* n_scanned;
+  float* est_key; float* est_lb; float* est_ub; const int64_t* est_off;  /* by scanned slot, probe order */
+  int64_t* n_visited;
+} orc_rabitq_debug;
+
+static int search_rabitq_one(const orc_rabitq_index* ix, const float* q, int32_t k, int32_t nprobe,
+                             int64_t* out_ids, float* out_dists, int32_t* out_count,
+                             const orc_rabitq_debug* dbg, int64_t qi) {
+  const int32_t D = ix->d, W = D / 32;
+  int32_t* lists = (int32_t*)malloc(sizeof(int32_t) * (size_t)nprobe);
+  float* lkeys = (float*)malloc(sizeof(float) * (size_t)nprobe);
+  float* qr = (float*)malloc(sizeof(float) * (size_t)D * 2);
+  uint32_t* planes = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)4 * W);
+  if (!lists || !lkeys || !qr || !planes) { free(lists); free(lkeys); free(qr); free(planes); return ORC_ENOMEM; }
+  float* y = qr + D;
+  int rc = probe_one(q, ix->centroids, ix->nlist, D, ix->metric, nprobe, lists, lkeys);
+  if (rc) { free(lists); free(lkeys); free(qr); free(planes); return rc; }
+  if (dbg && dbg->probe_lists)
+    for (int32_t i = 0; i < nprobe; ++i) dbg->probe_lists[dbg->probe_off[qi] + i] = lists[i];
+  if (dbg && dbg->probe_keys)
+    for (int32_t i = 0; i < nprobe; ++i) dbg->probe_keys[dbg->probe_off[qi] + i] = lkeys[i];
+  int64_t S = 0;
+  for (int32_t i = 0; i < nprobe; ++i) S += ix->list_off[lists[i] + 1] - ix->list_off[lists[i]];
+  kv_t* ord = (kv_t*)malloc(sizeof(kv_t) * (size_t)(S > 0 ? S : 1));
+  float* kb = (float*)malloc(sizeof(float) * (size_t)(S > 0 ? S : 1) * 3);
+  kv_t* res = (kv_t*)malloc(sizeof(kv_t) * (size_t)(k > 0 ? k : 1));
+  if (!ord || !kb || !res) {
+    free(lists); free(lkeys); free(qr); free(planes); free(ord); free(kb); free(res);
+    return ORC_ENOMEM;
+  }
+  orc_rotate(ix->P, D, q, 1, qr);
+  float scal[6];
+  float qn = 0.0f;
+  if (ix->metric != 0) {
+    orc_rabitq_prep(qr, D, planes, scal);
+    qn = sqrtf(orc_canon_ip(q, q, D));
+  }
+  int64_t w = 0;
+  for (int32_t i = 0; i < nprobe; ++i) {
+    const int32_t j = lists[i];
+    const int64_t n = ix->list_off[j + 1] - ix->list_off[j];
+    float a;
+    if (ix->metric == 0) {
+      const float* cr = ix->rot_centroids + (int64_t)j * D;
+      for (int32_t e = 0; e < D; ++e) y[e] = qr[e] - cr[e];
+      orc_rabitq_prep(y, D, planes, scal);
+      a = lkeys[i];                 /* canon_l2(q, c_j) */
+    } else {
+      a = -lkeys[i];                /* canon_ip(q, c_j) */
+    }
+    float* key = kb + w;
+    float* lb = kb + S + w;
+    float* ub = kb + 2 * S + w;
+    orc_rabitq_bounds(ix->codes + ix->list_off[j] * W, ix->factors + ix->list_off[j] * 4, n, D, planes, scal,
+                      ix->metric, a, qn, ix->eps0, key, lb, ub);
+    for (int64_t p = 0; p < n; ++p) {
+      ord[w + p].key = lb[p];
+      ord[w + p].pad = 0;
+      ord[w + p].id = ix->list_ids[ix->list_off[j] + p];
+    }
+    w += n;
+  }
+  if (dbg && dbg->n_scanned) dbg->n_scanned[qi] = S;
+  if (dbg && dbg->est_key)
+    for (int64_t p = 0; p < S; ++p) {
+      dbg->est_key[dbg->est_off[qi] + p] = kb[p];
+      dbg->est_lb[dbg->est_off[qi] + p] = kb[S + p];
+      dbg->est_ub[dbg->est_off[qi] + p] = kb[2 * S + p];
+    }
+  qsort(ord, (size_t)S, sizeof(kv_t), kv_cmp);
+  int64_t nres = 0;
+  const int64_t visited = bounded_walk(ord, S, k, q, ix, res, &nres);
+  if (dbg && dbg->n_visited) dbg->n_visited[qi] = visited;
+  qsort(res, (size_t)nres, sizeof(kv_t), kv_cmp);
+  for (int64_t i = 0; i < k; ++i) {
+    if (i < nres) {
+      out_ids[i] = res[i].id;
+      out_dists[i] = ix->metric == 0 ? res[i].key : -res[i].key;
+    } else {
+      out_ids[i] = -1;
+      out_dists[i] = ix->metric == 0 ? INFINITY : -INFINITY;
+    }
+  }
+  *out_count = (int32_t)nres;
+  free(lists); free(lkeys); free(qr); free(planes); free(ord); free(kb); free(res);
+  return ORC_OK;
+}
+
+int orc_search_rabitq(int64_t n, int32_t d, int32_t nlist, const float* centroids, const float* rot_centroids,
+                      const float* P, const int64_t* list_off, const int64_t* list_ids, const uint32_t* codes,
+                      const float* factors, const float* base, int32_t metric, float eps0,
+                      const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                      const int64_t* out_off, int64_t* out_ids, float* out_dists, int32_t* out_counts,
+                      int32_t* dbg_probe_lists, float* dbg_probe_keys, const int64_t* dbg_probe_off,
+                      int64_t* dbg_n_scanned, float* dbg_key, float* dbg_lb, float* dbg_ub,
+                      const int64_t* dbg_est_off, int64_t* dbg_n_visited) {
+  if (d % 64) return ORC_EINVAL;
+  orc_rabitq_index ix = {n, d, nlist, centroids, rot_centroids, P, list_off, list_ids, codes, factors, base,
+                         metric, eps0};
+  orc_rabitq_debug dbg = {dbg_probe_lists, dbg_probe_keys, dbg_probe_off, dbg_n_scanned,
+                          dbg_key, dbg_lb, dbg_ub, dbg_est_off, dbg_n_visited};
+  int err = ORC_OK;
+#pragma omp parallel for schedule(dynamic)
+  for (int64_t qi = 0; qi < nq; ++qi) {
+    int rc = search_rabitq_one(&ix, queries + qi * d, k[qi], nprobe[qi], out_ids + out_off[qi],
+                               out_dists + out_off[qi], out_counts + qi, &dbg, qi);
+    if (rc) {
+#pragma omp critical
+      err = rc;
+    }
+  }
+  return err;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Ground truth: exact float64 k nearest over all rows                       */
 /* ------------------------------------------------------------------------ */
 

@@ -21,7 +21,7 @@ import numpy as np
 
 __all__ = [
     "Workload", "WORKLOADS", "workload", "mixture_centers", "base_vectors",
-    "query_vectors", "kmeans_draws", "pq_draws", "rotation_gaussian",
+    "query_vectors", "kmeans_draws", "pq_draws", "rotation_orthogonal",
     "uneven_k_nprobe", "poisson_arrivals", "small_workload",
 ]
 
@@ -180,9 +180,15 @@ def pq_draws(n: int, m: int, ksub: int, train_size: int, seed: int = 0) -> Tuple
     return train, init
 
 
-def rotation_gaussian(dim: int, seed: int) -> np.ndarray:
-    """Standard normal [dim, dim] float64 matrix; the index build orthogonalises it."""
-    return np.random.default_rng(seed).standard_normal((dim, dim))
+def rotation_orthogonal(dim: int, seed: int) -> np.ndarray:
+    """A random orthogonal [dim, dim] matrix (Haar distributed: QR of a
+    standard normal draw, columns signed by R's diagonal), as float32.  It is
+    the random rotation of the RaBitQ codes, drawn here and passed to the
+    index build and to the oracle alike."""
+    g = np.random.default_rng(seed).standard_normal((dim, dim))
+    qm, rm = np.linalg.qr(g)
+    qm = qm * np.where(np.diag(rm) < 0, -1.0, 1.0)[None, :]
+    return np.ascontiguousarray(qm.astype(np.float32))
 
 
 def uneven_k_nprobe(nq: int, k_range: Tuple[int, int], nprobe_range: Tuple[int, int],
