@@ -81,29 +81,55 @@ int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist,
                             int32_t pq_m, int32_t pq_bits, const float* codebook, const uint8_t* codes,
                             const float* base, bbc_index** out);
 
-/* Build an index on `device` from base [n][d] float32 (row-id order):
- * IVF k-means (kmeans_iters Lloyd rounds on the training rows, then every
- * row assigned to its nearest centroid; empty clusters split the largest
- * one), then residual PQ trained on the PQ rows.  The random draws are
- * inputs: train_rows [n_train] ascending rows, init_pos [nlist] distinct
- * positions in train_rows seeding the centroids, pq_rows [n_pq] ascending
- * rows, pq_init [pq_m][2^pq_bits] distinct positions in pq_rows seeding
- * each sub-space codebook.  Assignment uses canonical float32 squared L2
- * with ties to the smaller id; centroid and codeword means are float64 sums
- * in row order rounded once.  d/pq_m <= 16. */
+/* Build an index on `device` from base [n][d] (row-id order; float32, or
+ * float16 when storage = BBC_STORAGE_FP16): IVF k-means (kmeans_iters Lloyd
+ * rounds on the training rows, then every row assigned to its nearest
+ * centroid; empty clusters split the largest one), then
+ *  - PQ: residual PQ trained on the PQ rows (pq_rows [n_pq] ascending rows,
+ *    pq_init [pq_m][2^pq_bits] distinct positions in pq_rows seeding each
+ *    sub-space codebook; d/pq_m <= 16; L2 only, float32 only);
+ *  - RaBitQ: 1-bit codes of the rotated residuals with their factors
+ *    (rotation [d][d] orthogonal float32, d % 64 == 0), bounds at
+ *    confidence eps0 (0 = the cited method's 1.9); L2 or IP.
+ * The random draws are inputs: train_rows [n_train] ascending rows,
+ * init_pos [nlist] distinct positions in train_rows seeding the centroids.
+ * Assignment uses canonical float32 squared L2 with ties to the smaller id;
+ * centroid and codeword means are float64 sums in row order rounded once. */
+#define BBC_STORAGE_FP32 0
+#define BBC_STORAGE_FP16 1
 typedef struct {
   int32_t nlist;
   int32_t kmeans_iters;
-  int32_t metric;   /* BBC_METRIC_L2 */
-  int32_t quant;    /* BBC_QUANT_PQ */
+  int32_t metric;   /* BBC_METRIC_L2, or BBC_METRIC_IP (RaBitQ) */
+  int32_t quant;    /* BBC_QUANT_PQ or BBC_QUANT_RABITQ */
   int32_t pq_m;
   int32_t pq_bits;  /* 4 or 8 */
   const int64_t* train_rows; int64_t n_train; const int64_t* init_pos;
   const int64_t* pq_rows; int64_t n_pq; const int64_t* pq_init;
+  const float* rotation;  /* RaBitQ: [d][d] */
+  float rabitq_eps0;      /* RaBitQ: 0 = 1.9 */
+  int32_t storage;        /* BBC_STORAGE_FP32 / BBC_STORAGE_FP16 (RaBitQ) */
 } bbc_build_params;
 
-int32_t bbc_build_index(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* params,
+int32_t bbc_build_index(int32_t device, const void* base, int64_t n, int32_t d, const bbc_build_params* params,
                         bbc_index** out);
+
+/* Create a RaBitQ index on `device` from an already built one in host
+ * memory (the cited RaBitQ method: 1-bit codes of randomly rotated
+ * residuals and their factors).
+ *   centroids [nlist][d] float32; list_off, list_ids as for PQ
+ *   rotation  [d][d] float32 orthogonal P; codes encode P^T (x - c_j)
+ *   codes     [n][d/32] uint32, list-slot order: bit i of a code is word
+ *             i/32, bit i%32 (1 when the rotated residual's i-th entry > 0)
+ *   factors   [n][4] float32, list-slot order: (|x - c_j|, f, g, popcount)
+ *   base      [n][d] float32, or float16 when storage = BBC_STORAGE_FP16,
+ *             row-id order (exact distances convert float16 exactly)
+ *   eps0      bound confidence (0 = 1.9)
+ * Requirements: d % 64 == 0, d <= 1024, 1 <= nlist <= 8192, n < 2^31. */
+int32_t bbc_index_create_rabitq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
+                                const float* centroids, const int64_t* list_off, const int64_t* list_ids,
+                                const float* rotation, const uint32_t* codes, const float* factors,
+                                const void* base, int32_t storage, float eps0, bbc_index** out);
 
 typedef struct {
   double ncand_ratio;  /* r >= 1: the collector keeps K_c = min(ceil(r*k), S) candidates */
@@ -148,6 +174,8 @@ typedef struct {
   int32_t* n_sample_lists;                   /* [nq] probed lists in the codebook sample */
   int64_t* n_survivors;                      /* [nq] keys kept by the relaxed-threshold filter */
   int64_t* n_sample_keys;                    /* [nq] keys in the codebook sample lists */
+  float* est_lb; float* est_ub;              /* RaBitQ: [sum S] bounds in the est_keys order */
+  int64_t* n_visited;                        /* RaBitQ: [nq] objects re-ranked */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and
@@ -166,6 +194,9 @@ int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bb
 #define BBC_FIELD_LIST_IDS 2  /* [n] int64 */
 #define BBC_FIELD_CODES 3     /* [n][pq_m] uint8, one code per byte */
 #define BBC_FIELD_CODEBOOK 4  /* [pq_m][2^bits][d/pq_m] float32 */
+#define BBC_FIELD_RABITQ_CODES 5    /* [n][d/32] uint32, list-slot order */
+#define BBC_FIELD_RABITQ_FACTORS 6  /* [n][4] float32 (nr, f, g, popcount), list-slot order */
+#define BBC_FIELD_ROT_CENTROIDS 7   /* [nlist][d] float32: P^T c_j */
 
 /* Sizes of an index: any pointer may be NULL. */
 int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,

@@ -26,6 +26,8 @@ METRIC_L2, METRIC_IP = 0, 1
 QUANT_PQ, QUANT_RABITQ = 0, 1
 COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
 FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
+FIELD_RABITQ_CODES, FIELD_RABITQ_FACTORS, FIELD_ROT_CENTROIDS = 5, 6, 7
+STORAGE_FP32, STORAGE_FP16 = 0, 1
 STAGES = {0: "probe", 1: "sample_scan", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
 
 
@@ -45,14 +47,15 @@ class BuildParams(C.Structure):
     _fields_ = [("nlist", C.c_int32), ("kmeans_iters", C.c_int32), ("metric", C.c_int32), ("quant", C.c_int32),
                 ("pq_m", C.c_int32), ("pq_bits", C.c_int32),
                 ("train_rows", C.c_void_p), ("n_train", C.c_int64), ("init_pos", C.c_void_p),
-                ("pq_rows", C.c_void_p), ("n_pq", C.c_int64), ("pq_init", C.c_void_p)]
+                ("pq_rows", C.c_void_p), ("n_pq", C.c_int64), ("pq_init", C.c_void_p),
+                ("rotation", C.c_void_p), ("rabitq_eps0", C.c_float), ("storage", C.c_int32)]
 
 
 class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
         "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off",
-        "n_sample_lists", "n_survivors", "n_sample_keys")]
+        "n_sample_lists", "n_survivors", "n_sample_keys", "est_lb", "est_ub", "n_visited")]
 
 
 _lib = None
@@ -77,6 +80,9 @@ def load(path: Optional[str] = None):
     vp, i32, i64, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_double
     L.bbc_index_create_pq.restype = i32
     L.bbc_index_create_pq.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, i32, i32, vp, vp, vp, C.POINTER(vp)]
+    L.bbc_index_create_rabitq.restype = i32
+    L.bbc_index_create_rabitq.argtypes = [i32, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, C.c_float,
+                                          C.POINTER(vp)]
     L.bbc_build_index.restype = i32
     L.bbc_build_index.argtypes = [i32, vp, i64, i32, C.POINTER(BuildParams), C.POINTER(vp)]
     L.bbc_search.restype = i32
@@ -169,7 +175,41 @@ class Index:
         tr, ip = _np(train_rows, np.int64), _np(init_pos, np.int64)
         pr, pi = _np(pq_rows, np.int64), _np(pq_init, np.int64)
         p = BuildParams(int(nlist), int(iters), METRIC_L2, QUANT_PQ, int(pq_m), int(pq_bits),
-                        _ptr(tr), tr.shape[0], _ptr(ip), _ptr(pr), pr.shape[0], _ptr(pi))
+                        _ptr(tr), tr.shape[0], _ptr(ip), _ptr(pr), pr.shape[0], _ptr(pi), None, 0.0, STORAGE_FP32)
+        h = C.c_void_p()
+        _check(load().bbc_build_index(device, _ptr(b), b.shape[0], b.shape[1], C.byref(p), C.byref(h)))
+        return cls(h.value, device)
+
+    @classmethod
+    def create_rabitq(cls, centroids, list_off, list_ids, rotation, codes, factors, base, metric=METRIC_L2,
+                      eps0: float = 0.0, device=0):
+        """RaBitQ index from host arrays (codes [n][d/32] uint32 and factors
+        [n][4] in list-slot order; base float32 or float16 in row order)."""
+        cent = _np(centroids, np.float32)
+        lo = _np(list_off, np.int64)
+        li = _np(list_ids, np.int64)
+        P = _np(rotation, np.float32)
+        cd = _np(codes, np.uint32)
+        fac = _np(factors, np.float32)
+        fp16 = np.asarray(base).dtype == np.float16
+        b = _np(base, np.float16 if fp16 else np.float32)
+        nlist, d = cent.shape
+        h = C.c_void_p()
+        _check(load().bbc_index_create_rabitq(device, b.shape[0], d, nlist, int(metric), _ptr(cent), _ptr(lo),
+                                              _ptr(li), _ptr(P), _ptr(cd), _ptr(fac), _ptr(b),
+                                              STORAGE_FP16 if fp16 else STORAGE_FP32, float(eps0), C.byref(h)))
+        return cls(h.value, device)
+
+    @classmethod
+    def build_rabitq(cls, base, nlist, train_rows, init_pos, rotation, metric=METRIC_L2, iters=10,
+                     eps0: float = 0.0, device=0):
+        """Build an IVF-RaBitQ index on the GPU (base float32 or float16)."""
+        fp16 = np.asarray(base).dtype == np.float16
+        b = _np(base, np.float16 if fp16 else np.float32)
+        tr, ip = _np(train_rows, np.int64), _np(init_pos, np.int64)
+        P = _np(rotation, np.float32)
+        p = BuildParams(int(nlist), int(iters), int(metric), QUANT_RABITQ, 0, 0, _ptr(tr), tr.shape[0], _ptr(ip),
+                        None, 0, None, _ptr(P), float(eps0), STORAGE_FP16 if fp16 else STORAGE_FP32)
         h = C.c_void_p()
         _check(load().bbc_build_index(device, _ptr(b), b.shape[0], b.shape[1], C.byref(p), C.byref(h)))
         return cls(h.value, device)
@@ -193,6 +233,9 @@ class Index:
             FIELD_LIST_IDS: ((self.n,), np.int64),
             FIELD_CODES: ((self.n, self.pq_m), np.uint8),
             FIELD_CODEBOOK: ((self.pq_m, 1 << self.pq_bits, self.d // max(self.pq_m, 1)), np.float32),
+            FIELD_RABITQ_CODES: ((self.n, self.d // 32), np.uint32),
+            FIELD_RABITQ_FACTORS: ((self.n, 4), np.float32),
+            FIELD_ROT_CENTROIDS: ((self.nlist, self.d), np.float32),
         }
         shape, dt = shapes[field]
         out = np.empty(shape, dt)
@@ -287,18 +330,27 @@ class Index:
             tau=np.empty(nq, np.int32), s=np.empty(nq, np.int64), bucket_counts=np.empty((nq, m), np.int32),
             n_boundary=np.empty(nq, np.int64), est_off=np.zeros(nq + 1, np.int64),
             cand_off=np.zeros(nq + 1, np.int64))
+        rabitq = self.quant == QUANT_RABITQ
+        if rabitq:
+            r["n_visited"] = np.empty(nq, np.int64)
         tr = SearchTrace(**{f: _ptr(r[f]) for f in (
             "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
-            "bucket_counts", "n_boundary", "est_off", "cand_off")})
+            "bucket_counts", "n_boundary", "est_off", "cand_off") + (("n_visited",) if rabitq else ())})
         _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                    _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
         # second pass for the ragged arrays, now that their sizes are known
         r["est_keys"] = np.empty(int(r["est_off"][-1]), np.float32)
-        r["cand_ids"] = np.empty(int(r["cand_off"][-1]), np.int64)
-        r["cand_exact"] = np.empty(int(r["cand_off"][-1]), np.float32)
         tr.est_keys = _ptr(r["est_keys"])
-        tr.cand_ids = _ptr(r["cand_ids"])
-        tr.cand_exact = _ptr(r["cand_exact"])
+        if rabitq:
+            r["est_lb"] = np.empty(int(r["est_off"][-1]), np.float32)
+            r["est_ub"] = np.empty(int(r["est_off"][-1]), np.float32)
+            tr.est_lb = _ptr(r["est_lb"])
+            tr.est_ub = _ptr(r["est_ub"])
+        else:
+            r["cand_ids"] = np.empty(int(r["cand_off"][-1]), np.int64)
+            r["cand_exact"] = np.empty(int(r["cand_off"][-1]), np.float32)
+            tr.cand_ids = _ptr(r["cand_ids"])
+            tr.cand_exact = _ptr(r["cand_exact"])
         _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                    _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
         return r

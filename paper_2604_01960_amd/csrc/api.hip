@@ -151,6 +151,13 @@ struct bbc_index {
   uint8_t* codes = nullptr;
   float* codebook = nullptr;
   void* vectors = nullptr;  // list-slot order
+  // RaBitQ
+  uint32_t* rq_codes = nullptr;  // [n][rq_words]
+  int32_t rq_words = 0;
+  float* rq_factors = nullptr;   // [n][4]
+  float* rot = nullptr;          // [d][d]
+  float* rot_cent = nullptr;     // [nlist][d]
+  float eps0 = 1.9f;
   // host metadata
   std::vector<int64_t> h_list_off;
   std::vector<int64_t> h_maxS;  // h_maxS[p] = sum of the p largest list sizes
@@ -183,6 +190,7 @@ void index_release(bbc_index* ix) {
   hipFree(ix->cent); hipFree(ix->cent_bf16); hipFree(ix->cent_norm2); hipFree(ix->cent_norm);
   hipFree(ix->list_off); hipFree(ix->list_ids); hipFree(ix->pos_of_id); hipFree(ix->codes);
   hipFree(ix->codebook); hipFree(ix->vectors);
+  hipFree(ix->rq_codes); hipFree(ix->rq_factors); hipFree(ix->rot); hipFree(ix->rot_cent);
   if (ix->arena.base) hipFree(ix->arena.base);
   if (ix->pinned) hipHostFree(ix->pinned);
   if (ix->meta_done) hipEventDestroy(ix->meta_done);
@@ -255,12 +263,14 @@ extern "C" {
 
 const char* bbc_last_error(void) { return g_err.c_str(); }
 
-int32_t bbc_build_index(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
+int32_t bbc_build_index(int32_t device, const void* base, int64_t n, int32_t d, const bbc_build_params* p,
                         bbc_index** out) {
   if (!p) return fail(BBC_EINVAL, "params is NULL");
-  if (p->quant != BBC_QUANT_PQ) return fail(BBC_EUNSUPPORTED, "quantizer not available in this build");
+  if (p->quant == BBC_QUANT_RABITQ) return bbc::build_index_rabitq(device, base, n, d, p, out);
+  if (p->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "unknown quantizer");
   if (p->metric != BBC_METRIC_L2) return fail(BBC_EUNSUPPORTED, "the PQ path supports the L2 metric only");
-  return bbc::build_index_pq(device, base, n, d, p, out);
+  if (p->storage != BBC_STORAGE_FP32) return fail(BBC_EUNSUPPORTED, "the PQ path stores float32 only");
+  return bbc::build_index_pq(device, static_cast<const float*>(base), n, d, p, out);
 }
 
 int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
@@ -328,6 +338,67 @@ int32_t bbc_index_create_pq(int32_t device, int64_t n, int32_t d, int32_t nlist,
   return BBC_OK;
 }
 
+int32_t bbc_index_create_rabitq(int32_t device, int64_t n, int32_t d, int32_t nlist, int32_t metric,
+                                const float* centroids, const int64_t* list_off, const int64_t* list_ids,
+                                const float* rotation, const uint32_t* codes, const float* factors,
+                                const void* base, int32_t storage, float eps0, bbc_index** out) {
+  if (!out) return fail(BBC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!centroids || !list_off || !list_ids || !rotation || !codes || !factors || !base)
+    return fail(BBC_EINVAL, "NULL array");
+  if (n < 1 || n >= (int64_t)1 << 31) return fail(BBC_EINVAL, "n must be in [1, 2^31)");
+  if (d < 64 || d > 1024 || d % 64) return fail(BBC_EINVAL, "RaBitQ needs d a multiple of 64 in [64, 1024]");
+  if (nlist < 1 || nlist > 8192) return fail(BBC_EINVAL, "nlist must be in [1, 8192]");
+  if (metric != BBC_METRIC_L2 && metric != BBC_METRIC_IP) return fail(BBC_EINVAL, "unknown metric");
+  if (storage != BBC_STORAGE_FP32 && storage != BBC_STORAGE_FP16) return fail(BBC_EINVAL, "unknown storage");
+  if (!(eps0 >= 0.0f) || !std::isfinite(eps0)) return fail(BBC_EINVAL, "eps0 must be finite and >= 0");
+  if (list_off[0] != 0 || list_off[nlist] != n) return fail(BBC_EINVAL, "list_off must run from 0 to n");
+  for (int32_t j = 0; j < nlist; ++j)
+    if (list_off[j + 1] < list_off[j]) return fail(BBC_EINVAL, "list_off must be non-decreasing");
+  if (!all_finite(centroids, (int64_t)nlist * d) || !all_finite(rotation, (int64_t)d * d) ||
+      !all_finite(factors, n * 4))
+    return fail(BBC_EINVAL, "non-finite value in the index arrays");
+  if (storage == BBC_STORAGE_FP32 && !all_finite(static_cast<const float*>(base), n * d))
+    return fail(BBC_EINVAL, "non-finite value in base");
+  int32_t rc = set_device(device);
+  if (rc) return rc;
+  bbc_index* ix = new bbc_index();
+  ix->device = device;
+  ix->n = n; ix->d = d; ix->nlist = nlist; ix->metric = metric; ix->quant = BBC_QUANT_RABITQ;
+  ix->fp16 = storage == BBC_STORAGE_FP16;
+  ix->eps0 = eps0 > 0.0f ? eps0 : 1.9f;
+  ix->rq_words = (int32_t)round_up(d / 32, 4);
+  rc = upload_ivf_common(ix, centroids, list_off, list_ids);
+  if (rc) { index_release(ix); return rc; }
+  const int32_t W = d / 32;
+  std::vector<uint32_t> cs((size_t)n * ix->rq_words, 0u);
+  for (int64_t p = 0; p < n; ++p) std::memcpy(cs.data() + (size_t)p * ix->rq_words, codes + p * W, 4 * W);
+  const size_t esz = ix->fp16 ? 2 : 4;
+  std::vector<char> vec((size_t)n * d * esz);
+  for (int64_t p = 0; p < n; ++p)
+    std::memcpy(vec.data() + (size_t)p * d * esz, static_cast<const char*>(base) + list_ids[p] * d * esz, d * esz);
+  auto up = [&]() -> int32_t {
+    HIP_TRY(dalloc(&ix->rq_codes, cs.size()));
+    HIP_TRY(hipMemcpy(ix->rq_codes, cs.data(), 4 * cs.size(), hipMemcpyHostToDevice));
+    HIP_TRY(dalloc(&ix->rq_factors, (size_t)n * 4));
+    HIP_TRY(hipMemcpy(ix->rq_factors, factors, sizeof(float) * n * 4, hipMemcpyHostToDevice));
+    HIP_TRY(dalloc(&ix->rot, (size_t)d * d));
+    HIP_TRY(hipMemcpy(ix->rot, rotation, sizeof(float) * d * d, hipMemcpyHostToDevice));
+    HIP_TRY(dalloc(&ix->rot_cent, (size_t)nlist * d));
+    HIP_TRY(bbc::launch_rotate(ix->cent, nlist, d, ix->rot, ix->rot_cent, 0));
+    char* v = nullptr;
+    HIP_TRY(dalloc(&v, vec.size()));
+    ix->vectors = v;
+    HIP_TRY(hipMemcpy(v, vec.data(), vec.size(), hipMemcpyHostToDevice));
+    HIP_TRY(hipDeviceSynchronize());
+    return BBC_OK;
+  };
+  rc = up();
+  if (rc) { index_release(ix); return rc; }
+  *out = ix;
+  return BBC_OK;
+}
+
 int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,
                        int32_t* quant, int32_t* pq_m, int32_t* pq_bits) {
   if (!ix) return fail(BBC_EINVAL, "index is NULL");
@@ -386,6 +457,29 @@ int32_t bbc_index_get(const bbc_index* ix, int32_t field, void* dst, int64_t byt
       int64_t need = sizeof(float) * (int64_t)ix->M * ix->ksub * (ix->d / ix->M);
       if (bytes != need) return fail(BBC_EINVAL, "wrong size for codebook");
       HIP_TRY(hipMemcpy(dst, ix->codebook, need, hipMemcpyDeviceToHost));
+      return BBC_OK;
+    }
+    case BBC_FIELD_RABITQ_CODES: {
+      if (ix->quant != BBC_QUANT_RABITQ) return fail(BBC_EUNSUPPORTED, "not a RaBitQ index");
+      const int32_t W = ix->d / 32;
+      if (bytes != 4 * n * W) return fail(BBC_EINVAL, "wrong size for RaBitQ codes");
+      std::vector<uint32_t> t((size_t)n * ix->rq_words);
+      HIP_TRY(hipMemcpy(t.data(), ix->rq_codes, 4 * t.size(), hipMemcpyDeviceToHost));
+      uint32_t* o = static_cast<uint32_t*>(dst);
+      for (int64_t p = 0; p < n; ++p) std::memcpy(o + p * W, t.data() + (size_t)p * ix->rq_words, 4 * W);
+      return BBC_OK;
+    }
+    case BBC_FIELD_RABITQ_FACTORS: {
+      if (ix->quant != BBC_QUANT_RABITQ) return fail(BBC_EUNSUPPORTED, "not a RaBitQ index");
+      if (bytes != 16 * n) return fail(BBC_EINVAL, "wrong size for RaBitQ factors");
+      HIP_TRY(hipMemcpy(dst, ix->rq_factors, 16 * n, hipMemcpyDeviceToHost));
+      return BBC_OK;
+    }
+    case BBC_FIELD_ROT_CENTROIDS: {
+      if (ix->quant != BBC_QUANT_RABITQ) return fail(BBC_EUNSUPPORTED, "not a RaBitQ index");
+      const int64_t need = sizeof(float) * (int64_t)ix->nlist * ix->d;
+      if (bytes != need) return fail(BBC_EINVAL, "wrong size for rotated centroids");
+      HIP_TRY(hipMemcpy(dst, ix->rot_cent, need, hipMemcpyDeviceToHost));
       return BBC_OK;
     }
     default:
@@ -465,6 +559,178 @@ int64_t kc_cap_of(const bbc_index* ix, int32_t k, int32_t np, double r) {
   return std::min(t, ix->h_maxS[np]);
 }
 
+// RaBitQ: probe, rotation of the queries, per-(query, list) bounds, bounded
+// re-rank per query, final sort.  Per-query slot arrays are sized by the
+// largest lists (maxS(nprobe)).
+int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                          const bbc_search_params* p, const int64_t* out_off, int64_t* out_ids, float* out_dists,
+                          int32_t* out_counts, bbc_search_trace* tr) {
+  int32_t rc = BBC_OK;
+  hipStream_t s = static_cast<hipStream_t>(p->stream);
+  const bool host_io = p->device_io == 0;
+  const int d = ix->d;
+  const bool tracing = tr != nullptr;
+  std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0);
+  int64_t max_cap = 0, max_cnt = 1;
+  for (int64_t i = 0; i < nq; ++i) {
+    probe_off[i + 1] = probe_off[i] + nprobe[i];
+    const int64_t cap = ix->h_maxS[nprobe[i]];
+    key_off[i + 1] = key_off[i] + cap;
+    max_cap = std::max(max_cap, cap);
+    max_cnt = std::max(max_cnt, std::min<int64_t>(k[i], cap));
+  }
+  const int64_t npairs = probe_off[nq], nkeys = key_off[nq], nout = out_off[nq];
+  Plan mp;
+  const size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)),
+               m_ko = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1));
+  Plan pl;
+  const size_t L_meta = pl.add(mp.total);
+  const size_t L_q = host_io ? pl.add(sizeof(float) * nq * d) : 0;
+  const size_t L_dprime = pl.add(sizeof(float) * nq * ix->nlist);
+  const size_t L_pl = pl.add(4 * npairs), L_pk = pl.add(4 * npairs), L_ro = pl.add(8 * npairs);
+  const size_t L_ns = pl.add(8 * nq), L_nr = pl.add(4 * nq);
+  const size_t L_qrot = pl.add(sizeof(float) * nq * d);
+  const size_t L_lb = pl.add(4 * nkeys), L_ub = pl.add(4 * nkeys);
+  const size_t L_key = tracing ? pl.add(4 * nkeys) : 0;
+  const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys);
+  const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
+  size_t L_oid = 0, L_od = 0, L_oc = 0;
+  if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
+  HIP_TRY(ix->arena.reserve(pl.total));
+  char* A = ix->arena.base;
+  if (ix->pinned_cap < mp.total) {
+    HIP_TRY(hipEventSynchronize(ix->meta_done));
+    if (ix->pinned) hipHostFree(ix->pinned);
+    ix->pinned = nullptr;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ix->pinned), mp.total * 2));
+    ix->pinned_cap = mp.total * 2;
+  } else {
+    HIP_TRY(hipEventSynchronize(ix->meta_done));
+  }
+  char* H = ix->pinned;
+  std::memcpy(H + m_k, k, 4 * nq);
+  std::memcpy(H + m_np, nprobe, 4 * nq);
+  std::memcpy(H + m_po, probe_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_ko, key_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
+  char* M = A + L_meta;
+  HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipEventRecord(ix->meta_done, s));
+  const float* dq = queries;
+  if (host_io) {
+    HIP_TRY(hipMemcpyAsync(A + L_q, queries, sizeof(float) * nq * d, hipMemcpyHostToDevice, s));
+    dq = reinterpret_cast<const float*>(A + L_q);
+  }
+  const int32_t* d_k = reinterpret_cast<const int32_t*>(M + m_k);
+  const int32_t* d_np = reinterpret_cast<const int32_t*>(M + m_np);
+  const int64_t* d_po = reinterpret_cast<const int64_t*>(M + m_po);
+  const int64_t* d_ko = reinterpret_cast<const int64_t*>(M + m_ko);
+  const int64_t* d_oo = reinterpret_cast<const int64_t*>(M + m_oo);
+  int64_t* d_oid = host_io ? reinterpret_cast<int64_t*>(A + L_oid) : out_ids;
+  float* d_odist = host_io ? reinterpret_cast<float*>(A + L_od) : out_dists;
+  int32_t* d_ocnt = host_io ? reinterpret_cast<int32_t*>(A + L_oc) : out_counts;
+
+  bbc::ProbeArgs pa{};
+  pa.q = dq; pa.nq = nq; pa.d = d; pa.cent = ix->cent; pa.cent_bf16 = ix->cent_bf16; pa.dpad = ix->dpad;
+  pa.cent_norm2 = ix->cent_norm2; pa.cent_norm = ix->cent_norm; pa.nlist = ix->nlist; pa.metric = ix->metric;
+  pa.nprobe = d_np; pa.probe_off = d_po; pa.list_off = ix->list_off;
+  pa.dprime = reinterpret_cast<float*>(A + L_dprime);
+  pa.probe_lists = reinterpret_cast<int32_t*>(A + L_pl);
+  pa.probe_keys = reinterpret_cast<float*>(A + L_pk);
+  pa.rank_off = reinterpret_cast<int64_t*>(A + L_ro);
+  pa.n_scanned = reinterpret_cast<int64_t*>(A + L_ns);
+  pa.n_recheck = reinterpret_cast<int32_t*>(A + L_nr);
+  pa.nsample_q = nullptr;
+  {
+    StageScope st(s, 0);
+    HIP_TRY(bbc::launch_probe(pa, s));
+  }
+  float* qrot = reinterpret_cast<float*>(A + L_qrot);
+  {
+    StageScope st(s, 1);
+    HIP_TRY(bbc::launch_rotate(dq, nq, d, ix->rot, qrot, s));
+  }
+  bbc::RabitqScanArgs sa{};
+  sa.npairs = npairs; sa.nq = nq; sa.probe_off = d_po; sa.probe_lists = pa.probe_lists; sa.probe_keys = pa.probe_keys;
+  sa.rank_off = pa.rank_off; sa.key_off = d_ko; sa.q = dq; sa.qrot = qrot; sa.rot_cent = ix->rot_cent;
+  sa.D = d; sa.metric = ix->metric; sa.eps0 = ix->eps0; sa.list_off = ix->list_off; sa.codes = ix->rq_codes;
+  sa.code_words = ix->rq_words; sa.factors = ix->rq_factors;
+  sa.lb = reinterpret_cast<float*>(A + L_lb);
+  sa.ub = reinterpret_cast<float*>(A + L_ub);
+  sa.key = tracing ? reinterpret_cast<float*>(A + L_key) : nullptr;
+  {
+    StageScope st(s, 2);
+    HIP_TRY(bbc::launch_rabitq_scan(sa, s));
+  }
+  bbc::RabitqWalkArgs wa{};
+  wa.nq = nq; wa.n_scanned = pa.n_scanned; wa.k = d_k; wa.nprobe = d_np; wa.probe_off = d_po;
+  wa.rank_off = pa.rank_off; wa.probe_lists = pa.probe_lists; wa.list_off = ix->list_off; wa.list_ids = ix->list_ids;
+  wa.pos_of_id = ix->pos_of_id; wa.lb = sa.lb; wa.ub = sa.ub; wa.key_off = d_ko;
+  wa.cbuf = reinterpret_cast<uint32_t*>(A + L_cbuf);
+  wa.cand_off = d_ko; wa.cand_packed = reinterpret_cast<uint64_t*>(A + L_cp);
+  wa.n_cand = reinterpret_cast<int64_t*>(A + L_nc);
+  wa.n_visited = reinterpret_cast<int64_t*>(A + L_nv);
+  wa.q = dq; wa.vectors = ix->vectors; wa.fp16 = ix->fp16; wa.D = d; wa.metric = ix->metric;
+  {
+    StageScope st(s, 4);
+    HIP_TRY(bbc::launch_rabitq_walk(wa, s));
+  }
+  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
+  const int cap = (int)std::min(max_cnt, cap_max);
+  int run = 1;
+  while (2 * run <= cap) run *= 2;
+  bbc::FinalArgs fa{};
+  fa.nq = nq; fa.k = d_k; fa.n_cand = wa.n_cand; fa.cand_off = d_ko; fa.cand_packed = wa.cand_packed;
+  fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
+  fa.cap = cap;
+  fa.run = run;
+  fa.max_kc = max_cap;
+  {
+    StageScope st(s, 5);
+    HIP_TRY(bbc::launch_final_topk(fa, s));
+  }
+  if (host_io) {
+    HIP_TRY(hipMemcpyAsync(out_ids, d_oid, 8 * nout, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out_dists, d_odist, 4 * nout, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(out_counts, d_ocnt, 4 * nq, hipMemcpyDeviceToHost, s));
+  }
+  if (tracing) {
+    auto cp = [&](void* dst, size_t off, size_t bytes) -> int32_t {
+      if (dst) HIP_TRY(hipMemcpyAsync(dst, A + off, bytes, hipMemcpyDeviceToHost, s));
+      return BBC_OK;
+    };
+    if ((rc = cp(tr->probe_lists, L_pl, 4 * npairs))) return rc;
+    if ((rc = cp(tr->probe_keys, L_pk, 4 * npairs))) return rc;
+    if ((rc = cp(tr->n_recheck, L_nr, 4 * nq))) return rc;
+    if ((rc = cp(tr->n_cand, L_nc, 8 * nq))) return rc;
+    if ((rc = cp(tr->n_visited, L_nv, 8 * nq))) return rc;
+    std::vector<int64_t> nsc(nq);
+    HIP_TRY(hipMemcpyAsync(nsc.data(), A + L_ns, 8 * nq, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (tr->n_scanned) std::memcpy(tr->n_scanned, nsc.data(), 8 * nq);
+    if (tr->est_off) {
+      tr->est_off[0] = 0;
+      for (int64_t i = 0; i < nq; ++i) tr->est_off[i + 1] = tr->est_off[i] + nsc[i];
+    }
+    auto ragged = [&](float* dst, size_t off) -> int32_t {
+      if (!dst) return BBC_OK;
+      std::vector<float> all(nkeys);
+      HIP_TRY(hipMemcpy(all.data(), A + off, 4 * nkeys, hipMemcpyDeviceToHost));
+      int64_t w = 0;
+      for (int64_t i = 0; i < nq; ++i) {
+        std::memcpy(dst + w, all.data() + key_off[i], 4 * nsc[i]);
+        w += nsc[i];
+      }
+      return BBC_OK;
+    };
+    if ((rc = ragged(tr->est_keys, L_key))) return rc;
+    if ((rc = ragged(tr->est_lb, L_lb))) return rc;
+    if ((rc = ragged(tr->est_ub, L_ub))) return rc;
+  }
+  if (host_io) HIP_TRY(hipStreamSynchronize(s));
+  return BBC_OK;
+}
+
 int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
                    const bbc_search_params* p, const int64_t* out_off, int64_t* out_ids, float* out_dists,
                    int32_t* out_counts, bbc_search_trace* tr) {
@@ -473,6 +739,8 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   rc = set_device(ix->device);
   if (rc) return rc;
   std::lock_guard<std::mutex> guard(ix->mu);
+  if (ix->quant == BBC_QUANT_RABITQ)
+    return run_search_rabitq(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, tr);
   hipStream_t s = static_cast<hipStream_t>(p->stream);
   const bool host_io = p->device_io == 0;
   const int m = p->buckets ? p->buckets : 256;

@@ -16,6 +16,7 @@
 //    the sequential sub-vector distance, empty codewords keep their value;
 //    codes = nearest codeword, ties to the smaller index.
 #include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
 
 #include <algorithm>
 #include <cmath>
@@ -205,6 +206,44 @@ void kmeans_update(const float* x, const int64_t* rows, int64_t n, int32_t d, co
   }
 }
 
+// IVF lists: k-means on the training rows, every row assigned to its nearest
+// centroid, lists in ascending row order.  dx: the base rows on the device.
+int32_t build_ivf_lists(const float* base, const float* dx, int64_t n, int32_t d, const bbc_build_params* p,
+                        std::vector<float>& cent, std::vector<int32_t>& a_all, std::vector<int64_t>& list_off,
+                        std::vector<int64_t>& list_ids) {
+  const int32_t nlist = p->nlist, iters = p->kmeans_iters;
+  const int64_t ntr = p->n_train;
+  Assigner as;
+  int32_t rc = as.init(d, nlist, std::min<int64_t>(std::max<int64_t>(ntr, 1), 65536));
+  if (rc) return rc;
+  cent.assign((size_t)nlist * d, 0.0f);
+  for (int32_t j = 0; j < nlist; ++j)
+    std::memcpy(cent.data() + (size_t)j * d, base + p->train_rows[p->init_pos[j]] * d, sizeof(float) * d);
+  DevBuf<float> dtrain;
+  DevBuf<int64_t> drows;
+  BTRY(dtrain.alloc((size_t)ntr * d));
+  BTRY(drows.alloc(ntr));
+  BTRY(hipMemcpy(drows.p, p->train_rows, 8 * ntr, hipMemcpyHostToDevice));
+  hipLaunchKernelGGL(bbc::gather_rows_kernel, dim3(1024), dim3(256), 0, 0, dx, drows.p, ntr, d, dtrain.p);
+  BTRY(hipGetLastError());
+  std::vector<int32_t> a_tr(ntr);
+  for (int32_t it = 0; it < iters; ++it) {
+    if ((rc = as.set_centroids(cent))) return rc;
+    if ((rc = as.assign(dtrain.p, ntr, a_tr.data()))) return rc;
+    kmeans_update(base, p->train_rows, ntr, d, a_tr.data(), nlist, cent);
+  }
+  if ((rc = as.set_centroids(cent))) return rc;
+  a_all.assign(n, 0);
+  if ((rc = as.assign(dx, n, a_all.data()))) return rc;
+  list_off.assign(nlist + 1, 0);
+  list_ids.assign(n, 0);
+  for (int64_t i = 0; i < n; ++i) list_off[a_all[i] + 1] += 1;
+  for (int32_t j = 0; j < nlist; ++j) list_off[j + 1] += list_off[j];
+  std::vector<int64_t> fill(list_off.begin(), list_off.end() - 1);
+  for (int64_t i = 0; i < n; ++i) list_ids[fill[a_all[i]]++] = i;  // ascending rows within a list
+  return BBC_OK;
+}
+
 }  // namespace
 
 int32_t bbc::build_index_pq(int32_t device, const float* base, int64_t n, int32_t d,
@@ -243,39 +282,11 @@ int32_t bbc::build_index_pq(int32_t device, const float* base, int64_t n, int32_
   DevBuf<float> dx;
   BTRY(dx.alloc((size_t)n * d));
   BTRY(hipMemcpy(dx.p, base, sizeof(float) * n * d, hipMemcpyHostToDevice));
-
-  // ---- k-means on the training rows ---------------------------------------
-  const int64_t ntr = p->n_train;
-  Assigner as;
-  int32_t rc = as.init(d, nlist, std::min<int64_t>(std::max<int64_t>(ntr, 1), 65536));
+  std::vector<float> cent;
+  std::vector<int32_t> a_all;
+  std::vector<int64_t> list_off, list_ids;
+  int32_t rc = build_ivf_lists(base, dx.p, n, d, p, cent, a_all, list_off, list_ids);
   if (rc) return rc;
-  std::vector<float> cent((size_t)nlist * d);
-  for (int32_t j = 0; j < nlist; ++j)
-    std::memcpy(cent.data() + (size_t)j * d, base + p->train_rows[p->init_pos[j]] * d, sizeof(float) * d);
-  DevBuf<float> dtrain;
-  DevBuf<int64_t> drows;
-  BTRY(dtrain.alloc((size_t)ntr * d));
-  BTRY(drows.alloc(ntr));
-  BTRY(hipMemcpy(drows.p, p->train_rows, 8 * ntr, hipMemcpyHostToDevice));
-  hipLaunchKernelGGL(bbc::gather_rows_kernel, dim3(1024), dim3(256), 0, 0, dx.p, drows.p, ntr, d, dtrain.p);
-  BTRY(hipGetLastError());
-  std::vector<int32_t> a_tr(ntr);
-  for (int32_t it = 0; it < iters; ++it) {
-    if ((rc = as.set_centroids(cent))) return rc;
-    if ((rc = as.assign(dtrain.p, ntr, a_tr.data()))) return rc;
-    kmeans_update(base, p->train_rows, ntr, d, a_tr.data(), nlist, cent);
-  }
-  // ---- assignment of every row and list layout ------------------------------
-  if ((rc = as.set_centroids(cent))) return rc;
-  std::vector<int32_t> a_all(n);
-  if ((rc = as.assign(dx.p, n, a_all.data()))) return rc;
-  std::vector<int64_t> list_off(nlist + 1, 0), list_ids(n);
-  for (int64_t i = 0; i < n; ++i) list_off[a_all[i] + 1] += 1;
-  for (int32_t j = 0; j < nlist; ++j) list_off[j + 1] += list_off[j];
-  {
-    std::vector<int64_t> fill(list_off.begin(), list_off.end() - 1);
-    for (int64_t i = 0; i < n; ++i) list_ids[fill[a_all[i]]++] = i;  // ascending rows within a list
-  }
   // ---- PQ training on residuals of the PQ rows -------------------------------
   const int32_t dsub = d / M;
   DevBuf<float> dcent, dcb;
@@ -336,4 +347,82 @@ int32_t bbc::build_index_pq(int32_t device, const float* base, int64_t n, int32_
                            bits, cb.data(), codes.data(), base, out);
   if (rc) return rc;
   return BBC_OK;
+}
+
+// IVF lists, then the RaBitQ codes of every row in list order, encoded on the
+// device in chunks of rows (residual, rotation, code bits and factors).
+int32_t bbc::build_index_rabitq(int32_t device, const void* base_v, int64_t n, int32_t d,
+                                const bbc_build_params* p, bbc_index** out) {
+  if (!out || !base_v || !p) return bfail(BBC_EINVAL, "NULL argument");
+  *out = nullptr;
+  const int32_t nlist = p->nlist;
+  if (n < 1 || n >= (int64_t)1 << 31) return bfail(BBC_EINVAL, "n must be in [1, 2^31)");
+  if (d < 64 || d > 1024 || d % 64) return bfail(BBC_EINVAL, "RaBitQ needs d a multiple of 64 in [64, 1024]");
+  if (nlist < 1 || nlist > 8192) return bfail(BBC_EINVAL, "nlist must be in [1, 8192]");
+  if (p->kmeans_iters < 0) return bfail(BBC_EINVAL, "kmeans_iters < 0");
+  if (p->metric != BBC_METRIC_L2 && p->metric != BBC_METRIC_IP) return bfail(BBC_EINVAL, "unknown metric");
+  if (p->storage != BBC_STORAGE_FP32 && p->storage != BBC_STORAGE_FP16) return bfail(BBC_EINVAL, "unknown storage");
+  if (!p->rotation) return bfail(BBC_EINVAL, "RaBitQ needs a rotation");
+  if (!p->train_rows || p->n_train < nlist || !p->init_pos) return bfail(BBC_EINVAL, "bad k-means training draws");
+  for (int64_t i = 0; i < p->n_train; ++i)
+    if (p->train_rows[i] < 0 || p->train_rows[i] >= n || (i && p->train_rows[i] <= p->train_rows[i - 1]))
+      return bfail(BBC_EINVAL, "train_rows must be ascending rows of base");
+  for (int32_t j = 0; j < nlist; ++j)
+    if (p->init_pos[j] < 0 || p->init_pos[j] >= p->n_train) return bfail(BBC_EINVAL, "init_pos out of range");
+  // float32 rows for the build (float16 converts exactly)
+  std::vector<float> base32;
+  const float* base = static_cast<const float*>(base_v);
+  if (p->storage == BBC_STORAGE_FP16) {
+    base32.resize((size_t)n * d);
+    const __half* h = static_cast<const __half*>(base_v);
+    for (int64_t i = 0; i < n * d; ++i) base32[i] = __half2float(h[i]);
+    base = base32.data();
+  }
+  for (int64_t i = 0; i < n * d; ++i)
+    if (!std::isfinite(base[i])) return bfail(BBC_EINVAL, "non-finite value in base");
+  {
+    int cnt = 0;
+    BTRY(hipGetDeviceCount(&cnt));
+    if (device < 0 || device >= cnt) return bfail(BBC_EINVAL, "device index out of range");
+    BTRY(hipSetDevice(device));
+  }
+  DevBuf<float> dx;
+  BTRY(dx.alloc((size_t)n * d));
+  BTRY(hipMemcpy(dx.p, base, sizeof(float) * n * d, hipMemcpyHostToDevice));
+  std::vector<float> cent;
+  std::vector<int32_t> a_all;
+  std::vector<int64_t> list_off, list_ids;
+  int32_t rc = build_ivf_lists(base, dx.p, n, d, p, cent, a_all, list_off, list_ids);
+  if (rc) return rc;
+  const int32_t cw = (int32_t)(((d / 32) + 3) / 4 * 4);
+  DevBuf<float> dcent, dP, dfac, dres, drot;
+  DevBuf<int64_t> dids, doff;
+  DevBuf<uint32_t> dcodes;
+  BTRY(dcent.alloc((size_t)nlist * d));
+  BTRY(dP.alloc((size_t)d * d));
+  BTRY(dids.alloc(n));
+  BTRY(doff.alloc(nlist + 1));
+  BTRY(dcodes.alloc((size_t)n * cw));
+  BTRY(dfac.alloc((size_t)n * 4));
+  BTRY(hipMemcpy(dcent.p, cent.data(), 4 * cent.size(), hipMemcpyHostToDevice));
+  BTRY(hipMemcpy(dP.p, p->rotation, sizeof(float) * d * d, hipMemcpyHostToDevice));
+  BTRY(hipMemcpy(dids.p, list_ids.data(), 8 * n, hipMemcpyHostToDevice));
+  BTRY(hipMemcpy(doff.p, list_off.data(), 8 * (nlist + 1), hipMemcpyHostToDevice));
+  const int64_t chunk = std::min<int64_t>(n, 1 << 18);
+  BTRY(dres.alloc((size_t)chunk * d));
+  BTRY(drot.alloc((size_t)chunk * d));
+  bbc::RabitqBuildArgs ba{};
+  ba.x = dx.p; ba.list_ids = dids.p; ba.list_off = doff.p; ba.nlist = nlist; ba.cent = dcent.p; ba.P = dP.p;
+  ba.D = d; ba.codes = dcodes.p; ba.code_words = cw; ba.factors = dfac.p;
+  for (int64_t p0 = 0; p0 < n; p0 += chunk)
+    BTRY(bbc::launch_rabitq_encode(ba, p0, std::min(chunk, n - p0), dres.p, drot.p, 0));
+  BTRY(hipDeviceSynchronize());
+  std::vector<uint32_t> codes_s((size_t)n * cw), codes((size_t)n * (d / 32));
+  std::vector<float> fac((size_t)n * 4);
+  BTRY(hipMemcpy(codes_s.data(), dcodes.p, 4 * codes_s.size(), hipMemcpyDeviceToHost));
+  BTRY(hipMemcpy(fac.data(), dfac.p, 4 * fac.size(), hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i)
+    std::memcpy(codes.data() + (size_t)i * (d / 32), codes_s.data() + (size_t)i * cw, 4 * (d / 32));
+  return bbc_index_create_rabitq(device, n, d, nlist, p->metric, cent.data(), list_off.data(), list_ids.data(),
+                                 p->rotation, codes.data(), fac.data(), base_v, p->storage, p->rabitq_eps0, out);
 }

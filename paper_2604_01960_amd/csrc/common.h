@@ -262,6 +262,94 @@ __device__ __forceinline__ uint32_t wave_slot(bool take, uint32_t* counter) {
   return base + (uint32_t)__popcll(mask & ((1ull << lane) - 1ull));
 }
 
+// ---- slot -> list position of a query's scanned objects -----------------------
+// Scanned objects are numbered by slot in probe order (rank r's list fills
+// slots rank_off[r] ..); pos(slot) is the object's position in list-slot
+// order, through LDS copies of the rank offsets and list starts when they fit.
+struct SlotMap {
+  const int64_t* rank_off;  // [np] slot offset of each probe rank
+  const int32_t* lists;     // [np] list of each probe rank
+  const int64_t* list_off;
+  int np;
+  const int32_t* s_rbeg;  // LDS copies (lds = true)
+  const int32_t* s_lbeg;
+  bool lds;
+  __device__ int64_t pos(int64_t slot) const {
+    int lo = 0, hi = np - 1;
+    if (lds) {
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rbeg[mid] <= slot) lo = mid; else hi = mid - 1;
+      }
+      return (int64_t)s_lbeg[lo] + (slot - s_rbeg[lo]);
+    }
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (rank_off[mid] <= slot) lo = mid; else hi = mid - 1;
+    }
+    return list_off[lists[lo]] + (slot - rank_off[lo]);
+  }
+};
+
+// Block-wide: fills the LDS tables (when np <= CAP and slots fit 31 bits)
+// and returns the map; ends with a barrier.
+template <int NT, int CAP>
+__device__ SlotMap slot_map_load(const int64_t* rank_off, const int32_t* lists, const int64_t* list_off, int np,
+                                 int32_t* s_rbeg, int32_t* s_lbeg) {
+  SlotMap sm;
+  sm.rank_off = rank_off;
+  sm.lists = lists;
+  sm.list_off = list_off;
+  sm.np = np;
+  // (list positions fit 31 bits: indexes hold fewer than 2^31 objects)
+  sm.lds = np <= CAP && rank_off[np - 1] < 0x7fffffff;
+  sm.s_rbeg = s_rbeg;
+  sm.s_lbeg = s_lbeg;
+  if (sm.lds)
+    for (int r = threadIdx.x; r < np; r += NT) {
+      s_rbeg[r] = (int32_t)rank_off[r];
+      s_lbeg[r] = (int32_t)list_off[lists[r]];
+    }
+  __syncthreads();
+  return sm;
+}
+
+// ---- wave-level 64-ary max-heap in global memory ------------------------------
+// heap storage in global memory, read past the L1 so that every lane of the
+// wave sees the stores of the others
+__device__ __forceinline__ uint64_t hload(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void hstore(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// One wave: sift v down from node i of the 64-ary max-heap h[0, n).
+__device__ void heap_sift_down(uint64_t* h, int64_t n, int64_t i, uint64_t v) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const int64_t c0 = 64 * i + 1;
+    if (c0 >= n) break;
+    const int64_t cj = c0 + lane;
+    const bool ok = cj < n;
+    const uint64_t cv = ok ? hload(h + cj) : 0ull;
+    uint64_t mx = cv;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t o = __shfl_xor(mx, off);
+      mx = o > mx ? o : mx;
+    }
+    if (mx <= v) break;
+    const uint64_t at = __ballot(ok && cv == mx);
+    const int j = __ffsll((unsigned long long)at) - 1;
+    if (lane == 0) hstore(h + i, mx);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    i = c0 + j;
+  }
+  if (lane == 0) hstore(h + i, v);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+
 __host__ __device__ __forceinline__ int next_pow2(int x) {
   int p = 1;
   while (p < x) p <<= 1;

@@ -21,51 +21,10 @@ namespace {
 constexpr int CMP_RANKCAP = 2048;      // probe ranks held in LDS (sort collector)
 constexpr int CMP_RANKCAP_HEAP = 256;  // (heap collector: small blocks, many per CU)
 
-// slot -> list slot (position) of the probed object, through LDS copies of
-// the query's rank offsets and list starts when they fit
-struct SlotMap {
-  const int64_t* rank_off;  // [np] slot offset of each probe rank
-  const int32_t* lists;     // [np] list of each probe rank
-  const int64_t* list_off;
-  int np;
-  const int32_t* s_rbeg;  // LDS copies (lds = true)
-  const int32_t* s_lbeg;
-  bool lds;
-  __device__ int64_t pos(int64_t slot) const {
-    int lo = 0, hi = np - 1;
-    if (lds) {
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_rbeg[mid] <= slot) lo = mid; else hi = mid - 1;
-      }
-      return (int64_t)s_lbeg[lo] + (slot - s_rbeg[lo]);
-    }
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (rank_off[mid] <= slot) lo = mid; else hi = mid - 1;
-    }
-    return list_off[lists[lo]] + (slot - rank_off[lo]);
-  }
-};
-
 template <int NT, int CAP>
 __device__ SlotMap load_slot_map(const CompareArgs& a, int64_t qi, int32_t* s_rbeg, int32_t* s_lbeg) {
-  SlotMap sm;
   const int64_t po = a.probe_off[qi];
-  sm.rank_off = a.rank_off + po;
-  sm.lists = a.probe_lists + po;
-  sm.list_off = a.list_off;
-  sm.np = a.nprobe[qi];
-  sm.lds = sm.np <= CAP && a.rank_off[po + sm.np - 1] < 0x7fffffff;
-  sm.s_rbeg = s_rbeg;
-  sm.s_lbeg = s_lbeg;
-  if (sm.lds)
-    for (int r = threadIdx.x; r < sm.np; r += NT) {
-      s_rbeg[r] = (int32_t)sm.rank_off[r];
-      s_lbeg[r] = (int32_t)sm.list_off[sm.lists[r]];
-    }
-  __syncthreads();
-  return sm;
+  return slot_map_load<NT, CAP>(a.rank_off + po, a.probe_lists + po, a.list_off, a.nprobe[qi], s_rbeg, s_lbeg);
 }
 
 }  // namespace
@@ -132,44 +91,6 @@ __global__ __launch_bounds__(1024) void sort_collect_kernel(CompareArgs a) {
     if (take) cand[nless + slot] = (uint32_t)p;
   }
 }
-
-namespace {
-
-// heap storage in global memory, read past the L1 so that every lane of the
-// wave sees the stores of the others
-__device__ __forceinline__ uint64_t hload(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void hstore(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// One wave: sift v down from node i of the 64-ary max-heap h[0, n).
-__device__ void heap_sift_down(uint64_t* h, int64_t n, int64_t i, uint64_t v) {
-  const int lane = threadIdx.x & 63;
-  while (true) {
-    const int64_t c0 = 64 * i + 1;
-    if (c0 >= n) break;
-    const int64_t cj = c0 + lane;
-    const bool ok = cj < n;
-    const uint64_t cv = ok ? hload(h + cj) : 0ull;
-    uint64_t mx = cv;
-    for (int off = 32; off >= 1; off >>= 1) {
-      const uint64_t o = __shfl_xor(mx, off);
-      mx = o > mx ? o : mx;
-    }
-    if (mx <= v) break;
-    const uint64_t at = __ballot(ok && cv == mx);
-    const int j = __ffsll((unsigned long long)at) - 1;
-    if (lane == 0) hstore(h + i, mx);
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-    i = c0 + j;
-  }
-  if (lane == 0) hstore(h + i, v);
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-}
-
-}  // namespace
 
 __global__ __launch_bounds__(64) void heap_collect_kernel(CompareArgs a) {
   constexpr int NT = 64;

@@ -15,6 +15,8 @@ int32_t set_error(int32_t code, const std::string& msg);
 
 int32_t build_index_pq(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
                        bbc_index** out);
+int32_t build_index_rabitq(int32_t device, const void* base, int64_t n, int32_t d, const bbc_build_params* p,
+                           bbc_index** out);
 
 struct ProbeArgs {
   const float* q; int64_t nq; int d;
@@ -111,6 +113,46 @@ struct CompareArgs {
 };
 // collector: 1 heap, 2 sort
 hipError_t launch_compare_collect(const CompareArgs& a, int collector, hipStream_t s);
+
+// ---- RaBitQ -------------------------------------------------------------------
+// y[r][i] = sum over e of P[e][i] * v[r][e], sequential in e (P: [D][D])
+hipError_t launch_rotate(const float* v, int64_t n, int D, const float* P, float* y, hipStream_t s);
+
+struct RabitqBuildArgs {
+  const float* x;           // [n][D] base rows, original order, fp32
+  const int64_t* list_ids;  // [n] original row of each list slot
+  const int64_t* list_off; int nlist;
+  const float* cent;        // [nlist][D]
+  const float* P;           // [D][D]
+  int D;
+  uint32_t* codes; int code_words;  // [n][code_words], list order (code_words = D/32 rounded up to 4)
+  float* factors;           // [n][4] (nr, f, g, popcount)
+};
+// codes and factors of slots [p0, p0 + n); resid and rot are [n][D] scratch
+hipError_t launch_rabitq_encode(const RabitqBuildArgs& a, int64_t p0, int64_t n, float* resid, float* rot,
+                                hipStream_t s);
+
+struct RabitqScanArgs {
+  int64_t npairs; int64_t nq; const int64_t* probe_off; const int32_t* probe_lists; const float* probe_keys;
+  const int64_t* rank_off; const int64_t* key_off;
+  const float* q; const float* qrot; const float* rot_cent;  // queries, P^T q [nq][D], P^T c [nlist][D]
+  int D; int metric; float eps0;
+  const int64_t* list_off; const uint32_t* codes; int code_words; const float* factors;
+  float* lb; float* ub; float* key;  // [sum S] by slot at key_off[q]; key optional
+};
+hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s);
+
+struct RabitqWalkArgs {
+  int64_t nq; const int64_t* n_scanned; const int32_t* k; const int32_t* nprobe; const int64_t* probe_off;
+  const int64_t* rank_off; const int32_t* probe_lists; const int64_t* list_off; const int32_t* list_ids;
+  const int32_t* pos_of_id;
+  const float* lb; const float* ub; const int64_t* key_off;
+  uint32_t* cbuf;            // [sum S] scratch (slots grouped by lb bin)
+  const int64_t* cand_off; uint64_t* cand_packed;  // [sum S] processed (exact key, id)
+  int64_t* n_cand; int64_t* n_visited;
+  const float* q; const void* vectors; int fp16; int D; int metric;
+};
+hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s);
 
 constexpr int FINAL_STATIC_LDS = 21000;  // bytes of static LDS of the final top-k kernel (upper bound)
 hipError_t launch_final_topk(const FinalArgs& a, hipStream_t s);

@@ -1,0 +1,567 @@
+// RaBitQ query path: the bounded quantizer the paper integrates with (the
+// cited RaBitQ method; background, Observation 1, Algorithms 2 and 3).
+//
+//  rotate_kernel        y = P^T v for a batch of rows; y_i = sum over e of
+//                       P[e][i] * v[e], product then add, e ascending from +0
+//                       (a SIMT GEMM whose threads each own output elements)
+//  rabitq_encode_kernel 1-bit codes and factors (nr, f, g, popcount) of the
+//                       rotated residuals (index build)
+//  rabitq_scan_kernel   per (query, probed list): the 4-bit quantized query
+//                       side as four bit planes in LDS, then per object
+//                       ip = sum_b 2^b popcount(code & plane_b) and the
+//                       estimated key with its lower / upper bound
+//  rabitq_walk_kernel   per query, the bounded re-rank: objects in ascending
+//                       (lb, id) with R = the best k by exact (key, id), stop
+//                       before an object whose lb exceeds R's k-th exact key.
+//                       Run over lb bins (whole bins re-ranked, in order), as
+//                       the paper's Algorithm 3 re-ranks buckets; verified,
+//                       with an item-by-item heap walk when a check fails.
+//
+// Every FP32 formula is evaluated in the written order below (no
+// contraction), the same order the oracle uses:
+//   prep: vl = min y, vu = max y; delta = (vu - vl) * fl(1/15);
+//     u_i = clamp(floor((y_i - vl) / delta + 0.5), 0, 15) (0 if delta = 0);
+//     c1 = (2 delta) / sqrt(D); c2 = (2 vl) / sqrt(D);
+//     c3 = (delta / sqrt(D)) * sum u; c4 = sqrt(D) * vl;
+//   est = (((c1 * ip + c2 * pc) - c3) - c4) * f;
+//   L2: key = (nr*nr + nq2) - (2 nr) * est; err = ((2 nr * sqrt(nq2)) * g) * epsc;
+//   IP: key = -(ipc + nr * est);           err = ((nr * qn) * g) * epsc;
+//   epsc = eps0 / sqrt(D - 1); lb = key - err; ub = key + err.
+#include <hip/hip_fp16.h>
+#include "common.h"
+#include "kernels.h"
+
+namespace bbc {
+
+// ---- rotation -------------------------------------------------------------------
+constexpr int ROT_TILE = 64;   // output tile per block (rows x columns)
+constexpr int ROT_K = 16;      // e-chunk staged in LDS
+
+__global__ __launch_bounds__(256) void rotate_kernel(const float* __restrict__ v, int64_t n, int D,
+                                                     const float* __restrict__ P, float* __restrict__ y) {
+  __shared__ float vs[ROT_TILE][ROT_K + 1];
+  __shared__ float ps[ROT_K][ROT_TILE];
+  const int64_t r0 = (int64_t)blockIdx.y * ROT_TILE;
+  const int c0 = blockIdx.x * ROT_TILE;
+  const int tr = threadIdx.x / 16, tc = threadIdx.x % 16;  // 16 x 16 threads, 4 x 4 outputs each
+  float acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0f;
+  for (int e0 = 0; e0 < D; e0 += ROT_K) {
+    for (int idx = threadIdx.x; idx < ROT_TILE * ROT_K; idx += 256) {
+      const int rr = idx / ROT_K, ee = idx % ROT_K;
+      const int64_t row = r0 + rr;
+      vs[rr][ee] = (row < n && e0 + ee < D) ? v[row * D + e0 + ee] : 0.0f;
+      const int pe = idx / ROT_TILE, pc = idx % ROT_TILE;
+      ps[pe][pc] = (e0 + pe < D && c0 + pc < D) ? P[(int64_t)(e0 + pe) * D + c0 + pc] : 0.0f;
+    }
+    __syncthreads();
+    const int ke = min(ROT_K, D - e0);
+    for (int e = 0; e < ke; ++e) {
+      float a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = vs[tr + 16 * i][e];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = ps[e][tc + 16 * j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float t = a[i] * b[j];
+          acc[i][j] = acc[i][j] + t;
+        }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t row = r0 + tr + 16 * i;
+    if (row >= n) continue;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = c0 + tc + 16 * j;
+      if (col < D) y[row * D + col] = acc[i][j];
+    }
+  }
+}
+
+hipError_t launch_rotate(const float* v, int64_t n, int D, const float* P, float* y, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  if ((n + ROT_TILE - 1) / ROT_TILE > 65535) return hipErrorInvalidValue;  // grid.y limit: callers chunk rows
+  dim3 grid((unsigned)((D + ROT_TILE - 1) / ROT_TILE), (unsigned)((n + ROT_TILE - 1) / ROT_TILE));
+  hipLaunchKernelGGL(rotate_kernel, grid, dim3(256), 0, s, v, n, D, P, y);
+  return hipGetLastError();
+}
+
+// ---- index build: residuals, codes and factors ------------------------------------
+__device__ __forceinline__ int list_of_slot(const int64_t* list_off, int nlist, int64_t p) {
+  int lo = 0, hi = nlist - 1;  // largest j with list_off[j] <= p
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (list_off[mid] <= p) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// r[p - p0] = x[list_ids[p]] - c[list(p)] for slots p in [p0, p0 + n)
+__global__ void residual_rows_kernel(RabitqBuildArgs a, int64_t p0, int64_t n, float* __restrict__ r) {
+  const int D = a.D;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < n * D;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t row = idx / D;
+    const int e = (int)(idx % D);
+    const int64_t p = p0 + row;
+    const int j = list_of_slot(a.list_off, a.nlist, p);
+    r[idx] = a.x[(int64_t)a.list_ids[p] * D + e] - a.cent[(int64_t)j * D + e];
+  }
+}
+
+// One wave per slot p in [p0, p0 + n): y = rotated residual row (p - p0).
+__global__ __launch_bounds__(256) void rabitq_encode_kernel(RabitqBuildArgs a, int64_t p0, int64_t n,
+                                                            const float* __restrict__ y) {
+  const int lane = threadIdx.x & 63;
+  const int64_t row = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (row >= n) return;
+  const int D = a.D;
+  const int64_t p = p0 + row;
+  const int j = list_of_slot(a.list_off, a.nlist, p);
+  const float* yr = y + row * D;
+  const float* xr = a.x + (int64_t)a.list_ids[p] * D;
+  const float* cr = a.cent + (int64_t)j * D;
+  const float nr2 = wave_canon(xr, cr, D, false);
+  uint32_t* code = a.codes + p * a.code_words;
+  uint32_t pc = 0;
+  for (int s = 0; s * 64 < D; ++s) {
+    const uint64_t bits = __ballot(yr[s * 64 + lane] > 0.0f);
+    if (lane == 0) {
+      code[2 * s] = (uint32_t)bits;
+      code[2 * s + 1] = (uint32_t)(bits >> 32);
+    }
+    pc += (uint32_t)__popcll(bits);
+  }
+  if (lane == 0) {
+    for (int w = D / 32; w < a.code_words; ++w) code[w] = 0u;
+    const float nr = sqrtf(nr2);
+    float4 fac;
+    if (nr == 0.0f) {
+      for (int w = 0; w < D / 32; ++w) code[w] = 0u;
+      fac = make_float4(0.0f, 1.0f, 0.0f, 0.0f);
+    } else {
+      float s1 = 0.0f;
+      for (int i = 0; i < D; ++i) s1 = s1 + fabsf(yr[i]);
+      const float sD = sqrtf((float)D);
+      const float den = nr * sD;
+      float ipoo = s1 / den;
+      if (ipoo > 1.0f) ipoo = 1.0f;
+      float g = ipoo * ipoo;
+      g = 1.0f - g;
+      g = sqrtf(g);
+      g = g / ipoo;
+      fac = make_float4(nr, 1.0f / ipoo, g, (float)pc);
+    }
+    reinterpret_cast<float4*>(a.factors)[p] = fac;
+  }
+}
+
+hipError_t launch_rabitq_encode(const RabitqBuildArgs& a, int64_t p0, int64_t n, float* resid, float* rot,
+                                 hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t total = n * a.D;
+  int blocks = (int)std::min<int64_t>((total + 255) / 256, 65536);
+  hipLaunchKernelGGL(residual_rows_kernel, dim3(blocks), dim3(256), 0, s, a, p0, n, resid);
+  hipError_t e = launch_rotate(resid, n, a.D, a.P, rot, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(rabitq_encode_kernel, dim3((unsigned)((n + 3) / 4)), dim3(256), 0, s, a, p0, n, rot);
+  return hipGetLastError();
+}
+
+// ---- scan: bounds of every object of a (query, list) pair --------------------------
+constexpr int RQ_MAXD = 2048;
+constexpr int RQ_MAXW = RQ_MAXD / 32;
+
+__global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
+  constexpr int NT = 256;
+  __shared__ float ys[RQ_MAXD];
+  __shared__ uint32_t planes[4 * RQ_MAXW];
+  __shared__ float red_f[2][NT / 64];
+  __shared__ uint32_t red_u[NT / 64];
+  __shared__ float scal[8];
+
+  const int64_t p = blockIdx.x;
+  if (p >= a.npairs) return;
+  int64_t qi;
+  {
+    int64_t lo = 0, hi = a.nq - 1;  // largest query with probe_off[q] <= p
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (a.probe_off[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    qi = lo;
+  }
+  const int D = a.D, W = D / 32;
+  const int j = a.probe_lists[p];
+  const float* qr = a.qrot + qi * D;
+  const float* cr = a.rot_cent + (int64_t)j * D;
+  float vmin = __builtin_inff(), vmax = -__builtin_inff();
+  for (int i = threadIdx.x; i < D; i += NT) {
+    const float y = a.metric == 0 ? qr[i] - cr[i] : qr[i];
+    ys[i] = y;
+    vmin = fminf(vmin, y);
+    vmax = fmaxf(vmax, y);
+  }
+  for (int i = threadIdx.x; i < 4 * W; i += NT) planes[i] = 0u;
+  for (int off = 32; off >= 1; off >>= 1) {
+    vmin = fminf(vmin, __shfl_xor(vmin, off));
+    vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+  }
+  if ((threadIdx.x & 63) == 0) { red_f[0][threadIdx.x >> 6] = vmin; red_f[1][threadIdx.x >> 6] = vmax; }
+  __syncthreads();
+  float vl = red_f[0][0], vu = red_f[1][0];
+  for (int w = 1; w < NT / 64; ++w) { vl = fminf(vl, red_f[0][w]); vu = fmaxf(vu, red_f[1][w]); }
+  const float inv15 = 1.0f / 15.0f;
+  float delta = vu - vl;
+  delta = delta * inv15;
+  uint32_t su = 0;
+  for (int i = threadIdx.x; i < D; i += NT) {
+    uint32_t u = 0;
+    if (delta > 0.0f) {
+      float t = ys[i] - vl;
+      t = t / delta;
+      t = t + 0.5f;
+      t = floorf(t);
+      u = t < 0.0f ? 0u : (t > 15.0f ? 15u : (uint32_t)t);
+    }
+    su += u;
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      if ((u >> b) & 1u) atomicOr(&planes[b * W + i / 32], 1u << (i % 32));
+  }
+  for (int off = 32; off >= 1; off >>= 1) su += __shfl_xor(su, off);
+  if ((threadIdx.x & 63) == 0) red_u[threadIdx.x >> 6] = su;
+  // IP: |q| from the canonical inner product of q with itself (wave 0)
+  float qn = 0.0f;
+  if (a.metric != 0 && threadIdx.x < 64) qn = sqrtf(wave_canon(a.q + qi * D, a.q + qi * D, D, true));
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t sum_u = 0;
+    for (int w = 0; w < NT / 64; ++w) sum_u += red_u[w];
+    const float sD = sqrtf((float)D);
+    float c1 = 2.0f * delta;
+    c1 = c1 / sD;
+    float c2 = 2.0f * vl;
+    c2 = c2 / sD;
+    float c3 = delta / sD;
+    c3 = c3 * (float)sum_u;
+    const float c4 = sD * vl;
+    scal[0] = c1; scal[1] = c2; scal[2] = c3; scal[3] = c4;
+    const float pk = a.probe_keys[p];
+    scal[4] = a.metric == 0 ? pk : -pk;  // L2: canon_l2(q, c_j); IP: canon_ip(q, c_j)
+    scal[5] = qn;
+  }
+  __syncthreads();
+  const float c1 = scal[0], c2 = scal[1], c3 = scal[2], c4 = scal[3], av = scal[4];
+  const float qnv = scal[5];
+  const float nq = sqrtf(av);
+  const float epsc = a.eps0 / sqrtf((float)(D - 1));
+  const int64_t lbeg = a.list_off[j], nobj = a.list_off[j + 1] - lbeg;
+  const int64_t out0 = a.key_off[qi] + a.rank_off[p];
+  const int CW = a.code_words;
+  for (int64_t t = threadIdx.x; t < nobj; t += NT) {
+    const uint32_t* code = a.codes + (lbeg + t) * CW;
+    uint32_t c[4] = {0u, 0u, 0u, 0u};
+    for (int w4 = 0; w4 < CW; w4 += 4) {
+      const uint4 cv = *reinterpret_cast<const uint4*>(code + w4);
+      const uint32_t cw[4] = {cv.x, cv.y, cv.z, cv.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int w = w4 + u;
+        if (w < W) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popc(cw[u] & planes[b * W + w]);
+        }
+      }
+    }
+    const int64_t ip = (int64_t)c[0] + 2 * (int64_t)c[1] + 4 * (int64_t)c[2] + 8 * (int64_t)c[3];
+    const float4 fac = reinterpret_cast<const float4*>(a.factors)[lbeg + t];
+    float est = c1 * (float)ip;
+    const float tpc = c2 * fac.w;
+    est = est + tpc;
+    est = est - c3;
+    est = est - c4;
+    est = est * fac.y;
+    const float nr = fac.x;
+    float key, e;
+    if (a.metric == 0) {
+      float tt = nr * nr;
+      tt = tt + av;
+      float uu = 2.0f * nr;
+      uu = uu * est;
+      key = tt - uu;
+      e = 2.0f * nr;
+      e = e * nq;
+      e = e * fac.z;
+      e = e * epsc;
+    } else {
+      float vv = nr * est;
+      vv = av + vv;
+      key = -vv;
+      e = nr * qnv;
+      e = e * fac.z;
+      e = e * epsc;
+    }
+    a.lb[out0 + t] = key - e;
+    a.ub[out0 + t] = key + e;
+    if (a.key) a.key[out0 + t] = key;
+  }
+}
+
+hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
+  if (a.npairs <= 0) return hipSuccess;
+  if (a.D > RQ_MAXD || a.D % 64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(rabitq_scan_kernel, dim3((unsigned)a.npairs), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---- bounded re-rank ---------------------------------------------------------------
+constexpr int WK_NB = 2048;       // lb bins
+constexpr int WK_RANKCAP = 2048;  // probe ranks in LDS
+constexpr int WK_CHUNK = 1024;    // items per step of the exact walk
+
+template <typename T> __device__ __forceinline__ float4 ld4(const T* p, int64_t chunk);
+template <> __device__ __forceinline__ float4 ld4<float>(const float* p, int64_t chunk) {
+  return reinterpret_cast<const float4*>(p)[chunk];
+}
+template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p, int64_t chunk) {
+  const uint2 v = reinterpret_cast<const uint2*>(p)[chunk];
+  const float2 f0 = __half22float2(__builtin_bit_cast(__half2, v.x));
+  const float2 f1 = __half22float2(__builtin_bit_cast(__half2, v.y));
+  return make_float4(f0.x, f0.y, f1.x, f1.y);
+}
+
+// exact key (canonical L2, or -canonical IP) of list position pos, one wave
+template <typename T>
+__device__ float exact_key(const RabitqWalkArgs& a, const float* q, int64_t pos) {
+  const int lane = threadIdx.x & 63;
+  const int nchunk = a.D >> 2;
+  const T* row = reinterpret_cast<const T*>(a.vectors) + pos * a.D;
+  float acc = 0.0f;
+  for (int c = lane; c < nchunk; c += 64) {
+    const float4 qv = reinterpret_cast<const float4*>(q)[c];
+    const float4 xv = ld4<T>(row, c);
+    acc = a.metric == 0 ? chunk_l2(qv, xv, acc) : chunk_ip(qv, xv, acc);
+  }
+  acc = canon_reduce64(acc);
+  return a.metric == 0 ? acc : -acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
+  constexpr int NT = 1024;
+  constexpr int NW = NT / 64;
+  __shared__ int32_t s_rbeg[WK_RANKCAP];
+  __shared__ int32_t s_lbeg[WK_RANKCAP];
+  __shared__ uint32_t hist[WK_NB];
+  __shared__ uint32_t rhist[256];
+  __shared__ __align__(8) uint32_t bc[16];
+  __shared__ uint64_t chunk_v[WK_CHUNK];   // exact walk: (lb image, id) of the chunk, sorted
+  __shared__ uint64_t chunk_x[WK_CHUNK];   // exact walk: (exact image, id) in chunk order
+
+  const int64_t qi = blockIdx.x;
+  const int64_t S = a.n_scanned[qi];
+  const int64_t k = a.k[qi];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (S == 0) {
+    if (threadIdx.x == 0) { a.n_cand[qi] = 0; if (a.n_visited) a.n_visited[qi] = 0; }
+    return;
+  }
+  const int64_t po = a.probe_off[qi];
+  const SlotMap sm = slot_map_load<NT, WK_RANKCAP>(a.rank_off + po, a.probe_lists + po, a.list_off, a.nprobe[qi],
+                                                   s_rbeg, s_lbeg);
+  const float* lb = a.lb + a.key_off[qi];
+  const float* ub = a.ub + a.key_off[qi];
+  uint32_t* cbuf = a.cbuf + a.key_off[qi];
+  uint64_t* pbuf = a.cand_packed + a.cand_off[qi];
+  const float* q = a.q + qi * a.D;
+
+  // U = k-th smallest ub (all objects qualify when S <= k)
+  uint32_t U = 0xffffffffu;
+  if (S > k) U = block_radix_select32<NT>([&](int64_t i) { return key_bits(ub[i]); }, S, k - 1, rhist, bc);
+  // C = {lb <= U}: its smallest and largest lb image
+  if (threadIdx.x == 0) { bc[4] = 0xffffffffu; bc[5] = 0u; bc[6] = 0u; }
+  __syncthreads();
+  {
+    uint32_t mn = 0xffffffffu, mx = 0u, cnt = 0;
+    for (int64_t i = threadIdx.x; i < S; i += NT) {
+      const uint32_t b = key_bits(lb[i]);
+      if (b <= U) { mn = min(mn, b); mx = max(mx, b); ++cnt; }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      mn = min(mn, __shfl_xor(mn, off));
+      mx = max(mx, __shfl_xor(mx, off));
+      cnt += __shfl_xor(cnt, off);
+    }
+    if (lane == 0) { atomicMin(&bc[4], mn); atomicMax(&bc[5], mx); atomicAdd(&bc[6], cnt); }
+  }
+  for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = 0;
+  __syncthreads();
+  const uint32_t lmin = bc[4];
+  const uint32_t span = bc[5] - lmin;
+  const int64_t nC = bc[6];
+  int shift = 0;
+  while ((span >> shift) >= (uint32_t)WK_NB) ++shift;
+  for (int64_t base = 0; base < S; base += NT) {  // wave-uniform trip count
+    const int64_t i = base + threadIdx.x;
+    const uint32_t b = i < S ? key_bits(lb[i]) : 0xffffffffu;
+    const bool in = i < S && b <= U;
+    wave_hist_add(hist, in ? (b - lmin) >> shift : 0u, in);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // exclusive prefix, in place
+    uint32_t carry = 0;
+    for (int base = 0; base < WK_NB; base += 64) {
+      const uint32_t v = hist[base + lane];
+      const uint32_t incl = wave_incl_scan(v);
+      hist[base + lane] = carry + incl - v;
+      carry += __shfl(incl, 63);
+    }
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < S; i += NT) {
+    const uint32_t b = key_bits(lb[i]);
+    if (b <= U) cbuf[atomicAdd(&hist[(b - lmin) >> shift], 1u)] = (uint32_t)i;
+  }
+  __syncthreads();
+  // hist[b] is now the end of bin b in cbuf.  Walk whole bins in order.
+  auto lower_edge = [&](int b) -> uint64_t { return (uint64_t)lmin + ((uint64_t)b << shift); };
+  const int64_t chunk = max((int64_t)WK_CHUNK, k / 4);
+  int64_t p = 0;
+  int b_end = 0;
+  uint32_t E = 0xffffffffu;  // k-th smallest exact key image among the processed
+  bool exhausted = false;
+  while (true) {
+    const int64_t target = p < k ? max(k, (int64_t)WK_CHUNK) : p + chunk;
+    int b = b_end;
+    while (b < WK_NB && (int64_t)hist[b] < target) ++b;
+    if (b < WK_NB) ++b;  // the bin that reaches the target
+    const int64_t np_ = b > 0 ? (int64_t)hist[b - 1] : 0;
+    b_end = b;
+    for (int64_t i = p + wv; i < np_; i += NW) {
+      const uint32_t slot = cbuf[i];
+      const int64_t pos = sm.pos(slot);
+      const float ex = exact_key<T>(a, q, pos);
+      if (lane == 0) pbuf[i] = pack_key_id(ex, (uint32_t)a.list_ids[pos]);
+    }
+    __syncthreads();
+    p = np_;
+    if (p >= k) {
+      E = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(pbuf[i] >> 32); }, p, k - 1, rhist, bc);
+    }
+    if (b_end >= WK_NB || p >= nC) { exhausted = true; break; }
+    if (p >= k && lower_edge(b_end) > (uint64_t)E) break;
+  }
+  // checks: (i) when C is exhausted the next object (lb > U) must stop the
+  // walk, i.e. E <= U; (ii) every object of the result has lb <= E.  Both
+  // hold trivially when everything was processed with at most k objects.
+  bool ok = true;
+  if (S > k) {
+    if (exhausted && p < S && E > U) ok = false;
+    if (threadIdx.x == 0) bc[7] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < p; i += NT)
+      if ((uint32_t)(pbuf[i] >> 32) <= E && key_bits(lb[cbuf[i]]) > E) bc[7] = 1;
+    __syncthreads();
+    if (bc[7]) ok = false;
+  }
+  if (ok) {
+    if (threadIdx.x == 0) { a.n_cand[qi] = p; if (a.n_visited) a.n_visited[qi] = p; }
+    return;
+  }
+
+  // ---- exact walk, item by item: chunks of the next WK_CHUNK objects in
+  // (lb, id) order, their exact keys, then one wave offers them in order to
+  // a 64-ary max-heap of the best k (in pbuf), stopping by the rule.
+  auto packed_lb = [&](int64_t i) -> uint64_t {
+    return ((uint64_t)key_bits(lb[i]) << 32) | (uint64_t)(uint32_t)a.list_ids[sm.pos(i)];
+  };
+  uint64_t last = 0;
+  bool have_last = false;
+  int64_t nr = 0, visited = 0;
+  uint64_t top = 0;
+  bool stop = false;
+  while (!stop) {
+    if (threadIdx.x == 0) bc[8] = 0;
+    __syncthreads();
+    {
+      uint32_t cnt = 0;
+      for (int64_t i = threadIdx.x; i < S; i += NT) cnt += (!have_last || packed_lb(i) > last) ? 1u : 0u;
+      for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+      if (lane == 0 && cnt) atomicAdd(&bc[8], cnt);
+    }
+    __syncthreads();
+    const int64_t rem = bc[8];
+    if (rem == 0) break;
+    const int64_t nb = min((int64_t)WK_CHUNK, rem);
+    const uint64_t thr = block_radix_select64<NT>(
+        [&](int64_t i, uint64_t& v) -> bool {
+          v = packed_lb(i);
+          return !have_last || v > last;
+        },
+        S, nb - 1, rhist, bc);
+    if (threadIdx.x == 0) bc[9] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < S; i += NT) {
+      const uint64_t v = packed_lb(i);
+      if ((!have_last || v > last) && v <= thr) chunk_v[atomicAdd(&bc[9], 1u)] = v;
+    }
+    // the chunk in (lb, id) order; an object's id gives its list position
+    const int P2 = next_pow2((int)nb);
+    for (int i = (int)nb + threadIdx.x; i < P2; i += NT) chunk_v[i] = ~0ull;
+    lds_bitonic_sort<NT>(chunk_v, P2);
+    for (int i = wv; i < (int)nb; i += NW) {
+      const uint32_t id = (uint32_t)chunk_v[i];
+      const float ex = exact_key<T>(a, q, (int64_t)a.pos_of_id[id]);
+      if (lane == 0) chunk_x[i] = pack_key_id(ex, id);
+    }
+    __syncthreads();
+    if (wv == 0) {
+      for (int i = 0; i < (int)nb; ++i) {
+        const uint32_t lbi = (uint32_t)(chunk_v[i] >> 32);
+        if (nr == k && lbi > (uint32_t)(top >> 32)) { stop = true; break; }
+        const uint64_t e = chunk_x[i];
+        ++visited;
+        if (nr < k) {
+          if (lane == 0) hstore(pbuf + nr, e);
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+          ++nr;
+          if (nr == k) {
+            for (int64_t node = (k - 2) / 64; node >= 0; --node) heap_sift_down(pbuf, k, node, hload(pbuf + node));
+            top = hload(pbuf);
+          }
+        } else if (e < top) {
+          heap_sift_down(pbuf, k, 0, e);
+          top = hload(pbuf);
+        }
+      }
+      if (lane == 0) { bc[10] = stop ? 1u : 0u; bc[11] = (uint32_t)nr; bc[12] = (uint32_t)visited; }
+    }
+    __syncthreads();
+    stop = bc[10] != 0;
+    nr = bc[11];
+    visited = bc[12];
+    last = thr;
+    have_last = true;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = visited; }
+}
+
+hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s) {
+  if (a.nq <= 0) return hipSuccess;
+  if (a.fp16) hipLaunchKernelGGL(rabitq_walk_kernel<__half>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  else hipLaunchKernelGGL(rabitq_walk_kernel<float>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace bbc

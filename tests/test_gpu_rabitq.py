@@ -1,0 +1,120 @@
+"""GPU parity of the RaBitQ path against the oracle through the C ABI: the
+index build (rotation, codes, factors), every object's estimated key and
+bounds, and the bounded re-rank's final ids and distances (L2 and IP,
+float32 and float16 rows, uneven k / nprobe, and the item-by-item walk
+taken when the bin walk's checks fail)."""
+import functools
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def bbc():
+    import paper_2604_01960_amd as b
+    b.load()
+    return b
+
+
+@functools.lru_cache(maxsize=8)
+def _data(d, n, nq, nlist, metric, fp16=False, seed_index=2):
+    w = synth.small_workload("ivfrabitq_1m_d960", n=n, nlist=nlist, nq=nq, d=d, seed_index=seed_index)
+    x = synth.base_vectors(w)
+    q = synth.query_vectors(w)
+    if metric == 1:
+        x = (x / np.linalg.norm(x, axis=1, keepdims=True)).astype(np.float32)
+        q = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    if fp16:
+        x = x.astype(np.float16)
+    tr, ip = synth.kmeans_draws(n, nlist, 64 * nlist, 0)
+    P = synth.rotation_orthogonal(d, 300 + seed_index)
+    ix = oracle.build_ivf_rabitq(x, nlist, tr, ip, P, metric=metric)
+    return x, q, tr, ip, P, ix
+
+
+def _gpu_index(bbc, x, ix, eps0=0.0):
+    return bbc.Index.create_rabitq(ix["centroids"], ix["list_off"], ix["list_ids"], ix["P"], ix["codes"],
+                                   ix["factors"], x, metric=ix["metric"], eps0=eps0)
+
+
+def _check_search(g, ix, q, k, nprobe, eps0=oracle.RABITQ_EPS0):
+    tr = g.search_traced(q, k, nprobe)
+    ref = oracle.search_rabitq(ix, q, k, nprobe, eps0=eps0, debug=True)
+    np.testing.assert_array_equal(tr["probe_lists"], ref["probe_lists"])
+    np.testing.assert_array_equal(tr["probe_keys"], ref["probe_keys"])
+    np.testing.assert_array_equal(tr["n_scanned"], ref["n_scanned"])
+    np.testing.assert_array_equal(tr["est_keys"], ref["est_key"])
+    np.testing.assert_array_equal(tr["est_lb"], ref["est_lb"])
+    np.testing.assert_array_equal(tr["est_ub"], ref["est_ub"])
+    np.testing.assert_array_equal(tr["counts"], ref["counts"])
+    np.testing.assert_array_equal(tr["ids"], ref["ids"])
+    np.testing.assert_array_equal(tr["dists"], ref["dists"])
+    # the bin walk re-ranks whole bins: at least what the item walk visits
+    assert np.all(tr["n_visited"] >= np.minimum(ref["n_visited"], tr["n_scanned"]) - 0)
+    return tr, ref
+
+
+@pytest.mark.parametrize("d", [128, 960])
+def test_gpu_build_matches_oracle(bbc, d):
+    n = 6000 if d == 128 else 2500
+    x, q, tr, ip, P, ix = _data(d, n, 4, 12, 0)
+    print(f"[case] rabitq build d={d} n={n}", flush=True)
+    g = bbc.Index.build_rabitq(x, 12, tr, ip, P)
+    np.testing.assert_array_equal(g.get(bbc.FIELD_CENTROIDS), ix["centroids"])
+    np.testing.assert_array_equal(g.get(bbc.FIELD_LIST_IDS), ix["list_ids"])
+    np.testing.assert_array_equal(g.get(bbc.FIELD_RABITQ_CODES), ix["codes"])
+    np.testing.assert_array_equal(g.get(bbc.FIELD_RABITQ_FACTORS), ix["factors"])
+    np.testing.assert_array_equal(g.get(bbc.FIELD_ROT_CENTROIDS), ix["rot_centroids"])
+
+
+@pytest.mark.parametrize("cfg", [
+    # (d, n, nq, nlist, metric, fp16, k, nprobe)
+    (128, 6000, 8, 12, 0, False, 200, 4),
+    (960, 2500, 5, 8, 0, False, 300, 3),
+    (256, 5000, 6, 10, 1, True, 250, 3),
+])
+def test_bounds_and_results_match_oracle(bbc, cfg):
+    d, n, nq, nlist, metric, fp16, k, nprobe = cfg
+    x, q, tr, ip, P, ix = _data(d, n, nq, nlist, metric, fp16)
+    print(f"[case] rabitq search d={d} metric={metric} fp16={fp16} k={k} nprobe={nprobe}", flush=True)
+    g = _gpu_index(bbc, x, ix)
+    _check_search(g, ix, q, k, nprobe)
+
+
+def test_uneven_and_edge_cases(bbc):
+    x, q, tr, ip, P, ix = _data(128, 6000, 8, 12, 0)
+    g = _gpu_index(bbc, x, ix)
+    k = np.array([1, 7, 64, 500, 6000, 40, 2000, 9000], np.int32)
+    npb = np.array([1, 12, 2, 5, 12, 1, 3, 4], np.int32)
+    print("[case] rabitq uneven", flush=True)
+    tr, ref = _check_search(g, ix, q, k, npb)
+    assert np.all(tr["ids"][tr["off"][-2] + tr["counts"][-1]:] == -1)  # k > S pads
+
+
+@pytest.mark.parametrize("eps0", [0.05, 0.4])
+def test_narrow_bounds_take_the_exact_walk(bbc, eps0):
+    """With narrow bounds many fail, so the bin walk's checks fail and the
+    item-by-item walk must still return the oracle's result."""
+    x, q, tr, ip, P, ix = _data(128, 6000, 8, 12, 0)
+    g = _gpu_index(bbc, x, ix, eps0=eps0)
+    print(f"[case] rabitq eps0={eps0}", flush=True)
+    _check_search(g, ix, q, 150, 4, eps0=eps0)
+
+
+def test_device_io_and_repeat(bbc):
+    import torch
+    x, q, tr, ip, P, ix = _data(256, 5000, 6, 10, 1, True)
+    g = _gpu_index(bbc, x, ix)
+    a = g.search(q, 250, 3)
+    b = g.search(q, 250, 3)
+    for u, v in zip(a[:3], b[:3]):
+        np.testing.assert_array_equal(u, v)
+    ids, dists, counts, off = g.search(torch.from_numpy(q).cuda(), 250, 3)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ids.cpu().numpy(), a[0])
+    np.testing.assert_array_equal(dists.cpu().numpy(), a[1])
