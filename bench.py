@@ -66,13 +66,17 @@ def recall_at_k(ids, off, gt, k):
     return float(sum(r) / len(r))
 
 
-def ground_truth(torch, x_gpu64, q, kmax):
-    """Exact float64 k nearest (evaluation only)."""
+def ground_truth(torch, x_gpu64, q, kmax, metric=0):
+    """Exact float64 k nearest (evaluation only): squared L2, or the largest
+    inner products for metric 1."""
     out = []
     xn = (x_gpu64 * x_gpu64).sum(1)
     for s in range(0, q.shape[0], 50):
         qq = torch.from_numpy(q[s:s + 50]).to(x_gpu64.device, torch.float64)
-        d = xn[None, :] - 2.0 * (qq @ x_gpu64.T) + (qq * qq).sum(1)[:, None]
+        if metric == 0:
+            d = xn[None, :] - 2.0 * (qq @ x_gpu64.T) + (qq * qq).sum(1)[:, None]
+        else:
+            d = -(qq @ x_gpu64.T)
         out.append(torch.topk(d, kmax, dim=1, largest=False).indices.cpu().numpy())
     import numpy as np
     return np.concatenate(out)
@@ -122,6 +126,8 @@ def main():
     dev = torch.device("cuda:0")
     bbc.load()
     w = synth.workload(args.workload)
+    if w.quant == "rabitq":
+        return run_rabitq(args, w, np, torch, bbc, synth, dev)
     nq = args.nq or w.nq
     ks = list(w.k)
     t0 = time.time()
@@ -329,6 +335,122 @@ def main():
         "sizes": sizes,
         "roofline": roof,
         "roofline_other_kernels": others,
+        "cpu_baseline": cpu,
+        "build_s": round(build_s, 2),
+    }
+    print(json.dumps(res), flush=True)
+
+
+def run_rabitq(args, w, np, torch, bbc, synth, dev):
+    """RaBitQ workload: one batch of queries at one k per step, nprobe swept
+    to the smallest value whose mean recall@k reaches the target."""
+    nq = args.nq or w.nq
+    k = int(w.k[0])
+    metric = bbc.METRIC_IP if w.metric == "ip" else bbc.METRIC_L2
+    t0 = time.time()
+    x = synth.base_vectors(w)
+    q = synth.query_vectors(w, nq)
+    if metric == bbc.METRIC_IP:  # unit queries, normalised in float32
+        q = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    tr, ip = synth.kmeans_draws(w.n, w.nlist, w.train_per_list * w.nlist, 0)
+    P = synth.rotation_orthogonal(w.d, w.seed_rotation)
+    log(f"data {x.shape} {x.dtype} queries {q.shape} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    index = bbc.Index.build_rabitq(x, w.nlist, tr, ip, P, metric=metric, iters=w.kmeans_iters)
+    build_s = time.time() - t0
+    log(f"GPU index build {build_s:.1f}s")
+    rq = q[: args.recall_queries]
+    x64 = torch.from_numpy(x).to(dev).to(torch.float64)
+    gt = ground_truth(torch, x64, rq, k, metric)
+    del x64
+    torch.cuda.empty_cache()
+    if args.nprobe:
+        npb = int(args.nprobe.split(",")[0])
+        ids, _, _, off = index.search(rq, k, npb)
+        rec = recall_at_k(ids, off, gt, k)
+    else:
+        npb, rec = None, None
+        for cand in [32, 64, 96, 128, 192, 256, 384, 512, 768, 1024]:
+            if cand > w.nlist:
+                break
+            ids, _, _, off = index.search(rq, k, cand)
+            r = recall_at_k(ids, off, gt, k)
+            log(f"nprobe {cand}: recall {r:.4f}")
+            if r >= args.target_recall:
+                npb, rec = cand, r
+                break
+        if npb is None:
+            raise SystemExit(f"recall {args.target_recall} not reached")
+    qd = torch.from_numpy(q).to(dev)
+    out = (torch.empty(nq * k, dtype=torch.int64, device=dev), torch.empty(nq * k, dtype=torch.float32, device=dev),
+           torch.empty(nq, dtype=torch.int32, device=dev))
+    for _ in range(args.warmup):
+        index.search(qd, k, npb, out=out)
+    torch.cuda.synchronize()
+    bbc.stage_times(reset=True)
+    bbc.stage_timing(True)
+    lat = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        index.search(qd, k, npb, out=out)
+        e1.record()
+        lat.append((e0, e1))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    bbc.stage_timing(False)
+    stages = bbc.stage_times(reset=True)
+    lat_ms = np.array([a.elapsed_time(b) for a, b in lat])
+    value = nq * args.steps / elapsed
+    sz = index.search_sizes(q, k, npb)
+    S, nv = int(sz["n_scanned"].sum()), int(sz["n_visited"].sum())
+    row_bytes = (2 if x.dtype == np.float16 else 4) * w.d
+    algo = {"scan": S * (w.d // 8 + 16), "rerank": nv * (row_bytes + 4)}
+    names = {"scan": "rabitq_scan_kernel (bounds of every scanned object)",
+             "rerank": "rabitq_walk_kernel (bounded re-rank)"}
+    entries = {}
+    for name in algo:
+        st = stages[name]
+        if st["launches"] == 0:
+            continue
+        avg_ms = st["ms"] / st["launches"]
+        bpl = algo[name] * args.steps / st["launches"]
+        gbs = bpl / (avg_ms * 1e-3) / 1e9
+        entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bpl)}
+    dominant = max(entries, key=lambda s: stages[s]["ms"])
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oix = dict(kind="rabitq", n=w.n, d=w.d, nlist=w.nlist, metric=metric,
+                   centroids=index.get(bbc.FIELD_CENTROIDS), rot_centroids=index.get(bbc.FIELD_ROT_CENTROIDS),
+                   P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
+                   codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
+                   base=np.ascontiguousarray(x, dtype=np.float32))
+        nqc = min(args.cpu_queries, nq)
+        t0 = time.perf_counter()
+        oracle.search_rabitq(oix, q[:nqc], k, npb)
+        t_cpu = time.perf_counter() - t0
+        cpu = {"value": round(nqc / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
+               "sample": f"first {nqc} queries of the batch, same nprobe; oracle search over the index arrays "
+                         f"of the GPU build (bit-identical to the oracle's own build); {t_cpu:.1f}s of CPU work"}
+    res = {
+        "metric": f"QPS at recall@k={args.target_recall}, k={k}, RaBitQ with the bounded re-rank",
+        "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "quant": "rabitq",
+                   "metric": w.metric, "storage": str(x.dtype), "nq": nq, "k": k, "nprobe": npb},
+        "recall": None if rec is None else round(rec, 4),
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3),
+                       "what": f"device time of one {nq}-query batch"},
+        "stage_ms_per_step": {s: round(v["ms"] / max(1, args.steps), 4) for s, v in stages.items()},
+        "sizes": {"S_mean": S / nq, "reranked_mean": nv / nq},
+        "roofline": entries[dominant],
+        "roofline_other_kernels": {n: e for n, e in entries.items() if n != dominant},
         "cpu_baseline": cpu,
         "build_s": round(build_s, 2),
     }

@@ -309,6 +309,30 @@ class Index:
                                         _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
         return r
 
+    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0) -> Dict[str, np.ndarray]:
+        """Host search returning per-query sizes only: S (n_scanned), the
+        candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
+        RaBitQ) and, for RaBitQ, n_visited."""
+        q = _np(queries, np.float32)
+        nq = q.shape[0]
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        r = dict(n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64))
+        fields = ["n_scanned", "n_cand"]
+        if self.quant == QUANT_RABITQ:
+            r["n_visited"] = np.empty(nq, np.int64)
+            fields.append("n_visited")
+        tr = SearchTrace(**{f: _ptr(r[f]) for f in fields})
+        p = self._params(ratio, "bucket", 0, 0, 0, None)
+        ids = np.empty(int(off[-1]), np.int64)
+        dists = np.empty(int(off[-1]), np.float32)
+        counts = np.empty(nq, np.int32)
+        _check(load().bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                        _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
+        return r
+
     def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
                       nsample: int = 0) -> Dict[str, np.ndarray]:
         """Host search that also returns every intermediate of the path."""

@@ -592,7 +592,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const size_t L_qrot = pl.add(sizeof(float) * nq * d);
   const size_t L_lb = pl.add(4 * nkeys), L_ub = pl.add(4 * nkeys);
   const size_t L_key = tracing ? pl.add(4 * nkeys) : 0;
-  const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys);
+  const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys), L_z = pl.add(16 * nkeys);
   const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
@@ -670,6 +670,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   wa.cand_off = d_ko; wa.cand_packed = reinterpret_cast<uint64_t*>(A + L_cp);
   wa.n_cand = reinterpret_cast<int64_t*>(A + L_nc);
   wa.n_visited = reinterpret_cast<int64_t*>(A + L_nv);
+  wa.zbuf = reinterpret_cast<uint64_t*>(A + L_z);
   wa.q = dq; wa.vectors = ix->vectors; wa.fp16 = ix->fp16; wa.D = d; wa.metric = ix->metric;
   {
     StageScope st(s, 4);

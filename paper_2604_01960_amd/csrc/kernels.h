@@ -150,6 +150,7 @@ struct RabitqWalkArgs {
   uint32_t* cbuf;            // [sum S] scratch (slots grouped by lb bin)
   const int64_t* cand_off; uint64_t* cand_packed;  // [sum S] processed (exact key, id)
   int64_t* n_cand; int64_t* n_visited;
+  uint64_t* zbuf;            // [2 * sum S] scratch (the k best so far, ping-pong)
   const float* q; const void* vectors; int fp16; int D; int metric;
 };
 hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s);

@@ -327,7 +327,8 @@ hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
 // ---- bounded re-rank ---------------------------------------------------------------
 constexpr int WK_NB = 2048;       // lb bins
 constexpr int WK_RANKCAP = 2048;  // probe ranks in LDS
-constexpr int WK_CHUNK = 1024;    // items per step of the exact walk
+constexpr int WK_CHUNK = 1024;    // items per step of the exact walk (and per bin-walk round)
+constexpr int WK_QCAP = 2048;     // objects above the k-th exact key resolved in LDS
 
 template <typename T> __device__ __forceinline__ float4 ld4(const T* p, int64_t chunk);
 template <> __device__ __forceinline__ float4 ld4<float>(const float* p, int64_t chunk) {
@@ -340,20 +341,53 @@ template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p, int64
   return make_float4(f0.x, f0.y, f1.x, f1.y);
 }
 
-// exact key (canonical L2, or -canonical IP) of list position pos, one wave
+// Exact keys (canonical L2, or -canonical IP) of up to four list positions
+// (the first `cnt`), one wave; the query's chunks (lane l: chunks l, l+64,
+// ...) are held in registers by the caller (d <= 1024).
 template <typename T>
-__device__ float exact_key(const RabitqWalkArgs& a, const float* q, int64_t pos) {
+__device__ void exact_keys4(const RabitqWalkArgs& a, const float4* qc, const int64_t* pos, int cnt, float* e) {
   const int lane = threadIdx.x & 63;
   const int nchunk = a.D >> 2;
-  const T* row = reinterpret_cast<const T*>(a.vectors) + pos * a.D;
-  float acc = 0.0f;
-  for (int c = lane; c < nchunk; c += 64) {
-    const float4 qv = reinterpret_cast<const float4*>(q)[c];
-    const float4 xv = ld4<T>(row, c);
-    acc = a.metric == 0 ? chunk_l2(qv, xv, acc) : chunk_ip(qv, xv, acc);
+  float4 x[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const T* row = reinterpret_cast<const T*>(a.vectors) + pos[r] * a.D;
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int c = lane + 64 * st;
+      x[r][st] = (r < cnt && c < nchunk) ? ld4<T>(row, c) : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
   }
-  acc = canon_reduce64(acc);
-  return a.metric == 0 ? acc : -acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      if (lane + 64 * st < nchunk) acc = a.metric == 0 ? chunk_l2(qc[st], x[r][st], acc) : chunk_ip(qc[st], x[r][st], acc);
+    acc = canon_reduce64(acc);
+    e[r] = a.metric == 0 ? acc : -acc;
+  }
+}
+
+// Block-wide bitonic sort of keys with a payload (n a power of two).
+template <int NT>
+__device__ void lds_bitonic_sort_kv(uint64_t* key, uint64_t* val, int n) {
+  for (int size = 2; size <= n; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      __syncthreads();
+      for (int t = threadIdx.x; t < (n >> 1); t += NT) {
+        const int lo = 2 * t - (t & (stride - 1));
+        const int hi = lo + stride;
+        const bool up = ((lo & size) == 0);
+        const uint64_t ka = key[lo], kb = key[hi];
+        if ((ka > kb) == up) {
+          key[lo] = kb; key[hi] = ka;
+          const uint64_t v = val[lo]; val[lo] = val[hi]; val[hi] = v;
+        }
+      }
+    }
+  }
+  __syncthreads();
 }
 
 template <typename T>
@@ -365,8 +399,8 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   __shared__ uint32_t hist[WK_NB];
   __shared__ uint32_t rhist[256];
   __shared__ __align__(8) uint32_t bc[16];
-  __shared__ uint64_t chunk_v[WK_CHUNK];   // exact walk: (lb image, id) of the chunk, sorted
-  __shared__ uint64_t chunk_x[WK_CHUNK];   // exact walk: (exact image, id) in chunk order
+  __shared__ uint64_t chunk_v[WK_QCAP];    // (lb image, id) keys, sorted
+  __shared__ uint64_t chunk_x[WK_QCAP];    // their (exact image, id)
 
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
@@ -384,6 +418,15 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   uint32_t* cbuf = a.cbuf + a.key_off[qi];
   uint64_t* pbuf = a.cand_packed + a.cand_off[qi];
   const float* q = a.q + qi * a.D;
+  float4 qc[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int c = lane + 64 * st;
+    qc[st] = c < (a.D >> 2) ? reinterpret_cast<const float4*>(q)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  const int64_t capq = a.key_off[qi + 1] - a.key_off[qi];
+  uint64_t* zA = a.zbuf + 2 * a.key_off[qi];
+  uint64_t* zB = zA + capq;
 
   // U = k-th smallest ub (all objects qualify when S <= k)
   uint32_t U = 0xffffffffu;
@@ -435,47 +478,187 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   __syncthreads();
   // hist[b] is now the end of bin b in cbuf.  Walk whole bins in order.
   auto lower_edge = [&](int b) -> uint64_t { return (uint64_t)lmin + ((uint64_t)b << shift); };
-  const int64_t chunk = max((int64_t)WK_CHUNK, k / 4);
-  int64_t p = 0;
+  // exact keys of cbuf[i0, i1) into pbuf, four rows per wave
+  auto rerank_range = [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0 + 4 * wv; i < i1; i += 4 * NW) {
+      const int cnt = (int)min((int64_t)4, i1 - i);
+      int64_t pos[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) pos[r] = sm.pos(cbuf[i + (r < cnt ? r : 0)]);
+      float e[4];
+      exact_keys4<T>(a, qc, pos, cnt, e);
+      if (lane < cnt) {
+        float ev = e[0];
+        int64_t pv = pos[0];
+#pragma unroll
+        for (int r = 1; r < 4; ++r)
+          if (lane == r) { ev = e[r]; pv = pos[r]; }
+        pbuf[i + lane] = pack_key_id(ev, (uint32_t)a.list_ids[pv]);
+      }
+    }
+  };
+  // Z = the processed (exact, id) that can still be among the k best: all of
+  // them until k are processed, then those whose key image is at most E, the
+  // k-th smallest key image (ties at E included).
+  int64_t p = 0, nz = 0;
   int b_end = 0;
-  uint32_t E = 0xffffffffu;  // k-th smallest exact key image among the processed
+  uint32_t Eimg = 0xffffffffu;
   bool exhausted = false;
   while (true) {
-    const int64_t target = p < k ? max(k, (int64_t)WK_CHUNK) : p + chunk;
+    const int64_t target = p < k ? max(k, (int64_t)WK_CHUNK) : p + WK_CHUNK;
     int b = b_end;
     while (b < WK_NB && (int64_t)hist[b] < target) ++b;
     if (b < WK_NB) ++b;  // the bin that reaches the target
     const int64_t np_ = b > 0 ? (int64_t)hist[b - 1] : 0;
     b_end = b;
-    for (int64_t i = p + wv; i < np_; i += NW) {
-      const uint32_t slot = cbuf[i];
-      const int64_t pos = sm.pos(slot);
-      const float ex = exact_key<T>(a, q, pos);
-      if (lane == 0) pbuf[i] = pack_key_id(ex, (uint32_t)a.list_ids[pos]);
+    rerank_range(p, np_);
+    if (threadIdx.x == 0) bc[13] = 0;
+    __syncthreads();
+    for (int64_t base = p; base < np_; base += NT) {  // wave-uniform trip count
+      const int64_t i = base + threadIdx.x;
+      const uint64_t v = i < np_ ? pbuf[i] : ~0ull;
+      const bool take = i < np_ && (p < k || (uint32_t)(v >> 32) <= Eimg);
+      const uint32_t slot = wave_slot(take, &bc[13]);
+      if (take) zA[nz + slot] = v;
     }
     __syncthreads();
+    nz += bc[13];
     p = np_;
     if (p >= k) {
-      E = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(pbuf[i] >> 32); }, p, k - 1, rhist, bc);
+      Eimg = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
+      if (threadIdx.x == 0) bc[13] = 0;
+      __syncthreads();
+      for (int64_t base = 0; base < nz; base += NT) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = i < nz ? zA[i] : ~0ull;
+        const bool take = i < nz && (uint32_t)(v >> 32) <= Eimg;
+        const uint32_t slot = wave_slot(take, &bc[13]);
+        if (take) zB[slot] = v;
+      }
+      __syncthreads();
+      nz = bc[13];
+      uint64_t* t = zA; zA = zB; zB = t;
     }
     if (b_end >= WK_NB || p >= nC) { exhausted = true; break; }
-    if (p >= k && lower_edge(b_end) > (uint64_t)E) break;
+    if (p >= k && lower_edge(b_end) > (uint64_t)Eimg) break;
   }
-  // checks: (i) when C is exhausted the next object (lb > U) must stop the
-  // walk, i.e. E <= U; (ii) every object of the result has lb <= E.  Both
-  // hold trivially when everything was processed with at most k objects.
+  const uint32_t E = Eimg;  // k-th smallest exact key image among the processed
+  // The processed set P is a prefix of the (lb, id) order.  The oracle's walk
+  // visits every object of P with lb <= E, and it stops at the latest at the
+  // object after P (its lb exceeds E: the next bin starts above E, or, when
+  // C is used up, lb > U >= E, which is checked).  Only the objects of P with
+  // lb > E (set Q) need ordering: the walk stops at the first t of Q (in
+  // (lb, id) order) with lb_t > the k-th exact key of (P minus Q) and Q[0, t),
+  // a predicate monotone in t, found by binary search.
   bool ok = true;
+  int64_t nvis = p;
   if (S > k) {
     if (exhausted && p < S && E > U) ok = false;
-    if (threadIdx.x == 0) bc[7] = 0;
+    if (threadIdx.x == 0) { bc[7] = 0; bc[14] = 0; }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < p; i += NT)
-      if ((uint32_t)(pbuf[i] >> 32) <= E && key_bits(lb[cbuf[i]]) > E) bc[7] = 1;
+    for (int64_t i = threadIdx.x; i < p; i += NT) {
+      const bool above = key_bits(lb[cbuf[i]]) > E;
+      if (above && (uint32_t)(pbuf[i] >> 32) <= E) bc[7] = 1;  // a possible result object above E
+      if (above) atomicAdd(&bc[14], 1u);
+    }
     __syncthreads();
-    if (bc[7]) ok = false;
+    const bool member_above = bc[7] != 0;
+    const int64_t nQ = bc[14];
+    if (ok && member_above) {
+      // Z0 = the objects of P minus Q whose key image is at most the k-th
+      // smallest image among them (all of them when fewer than k)
+      const int64_t n0 = p - nQ;
+      uint32_t thr0 = 0xffffffffu;
+      if (n0 > k)
+        thr0 = block_radix_select32<NT>(
+            [&](int64_t i) { return key_bits(lb[cbuf[i]]) <= E ? (uint32_t)(pbuf[i] >> 32) : 0xffffffffu; }, p,
+            k - 1, rhist, bc);
+      if (threadIdx.x == 0) bc[13] = 0;
+      __syncthreads();
+      for (int64_t base = 0; base < p; base += NT) {
+        const int64_t i = base + threadIdx.x;
+        const uint64_t v = i < p ? pbuf[i] : ~0ull;
+        const bool take = i < p && key_bits(lb[cbuf[i]]) <= E && (uint32_t)(v >> 32) <= thr0;
+        const uint32_t slot = wave_slot(take, &bc[13]);
+        if (take) zB[slot] = v;
+      }
+      __syncthreads();
+      const int64_t nz0 = bc[13];
+      const int64_t kz = min(k, n0);  // objects of R that Z0 provides
+      int64_t lo = max((int64_t)0, k - kz), hi = nQ;
+      uint64_t cut = ~0ull;
+      if (nQ <= WK_QCAP) {
+        // Q sorted in LDS by (lb image, id), with its exact (key, id)
+        if (threadIdx.x == 0) bc[9] = 0;
+        __syncthreads();
+        for (int64_t i = threadIdx.x; i < p; i += NT) {
+          const uint32_t lbi = key_bits(lb[cbuf[i]]);
+          if (lbi > E) {
+            const uint32_t j = atomicAdd(&bc[9], 1u);
+            chunk_v[j] = ((uint64_t)lbi << 32) | (uint64_t)(uint32_t)pbuf[i];
+            chunk_x[j] = pbuf[i];
+          }
+        }
+        const int P2 = next_pow2((int)nQ);
+        for (int i = (int)nQ + threadIdx.x; i < P2; i += NT) { chunk_v[i] = ~0ull; chunk_x[i] = ~0ull; }
+        lds_bitonic_sort_kv<NT>(chunk_v, chunk_x, P2);
+        // first t in [lo, nQ) with lb(Q[t]) > the k-th key of Z0 and Q[0, t)
+        while (lo < hi) {
+          const int64_t t = (lo + hi) >> 1;
+          const uint32_t kth = block_radix_select32<NT>(
+              [&](int64_t i) { return (uint32_t)((i < nz0 ? zB[i] : chunk_x[i - nz0]) >> 32); }, nz0 + t, k - 1,
+              rhist, bc);
+          if ((uint32_t)(chunk_v[t] >> 32) > kth) hi = t; else lo = t + 1;
+        }
+        if (lo < nQ) cut = chunk_v[lo];
+      } else {
+        // the same search with Q left in place: Q[t] by a radix select over
+        // the (lb image, id) keys of Q, Q[0, t) as the keys below it
+        auto qkey = [&](int64_t i, uint64_t& v) -> bool {
+          const uint32_t lbi = key_bits(lb[cbuf[i]]);
+          v = ((uint64_t)lbi << 32) | (uint64_t)(uint32_t)pbuf[i];
+          return lbi > E;
+        };
+        while (lo < hi) {
+          const int64_t t = (lo + hi) >> 1;
+          const uint64_t kt = block_radix_select64<NT>(qkey, p, t, rhist, bc);
+          const uint32_t kth = block_radix_select32<NT>(
+              [&](int64_t i) -> uint32_t {
+                if (i < nz0) return (uint32_t)(zB[i] >> 32);
+                uint64_t v;
+                const bool inq = qkey(i - nz0, v);
+                return (inq && v < kt) ? (uint32_t)(pbuf[i - nz0] >> 32) : 0xffffffffu;
+              },
+              nz0 + p, k - 1, rhist, bc);
+          if ((uint32_t)(kt >> 32) > kth) hi = t; else lo = t + 1;
+        }
+        if (lo < nQ) cut = block_radix_select64<NT>(qkey, p, lo, rhist, bc);
+      }
+      // visited: P minus the objects of Q from position lo on
+      if (lo < nQ) {
+        if (threadIdx.x == 0) bc[13] = 0;
+        __syncthreads();
+        for (int64_t base = 0; base < p; base += NT) {
+          const int64_t i = base + threadIdx.x;
+          bool take = false;
+          uint64_t v = 0;
+          if (i < p) {
+            v = pbuf[i];
+            const uint64_t kk = ((uint64_t)key_bits(lb[cbuf[i]]) << 32) | (uint64_t)(uint32_t)v;
+            take = kk < cut;
+          }
+          const uint32_t slot = wave_slot(take, &bc[13]);
+          if (take) zB[slot] = v;
+        }
+        __syncthreads();
+        nvis = bc[13];
+        for (int64_t i = threadIdx.x; i < nvis; i += NT) pbuf[i] = zB[i];
+        __syncthreads();
+      }
+    }
   }
   if (ok) {
-    if (threadIdx.x == 0) { a.n_cand[qi] = p; if (a.n_visited) a.n_visited[qi] = p; }
+    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = nvis; }
     return;
   }
 
@@ -521,8 +704,10 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
     lds_bitonic_sort<NT>(chunk_v, P2);
     for (int i = wv; i < (int)nb; i += NW) {
       const uint32_t id = (uint32_t)chunk_v[i];
-      const float ex = exact_key<T>(a, q, (int64_t)a.pos_of_id[id]);
-      if (lane == 0) chunk_x[i] = pack_key_id(ex, id);
+      int64_t pos[4] = {(int64_t)a.pos_of_id[id], 0, 0, 0};
+      float ex[4];
+      exact_keys4<T>(a, qc, pos, 1, ex);
+      if (lane == 0) chunk_x[i] = pack_key_id(ex[0], id);
     }
     __syncthreads();
     if (wv == 0) {
