@@ -216,6 +216,24 @@ void bbc_index_free(bbc_index* ix);
 int32_t bbc_stage_timing(int32_t enable);
 int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset);
 
+/* Plans: one batch shape (nq, k[], nprobe[], fixed device buffers) whose
+ * per-query metadata is uploaded once and whose whole launch sequence is
+ * captured into a HIP graph, replayed by bbc_plan_execute on any stream.
+ * The plan owns its workspace (searches through the index itself keep
+ * working meanwhile).  params->device_io must be 1; queries, outputs and
+ * out_offsets are fixed at creation: each execution searches whatever the
+ * query buffer holds then and overwrites the outputs.  With autotune = 1
+ * (PQ, bucket collector) the scan block geometry and the bucket count are
+ * chosen by timing each candidate on the batch once (the choice is read
+ * back by bbc_plan_info).  Results are identical for every choice. */
+typedef struct bbc_plan bbc_plan;
+int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                        const bbc_search_params* params, const float* queries, const int64_t* out_offsets,
+                        int64_t* out_ids, float* out_dists, int32_t* out_counts, int32_t autotune, bbc_plan** out);
+int32_t bbc_plan_execute(bbc_plan* plan, void* stream);
+int32_t bbc_plan_info(const bbc_plan* plan, int32_t* scan_variant, int32_t* buckets, int64_t* workspace_bytes);
+void bbc_plan_free(bbc_plan* plan);
+
 const char* bbc_last_error(void);
 
 #ifdef __cplusplus

@@ -102,6 +102,14 @@ def load(path: Optional[str] = None):
     L.bbc_stage_timing.argtypes = [i32]
     L.bbc_stage_times.restype = i32
     L.bbc_stage_times.argtypes = [vp, vp, i32, i32]
+    L.bbc_plan_create.restype = i32
+    L.bbc_plan_create.argtypes = [vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp, vp, i32, C.POINTER(vp)]
+    L.bbc_plan_execute.restype = i32
+    L.bbc_plan_execute.argtypes = [vp, vp]
+    L.bbc_plan_info.restype = i32
+    L.bbc_plan_info.argtypes = [vp, vp, vp, vp]
+    L.bbc_plan_free.restype = None
+    L.bbc_plan_free.argtypes = [vp]
     L.bbc_last_error.restype = C.c_char_p
     L.bbc_last_error.argtypes = []
     _lib = L
@@ -309,6 +317,25 @@ class Index:
                                         _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
         return r
 
+    def plan(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
+             nsample: int = 0, autotune: bool = False) -> Plan:
+        """Capture the search of a fixed device batch (torch queries and
+        `out` = (ids, dists, counts) torch buffers) into a replayable plan."""
+        import torch
+        nq = int(queries.shape[0])
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        ids, dists, counts = out
+        assert ids.numel() == off[-1] and dists.numel() == off[-1] and counts.numel() == nq
+        p = self._params(ratio, collector, buckets, nsample, 1, None)
+        h = C.c_void_p()
+        torch.cuda.synchronize()
+        _check(load().bbc_plan_create(self._h, nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(queries), _ptr(off),
+                                      _ptr(ids), _ptr(dists), _ptr(counts), 1 if autotune else 0, C.byref(h)))
+        return Plan(h.value, self, (queries, ids, dists, counts))
+
     def search_sizes(self, queries, k, nprobe, ratio: float = 2.0) -> Dict[str, np.ndarray]:
         """Host search returning per-query sizes only: S (n_scanned), the
         candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
@@ -378,6 +405,37 @@ class Index:
         _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                    _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
         return r
+
+
+class Plan:
+    """A captured batch (bbc_plan_*): fixed queries / outputs on the device,
+    replayed as one HIP graph launch by execute()."""
+
+    def __init__(self, handle: int, index: "Index", keep):
+        self._h = C.c_void_p(handle)
+        self._index = index   # the index must outlive the plan
+        self._keep = keep     # buffers the graph reads and writes
+
+    def execute(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(load().bbc_plan_execute(self._h, C.c_void_p(int(s.cuda_stream))))
+
+    def info(self) -> Dict[str, int]:
+        v, b, w = C.c_int32(), C.c_int32(), C.c_int64()
+        _check(load().bbc_plan_info(self._h, C.byref(v), C.byref(b), C.byref(w)))
+        return dict(scan_variant=v.value, buckets=b.value, workspace_bytes=w.value)
+
+    def free(self):
+        if self._h and self._h.value:
+            load().bbc_plan_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def stage_timing(enable: bool = True):

@@ -45,6 +45,7 @@ hipError_t dalloc(T** p, size_t count) {
 }
 
 inline int64_t round_up(int64_t x, int64_t a) { return (x + a - 1) / a * a; }
+inline bool HIP_FAILED(hipError_t e) { return e != hipSuccess; }
 
 uint16_t bf16_rne(float f) {
   uint32_t u;
@@ -112,13 +113,14 @@ struct StageTimer {
   }
 };
 StageTimer g_timer;
+thread_local bool t_capturing = false;  // a plan is capturing its launches: no stage events
 
 struct StageScope {
   hipStream_t s;
   int stage;
   hipEvent_t a = nullptr, b = nullptr;
   StageScope(hipStream_t s_, int st) : s(s_), stage(st) {
-    if (!g_timer.enabled) return;
+    if (!g_timer.enabled || t_capturing) return;
     std::lock_guard<std::mutex> g(g_timer.mu);
     a = g_timer.get();
     b = g_timer.get();
@@ -559,12 +561,24 @@ int64_t kc_cap_of(const bbc_index* ix, int32_t k, int32_t np, double r) {
   return std::min(t, ix->h_maxS[np]);
 }
 
+// How a search call is run: normally (the index's arena, asynchronous
+// metadata upload), as a sizing pass (workspace bytes only), or captured
+// into a graph on a plan's own workspace (metadata uploaded synchronously,
+// then every launch recorded).
+struct SearchCtx {
+  bool size_only = false;
+  size_t ws_bytes = 0;
+  char* ws = nullptr;
+  bool capture = false;
+  hipGraph_t graph = nullptr;
+};
+
 // RaBitQ: probe, rotation of the queries, per-(query, list) bounds, bounded
 // re-rank per query, final sort.  Per-query slot arrays are sized by the
 // largest lists (maxS(nprobe)).
 int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
                           const bbc_search_params* p, const int64_t* out_off, int64_t* out_ids, float* out_dists,
-                          int32_t* out_counts, bbc_search_trace* tr) {
+                          int32_t* out_counts, bbc_search_trace* tr, SearchCtx* ctx) {
   int32_t rc = BBC_OK;
   hipStream_t s = static_cast<hipStream_t>(p->stream);
   const bool host_io = p->device_io == 0;
@@ -596,8 +610,17 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
-  HIP_TRY(ix->arena.reserve(pl.total));
-  char* A = ix->arena.base;
+  if (ctx && ctx->size_only) {
+    ctx->ws_bytes = pl.total;
+    return BBC_OK;
+  }
+  char* A;
+  if (ctx && ctx->ws) {
+    A = ctx->ws;
+  } else {
+    HIP_TRY(ix->arena.reserve(pl.total));
+    A = ix->arena.base;
+  }
   if (ix->pinned_cap < mp.total) {
     HIP_TRY(hipEventSynchronize(ix->meta_done));
     if (ix->pinned) hipHostFree(ix->pinned);
@@ -614,8 +637,14 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   std::memcpy(H + m_ko, key_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
   char* M = A + L_meta;
-  HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ix->meta_done, s));
+  if (ctx && ctx->capture) {
+    HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    t_capturing = true;
+  } else {
+    HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ix->meta_done, s));
+  }
   const float* dq = queries;
   if (host_io) {
     HIP_TRY(hipMemcpyAsync(A + L_q, queries, sizeof(float) * nq * d, hipMemcpyHostToDevice, s));
@@ -728,20 +757,24 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     if ((rc = ragged(tr->est_lb, L_lb))) return rc;
     if ((rc = ragged(tr->est_ub, L_ub))) return rc;
   }
+  if (ctx && ctx->capture) {
+    t_capturing = false;
+    HIP_TRY(hipStreamEndCapture(s, &ctx->graph));
+  }
   if (host_io) HIP_TRY(hipStreamSynchronize(s));
   return BBC_OK;
 }
 
 int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
                    const bbc_search_params* p, const int64_t* out_off, int64_t* out_ids, float* out_dists,
-                   int32_t* out_counts, bbc_search_trace* tr) {
+                   int32_t* out_counts, bbc_search_trace* tr, SearchCtx* ctx = nullptr) {
   int32_t rc = validate_search(ix, queries, nq, k, nprobe, p, out_off);
   if (rc || nq == 0) return rc;
   rc = set_device(ix->device);
   if (rc) return rc;
   std::lock_guard<std::mutex> guard(ix->mu);
   if (ix->quant == BBC_QUANT_RABITQ)
-    return run_search_rabitq(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, tr);
+    return run_search_rabitq(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, tr, ctx);
   hipStream_t s = static_cast<hipStream_t>(p->stream);
   const bool host_io = p->device_io == 0;
   const int m = p->buckets ? p->buckets : 256;
@@ -818,8 +851,17 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     L.t_dmin = pl.add(4 * nq); L.t_delta = pl.add(4 * nq); L.t_map = pl.add(256 * nq);
     L.t_tau = pl.add(4 * nq); L.t_s = pl.add(8 * nq); L.t_counts = pl.add(4 * nq * m); L.t_nb = pl.add(8 * nq); L.t_nsk = pl.add(8 * nq);
   }
-  HIP_TRY(ix->arena.reserve(pl.total));
-  char* A = ix->arena.base;
+  if (ctx && ctx->size_only) {
+    ctx->ws_bytes = pl.total;
+    return BBC_OK;
+  }
+  char* A;
+  if (ctx && ctx->ws) {
+    A = ctx->ws;
+  } else {
+    HIP_TRY(ix->arena.reserve(pl.total));
+    A = ix->arena.base;
+  }
 
   // stage metadata through pinned memory (wait for the previous call's copy)
   if (ix->pinned_cap < mp.total) {
@@ -842,8 +884,14 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::memcpy(H + m_so, sample_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_vo, surv_off.data(), 8 * (nq + 1));
   char* M = A + L.meta;
-  HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
-  HIP_TRY(hipEventRecord(ix->meta_done, s));
+  if (ctx && ctx->capture) {
+    HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
+    HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    t_capturing = true;
+  } else {
+    HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ix->meta_done, s));
+  }
   const float* dq = queries;
   if (host_io) {
     HIP_TRY(hipMemcpyAsync(A + L.q, queries, sizeof(float) * nq * d, hipMemcpyHostToDevice, s));
@@ -1060,6 +1108,10 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       }
     }
   }
+  if (ctx && ctx->capture) {
+    t_capturing = false;
+    HIP_TRY(hipStreamEndCapture(s, &ctx->graph));
+  }
   if (host_io) HIP_TRY(hipStreamSynchronize(s));
   return BBC_OK;
 }
@@ -1084,6 +1136,124 @@ int32_t bbc_search_traced(const bbc_index* ix, const float* queries, int64_t nq,
   return run_search(const_cast<bbc_index*>(ix), queries, nq, k, nprobe, params, out_offsets, out_ids,
                     out_dists, out_counts, trace);
 }
+
+struct bbc_plan {
+  bbc_index* ix = nullptr;
+  int64_t nq = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  hipStream_t stream = nullptr;  // capture stream
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int32_t scan_variant = 0, buckets = 0;
+};
+
+static void plan_release(bbc_plan* pl) {
+  if (!pl) return;
+  if (pl->ix) hipSetDevice(pl->ix->device);
+  if (pl->exec) hipGraphExecDestroy(pl->exec);
+  if (pl->graph) hipGraphDestroy(pl->graph);
+  if (pl->stream) { hipStreamSynchronize(pl->stream); hipStreamDestroy(pl->stream); }
+  if (pl->ws) hipFree(pl->ws);
+  delete pl;
+}
+
+int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32_t* nprobe,
+                        const bbc_search_params* params, const float* queries, const int64_t* out_offsets,
+                        int64_t* out_ids, float* out_dists, int32_t* out_counts, int32_t autotune, bbc_plan** out) {
+  if (!out) return fail(BBC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!params || !params->device_io) return fail(BBC_EINVAL, "a plan needs device pointers (device_io = 1)");
+  if (!out_ids || !out_dists || !out_counts) return fail(BBC_EINVAL, "NULL output");
+  int32_t rc = validate_search(ix, queries, nq, k, nprobe, params, out_offsets);
+  if (rc) return rc;
+  if (nq < 1) return fail(BBC_EINVAL, "a plan needs nq >= 1");
+  if ((rc = set_device(ix->device))) return rc;
+  bbc_plan* pl = new bbc_plan();
+  pl->ix = ix;
+  pl->nq = nq;
+  bbc_search_params prm = *params;
+  if (HIP_FAILED(hipStreamCreateWithFlags(&pl->stream, hipStreamNonBlocking))) {
+    plan_release(pl);
+    return fail(BBC_EDEVICE, "hipStreamCreateWithFlags failed");
+  }
+  prm.stream = pl->stream;
+  const int saved_variant = ix->scan_variant;
+  pl->scan_variant = ix->scan_variant;
+  pl->buckets = prm.buckets;
+  // autotune (PQ): scan block geometry x bucket count, each timed on the batch
+  if (autotune && ix->quant == BBC_QUANT_PQ && prm.collector == BBC_COLLECT_BUCKET) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipEventCreate(&e0);
+    hipEventCreate(&e1);
+    float best = 1e30f;
+    const int variants[3] = {0, 1, 2};
+    const int buckets[3] = {64, 128, 256};
+    for (int vi = 0; vi < 3; ++vi)
+      for (int bi = 0; bi < 3; ++bi) {
+        ix->scan_variant = variants[vi];
+        prm.buckets = buckets[bi];
+        float ms = 0.0f;
+        for (int rep = 0; rep < 2 && rc == BBC_OK; ++rep) {
+          hipEventRecord(e0, pl->stream);
+          rc = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts, nullptr);
+          hipEventRecord(e1, pl->stream);
+          hipEventSynchronize(e1);
+          hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (rc) break;
+        if (ms < best) { best = ms; pl->scan_variant = variants[vi]; pl->buckets = buckets[bi]; }
+      }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (rc) { ix->scan_variant = saved_variant; plan_release(pl); return rc; }
+  }
+  ix->scan_variant = pl->scan_variant;
+  prm.buckets = pl->buckets;
+  SearchCtx sz;
+  sz.size_only = true;
+  rc = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts, nullptr, &sz);
+  if (rc == BBC_OK && HIP_FAILED(hipMalloc(reinterpret_cast<void**>(&pl->ws), sz.ws_bytes)))
+    rc = fail(BBC_ENOMEM, "plan workspace allocation failed");
+  pl->ws_bytes = sz.ws_bytes;
+  SearchCtx cap;
+  cap.ws = pl->ws;
+  cap.capture = true;
+  if (rc == BBC_OK) {
+    rc = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts, nullptr, &cap);
+    if (t_capturing) {  // a launch failed during the capture: close it
+      t_capturing = false;
+      hipGraph_t g = nullptr;
+      hipStreamEndCapture(pl->stream, &g);
+      if (g) hipGraphDestroy(g);
+    }
+  }
+  ix->scan_variant = saved_variant;
+  pl->graph = cap.graph;
+  if (rc == BBC_OK && HIP_FAILED(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0)))
+    rc = fail(BBC_EDEVICE, "hipGraphInstantiate failed");
+  if (rc) { plan_release(pl); return rc; }
+  *out = pl;
+  return BBC_OK;
+}
+
+int32_t bbc_plan_execute(bbc_plan* pl, void* stream) {
+  if (!pl || !pl->exec) return fail(BBC_EINVAL, "plan is NULL");
+  int32_t rc = set_device(pl->ix->device);
+  if (rc) return rc;
+  HIP_TRY(hipGraphLaunch(pl->exec, static_cast<hipStream_t>(stream)));
+  return BBC_OK;
+}
+
+int32_t bbc_plan_info(const bbc_plan* pl, int32_t* scan_variant, int32_t* buckets, int64_t* workspace_bytes) {
+  if (!pl) return fail(BBC_EINVAL, "plan is NULL");
+  if (scan_variant) *scan_variant = pl->scan_variant;
+  if (buckets) *buckets = pl->buckets;
+  if (workspace_bytes) *workspace_bytes = (int64_t)pl->ws_bytes;
+  return BBC_OK;
+}
+
+void bbc_plan_free(bbc_plan* pl) { plan_release(pl); }
 
 int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bbc_search_params* p) {
   if (!ix || !p || k < 1 || nprobe < 1 || nprobe > ix->nlist || !(p->ncand_ratio >= 1.0))
