@@ -234,6 +234,48 @@ int32_t bbc_plan_execute(bbc_plan* plan, void* stream);
 int32_t bbc_plan_info(const bbc_plan* plan, int32_t* scan_variant, int32_t* buckets, int64_t* workspace_bytes);
 void bbc_plan_free(bbc_plan* plan);
 
+/* Serving form (continuous batching; a request loop with admission by the
+ * device memory of the candidate buffers).  Single requests (one query, its
+ * k and nprobe) are submitted one by one and answered from device batches.
+ * A worker thread owned by the server keeps up to `lanes` batches in flight
+ * (0 = 2), each on its own stream with its own workspace, so requests
+ * admitted while others run overlap with them on the device.  Admission
+ * takes the pending requests in arrival order into a new batch while a lane
+ * is free, at most max_slots requests are in flight, and the sum of
+ * bbc_query_bytes over the requests in flight stays within
+ * mem_budget_bytes; a finished batch frees its slots and bytes.  Each
+ * result is the one bbc_search returns for that request alone with
+ * `params` (collector, ncand_ratio, buckets, sampling); params->device_io
+ * and params->stream are ignored.  The index must outlive the server.
+ *
+ * bbc_server_create: the server and its worker on the current device.
+ * bbc_server_submit: copies the query [d] float32 (host) and returns a
+ *   ticket > 0 without waiting for the device; BBC_ENOMEM if the request
+ *   alone exceeds the budget, BBC_EINVAL for bad k / nprobe or non-finite
+ *   values.
+ * bbc_server_poll: if the ticket's result is ready, copies it to the host
+ *   arrays ids [k] int64 and dists [k] float32, count (results found) and
+ *   latency_ns (submission to completion, as seen by the worker), any of
+ *   them NULL to skip, hands the ticket back and returns the request's
+ *   status; BBC_EBUSY if it is not ready yet; BBC_EINVAL for a ticket never
+ *   issued or already collected.
+ * bbc_server_wait: as poll, waiting up to timeout_ms (BBC_EBUSY after).
+ * bbc_server_stats: batches run, requests answered, largest batch, most
+ *   requests in flight at once, requests waiting (any pointer may be NULL).
+ * bbc_server_destroy: answers every request already submitted, stops the
+ *   worker and frees the server (uncollected results are dropped). */
+typedef struct bbc_server bbc_server;
+int32_t bbc_server_create(bbc_index* ix, const bbc_search_params* params, int64_t mem_budget_bytes,
+                          int32_t max_slots, int32_t lanes, bbc_server** out);
+int32_t bbc_server_submit(bbc_server* srv, const float* query, int32_t k, int32_t nprobe, uint64_t* ticket);
+int32_t bbc_server_poll(bbc_server* srv, uint64_t ticket, int64_t* ids, float* dists, int32_t* count,
+                        int64_t* latency_ns);
+int32_t bbc_server_wait(bbc_server* srv, uint64_t ticket, int32_t timeout_ms, int64_t* ids, float* dists,
+                        int32_t* count, int64_t* latency_ns);
+int32_t bbc_server_stats(bbc_server* srv, int64_t* batches, int64_t* requests, int64_t* max_batch,
+                         int64_t* max_inflight, int64_t* pending);
+void bbc_server_destroy(bbc_server* srv);
+
 const char* bbc_last_error(void);
 
 #ifdef __cplusplus

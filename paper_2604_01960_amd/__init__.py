@@ -110,6 +110,18 @@ def load(path: Optional[str] = None):
     L.bbc_plan_info.argtypes = [vp, vp, vp, vp]
     L.bbc_plan_free.restype = None
     L.bbc_plan_free.argtypes = [vp]
+    L.bbc_server_create.restype = i32
+    L.bbc_server_create.argtypes = [vp, C.POINTER(SearchParams), i64, i32, i32, C.POINTER(vp)]
+    L.bbc_server_submit.restype = i32
+    L.bbc_server_submit.argtypes = [vp, vp, i32, i32, C.POINTER(C.c_uint64)]
+    L.bbc_server_poll.restype = i32
+    L.bbc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
+    L.bbc_server_wait.restype = i32
+    L.bbc_server_wait.argtypes = [vp, C.c_uint64, i32, vp, vp, vp, vp]
+    L.bbc_server_stats.restype = i32
+    L.bbc_server_stats.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.bbc_server_destroy.restype = None
+    L.bbc_server_destroy.argtypes = [vp]
     L.bbc_last_error.restype = C.c_char_p
     L.bbc_last_error.argtypes = []
     _lib = L
@@ -336,6 +348,15 @@ class Index:
                                       _ptr(ids), _ptr(dists), _ptr(counts), 1 if autotune else 0, C.byref(h)))
         return Plan(h.value, self, (queries, ids, dists, counts))
 
+    def server(self, mem_budget: int, max_slots: int = 1024, lanes: int = 2, ratio: float = 2.0,
+               collector="bucket", buckets: int = 0, nsample: int = 0) -> "Server":
+        """A continuous-batching server over this index (bbc_server_*)."""
+        p = self._params(ratio, collector, buckets, nsample, 1, None)
+        h = C.c_void_p()
+        _check(load().bbc_server_create(self._h, C.byref(p), int(mem_budget), int(max_slots), int(lanes),
+                                        C.byref(h)))
+        return Server(h.value, self)
+
     def search_sizes(self, queries, k, nprobe, ratio: float = 2.0) -> Dict[str, np.ndarray]:
         """Host search returning per-query sizes only: S (n_scanned), the
         candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
@@ -429,6 +450,68 @@ class Plan:
     def free(self):
         if self._h and self._h.value:
             load().bbc_plan_free(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Single requests in, device batches inside (bbc_server_*).  submit()
+    returns a ticket; poll() returns None while the result is not ready, else
+    (ids, dists, count, latency_ns); wait() blocks up to a timeout."""
+
+    def __init__(self, handle: int, index: "Index"):
+        self._h = C.c_void_p(handle)
+        self._index = index   # the index must outlive the server
+        self._k: Dict[int, int] = {}
+        self._d = int(index.d)
+
+    def submit(self, query, k: int, nprobe: int) -> int:
+        q = _np(query, np.float32).reshape(-1)
+        if q.shape[0] != self._d:
+            raise ValueError(f"query must have {self._d} values")
+        t = C.c_uint64()
+        _check(load().bbc_server_submit(self._h, _ptr(q), int(k), int(nprobe), C.byref(t)))
+        self._k[t.value] = int(k)
+        return t.value
+
+    def _take(self, ticket: int, timeout_ms: Optional[int]):
+        k = self._k.get(int(ticket))
+        if k is None:
+            raise BBCError(EINVAL, "unknown ticket")
+        ids = np.empty(k, np.int64)
+        dists = np.empty(k, np.float32)
+        cnt, lat = C.c_int32(), C.c_int64()
+        if timeout_ms is None:
+            rc = load().bbc_server_poll(self._h, int(ticket), _ptr(ids), _ptr(dists), C.byref(cnt), C.byref(lat))
+        else:
+            rc = load().bbc_server_wait(self._h, int(ticket), int(timeout_ms), _ptr(ids), _ptr(dists),
+                                        C.byref(cnt), C.byref(lat))
+        if rc == EBUSY:
+            return None
+        del self._k[int(ticket)]
+        _check(rc)
+        return ids, dists, cnt.value, lat.value
+
+    def poll(self, ticket: int):
+        return self._take(ticket, None)
+
+    def wait(self, ticket: int, timeout_ms: int = 60000):
+        return self._take(ticket, timeout_ms)
+
+    def stats(self) -> Dict[str, int]:
+        v = [C.c_int64() for _ in range(5)]
+        _check(load().bbc_server_stats(self._h, *[C.byref(x) for x in v]))
+        return dict(batches=v[0].value, requests=v[1].value, max_batch=v[2].value, max_inflight=v[3].value,
+                    pending=v[4].value)
+
+    def free(self):
+        if self._h and self._h.value:
+            load().bbc_server_destroy(self._h)
             self._h = C.c_void_p()
 
     def __del__(self):

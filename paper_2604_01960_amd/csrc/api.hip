@@ -1118,6 +1118,26 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
 
 }  // namespace
 
+namespace bbc {
+
+int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                            const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
+                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes) {
+  if (!p || !ws_bytes) return fail(BBC_EINVAL, "NULL argument");
+  if (!p->device_io) return fail(BBC_EINVAL, "a workspace search needs device I/O");
+  // a sizing pass reads no query: any non-null pointer passes validation
+  static const float no_query = 0.0f;
+  if (!ws && !queries) queries = &no_query;
+  SearchCtx ctx;
+  ctx.size_only = ws == nullptr;
+  ctx.ws = ws;
+  const int32_t rc = run_search(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, nullptr, &ctx);
+  if (ctx.size_only) *ws_bytes = ctx.ws_bytes;
+  return rc;
+}
+
+}  // namespace bbc
+
 extern "C" {
 
 int32_t bbc_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
@@ -1256,16 +1276,20 @@ int32_t bbc_plan_info(const bbc_plan* pl, int32_t* scan_variant, int32_t* bucket
 void bbc_plan_free(bbc_plan* pl) { plan_release(pl); }
 
 int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bbc_search_params* p) {
-  if (!ix || !p || k < 1 || nprobe < 1 || nprobe > ix->nlist || !(p->ncand_ratio >= 1.0))
-    return fail(BBC_EINVAL, "bad argument");
-  int64_t kc = kc_cap_of(ix, k, nprobe, p->ncand_ratio);
-  int64_t bytes = 0;
-  bytes += 4 * (int64_t)ix->d + 4 * (int64_t)ix->nlist;     // query, coarse scores
-  bytes += 16 * (int64_t)nprobe;                            // probe lists, keys, rank offsets
-  bytes += 4 * ix->h_maxS[nprobe];                          // estimated keys
-  bytes += 12 * kc;                                         // candidate slots + packed exact keys
-  bytes += 12 * (int64_t)k + 64;                            // outputs + per-query scalars
-  return bytes;
+  if (!ix || !p) return fail(BBC_EINVAL, "NULL argument");
+  // the workspace a one-query search with device I/O reserves, from the
+  // search's own sizing pass (the same layout the search then allocates)
+  bbc_search_params q = *p;
+  q.device_io = 1;
+  q.stream = nullptr;
+  const float dummy = 0.0f;
+  const int64_t off[2] = {0, k};
+  SearchCtx sz;
+  sz.size_only = true;
+  const int32_t rc = run_search(const_cast<bbc_index*>(ix), &dummy, 1, &k, &nprobe, &q, off, nullptr, nullptr,
+                                nullptr, nullptr, &sz);
+  if (rc) return rc;
+  return (int64_t)sz.ws_bytes;
 }
 
 }  // extern "C"

@@ -13,6 +13,14 @@ namespace bbc {
 // Records the message of a failing call (bbc_last_error) and returns code.
 int32_t set_error(int32_t code, const std::string& msg);
 
+// A search with device I/O whose scratch is the caller's `ws` (the index
+// arena is not touched, so calls on different streams with different
+// workspaces may overlap on the device).  With ws == nullptr only *ws_bytes
+// is set: the bytes the call needs.
+int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                            const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
+                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes);
+
 int32_t build_index_pq(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
                        bbc_index** out);
 int32_t build_index_rabitq(int32_t device, const void* base, int64_t n, int32_t d, const bbc_build_params* p,
