@@ -89,6 +89,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="ivfpq_1m_d128")
     ap.add_argument("--nq", type=int, default=0, help="queries per batch (default: the workload's)")
+    ap.add_argument("--n", type=int, default=0,
+                    help="a scaled-down copy of the workload with this many rows (about 1221 per list)")
     ap.add_argument("--recall-queries", type=int, default=200)
     ap.add_argument("--target-recall", type=float, default=0.95)
     ap.add_argument("--nprobe", type=str, default="", help="fixed nprobe per k, e.g. 128,128 (skips the sweep)")
@@ -96,6 +98,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-queries", type=int, default=3000)
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
+    ap.add_argument("--serve-qps", type=float, default=0.0, help="serving: arrival rate (default: the workload's)")
+    ap.add_argument("--serve-seconds", type=float, default=None, help="serving: stream length (default: the workload's)")
+    ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving: workspace bytes in flight")
+    ap.add_argument("--serve-slots", type=int, default=512, help="serving: requests in flight")
+    ap.add_argument("--serve-lanes", type=int, default=2, help="serving: batches in flight")
+    ap.add_argument("--serve-warmup", type=int, default=256, help="serving: closed-loop warmup requests")
+    ap.add_argument("--capacity-requests", type=int, default=4096,
+                    help="serving: closed-loop requests for the capacity figure (0 skips it)")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="serving: oracle sample length")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (3 times) for counter calibration")
     args = ap.parse_args()
@@ -126,6 +137,10 @@ def main():
     dev = torch.device("cuda:0")
     bbc.load()
     w = synth.workload(args.workload)
+    if args.n:
+        w = synth.small_workload(args.workload, n=args.n, nlist=max(16, args.n // 1221), nq=w.nq)
+    if w.arrival_qps:
+        return run_serving(args, w, np, torch, bbc, synth, dev)
     if w.quant == "rabitq":
         return run_rabitq(args, w, np, torch, bbc, synth, dev)
     if w.uneven:
@@ -591,6 +606,232 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
         "sizes": {"S_mean": S / nq, "reranked_mean": nv / nq},
         "roofline": entries[dominant],
         "roofline_other_kernels": {n: e for n, e in entries.items() if n != dominant},
+        "cpu_baseline": cpu,
+        "build_s": round(build_s, 2),
+    }
+    print(json.dumps(res), flush=True)
+
+
+def recall_each(ids, off, gt, ks):
+    """recall@k_i of each request against its exact top-k_i."""
+    out = []
+    for i, k in enumerate(ks):
+        k = int(k)
+        got = ids[off[i]:off[i] + k]
+        out.append(len(set(got.tolist()) & set(gt[i, :k].tolist())) / k)
+    import numpy as np
+    return np.array(out)
+
+
+def run_serving(args, w, np, torch, bbc, synth, dev):
+    """Serving form: single requests from the workload's seeded Poisson stream
+    (k log-uniform over its range, each query drawn from a pool) through the
+    continuous-batching server.  nprobe is set per k band (four log-spaced
+    bands) to the smallest value whose mean recall@k on a sample of the
+    stream's requests reaches the target.  Reports the served rate, per
+    request latency (submission to completion), the closed-loop capacity,
+    and the roofline of the dominant kernel over the open-loop phase."""
+    import queue
+    import threading
+    assert w.quant == "rabitq", "the serving workload is a RaBitQ index"
+    metric = bbc.METRIC_IP if w.metric == "ip" else bbc.METRIC_L2
+    pool_n = args.nq or w.nq
+    rate = args.serve_qps or w.arrival_qps
+    seconds = w.serve_seconds if args.serve_seconds is None else args.serve_seconds
+    t0 = time.time()
+    x = synth.base_vectors(w)
+    pool = synth.query_vectors(w, pool_n)
+    if metric == bbc.METRIC_IP:  # unit queries, normalised in float32
+        pool = (pool / np.linalg.norm(pool, axis=1, keepdims=True)).astype(np.float32)
+    tr, ip = synth.kmeans_draws(w.n, w.nlist, w.train_per_list * w.nlist, 0)
+    P = synth.rotation_orthogonal(w.d, w.seed_rotation)
+    log(f"data {x.shape} {x.dtype} pool {pool.shape} in {time.time() - t0:.1f}s")
+    t0 = time.time()
+    index = bbc.Index.build_rabitq(x, w.nlist, tr, ip, P, metric=metric, iters=w.kmeans_iters)
+    build_s = time.time() - t0
+    log(f"GPU index build {build_s:.1f}s")
+
+    # ---- operating point: nprobe per k band -----------------------------------
+    kmin, kmax = w.k
+    edges = np.geomspace(kmin, kmax + 1, 5)
+    band_of = lambda kk: np.clip(np.searchsorted(edges, kk, side="right") - 1, 0, 3)
+    grid = [8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048]
+    grid = [g for g in grid if g <= w.nlist]
+    fixed = [int(v) for v in args.nprobe.split(",")] if args.nprobe else []
+    st_t, st_q, st_k = synth.request_stream(w, pool_n, rate, max(seconds, 1.0))
+    R = min(args.recall_queries, len(st_t))
+    band_np, band_rec = [0] * 4, [None] * 4
+    if R > 0:
+        sq, sk = pool[st_q[:R]], st_k[:R].astype(np.int32)
+        x64 = torch.from_numpy(x).to(dev).to(torch.float64)
+        gt = ground_truth(torch, x64, sq, int(sk.max()), metric)
+        del x64
+        torch.cuda.empty_cache()
+        sb = band_of(sk)
+        for b in range(4):
+            m = np.nonzero(sb == b)[0]
+            cands = [fixed[b]] if fixed else grid
+            for npb in cands:
+                if len(m) == 0:
+                    band_np[b] = npb
+                    break
+                ids, _, _, off = index.search(sq[m], sk[m], npb)
+                rec = float(recall_each(ids, off, gt[m], sk[m]).mean())
+                log(f"band {b} ({len(m)} requests, k {int(edges[b])}-{int(edges[b + 1]) - 1}) nprobe {npb}: "
+                    f"recall {rec:.4f}")
+                band_np[b], band_rec[b] = npb, rec
+                if rec >= args.target_recall:
+                    break
+        counts = np.bincount(sb, minlength=4)
+        rec_all = float(sum(band_rec[b] * counts[b] for b in range(4) if band_rec[b] is not None) / max(1, R))
+    elif len(fixed) == 4:
+        band_np, rec_all = fixed, None
+    else:
+        raise SystemExit("--recall-queries 0 needs --nprobe with four values (one per k band)")
+    log(f"nprobe per band {band_np}")
+
+    t_arr, qi, ks = st_t, st_q, st_k.astype(np.int32)
+    if seconds < 1.0:
+        keep = t_arr < seconds
+        t_arr, qi, ks = t_arr[keep], qi[keep], ks[keep]
+    npr = np.array(band_np, np.int32)[band_of(ks)]
+    n = len(t_arr)
+    srv = index.server(mem_budget=args.serve_budget, max_slots=args.serve_slots, lanes=args.serve_lanes)
+
+    def closed_loop(count):
+        j = np.arange(count) % n
+        t = time.perf_counter()
+        tk = [srv.submit(pool[qi[i]], int(ks[i]), int(npr[i])) for i in j]
+        for tt in tk:
+            assert srv.wait(tt, 600000) is not None
+        return time.perf_counter() - t
+
+    closed_loop(min(args.serve_warmup, n))
+    capacity = None
+    if args.capacity_requests:
+        el = closed_loop(args.capacity_requests)
+        st = srv.stats()
+        capacity = {"qps": round(args.capacity_requests / el, 1), "requests": args.capacity_requests,
+                    "what": "all requests submitted at once, closed loop"}
+        log(f"capacity {capacity['qps']} QPS")
+    base_stats = srv.stats()
+
+    # ---- open loop: Poisson arrivals ------------------------------------------
+    q_tk = queue.Queue()
+    t_sub = np.zeros(n)
+    lag = np.zeros(n)
+
+    def producer():
+        # sleeps (never spins holding the interpreter lock) until each arrival
+        base = time.perf_counter()
+        q_tk.put(base)
+        for i in range(n):
+            target = base + t_arr[i]
+            dt = target - time.perf_counter()
+            if dt > 0:
+                time.sleep(dt)
+            t_sub[i] = time.perf_counter()
+            q_tk.put(srv.submit(pool[qi[i]], int(ks[i]), int(npr[i])))
+            lag[i] = t_sub[i] - target
+
+    switch = sys.getswitchinterval()
+    sys.setswitchinterval(1e-4)
+    bbc.stage_times(reset=True)
+    bbc.stage_timing(True)
+    th = threading.Thread(target=producer)
+    th.start()
+    base = q_tk.get()
+    infos = []
+    for i in range(n):
+        r = srv.wait(q_tk.get(), 600000)
+        assert r is not None
+        infos.append(r[2])
+        if (i + 1) % 10000 == 0:
+            log(f"served {i + 1}/{n}")
+    th.join()
+    sys.setswitchinterval(switch)
+    bbc.stage_timing(False)
+    stages = bbc.stage_times(reset=True)
+    st = srv.stats()
+    srv.free()
+    srv_ms = np.array([f["latency_ns"] for f in infos]) / 1e6
+    lat_ms = lag * 1e3 + srv_ms  # from the scheduled arrival
+    done = t_sub + srv_ms / 1e3
+    wall = float(done.max() - base)
+    served = n / wall
+    S = int(sum(f["n_scanned"] for f in infos))
+    nv = int(sum(f["n_reranked"] for f in infos))
+    bsz = np.array([f["batch_size"] for f in infos])
+    row_bytes = (2 if x.dtype == np.float16 else 4) * w.d
+    algo = {"scan": S * (w.d // 8 + 16), "rerank": nv * (row_bytes + 4)}
+    names = {"scan": "rabitq_scan_kernel (bounds of every scanned object)",
+             "rerank": "rabitq_walk_kernel (bounded re-rank)"}
+    entries = {}
+    for name in algo:
+        sg = stages[name]
+        if sg["launches"] == 0:
+            continue
+        avg_ms = sg["ms"] / sg["launches"]
+        bpl = algo[name] / sg["launches"]
+        gbs = bpl / (avg_ms * 1e-3) / 1e9
+        entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                         "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bpl),
+                         "launches": sg["launches"]}
+    dominant = max(entries, key=lambda s_: stages[s_]["ms"])
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        oix = dict(kind="rabitq", n=w.n, d=w.d, nlist=w.nlist, metric=metric,
+                   centroids=index.get(bbc.FIELD_CENTROIDS), rot_centroids=index.get(bbc.FIELD_ROT_CENTROIDS),
+                   P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
+                   codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
+                   base=np.ascontiguousarray(x, dtype=np.float32))
+        done_n, t_cpu = 0, 0.0
+        per_call = max(8, oracle.num_threads())
+        while t_cpu < args.cpu_seconds and done_n < n:
+            j = np.arange(done_n, min(n, done_n + per_call))
+            t1 = time.perf_counter()
+            oracle.search_rabitq(oix, pool[qi[j]], ks[j], npr[j])
+            t_cpu += time.perf_counter() - t1
+            done_n += len(j)
+        cpu = {"value": round(done_n / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"the first {done_n} requests of the stream (their k and nprobe), {per_call} per oracle call, "
+                         f"over the index arrays of the GPU build; {t_cpu:.1f}s of CPU work"}
+    res = {
+        "metric": f"served QPS at recall@k>={args.target_recall} under Poisson arrivals at {rate:g}/s, "
+                  f"k log-uniform in [{kmin}, {kmax}]; p50/p99 latency",
+        "value": round(served, 1), "unit": "queries/s", "n_gpus": 1, "steps": n,
+        "warmup": min(args.serve_warmup, n), "ms_per_step": round(wall / n * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "quant": "rabitq",
+                   "metric": w.metric, "storage": str(x.dtype), "pool": pool_n, "arrival_qps": rate,
+                   "seconds": seconds, "k_range": [kmin, kmax], "nprobe_by_k_band": band_np,
+                   "k_band_edges": [int(e) for e in edges]},
+        "recall": None if rec_all is None else round(rec_all, 4),
+        "recall_by_band": [None if r is None else round(r, 4) for r in band_rec],
+        "latency_ms": {"p50": round(float(np.percentile(lat_ms, 50)), 3),
+                       "p90": round(float(np.percentile(lat_ms, 90)), 3),
+                       "p99": round(float(np.percentile(lat_ms, 99)), 3),
+                       "max": round(float(lat_ms.max()), 3), "mean": round(float(lat_ms.mean()), 3),
+                       "what": "per request, scheduled arrival to completion (submission lag, queueing, "
+                               "batch, query upload and result download included)"},
+        "server_latency_ms": {"p50": round(float(np.percentile(srv_ms, 50)), 3),
+                              "p99": round(float(np.percentile(srv_ms, 99)), 3),
+                              "what": "submission to completion, as seen by the server"},
+        "offered_qps": rate,
+        "capacity": capacity,
+        "submit_lag_ms": {"p99": round(float(np.percentile(lag, 99)) * 1e3, 3),
+                          "max": round(float(lag.max()) * 1e3, 3)},
+        "server": {"budget_bytes": args.serve_budget, "max_slots": args.serve_slots, "lanes": args.serve_lanes,
+                   "batches": st["batches"] - base_stats["batches"], "mean_batch": round(float(bsz.mean()), 2),
+                   "max_batch": int(bsz.max()), "max_inflight": st["max_inflight"]},
+        "stage_ms_per_request": {s_: round(v["ms"] / n, 5) for s_, v in stages.items()},
+        "sizes": {"S_mean": S / n, "reranked_mean": nv / n},
+        "roofline": entries[dominant],
+        "roofline_other_kernels": {k_: e for k_, e in entries.items() if k_ != dominant},
         "cpu_baseline": cpu,
         "build_s": round(build_s, 2),
     }

@@ -209,10 +209,14 @@ void bbc_index_free(bbc_index* ix);
  * bracketed by HIP events recorded on the search stream; bbc_stage_times
  * waits for them and returns, per stage, the summed milliseconds and the
  * launch count since the last reset (stages: 0 probe (coarse GEMM and
- * select), 1 pair sort and scan of the codebook sample lists, 2 scan of the
- * remaining lists through the relaxed threshold (one kernel launch per
- * search), 3 collector (codebook and bucket collection), 4 re-rank, 5 final
- * top-k). */
+ * select), 1 pair sort and scan of the codebook sample lists (RaBitQ: the
+ * rotation of the queries), 2 scan of the remaining lists through the
+ * relaxed threshold (RaBitQ: the bounds of every scanned object; one kernel
+ * launch per search), 3 collector (codebook and bucket collection; RaBitQ
+ * in the wide form: the lower-bound bins of the candidates), 4 re-rank
+ * (RaBitQ: the bounded walk, after the exact keys of all candidates in the
+ * wide form), 5 final top-k).  A RaBitQ batch of at most as many queries as
+ * the device has compute units takes the wide form. */
 int32_t bbc_stage_timing(int32_t enable);
 int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset);
 
@@ -254,8 +258,7 @@ void bbc_plan_free(bbc_plan* plan);
  *   alone exceeds the budget, BBC_EINVAL for bad k / nprobe or non-finite
  *   values.
  * bbc_server_poll: if the ticket's result is ready, copies it to the host
- *   arrays ids [k] int64 and dists [k] float32, count (results found) and
- *   latency_ns (submission to completion, as seen by the worker), any of
+ *   arrays ids [k] int64 and dists [k] float32 and fills `info`, any of
  *   them NULL to skip, hands the ticket back and returns the request's
  *   status; BBC_EBUSY if it is not ready yet; BBC_EINVAL for a ticket never
  *   issued or already collected.
@@ -265,13 +268,20 @@ void bbc_plan_free(bbc_plan* plan);
  * bbc_server_destroy: answers every request already submitted, stops the
  *   worker and frees the server (uncollected results are dropped). */
 typedef struct bbc_server bbc_server;
+typedef struct {
+  int32_t count;       /* results found (<= k; the rest of ids is -1) */
+  int32_t status;      /* BBC_OK or the batch's error */
+  int64_t latency_ns;  /* submission to completion, as seen by the worker */
+  int64_t n_scanned;   /* codes scanned (S) */
+  int64_t n_reranked;  /* exact distances computed: K_c (PQ), objects the bounded walk visited (RaBitQ) */
+  int64_t batch_size;  /* requests in the batch that answered this one */
+} bbc_request_info;
 int32_t bbc_server_create(bbc_index* ix, const bbc_search_params* params, int64_t mem_budget_bytes,
                           int32_t max_slots, int32_t lanes, bbc_server** out);
 int32_t bbc_server_submit(bbc_server* srv, const float* query, int32_t k, int32_t nprobe, uint64_t* ticket);
-int32_t bbc_server_poll(bbc_server* srv, uint64_t ticket, int64_t* ids, float* dists, int32_t* count,
-                        int64_t* latency_ns);
+int32_t bbc_server_poll(bbc_server* srv, uint64_t ticket, int64_t* ids, float* dists, bbc_request_info* info);
 int32_t bbc_server_wait(bbc_server* srv, uint64_t ticket, int32_t timeout_ms, int64_t* ids, float* dists,
-                        int32_t* count, int64_t* latency_ns);
+                        bbc_request_info* info);
 int32_t bbc_server_stats(bbc_server* srv, int64_t* batches, int64_t* requests, int64_t* max_batch,
                          int64_t* max_inflight, int64_t* pending);
 void bbc_server_destroy(bbc_server* srv);

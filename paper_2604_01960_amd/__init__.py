@@ -51,6 +51,11 @@ class BuildParams(C.Structure):
                 ("rotation", C.c_void_p), ("rabitq_eps0", C.c_float), ("storage", C.c_int32)]
 
 
+class RequestInfo(C.Structure):
+    _fields_ = [("count", C.c_int32), ("status", C.c_int32), ("latency_ns", C.c_int64), ("n_scanned", C.c_int64),
+                ("n_reranked", C.c_int64), ("batch_size", C.c_int64)]
+
+
 class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
@@ -115,9 +120,9 @@ def load(path: Optional[str] = None):
     L.bbc_server_submit.restype = i32
     L.bbc_server_submit.argtypes = [vp, vp, i32, i32, C.POINTER(C.c_uint64)]
     L.bbc_server_poll.restype = i32
-    L.bbc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, vp, vp]
+    L.bbc_server_poll.argtypes = [vp, C.c_uint64, vp, vp, C.POINTER(RequestInfo)]
     L.bbc_server_wait.restype = i32
-    L.bbc_server_wait.argtypes = [vp, C.c_uint64, i32, vp, vp, vp, vp]
+    L.bbc_server_wait.argtypes = [vp, C.c_uint64, i32, vp, vp, C.POINTER(RequestInfo)]
     L.bbc_server_stats.restype = i32
     L.bbc_server_stats.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bbc_server_destroy.restype = None
@@ -462,7 +467,8 @@ class Plan:
 class Server:
     """Single requests in, device batches inside (bbc_server_*).  submit()
     returns a ticket; poll() returns None while the result is not ready, else
-    (ids, dists, count, latency_ns); wait() blocks up to a timeout."""
+    (ids, dists, info) with info a dict of bbc_request_info; wait() blocks up
+    to a timeout."""
 
     def __init__(self, handle: int, index: "Index"):
         self._h = C.c_void_p(handle)
@@ -485,17 +491,17 @@ class Server:
             raise BBCError(EINVAL, "unknown ticket")
         ids = np.empty(k, np.int64)
         dists = np.empty(k, np.float32)
-        cnt, lat = C.c_int32(), C.c_int64()
+        info = RequestInfo()
         if timeout_ms is None:
-            rc = load().bbc_server_poll(self._h, int(ticket), _ptr(ids), _ptr(dists), C.byref(cnt), C.byref(lat))
+            rc = load().bbc_server_poll(self._h, int(ticket), _ptr(ids), _ptr(dists), C.byref(info))
         else:
             rc = load().bbc_server_wait(self._h, int(ticket), int(timeout_ms), _ptr(ids), _ptr(dists),
-                                        C.byref(cnt), C.byref(lat))
+                                        C.byref(info))
         if rc == EBUSY:
             return None
         del self._k[int(ticket)]
         _check(rc)
-        return ids, dists, cnt.value, lat.value
+        return ids, dists, {f: getattr(info, f) for f, _ in RequestInfo._fields_}
 
     def poll(self, ticket: int):
         return self._take(ticket, None)

@@ -167,6 +167,7 @@ struct bbc_index {
   int num_cu = 256;
   int nxcd = 8;
   int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
+  int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -254,6 +255,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_SCAN_VARIANT")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 2) ix->scan_variant = x;
+  }
+  if (const char* sv = std::getenv("BBC_WALK_FORM")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 2) ix->walk_form = x;
   }
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
   return BBC_OK;
@@ -569,6 +574,7 @@ struct SearchCtx {
   bool size_only = false;
   size_t ws_bytes = 0;
   char* ws = nullptr;
+  int64_t* work_out = nullptr;  // [2][nq]: codes scanned, exact distances computed
   bool capture = false;
   hipGraph_t graph = nullptr;
 };
@@ -608,6 +614,11 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const size_t L_key = tracing ? pl.add(4 * nkeys) : 0;
   const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys), L_z = pl.add(16 * nkeys);
   const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
+  // the wide re-rank form when the batch alone leaves compute units idle
+  // with one block per query
+  const bool wide = ix->walk_form == 2 || (ix->walk_form == 0 && nq <= ix->num_cu);
+  size_t L_cpos = 0, L_wbins = 0, L_wst = 0;
+  if (wide) { L_cpos = pl.add(4 * nkeys); L_wbins = pl.add(4 * 2048 * nq); L_wst = pl.add(16 * nq); }
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
   if (ctx && ctx->size_only) {
@@ -701,6 +712,17 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   wa.n_visited = reinterpret_cast<int64_t*>(A + L_nv);
   wa.zbuf = reinterpret_cast<uint64_t*>(A + L_z);
   wa.q = dq; wa.vectors = ix->vectors; wa.fp16 = ix->fp16; wa.D = d; wa.metric = ix->metric;
+  wa.wide = wide ? 1 : 0;
+  wa.max_c = max_cap;
+  if (wide) {
+    wa.cpos = reinterpret_cast<int32_t*>(A + L_cpos);
+    wa.wbins = reinterpret_cast<uint32_t*>(A + L_wbins);
+    wa.wstate = reinterpret_cast<uint32_t*>(A + L_wst);
+  }
+  if (wide) {
+    StageScope st(s, 3);
+    HIP_TRY(bbc::launch_rabitq_walk_prep(wa, s));
+  }
   {
     StageScope st(s, 4);
     HIP_TRY(bbc::launch_rabitq_walk(wa, s));
@@ -756,6 +778,10 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     if ((rc = ragged(tr->est_keys, L_key))) return rc;
     if ((rc = ragged(tr->est_lb, L_lb))) return rc;
     if ((rc = ragged(tr->est_ub, L_ub))) return rc;
+  }
+  if (ctx && ctx->work_out) {
+    HIP_TRY(hipMemcpyAsync(ctx->work_out, A + L_ns, 8 * nq, hipMemcpyDefault, s));
+    HIP_TRY(hipMemcpyAsync(ctx->work_out + nq, A + L_nv, 8 * nq, hipMemcpyDefault, s));
   }
   if (ctx && ctx->capture) {
     t_capturing = false;
@@ -1108,6 +1134,10 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       }
     }
   }
+  if (ctx && ctx->work_out) {
+    HIP_TRY(hipMemcpyAsync(ctx->work_out, A + L.n_scanned, 8 * nq, hipMemcpyDefault, s));
+    HIP_TRY(hipMemcpyAsync(ctx->work_out + nq, A + L.n_cand, 8 * nq, hipMemcpyDefault, s));
+  }
   if (ctx && ctx->capture) {
     t_capturing = false;
     HIP_TRY(hipStreamEndCapture(s, &ctx->graph));
@@ -1122,7 +1152,8 @@ namespace bbc {
 
 int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
                             const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
-                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes) {
+                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes,
+                            int64_t* work_out) {
   if (!p || !ws_bytes) return fail(BBC_EINVAL, "NULL argument");
   if (!p->device_io) return fail(BBC_EINVAL, "a workspace search needs device I/O");
   // a sizing pass reads no query: any non-null pointer passes validation
@@ -1131,6 +1162,7 @@ int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, con
   SearchCtx ctx;
   ctx.size_only = ws == nullptr;
   ctx.ws = ws;
+  ctx.work_out = work_out;
   const int32_t rc = run_search(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, nullptr, &ctx);
   if (ctx.size_only) *ws_bytes = ctx.ws_bytes;
   return rc;

@@ -201,6 +201,29 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t bin, bool
   else if (valid && bin != lb) atomicAdd(&hist[bin], 1u);
 }
 
+// i = threadIdx.x, threadIdx.x + NT, ... < n over the block: the values
+// load(i) of U consecutive strides are loaded before any is used (U loads in
+// flight per thread), then use(i, valid, v) runs for each; every lane calls
+// use() the same block-uniform number of times (valid = false past n), so
+// use() may take wave-wide collectives.
+template <int NT, int U, typename Load, typename Use>
+__device__ __forceinline__ void block_for_batched(int64_t n, Load load, Use use) {
+  using V = decltype(load((int64_t)0));
+  for (int64_t base = 0; base < n; base += (int64_t)NT * U) {
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+      v[u] = i < n ? load(i) : V{};
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+      use(i, i < n, v[u]);
+    }
+  }
+}
+
 // Radix select over a block: value of the element of rank r (0-based,
 // ascending) among n 32-bit values produced by get(i).  hist: 256 LDS words;
 // bc: 4 LDS words for broadcast, 8-byte aligned.
@@ -210,11 +233,9 @@ __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int64_t base = 0; base < n; base += NT) {  // wave-uniform trip count
-      const int64_t i = base + threadIdx.x;
-      const uint32_t v = i < n ? get(i) : 0u;
-      wave_hist_add(hist, (v >> shift) & 255u, i < n && (v & mask) == prefix);
-    }
+    block_for_batched<NT, 4>(n, get, [&](int64_t, bool valid, uint32_t v) {
+      wave_hist_add(hist, (v >> shift) & 255u, valid && (v & mask) == prefix);
+    });
     __syncthreads();
     if (threadIdx.x < 64) wave_find_rank(hist, 256, r, &bc[0], reinterpret_cast<int64_t*>(bc + 2));
     __syncthreads();
@@ -230,15 +251,20 @@ __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t
 template <int NT, typename Get>
 __device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
   uint64_t prefix = 0, mask = 0;
+  struct KV { uint64_t v; bool ok; };
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    for (int64_t base = 0; base < n; base += NT) {  // wave-uniform trip count
-      const int64_t i = base + threadIdx.x;
-      uint64_t v = 0;
-      const bool ok = i < n && get(i, v) && (v & mask) == prefix;
-      wave_hist_add(hist, (uint32_t)((v >> shift) & 255u), ok);
-    }
+    block_for_batched<NT, 4>(
+        n,
+        [&](int64_t i) {
+          KV e{0, false};
+          e.ok = get(i, e.v);
+          return e;
+        },
+        [&](int64_t, bool valid, KV e) {
+          wave_hist_add(hist, (uint32_t)((e.v >> shift) & 255u), valid && e.ok && (e.v & mask) == prefix);
+        });
     __syncthreads();
     if (threadIdx.x < 64) wave_find_rank(hist, 256, r, &bc[0], reinterpret_cast<int64_t*>(bc + 2));
     __syncthreads();

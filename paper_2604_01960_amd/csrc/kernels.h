@@ -16,10 +16,13 @@ int32_t set_error(int32_t code, const std::string& msg);
 // A search with device I/O whose scratch is the caller's `ws` (the index
 // arena is not touched, so calls on different streams with different
 // workspaces may overlap on the device).  With ws == nullptr only *ws_bytes
-// is set: the bytes the call needs.
+// is set: the bytes the call needs.  work_out (device or pinned host, may be
+// NULL) receives [2][nq] int64 on the search stream: codes scanned, then
+// exact distances computed (K_c, or the objects the bounded walk visited).
 int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
                             const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
-                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes);
+                            int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes,
+                            int64_t* work_out = nullptr);
 
 int32_t build_index_pq(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
                        bbc_index** out);
@@ -160,7 +163,17 @@ struct RabitqWalkArgs {
   int64_t* n_cand; int64_t* n_visited;
   uint64_t* zbuf;            // [2 * sum S] scratch (the k best so far, ping-pong)
   const float* q; const void* vectors; int fp16; int D; int metric;
+  // wide form (small batches): the exact keys of all of C = {lb <= U} are
+  // computed first by a grid over the device, then the walk reads them
+  int wide;
+  int64_t max_c;             // upper bound of |C| over the queries (largest S)
+  int32_t* cpos;             // [sum S] list positions of C in cbuf order
+  uint32_t* wbins;           // [nq][2048] bin ends
+  uint32_t* wstate;          // [nq][4] U, lmin, shift, |C|
 };
+// wide form: the bins of C (a no-op otherwise); then the exact keys of C
+// (wide form) and the walk
+hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s);
 hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s);
 
 constexpr int FINAL_STATIC_LDS = 21000;  // bytes of static LDS of the final top-k kernel (upper bound)

@@ -329,6 +329,7 @@ constexpr int WK_NB = 2048;       // lb bins
 constexpr int WK_RANKCAP = 2048;  // probe ranks in LDS
 constexpr int WK_CHUNK = 1024;    // items per step of the exact walk (and per bin-walk round)
 constexpr int WK_QCAP = 2048;     // objects above the k-th exact key resolved in LDS
+constexpr int WK_U = 2;           // loads in flight per thread in the block-wide passes
 
 template <typename T> __device__ __forceinline__ float4 ld4(const T* p, int64_t chunk);
 template <> __device__ __forceinline__ float4 ld4<float>(const float* p, int64_t chunk) {
@@ -342,8 +343,8 @@ template <> __device__ __forceinline__ float4 ld4<__half>(const __half* p, int64
 }
 
 // Exact keys (canonical L2, or -canonical IP) of up to four list positions
-// (the first `cnt`), one wave; the query's chunks (lane l: chunks l, l+64,
-// ...) are held in registers by the caller (d <= 1024).
+// (the first `cnt`), one wave; qc is the query as float4 chunks in LDS
+// (lane l takes chunks l, l+64, ...; d <= 1024).
 template <typename T>
 __device__ void exact_keys4(const RabitqWalkArgs& a, const float4* qc, const int64_t* pos, int cnt, float* e) {
   const int lane = threadIdx.x & 63;
@@ -363,7 +364,8 @@ __device__ void exact_keys4(const RabitqWalkArgs& a, const float4* qc, const int
     float acc = 0.0f;
 #pragma unroll
     for (int st = 0; st < 4; ++st)
-      if (lane + 64 * st < nchunk) acc = a.metric == 0 ? chunk_l2(qc[st], x[r][st], acc) : chunk_ip(qc[st], x[r][st], acc);
+      if (lane + 64 * st < nchunk)
+        acc = a.metric == 0 ? chunk_l2(qc[64 * st], x[r][st], acc) : chunk_ip(qc[64 * st], x[r][st], acc);
     acc = canon_reduce64(acc);
     e[r] = a.metric == 0 ? acc : -acc;
   }
@@ -388,6 +390,137 @@ __device__ void lds_bitonic_sort_kv(uint64_t* key, uint64_t* val, int n) {
     }
   }
   __syncthreads();
+}
+
+// The lb bins of a query's candidate set C = {lb <= U}, U = the k-th smallest
+// ub (every object when S <= k): C's slots grouped by bin in cbuf (and their
+// list positions in cpos when it is not NULL), hist[b] = the end of bin b.
+struct WalkBins {
+  uint32_t U, lmin;
+  int shift;
+  int64_t nC;
+};
+
+template <int NT>
+__device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float* ub, uint32_t* cbuf, int32_t* cpos,
+                              const SlotMap& sm, uint32_t* hist, uint32_t* rhist, uint32_t* bc) {
+  const int lane = threadIdx.x & 63;
+  WalkBins w;
+  w.U = 0xffffffffu;
+  if (S > k) w.U = block_radix_select32<NT>([&](int64_t i) { return key_bits(ub[i]); }, S, k - 1, rhist, bc);
+  const uint32_t U = w.U;
+  // C's smallest and largest lb image
+  if (threadIdx.x == 0) { bc[4] = 0xffffffffu; bc[5] = 0u; bc[6] = 0u; }
+  __syncthreads();
+  auto lb_bits = [&](int64_t i) { return key_bits(lb[i]); };
+  {
+    uint32_t mn = 0xffffffffu, mx = 0u, cnt = 0;
+    block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
+      if (valid && b <= U) { mn = min(mn, b); mx = max(mx, b); ++cnt; }
+    });
+    for (int off = 32; off >= 1; off >>= 1) {
+      mn = min(mn, __shfl_xor(mn, off));
+      mx = max(mx, __shfl_xor(mx, off));
+      cnt += __shfl_xor(cnt, off);
+    }
+    if (lane == 0) { atomicMin(&bc[4], mn); atomicMax(&bc[5], mx); atomicAdd(&bc[6], cnt); }
+  }
+  for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = 0;
+  __syncthreads();
+  w.lmin = bc[4];
+  const uint32_t lmin = w.lmin;
+  const uint32_t span = bc[5] - lmin;
+  w.nC = bc[6];
+  int shift = 0;
+  while ((span >> shift) >= (uint32_t)WK_NB) ++shift;
+  w.shift = shift;
+  block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
+    const bool in = valid && b <= U;
+    wave_hist_add(hist, in ? (b - lmin) >> shift : 0u, in);
+  });
+  __syncthreads();
+  if (threadIdx.x < 64) {  // exclusive prefix, in place
+    uint32_t carry = 0;
+    for (int base = 0; base < WK_NB; base += 64) {
+      const uint32_t v = hist[base + lane];
+      const uint32_t incl = wave_incl_scan(v);
+      hist[base + lane] = carry + incl - v;
+      carry += __shfl(incl, 63);
+    }
+  }
+  __syncthreads();
+  block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
+    if (valid && b <= U) {
+      const uint32_t j = atomicAdd(&hist[(b - lmin) >> shift], 1u);
+      cbuf[j] = (uint32_t)i;
+      if (cpos) cpos[j] = (int32_t)sm.pos(i);
+    }
+  });
+  __syncthreads();
+  return w;
+}
+
+// Wide form, step 1 (block per query): the bins of C, kept in global memory
+// (bin ends in wbins, U / lmin / shift / |C| in wstate) with C's list
+// positions, for the exact keys of all of C computed by a grid over the
+// whole device and the walk over them.
+__global__ __launch_bounds__(1024) void rabitq_walk_prep_kernel(RabitqWalkArgs a) {
+  constexpr int NT = 1024;
+  __shared__ int32_t s_rbeg[WK_RANKCAP];
+  __shared__ int32_t s_lbeg[WK_RANKCAP];
+  __shared__ uint32_t hist[WK_NB];
+  __shared__ uint32_t rhist[256];
+  __shared__ __align__(8) uint32_t bc[16];
+  const int64_t qi = blockIdx.x;
+  const int64_t S = a.n_scanned[qi];
+  uint32_t* st = a.wstate + 4 * qi;
+  if (S == 0) {
+    if (threadIdx.x == 0) { st[0] = 0; st[1] = 0; st[2] = 0; st[3] = 0; }
+    return;
+  }
+  const int64_t po = a.probe_off[qi];
+  const SlotMap sm = slot_map_load<NT, WK_RANKCAP>(a.rank_off + po, a.probe_lists + po, a.list_off, a.nprobe[qi],
+                                                   s_rbeg, s_lbeg);
+  const WalkBins w = walk_bins<NT>(S, a.k[qi], a.lb + a.key_off[qi], a.ub + a.key_off[qi], a.cbuf + a.key_off[qi],
+                                   a.cpos + a.key_off[qi], sm, hist, rhist, bc);
+  for (int i = threadIdx.x; i < WK_NB; i += NT) a.wbins[qi * WK_NB + i] = hist[i];
+  if (threadIdx.x == 0) { st[0] = w.U; st[1] = w.lmin; st[2] = (uint32_t)w.shift; st[3] = (uint32_t)w.nC; }
+}
+
+// Wide form, step 2: exact (key, id) of every object of C, in cbuf order,
+// EX_ROWS objects per block over (chunk, query).
+constexpr int EX_ROWS = 64;
+template <typename T>
+__global__ __launch_bounds__(256) void rabitq_exact_kernel(RabitqWalkArgs a) {
+  const int64_t qi = blockIdx.y;
+  const int64_t nC = a.wstate[4 * qi + 3];
+  const int64_t i0 = (int64_t)blockIdx.x * EX_ROWS;
+  if (i0 >= nC) return;  // block-uniform
+  __shared__ float4 s_qc[256];
+  const float* q = a.q + qi * a.D;
+  for (int c = threadIdx.x; c < 256; c += 256)
+    s_qc[c] = c < (a.D >> 2) ? reinterpret_cast<const float4*>(q)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int32_t* cpos = a.cpos + a.key_off[qi];
+  uint64_t* pbuf = a.cand_packed + a.cand_off[qi];
+  const int64_t i1 = min(nC, i0 + EX_ROWS);
+  for (int64_t i = i0 + 4 * wv; i < i1; i += 16) {
+    const int cnt = (int)min((int64_t)4, i1 - i);
+    int64_t pos[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pos[r] = cpos[i + (r < cnt ? r : 0)];
+    float e[4];
+    exact_keys4<T>(a, s_qc + lane, pos, cnt, e);
+    if (lane < cnt) {
+      float ev = e[0];
+      int64_t pv = pos[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r)
+        if (lane == r) { ev = e[r]; pv = pos[r]; }
+      pbuf[i + lane] = pack_key_id(ev, (uint32_t)a.list_ids[pv]);
+    }
+  }
 }
 
 template <typename T>
@@ -418,64 +551,28 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   uint32_t* cbuf = a.cbuf + a.key_off[qi];
   uint64_t* pbuf = a.cand_packed + a.cand_off[qi];
   const float* q = a.q + qi * a.D;
-  float4 qc[4];
-#pragma unroll
-  for (int st = 0; st < 4; ++st) {
-    const int c = lane + 64 * st;
-    qc[st] = c < (a.D >> 2) ? reinterpret_cast<const float4*>(q)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
-  }
+  __shared__ float4 s_qc[256];  // the query, lane l's chunks at l, l + 64, ...
+  for (int c = threadIdx.x; c < 256; c += NT)
+    s_qc[c] = c < (a.D >> 2) ? reinterpret_cast<const float4*>(q)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  const float4* qc = s_qc + lane;
   const int64_t capq = a.key_off[qi + 1] - a.key_off[qi];
   uint64_t* zA = a.zbuf + 2 * a.key_off[qi];
   uint64_t* zB = zA + capq;
 
-  // U = k-th smallest ub (all objects qualify when S <= k)
-  uint32_t U = 0xffffffffu;
-  if (S > k) U = block_radix_select32<NT>([&](int64_t i) { return key_bits(ub[i]); }, S, k - 1, rhist, bc);
-  // C = {lb <= U}: its smallest and largest lb image
-  if (threadIdx.x == 0) { bc[4] = 0xffffffffu; bc[5] = 0u; bc[6] = 0u; }
-  __syncthreads();
-  {
-    uint32_t mn = 0xffffffffu, mx = 0u, cnt = 0;
-    for (int64_t i = threadIdx.x; i < S; i += NT) {
-      const uint32_t b = key_bits(lb[i]);
-      if (b <= U) { mn = min(mn, b); mx = max(mx, b); ++cnt; }
-    }
-    for (int off = 32; off >= 1; off >>= 1) {
-      mn = min(mn, __shfl_xor(mn, off));
-      mx = max(mx, __shfl_xor(mx, off));
-      cnt += __shfl_xor(cnt, off);
-    }
-    if (lane == 0) { atomicMin(&bc[4], mn); atomicMax(&bc[5], mx); atomicAdd(&bc[6], cnt); }
+  // the bins of C: computed here, or (wide form) read back with the exact
+  // keys of all of C already in pbuf
+  WalkBins w;
+  if (a.wide) {
+    const uint32_t* st = a.wstate + 4 * qi;
+    w.U = st[0]; w.lmin = st[1]; w.shift = (int)st[2]; w.nC = st[3];
+    for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = a.wbins[qi * WK_NB + i];
+    __syncthreads();
+  } else {
+    w = walk_bins<NT>(S, k, lb, ub, cbuf, nullptr, sm, hist, rhist, bc);
   }
-  for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = 0;
-  __syncthreads();
-  const uint32_t lmin = bc[4];
-  const uint32_t span = bc[5] - lmin;
-  const int64_t nC = bc[6];
-  int shift = 0;
-  while ((span >> shift) >= (uint32_t)WK_NB) ++shift;
-  for (int64_t base = 0; base < S; base += NT) {  // wave-uniform trip count
-    const int64_t i = base + threadIdx.x;
-    const uint32_t b = i < S ? key_bits(lb[i]) : 0xffffffffu;
-    const bool in = i < S && b <= U;
-    wave_hist_add(hist, in ? (b - lmin) >> shift : 0u, in);
-  }
-  __syncthreads();
-  if (threadIdx.x < 64) {  // exclusive prefix, in place
-    uint32_t carry = 0;
-    for (int base = 0; base < WK_NB; base += 64) {
-      const uint32_t v = hist[base + lane];
-      const uint32_t incl = wave_incl_scan(v);
-      hist[base + lane] = carry + incl - v;
-      carry += __shfl(incl, 63);
-    }
-  }
-  __syncthreads();
-  for (int64_t i = threadIdx.x; i < S; i += NT) {
-    const uint32_t b = key_bits(lb[i]);
-    if (b <= U) cbuf[atomicAdd(&hist[(b - lmin) >> shift], 1u)] = (uint32_t)i;
-  }
-  __syncthreads();
+  const uint32_t U = w.U, lmin = w.lmin;
+  const int shift = w.shift;
+  const int64_t nC = w.nC;
   // hist[b] is now the end of bin b in cbuf.  Walk whole bins in order.
   auto lower_edge = [&](int b) -> uint64_t { return (uint64_t)lmin + ((uint64_t)b << shift); };
   // exact keys of cbuf[i0, i1) into pbuf, four rows per wave
@@ -511,16 +608,15 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
     if (b < WK_NB) ++b;  // the bin that reaches the target
     const int64_t np_ = b > 0 ? (int64_t)hist[b - 1] : 0;
     b_end = b;
-    rerank_range(p, np_);
+    if (!a.wide) rerank_range(p, np_);
     if (threadIdx.x == 0) bc[13] = 0;
     __syncthreads();
-    for (int64_t base = p; base < np_; base += NT) {  // wave-uniform trip count
-      const int64_t i = base + threadIdx.x;
-      const uint64_t v = i < np_ ? pbuf[i] : ~0ull;
-      const bool take = i < np_ && (p < k || (uint32_t)(v >> 32) <= Eimg);
-      const uint32_t slot = wave_slot(take, &bc[13]);
-      if (take) zA[nz + slot] = v;
-    }
+    block_for_batched<NT, WK_U>(np_ - p, [&](int64_t j) { return pbuf[p + j]; },
+                             [&](int64_t, bool valid, uint64_t v) {
+                               const bool take = valid && (p < k || (uint32_t)(v >> 32) <= Eimg);
+                               const uint32_t slot = wave_slot(take, &bc[13]);
+                               if (take) zA[nz + slot] = v;
+                             });
     __syncthreads();
     nz += bc[13];
     p = np_;
@@ -528,13 +624,11 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
       Eimg = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
       if (threadIdx.x == 0) bc[13] = 0;
       __syncthreads();
-      for (int64_t base = 0; base < nz; base += NT) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t v = i < nz ? zA[i] : ~0ull;
-        const bool take = i < nz && (uint32_t)(v >> 32) <= Eimg;
+      block_for_batched<NT, WK_U>(nz, [&](int64_t i) { return zA[i]; }, [&](int64_t, bool valid, uint64_t v) {
+        const bool take = valid && (uint32_t)(v >> 32) <= Eimg;
         const uint32_t slot = wave_slot(take, &bc[13]);
         if (take) zB[slot] = v;
-      }
+      });
       __syncthreads();
       nz = bc[13];
       uint64_t* t = zA; zA = zB; zB = t;
@@ -556,10 +650,20 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
     if (exhausted && p < S && E > U) ok = false;
     if (threadIdx.x == 0) { bc[7] = 0; bc[14] = 0; }
     __syncthreads();
-    for (int64_t i = threadIdx.x; i < p; i += NT) {
-      const bool above = key_bits(lb[cbuf[i]]) > E;
-      if (above && (uint32_t)(pbuf[i] >> 32) <= E) bc[7] = 1;  // a possible result object above E
-      if (above) atomicAdd(&bc[14], 1u);
+    // (lb image, exact image) of processed object i
+    auto lb_ex = [&](int64_t i) { return make_uint2(key_bits(lb[cbuf[i]]), (uint32_t)(pbuf[i] >> 32)); };
+    {
+      uint32_t nab = 0;
+      bool member = false;
+      block_for_batched<NT, WK_U>(p, lb_ex, [&](int64_t, bool valid, uint2 e) {
+        if (valid && e.x > E) {
+          ++nab;
+          member |= e.y <= E;  // a possible result object above E
+        }
+      });
+      for (int off = 32; off >= 1; off >>= 1) nab += __shfl_xor(nab, off);
+      if (lane == 0 && nab) atomicAdd(&bc[14], nab);
+      if (member) bc[7] = 1;
     }
     __syncthreads();
     const bool member_above = bc[7] != 0;
@@ -575,13 +679,12 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
             k - 1, rhist, bc);
       if (threadIdx.x == 0) bc[13] = 0;
       __syncthreads();
-      for (int64_t base = 0; base < p; base += NT) {
-        const int64_t i = base + threadIdx.x;
-        const uint64_t v = i < p ? pbuf[i] : ~0ull;
-        const bool take = i < p && key_bits(lb[cbuf[i]]) <= E && (uint32_t)(v >> 32) <= thr0;
-        const uint32_t slot = wave_slot(take, &bc[13]);
-        if (take) zB[slot] = v;
-      }
+      block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+                               [&](int64_t, bool valid, ulonglong2 e) {
+                                 const bool take = valid && e.x <= E && (uint32_t)(e.y >> 32) <= thr0;
+                                 const uint32_t slot = wave_slot(take, &bc[13]);
+                                 if (take) zB[slot] = e.y;
+                               });
       __syncthreads();
       const int64_t nz0 = bc[13];
       const int64_t kz = min(k, n0);  // objects of R that Z0 provides
@@ -591,14 +694,14 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
         // Q sorted in LDS by (lb image, id), with its exact (key, id)
         if (threadIdx.x == 0) bc[9] = 0;
         __syncthreads();
-        for (int64_t i = threadIdx.x; i < p; i += NT) {
-          const uint32_t lbi = key_bits(lb[cbuf[i]]);
-          if (lbi > E) {
-            const uint32_t j = atomicAdd(&bc[9], 1u);
-            chunk_v[j] = ((uint64_t)lbi << 32) | (uint64_t)(uint32_t)pbuf[i];
-            chunk_x[j] = pbuf[i];
-          }
-        }
+        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+                                 [&](int64_t, bool valid, ulonglong2 e) {
+                                   if (valid && e.x > E) {
+                                     const uint32_t j = atomicAdd(&bc[9], 1u);
+                                     chunk_v[j] = (e.x << 32) | (uint64_t)(uint32_t)e.y;
+                                     chunk_x[j] = e.y;
+                                   }
+                                 });
         const int P2 = next_pow2((int)nQ);
         for (int i = (int)nQ + threadIdx.x; i < P2; i += NT) { chunk_v[i] = ~0ull; chunk_x[i] = ~0ull; }
         lds_bitonic_sort_kv<NT>(chunk_v, chunk_x, P2);
@@ -638,18 +741,12 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
       if (lo < nQ) {
         if (threadIdx.x == 0) bc[13] = 0;
         __syncthreads();
-        for (int64_t base = 0; base < p; base += NT) {
-          const int64_t i = base + threadIdx.x;
-          bool take = false;
-          uint64_t v = 0;
-          if (i < p) {
-            v = pbuf[i];
-            const uint64_t kk = ((uint64_t)key_bits(lb[cbuf[i]]) << 32) | (uint64_t)(uint32_t)v;
-            take = kk < cut;
-          }
-          const uint32_t slot = wave_slot(take, &bc[13]);
-          if (take) zB[slot] = v;
-        }
+        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+                                 [&](int64_t, bool valid, ulonglong2 e) {
+                                   const bool take = valid && ((e.x << 32) | (uint64_t)(uint32_t)e.y) < cut;
+                                   const uint32_t slot = wave_slot(take, &bc[13]);
+                                   if (take) zB[slot] = e.y;
+                                 });
         __syncthreads();
         nvis = bc[13];
         for (int64_t i = threadIdx.x; i < nvis; i += NT) pbuf[i] = zB[i];
@@ -742,8 +839,20 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = visited; }
 }
 
+hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s) {
+  if (a.nq <= 0 || !a.wide) return hipSuccess;
+  hipLaunchKernelGGL(rabitq_walk_prep_kernel, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
+  if (a.wide) {
+    if (a.nq > 65535 || a.max_c < 1) return hipErrorInvalidValue;
+    const dim3 g((unsigned)((a.max_c + EX_ROWS - 1) / EX_ROWS), (unsigned)a.nq);
+    if (a.fp16) hipLaunchKernelGGL(rabitq_exact_kernel<__half>, g, dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(rabitq_exact_kernel<float>, g, dim3(256), 0, s, a);
+  }
   if (a.fp16) hipLaunchKernelGGL(rabitq_walk_kernel<__half>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
   else hipLaunchKernelGGL(rabitq_walk_kernel<float>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
   return hipGetLastError();

@@ -45,10 +45,8 @@ struct Req {
 struct Res {
   std::vector<int64_t> ids;
   std::vector<float> dists;
-  int32_t count = 0;
-  int32_t status = BBC_OK;
+  bbc_request_info info{};
   std::string err;
-  int64_t latency_ns = 0;
 };
 
 // One batch in flight: stream, completion event, workspace and I/O buffers
@@ -62,6 +60,7 @@ struct Lane {
   int32_t* dcnt = nullptr;
   float* hq = nullptr;
   int32_t* hcnt = nullptr;
+  int64_t* hwork = nullptr;  // [2][nq] codes scanned, exact distances computed
   size_t cap_q = 0;
   int64_t* dids = nullptr;
   float* ddist = nullptr;
@@ -79,7 +78,7 @@ struct Lane {
     if (stream) { hipStreamSynchronize(stream); hipStreamDestroy(stream); }
     if (done) hipEventDestroy(done);
     hipFree(ws); hipFree(dq); hipFree(dcnt); hipFree(dids); hipFree(ddist);
-    hipHostFree(hq); hipHostFree(hcnt); hipHostFree(hids); hipHostFree(hdist);
+    hipHostFree(hq); hipHostFree(hcnt); hipHostFree(hwork); hipHostFree(hids); hipHostFree(hdist);
     stream = nullptr; done = nullptr;
   }
 
@@ -94,13 +93,14 @@ struct Lane {
     }
     if (nq > cap_q) {
       const size_t c = std::max<size_t>(nq, 2 * cap_q);
-      hipFree(dq); hipFree(dcnt); hipHostFree(hq); hipHostFree(hcnt);
-      dq = nullptr; dcnt = nullptr; hq = nullptr; hcnt = nullptr;
+      hipFree(dq); hipFree(dcnt); hipHostFree(hq); hipHostFree(hcnt); hipHostFree(hwork);
+      dq = nullptr; dcnt = nullptr; hq = nullptr; hcnt = nullptr; hwork = nullptr;
       cap_q = 0;
       if (hipMalloc(reinterpret_cast<void**>(&dq), sizeof(float) * c * d) != hipSuccess ||
           hipMalloc(reinterpret_cast<void**>(&dcnt), sizeof(int32_t) * c) != hipSuccess ||
           hipHostMalloc(reinterpret_cast<void**>(&hq), sizeof(float) * c * d) != hipSuccess ||
-          hipHostMalloc(reinterpret_cast<void**>(&hcnt), sizeof(int32_t) * c) != hipSuccess)
+          hipHostMalloc(reinterpret_cast<void**>(&hcnt), sizeof(int32_t) * c) != hipSuccess ||
+          hipHostMalloc(reinterpret_cast<void**>(&hwork), sizeof(int64_t) * 2 * c) != hipSuccess)
         return BBC_ENOMEM;
       cap_q = c;
     }
@@ -170,7 +170,7 @@ struct bbc_server {
     if (hipMemcpyAsync(L.dq, L.hq, sizeof(float) * nq * d, hipMemcpyHostToDevice, L.stream) != hipSuccess)
       return bbc::set_error(BBC_EDEVICE, "query upload failed");
     rc = bbc::search_in_workspace(ix, L.dq, (int64_t)nq, L.k.data(), L.nprobe.data(), &p, L.off.data(), L.dids,
-                                  L.ddist, L.dcnt, L.ws, &wsb);
+                                  L.ddist, L.dcnt, L.ws, &wsb, L.hwork);
     if (rc) return rc;
     const int64_t nout = L.off[nq];
     if (hipMemcpyAsync(L.hids, L.dids, sizeof(int64_t) * nout, hipMemcpyDeviceToHost, L.stream) != hipSuccess ||
@@ -186,14 +186,18 @@ struct bbc_server {
     const int64_t t = now_ns();
     {
       std::lock_guard<std::mutex> lk(mu);
-      for (size_t i = 0; i < L.batch.size(); ++i) {
+      const size_t nq = L.batch.size();
+      for (size_t i = 0; i < nq; ++i) {
         Res r;
-        r.status = status;
-        r.latency_ns = t - L.batch[i].t_submit;
+        r.info.status = status;
+        r.info.latency_ns = t - L.batch[i].t_submit;
+        r.info.batch_size = (int64_t)nq;
         if (status == BBC_OK) {
           r.ids.assign(L.hids + L.off[i], L.hids + L.off[i + 1]);
           r.dists.assign(L.hdist + L.off[i], L.hdist + L.off[i + 1]);
-          r.count = L.hcnt[i];
+          r.info.count = L.hcnt[i];
+          r.info.n_scanned = L.hwork[i];
+          r.info.n_reranked = L.hwork[nq + i];
         } else {
           r.err = err ? err : "";
         }
@@ -281,19 +285,18 @@ struct bbc_server {
 namespace {
 
 // Under s->mu.  True if the ticket's result was filed (and is now handed out).
-bool take_result(bbc_server* s, uint64_t ticket, int64_t* ids, float* dists, int32_t* count, int64_t* latency_ns,
+bool take_result(bbc_server* s, uint64_t ticket, int64_t* ids, float* dists, bbc_request_info* info,
                  int32_t* status) {
   auto it = s->done.find(ticket);
   if (it == s->done.end()) return false;
   const Res& r = it->second;
-  *status = r.status;
-  if (r.status == BBC_OK) {
+  *status = r.info.status;
+  if (info) *info = r.info;
+  if (r.info.status == BBC_OK) {
     if (ids) std::memcpy(ids, r.ids.data(), sizeof(int64_t) * r.ids.size());
     if (dists) std::memcpy(dists, r.dists.data(), sizeof(float) * r.dists.size());
-    if (count) *count = r.count;
-    if (latency_ns) *latency_ns = r.latency_ns;
   } else {
-    bbc::set_error(r.status, r.err);
+    bbc::set_error(r.info.status, r.err);
   }
   s->done.erase(it);
   return true;
@@ -362,26 +365,25 @@ int32_t bbc_server_submit(bbc_server* s, const float* q, int32_t k, int32_t npro
   return BBC_OK;
 }
 
-int32_t bbc_server_poll(bbc_server* s, uint64_t ticket, int64_t* ids, float* dists, int32_t* count,
-                        int64_t* latency_ns) {
+int32_t bbc_server_poll(bbc_server* s, uint64_t ticket, int64_t* ids, float* dists, bbc_request_info* info) {
   if (!s) return bbc::set_error(BBC_EINVAL, "server is NULL");
   std::lock_guard<std::mutex> lk(s->mu);
   int32_t status = BBC_OK;
-  if (take_result(s, ticket, ids, dists, count, latency_ns, &status)) return status;
+  if (take_result(s, ticket, ids, dists, info, &status)) return status;
   if (s->outstanding.count(ticket)) return BBC_EBUSY;
   return bbc::set_error(BBC_EINVAL, "unknown or already collected ticket");
 }
 
 int32_t bbc_server_wait(bbc_server* s, uint64_t ticket, int32_t timeout_ms, int64_t* ids, float* dists,
-                        int32_t* count, int64_t* latency_ns) {
+                        bbc_request_info* info) {
   if (!s) return bbc::set_error(BBC_EINVAL, "server is NULL");
   std::unique_lock<std::mutex> lk(s->mu);
   const auto until = Clock::now() + std::chrono::milliseconds(std::max(0, timeout_ms));
   int32_t status = BBC_OK;
-  while (!take_result(s, ticket, ids, dists, count, latency_ns, &status)) {
+  while (!take_result(s, ticket, ids, dists, info, &status)) {
     if (!s->outstanding.count(ticket)) return bbc::set_error(BBC_EINVAL, "unknown or already collected ticket");
     if (s->cv_done.wait_until(lk, until) == std::cv_status::timeout) {
-      if (take_result(s, ticket, ids, dists, count, latency_ns, &status)) return status;
+      if (take_result(s, ticket, ids, dists, info, &status)) return status;
       return BBC_EBUSY;
     }
   }

@@ -14,6 +14,8 @@ the result-buffer section.
 from __future__ import annotations
 
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field, replace
 from typing import Optional, Tuple
 
@@ -26,6 +28,7 @@ __all__ = [
 ]
 
 CHUNK_ROWS = 1 << 20
+BLOCK_ROWS = 1 << 15  # rows drawn per block inside a chunk (bounds the float64 temporaries)
 
 
 @dataclass(frozen=True)
@@ -51,6 +54,8 @@ class Workload:
     train_per_list: int = 64    # k-means training sample: min(n, train_per_list * nlist)
     pq_train: int = 65536       # PQ training sample size (rows)
     uneven: bool = False
+    arrival_qps: float = 0.0    # served from a Poisson stream at this rate (0: batch workload)
+    serve_seconds: float = 0.0  # length of the arrival stream
 
     @property
     def seed_data(self) -> int:
@@ -85,7 +90,7 @@ WORKLOADS = {
     # 10M x 768 unit fp16, inner product, IVF8192 + RaBitQ, served from a Poisson stream
     "ivfrabitq_ip_10m_d768": Workload("ivfrabitq_ip_10m_d768", 10_000_000, 768, 8192, 8192,
                                       "rabitq", 8192, (1000, 20000), 128, metric="ip",
-                                      fp16=True, seed_index=4),
+                                      fp16=True, seed_index=4, arrival_qps=2000.0, serve_seconds=30.0),
 }
 
 
@@ -118,19 +123,33 @@ def mixture_centers(w: Workload) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def _draw_points(w: Workload, n: int, seed: int, out_dtype) -> np.ndarray:
+    """Rows in chunks of CHUNK_ROWS, each from its own child seed (labels
+    first, then the noise row by row), so chunks are drawn in parallel
+    threads and in row blocks without changing a value."""
     centers, scale = mixture_centers(w)
     nchunks = max(1, math.ceil(n / CHUNK_ROWS))
     children = np.random.SeedSequence(seed).spawn(nchunks)
     out = np.empty((n, w.d), dtype=out_dtype)
-    for ci, child in enumerate(children):
+
+    def chunk(ci):
         lo = ci * CHUNK_ROWS
         hi = min(n, lo + CHUNK_ROWS)
-        rng = np.random.default_rng(child)
+        rng = np.random.default_rng(children[ci])
         labels = rng.integers(0, w.ncomp, size=hi - lo)
-        pts = centers[labels] + rng.standard_normal((hi - lo, w.d)) * scale
-        if w.fp16:
-            pts /= np.linalg.norm(pts, axis=1, keepdims=True)
-        out[lo:hi] = pts.astype(out_dtype)
+        for b in range(lo, hi, BLOCK_ROWS):
+            e = min(hi, b + BLOCK_ROWS)
+            pts = centers[labels[b - lo:e - lo]] + rng.standard_normal((e - b, w.d)) * scale
+            if w.fp16:
+                pts /= np.linalg.norm(pts, axis=1, keepdims=True)
+            out[b:e] = pts.astype(out_dtype)
+
+    workers = min(nchunks, os.cpu_count() or 1, 16)
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as ex:
+            list(ex.map(chunk, range(nchunks)))
+    else:
+        for ci in range(nchunks):
+            chunk(ci)
     return out
 
 
@@ -210,6 +229,20 @@ def poisson_arrivals(rate: float, duration_s: float, seed: int) -> np.ndarray:
     while t[-1] < duration_s:
         t = np.concatenate([t, t[-1] + np.cumsum(rng.exponential(1.0 / rate, size=n_est))])
     return t[t < duration_s]
+
+
+def request_stream(w: Workload, pool: int, rate: Optional[float] = None,
+                   duration_s: Optional[float] = None) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
+    """A serving workload's requests: Poisson arrival times (seconds), the
+    query of each (an index into a pool of `pool` queries, uniform) and its k
+    (log-uniform over the workload's k range)."""
+    rate = w.arrival_qps if rate is None else rate
+    duration_s = w.serve_seconds if duration_s is None else duration_s
+    t = poisson_arrivals(rate, duration_s, w.seed_arrivals)
+    rng = np.random.default_rng(w.seed_arrivals + 1)
+    qi = rng.integers(0, pool, size=t.shape[0]).astype(np.int64)
+    k, _ = uneven_k_nprobe(t.shape[0], w.k, (1, 1), w.seed_arrivals + 2)
+    return t, qi, k
 
 
 def integer_vectors(n: int, d: int, lo: int, hi: int, seed: int) -> np.ndarray:

@@ -37,9 +37,23 @@ def _data(d, n, nq, nlist, metric, fp16=False, seed_index=2):
     return x, q, tr, ip, P, ix
 
 
-def _gpu_index(bbc, x, ix, eps0=0.0):
-    return bbc.Index.create_rabitq(ix["centroids"], ix["list_off"], ix["list_ids"], ix["P"], ix["codes"],
-                                   ix["factors"], x, metric=ix["metric"], eps0=eps0)
+FORMS = {"per_query": "1", "wide": "2"}
+
+
+def _gpu_index(bbc, x, ix, eps0=0.0, form="per_query"):
+    """The re-rank form (one block per query, or the exact keys of all
+    candidates by a device-wide grid first) is fixed when the index is made."""
+    import os
+    old = os.environ.get("BBC_WALK_FORM")
+    os.environ["BBC_WALK_FORM"] = FORMS[form]
+    try:
+        return bbc.Index.create_rabitq(ix["centroids"], ix["list_off"], ix["list_ids"], ix["P"], ix["codes"],
+                                       ix["factors"], x, metric=ix["metric"], eps0=eps0)
+    finally:
+        if old is None:
+            del os.environ["BBC_WALK_FORM"]
+        else:
+            os.environ["BBC_WALK_FORM"] = old
 
 
 def _check_search(g, ix, q, k, nprobe, eps0=oracle.RABITQ_EPS0):
@@ -72,23 +86,25 @@ def test_gpu_build_matches_oracle(bbc, d):
     np.testing.assert_array_equal(g.get(bbc.FIELD_ROT_CENTROIDS), ix["rot_centroids"])
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("cfg", [
     # (d, n, nq, nlist, metric, fp16, k, nprobe)
     (128, 6000, 8, 12, 0, False, 200, 4),
     (960, 2500, 5, 8, 0, False, 300, 3),
     (256, 5000, 6, 10, 1, True, 250, 3),
 ])
-def test_bounds_and_results_match_oracle(bbc, cfg):
+def test_bounds_and_results_match_oracle(bbc, cfg, form):
     d, n, nq, nlist, metric, fp16, k, nprobe = cfg
     x, q, tr, ip, P, ix = _data(d, n, nq, nlist, metric, fp16)
-    print(f"[case] rabitq search d={d} metric={metric} fp16={fp16} k={k} nprobe={nprobe}", flush=True)
-    g = _gpu_index(bbc, x, ix)
+    print(f"[case] rabitq search d={d} metric={metric} fp16={fp16} k={k} nprobe={nprobe} form={form}", flush=True)
+    g = _gpu_index(bbc, x, ix, form=form)
     _check_search(g, ix, q, k, nprobe)
 
 
-def test_uneven_and_edge_cases(bbc):
+@pytest.mark.parametrize("form", list(FORMS))
+def test_uneven_and_edge_cases(bbc, form):
     x, q, tr, ip, P, ix = _data(128, 6000, 8, 12, 0)
-    g = _gpu_index(bbc, x, ix)
+    g = _gpu_index(bbc, x, ix, form=form)
     k = np.array([1, 7, 64, 500, 6000, 40, 2000, 9000], np.int32)
     npb = np.array([1, 12, 2, 5, 12, 1, 3, 4], np.int32)
     print("[case] rabitq uneven", flush=True)
@@ -96,13 +112,14 @@ def test_uneven_and_edge_cases(bbc):
     assert np.all(tr["ids"][tr["off"][-2] + tr["counts"][-1]:] == -1)  # k > S pads
 
 
+@pytest.mark.parametrize("form", list(FORMS))
 @pytest.mark.parametrize("eps0", [0.05, 0.4])
-def test_narrow_bounds_take_the_exact_walk(bbc, eps0):
+def test_narrow_bounds_take_the_exact_walk(bbc, eps0, form):
     """With narrow bounds many fail, so the bin walk's checks fail and the
     item-by-item walk must still return the oracle's result."""
     x, q, tr, ip, P, ix = _data(128, 6000, 8, 12, 0)
-    g = _gpu_index(bbc, x, ix, eps0=eps0)
-    print(f"[case] rabitq eps0={eps0}", flush=True)
+    g = _gpu_index(bbc, x, ix, eps0=eps0, form=form)
+    print(f"[case] rabitq eps0={eps0} form={form}", flush=True)
     _check_search(g, ix, q, 150, 4, eps0=eps0)
 
 

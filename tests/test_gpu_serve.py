@@ -44,11 +44,14 @@ def test_pq_server_matches_oracle_alone_and_in_the_mix(bbc, lanes):
     srv.free()
     assert st["requests"] == nq and st["pending"] == 0
     assert 1 <= st["max_batch"] <= 8 and st["max_inflight"] <= 8
-    for i, (ids, dists, cnt, lat) in enumerate(res):
+    sizes = g.search_sizes(q, k, npb, ratio=2.0)
+    for i, (ids, dists, info) in enumerate(res):
         s = slice(ref["off"][i], ref["off"][i + 1])
         np.testing.assert_array_equal(ids, ref["ids"][s], err_msg=f"request {i}")
         np.testing.assert_array_equal(dists, ref["dists"][s], err_msg=f"request {i}")
-        assert cnt == ref["counts"][i] and lat > 0
+        assert info["count"] == ref["counts"][i] and info["latency_ns"] > 0 and info["status"] == 0
+        assert info["n_scanned"] == sizes["n_scanned"][i] and info["n_reranked"] == sizes["n_cand"][i]
+        assert 1 <= info["batch_size"] <= 8
         if i % 8 == 0:  # the same request searched alone
             a = g.search(q[i:i + 1], int(k[i]), int(npb[i]), ratio=2.0)
             np.testing.assert_array_equal(ids, a[0])
@@ -76,7 +79,7 @@ def test_admission_bounds_what_is_in_flight(bbc):
             assert e.value.code == bbc.ENOMEM
         srv.free()
         assert st["max_inflight"] <= cap and st["max_batch"] <= cap and st["requests"] == nq
-        for i, (ids, dists, cnt, lat) in enumerate(res):
+        for i, (ids, dists, info) in enumerate(res):
             s = slice(direct[3][i], direct[3][i + 1])
             np.testing.assert_array_equal(ids, direct[0][s])
             np.testing.assert_array_equal(dists, direct[1][s])
@@ -97,10 +100,10 @@ def test_ticket_protocol_and_errors(bbc):
             break
     if got is None:
         got = srv.wait(t, 60000)
-    assert got is not None and got[2] == 500
-    assert L.bbc_server_poll(srv._h, t, None, None, None, None) == bbc.EINVAL   # collected
-    assert L.bbc_server_poll(srv._h, 10 ** 9, None, None, None, None) == bbc.EINVAL  # never issued
-    assert L.bbc_server_wait(srv._h, t, 10, None, None, None, None) == bbc.EINVAL
+    assert got is not None and got[2]["count"] == 500
+    assert L.bbc_server_poll(srv._h, t, None, None, None) == bbc.EINVAL   # collected
+    assert L.bbc_server_poll(srv._h, 10 ** 9, None, None, None) == bbc.EINVAL  # never issued
+    assert L.bbc_server_wait(srv._h, t, 10, None, None, None) == bbc.EINVAL
     for args in [(q[0], 0, 10), (q[0], 10, 0), (q[0], 10, 51)]:
         with pytest.raises(bbc.BBCError) as e:
             srv.submit(*args)
@@ -136,8 +139,10 @@ def test_rabitq_server_matches_oracle(bbc):
     srv = g.server(mem_budget=1 << 30, max_slots=4, lanes=2)
     res = _collect(srv, [srv.submit(q[i], int(k[i]), int(npb[i])) for i in range(nq)])
     srv.free()
-    for i, (ids, dists, cnt, lat) in enumerate(res):
+    sizes = g.search_sizes(q, k, npb)
+    for i, (ids, dists, info) in enumerate(res):
         s = slice(ref["off"][i], ref["off"][i + 1])
         np.testing.assert_array_equal(ids, ref["ids"][s], err_msg=f"request {i}")
         np.testing.assert_array_equal(dists, ref["dists"][s])
-        assert cnt == ref["counts"][i]
+        assert info["count"] == ref["counts"][i]
+        assert info["n_scanned"] == sizes["n_scanned"][i] and info["n_reranked"] == sizes["n_visited"][i]
