@@ -515,14 +515,20 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
     build_s = time.time() - t0
     log(f"GPU index build {build_s:.1f}s")
     rq = q[: args.recall_queries]
-    x64 = torch.from_numpy(x).to(dev).to(torch.float64)
-    gt = ground_truth(torch, x64, rq, k, metric)
-    del x64
-    torch.cuda.empty_cache()
+    gt = None
+    if len(rq):
+        x64 = torch.from_numpy(x).to(dev).to(torch.float64)
+        gt = ground_truth(torch, x64, rq, k, metric)
+        del x64
+        torch.cuda.empty_cache()
+    elif not args.nprobe:
+        raise SystemExit("--recall-queries 0 needs a fixed --nprobe")
     if args.nprobe:
         npb = int(args.nprobe.split(",")[0])
-        ids, _, _, off = index.search(rq, k, npb)
-        rec = recall_at_k(ids, off, gt, k)
+        rec = None
+        if gt is not None:
+            ids, _, _, off = index.search(rq, k, npb)
+            rec = recall_at_k(ids, off, gt, k)
     else:
         npb, rec = None, None
         for cand in [32, 64, 96, 128, 192, 256, 384, 512, 768, 1024]:

@@ -681,6 +681,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   pa.n_scanned = reinterpret_cast<int64_t*>(A + L_ns);
   pa.n_recheck = reinterpret_cast<int32_t*>(A + L_nr);
   pa.nsample_q = nullptr;
+  pa.num_cu = ix->num_cu;
   {
     StageScope st(s, 0);
     HIP_TRY(bbc::launch_probe(pa, s));
@@ -948,6 +949,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   pa.n_recheck = reinterpret_cast<int32_t*>(A + L.n_recheck);
   pa.kc_target = d_kt; pa.nsample = bucket ? nsample : ix->nlist; pa.sample_factor = sample_factor;
   pa.nsample_q = reinterpret_cast<int32_t*>(A + L.nsample_q);
+  pa.num_cu = ix->num_cu;
   {
     StageScope st(s, 0);  // coarse GEMM and probe select
     HIP_TRY(bbc::launch_probe(pa, s));

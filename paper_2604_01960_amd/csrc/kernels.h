@@ -40,6 +40,7 @@ struct ProbeArgs {
   // until they hold sample_factor * kc_target keys (all probed lists if they
   // never do)
   const int64_t* kc_target; int nsample; int sample_factor; int32_t* nsample_q;
+  int num_cu = 256;  // compute units of the device (block shape of the select)
 };
 hipError_t launch_probe(const ProbeArgs& a, hipStream_t s);
 size_t probe_select_lds(int nlist);

@@ -5,13 +5,17 @@
 // Step 1 (probe_gemm): D'[q][j] = |c_j|^2 - 2 <q~, c~_j>  (L2) or -<q~, c~_j>
 //   (inner product) on BF16 MFMA with FP32 accumulation, q~ and c~ the
 //   round-to-nearest BF16 images of the query and the centroid.
-// Step 2 (probe_select): the BF16 scores only pre-filter.  With
-//   E_j = 2^-5 |q| |c_j| + 2^-12 (|q|^2 + |c_j|^2) bounding the BF16 and
-//   accumulation error (unit roundoff 2^-8 on each operand, a factor 2 of
-//   margin, and the FP32 terms for d <= 1024), every list of the exact
-//   top-nprobe satisfies D'_j - E_j <= U*, U* the nprobe-th smallest
-//   D'_j + E_j.  Only that recheck set gets the canonical FP32 key, and the
-//   nprobe smallest (key, list id) are the probe, nearest first.
+// Step 2 (probe_select): the BF16 scores only pre-filter.  The BF16 dot
+//   product differs from the exact one by at most (2u + u^2) |q| |c_j| with
+//   u = 2^-8 the unit roundoff of each operand, plus the FP32 accumulation
+//   (d 2^-24 |q| |c_j| for d <= 1024): under 2^-7 |q| |c_j| in all.  With
+//   E_j = a |q| |c_j| + 2^-12 (|q|^2 + |c_j|^2), a = 2^-5 for L2 (the dot
+//   enters twice) and 2^-6 for the inner product (a factor 2 of margin
+//   either way; the second term covers the FP32 norms and the canonical
+//   key's own rounding), every list of the exact top-nprobe satisfies
+//   D'_j - E_j <= U*, U* the nprobe-th smallest D'_j + E_j.  Only that
+//   recheck set gets the canonical FP32 key, and the nprobe smallest
+//   (key, list id) are the probe, nearest first.
 #include "common.h"
 #include "kernels.h"
 
@@ -83,9 +87,37 @@ __global__ __launch_bounds__(256) void probe_gemm_kernel(
   }
 }
 
+// Canonical keys (L2, or the inner product when ip) of the centroids
+// rows[0, cnt), cnt <= 4, by one wave; qc holds the query's chunks
+// lane, lane + 64, ... (d <= 1024).
+__device__ __forceinline__ void wave_canon4(const float4* qc, const float* __restrict__ cent, int d,
+                                            const int* rows, int cnt, bool ip, float* out) {
+  const int lane = threadIdx.x & 63;
+  const int nchunk = d >> 2;
+  float4 x[4][4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float4* row = reinterpret_cast<const float4*>(cent + (int64_t)rows[r] * d);
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+      const int c = lane + 64 * st;
+      x[r][st] = (r < cnt && c < nchunk) ? row[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    float acc = 0.0f;
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+      if (lane + 64 * st < nchunk) acc = ip ? chunk_ip(qc[st], x[r][st], acc) : chunk_l2(qc[st], x[r][st], acc);
+    out[r] = canon_reduce64(acc);
+  }
+}
+
 // One block per query.  LDS (dynamic): sel[nlist] u32, cand[P] u64 with
 // P = next_pow2(nlist), plus small scratch.
-__global__ __launch_bounds__(256) void probe_select_kernel(
+template <int NT>
+__global__ __launch_bounds__(NT) void probe_select_kernel(
     const float* __restrict__ q, int64_t nq, int d, const float* __restrict__ cent,
     const float* __restrict__ cn, const float* __restrict__ dprime, int nlist, int metric,
     const int32_t* __restrict__ nprobe, const int64_t* __restrict__ probe_off,
@@ -93,7 +125,6 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
     float* __restrict__ probe_keys, int64_t* __restrict__ rank_off, int64_t* __restrict__ n_scanned,
     int32_t* __restrict__ n_recheck, const int64_t* __restrict__ kc_target, int nsample, int sample_factor,
     int32_t* __restrict__ nsample_q) {
-  constexpr int NT = 256;
   extern __shared__ __align__(16) unsigned char smem[];
   const int P = next_pow2(nlist);
   uint64_t* cand = reinterpret_cast<uint64_t*>(smem);
@@ -119,7 +150,7 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
   __syncthreads();
   const float qn2 = qn_s[0], qn = qn_s[1];
   const float* dp = dprime + qi * (int64_t)nlist;
-  const float c1 = 0.03125f, c2 = 1.0f / 4096.0f;
+  const float c1 = metric != 0 ? 0.015625f : 0.03125f, c2 = 1.0f / 4096.0f;
   for (int j = threadIdx.x; j < nlist; j += NT) {
     float cj = cn[j];
     float e = c1 * qn * cj + c2 * (qn2 + cj * cj);
@@ -141,12 +172,40 @@ __global__ __launch_bounds__(256) void probe_select_kernel(
   }
   __syncthreads();
   const int nr = (int)bc[2];
-  // canonical keys, one wave per list
-  for (int i = w; i < nr; i += NT / 64) {
-    int j = (int)sel[i];
-    float key = wave_canon(qv, cent + (int64_t)j * d, d, metric != 0);
-    if (metric != 0) key = -key;
-    if (lane == 0) cand[i] = pack_key_id(key, (uint32_t)j);
+  // canonical keys: wide blocks take four lists per wave at a time (the
+  // query in registers), narrow ones one list per wave (fewer registers,
+  // more blocks per compute unit)
+  if constexpr (NT < 1024) {
+    for (int i = w; i < nr; i += NT / 64) {
+      const int j = (int)sel[i];
+      float key = wave_canon(qv, cent + (int64_t)j * d, d, metric != 0);
+      if (metric != 0) key = -key;
+      if (lane == 0) cand[i] = pack_key_id(key, (uint32_t)j);
+    }
+  } else {
+  float4 qc[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int c = lane + 64 * st;
+    qc[st] = c < (d >> 2) ? reinterpret_cast<const float4*>(qv)[c] : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  for (int i = 4 * w; i < nr; i += 4 * (NT / 64)) {
+    const int cnt = min(4, nr - i);
+    int rows[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) rows[r] = (int)sel[i + (r < cnt ? r : 0)];
+    float key[4];
+    wave_canon4(qc, cent, d, rows, cnt, metric != 0, key);
+    if (lane < cnt) {
+      float kv = key[0];
+      int jv = rows[0];
+#pragma unroll
+      for (int r = 1; r < 4; ++r)
+        if (lane == r) { kv = key[r]; jv = rows[r]; }
+      if (metric != 0) kv = -kv;
+      cand[i + lane] = pack_key_id(kv, (uint32_t)jv);
+    }
+  }
   }
   const int PR = next_pow2(nr);
   for (int i = nr + threadIdx.x; i < PR; i += NT) cand[i] = ~0ull;
@@ -216,7 +275,16 @@ hipError_t launch_probe(const ProbeArgs& a, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   size_t lds = sizeof(uint64_t) * next_pow2(a.nlist) + sizeof(uint32_t) * a.nlist;
-  hipLaunchKernelGGL(probe_select_kernel, dim3((unsigned)a.nq), dim3(256), lds, s, a.q, a.nq, a.d,
+  // a batch too small to fill the device takes wide blocks (the recheck
+  // of one query spread over 16 waves); otherwise narrow ones, several per
+  // compute unit
+  if (a.nq < 4 * (int64_t)a.num_cu)
+    hipLaunchKernelGGL(probe_select_kernel<1024>, dim3((unsigned)a.nq), dim3(1024), lds, s, a.q, a.nq, a.d,
+                     a.cent, a.cent_norm, a.dprime, a.nlist, a.metric, a.nprobe, a.probe_off,
+                     a.list_off, a.probe_lists, a.probe_keys, a.rank_off, a.n_scanned, a.n_recheck,
+                     a.kc_target, a.nsample, a.sample_factor, a.nsample_q);
+  else
+    hipLaunchKernelGGL(probe_select_kernel<256>, dim3((unsigned)a.nq), dim3(256), lds, s, a.q, a.nq, a.d,
                      a.cent, a.cent_norm, a.dprime, a.nlist, a.metric, a.nprobe, a.probe_off,
                      a.list_off, a.probe_lists, a.probe_keys, a.rank_off, a.n_scanned, a.n_recheck,
                      a.kc_target, a.nsample, a.sample_factor, a.nsample_q);

@@ -601,8 +601,21 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   int b_end = 0;
   uint32_t Eimg = 0xffffffffu;
   bool exhausted = false;
+  // Wide form: the running k-th exact key never drops below E_C, the k-th
+  // smallest exact key image over all of C, so no stop can come before the
+  // first bin whose lower edge exceeds E_C: the first round takes every bin
+  // before it.
+  int64_t first_end = 0;
+  if (a.wide && nC > k) {
+    const uint32_t EC =
+        block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(pbuf[i] >> 32); }, nC, k - 1, rhist, bc);
+    if (EC >= lmin) {
+      const uint64_t bC = ((uint64_t)(EC - lmin) >> shift) + 1;
+      first_end = bC >= (uint64_t)WK_NB ? nC : (int64_t)hist[bC - 1];
+    }
+  }
   while (true) {
-    const int64_t target = p < k ? max(k, (int64_t)WK_CHUNK) : p + WK_CHUNK;
+    const int64_t target = max(p < k ? max(k, (int64_t)WK_CHUNK) : p + WK_CHUNK, first_end);
     int b = b_end;
     while (b < WK_NB && (int64_t)hist[b] < target) ++b;
     if (b < WK_NB) ++b;  // the bin that reaches the target

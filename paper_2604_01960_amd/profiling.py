@@ -35,29 +35,42 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "")
 
 
-def kernel_stats(db: str, regex: str = "") -> List[Tuple]:
-    """(name, blocks, block size, LDS bytes, VGPRs, calls, avg us, min us, max us),
-    by total time."""
+def kernel_stats(db: str, regex: str = "", by_name: bool = False) -> List[Tuple]:
+    """(name, blocks, block size, LDS bytes, VGPRs, calls, avg us, min us, max us,
+    total ms), by total time.  by_name: one row per kernel (grid and LDS given as
+    their range over the dispatches)."""
     c = sqlite3.connect(db)
     rows = c.execute("select name, grid_x, grid_y, workgroup_x, duration, lds_size, vgpr_count from kernels").fetchall()
-    g: Dict[Tuple, List[float]] = collections.defaultdict(list)
+    g: Dict[Tuple, List[Tuple]] = collections.defaultdict(list)
     rx = re.compile(regex) if regex else None
     for name, gx, gy, wx, dur, lds, vg in rows:
         short = _short(name)
         if rx and not rx.search(short):
             continue
-        g[(short, gx // max(1, wx), gy, wx, lds, vg)].append(dur / 1000.0)
+        key = (short, wx, vg) if by_name else (short, gx // max(1, wx), gy, wx, lds, vg)
+        g[key].append((dur / 1000.0, gx // max(1, wx), gy, lds))
     out = []
-    for (name, bx, by, wx, lds, vg), ds in sorted(g.items(), key=lambda kv: -sum(kv[1])):
-        out.append((name, f"{bx},{by}", wx, lds, vg, len(ds), sum(ds) / len(ds), min(ds), max(ds)))
+    for key, recs in sorted(g.items(), key=lambda kv: -sum(r[0] for r in kv[1])):
+        ds = [r[0] for r in recs]
+        if by_name:
+            name, wx, vg = key
+            bx = sorted({r[1] for r in recs})
+            by = sorted({r[2] for r in recs})
+            ld = sorted({r[3] for r in recs})
+            span = lambda v: str(v[0]) if len(v) == 1 else f"{v[0]}-{v[-1]}"
+            grid, lds = f"{span(bx)},{span(by)}", span(ld)
+        else:
+            name, bx, by, wx, lds, vg = key
+            grid = f"{bx},{by}"
+        out.append((name, grid, wx, lds, vg, len(ds), sum(ds) / len(ds), min(ds), max(ds), sum(ds) / 1000.0))
     return out
 
 
-def stats_markdown(db: str, regex: str = "") -> str:
-    lines = ["| kernel | grid (blocks) | block | LDS B | VGPR | calls | avg us | min us | max us |",
-             "|---|---|---|---|---|---|---|---|---|"]
-    for name, grid, wx, lds, vg, n, avg, mn, mx in kernel_stats(db, regex):
-        lines.append(f"| `{name}` | {grid} | {wx} | {lds} | {vg} | {n} | {avg:.1f} | {mn:.1f} | {mx:.1f} |")
+def stats_markdown(db: str, regex: str = "", by_name: bool = False) -> str:
+    lines = ["| kernel | grid (blocks) | block | LDS B | VGPR | calls | avg us | min us | max us | total ms |",
+             "|---|---|---|---|---|---|---|---|---|---|"]
+    for name, grid, wx, lds, vg, n, avg, mn, mx, tot in kernel_stats(db, regex, by_name):
+        lines.append(f"| `{name}` | {grid} | {wx} | {lds} | {vg} | {n} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {tot:.1f} |")
     return "\n".join(lines)
 
 
@@ -101,6 +114,7 @@ def main(argv=None):
     s = sub.add_parser("stats")
     s.add_argument("db")
     s.add_argument("--regex", default="")
+    s.add_argument("--by-name", action="store_true", help="one row per kernel name")
     c = sub.add_parser("counter")
     c.add_argument("db")
     c.add_argument("counter")
@@ -112,7 +126,7 @@ def main(argv=None):
     t.add_argument("--source", action="append", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
-        print(stats_markdown(args.db, args.regex))
+        print(stats_markdown(args.db, args.regex, args.by_name))
     elif args.cmd == "counter":
         v, n = counter_per_dispatch(args.db, args.counter, args.regex)
         print(f"{args.counter}: {v:.1f} per dispatch over {n} dispatches")
