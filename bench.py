@@ -58,6 +58,20 @@ def measured_traffic(workload, stage, sources):
     return int(rec["traffic_bytes"])
 
 
+def oracle_sample(run, n_total, seconds, per_call):
+    """Calls run(lo, hi) on consecutive query ranges of per_call queries until
+    `seconds` of CPU work are spent or n_total queries are done; returns
+    (queries done, seconds)."""
+    done, t = 0, 0.0
+    while done < n_total and t < seconds:
+        hi = min(n_total, done + per_call)
+        t0 = time.perf_counter()
+        run(done, hi)
+        t += time.perf_counter() - t0
+        done = hi
+    return done, t
+
+
 def recall_at_k(ids, off, gt, k):
     r = []
     for i in range(gt.shape[0]):
@@ -106,7 +120,8 @@ def main():
     ap.add_argument("--serve-warmup", type=int, default=256, help="serving: closed-loop warmup requests")
     ap.add_argument("--capacity-requests", type=int, default=4096,
                     help="serving: closed-loop requests for the capacity figure (0 skips it)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="serving: oracle sample length")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0,
+                    help="oracle sample length (seconds of CPU work; the RaBitQ, uneven and serving runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES bytes (3 times) for counter calibration")
     args = ap.parse_args()
@@ -392,20 +407,22 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
     else:
         # nprobe is fixed per query by the workload, so a query with few
         # probes and a large k may not reach the target at any r: take the
-        # first r that reaches it, else the r with the best recall
-        ratio, rec, best = None, None, (-1.0, None)
+        # first r that reaches it, else the knee of the saturated curve (the
+        # smallest r within 0.005 of the best recall)
+        ratio, rec, curve = None, None, []
         for r in (1.5, 2.0, 3.0, 4.0, 6.0, 8.0):
             ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r)
             rr = mean_recall(ids, off)
             log(f"ratio {r}: mean recall {rr:.4f}")
-            if rr > best[0]:
-                best = (rr, r)
+            curve.append((r, rr))
             if rr >= args.target_recall:
                 ratio, rec = r, rr
                 break
         if ratio is None:
-            rec, ratio = best
-            log(f"recall {args.target_recall} not reachable with these nprobe; r = {ratio} (recall {rec:.4f})")
+            top = max(rr for _, rr in curve)
+            ratio, rec = next((r, rr) for r, rr in curve if rr >= top - 0.005)
+            log(f"recall {args.target_recall} not reachable with these nprobe (best {top:.4f}); r = {ratio} "
+                f"(recall {rec:.4f})")
     qd = torch.from_numpy(q).to(dev)
     tot = int(k.sum())
     out = (torch.empty(tot, dtype=torch.int64, device=dev), torch.empty(tot, dtype=torch.float32, device=dev),
@@ -464,14 +481,13 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
                    centroids=index.get(bbc.FIELD_CENTROIDS), list_off=index.get(bbc.FIELD_LIST_OFF),
                    list_ids=index.get(bbc.FIELD_LIST_IDS), codes=index.get(bbc.FIELD_CODES),
                    codebook=index.get(bbc.FIELD_CODEBOOK), base=x)
-        nqc = min(args.cpu_queries, nq)
-        t0 = time.perf_counter()
-        oracle.search_pq(oix, q[:nqc], k[:nqc], npb[:nqc], ratio)
-        t_cpu = time.perf_counter() - t0
+        per_call = max(8, oracle.num_threads())
+        nqc, t_cpu = oracle_sample(lambda lo, hi: oracle.search_pq(oix, q[lo:hi], k[lo:hi], npb[lo:hi], ratio),
+                                   min(args.cpu_queries, nq), args.cpu_seconds, per_call)
         cpu = {"value": round(nqc / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"first {nqc} queries of the batch (their own k and nprobe), same r; oracle search over "
-                         f"the index arrays of the GPU build (bit-identical to the oracle's own build); "
-                         f"{t_cpu:.1f}s of CPU work"}
+               "sample": f"first {nqc} queries of the batch (their own k and nprobe), same r, {per_call} per "
+                         f"oracle call; oracle search over the index arrays of the GPU build (bit-identical to the "
+                         f"oracle's own build); {t_cpu:.1f}s of CPU work"}
     res = {
         "metric": f"QPS at mean recall@k={args.target_recall}, k log-uniform in [100, 50000], nprobe uniform in "
                   f"[16, 256] (batched uneven form)",
@@ -590,13 +606,13 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
                    P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
                    codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
                    base=np.ascontiguousarray(x, dtype=np.float32))
-        nqc = min(args.cpu_queries, nq)
-        t0 = time.perf_counter()
-        oracle.search_rabitq(oix, q[:nqc], k, npb)
-        t_cpu = time.perf_counter() - t0
+        per_call = max(8, oracle.num_threads())
+        nqc, t_cpu = oracle_sample(lambda lo, hi: oracle.search_rabitq(oix, q[lo:hi], k, npb),
+                                   min(args.cpu_queries, nq), args.cpu_seconds, per_call)
         cpu = {"value": round(nqc / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
-               "sample": f"first {nqc} queries of the batch, same nprobe; oracle search over the index arrays "
-                         f"of the GPU build (bit-identical to the oracle's own build); {t_cpu:.1f}s of CPU work"}
+               "sample": f"first {nqc} queries of the batch, same nprobe, {per_call} per oracle call; oracle "
+                         f"search over the index arrays of the GPU build (bit-identical to the oracle's own build); "
+                         f"{t_cpu:.1f}s of CPU work"}
     res = {
         "metric": f"QPS at recall@k={args.target_recall}, k={k}, RaBitQ with the bounded re-rank",
         "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -794,14 +810,10 @@ def run_serving(args, w, np, torch, bbc, synth, dev):
                    P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
                    codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
                    base=np.ascontiguousarray(x, dtype=np.float32))
-        done_n, t_cpu = 0, 0.0
         per_call = max(8, oracle.num_threads())
-        while t_cpu < args.cpu_seconds and done_n < n:
-            j = np.arange(done_n, min(n, done_n + per_call))
-            t1 = time.perf_counter()
-            oracle.search_rabitq(oix, pool[qi[j]], ks[j], npr[j])
-            t_cpu += time.perf_counter() - t1
-            done_n += len(j)
+        done_n, t_cpu = oracle_sample(
+            lambda lo, hi: oracle.search_rabitq(oix, pool[qi[lo:hi]], ks[lo:hi], npr[lo:hi]), n, args.cpu_seconds,
+            per_call)
         cpu = {"value": round(done_n / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(),
                "kind": "oracle",
                "sample": f"the first {done_n} requests of the stream (their k and nprobe), {per_call} per oracle call, "

@@ -197,13 +197,29 @@ int64_t bbc_query_bytes(const bbc_index* ix, int32_t k, int32_t nprobe, const bb
 #define BBC_FIELD_RABITQ_CODES 5    /* [n][d/32] uint32, list-slot order */
 #define BBC_FIELD_RABITQ_FACTORS 6  /* [n][4] float32 (nr, f, g, popcount), list-slot order */
 #define BBC_FIELD_ROT_CENTROIDS 7   /* [nlist][d] float32: P^T c_j */
+#define BBC_FIELD_ROTATION 8        /* [d][d] float32: P (RaBitQ) */
+#define BBC_FIELD_BASE 9            /* [n][d] float32 (float16 when stored so), row-id order */
 
-/* Sizes of an index: any pointer may be NULL. */
+/* Sizes of an index: any pointer may be NULL (storage: BBC_STORAGE_*). */
 int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,
-                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits);
+                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits, int32_t* storage);
 /* Copy one array of the index (BBC_FIELD_*) to host memory of `bytes` bytes. */
 int32_t bbc_index_get(const bbc_index* ix, int32_t field, void* dst, int64_t bytes);
 void bbc_index_free(bbc_index* ix);
+
+/* Index files: bbc_index_save writes the index's host-side image (what the
+ * create calls take) to `path`; bbc_index_load reads one and creates the
+ * index on `device` (BBC_EINVAL for a missing, foreign, truncated or
+ * inconsistent file).  Layout, little-endian, arrays packed in this order:
+ *   char[8] "BBCIDX1\0"; int32 quant, metric, storage, d, nlist, pq_m,
+ *   pq_bits, 0; int64 n; float32 eps0; int32 0            (56 bytes)
+ *   float32 centroids [nlist][d]; int64 list_off [nlist+1]; int64 list_ids [n]
+ *   PQ:     float32 codebook [pq_m][2^pq_bits][d/pq_m]; uint8 codes [n][pq_m]
+ *   RaBitQ: float32 rotation [d][d]; uint32 codes [n][d/32]; float32 factors [n][4]
+ *   base [n][d] float32, or float16 when storage = BBC_STORAGE_FP16, row-id order
+ * The caller owns `path`; the file holds the whole base (about n*d*4 bytes). */
+int32_t bbc_index_save(const bbc_index* ix, const char* path);
+int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out);
 
 /* Per-stage device time: when enabled, every kernel launch of a search is
  * bracketed by HIP events recorded on the search stream; bbc_stage_times

@@ -26,7 +26,7 @@ METRIC_L2, METRIC_IP = 0, 1
 QUANT_PQ, QUANT_RABITQ = 0, 1
 COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
 FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
-FIELD_RABITQ_CODES, FIELD_RABITQ_FACTORS, FIELD_ROT_CENTROIDS = 5, 6, 7
+FIELD_RABITQ_CODES, FIELD_RABITQ_FACTORS, FIELD_ROT_CENTROIDS, FIELD_ROTATION, FIELD_BASE = 5, 6, 7, 8, 9
 STORAGE_FP32, STORAGE_FP16 = 0, 1
 STAGES = {0: "probe", 1: "sample_scan", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
 
@@ -98,7 +98,7 @@ def load(path: Optional[str] = None):
     L.bbc_query_bytes.restype = i64
     L.bbc_query_bytes.argtypes = [vp, i32, i32, C.POINTER(SearchParams)]
     L.bbc_index_info.restype = i32
-    L.bbc_index_info.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
+    L.bbc_index_info.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
     L.bbc_index_get.restype = i32
     L.bbc_index_get.argtypes = [vp, i32, vp, i64]
     L.bbc_index_free.restype = None
@@ -127,6 +127,10 @@ def load(path: Optional[str] = None):
     L.bbc_server_stats.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bbc_server_destroy.restype = None
     L.bbc_server_destroy.argtypes = [vp]
+    L.bbc_index_save.restype = i32
+    L.bbc_index_save.argtypes = [vp, C.c_char_p]
+    L.bbc_index_load.restype = i32
+    L.bbc_index_load.argtypes = [i32, C.c_char_p, C.POINTER(vp)]
     L.bbc_last_error.restype = C.c_char_p
     L.bbc_last_error.argtypes = []
     _lib = L
@@ -169,12 +173,13 @@ class Index:
     def __init__(self, handle: int, device: int = 0):
         self._h = C.c_void_p(handle)
         self.device = device
-        n, d, nlist, metric, quant, m, bits = (C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
-                                               C.c_int32(), C.c_int32(), C.c_int32())
+        n, d, nlist, metric, quant, m, bits, st = (C.c_int64(), C.c_int32(), C.c_int32(), C.c_int32(),
+                                                   C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32())
         _check(load().bbc_index_info(self._h, C.byref(n), C.byref(d), C.byref(nlist), C.byref(metric),
-                                     C.byref(quant), C.byref(m), C.byref(bits)))
+                                     C.byref(quant), C.byref(m), C.byref(bits), C.byref(st)))
         self.n, self.d, self.nlist = n.value, d.value, nlist.value
         self.metric, self.quant, self.pq_m, self.pq_bits = metric.value, quant.value, m.value, bits.value
+        self.storage = st.value
 
     # -- construction ------------------------------------------------------
     @classmethod
@@ -250,6 +255,17 @@ class Index:
         except Exception:
             pass
 
+    # -- files -------------------------------------------------------------
+    def save(self, path: str):
+        """Write the index file (layout in include/bbc.h)."""
+        _check(load().bbc_index_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str, device: int = 0) -> "Index":
+        h = C.c_void_p()
+        _check(load().bbc_index_load(int(device), os.fsencode(path), C.byref(h)))
+        return cls(h.value, device)
+
     # -- introspection -----------------------------------------------------
     def get(self, field: int) -> np.ndarray:
         shapes = {
@@ -261,6 +277,8 @@ class Index:
             FIELD_RABITQ_CODES: ((self.n, self.d // 32), np.uint32),
             FIELD_RABITQ_FACTORS: ((self.n, 4), np.float32),
             FIELD_ROT_CENTROIDS: ((self.nlist, self.d), np.float32),
+            FIELD_ROTATION: ((self.d, self.d), np.float32),
+            FIELD_BASE: ((self.n, self.d), np.float16 if self.storage == STORAGE_FP16 else np.float32),
         }
         shape, dt = shapes[field]
         out = np.empty(shape, dt)

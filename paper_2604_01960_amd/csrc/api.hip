@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -407,8 +408,9 @@ int32_t bbc_index_create_rabitq(int32_t device, int64_t n, int32_t d, int32_t nl
 }
 
 int32_t bbc_index_info(const bbc_index* ix, int64_t* n, int32_t* d, int32_t* nlist, int32_t* metric,
-                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits) {
+                       int32_t* quant, int32_t* pq_m, int32_t* pq_bits, int32_t* storage) {
   if (!ix) return fail(BBC_EINVAL, "index is NULL");
+  if (storage) *storage = ix->fp16 ? BBC_STORAGE_FP16 : BBC_STORAGE_FP32;
   if (n) *n = ix->n;
   if (d) *d = ix->d;
   if (nlist) *nlist = ix->nlist;
@@ -489,12 +491,142 @@ int32_t bbc_index_get(const bbc_index* ix, int32_t field, void* dst, int64_t byt
       HIP_TRY(hipMemcpy(dst, ix->rot_cent, need, hipMemcpyDeviceToHost));
       return BBC_OK;
     }
+    case BBC_FIELD_ROTATION: {
+      if (ix->quant != BBC_QUANT_RABITQ) return fail(BBC_EUNSUPPORTED, "not a RaBitQ index");
+      const int64_t need = sizeof(float) * (int64_t)ix->d * ix->d;
+      if (bytes != need) return fail(BBC_EINVAL, "wrong size for the rotation");
+      HIP_TRY(hipMemcpy(dst, ix->rot, need, hipMemcpyDeviceToHost));
+      return BBC_OK;
+    }
+    case BBC_FIELD_BASE: {
+      // rows are held in list-slot order: copied in chunks, placed by row id
+      const int64_t row = (ix->fp16 ? 2 : 4) * (int64_t)ix->d;
+      if (bytes != row * n) return fail(BBC_EINVAL, "wrong size for the base rows");
+      std::vector<int32_t> ids(n);
+      HIP_TRY(hipMemcpy(ids.data(), ix->list_ids, sizeof(int32_t) * n, hipMemcpyDeviceToHost));
+      const int64_t chunk = std::max<int64_t>(1, (int64_t)(256 << 20) / row);
+      std::vector<char> t((size_t)(std::min(chunk, std::max<int64_t>(n, 1)) * row));
+      char* o = static_cast<char*>(dst);
+      for (int64_t p0 = 0; p0 < n; p0 += chunk) {
+        const int64_t c = std::min(chunk, n - p0);
+        HIP_TRY(hipMemcpy(t.data(), static_cast<const char*>(ix->vectors) + p0 * row, c * row, hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < c; ++p) std::memcpy(o + (int64_t)ids[p0 + p] * row, t.data() + p * row, row);
+      }
+      return BBC_OK;
+    }
     default:
       return fail(BBC_EINVAL, "unknown field");
   }
 }
 
 void bbc_index_free(bbc_index* ix) { index_release(ix); }
+
+}  // extern "C"
+
+namespace {
+
+constexpr char kIndexMagic[8] = {'B', 'B', 'C', 'I', 'D', 'X', '1', '\0'};
+
+struct IndexFileHeader {
+  char magic[8];
+  int32_t quant, metric, storage, d, nlist, pq_m, pq_bits, reserved0;
+  int64_t n;
+  float eps0;
+  int32_t reserved1;
+};
+static_assert(sizeof(IndexFileHeader) == 56, "index file header layout");
+
+// Bytes of each array of an index file after the header, in file order.
+std::vector<int64_t> index_file_sections(const IndexFileHeader& h) {
+  const int64_t n = h.n, d = h.d, nl = h.nlist;
+  std::vector<int64_t> s = {4 * nl * d, 8 * (nl + 1), 8 * n};
+  if (h.quant == BBC_QUANT_PQ) {
+    s.push_back(4 * (int64_t)h.pq_m * (1LL << h.pq_bits) * (d / h.pq_m));
+    s.push_back(n * h.pq_m);
+  } else {
+    s.push_back(4 * d * d);
+    s.push_back(4 * n * (d / 32));
+    s.push_back(16 * n);
+  }
+  s.push_back((h.storage == BBC_STORAGE_FP16 ? 2 : 4) * n * d);
+  return s;
+}
+
+struct FileCloser {
+  void operator()(FILE* f) const { if (f) std::fclose(f); }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t bbc_index_save(const bbc_index* ix, const char* path) {
+  if (!ix || !path) return fail(BBC_EINVAL, "NULL argument");
+  IndexFileHeader h{};
+  std::memcpy(h.magic, kIndexMagic, 8);
+  h.quant = ix->quant; h.metric = ix->metric; h.storage = ix->fp16 ? BBC_STORAGE_FP16 : BBC_STORAGE_FP32;
+  h.d = ix->d; h.nlist = ix->nlist; h.pq_m = ix->M; h.pq_bits = ix->bits; h.n = ix->n; h.eps0 = ix->eps0;
+  const std::vector<int64_t> sec = index_file_sections(h);
+  const int32_t fields_pq[] = {BBC_FIELD_CENTROIDS, BBC_FIELD_LIST_OFF, BBC_FIELD_LIST_IDS, BBC_FIELD_CODEBOOK,
+                               BBC_FIELD_CODES, BBC_FIELD_BASE};
+  const int32_t fields_rq[] = {BBC_FIELD_CENTROIDS, BBC_FIELD_LIST_OFF, BBC_FIELD_LIST_IDS, BBC_FIELD_ROTATION,
+                               BBC_FIELD_RABITQ_CODES, BBC_FIELD_RABITQ_FACTORS, BBC_FIELD_BASE};
+  const int32_t* fields = ix->quant == BBC_QUANT_PQ ? fields_pq : fields_rq;
+  std::unique_ptr<FILE, FileCloser> f(std::fopen(path, "wb"));
+  if (!f) return fail(BBC_EINVAL, std::string("cannot open for writing: ") + path);
+  if (std::fwrite(&h, sizeof(h), 1, f.get()) != 1) return fail(BBC_EINVAL, "write failed");
+  for (size_t i = 0; i < sec.size(); ++i) {
+    std::vector<char> buf((size_t)sec[i]);
+    const int32_t rc = bbc_index_get(ix, fields[i], buf.data(), sec[i]);
+    if (rc) return rc;
+    if (sec[i] && std::fwrite(buf.data(), 1, buf.size(), f.get()) != buf.size()) return fail(BBC_EINVAL, "write failed");
+  }
+  if (std::fflush(f.get()) != 0) return fail(BBC_EINVAL, "write failed");
+  return BBC_OK;
+}
+
+int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out) {
+  if (!out) return fail(BBC_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!path) return fail(BBC_EINVAL, "path is NULL");
+  std::unique_ptr<FILE, FileCloser> f(std::fopen(path, "rb"));
+  if (!f) return fail(BBC_EINVAL, std::string("cannot open: ") + path);
+  IndexFileHeader h{};
+  if (std::fread(&h, sizeof(h), 1, f.get()) != 1 || std::memcmp(h.magic, kIndexMagic, 8) != 0)
+    return fail(BBC_EINVAL, "not an index file");
+  const bool pq = h.quant == BBC_QUANT_PQ;
+  if ((!pq && h.quant != BBC_QUANT_RABITQ) || h.n < 1 || h.n >= (1LL << 31) || h.d < 4 || h.d > 1024 ||
+      h.nlist < 1 || h.nlist > 8192 || (h.storage != BBC_STORAGE_FP32 && h.storage != BBC_STORAGE_FP16) ||
+      (pq && (h.pq_m < 1 || h.d % h.pq_m || (h.pq_bits != 4 && h.pq_bits != 8))) || (!pq && h.d % 64))
+    return fail(BBC_EINVAL, "index file header out of range");
+  const std::vector<int64_t> sec = index_file_sections(h);
+  int64_t total = (int64_t)sizeof(h);
+  for (int64_t b : sec) total += b;
+  if (std::fseek(f.get(), 0, SEEK_END) != 0 || std::ftell(f.get()) != total)
+    return fail(BBC_EINVAL, "index file size does not match its header");
+  std::fseek(f.get(), (long)sizeof(h), SEEK_SET);
+  std::vector<std::vector<char>> a(sec.size());
+  for (size_t i = 0; i < sec.size(); ++i) {
+    a[i].resize((size_t)sec[i]);
+    if (sec[i] && std::fread(a[i].data(), 1, a[i].size(), f.get()) != a[i].size())
+      return fail(BBC_EINVAL, "index file read failed");
+  }
+  f.reset();
+  const float* cent = reinterpret_cast<const float*>(a[0].data());
+  const int64_t* list_off = reinterpret_cast<const int64_t*>(a[1].data());
+  const int64_t* list_ids = reinterpret_cast<const int64_t*>(a[2].data());
+  if (pq) {
+    if (h.storage != BBC_STORAGE_FP32) return fail(BBC_EINVAL, "PQ index files hold float32 rows");
+    return bbc_index_create_pq(device, h.n, h.d, h.nlist, h.metric, cent, list_off, list_ids, h.pq_m, h.pq_bits,
+                               reinterpret_cast<const float*>(a[3].data()),
+                               reinterpret_cast<const uint8_t*>(a[4].data()),
+                               reinterpret_cast<const float*>(a[5].data()), out);
+  }
+  return bbc_index_create_rabitq(device, h.n, h.d, h.nlist, h.metric, cent, list_off, list_ids,
+                                 reinterpret_cast<const float*>(a[3].data()),
+                                 reinterpret_cast<const uint32_t*>(a[4].data()),
+                                 reinterpret_cast<const float*>(a[5].data()), a[6].data(), h.storage, h.eps0, out);
+}
 
 int32_t bbc_stage_timing(int32_t enable) {
   g_timer.enabled = enable != 0;

@@ -315,7 +315,7 @@ int32_t bbc_server_create(bbc_index* ix, const bbc_search_params* params, int64_
   if (lanes < 0 || lanes > 8) return bbc::set_error(BBC_EINVAL, "lanes must be in [0, 8]");
   if (!(params->ncand_ratio >= 1.0)) return bbc::set_error(BBC_EINVAL, "ncand_ratio must be >= 1");
   int32_t d = 0;
-  const int32_t rc = bbc_index_info(ix, nullptr, &d, nullptr, nullptr, nullptr, nullptr, nullptr);
+  const int32_t rc = bbc_index_info(ix, nullptr, &d, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
   if (rc) return rc;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return bbc::set_error(BBC_EDEVICE, "hipGetDevice failed");

@@ -103,3 +103,38 @@ def check_trace(tr, exp, m, bucket=True):
         assert tr["counts"][i] == e["count"]
         np.testing.assert_array_equal(tr["ids"][os_], e["ids"], err_msg=f"ids q{i}")
         np.testing.assert_array_equal(tr["dists"][os_], e["dists"], err_msg=f"dists q{i}")
+
+
+def read_index_file(path):
+    """Arrays of an index file, parsed from its documented layout (a 56-byte
+    header of int32 quant, metric, storage, d, nlist, pq_m, pq_bits, 0, int64
+    n, float32 eps0, then the packed arrays); checks that the sizes add up
+    to the file size."""
+    raw = np.fromfile(path, np.uint8)
+    assert raw[:8].tobytes() == b"BBCIDX1\0"
+    quant, metric, storage, d, nlist, pq_m, pq_bits, _ = (int(v) for v in raw[8:40].view(np.int32))
+    n = int(raw[40:48].view(np.int64)[0])
+    eps0 = float(raw[48:52].view(np.float32)[0])
+    off = 56
+
+    def take(dtype, shape):
+        nonlocal off
+        nb = int(np.prod(shape)) * np.dtype(dtype).itemsize
+        a = raw[off:off + nb].view(dtype).reshape(shape).copy()
+        off += nb
+        return a
+
+    f = dict(quant=quant, metric=metric, storage=storage, d=d, nlist=nlist, n=n, eps0=eps0)
+    f["centroids"] = take(np.float32, (nlist, d))
+    f["list_off"] = take(np.int64, (nlist + 1,))
+    f["list_ids"] = take(np.int64, (n,))
+    if quant == 0:
+        f["codebook"] = take(np.float32, (pq_m, 1 << pq_bits, d // pq_m))
+        f["codes"] = take(np.uint8, (n, pq_m))
+    else:
+        f["P"] = take(np.float32, (d, d))
+        f["codes"] = take(np.uint32, (n, d // 32))
+        f["factors"] = take(np.float32, (n, 4))
+    f["base"] = take(np.float16 if storage == 1 else np.float32, (n, d))
+    assert off == raw.size
+    return f
