@@ -228,8 +228,9 @@ int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out);
  * select), 1 pair sort and scan of the codebook sample lists (RaBitQ: the
  * rotation of the queries), 2 scan of the remaining lists through the
  * relaxed threshold (RaBitQ: the bounds of every scanned object; one kernel
- * launch per search), 3 collector (codebook and bucket collection; RaBitQ
- * in the wide form: the lower-bound bins of the candidates), 4 re-rank
+ * launch per search), 3 collector (the bucket collection or a comparator;
+ * RaBitQ in the wide form: the lower-bound bins of the candidates),
+ * 6 the collector codebook, 4 re-rank
  * (RaBitQ: the bounded walk, after the exact keys of all candidates in the
  * wide form), 5 final top-k).  A RaBitQ batch of at most as many queries as
  * the device has compute units takes the wide form. */

@@ -28,7 +28,7 @@ COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
 FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
 FIELD_RABITQ_CODES, FIELD_RABITQ_FACTORS, FIELD_ROT_CENTROIDS, FIELD_ROTATION, FIELD_BASE = 5, 6, 7, 8, 9
 STORAGE_FP32, STORAGE_FP16 = 0, 1
-STAGES = {0: "probe", 1: "sample_scan", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk"}
+STAGES = {0: "probe", 1: "sample_scan", 2: "scan", 3: "collect", 4: "rerank", 5: "final_topk", 6: "codebook"}
 
 
 class BBCError(RuntimeError):

@@ -1139,7 +1139,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   }
   if (bucket) {
     {
-      StageScope st(s, 3);
+      StageScope st(s, 6);
       HIP_TRY(bbc::launch_codebook(ca, s));
     }
     {

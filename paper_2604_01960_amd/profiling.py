@@ -35,15 +35,22 @@ def _short(name: str) -> str:
     return name.split("(")[0].replace("void ", "")
 
 
-def kernel_stats(db: str, regex: str = "", by_name: bool = False) -> List[Tuple]:
+def kernel_stats(db: str, regex: str = "", by_name: bool = False, since: str = "") -> List[Tuple]:
     """(name, blocks, block size, LDS bytes, VGPRs, calls, avg us, min us, max us,
     total ms), by total time.  by_name: one row per kernel (grid and LDS given as
-    their range over the dispatches)."""
+    their range over the dispatches).  since: only the dispatches that start at
+    or after the first dispatch of a kernel matching this pattern (to leave
+    out an index build that runs before the searches)."""
     c = sqlite3.connect(db)
-    rows = c.execute("select name, grid_x, grid_y, workgroup_x, duration, lds_size, vgpr_count from kernels").fetchall()
+    rows = c.execute("select name, grid_x, grid_y, workgroup_x, duration, lds_size, vgpr_count, start from kernels "
+                     "order by start").fetchall()
+    if since:
+        sx = re.compile(since)
+        first = next((r[7] for r in rows if sx.search(_short(r[0]))), None)
+        rows = [] if first is None else [r for r in rows if r[7] >= first]
     g: Dict[Tuple, List[Tuple]] = collections.defaultdict(list)
     rx = re.compile(regex) if regex else None
-    for name, gx, gy, wx, dur, lds, vg in rows:
+    for name, gx, gy, wx, dur, lds, vg, _ in rows:
         short = _short(name)
         if rx and not rx.search(short):
             continue
@@ -66,10 +73,10 @@ def kernel_stats(db: str, regex: str = "", by_name: bool = False) -> List[Tuple]
     return out
 
 
-def stats_markdown(db: str, regex: str = "", by_name: bool = False) -> str:
+def stats_markdown(db: str, regex: str = "", by_name: bool = False, since: str = "") -> str:
     lines = ["| kernel | grid (blocks) | block | LDS B | VGPR | calls | avg us | min us | max us | total ms |",
              "|---|---|---|---|---|---|---|---|---|---|"]
-    for name, grid, wx, lds, vg, n, avg, mn, mx, tot in kernel_stats(db, regex, by_name):
+    for name, grid, wx, lds, vg, n, avg, mn, mx, tot in kernel_stats(db, regex, by_name, since):
         lines.append(f"| `{name}` | {grid} | {wx} | {lds} | {vg} | {n} | {avg:.1f} | {mn:.1f} | {mx:.1f} | {tot:.1f} |")
     return "\n".join(lines)
 
@@ -115,6 +122,7 @@ def main(argv=None):
     s.add_argument("db")
     s.add_argument("--regex", default="")
     s.add_argument("--by-name", action="store_true", help="one row per kernel name")
+    s.add_argument("--since", default="", help="only dispatches from the first one of a kernel matching this")
     c = sub.add_parser("counter")
     c.add_argument("db")
     c.add_argument("counter")
@@ -126,7 +134,7 @@ def main(argv=None):
     t.add_argument("--source", action="append", required=True)
     args = ap.parse_args(argv)
     if args.cmd == "stats":
-        print(stats_markdown(args.db, args.regex, args.by_name))
+        print(stats_markdown(args.db, args.regex, args.by_name, args.since))
     elif args.cmd == "counter":
         v, n = counter_per_dispatch(args.db, args.counter, args.regex)
         print(f"{args.counter}: {v:.1f} per dispatch over {n} dispatches")
