@@ -169,6 +169,7 @@ struct bbc_index {
   int nxcd = 8;
   int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide)
+  int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -260,6 +261,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 2) ix->walk_form = x;
+  }
+  if (const char* sv = std::getenv("BBC_COLLECT_BCAP")) {
+    const int x = std::atoi(sv);
+    if (x >= 64 && x <= 4096 && (x & (x - 1)) == 0) ix->collect_bcap = x;
   }
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
   return BBC_OK;
@@ -1087,7 +1092,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     HIP_TRY(bbc::launch_probe(pa, s));
   }
 
-  const int bcap = 4096;
+  const int bcap = ix->collect_bcap;
   bbc::QueryBook* books = reinterpret_cast<bbc::QueryBook*>(A + L.books);
   float* surv_key = reinterpret_cast<float*>(A + L.surv_key);
   uint32_t* surv_pos = reinterpret_cast<uint32_t*>(A + L.surv_pos);
@@ -1115,6 +1120,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ca.probe_off = d_po; ca.probe_lists = pa.probe_lists; ca.rank_off = pa.rank_off; ca.list_off = ix->list_off;
   ca.list_ids = ix->list_ids; ca.pos_of_id = ix->pos_of_id; ca.kc_target = d_kt; ca.cand_off = d_co; ca.m = m;
   ca.nsample_q = pa.nsample_q; ca.bcap = bcap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
+  ca.bnd_scratch = reinterpret_cast<uint64_t*>(A + L.cand_packed);
   ca.n_cand = reinterpret_cast<int64_t*>(A + L.n_cand);
   ca.sample_keys = sample_keys; ca.sample_off = d_so; ca.books = books;
   ca.surv_key = surv_key; ca.surv_pos = surv_pos; ca.surv_off = d_vo; ca.pair_nsurv = pair_nsurv;

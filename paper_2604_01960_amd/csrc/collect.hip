@@ -361,6 +361,11 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int64_t s = kc - nbelow;
   const int bcap = a.bcap;
   uint32_t* cand = a.cand_pos + a.cand_off[qi];
+  // the threshold bucket's members also go to global scratch (room for
+  // K_c of them), where a larger bucket is selected without another pass
+  // over the survivors
+  uint64_t* bnd = a.bnd_scratch + a.cand_off[qi];
+  const int64_t bnd_cap = a.cand_off[qi + 1] - a.cand_off[qi];
 
   // ---- Collect -----------------------------------------------------------------
   // one atomic per counter for a lane's whole batch
@@ -390,7 +395,9 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
       if (b[u] < tau) cand[basec + (uint32_t)__popcll(mc[u] & lt)] = spos[idx[u]];
       if (b[u] == tau) {
         const uint32_t bs = baseb + (uint32_t)__popcll(mb[u] & lt);
-        if ((int)bs < bcap) bbuf[bs] = pack_key_id(skey[idx[u]], (uint32_t)a.list_ids[spos[idx[u]]]);
+        const uint64_t pk = pack_key_id(skey[idx[u]], (uint32_t)a.list_ids[spos[idx[u]]]);
+        if ((int)bs < bcap) bbuf[bs] = pk;
+        if ((int64_t)bs < bnd_cap) bnd[bs] = pk;
       }
       basec += (uint32_t)__popcll(mc[u]);
       baseb += (uint32_t)__popcll(mb[u]);
@@ -405,6 +412,17 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     lds_bitonic_sort<NT>(bbuf, P);
     for (int64_t r = threadIdx.x; r < s; r += NT)
       cand[nbelow + r] = (uint32_t)a.pos_of_id[packed_id(bbuf[r])];
+  } else if (nb <= bnd_cap) {
+    // the s smallest (key, id) of the members gathered in global scratch:
+    // radix select of the s-th, then one pass over the members
+    const uint64_t thr =
+        block_radix_select64<NT>([&](int64_t i, uint64_t& v) { v = bnd[i]; return true; }, nb, s - 1, hist, bc);
+    if (threadIdx.x == 0) bc[6] = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nb; i += NT) {
+      const uint64_t v = bnd[i];
+      if (v <= thr) cand[nbelow + atomicAdd(&bc[6], 1u)] = (uint32_t)a.pos_of_id[packed_id(v)];
+    }
   } else {
     // exact selection of the s smallest (key, id) of the threshold bucket:
     // 64-bit radix select over its members, then one pass to collect them

@@ -92,6 +92,7 @@ struct CollectArgs {
   float* surv_key; uint32_t* surv_pos; const int64_t* surv_off; uint32_t* pair_nsurv; uint32_t* n_rejected;
   uint32_t* surv_total;     // [nq] survivors per query (written by the collector)
   uint8_t* surv_bucket;     // bucket of each survivor (collector scratch, same slots as surv_key)
+  uint64_t* bnd_scratch;    // [sum K_c] the threshold bucket's (key, id), by cand_off (free until the re-rank)
   // trace outputs (all null when tracing is off)
   float* t_dmin; float* t_delta; uint8_t* t_map; int32_t* t_tau; int64_t* t_s; int32_t* t_counts;
   int64_t* t_nboundary;

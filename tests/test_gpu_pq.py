@@ -100,3 +100,26 @@ def test_repeat_and_device_io(bbc):
     np.testing.assert_array_equal(ids.cpu().numpy(), a[0])
     np.testing.assert_array_equal(dists.cpu().numpy(), a[1])
     np.testing.assert_array_equal(counts.cpu().numpy(), a[2])
+
+
+@pytest.mark.parametrize("bcap", [64, 4096])
+def test_large_threshold_buckets(bbc, bcap):
+    """Threshold buckets larger than the LDS sort capacity: their members are
+    selected from global scratch (or, beyond K_c members, by passes over the
+    survivors); both give the oracle's candidates (few buckets, large k)."""
+    import os
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 20000, 64, 16, 8, 10)
+    os.environ["BBC_COLLECT_BCAP"] = str(bcap)
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        del os.environ["BBC_COLLECT_BCAP"]
+    k = np.array([300, 900, 2500, 4000, 1200, 700, 3000, 150, 5000, 2000], np.int32)
+    npb = np.array([6, 12, 20, 30, 9, 64, 25, 3, 40, 15], np.int32)
+    for m in (4, 16, 64):
+        print(f"[case] large threshold buckets bcap={bcap} m={m}", flush=True)
+        tr = g.search_traced(q, k, npb, ratio=2.0, buckets=m, nsample=8)
+        exp = expected_steps(ix, q, k, npb, 2.0, m, 8)
+        check_trace(tr, exp, m)
+        if bcap == 64:
+            assert np.any(tr["n_boundary"] > 64)
