@@ -669,7 +669,7 @@ namespace {
 
 struct Layout {
   // offsets into the arena
-  size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
+  size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb;
@@ -1002,6 +1002,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.books = pl.add(sizeof(bbc::QueryBook) * nq);
   L.pair_cnt = pl.add(4 * 2 * (size_t)ix->nlist);
   L.sorted_pairs = pl.add(4 * bbc::pair_slots(npairs, ix->nlist));
+  L.sorted_q = pl.add(4 * bbc::pair_slots(npairs, ix->nlist));
   L.pair_split = pl.add(8);
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
@@ -1109,6 +1110,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   sa.scan_variant = ix->scan_variant;
   sa.pair_cnt = reinterpret_cast<uint32_t*>(A + L.pair_cnt);
   sa.sorted_pairs = reinterpret_cast<uint32_t*>(A + L.sorted_pairs);
+  sa.sorted_q = reinterpret_cast<uint32_t*>(A + L.sorted_q);
   sa.pair_split = reinterpret_cast<uint32_t*>(A + L.pair_split);
   sa.nsample_q = pa.nsample_q; sa.sample_keys = sample_keys; sa.sample_off = d_so; sa.books = books;
   sa.surv_key = surv_key; sa.surv_pos = surv_pos; sa.surv_off = d_vo; sa.pair_nsurv = pair_nsurv;

@@ -62,6 +62,7 @@ struct PqScanArgs {
   int nlist; int64_t npairs; int num_cu; int nxcd;
   uint32_t* pair_cnt;       // [2*nlist] scratch
   uint32_t* sorted_pairs;   // [npairs] scratch: sample pairs then the rest, each grouped by list
+  uint32_t* sorted_q;       // [pair slots] the query of each sorted pair (NO_PAIR slots: unused)
   // pairs scanned by this launch: sorted_pairs[0, split) for mode 0 and
   // [split, total) for mode 1, with pair_split = {split, total} (bins padded
   // to SCAN_GROUP entries with NO_PAIR)

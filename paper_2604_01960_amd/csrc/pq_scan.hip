@@ -86,8 +86,12 @@ __global__ __launch_bounds__(1024) void pair_offsets_kernel(uint32_t* __restrict
 
 __global__ void pair_scatter_kernel(PqScanArgs a) {
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < a.npairs; p += (int64_t)gridDim.x * blockDim.x) {
-    uint32_t slot = atomicAdd(&a.pair_cnt[pair_bin(a, p)], 1u);
+    const int64_t qi = find_query(a.probe_off, a.nq, p);
+    const int rank = (int)(p - a.probe_off[qi]);
+    const int bin = (rank >= a.nsample_q[qi] ? a.nlist : 0) + a.probe_lists[p];
+    const uint32_t slot = atomicAdd(&a.pair_cnt[bin], 1u);
     a.sorted_pairs[slot] = (uint32_t)p;
+    a.sorted_q[slot] = (uint32_t)qi;
   }
 }
 
@@ -218,16 +222,29 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   const int64_t span = cend - cbeg;
   const int64_t lo = cbeg + span * xcd / nx;
   const int64_t hi = cbeg + span * (xcd + 1) / nx;
+  // a group's pairs, their queries and list are loaded one group ahead, so
+  // that those loads overlap the previous group's table build and scan
+  uint32_t npp[G];
+  int64_t nqq[G];
+  auto load_group = [&](int64_t cg) {
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      npp[g] = uniform(a.sorted_pairs[cg * G + g]);
+      nqq[g] = npp[g] != NO_PAIR ? (int64_t)uniform(a.sorted_q[cg * G + g]) : 0;
+    }
+  };
+  if (lo + wid < hi) load_group(lo + wid);
   for (int64_t c = lo + wid; c < hi; c += nw) {
     uint32_t pp[G];
     int64_t qq[G];
     bool valid[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      pp[g] = uniform(a.sorted_pairs[c * G + g]);
+      pp[g] = npp[g];
+      qq[g] = nqq[g];
       valid[g] = pp[g] != NO_PAIR;
-      qq[g] = valid[g] ? uniform(find_query(a.probe_off, a.nq, pp[g])) : 0;
     }
+    if (c + nw < hi) load_group(c + nw);
     const int j = uniform(a.probe_lists[pp[0]]);  // the first pair of a group is always real
     const float* cv = a.cent + (int64_t)j * D;
     __syncthreads();  // the previous group is done with res and the tables
@@ -373,7 +390,7 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   const uint32_t pv = a.sorted_pairs[it];
   if (pv == NO_PAIR) return;
   const int64_t p = pv;
-  const int64_t qi = find_query(a.probe_off, a.nq, p);
+  const int64_t qi = a.sorted_q[it];
   const int j = a.probe_lists[p];
   const float* qv = a.q + qi * a.d;
   const float* cv = a.cent + (int64_t)j * a.d;
