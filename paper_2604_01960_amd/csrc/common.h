@@ -136,6 +136,15 @@ __device__ __forceinline__ int64_t uniform(int64_t v) {
   const uint32_t lo = uniform((uint32_t)v), hi = uniform((uint32_t)((uint64_t)v >> 32));
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
+// The value lane l of the wave holds (l wave-uniform), in a scalar register.
+__device__ __forceinline__ uint32_t lane_value(uint32_t v, int l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, l);
+}
+__device__ __forceinline__ int32_t lane_value(int32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ int64_t lane_value(int64_t v, int l) {
+  const uint32_t lo = lane_value((uint32_t)v, l), hi = lane_value((uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 template <class T>
 __device__ __forceinline__ T* uniform(T* p) {
   return reinterpret_cast<T*>(uniform((int64_t)reinterpret_cast<uintptr_t>(p)));

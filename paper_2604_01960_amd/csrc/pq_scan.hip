@@ -159,6 +159,8 @@ struct PairOut {
   uint32_t* spos;
   float* trace_out;
   uint32_t prune, dmax_bits;
+  // loads only (everything a pair's output needs), so that a group's outputs
+  // can be fetched while the previous group is being scanned
   __device__ __forceinline__ void init(const PqScanArgs& a, int mode, int64_t qi, int64_t p) {
     const int64_t ro = uniform(a.rank_off[p]);
     trace_out = a.trace_keys ? uniform(a.trace_keys + a.key_off[qi] + ro) : nullptr;
@@ -222,40 +224,108 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   const int64_t span = cend - cbeg;
   const int64_t lo = cbeg + span * xcd / nx;
   const int64_t hi = cbeg + span * (xcd + 1) / nx;
-  // a group's pairs, their queries and list are loaded one group ahead, so
-  // that those loads overlap the previous group's table build and scan
-  uint32_t npp[G];
-  int64_t nqq[G];
-  auto load_group = [&](int64_t cg) {
-#pragma unroll
-    for (int g = 0; g < G; ++g) {
-      npp[g] = uniform(a.sorted_pairs[cg * G + g]);
-      nqq[g] = npp[g] != NO_PAIR ? (int64_t)uniform(a.sorted_q[cg * G + g]) : 0;
+  // A group's pairs, queries, list and output places, and its residual
+  // inputs, are fetched while the previous group is processed, by vector
+  // loads (lane g of each wave holding pair g) so that the LDS waits of that
+  // group do not also wait for them: pairs and queries when the previous
+  // group starts, places after its table build, the query and centroid
+  // values after its first scan pass.
+  const int lane = threadIdx.x & 63;
+  constexpr int RPT = (G * D + NT - 1) / NT;  // residual inputs per thread
+  uint32_t f_pp = NO_PAIR, f_prune = 0, f_dmax = 0;
+  int64_t f_qq = 0, f_ro = 0, f_base = 0, f_tr = 0;
+  int32_t f_j = 0;
+  float f_q[RPT], f_c[RPT];
+  auto fetch_pairs = [&](int64_t cg) {
+    const int g = lane & (G - 1);
+    f_pp = a.sorted_pairs[cg * G + g];
+    f_qq = (int64_t)a.sorted_q[cg * G + g];  // meaningless (never used) for an empty slot
+  };
+  auto fetch_places = [&]() {
+    if (f_pp != NO_PAIR) {
+      f_ro = a.rank_off[f_pp];
+      f_j = a.probe_lists[f_pp];
+      if (a.trace_keys) f_tr = a.key_off[f_qq];
+      if (MODE == 0) {
+        f_base = a.sample_off[f_qq];
+      } else {
+        f_base = a.surv_off[f_qq];
+        f_prune = a.books[f_qq].prune;
+        f_dmax = a.books[f_qq].dmax_bits;
+      }
     }
   };
-  if (lo + wid < hi) load_group(lo + wid);
-  for (int64_t c = lo + wid; c < hi; c += nw) {
+  auto fetch_inputs = [&]() {
+    const int64_t jn = lane_value(f_j, 0);  // the first pair of a group is always real
+    bool vn[G];
+    int64_t qn[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      vn[g] = lane_value(f_pp, g) != NO_PAIR;
+      qn[g] = lane_value(f_qq, g);
+    }
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      f_q[r] = 0.0f;
+      f_c[r] = 0.0f;
+      if (idx < G * D) {
+        const int g = idx / D, e = idx % D;
+        f_c[r] = a.cent[jn * D + e];
+#pragma unroll
+        for (int h = 0; h < G; ++h)
+          if (h == g && vn[h]) f_q[r] = a.q[qn[h] * D + e];
+      }
+    }
+  };
+  const int64_t c0 = lo + wid;
+  if (c0 < hi) {
+    fetch_pairs(c0);
+    fetch_places();
+    fetch_inputs();
+  }
+  for (int64_t c = c0; c < hi; c += nw) {
     uint32_t pp[G];
     int64_t qq[G];
     bool valid[G];
+    PairOut out[G];
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      pp[g] = npp[g];
-      qq[g] = nqq[g];
+      pp[g] = lane_value(f_pp, g);
+      qq[g] = lane_value(f_qq, g);
       valid[g] = pp[g] != NO_PAIR;
+      if (valid[g]) {
+        const int64_t ro = lane_value(f_ro, g), base = lane_value(f_base, g);
+        out[g].trace_out = a.trace_keys ? a.trace_keys + lane_value(f_tr, g) + ro : nullptr;
+        if (MODE == 0) {
+          out[g].sample_out = a.sample_keys + base + ro;
+          out[g].prune = 0;
+          out[g].dmax_bits = 0;
+        } else {
+          out[g].prune = lane_value(f_prune, g);
+          out[g].dmax_bits = lane_value(f_dmax, g);
+          out[g].skey = a.surv_key + base + ro;
+          out[g].spos = a.surv_pos + base + ro;
+        }
+      }
     }
-    if (c + nw < hi) load_group(c + nw);
-    const int j = uniform(a.probe_lists[pp[0]]);  // the first pair of a group is always real
-    const float* cv = a.cent + (int64_t)j * D;
+    const int j = lane_value(f_j, 0);
+    float rq[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) rq[r] = f_q[r] - f_c[r];  // r = q - c, once per element
+    if (c + nw < hi) fetch_pairs(c + nw);
     __syncthreads();  // the previous group is done with res and the tables
-    for (int idx = threadIdx.x; idx < G * D; idx += NT) {
-      const int g = idx / D, e = idx % D;
-      float r = 0.0f;
-      if (g == 0) r = a.q[qq[0] * D + e] - cv[e];
-      else if (g == 1 && valid[1]) r = a.q[qq[1] * D + e] - cv[e];
-      else if (g == 2 && valid[2]) r = a.q[qq[2] * D + e] - cv[e];
-      else if (g == 3 && valid[3]) r = a.q[qq[3] * D + e] - cv[e];
-      res[g][e] = r;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int idx = threadIdx.x + r * NT;
+      if (idx < G * D) {
+        const int g = idx / D, e = idx % D;
+        bool v = false;
+#pragma unroll
+        for (int h = 0; h < G; ++h)
+          if (h == g) v = valid[h];
+        res[g][e] = v ? rq[r] : 0.0f;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -286,12 +356,9 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
       asm volatile("" ::: "memory");  // one entry's LDS reads at a time
     }
     __syncthreads();
+    if (c + nw < hi) fetch_places();
     const int64_t lbeg = uniform(a.list_off[j]);
     const int64_t nobj = uniform(a.list_off[j + 1]) - lbeg;
-    PairOut out[G];
-#pragma unroll
-    for (int g = 0; g < G; ++g)
-      if (valid[g]) out[g].init(a, MODE, qq[g], pp[g]);
     BlockCompactor<G, NT, O> comp;
     comp.reset();
     const uint8_t* codes = a.codes + lbeg * (NVEC * 16);
@@ -332,6 +399,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
           acc[o][3] = acc[o][3] + v.w;
         }
       }
+      if (base == 0 && c + nw < hi) fetch_inputs();
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         const int64_t i = base + o * NT + threadIdx.x;
