@@ -1,6 +1,5 @@
-// IVF probe (routing to the nprobe nearest lists; background section of the
-// paper, "The IVF index ... routes each query to the n_probe nearest
-// clusters").
+// IVF probe: each query is routed to its nprobe nearest lists (the IVF
+// index of the paper's background section, quantization methods).
 //
 // Step 1 (probe_gemm): D'[q][j] = |c_j|^2 - 2 <q~, c~_j>  (L2) or -<q~, c~_j>
 //   (inner product) on BF16 MFMA with FP32 accumulation, q~ and c~ the
