@@ -833,6 +833,8 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   sa.rank_off = pa.rank_off; sa.key_off = d_ko; sa.q = dq; sa.qrot = qrot; sa.rot_cent = ix->rot_cent;
   sa.D = d; sa.metric = ix->metric; sa.eps0 = ix->eps0; sa.list_off = ix->list_off; sa.codes = ix->rq_codes;
   sa.code_words = ix->rq_words; sa.factors = ix->rq_factors;
+  sa.max_np = 1;
+  for (int64_t i = 0; i < nq; ++i) sa.max_np = std::max(sa.max_np, (int)nprobe[i]);
   sa.lb = reinterpret_cast<float*>(A + L_lb);
   sa.ub = reinterpret_cast<float*>(A + L_ub);
   sa.key = tracing ? reinterpret_cast<float*>(A + L_key) : nullptr;

@@ -153,6 +153,8 @@ struct RabitqScanArgs {
   int D; int metric; float eps0;
   const int64_t* list_off; const uint32_t* codes; int code_words; const float* factors;
   float* lb; float* ub; float* key;  // [sum S] by slot at key_off[q]; key optional
+  int max_np;               // largest nprobe of the batch (the 2-D grid's first dimension)
+  int grid2d;               // set by the launcher
 };
 hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s);
 

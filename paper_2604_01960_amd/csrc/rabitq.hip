@@ -180,19 +180,31 @@ hipError_t launch_rabitq_encode(const RabitqBuildArgs& a, int64_t p0, int64_t n,
 // ---- scan: bounds of every object of a (query, list) pair --------------------------
 constexpr int RQ_MAXD = 2048;
 constexpr int RQ_MAXW = RQ_MAXD / 32;
+constexpr int RQ_MAXW_ROW = 32;  // code words per row held in registers (d <= 1024)
 
+// Block (rank r, query q) of a 2-D grid, or block p of the pairs when the
+// batch has more queries than a grid's second dimension holds.  The four
+// planes of code word w sit side by side in LDS (one 16-byte read), and each
+// thread takes two objects, their whole code rows loaded before any popcount.
 __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
   constexpr int NT = 256;
+  constexpr int OBJ = 2;                  // objects per thread per pass
+  constexpr int CV = RQ_MAXW_ROW / 4;     // 16-byte pieces of a code row
   __shared__ float ys[RQ_MAXD];
-  __shared__ uint32_t planes[4 * RQ_MAXW];
+  __shared__ uint4 planes4[RQ_MAXW];
   __shared__ float red_f[2][NT / 64];
   __shared__ uint32_t red_u[NT / 64];
   __shared__ float scal[8];
 
-  const int64_t p = blockIdx.x;
-  if (p >= a.npairs) return;
-  int64_t qi;
-  {
+  int64_t p, qi;
+  if (a.grid2d) {
+    qi = blockIdx.y;
+    const int64_t pb = a.probe_off[qi], pe = a.probe_off[qi + 1];
+    p = pb + blockIdx.x;
+    if (p >= pe) return;
+  } else {
+    p = blockIdx.x;
+    if (p >= a.npairs) return;
     int64_t lo = 0, hi = a.nq - 1;  // largest query with probe_off[q] <= p
     while (lo < hi) {
       const int64_t mid = (lo + hi + 1) >> 1;
@@ -211,7 +223,7 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
     vmin = fminf(vmin, y);
     vmax = fmaxf(vmax, y);
   }
-  for (int i = threadIdx.x; i < 4 * W; i += NT) planes[i] = 0u;
+  for (int i = threadIdx.x; i < W; i += NT) planes4[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int off = 32; off >= 1; off >>= 1) {
     vmin = fminf(vmin, __shfl_xor(vmin, off));
     vmax = fmaxf(vmax, __shfl_xor(vmax, off));
@@ -234,9 +246,10 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
       u = t < 0.0f ? 0u : (t > 15.0f ? 15u : (uint32_t)t);
     }
     su += u;
+    uint32_t* pw = reinterpret_cast<uint32_t*>(&planes4[i / 32]);
 #pragma unroll
     for (int b = 0; b < 4; ++b)
-      if ((u >> b) & 1u) atomicOr(&planes[b * W + i / 32], 1u << (i % 32));
+      if ((u >> b) & 1u) atomicOr(pw + b, 1u << (i % 32));
   }
   for (int off = 32; off >= 1; off >>= 1) su += __shfl_xor(su, off);
   if ((threadIdx.x & 63) == 0) red_u[threadIdx.x >> 6] = su;
@@ -267,60 +280,86 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
   const float epsc = a.eps0 / sqrtf((float)(D - 1));
   const int64_t lbeg = a.list_off[j], nobj = a.list_off[j + 1] - lbeg;
   const int64_t out0 = a.key_off[qi] + a.rank_off[p];
-  const int CW = a.code_words;
-  for (int64_t t = threadIdx.x; t < nobj; t += NT) {
-    const uint32_t* code = a.codes + (lbeg + t) * CW;
-    uint32_t c[4] = {0u, 0u, 0u, 0u};
-    for (int w4 = 0; w4 < CW; w4 += 4) {
-      const uint4 cv = *reinterpret_cast<const uint4*>(code + w4);
-      const uint32_t cw[4] = {cv.x, cv.y, cv.z, cv.w};
+  const int CW = a.code_words;  // a multiple of 4, at most RQ_MAXW_ROW
+  for (int64_t t0 = threadIdx.x; t0 < nobj; t0 += OBJ * NT) {
+    uint4 cv[OBJ][CV];
+    float4 fac[OBJ];
+    bool act[OBJ];
+#pragma unroll
+    for (int o = 0; o < OBJ; ++o) {
+      const int64_t t = t0 + o * NT;
+      act[o] = t < nobj;
+      const uint4* row = reinterpret_cast<const uint4*>(a.codes + (lbeg + (act[o] ? t : 0)) * CW);
+#pragma unroll
+      for (int v = 0; v < CV; ++v) cv[o][v] = (act[o] && 4 * v < CW) ? row[v] : make_uint4(0u, 0u, 0u, 0u);
+      fac[o] = act[o] ? reinterpret_cast<const float4*>(a.factors)[lbeg + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    uint32_t c[OBJ][4];
+#pragma unroll
+    for (int o = 0; o < OBJ; ++o) c[o][0] = c[o][1] = c[o][2] = c[o][3] = 0u;
+#pragma unroll
+    for (int v = 0; v < CV; ++v) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const int w = w4 + u;
+        const int w = 4 * v + u;
         if (w < W) {
+          const uint4 pv = planes4[w];
 #pragma unroll
-          for (int b = 0; b < 4; ++b) c[b] += (uint32_t)__popc(cw[u] & planes[b * W + w]);
+          for (int o = 0; o < OBJ; ++o) {
+            const uint32_t cw = u == 0 ? cv[o][v].x : u == 1 ? cv[o][v].y : u == 2 ? cv[o][v].z : cv[o][v].w;
+            c[o][0] += (uint32_t)__popc(cw & pv.x);
+            c[o][1] += (uint32_t)__popc(cw & pv.y);
+            c[o][2] += (uint32_t)__popc(cw & pv.z);
+            c[o][3] += (uint32_t)__popc(cw & pv.w);
+          }
         }
       }
     }
-    const int64_t ip = (int64_t)c[0] + 2 * (int64_t)c[1] + 4 * (int64_t)c[2] + 8 * (int64_t)c[3];
-    const float4 fac = reinterpret_cast<const float4*>(a.factors)[lbeg + t];
-    float est = c1 * (float)ip;
-    const float tpc = c2 * fac.w;
-    est = est + tpc;
-    est = est - c3;
-    est = est - c4;
-    est = est * fac.y;
-    const float nr = fac.x;
-    float key, e;
-    if (a.metric == 0) {
-      float tt = nr * nr;
-      tt = tt + av;
-      float uu = 2.0f * nr;
-      uu = uu * est;
-      key = tt - uu;
-      e = 2.0f * nr;
-      e = e * nq;
-      e = e * fac.z;
-      e = e * epsc;
-    } else {
-      float vv = nr * est;
-      vv = av + vv;
-      key = -vv;
-      e = nr * qnv;
-      e = e * fac.z;
-      e = e * epsc;
+#pragma unroll
+    for (int o = 0; o < OBJ; ++o) {
+      if (!act[o]) continue;
+      const int64_t t = t0 + o * NT;
+      const int64_t ip = (int64_t)c[o][0] + 2 * (int64_t)c[o][1] + 4 * (int64_t)c[o][2] + 8 * (int64_t)c[o][3];
+      float est = c1 * (float)ip;
+      const float tpc = c2 * fac[o].w;
+      est = est + tpc;
+      est = est - c3;
+      est = est - c4;
+      est = est * fac[o].y;
+      const float nr = fac[o].x;
+      float key, e;
+      if (a.metric == 0) {
+        float tt = nr * nr;
+        tt = tt + av;
+        float uu = 2.0f * nr;
+        uu = uu * est;
+        key = tt - uu;
+        e = 2.0f * nr;
+        e = e * nq;
+        e = e * fac[o].z;
+        e = e * epsc;
+      } else {
+        float vv = nr * est;
+        vv = av + vv;
+        key = -vv;
+        e = nr * qnv;
+        e = e * fac[o].z;
+        e = e * epsc;
+      }
+      a.lb[out0 + t] = key - e;
+      a.ub[out0 + t] = key + e;
+      if (a.key) a.key[out0 + t] = key;
     }
-    a.lb[out0 + t] = key - e;
-    a.ub[out0 + t] = key + e;
-    if (a.key) a.key[out0 + t] = key;
   }
 }
 
 hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
   if (a.npairs <= 0) return hipSuccess;
-  if (a.D > RQ_MAXD || a.D % 64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(rabitq_scan_kernel, dim3((unsigned)a.npairs), dim3(256), 0, s, a);
+  if (a.D > 32 * RQ_MAXW_ROW || a.D % 64 || a.code_words > RQ_MAXW_ROW || a.code_words % 4) return hipErrorInvalidValue;
+  RabitqScanArgs b = a;
+  b.grid2d = a.nq <= 65535 && a.max_np >= 1;
+  const dim3 g = b.grid2d ? dim3((unsigned)a.max_np, (unsigned)a.nq) : dim3((unsigned)a.npairs);
+  hipLaunchKernelGGL(rabitq_scan_kernel, g, dim3(256), 0, s, b);
   return hipGetLastError();
 }
 
