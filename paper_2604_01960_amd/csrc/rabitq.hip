@@ -562,9 +562,10 @@ __global__ __launch_bounds__(256) void rabitq_exact_kernel(RabitqWalkArgs a) {
   }
 }
 
+constexpr int WK_NT = 1024;
 template <typename T>
-__global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
-  constexpr int NT = 1024;
+__global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
+  constexpr int NT = WK_NT;
   constexpr int NW = NT / 64;
   __shared__ int32_t s_rbeg[WK_RANKCAP];
   __shared__ int32_t s_lbeg[WK_RANKCAP];
@@ -598,6 +599,20 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
   uint64_t* zA = a.zbuf + 2 * a.key_off[qi];
   uint64_t* zB = zA + capq;
 
+  // number of the n images get(i) strictly below L (block-wide; bc[15] as
+  // the counter; ends with a barrier)
+  auto count_below = [&](int64_t n, auto get, uint32_t L) -> int64_t {
+    if (threadIdx.x == 0) bc[15] = 0;
+    __syncthreads();
+    uint32_t cnt = 0;
+    block_for_batched<NT, WK_U>(n, get, [&](int64_t, bool valid, uint32_t v) { cnt += (valid && v < L) ? 1u : 0u; });
+    for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off);
+    if (lane == 0 && cnt) atomicAdd(&bc[15], cnt);
+    __syncthreads();
+    const int64_t r = bc[15];
+    __syncthreads();
+    return r;
+  };
   // the bins of C: computed here, or (wide form) read back with the exact
   // keys of all of C already in pbuf
   WalkBins w;
@@ -757,13 +772,14 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
         const int P2 = next_pow2((int)nQ);
         for (int i = (int)nQ + threadIdx.x; i < P2; i += NT) { chunk_v[i] = ~0ull; chunk_x[i] = ~0ull; }
         lds_bitonic_sort_kv<NT>(chunk_v, chunk_x, P2);
-        // first t in [lo, nQ) with lb(Q[t]) > the k-th key of Z0 and Q[0, t)
+        // first t in [lo, nQ) with lb(Q[t]) > the k-th key of Z0 and Q[0, t),
+        // i.e. with at least k of those keys below lb(Q[t])
         while (lo < hi) {
           const int64_t t = (lo + hi) >> 1;
-          const uint32_t kth = block_radix_select32<NT>(
-              [&](int64_t i) { return (uint32_t)((i < nz0 ? zB[i] : chunk_x[i - nz0]) >> 32); }, nz0 + t, k - 1,
-              rhist, bc);
-          if ((uint32_t)(chunk_v[t] >> 32) > kth) hi = t; else lo = t + 1;
+          const uint32_t L = (uint32_t)(chunk_v[t] >> 32);
+          const int64_t below = count_below(
+              nz0 + t, [&](int64_t i) { return (uint32_t)((i < nz0 ? zB[i] : chunk_x[i - nz0]) >> 32); }, L);
+          if (below >= k) hi = t; else lo = t + 1;
         }
         if (lo < nQ) cut = chunk_v[lo];
       } else {
@@ -777,15 +793,17 @@ __global__ __launch_bounds__(1024) void rabitq_walk_kernel(RabitqWalkArgs a) {
         while (lo < hi) {
           const int64_t t = (lo + hi) >> 1;
           const uint64_t kt = block_radix_select64<NT>(qkey, p, t, rhist, bc);
-          const uint32_t kth = block_radix_select32<NT>(
+          const uint32_t L = (uint32_t)(kt >> 32);
+          const int64_t below = count_below(
+              nz0 + p,
               [&](int64_t i) -> uint32_t {
                 if (i < nz0) return (uint32_t)(zB[i] >> 32);
                 uint64_t v;
                 const bool inq = qkey(i - nz0, v);
                 return (inq && v < kt) ? (uint32_t)(pbuf[i - nz0] >> 32) : 0xffffffffu;
               },
-              nz0 + p, k - 1, rhist, bc);
-          if ((uint32_t)(kt >> 32) > kth) hi = t; else lo = t + 1;
+              L);
+          if (below >= k) hi = t; else lo = t + 1;
         }
         if (lo < nQ) cut = block_radix_select64<NT>(qkey, p, lo, rhist, bc);
       }
@@ -905,8 +923,8 @@ hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s) {
     if (a.fp16) hipLaunchKernelGGL(rabitq_exact_kernel<__half>, g, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(rabitq_exact_kernel<float>, g, dim3(256), 0, s, a);
   }
-  if (a.fp16) hipLaunchKernelGGL(rabitq_walk_kernel<__half>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
-  else hipLaunchKernelGGL(rabitq_walk_kernel<float>, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  if (a.fp16) hipLaunchKernelGGL(rabitq_walk_kernel<__half>, dim3((unsigned)a.nq), dim3(WK_NT), 0, s, a);
+  else hipLaunchKernelGGL(rabitq_walk_kernel<float>, dim3((unsigned)a.nq), dim3(WK_NT), 0, s, a);
   return hipGetLastError();
 }
 
