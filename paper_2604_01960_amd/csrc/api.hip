@@ -955,7 +955,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   // host-side metadata: per query k, nprobe, and prefix offsets
   std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq),
       sample_off(nq + 1, 0), surv_off(nq + 1, 0);
-  int64_t max_kc = 0;
+  int64_t max_kc = 0, max_scap = 0;
   const int64_t max_list = ix->h_maxS[1];
   for (int64_t i = 0; i < nq; ++i) {
     probe_off[i + 1] = probe_off[i] + nprobe[i];
@@ -966,6 +966,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
                                             std::max(ix->h_maxS[std::min(nsample, nprobe[i])],
                                                      (int64_t)sample_factor * cap + max_list));
     sample_off[i + 1] = sample_off[i] + scap;
+    max_scap = std::max(max_scap, scap);
     surv_off[i + 1] = surv_off[i] + (bucket ? ix->h_maxS[nprobe[i]] : 0);
     key_off[i + 1] = key_off[i] + (tracing ? ix->h_maxS[nprobe[i]] : 0);
     kc_target[i] = (int64_t)std::ceil(p->ncand_ratio * (double)k[i]);
@@ -1123,7 +1124,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ca.nq = nq; ca.n_scanned = pa.n_scanned; ca.nprobe = d_np;
   ca.probe_off = d_po; ca.probe_lists = pa.probe_lists; ca.rank_off = pa.rank_off; ca.list_off = ix->list_off;
   ca.list_ids = ix->list_ids; ca.pos_of_id = ix->pos_of_id; ca.kc_target = d_kt; ca.cand_off = d_co; ca.m = m;
-  ca.nsample_q = pa.nsample_q; ca.bcap = bcap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
+  ca.nsample_q = pa.nsample_q; ca.bcap = bcap; ca.max_sample = max_scap; ca.cand_pos = reinterpret_cast<uint32_t*>(A + L.cand_pos);
   ca.bnd_scratch = reinterpret_cast<uint64_t*>(A + L.cand_packed);
   ca.n_cand = reinterpret_cast<int64_t*>(A + L.n_cand);
   ca.sample_keys = sample_keys; ca.sample_off = d_so; ca.books = books;

@@ -33,6 +33,7 @@ namespace bbc {
 
 constexpr int COLLECT_RANKCAP = 2048;
 constexpr int COLLECT_CHUNKCAP = 4096;  // 64-survivor chunks mapped to their run by an LDS table
+template <int N> struct Unroll { static constexpr int value = N; };
 constexpr int COLLECT_UNROLL = 4;       // chunks a wave has in flight
 
 __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restrict__ rank_off,
@@ -46,11 +47,18 @@ __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restr
   return list_off[lists[lo]] + (i - rank_off[lo]);
 }
 
+// Keys of the sample held in registers per thread, as their 32-bit images:
+// key j * 1024 + t in slot j of thread t.  R = 0 reads them from memory in
+// every pass instead; a query whose sample exceeds 1024 * R keys takes that
+// path too.
+template <int R>
 __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
-  constexpr int NT = 1024;
-  __shared__ uint32_t hist[256];
+  constexpr int NT = 1024, NW = NT / 64;
+  constexpr int SEL_BITS = 12;  // bits of the key image resolved per select pass
+  __shared__ uint32_t hist[1 << SEL_BITS];
   __shared__ uint8_t cmap[256];
   __shared__ __align__(8) uint32_t bc[8];
+  __shared__ uint32_t s_wred[2][NW];
   __shared__ float fbc[2];
 
   const int64_t qi = blockIdx.x;
@@ -64,6 +72,7 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
   const float* keys = a.sample_keys + a.sample_off[qi];
   const int m = a.m;
   QueryBook* book = a.books + qi;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
 
   const int nsr = a.nsample_q[qi];
   const int64_t Ts = nsr < np ? rank_off[nsr] : S;
@@ -75,43 +84,157 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
       s_rbeg[r] = (int32_t)rank_off[r];
       s_lbeg[r] = (int32_t)a.list_off[lists[r]];
     }
-  auto pos_of = [&](int64_t i) -> int64_t {
+  // list position of sample slot i; r is the probe rank of the previous slot
+  // this thread asked for (slots are asked for in increasing order), and
+  // becomes the rank of i
+  auto pos_at = [&](int64_t i, int& r) -> int64_t {
     if (!lds_ranks) return slot_to_pos(i, rank_off, lists, a.list_off, nsr);
-    int lo = 0, hi = nsr - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (s_rbeg[mid] <= i) lo = mid; else hi = mid - 1;
+    if (r + 1 < nsr && (int64_t)s_rbeg[r + 1] <= i) {
+      int lo = r + 1, hi = nsr - 1;
+      if (lo < hi && (int64_t)s_rbeg[lo + 1] > i) hi = lo;  // usually the next list
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_rbeg[mid] <= i) lo = mid; else hi = mid - 1;
+      }
+      r = lo;
     }
-    return (int64_t)s_lbeg[lo] + (i - s_rbeg[lo]);
+    return (int64_t)s_lbeg[r] + (i - s_rbeg[r]);
   };
+
+  // the sample's key images, once from memory into registers when they fit
+  uint32_t kv[R > 0 ? R : 1];
+  const bool in_regs = R > 0 && Ts > 0 && Ts <= (int64_t)NT * R;
+  if constexpr (R > 0) {
+    if (in_regs) {
+      // unconditional loads (slots past the end read the last key), all
+      // issued before any key is converted to its image
+      const int last = (int)Ts - 1;
+#pragma unroll
+      for (int j = 0; j < R; ++j) kv[j] = __float_as_uint(keys[min(j * NT + (int)threadIdx.x, last)]);
+#pragma unroll
+      for (int j = 0; j < R; ++j) kv[j] = key_bits(__uint_as_float(kv[j]));
+    }
+  }
+  // use(i, valid, image) for every sample slot i, in increasing i per
+  // thread, the same block-uniform number of times on every lane (valid =
+  // false past Ts).  In registers, rows j < jfull are whole and row jfull
+  // holds the tail (validity from two values, nothing kept per row).
+  const int jfull = (int)(Ts / NT);
+  const bool tail_ok = (int64_t)threadIdx.x < Ts - (int64_t)jfull * NT;
+  const bool tail_rows = Ts > (int64_t)jfull * NT;  // row jfull holds keys
+  auto each = [&](auto&& use) {
+    if constexpr (R > 0) {
+      if (in_regs) {
+#pragma unroll
+        for (int j = 0; j < R; ++j)
+          if (j < jfull || (j == jfull && tail_rows))
+            use((int64_t)(j * NT + (int)threadIdx.x), j < jfull || tail_ok, kv[j]);
+        return;
+      }
+    }
+    block_for_batched<NT, 4>(Ts, [&](int64_t i) { return key_bits(keys[i]); }, use);
+  };
+
   if (a.t_nsample_keys && threadIdx.x == 0) a.t_nsample_keys[qi] = Ts;
   const int64_t T = kc < Ts ? kc : Ts;
   uint32_t dmax_b = 0;
   if (T > 0) {
-    dmax_b = block_radix_select32<NT>([&](int64_t i) { return key_bits(keys[i]); }, Ts, T - 1, hist, bc);
-    if (threadIdx.x == 0) bc[4] = 0xffffffffu;
+    // smallest and largest image of the sample
+    uint32_t mn = 0xffffffffu, mx = 0u;
+    each([&](int64_t, bool valid, uint32_t v) {
+      if (valid) {
+        mn = min(mn, v);
+        mx = max(mx, v);
+      }
+    });
+    for (int off = 32; off >= 1; off >>= 1) {
+      mn = min(mn, __shfl_xor(mn, off));
+      mx = max(mx, __shfl_xor(mx, off));
+    }
+    if (lane == 0) {
+      s_wred[0][wv] = mn;
+      s_wred[1][wv] = mx;
+    }
     __syncthreads();
-    uint32_t mn = 0xffffffffu;
-    for (int64_t i = threadIdx.x; i < Ts; i += NT) mn = min(mn, key_bits(keys[i]));
-    for (int off = 32; off >= 1; off >>= 1) mn = min(mn, __shfl_xor(mn, off));
-    if ((threadIdx.x & 63) == 0) atomicMin(&bc[4], mn);
+    mn = 0xffffffffu;
+    mx = 0u;
+    for (int w = 0; w < NW; ++w) {
+      mn = min(mn, s_wred[0][w]);
+      mx = max(mx, s_wred[1][w]);
+    }
+    if (threadIdx.x == 0) bc[4] = mn;
+    __syncthreads();
+    // d_max: rank T - 1 of the images, radix-selected over v - mn from the
+    // span's top bit down, SEL_BITS bits a pass (at most three passes)
+    const uint32_t span = mx - mn;
+    int sh = span ? 32 - __clz(span) : 0;  // bits of v - mn still to resolve
+    uint32_t pref = 0;                     // the resolved high bits of v - mn
+    int64_t rr = T - 1;
+    for (bool first = true; sh > 0; first = false) {
+      const int w = sh < SEL_BITS ? sh : SEL_BITS;
+      const int nsh = sh - w;
+      const uint32_t dmask = (1u << w) - 1u;
+      for (int i = threadIdx.x; i < (1 << w); i += NT) hist[i] = 0;
+      __syncthreads();
+      // mn read again after the barrier: v - mn is then formed in the pass
+      // rather than kept for every register slot across the passes
+      const uint32_t mnp = bc[4];
+      each([&](int64_t, bool valid, uint32_t v) {
+        const uint32_t d = v - mnp;
+        if (valid && (first || (d >> sh) == pref)) atomicAdd(&hist[(d >> nsh) & dmask], 1u);
+      });
+      __syncthreads();
+      {
+        // the bin holding rank rr: 4 bins per thread, a block-wide scan
+        uint32_t h[4], sum = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int e = 4 * threadIdx.x + j;
+          h[j] = e < (1 << w) ? hist[e] : 0u;
+          sum += h[j];
+        }
+        const uint32_t incl = wave_incl_scan(sum);
+        if (lane == 63) s_wred[0][wv] = incl;
+        __syncthreads();
+        if (threadIdx.x < 64) {
+          const uint32_t t = threadIdx.x < NW ? s_wred[0][threadIdx.x] : 0u;
+          const uint32_t ti = wave_incl_scan(t);
+          if (threadIdx.x < NW) s_wred[1][threadIdx.x] = ti - t;
+        }
+        __syncthreads();
+        const int64_t excl = (int64_t)s_wred[1][wv] + incl - sum;
+        if (excl <= rr && rr < excl + (int64_t)sum) {
+          int64_t rem = rr - excl;
+          int j = 0;
+          for (; j < 3; ++j) {
+            if (rem < (int64_t)h[j]) break;
+            rem -= h[j];
+          }
+          bc[0] = 4 * threadIdx.x + j;
+          *reinterpret_cast<int64_t*>(bc + 2) = rem;
+        }
+      }
+      __syncthreads();
+      pref = (pref << w) | bc[0];
+      rr = *reinterpret_cast<const int64_t*>(bc + 2);
+      sh = nsh;
+      __syncthreads();
+    }
+    dmax_b = mn + pref;
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    const float dmin = bits_key(bc[4]);
+    const float dmin = bits_key(mn);
     const float dmax = bits_key(dmax_b);
     float delta = (dmax - dmin) / 256.0f;
     if (!(delta > 0.0f)) delta = 1.0f;
-    for (int64_t base = 0; base < Ts; base += NT) {
-      const int64_t i = base + threadIdx.x;
-      const float k = i < Ts ? keys[i] : 0.0f;
-      wave_hist_add(hist, (uint32_t)cell_of(k, dmin, delta), i < Ts && key_bits(k) < dmax_b);
-    }
+    each([&](int64_t, bool valid, uint32_t v) {
+      wave_hist_add(hist, (uint32_t)cell_of(bits_key(v), dmin, delta), valid && v < dmax_b);
+    });
     __syncthreads();
     if (threadIdx.x < 64) {
       // cell counts of the sample's T smallest keys: the keys below d_max as
       // counted, plus (T - their number) copies of d_max in d_max's cell;
       // map[e] = min(m - 1, floor(m * C_<e / T)), one wave, 4 cells per lane
-      const int lane = threadIdx.x;
       uint32_t h[4], sum = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -157,20 +280,56 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
   // the sample's keys through the relaxed-threshold filter
   float* skey = a.surv_key + a.surv_off[qi];
   uint32_t* spos = a.surv_pos + a.surv_off[qi];
-  uint32_t n_rej = 0;
-  for (int64_t i = threadIdx.x; i < Ts; i += NT) {
-    const float k = keys[i];
-    const bool keep = !prune || key_bits(k) <= dmax_b;
-    const uint32_t slot = wave_slot(keep, &bc[6]);
-    if (keep) {
-      skey[slot] = k;
-      spos[slot] = (uint32_t)pos_of(i);
-    } else {
-      ++n_rej;
+  const uint64_t lt = (1ull << lane) - 1ull;
+  int rk = 0;
+  if (in_regs) {
+    // slots from a count of each wave's kept keys (registers are read twice)
+    uint32_t nkeep = 0, nrej = 0;
+    each([&](int64_t, bool valid, uint32_t v) {
+      const bool keep = valid && (!prune || v <= dmax_b);
+      nkeep += (uint32_t)__popcll(__ballot(keep));
+      nrej += (uint32_t)__popcll(__ballot(valid && !keep));
+    });
+    if (lane == 0) {
+      s_wred[0][wv] = nkeep;
+      s_wred[1][wv] = nrej;
     }
+    __syncthreads();
+    uint32_t base = 0, tot = 0, rej = 0;
+    for (int x = 0; x < NW; ++x) {
+      if (x < wv) base += s_wred[0][x];
+      tot += s_wred[0][x];
+      rej += s_wred[1][x];
+    }
+    each([&](int64_t i, bool valid, uint32_t v) {
+      const bool keep = valid && (!prune || v <= dmax_b);
+      const uint64_t mk = __ballot(keep);
+      if (keep) {
+        const uint32_t slot = base + (uint32_t)__popcll(mk & lt);
+        skey[slot] = bits_key(v);
+        spos[slot] = (uint32_t)pos_at(i, rk);
+      }
+      base += (uint32_t)__popcll(mk);
+    });
+    if (threadIdx.x == 0) {
+      bc[6] = tot;
+      bc[7] = rej;
+    }
+  } else {
+    uint32_t n_rej = 0;
+    each([&](int64_t i, bool valid, uint32_t v) {
+      const bool keep = valid && (!prune || v <= dmax_b);
+      const uint32_t slot = wave_slot(keep, &bc[6]);
+      if (keep) {
+        skey[slot] = bits_key(v);
+        spos[slot] = (uint32_t)pos_at(i, rk);
+      } else if (valid) {
+        ++n_rej;
+      }
+    });
+    for (int off = 32; off >= 1; off >>= 1) n_rej += __shfl_xor(n_rej, off);
+    if (lane == 0 && n_rej) atomicAdd(&bc[7], n_rej);
   }
-  for (int off = 32; off >= 1; off >>= 1) n_rej += __shfl_xor(n_rej, off);
-  if ((threadIdx.x & 63) == 0 && n_rej) atomicAdd(&bc[7], n_rej);
   __syncthreads();
   if (threadIdx.x == 0) {
     a.n_rejected[qi] = bc[7];
@@ -179,7 +338,7 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
   for (int r = 1 + threadIdx.x; r < nsr; r += NT) a.pair_nsurv[po + r] = 0;
 }
 
-__global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
+__global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) {
   constexpr int NT = 1024;
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* bbuf = reinterpret_cast<uint64_t*>(smem);  // [bcap], bcap a power of two
@@ -258,16 +417,17 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   constexpr int U = COLLECT_UNROLL;
   constexpr int NW = NT / 64;
-  // Batches of up to U elements per lane: batch(n, act, idx) gets the slots
-  // idx[0, n) (with their active flags) of this lane; n and the number of
-  // calls are wave-uniform (batch() may take wave-wide collectives).
-  auto for_each_batch = [&](auto batch) {
+  // Batches of UB chunks per wave (UB = the Unroll argument): batch(act,
+  // idx) gets this lane's slot of each (with its active flag); the number of
+  // calls is wave-uniform (batch() may take wave-wide collectives).
+  auto for_each_batch = [&](auto uc, auto batch) {
+    constexpr int UB = decltype(uc)::value;
     if (flat) {
-      for (uint32_t c0 = (uint32_t)wv * U; c0 < nchunks; c0 += NW * U) {
-        bool act[U];
-        int64_t idx[U];
+      for (uint32_t c0 = (uint32_t)wv * UB; c0 < nchunks; c0 += NW * UB) {
+        bool act[UB];
+        int64_t idx[UB];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UB; ++u) {
           const uint32_t ch = c0 + u;
           act[u] = false;
           idx[u] = 0;
@@ -295,10 +455,10 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
         const int64_t rb = rank_off[r];
         const int64_t rn = nsurv[r];
         for (int64_t base = 0; base < rn; base += NT) {
-          bool act[U];
-          int64_t idx[U];
+          bool act[UB];
+          int64_t idx[UB];
 #pragma unroll
-          for (int u = 0; u < U; ++u) {
+          for (int u = 0; u < UB; ++u) {
             act[u] = u == 0 && base + threadIdx.x < rn;
             idx[u] = rb + base + threadIdx.x;
           }
@@ -308,18 +468,19 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     }
   };
   // For every survivor: v = load(active, slot), then use(active, slot, v).
-  auto for_each_wave = [&](auto load, auto use) {
+  auto for_each_wave = [&](auto uc, auto load, auto use) {
+    constexpr int UB = decltype(uc)::value;
     using V = decltype(load(false, (int64_t)0));
-    for_each_batch([&](const bool* act, const int64_t* idx) {
-      V v[U];
+    for_each_batch(uc, [&](const bool* act, const int64_t* idx) {
+      V v[UB];
 #pragma unroll
-      for (int u = 0; u < U; ++u) v[u] = load(act[u], idx[u]);
+      for (int u = 0; u < UB; ++u) v[u] = load(act[u], idx[u]);
 #pragma unroll
-      for (int u = 0; u < U; ++u) use(act[u], idx[u], v[u]);
+      for (int u = 0; u < UB; ++u) use(act[u], idx[u], v[u]);
     });
   };
   auto for_each = [&](auto fn) {
-    for_each_wave([&](bool act, int64_t i) { return 0; },
+    for_each_wave(Unroll<U>{}, [&](bool act, int64_t i) { return 0; },
                   [&](bool act, int64_t i, int) { if (act) fn(i); });
   };
 
@@ -327,7 +488,7 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   // bucket is kept for the collection pass --------------------------------
   {
     uint32_t n_last = 0, n_all = 0;
-    for_each_wave([&](bool act, int64_t i) { return act ? skey[i] : 0.0f; },
+    for_each_wave(Unroll<2 * U>{}, [&](bool act, int64_t i) { return act ? skey[i] : 0.0f; },
                   [&](bool act, int64_t i, float key) {
                     const int c = act ? cell_of(key, dmin, delta) : 255;
                     const uint32_t b = cmap[c];
@@ -368,13 +529,21 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   const int64_t bnd_cap = a.cand_off[qi + 1] - a.cand_off[qi];
 
   // ---- Collect -----------------------------------------------------------------
-  // one atomic per counter for a lane's whole batch
-  for_each_batch([&](const bool* act, const int64_t* idx) {
+  // Each batch loads the buckets and the list positions of its survivors
+  // together (one round trip).  Candidates below tau are written at once;
+  // the threshold bucket's members are recorded by survivor slot, and their
+  // keys and ids are looked up afterwards, all at once.  One atomic per
+  // counter for a lane's whole batch.
+  for_each_batch(Unroll<U>{}, [&](const bool* act, const int64_t* idx) {
     int b[U];
+    uint32_t pv[U];
     uint64_t mc[U], mb[U];
     uint32_t nc = 0, nbd = 0;
 #pragma unroll
-    for (int u = 0; u < U; ++u) b[u] = act[u] ? (int)sbkt[idx[u]] : m;
+    for (int u = 0; u < U; ++u) {
+      b[u] = act[u] ? (int)sbkt[idx[u]] : m;
+      pv[u] = act[u] ? spos[idx[u]] : 0u;
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       mc[u] = __ballot(b[u] < tau);
@@ -392,10 +561,10 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
     const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (b[u] < tau) cand[basec + (uint32_t)__popcll(mc[u] & lt)] = spos[idx[u]];
+      if (b[u] < tau) cand[basec + (uint32_t)__popcll(mc[u] & lt)] = pv[u];
       if (b[u] == tau) {
         const uint32_t bs = baseb + (uint32_t)__popcll(mb[u] & lt);
-        const uint64_t pk = pack_key_id(skey[idx[u]], (uint32_t)a.list_ids[spos[idx[u]]]);
+        const uint64_t pk = (uint64_t)idx[u];  // survivor slot, resolved below
         if ((int)bs < bcap) bbuf[bs] = pk;
         if ((int64_t)bs < bnd_cap) bnd[bs] = pk;
       }
@@ -406,6 +575,11 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
   __syncthreads();
   const int64_t nb = bc[3];
   if (nb <= bcap) {
+    // members: survivor slot -> (key, id)
+    for (int i = threadIdx.x; i < (int)nb; i += NT) {
+      const int64_t x = (int64_t)bbuf[i];
+      bbuf[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x]]);
+    }
     const int P = next_pow2((int)nb);
     for (int i = (int)nb + threadIdx.x; i < P; i += NT) bbuf[i] = ~0ull;
     __syncthreads();
@@ -414,7 +588,12 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
       cand[nbelow + r] = (uint32_t)a.pos_of_id[packed_id(bbuf[r])];
   } else if (nb <= bnd_cap) {
     // the s smallest (key, id) of the members gathered in global scratch:
-    // radix select of the s-th, then one pass over the members
+    // slots -> (key, id), radix select of the s-th, one pass over them
+    for (int64_t i = threadIdx.x; i < nb; i += NT) {
+      const int64_t x = (int64_t)bnd[i];
+      bnd[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x]]);
+    }
+    __syncthreads();
     const uint64_t thr =
         block_radix_select64<NT>([&](int64_t i, uint64_t& v) { v = bnd[i]; return true; }, nb, s - 1, hist, bc);
     if (threadIdx.x == 0) bc[6] = 0;
@@ -480,7 +659,14 @@ __global__ __launch_bounds__(1024) void collect_bucket_kernel(CollectArgs a) {
 
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
-  hipLaunchKernelGGL(codebook_kernel, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
+  // the smallest register slot count that holds the largest sample (48
+  // slots fill the 128 registers a lane of a 1024-thread block may hold)
+  const dim3 g((unsigned)a.nq), b(1024);
+  const int64_t ms = a.max_sample;
+  if (ms <= 16 * 1024) hipLaunchKernelGGL(codebook_kernel<16>, g, b, 0, s, a);
+  else if (ms <= 32 * 1024) hipLaunchKernelGGL(codebook_kernel<32>, g, b, 0, s, a);
+  else if (ms <= 48 * 1024) hipLaunchKernelGGL(codebook_kernel<48>, g, b, 0, s, a);
+  else hipLaunchKernelGGL(codebook_kernel<0>, g, b, 0, s, a);
   return hipGetLastError();
 }
 

@@ -88,6 +88,7 @@ struct CollectArgs {
   const int32_t* nprobe; const int64_t* probe_off; const int32_t* probe_lists; const int64_t* rank_off;
   const int64_t* list_off; const int32_t* list_ids; const int32_t* pos_of_id;
   const int64_t* kc_target; const int64_t* cand_off; int m; const int32_t* nsample_q; int bcap;
+  int64_t max_sample;       // upper bound of the codebook sample's keys over the queries
   uint32_t* cand_pos; int64_t* n_cand;
   const float* sample_keys; const int64_t* sample_off; QueryBook* books;
   float* surv_key; uint32_t* surv_pos; const int64_t* surv_off; uint32_t* pair_nsurv; uint32_t* n_rejected;
