@@ -34,6 +34,20 @@ namespace bbc {
 constexpr int COLLECT_RANKCAP = 2048;
 constexpr int COLLECT_CHUNKCAP = 4096;  // 64-survivor chunks mapped to their run by an LDS table
 template <int N> struct Unroll { static constexpr int value = N; };
+
+// cell_of(key, dmin, delta) with a reciprocal (rdelta = rcp(delta), within
+// 1 ulp): for quotients below 512, q = (key - dmin) * rdelta lies within
+// 2^-13 of the exact quotient, so when q is more than 2^-11 away from every
+// integer the correctly rounded quotient has the same floor.  Otherwise (and
+// for NaN from a flushed reciprocal) the quotient is formed by division.
+__device__ __forceinline__ int cell_fast(float key, float dmin, float delta, float rdelta) {
+  const float q = (key - dmin) * rdelta;
+  if (q >= 256.0f) return 255;
+  const float n = floorf(q);
+  const float f = q - n;
+  if (f > 0x1p-11f && f < 1.0f - 0x1p-11f) return n < 0.0f ? 0 : (n > 255.0f ? 255 : (int)n);
+  return cell_of(key, dmin, delta);
+}
 constexpr int COLLECT_UNROLL = 4;       // chunks a wave has in flight
 
 __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restrict__ rank_off,
@@ -84,11 +98,28 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
       s_rbeg[r] = (int32_t)rank_off[r];
       s_lbeg[r] = (int32_t)a.list_off[lists[r]];
     }
+  const bool in_regs = R > 0 && Ts > 0 && Ts <= (int64_t)NT * R;
+  // chunk -> rank of its first slot, for the register path's positions
+  __shared__ uint16_t s_crank[R > 0 ? R * NT / 64 : 1];
+  const bool ctab = in_regs && lds_ranks;
+  if (ctab) {
+    __syncthreads();  // s_rbeg
+    for (int r = threadIdx.x; r < nsr; r += NT) {
+      const int64_t rb = s_rbeg[r], re = r + 1 < nsr ? (int64_t)s_rbeg[r + 1] : Ts;
+      for (int64_t ch = (rb + 63) >> 6; ch * 64 < re; ++ch) s_crank[ch] = (uint16_t)r;
+    }
+  }
   // list position of sample slot i; r is the probe rank of the previous slot
   // this thread asked for (slots are asked for in increasing order), and
-  // becomes the rank of i
+  // becomes the rank of i.  With the chunk table (register path), the rank
+  // of the 64-slot chunk's first slot starts the search instead.
   auto pos_at = [&](int64_t i, int& r) -> int64_t {
     if (!lds_ranks) return slot_to_pos(i, rank_off, lists, a.list_off, nsr);
+    if (ctab) {
+      r = s_crank[i >> 6];
+      while (r + 1 < nsr && (int64_t)s_rbeg[r + 1] <= i) ++r;
+      return (int64_t)s_lbeg[r] + (i - s_rbeg[r]);
+    }
     if (r + 1 < nsr && (int64_t)s_rbeg[r + 1] <= i) {
       int lo = r + 1, hi = nsr - 1;
       if (lo < hi && (int64_t)s_rbeg[lo + 1] > i) hi = lo;  // usually the next list
@@ -103,7 +134,6 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
 
   // the sample's key images, once from memory into registers when they fit
   uint32_t kv[R > 0 ? R : 1];
-  const bool in_regs = R > 0 && Ts > 0 && Ts <= (int64_t)NT * R;
   if constexpr (R > 0) {
     if (in_regs) {
       // unconditional loads (slots past the end read the last key), all
@@ -227,8 +257,9 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
     const float dmax = bits_key(dmax_b);
     float delta = (dmax - dmin) / 256.0f;
     if (!(delta > 0.0f)) delta = 1.0f;
+    const float rdelta = __builtin_amdgcn_rcpf(delta);
     each([&](int64_t, bool valid, uint32_t v) {
-      wave_hist_add(hist, (uint32_t)cell_of(bits_key(v), dmin, delta), valid && v < dmax_b);
+      wave_hist_add(hist, (uint32_t)cell_fast(bits_key(v), dmin, delta, rdelta), valid && v < dmax_b);
     });
     __syncthreads();
     if (threadIdx.x < 64) {
@@ -373,6 +404,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
   if (threadIdx.x == 0) bc[4] = 0;
   __syncthreads();
   const float dmin = book->dmin, delta = book->delta;
+  const float rdelta = __builtin_amdgcn_rcpf(delta);
   const int np = a.nprobe[qi];
   const int64_t po = a.probe_off[qi];
   const int64_t* rank_off = a.rank_off + po;
@@ -490,7 +522,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     uint32_t n_last = 0, n_all = 0;
     for_each_wave(Unroll<2 * U>{}, [&](bool act, int64_t i) { return act ? skey[i] : 0.0f; },
                   [&](bool act, int64_t i, float key) {
-                    const int c = act ? cell_of(key, dmin, delta) : 255;
+                    const int c = act ? cell_fast(key, dmin, delta, rdelta) : 255;
                     const uint32_t b = cmap[c];
                     if (act) sbkt[i] = (uint8_t)b;
                     n_all += act;
