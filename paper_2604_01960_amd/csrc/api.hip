@@ -672,7 +672,7 @@ struct Layout {
   size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
-      t_nb;
+      t_nb, qorder;
 };
 
 int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
@@ -1010,6 +1010,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
+  L.qorder = pl.add(4 * nq);
   if (host_io) {
     L.out_ids = pl.add(8 * nout);
     L.out_dists = pl.add(4 * nout);
@@ -1180,6 +1181,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ra.cand_packed = reinterpret_cast<uint64_t*>(A + L.cand_packed);
   {
     StageScope st(s, 4);
+    if (ix->nlist <= bbc::QUERY_ORDER_MAX_LISTS && nq > 1) {
+      int32_t* qo = reinterpret_cast<int32_t*>(A + L.qorder);
+      HIP_TRY(bbc::launch_query_order(pa.probe_lists, d_po, d_np, nq, ix->nlist, qo, s));
+      ra.qorder = qo;
+    }
     HIP_TRY(bbc::launch_rerank(ra, max_kc, s));
   }
 

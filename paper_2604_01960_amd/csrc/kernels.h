@@ -107,8 +107,13 @@ struct RerankArgs {
   const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;
   const int32_t* list_ids; const uint32_t* cand_pos; const int64_t* cand_off; const int64_t* n_cand;
   uint64_t* cand_packed;
+  const int32_t* qorder;    // optional: block row y re-ranks query qorder[y] (else query y)
 };
 hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
+constexpr int QUERY_ORDER_MAX_LISTS = 32768;
+// order[0, nq): the queries sorted by their nearest probed list
+hipError_t launch_query_order(const int32_t* probe_lists, const int64_t* probe_off, const int32_t* nprobe,
+                              int64_t nq, int nlist, int32_t* order, hipStream_t s);
 
 struct FinalArgs {
   int64_t nq; const int32_t* k; const int64_t* n_cand; const int64_t* cand_off; uint64_t* cand_packed;

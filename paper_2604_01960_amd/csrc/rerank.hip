@@ -33,7 +33,7 @@ constexpr int RR_UNROLL = 4;
 // Half-wave rows (nchunk <= 32).
 template <typename T>
 __global__ __launch_bounds__(256) void rerank_half_kernel(RerankArgs a) {
-  const int64_t qi = blockIdx.y;
+  const int64_t qi = a.qorder ? a.qorder[blockIdx.y] : blockIdx.y;
   const int64_t kc = a.n_cand[qi];
   const int64_t row0 = (int64_t)blockIdx.x * RR_ROWS_PER_BLOCK;
   if (row0 >= kc) return;
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(256) void rerank_half_kernel(RerankArgs a) {
 // Full-wave rows (nchunk > 32), at most 4 steps (d <= 1024).
 template <typename T>
 __global__ __launch_bounds__(256) void rerank_full_kernel(RerankArgs a) {
-  const int64_t qi = blockIdx.y;
+  const int64_t qi = a.qorder ? a.qorder[blockIdx.y] : blockIdx.y;
   const int64_t kc = a.n_cand[qi];
   const int64_t row0 = (int64_t)blockIdx.x * RR_ROWS_PER_BLOCK;
   if (row0 >= kc) return;
@@ -125,6 +125,43 @@ __global__ __launch_bounds__(256) void rerank_full_kernel(RerankArgs a) {
       }
     }
   }
+}
+
+// Queries ordered by their nearest probed list (a counting sort in one
+// block): queries that share it tend to share candidates, and re-ranking them
+// together lets the caches serve the rows they have in common.
+__global__ __launch_bounds__(1024) void query_order_kernel(const int32_t* __restrict__ probe_lists,
+                                                           const int64_t* __restrict__ probe_off,
+                                                           const int32_t* __restrict__ nprobe, int64_t nq,
+                                                           int nlist, int32_t* __restrict__ order) {
+  extern __shared__ uint32_t cnt[];  // [nlist + 1]
+  const int NT = 1024;
+  auto top = [&](int64_t q) { return nprobe[q] > 0 ? probe_lists[probe_off[q]] : nlist; };
+  for (int i = threadIdx.x; i <= nlist; i += NT) cnt[i] = 0;
+  __syncthreads();
+  for (int64_t q = threadIdx.x; q < nq; q += NT) atomicAdd(&cnt[top(q)], 1u);
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    uint32_t carry = 0;
+    for (int base = 0; base <= nlist; base += 64) {
+      const int i = base + (int)threadIdx.x;
+      const uint32_t v = i <= nlist ? cnt[i] : 0u;
+      const uint32_t incl = wave_incl_scan(v);
+      if (i <= nlist) cnt[i] = carry + incl - v;
+      carry += __shfl(incl, 63);
+    }
+  }
+  __syncthreads();
+  for (int64_t q = threadIdx.x; q < nq; q += NT) order[atomicAdd(&cnt[top(q)], 1u)] = (int32_t)q;
+}
+
+hipError_t launch_query_order(const int32_t* probe_lists, const int64_t* probe_off, const int32_t* nprobe,
+                              int64_t nq, int nlist, int32_t* order, hipStream_t s) {
+  if (nq <= 0) return hipSuccess;
+  if (nlist > QUERY_ORDER_MAX_LISTS) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(query_order_kernel, dim3(1), dim3(1024), sizeof(uint32_t) * (nlist + 1), s, probe_lists,
+                     probe_off, nprobe, nq, nlist, order);
+  return hipGetLastError();
 }
 
 hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s) {
