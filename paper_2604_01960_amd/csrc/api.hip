@@ -151,6 +151,7 @@ struct bbc_index {
   int64_t* list_off = nullptr;
   int32_t* list_ids = nullptr;
   int32_t* pos_of_id = nullptr;
+  int32_t* list_of_pos = nullptr;  // list holding each list slot
   uint8_t* codes = nullptr;
   float* codebook = nullptr;
   void* vectors = nullptr;  // list-slot order
@@ -170,6 +171,7 @@ struct bbc_index {
   int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
+  int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -193,7 +195,8 @@ void index_release(bbc_index* ix) {
   hipSetDevice(ix->device);
   hipDeviceSynchronize();
   hipFree(ix->cent); hipFree(ix->cent_bf16); hipFree(ix->cent_norm2); hipFree(ix->cent_norm);
-  hipFree(ix->list_off); hipFree(ix->list_ids); hipFree(ix->pos_of_id); hipFree(ix->codes);
+  hipFree(ix->list_off); hipFree(ix->list_ids); hipFree(ix->pos_of_id); hipFree(ix->list_of_pos);
+  hipFree(ix->codes);
   hipFree(ix->codebook); hipFree(ix->vectors);
   hipFree(ix->rq_codes); hipFree(ix->rq_factors); hipFree(ix->rot); hipFree(ix->rot_cent);
   if (ix->arena.base) hipFree(ix->arena.base);
@@ -233,6 +236,13 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   HIP_TRY(dalloc(&ix->list_off, nlist + 1));
   HIP_TRY(dalloc(&ix->list_ids, n));
   HIP_TRY(dalloc(&ix->pos_of_id, n));
+  HIP_TRY(dalloc(&ix->list_of_pos, n));
+  {
+    std::vector<int32_t> lop(n);
+    for (int32_t j = 0; j < nlist; ++j)
+      for (int64_t p = list_off[j]; p < list_off[j + 1]; ++p) lop[p] = j;
+    HIP_TRY(hipMemcpy(ix->list_of_pos, lop.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
+  }
   HIP_TRY(hipMemcpy(ix->cent, centroids, sizeof(float) * nlist * d, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ix->cent_bf16, cb16.data(), sizeof(uint16_t) * cb16.size(), hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy(ix->cent_norm2, cn2.data(), sizeof(float) * nlist, hipMemcpyHostToDevice));
@@ -261,6 +271,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 2) ix->walk_form = x;
+  }
+  if (const char* sv = std::getenv("BBC_RERANK_FORM")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 1) ix->rerank_form = x;
   }
   if (const char* sv = std::getenv("BBC_COLLECT_BCAP")) {
     const int x = std::atoi(sv);
@@ -672,7 +686,7 @@ struct Layout {
   size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
-      t_nb, qorder;
+      t_nb, qorder, rt_sorted, rt_bins, rt_lcnt, rt_lpairs;
 };
 
 int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
@@ -956,9 +970,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0), cand_off(nq + 1, 0), kc_target(nq),
       sample_off(nq + 1, 0), surv_off(nq + 1, 0);
   int64_t max_kc = 0, max_scap = 0;
+  int max_np = 0;
   const int64_t max_list = ix->h_maxS[1];
   for (int64_t i = 0; i < nq; ++i) {
     probe_off[i + 1] = probe_off[i] + nprobe[i];
+    max_np = std::max(max_np, nprobe[i]);
     int64_t cap = kc_cap_of(ix, k[i], nprobe[i], p->ncand_ratio);
     // the sample stops at the first list that brings it to K_c keys
     const int64_t scap = !bucket ? ix->h_maxS[nprobe[i]]
@@ -1011,6 +1027,19 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
   L.qorder = pl.add(4 * nq);
+  // tile-major re-rank: its sort buffers
+  int rt_shift = 0, rt_nbin = 0;
+  size_t rt_lds = 0;
+  const bool tile_rr = ix->rerank_form == 0 && ix->list_of_pos && nq <= 65535 &&
+                       bbc::tile_rerank_shape(d, ix->fp16, max_list, max_np, ix->nlist, (size_t)ix->max_lds,
+                                              &rt_shift, &rt_nbin, &rt_lds);
+  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
+  if (tile_rr) {
+    L.rt_sorted = pl.add(4 * ncand);
+    L.rt_bins = pl.add(4 * npairs * (rt_nbin + 1));
+    L.rt_lcnt = pl.add(4 * ((int64_t)ix->nlist + 1));
+    L.rt_lpairs = pl.add(8 * rt_lpairs_cap);
+  }
   if (host_io) {
     L.out_ids = pl.add(8 * nout);
     L.out_dists = pl.add(4 * nout);
@@ -1181,12 +1210,27 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ra.cand_packed = reinterpret_cast<uint64_t*>(A + L.cand_packed);
   {
     StageScope st(s, 4);
-    if (ix->nlist <= bbc::QUERY_ORDER_MAX_LISTS && nq > 1) {
-      int32_t* qo = reinterpret_cast<int32_t*>(A + L.qorder);
-      HIP_TRY(bbc::launch_query_order(pa.probe_lists, d_po, d_np, nq, ix->nlist, qo, s));
-      ra.qorder = qo;
+    if (tile_rr) {
+      bbc::TileRerankArgs ta{};
+      ta.q = dq; ta.nq = nq; ta.d = d; ta.metric = ix->metric; ta.vectors = ix->vectors; ta.fp16 = ix->fp16;
+      ta.list_ids = ix->list_ids; ta.list_off = ix->list_off; ta.list_of_pos = ix->list_of_pos;
+      ta.nprobe = d_np; ta.probe_off = d_po; ta.probe_lists = pa.probe_lists; ta.nlist = ix->nlist;
+      ta.cand_pos = ca.cand_pos; ta.cand_off = d_co; ta.n_cand = ca.n_cand; ta.cand_packed = ra.cand_packed;
+      ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.nbin = rt_nbin;
+      ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L.rt_sorted);
+      ta.bin_beg = reinterpret_cast<uint32_t*>(A + L.rt_bins);
+      ta.lcnt = reinterpret_cast<uint32_t*>(A + L.rt_lcnt);
+      ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);
+      ta.lpairs_cap = rt_lpairs_cap;
+      HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
+    } else {
+      if (ix->nlist <= bbc::QUERY_ORDER_MAX_LISTS && nq > 1) {
+        int32_t* qo = reinterpret_cast<int32_t*>(A + L.qorder);
+        HIP_TRY(bbc::launch_query_order(pa.probe_lists, d_po, d_np, nq, ix->nlist, qo, s));
+        ra.qorder = qo;
+      }
+      HIP_TRY(bbc::launch_rerank(ra, max_kc, s));
     }
-    HIP_TRY(bbc::launch_rerank(ra, max_kc, s));
   }
 
   // trace copies of the exact candidate keys happen before the final step

@@ -111,6 +111,29 @@ struct RerankArgs {
 };
 hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 constexpr int QUERY_ORDER_MAX_LISTS = 32768;
+
+// Tile-major re-rank (rows of at most 32 four-element chunks).
+constexpr int RT_G = 64;               // (query, list) pairs per block
+constexpr int RT_TILE_BYTES = 65536;   // LDS rows per tile
+struct TileRerankArgs {
+  const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;
+  const int32_t* list_ids; const int64_t* list_off; const int32_t* list_of_pos;
+  const int32_t* nprobe; const int64_t* probe_off; const int32_t* probe_lists; int nlist;
+  const uint32_t* cand_pos; const int64_t* cand_off; const int64_t* n_cand;
+  uint64_t* cand_packed;    // out: (key, id) of candidate j of query q at cand_off[q] + j (sorted_pos order)
+  int64_t npairs; int max_np;
+  int tshift;               // rows per tile = 1 << tshift
+  int nbin;                 // bins per (query, list) pair; tiles from nbin - 1 on share the last
+  uint32_t* sorted_pos;     // [sum cap] each query's candidates grouped by (rank, bin)
+  uint32_t* bin_beg;        // [npairs][nbin + 1] bin starts within the query's candidates, then the end
+  uint32_t* lcnt;           // [nlist + 1] pair counts, then cursors; [nlist] = number of groups
+  uint64_t* lpairs;         // [lpairs_cap] (query << 32 | rank) grouped by list, whole groups of RT_G
+  int64_t lpairs_cap;       // npairs + nlist * (RT_G - 1)
+};
+// Tile rows and bins for the batch shape; false where the form does not apply.
+bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int* tshift,
+                       int* nbin, size_t* sort_lds);
+hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s);
 // order[0, nq): the queries sorted by their nearest probed list
 hipError_t launch_query_order(const int32_t* probe_lists, const int64_t* probe_off, const int32_t* nprobe,
                               int64_t nq, int nlist, int32_t* order, hipStream_t s);

@@ -123,3 +123,31 @@ def test_large_threshold_buckets(bbc, bcap):
         check_trace(tr, exp, m)
         if bcap == 64:
             assert np.any(tr["n_boundary"] > 64)
+
+
+@pytest.mark.parametrize("form", ["tile", "per_query"])
+@pytest.mark.parametrize("shape", ["long_lists", "many_queries"])
+def test_rerank_forms(bbc, form, shape):
+    """Both re-rank forms against the oracle: the tile-major one (a list's
+    rows staged in LDS once per group of queries) and one block per query.
+    Long lists have more tiles than bins (the last bin is shared); many
+    queries per list fill several groups of pairs for one list."""
+    import os
+    if shape == "long_lists":
+        w, ix, q = oracle_pq_index("ivfpq4_10m_d96", 20000, 6, 48, 4, 10)
+        k = np.array([50, 900, 2500, 4000, 1200, 700, 3000, 150, 5000, 2000], np.int32)
+        npb = np.array([1, 2, 3, 6, 4, 2, 5, 1, 6, 3], np.int32)
+    else:
+        w, ix, q = oracle_pq_index("ivfpq_100k_d128", 20000, 32, 16, 8, 150)
+        k = np.full(150, 200, np.int32)
+        npb = np.full(150, 20, np.int32)
+        npb[::7] = 32
+    os.environ["BBC_RERANK_FORM"] = {"tile": "0", "per_query": "1"}[form]
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        del os.environ["BBC_RERANK_FORM"]
+    print(f"[case] rerank form={form} shape={shape}", flush=True)
+    tr = g.search_traced(q, k, npb, ratio=2.0, buckets=64, nsample=2)
+    exp = expected_steps(ix, q, k, npb, 2.0, 64, 2)
+    check_trace(tr, exp, 64)
