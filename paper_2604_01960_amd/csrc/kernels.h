@@ -113,7 +113,7 @@ hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 constexpr int QUERY_ORDER_MAX_LISTS = 32768;
 
 // Tile-major re-rank (rows of at most 32 four-element chunks).
-constexpr int RT_G = 64;               // (query, list) pairs per block
+constexpr int RT_G = 128;              // (query, list) pairs per block
 constexpr int RT_TILE_BYTES = 65536;   // LDS rows per tile
 struct TileRerankArgs {
   const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;

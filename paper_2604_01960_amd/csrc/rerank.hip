@@ -358,20 +358,31 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
       }
     }
     if (threadIdx.x < 64) {
-      // each pair's candidates in this tile's bin, cut into 64-candidate chunks
-      const int e = threadIdx.x;
-      uint32_t b0 = 0, b1 = 0;
-      if (s_q[e] >= 0) {
-        const uint32_t* bb = a.bin_beg + (a.probe_off[s_q[e]] + s_r[e]) * (B + 1);
-        b0 = bb[bin];
-        b1 = bb[bin + 1];
+      // each pair's candidates in this tile's bin, cut into 64-candidate
+      // chunks (RT_G / 64 consecutive pairs per lane)
+      constexpr int EPL = RT_G / 64;
+      uint32_t nc[EPL], tot = 0;
+#pragma unroll
+      for (int h = 0; h < EPL; ++h) {
+        const int e = EPL * (int)threadIdx.x + h;
+        uint32_t b0 = 0, b1 = 0;
+        if (s_q[e] >= 0) {
+          const uint32_t* bb = a.bin_beg + (a.probe_off[s_q[e]] + s_r[e]) * (B + 1);
+          b0 = bb[bin];
+          b1 = bb[bin + 1];
+        }
+        s_beg[e] = b0;
+        s_end[e] = b1;
+        nc[h] = (b1 - b0 + 63) / 64;
+        tot += nc[h];
       }
-      s_beg[e] = b0;
-      s_end[e] = b1;
-      const uint32_t nc = (b1 - b0 + 63) / 64;
-      const uint32_t incl = wave_incl_scan(nc);
-      s_cpre[e] = incl - nc;
-      if (e == 63) s_cpre[RT_G] = incl;
+      uint32_t run = wave_incl_scan(tot) - tot;
+#pragma unroll
+      for (int h = 0; h < EPL; ++h) {
+        s_cpre[EPL * threadIdx.x + h] = run;
+        run += nc[h];
+      }
+      if (threadIdx.x == 63) s_cpre[RT_G] = run;
     }
     __syncthreads();
     const uint32_t nchk = s_cpre[RT_G];
