@@ -30,6 +30,25 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector peak for plain (non-FMA, non-packed) adds and multiplies: 256
+# CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane per clock
+VALU_PEAK_TFLOPS = 39.3
+
+
+def rerank_tile_form(d: int) -> bool:
+    """Whether the PQ re-rank runs tile-major (rows of at most 32 chunks)."""
+    return d % 4 == 0 and d <= 128 and os.environ.get("BBC_RERANK_FORM", "0") == "0"
+
+
+def rerank_entry(ms_per_launch: float, kc_per_launch: float, d: int) -> dict:
+    """Roofline entry of the tile-major PQ re-rank stage: each candidate row is
+    staged once per group of queries, so the stage is bound by the 3 d
+    arithmetic operations (subtract, multiply, add) of each candidate."""
+    tf = kc_per_launch * 3 * d / (ms_per_launch * 1e-3) / 1e12
+    return {"kernel": "rt_rerank_tile (tile-major re-rank stage, with its pair and candidate sorts)",
+            "bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": None, "avg_launch_ms": round(ms_per_launch, 4),
+            "algorithmic_flops_per_launch": int(kc_per_launch * 3 * d)}
 CSRC = os.path.join(ROOT, "paper_2604_01960_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SCAN = "pq_scan_grouped<1, ...> (scan through the relaxed threshold)"
@@ -330,6 +349,10 @@ def main():
         bytes_total = algo[name] * args.steps
         bytes_per_launch = bytes_total / st["launches"]
         gbs = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+        if name == "rerank" and rerank_tile_form(d):
+            kc_pl = sum(sizes[k]["Kc"] for k in ks) * args.steps / st["launches"]
+            entries[name] = rerank_entry(avg_ms, kc_pl, d)
+            continue
         entries[name] = {"kernel": kernels[name][0], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(w.name, name, kernels[name][1]),
@@ -485,6 +508,9 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         avg_ms = st["ms"] / st["launches"]
         bpl = algo[name] * args.steps / st["launches"]
         gbs = bpl / (avg_ms * 1e-3) / 1e9
+        if name == "rerank" and rerank_tile_form(w.d):
+            entries[name] = rerank_entry(avg_ms, Kc * args.steps / st["launches"], w.d)
+            continue
         entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
                          "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bpl)}

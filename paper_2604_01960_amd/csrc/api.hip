@@ -172,6 +172,7 @@ struct bbc_index {
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
+  int rerank_bins = 1024;   // tile-major form: most bins per (query, list) (BBC_RERANK_BINS, 1..1024)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -271,6 +272,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 2) ix->walk_form = x;
+  }
+  if (const char* sv = std::getenv("BBC_RERANK_BINS")) {
+    const int x = std::atoi(sv);
+    if (x >= 1 && x <= 1024) ix->rerank_bins = x;
   }
   if (const char* sv = std::getenv("BBC_RERANK_FORM")) {
     const int x = std::atoi(sv);
@@ -1032,7 +1037,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   size_t rt_lds = 0;
   const bool tile_rr = ix->rerank_form == 0 && ix->list_of_pos && nq <= 65535 &&
                        bbc::tile_rerank_shape(d, ix->fp16, max_list, max_np, ix->nlist, (size_t)ix->max_lds,
-                                              &rt_shift, &rt_nbin, &rt_lds);
+                                              ix->rerank_bins, &rt_shift, &rt_nbin, &rt_lds);
   const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
   if (tile_rr) {
     L.rt_sorted = pl.add(4 * ncand);

@@ -131,8 +131,8 @@ struct TileRerankArgs {
   int64_t lpairs_cap;       // npairs + nlist * (RT_G - 1)
 };
 // Tile rows and bins for the batch shape; false where the form does not apply.
-bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int* tshift,
-                       int* nbin, size_t* sort_lds);
+bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int max_bins,
+                       int* tshift, int* nbin, size_t* sort_lds);
 hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s);
 // order[0, nq): the queries sorted by their nearest probed list
 hipError_t launch_query_order(const int32_t* probe_lists, const int64_t* probe_off, const int32_t* nprobe,

@@ -433,17 +433,22 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   }
 }
 
-bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int* tshift,
-                       int* nbin, size_t* sort_lds) {
+bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int max_bins,
+                       int* tshift, int* nbin, size_t* sort_lds) {
   if (d <= 0 || d % 4 || d / 4 > 32 || nlist > QUERY_ORDER_MAX_LISTS || max_np <= 0) return false;
   const int64_t row_bytes = (int64_t)d * (fp16 ? 2 : 4);
   if (row_bytes % 16) return false;
   int ts = 0;
   while (((int64_t)2 << ts) * row_bytes <= RT_TILE_BYTES) ++ts;
+  // one bin per tile of the longest list where the candidate sort's LDS
+  // allows it (a shared last bin is read again for each of its tiles)
   const int64_t tiles = (max_list + ((int64_t)1 << ts) - 1) >> ts;
-  int B = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), 16);
-  while (B > 1 && (int64_t)max_np * B > 16384) --B;
-  const size_t lds = sizeof(uint32_t) * ((size_t)max_np * B + max_np) + sizeof(uint16_t) * nlist;
+  int B = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), std::max(1, max_bins));
+  auto lds_of = [&](int b) {
+    return sizeof(uint32_t) * ((size_t)max_np * b + max_np) + sizeof(uint16_t) * (size_t)nlist;
+  };
+  while (B > 1 && lds_of(B) + 1024 > max_lds) --B;
+  const size_t lds = lds_of(B);
   if (lds + 1024 > max_lds) return false;
   *tshift = ts;
   *nbin = B;
