@@ -66,7 +66,7 @@ __device__ __forceinline__ int64_t slot_to_pos(int64_t i, const int64_t* __restr
 // every pass instead; a query whose sample exceeds 1024 * R keys takes that
 // path too.
 template <int R>
-__global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
+__global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectArgs a) {
   constexpr int NT = 1024, NW = NT / 64;
   constexpr int SEL_BITS = 12;  // bits of the key image resolved per select pass
   __shared__ uint32_t hist[1 << SEL_BITS];
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(1024) void codebook_kernel(CollectArgs a) {
         return;
       }
     }
-    block_for_batched<NT, 4>(Ts, [&](int64_t i) { return key_bits(keys[i]); }, use);
+    block_for_batched<NT, 8>(Ts, [&](int64_t i) { return key_bits(keys[i]); }, use);
   };
 
   if (a.t_nsample_keys && threadIdx.x == 0) a.t_nsample_keys[qi] = Ts;
