@@ -165,14 +165,16 @@ struct bbc_index {
   // host metadata
   std::vector<int64_t> h_list_off;
   std::vector<int64_t> h_maxS;  // h_maxS[p] = sum of the p largest list sizes
+  std::vector<int64_t> h_maxT;  // h_maxT[p] = sum of the p largest tile counts (tiles of 1 << h_maxT_ts rows)
+  int h_maxT_ts = -1;
   int max_lds = 65536;
   int num_cu = 256;
   int nxcd = 8;
   int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
-  int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide)
+  int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide, 3 wide with tile-major keys)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
-  int rerank_bins = 1024;   // tile-major form: most bins per (query, list) (BBC_RERANK_BINS, 1..1024)
+  int64_t rt_sort_bins = (int64_t)1 << 30;  // tile-major sort: most bin counters (BBC_RERANK_SORT_BINS)
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -271,11 +273,11 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   }
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
-    if (x >= 0 && x <= 2) ix->walk_form = x;
+    if (x >= 0 && x <= 3) ix->walk_form = x;
   }
-  if (const char* sv = std::getenv("BBC_RERANK_BINS")) {
-    const int x = std::atoi(sv);
-    if (x >= 1 && x <= 1024) ix->rerank_bins = x;
+  if (const char* sv = std::getenv("BBC_RERANK_SORT_BINS")) {
+    const long long x = std::atoll(sv);
+    if (x >= 1) ix->rt_sort_bins = x;
   }
   if (const char* sv = std::getenv("BBC_RERANK_FORM")) {
     const int x = std::atoi(sv);
@@ -691,7 +693,7 @@ struct Layout {
   size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
-      t_nb, qorder, rt_sorted, rt_bins, rt_lcnt, rt_lpairs;
+      t_nb, qorder, rt_sorted, rt_bins, rt_ptb, rt_lcnt, rt_lpairs;
 };
 
 int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
@@ -735,6 +737,51 @@ struct SearchCtx {
   hipGraph_t graph = nullptr;
 };
 
+// Tile counts of the largest lists for tiles of 1 << ts rows: h_maxT[p] =
+// sum of the p largest ceil(size / 2^ts), a bound on the bins of a query
+// probing p lists.
+const std::vector<int64_t>& tile_bounds(bbc_index* ix, int ts) {
+  if (ix->h_maxT_ts != ts) {
+    std::vector<int64_t> t(ix->nlist);
+    for (int32_t j = 0; j < ix->nlist; ++j)
+      t[j] = (ix->h_list_off[j + 1] - ix->h_list_off[j] + ((int64_t)1 << ts) - 1) >> ts;
+    std::sort(t.begin(), t.end(), std::greater<int64_t>());
+    ix->h_maxT.assign(ix->nlist + 1, 0);
+    for (int32_t j = 0; j < ix->nlist; ++j) ix->h_maxT[j + 1] = ix->h_maxT[j] + t[j];
+    ix->h_maxT_ts = ts;
+  }
+  return ix->h_maxT;
+}
+
+// Shape of the tile-major form for a batch: bin offsets per query and the
+// candidate sort's LDS; false where the form does not apply.
+bool tile_plan(bbc_index* ix, int64_t nq, const int32_t* nprobe, int max_np, int max_chunks,
+               std::vector<int64_t>& bin_off, int* ts, int* max_bins, size_t* lds) {
+  if (!ix->list_of_pos || nq > 65535 || ix->nlist > bbc::QUERY_ORDER_MAX_LISTS || max_np <= 0) return false;
+  if (ix->d / 4 > max_chunks) return false;
+  *ts = bbc::tile_rerank_shift(ix->d, ix->fp16);
+  if (*ts < 0) return false;
+  const std::vector<int64_t>& mt = tile_bounds(ix, *ts);
+  bin_off.assign(nq + 1, 0);
+  int64_t mb = 0;
+  for (int64_t i = 0; i < nq; ++i) {
+    const int64_t nb = mt[nprobe[i]];
+    bin_off[i + 1] = bin_off[i] + nb + 1;
+    mb = std::max(mb, nb);
+  }
+  // bin counters: as many as any query can have, or as many as fit in LDS
+  // (the candidate sort then takes a query's ranks in ranges); one list's
+  // tiles must fit
+  const size_t fixed = bbc::tile_rerank_sort_lds(0, max_np, ix->nlist) + 1024;
+  if (fixed >= (size_t)ix->max_lds) return false;
+  mb = std::min<int64_t>(mb, (int64_t)(((size_t)ix->max_lds - fixed) / sizeof(uint32_t)));
+  mb = std::max<int64_t>(std::min(mb, ix->rt_sort_bins), std::min(mb, mt[1]));
+  if (mb < mt[1] || mb > (int64_t)1 << 30) return false;
+  *max_bins = (int)mb;
+  *lds = bbc::tile_rerank_sort_lds(*max_bins, max_np, ix->nlist);
+  return *lds + 1024 <= (size_t)ix->max_lds;
+}
+
 // RaBitQ: probe, rotation of the queries, per-(query, list) bounds, bounded
 // re-rank per query, final sort.  Per-query slot arrays are sized by the
 // largest lists (maxS(nprobe)).
@@ -748,17 +795,33 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const bool tracing = tr != nullptr;
   std::vector<int64_t> probe_off(nq + 1, 0), key_off(nq + 1, 0);
   int64_t max_cap = 0, max_cnt = 1;
+  int max_np = 0;
   for (int64_t i = 0; i < nq; ++i) {
     probe_off[i + 1] = probe_off[i] + nprobe[i];
     const int64_t cap = ix->h_maxS[nprobe[i]];
     key_off[i + 1] = key_off[i] + cap;
     max_cap = std::max(max_cap, cap);
     max_cnt = std::max(max_cnt, std::min<int64_t>(k[i], cap));
+    max_np = std::max(max_np, nprobe[i]);
   }
   const int64_t npairs = probe_off[nq], nkeys = key_off[nq], nout = out_off[nq];
+  // Re-rank form: one block per query walking and gathering its rows, or the
+  // wide form (exact keys of the candidate set C first, then the walk over
+  // them), whose keys come from a device-wide grid per query (small
+  // batches) or tile-major from rows staged once per group of queries
+  // (large batches, where queries share rows).
+  std::vector<int64_t> bin_off;
+  int rt_shift = 0, rt_bins = 0;
+  size_t rt_lds = 0;
+  // (by default only for rows of at most 32 chunks: with longer rows a tile
+  // holds few rows, and each query's short run per tile does not repay
+  // loading its query again)
+  const bool want_tiles = ix->walk_form == 3 || (ix->walk_form == 0 && nq > ix->num_cu && d / 4 <= 32);
+  const bool tile_keys = want_tiles && tile_plan(ix, nq, nprobe, max_np, 256, bin_off, &rt_shift, &rt_bins, &rt_lds);
+  if (!tile_keys) bin_off.assign(nq + 1, 0);
   Plan mp;
   const size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)),
-               m_ko = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1));
+               m_ko = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1));
   Plan pl;
   const size_t L_meta = pl.add(mp.total);
   const size_t L_q = host_io ? pl.add(sizeof(float) * nq * d) : 0;
@@ -771,10 +834,16 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys), L_z = pl.add(16 * nkeys);
   const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
   // the wide re-rank form when the batch alone leaves compute units idle
-  // with one block per query
-  const bool wide = ix->walk_form == 2 || (ix->walk_form == 0 && nq <= ix->num_cu);
+  // with one block per query, or when its keys come tile-major
+  const bool wide = ix->walk_form == 2 || tile_keys || (ix->walk_form == 0 && nq <= ix->num_cu);
   size_t L_cpos = 0, L_wbins = 0, L_wst = 0;
   if (wide) { L_cpos = pl.add(4 * nkeys); L_wbins = pl.add(4 * 2048 * nq); L_wst = pl.add(16 * nq); }
+  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
+  size_t L_rts = 0, L_rti = 0, L_rtb = 0, L_rtp = 0, L_rtc = 0, L_rtl = 0;
+  if (tile_keys) {
+    L_rts = pl.add(4 * nkeys); L_rti = pl.add(4 * nkeys); L_rtb = pl.add(4 * bin_off[nq]);
+    L_rtp = pl.add(4 * npairs); L_rtc = pl.add(4 * ((int64_t)ix->nlist + 1)); L_rtl = pl.add(8 * rt_lpairs_cap);
+  }
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
   if (ctx && ctx->size_only) {
@@ -803,6 +872,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   std::memcpy(H + m_po, probe_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_ko, key_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
+  std::memcpy(H + m_bo, bin_off.data(), 8 * (nq + 1));
   char* M = A + L_meta;
   if (ctx && ctx->capture) {
     HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
@@ -821,6 +891,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const int32_t* d_np = reinterpret_cast<const int32_t*>(M + m_np);
   const int64_t* d_po = reinterpret_cast<const int64_t*>(M + m_po);
   const int64_t* d_ko = reinterpret_cast<const int64_t*>(M + m_ko);
+  const int64_t* d_bo = reinterpret_cast<const int64_t*>(M + m_bo);
   const int64_t* d_oo = reinterpret_cast<const int64_t*>(M + m_oo);
   int64_t* d_oid = host_io ? reinterpret_cast<int64_t*>(A + L_oid) : out_ids;
   float* d_odist = host_io ? reinterpret_cast<float*>(A + L_od) : out_dists;
@@ -884,6 +955,27 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   }
   {
     StageScope st(s, 4);
+    if (tile_keys) {
+      // the exact keys of C, tile-major, at C's indices (what the walk reads)
+      bbc::TileRerankArgs ta{};
+      ta.q = dq; ta.nq = nq; ta.d = d; ta.metric = ix->metric; ta.vectors = ix->vectors; ta.fp16 = ix->fp16;
+      ta.list_ids = ix->list_ids; ta.list_off = ix->list_off; ta.list_of_pos = ix->list_of_pos;
+      ta.nprobe = d_np; ta.probe_off = d_po; ta.probe_lists = pa.probe_lists; ta.nlist = ix->nlist;
+      ta.cand_pos = reinterpret_cast<const uint32_t*>(wa.cpos); ta.pos_off = d_ko;
+      ta.ncand_w = wa.wstate + 3; ta.ncand_stride = 4;
+      ta.cand_off = d_ko; ta.cand_packed = wa.cand_packed;
+      ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
+      ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L_rts);
+      ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L_rti);
+      ta.pair_tb = reinterpret_cast<uint32_t*>(A + L_rtp);
+      ta.bin_off = d_bo;
+      ta.bin_beg = reinterpret_cast<uint32_t*>(A + L_rtb);
+      ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
+      ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
+      ta.lpairs_cap = rt_lpairs_cap;
+      HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
+      wa.keys_ready = 1;
+    }
     HIP_TRY(bbc::launch_rabitq_walk(wa, s));
   }
   const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
@@ -998,12 +1090,19 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const int64_t nkeys = key_off[nq];
   const int64_t ncand = cand_off[nq];
   const int64_t nout = out_off[nq];
+  // tile-major re-rank (rows of at most 32 chunks): bins per query
+  std::vector<int64_t> bin_off;
+  int rt_shift = 0, rt_bins = 0;
+  size_t rt_lds = 0;
+  const bool tile_rr = ix->rerank_form == 0 &&
+                       tile_plan(ix, nq, nprobe, max_np, 32, bin_off, &rt_shift, &rt_bins, &rt_lds);
+  if (!tile_rr) bin_off.assign(nq + 1, 0);
 
   // metadata block (one upload): k, nprobe, then the prefix arrays
   Plan mp;
   size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),
          m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)),
-         m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1));
+         m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1));
   Plan pl;
   Layout L{};
   L.meta = pl.add(mp.total);
@@ -1033,15 +1132,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.n_cand = pl.add(8 * nq);
   L.qorder = pl.add(4 * nq);
   // tile-major re-rank: its sort buffers
-  int rt_shift = 0, rt_nbin = 0;
-  size_t rt_lds = 0;
-  const bool tile_rr = ix->rerank_form == 0 && ix->list_of_pos && nq <= 65535 &&
-                       bbc::tile_rerank_shape(d, ix->fp16, max_list, max_np, ix->nlist, (size_t)ix->max_lds,
-                                              ix->rerank_bins, &rt_shift, &rt_nbin, &rt_lds);
   const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
   if (tile_rr) {
     L.rt_sorted = pl.add(4 * ncand);
-    L.rt_bins = pl.add(4 * npairs * (rt_nbin + 1));
+    L.rt_bins = pl.add(4 * bin_off[nq]);
+    L.rt_ptb = pl.add(4 * npairs);
     L.rt_lcnt = pl.add(4 * ((int64_t)ix->nlist + 1));
     L.rt_lpairs = pl.add(8 * rt_lpairs_cap);
   }
@@ -1086,6 +1181,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
   std::memcpy(H + m_so, sample_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_vo, surv_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_bo, bin_off.data(), 8 * (nq + 1));
   char* M = A + L.meta;
   if (ctx && ctx->capture) {
     HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
@@ -1109,6 +1205,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const int64_t* d_oo = reinterpret_cast<const int64_t*>(M + m_oo);
   const int64_t* d_so = reinterpret_cast<const int64_t*>(M + m_so);
   const int64_t* d_vo = reinterpret_cast<const int64_t*>(M + m_vo);
+  const int64_t* d_bo = reinterpret_cast<const int64_t*>(M + m_bo);
   int64_t* d_oid = host_io ? reinterpret_cast<int64_t*>(A + L.out_ids) : out_ids;
   float* d_odist = host_io ? reinterpret_cast<float*>(A + L.out_dists) : out_dists;
   int32_t* d_ocnt = host_io ? reinterpret_cast<int32_t*>(A + L.out_counts) : out_counts;
@@ -1220,9 +1317,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.q = dq; ta.nq = nq; ta.d = d; ta.metric = ix->metric; ta.vectors = ix->vectors; ta.fp16 = ix->fp16;
       ta.list_ids = ix->list_ids; ta.list_off = ix->list_off; ta.list_of_pos = ix->list_of_pos;
       ta.nprobe = d_np; ta.probe_off = d_po; ta.probe_lists = pa.probe_lists; ta.nlist = ix->nlist;
-      ta.cand_pos = ca.cand_pos; ta.cand_off = d_co; ta.n_cand = ca.n_cand; ta.cand_packed = ra.cand_packed;
-      ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.nbin = rt_nbin;
+      ta.cand_pos = ca.cand_pos; ta.pos_off = d_co; ta.n_cand = ca.n_cand;
+      ta.cand_off = d_co; ta.cand_packed = ra.cand_packed;
+      ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
       ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L.rt_sorted);
+      ta.pair_tb = reinterpret_cast<uint32_t*>(A + L.rt_ptb);
+      ta.bin_off = d_bo;
       ta.bin_beg = reinterpret_cast<uint32_t*>(A + L.rt_bins);
       ta.lcnt = reinterpret_cast<uint32_t*>(A + L.rt_lcnt);
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);

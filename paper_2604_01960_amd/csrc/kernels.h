@@ -112,27 +112,36 @@ struct RerankArgs {
 hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 constexpr int QUERY_ORDER_MAX_LISTS = 32768;
 
-// Tile-major re-rank (rows of at most 32 four-element chunks).
+// Tile-major re-rank (rows of at most 256 four-element chunks).
 constexpr int RT_G = 128;              // (query, list) pairs per block
 constexpr int RT_TILE_BYTES = 65536;   // LDS rows per tile
 struct TileRerankArgs {
   const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;
   const int32_t* list_ids; const int64_t* list_off; const int32_t* list_of_pos;
   const int32_t* nprobe; const int64_t* probe_off; const int32_t* probe_lists; int nlist;
-  const uint32_t* cand_pos; const int64_t* cand_off; const int64_t* n_cand;
-  uint64_t* cand_packed;    // out: (key, id) of candidate j of query q at cand_off[q] + j (sorted_pos order)
+  // candidates of query q: cand_pos[pos_off[q] + i], i < n_cand[q] (or
+  // ncand_w[q * ncand_stride] when ncand_w is set)
+  const uint32_t* cand_pos; const int64_t* pos_off; const int64_t* n_cand;
+  const uint32_t* ncand_w; int ncand_stride;
+  // out: (key, id) of candidate i at cand_packed[cand_off[q] + i] when
+  // sorted_idx is set, else at the candidate's place in the sorted order
+  const int64_t* cand_off; uint64_t* cand_packed;
   int64_t npairs; int max_np;
   int tshift;               // rows per tile = 1 << tshift
-  int nbin;                 // bins per (query, list) pair; tiles from nbin - 1 on share the last
-  uint32_t* sorted_pos;     // [sum cap] each query's candidates grouped by (rank, bin)
-  uint32_t* bin_beg;        // [npairs][nbin + 1] bin starts within the query's candidates, then the end
+  int max_bins;             // most bins of a query (tiles of its probed lists)
+  uint32_t* sorted_pos;     // [by pos_off] each query's candidates grouped by (rank, tile)
+  uint32_t* sorted_idx;     // optional [by pos_off]: their candidate indices
+  uint32_t* pair_tb;        // [npairs] first bin of each (query, rank) pair within its query
+  const int64_t* bin_off;   // [nq + 1] each query's bins in bin_beg
+  uint32_t* bin_beg;        // [bin_off[nq]] bin starts within the query's candidates, then the count
   uint32_t* lcnt;           // [nlist + 1] pair counts, then cursors; [nlist] = number of groups
   uint64_t* lpairs;         // [lpairs_cap] (query << 32 | rank) grouped by list, whole groups of RT_G
   int64_t lpairs_cap;       // npairs + nlist * (RT_G - 1)
 };
-// Tile rows and bins for the batch shape; false where the form does not apply.
-bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int max_bins,
-                       int* tshift, int* nbin, size_t* sort_lds);
+// log2 of the rows per tile for the row shape, or -1 where the form does not apply
+int tile_rerank_shift(int d, int fp16);
+// dynamic LDS of the candidate sort
+size_t tile_rerank_sort_lds(int max_bins, int max_np, int nlist);
 hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s);
 // order[0, nq): the queries sorted by their nearest probed list
 hipError_t launch_query_order(const int32_t* probe_lists, const int64_t* probe_off, const int32_t* nprobe,
@@ -204,6 +213,7 @@ struct RabitqWalkArgs {
   int32_t* cpos;             // [sum S] list positions of C in cbuf order
   uint32_t* wbins;           // [nq][2048] bin ends
   uint32_t* wstate;          // [nq][4] U, lmin, shift, |C|
+  int keys_ready;            // wide form: the exact keys of C are already in cand_packed
 };
 // wide form: the bins of C (a no-op otherwise); then the exact keys of C
 // (wide form) and the walk

@@ -917,7 +917,7 @@ hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s) {
 
 hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
-  if (a.wide) {
+  if (a.wide && !a.keys_ready) {
     if (a.nq > 65535 || a.max_c < 1) return hipErrorInvalidValue;
     const dim3 g((unsigned)((a.max_c + EX_ROWS - 1) / EX_ROWS), (unsigned)a.nq);
     if (a.fp16) hipLaunchKernelGGL(rabitq_exact_kernel<__half>, g, dim3(256), 0, s, a);

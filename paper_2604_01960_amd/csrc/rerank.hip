@@ -180,20 +180,19 @@ hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---- Tile-major re-rank (rows of at most 32 chunks) --------------------------
+// ---- Tile-major re-rank -------------------------------------------------------
 // The per-query form reads every candidate row once per query that holds it.
 // Here the batch's (query, probed list) pairs are grouped by list, a block
 // takes one list and up to RT_G of the queries probing it, and it stages the
 // list's rows in LDS one tile (1 << tshift rows) at a time: each row then
 // comes from memory once per block instead of once per query.  Each query's
 // candidates are first grouped by (probe rank, tile of the list) with a
-// counting sort in LDS, so that a block finds the candidates of a (query,
-// tile) as one range.  Tiles from nbin - 1 on share the last bin and are
-// told apart by position.  The distance of each pair is the same canonical
-// half-wave computation as above, so the keys are identical.
+// counting sort in LDS (one bin per tile of each probed list), so that a
+// block finds the candidates of a (query, tile) as one range.  The distance
+// of each candidate follows the canonical order, so the keys are identical
+// to those of the per-query kernels.
 
 constexpr uint64_t RT_NO_PAIR = ~0ull;
-constexpr int RT_UNROLL = 2;  // rows of a half-wave in flight (they come from LDS)
 
 __global__ void rt_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -259,147 +258,197 @@ __global__ __launch_bounds__(256) void rt_pair_scatter(TileRerankArgs a) {
   }
 }
 
-// One block per query: its candidates grouped by bin = rank * nbin +
-// min(tile, nbin - 1); bin_beg[(pair) * (nbin + 1) + b] = start of bin b of
-// the pair (within the query's candidates), [.. + nbin] = the pair's end.
+__device__ __forceinline__ int64_t rt_ncand(const TileRerankArgs& a, int64_t q) {
+  return a.ncand_w ? (int64_t)a.ncand_w[q * a.ncand_stride] : a.n_cand[q];
+}
+
+// One block per query: its candidates grouped by bin = pair_tb[rank] + tile
+// (one bin per tile of each probed list); bin_beg[bin_off[q] + b] = start of
+// bin b within the query's candidates, [.. + nbins] = their count.  The bin
+// counters live in LDS (max_bins of them); a query with more bins is sorted
+// in consecutive rank ranges whose bins fit, one pair of passes each.
 __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
   constexpr int NT = 1024;
   extern __shared__ __align__(16) uint32_t sm[];
   __shared__ uint32_t s_w[16];
-  __shared__ uint32_t s_tot;
+  __shared__ uint32_t s_tot, s_nb;
   const int64_t q = blockIdx.x;
   const int np = a.nprobe[q];
-  const int64_t po = a.probe_off[q], co = a.cand_off[q];
-  const int64_t kc = a.n_cand[q];
-  const int B = a.nbin, nb = np * B;
-  uint32_t* cnt = sm;                                                      // [max_np * nbin]
-  int32_t* s_lbeg = reinterpret_cast<int32_t*>(sm + (size_t)a.max_np * B);  // [max_np]
-  uint16_t* rank_of = reinterpret_cast<uint16_t*>(s_lbeg + a.max_np);      // [nlist]
+  const int64_t po = a.probe_off[q], pof = a.pos_off[q];
+  const int64_t kc = rt_ncand(a, q);
+  uint32_t* cnt = sm;                                                     // [max_bins]
+  uint32_t* s_tb = sm + a.max_bins;                                       // [max_np] first bin of each rank
+  int32_t* s_lbeg = reinterpret_cast<int32_t*>(s_tb + a.max_np);          // [max_np]
+  uint16_t* rank_of = reinterpret_cast<uint16_t*>(s_lbeg + a.max_np);     // [nlist]
   for (int L = threadIdx.x; L < a.nlist; L += NT) rank_of[L] = 0;
-  for (int i = threadIdx.x; i < nb; i += NT) cnt[i] = 0;
   __syncthreads();
   for (int r = threadIdx.x; r < np; r += NT) {
     const int L = a.probe_lists[po + r];
     rank_of[L] = (uint16_t)r;
-    s_lbeg[r] = (int32_t)a.list_off[L];
+    const int64_t lb = a.list_off[L];
+    s_lbeg[r] = (int32_t)lb;
+    s_tb[r] = (uint32_t)((a.list_off[L + 1] - lb + ((int64_t)1 << a.tshift) - 1) >> a.tshift);
   }
   __syncthreads();
-  const uint32_t* cpos = a.cand_pos + co;
-  auto bin_of = [&](uint32_t pos) -> uint32_t {
-    const int r = min((int)rank_of[a.list_of_pos[pos]], np - 1);  // candidates lie in probed lists
-    const uint32_t t = (pos - (uint32_t)s_lbeg[r]) >> a.tshift;
-    return (uint32_t)(r * B) + min(t, (uint32_t)(B - 1));
-  };
-  block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t, bool valid, uint32_t pos) {
-    if (valid) atomicAdd(&cnt[bin_of(pos)], 1u);
-  });
-  __syncthreads();
-  block_excl_scan<NT>(cnt, nb, s_w, &s_tot);
-  uint32_t* bb = a.bin_beg + po * (B + 1);
-  for (int i = threadIdx.x; i < np * (B + 1); i += NT) {
-    const int r = i / (B + 1), b = i - r * (B + 1);
-    bb[i] = b < B ? cnt[r * B + b] : (r + 1 < np ? cnt[(r + 1) * B] : (uint32_t)kc);
+  block_excl_scan<NT>(s_tb, np, s_w, &s_nb);
+  const uint32_t nb = s_nb;  // bins of this query
+  for (int r = threadIdx.x; r < np; r += NT) a.pair_tb[po + r] = s_tb[r];
+  const uint32_t* cpos = a.cand_pos + pof;
+  uint32_t* bb = a.bin_beg + a.bin_off[q];
+  uint32_t* out = a.sorted_pos + pof;
+  uint32_t* oidx = a.sorted_idx ? a.sorted_idx + pof : nullptr;
+  auto rank_at = [&](uint32_t pos) { return min((int)rank_of[a.list_of_pos[pos]], np - 1); };
+  uint32_t base = 0;  // candidates placed by the earlier rank ranges
+  for (int rlo = 0; rlo < np;) {
+    // ranks [rlo, rhi): the most whose bins fit in the counters (at least one:
+    // a list's tiles never exceed them)
+    int rhi = rlo + 1;
+    while (rhi < np && (rhi + 1 < np ? s_tb[rhi + 1] : nb) - s_tb[rlo] <= (uint32_t)a.max_bins) ++rhi;
+    const uint32_t b0 = s_tb[rlo], b1 = rhi < np ? s_tb[rhi] : nb;
+    for (uint32_t i = threadIdx.x; i < b1 - b0; i += NT) cnt[i] = 0;
+    __syncthreads();
+    block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t, bool valid, uint32_t pos) {
+      if (!valid) return;
+      const int r = rank_at(pos);
+      if (r >= rlo && r < rhi) atomicAdd(&cnt[s_tb[r] - b0 + ((pos - (uint32_t)s_lbeg[r]) >> a.tshift)], 1u);
+    });
+    __syncthreads();
+    block_excl_scan<NT>(cnt, (int)(b1 - b0), s_w, &s_tot);
+    for (uint32_t i = threadIdx.x; i < b1 - b0; i += NT) {
+      cnt[i] += base;
+      bb[b0 + i] = cnt[i];
+    }
+    __syncthreads();
+    block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t i, bool valid, uint32_t pos) {
+      if (!valid) return;
+      const int r = rank_at(pos);
+      if (r >= rlo && r < rhi) {
+        const uint32_t slot = atomicAdd(&cnt[s_tb[r] - b0 + ((pos - (uint32_t)s_lbeg[r]) >> a.tshift)], 1u);
+        out[slot] = pos;
+        if (oidx) oidx[slot] = (uint32_t)i;
+      }
+    });
+    base += s_tot;
+    rlo = rhi;
+    __syncthreads();
   }
-  __syncthreads();
-  uint32_t* out = a.sorted_pos + co;
-  block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t, bool valid, uint32_t pos) {
-    if (valid) out[atomicAdd(&cnt[bin_of(pos)], 1u)] = pos;
-  });
+  if (threadIdx.x == 0) bb[nb] = (uint32_t)kc;
 }
 
+// Shared by both tile kernels: the block's pairs, the rows of tile t in LDS,
+// and the tile's work cut into runs of up to 64 candidates of one pair.
+struct RtGroup {
+  int32_t q[RT_G], r[RT_G];
+  int64_t co[RT_G], pof[RT_G];   // output and position offsets of the pair's query
+  int64_t bbase[RT_G];           // the pair's first bin in bin_beg
+  uint32_t beg[RT_G], end[RT_G];  // the pair's candidates in this tile's bin
+  uint32_t cpre[RT_G + 1];       // runs before each pair (this tile)
+};
+
+template <int NT>
+__device__ __forceinline__ void rt_load_group(const TileRerankArgs& a, int64_t blk, RtGroup& g) {
+  if (threadIdx.x < RT_G) {
+    const uint64_t e = a.lpairs[blk * RT_G + threadIdx.x];
+    const int q = e == RT_NO_PAIR ? -1 : (int32_t)(e >> 32);
+    g.q[threadIdx.x] = q;
+    g.r[threadIdx.x] = (int32_t)(e & 0xffffffffu);
+    g.co[threadIdx.x] = q >= 0 ? a.cand_off[q] : 0;
+    g.pof[threadIdx.x] = q >= 0 ? a.pos_off[q] : 0;
+    g.bbase[threadIdx.x] = q >= 0 ? a.bin_off[q] + a.pair_tb[a.probe_off[q] + g.r[threadIdx.x]] : 0;
+  }
+}
+
+// rows [r0, r0 + nr) of the list into LDS, two loads in flight per thread
+template <int NT>
+__device__ __forceinline__ void rt_stage_rows(uint4* tile, const uint4* sw, int nw) {
+  for (int w = threadIdx.x; w < nw; w += 2 * NT) {
+    const int w2 = w + NT;
+    const uint4 v0 = sw[w];
+    const uint4 v1 = w2 < nw ? sw[w2] : make_uint4(0u, 0u, 0u, 0u);
+    tile[w] = v0;
+    if (w2 < nw) tile[w2] = v1;
+  }
+}
+
+// by lanes 0..63 of wave 0: each pair's bin for tile t, cut into 64-candidate runs
+__device__ __forceinline__ void rt_runs(const TileRerankArgs& a, int t, RtGroup& g) {
+  constexpr int EPL = RT_G / 64;
+  uint32_t nc[EPL], tot = 0;
+#pragma unroll
+  for (int h = 0; h < EPL; ++h) {
+    const int e = EPL * (int)threadIdx.x + h;
+    uint32_t b0 = 0, b1 = 0;
+    if (g.q[e] >= 0) {
+      const uint32_t* bb = a.bin_beg + g.bbase[e] + t;
+      b0 = bb[0];
+      b1 = bb[1];
+    }
+    g.beg[e] = b0;
+    g.end[e] = b1;
+    nc[h] = (b1 - b0 + 63) / 64;
+    tot += nc[h];
+  }
+  uint32_t run = wave_incl_scan(tot) - tot;
+#pragma unroll
+  for (int h = 0; h < EPL; ++h) {
+    g.cpre[EPL * threadIdx.x + h] = run;
+    run += nc[h];
+  }
+  if (threadIdx.x == 63) g.cpre[RT_G] = run;
+}
+
+__device__ __forceinline__ int rt_run_pair(const RtGroup& g, uint32_t c) {
+  int e = 0;
+#pragma unroll
+  for (int step = RT_G / 2; step >= 1; step >>= 1)
+    if (g.cpre[e + step] <= c) e += step;
+  return e;
+}
+
+// Rows of at most 32 chunks: 8 lanes per candidate, lane p of an octet
+// holding the virtual lanes (four-element chunks) p, p + 8, p + 16 and p + 24
+// of the canonical sum.
 template <typename T>
 __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   constexpr int NT = 1024, NW = NT / 64;
   __shared__ uint4 tile[RT_TILE_BYTES / 16];
-  __shared__ int32_t s_q[RT_G], s_r[RT_G];
-  __shared__ int64_t s_co[RT_G];             // candidate offset of the pair's query
-  __shared__ uint32_t s_beg[RT_G], s_end[RT_G];  // the pair's candidates in this tile's bin
-  __shared__ uint32_t s_cpre[RT_G + 1];      // 64-candidate chunks before each pair (this tile)
+  __shared__ RtGroup g;
   const int64_t blk = blockIdx.x;
   if (blk >= (int64_t)a.lcnt[a.nlist]) return;
-  if (threadIdx.x < RT_G) {
-    const uint64_t e = a.lpairs[blk * RT_G + threadIdx.x];
-    const int q = e == RT_NO_PAIR ? -1 : (int32_t)(e >> 32);
-    s_q[threadIdx.x] = q;
-    s_r[threadIdx.x] = (int32_t)(e & 0xffffffffu);
-    s_co[threadIdx.x] = q >= 0 ? a.cand_off[q] : 0;
-  }
+  rt_load_group<NT>(a, blk, g);
   __syncthreads();
   // the group's first pair is always a real one (padding ends a segment)
-  const int L = a.probe_lists[a.probe_off[s_q[0]] + s_r[0]];
+  const int L = a.probe_lists[a.probe_off[g.q[0]] + g.r[0]];
   const int64_t lb = a.list_off[L], le = a.list_off[L + 1];
   const int TR = 1 << a.tshift;
   const int ntile = (int)((le - lb + TR - 1) >> a.tshift);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  // 8 lanes per candidate: lane p of an octet holds the virtual lanes
-  // (four-element chunks) p, p + 8, p + 16 and p + 24 of the canonical sum
   const int oct = lane >> 3, p = lane & 7;
   const int nchunk = a.d >> 2;
   const bool ip = a.metric != 0;
-  const int B = a.nbin;
   const int row_words = a.d * (int)sizeof(T) / 16;  // 16-byte words per row
   const T* trow = reinterpret_cast<const T*>(tile);
   const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
   for (int t = 0; t < ntile; ++t) {
     const int64_t r0 = (int64_t)t * TR;
     const int nr = (int)min((int64_t)TR, le - lb - r0);
-    const int bin = min(t, B - 1);
     __syncthreads();  // the previous tile is no longer read
-    {
-      // the tile's rows, two loads in flight per thread
-      const int nw = nr * row_words;
-      const uint4* sw = src + r0 * row_words;
-      for (int w = threadIdx.x; w < nw; w += 2 * NT) {
-        const int w2 = w + NT;
-        const uint4 v0 = sw[w];
-        const uint4 v1 = w2 < nw ? sw[w2] : make_uint4(0u, 0u, 0u, 0u);
-        tile[w] = v0;
-        if (w2 < nw) tile[w2] = v1;
-      }
-    }
-    if (threadIdx.x < 64) {
-      // each pair's candidates in this tile's bin, cut into 64-candidate
-      // chunks (RT_G / 64 consecutive pairs per lane)
-      constexpr int EPL = RT_G / 64;
-      uint32_t nc[EPL], tot = 0;
-#pragma unroll
-      for (int h = 0; h < EPL; ++h) {
-        const int e = EPL * (int)threadIdx.x + h;
-        uint32_t b0 = 0, b1 = 0;
-        if (s_q[e] >= 0) {
-          const uint32_t* bb = a.bin_beg + (a.probe_off[s_q[e]] + s_r[e]) * (B + 1);
-          b0 = bb[bin];
-          b1 = bb[bin + 1];
-        }
-        s_beg[e] = b0;
-        s_end[e] = b1;
-        nc[h] = (b1 - b0 + 63) / 64;
-        tot += nc[h];
-      }
-      uint32_t run = wave_incl_scan(tot) - tot;
-#pragma unroll
-      for (int h = 0; h < EPL; ++h) {
-        s_cpre[EPL * threadIdx.x + h] = run;
-        run += nc[h];
-      }
-      if (threadIdx.x == 63) s_cpre[RT_G] = run;
-    }
+    rt_stage_rows<NT>(tile, src + r0 * row_words, nr * row_words);
+    if (threadIdx.x < 64) rt_runs(a, t, g);
     __syncthreads();
-    const uint32_t nchk = s_cpre[RT_G];
-    for (uint32_t c = wv; c < nchk; c += NW) {
-      int e = 0;  // the pair holding chunk c
-#pragma unroll
-      for (int step = RT_G / 2; step >= 1; step >>= 1)
-        if (s_cpre[e + step] <= c) e += step;
-      const uint32_t j0 = s_beg[e] + (c - s_cpre[e]) * 64;
-      const int cnt = (int)min(64u, s_end[e] - j0);
-      const int q = s_q[e];
-      const int64_t co = s_co[e];
-      // lane l: candidate l's position, id and row in the tile (-1: none)
-      const uint32_t pl = lane < cnt ? a.sorted_pos[co + j0 + lane] : 0u;
+    const uint32_t nrun = g.cpre[RT_G];
+    for (uint32_t c = wv; c < nrun; c += NW) {
+      const int e = rt_run_pair(g, c);
+      const uint32_t j0 = g.beg[e] + (c - g.cpre[e]) * 64;
+      const int cnt = (int)min(64u, g.end[e] - j0);
+      const int q = g.q[e];
+      const int64_t co = g.co[e], pof = g.pof[e];
+      // lane l: candidate l's position, id, output index and row in the tile (-1: none)
+      const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
       const int64_t rl = (int64_t)pl - lb - r0;
       const bool okl = lane < cnt && rl >= 0 && rl < nr;
       const int32_t idl = okl ? a.list_ids[pl] : 0;
+      const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
       const int rowl = okl ? (int)rl : -1;
       float4 qv[4];
 #pragma unroll
@@ -428,32 +477,88 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
         const float kk = __shfl(sum, 8 * (lane & 7));
         if ((lane >> 3) == it) mykey = ip ? -kk : kk;
       }
-      if (okl) a.cand_packed[co + j0 + lane] = pack_key_id(mykey, (uint32_t)idl);
+      if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
     }
   }
 }
 
-bool tile_rerank_shape(int d, int fp16, int64_t max_list, int max_np, int nlist, size_t max_lds, int max_bins,
-                       int* tshift, int* nbin, size_t* sort_lds) {
-  if (d <= 0 || d % 4 || d / 4 > 32 || nlist > QUERY_ORDER_MAX_LISTS || max_np <= 0) return false;
+// Rows of 33 to 256 chunks: one wave per candidate, lane l holding chunks
+// l, l + 64, l + 128 and l + 192 (the canonical steps of virtual lane l).
+template <typename T>
+__global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a) {
+  constexpr int NT = 1024, NW = NT / 64;
+  __shared__ uint4 tile[RT_TILE_BYTES / 16];
+  __shared__ RtGroup g;
+  const int64_t blk = blockIdx.x;
+  if (blk >= (int64_t)a.lcnt[a.nlist]) return;
+  rt_load_group<NT>(a, blk, g);
+  __syncthreads();
+  const int L = a.probe_lists[a.probe_off[g.q[0]] + g.r[0]];
+  const int64_t lb = a.list_off[L], le = a.list_off[L + 1];
+  const int TR = 1 << a.tshift;
+  const int ntile = (int)((le - lb + TR - 1) >> a.tshift);
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nchunk = a.d >> 2;
+  const bool ip = a.metric != 0;
+  const int row_words = a.d * (int)sizeof(T) / 16;
+  const T* trow = reinterpret_cast<const T*>(tile);
+  const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
+  for (int t = 0; t < ntile; ++t) {
+    const int64_t r0 = (int64_t)t * TR;
+    const int nr = (int)min((int64_t)TR, le - lb - r0);
+    __syncthreads();
+    rt_stage_rows<NT>(tile, src + r0 * row_words, nr * row_words);
+    if (threadIdx.x < 64) rt_runs(a, t, g);
+    __syncthreads();
+    const uint32_t nrun = g.cpre[RT_G];
+    for (uint32_t c = wv; c < nrun; c += NW) {
+      const int e = rt_run_pair(g, c);
+      const uint32_t j0 = g.beg[e] + (c - g.cpre[e]) * 64;
+      const int cnt = (int)min(64u, g.end[e] - j0);
+      const int q = g.q[e];
+      const int64_t co = g.co[e], pof = g.pof[e];
+      const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
+      const int64_t rl = (int64_t)pl - lb - r0;
+      const bool okl = lane < cnt && rl >= 0 && rl < nr;
+      const int32_t idl = okl ? a.list_ids[pl] : 0;
+      const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
+      const int rowl = okl ? (int)rl : -1;
+      float4 qv[4];
+#pragma unroll
+      for (int st = 0; st < 4; ++st) {
+        const int c4 = lane + 64 * st;
+        qv[st] = c4 < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * a.d)[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      float mykey = 0.0f;
+      for (int jj = 0; jj < cnt; ++jj) {
+        const int rr = __builtin_amdgcn_readlane(rowl, jj);
+        if (rr < 0) continue;  // wave-uniform
+        const T* row = trow + (int64_t)rr * a.d;
+        float acc = 0.0f;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          const int c4 = lane + 64 * st;
+          if (c4 < nchunk) acc = ip ? chunk_ip(qv[st], load4<T>(row, c4), acc) : chunk_l2(qv[st], load4<T>(row, c4), acc);
+        }
+        acc = canon_reduce64(acc);  // every lane ends with the sum
+        if (lane == jj) mykey = ip ? -acc : acc;
+      }
+      if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
+    }
+  }
+}
+
+int tile_rerank_shift(int d, int fp16) {
+  if (d <= 0 || d % 4 || d / 4 > 256) return -1;
   const int64_t row_bytes = (int64_t)d * (fp16 ? 2 : 4);
-  if (row_bytes % 16) return false;
+  if (row_bytes % 16 || row_bytes > RT_TILE_BYTES) return -1;
   int ts = 0;
   while (((int64_t)2 << ts) * row_bytes <= RT_TILE_BYTES) ++ts;
-  // one bin per tile of the longest list where the candidate sort's LDS
-  // allows it (a shared last bin is read again for each of its tiles)
-  const int64_t tiles = (max_list + ((int64_t)1 << ts) - 1) >> ts;
-  int B = (int)std::min<int64_t>(std::max<int64_t>(tiles, 1), std::max(1, max_bins));
-  auto lds_of = [&](int b) {
-    return sizeof(uint32_t) * ((size_t)max_np * b + max_np) + sizeof(uint16_t) * (size_t)nlist;
-  };
-  while (B > 1 && lds_of(B) + 1024 > max_lds) --B;
-  const size_t lds = lds_of(B);
-  if (lds + 1024 > max_lds) return false;
-  *tshift = ts;
-  *nbin = B;
-  *sort_lds = lds;
-  return true;
+  return ts;
+}
+
+size_t tile_rerank_sort_lds(int max_bins, int max_np, int nlist) {
+  return sizeof(uint32_t) * ((size_t)max_bins + 2 * (size_t)max_np) + sizeof(uint16_t) * (size_t)nlist;
 }
 
 hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s) {
@@ -468,8 +573,14 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
   hipLaunchKernelGGL(rt_pair_scatter, pg, dim3(256), 0, s, a);
   hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
   const int64_t groups = (a.npairs + RT_G - 1) / RT_G + a.nlist;  // bound on the padded group count
-  if (a.fp16) hipLaunchKernelGGL(rt_rerank_tile<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
-  else hipLaunchKernelGGL(rt_rerank_tile<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  const bool wide = a.d / 4 > 32;
+  if (a.fp16) {
+    if (wide) hipLaunchKernelGGL(rt_rerank_tile_wide<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL(rt_rerank_tile<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  } else {
+    if (wide) hipLaunchKernelGGL(rt_rerank_tile_wide<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL(rt_rerank_tile<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  }
   return hipGetLastError();
 }
 

@@ -125,14 +125,14 @@ def test_large_threshold_buckets(bbc, bcap):
             assert np.any(tr["n_boundary"] > 64)
 
 
-@pytest.mark.parametrize("form", ["tile", "tile_4bins", "per_query"])
+@pytest.mark.parametrize("form", ["tile", "tile_ranges", "per_query"])
 @pytest.mark.parametrize("shape", ["long_lists", "many_queries"])
 def test_rerank_forms(bbc, form, shape):
     """Both re-rank forms against the oracle: the tile-major one (a list's
     rows staged in LDS once per group of queries) and one block per query.
-    With 4 bins, long lists have more tiles than bins (the last bin is
-    shared); many queries per list fill several groups of pairs for one
-    list."""
+    Long lists span many tiles (one bin each); many queries per list fill
+    several groups of pairs for one list.  With the bin counters cut to one
+    list's tiles, the candidate sort takes each query's ranks in ranges."""
     import os
     if shape == "long_lists":
         w, ix, q = oracle_pq_index("ivfpq4_10m_d96", 20000, 6, 48, 4, 10)
@@ -143,14 +143,14 @@ def test_rerank_forms(bbc, form, shape):
         k = np.full(150, 200, np.int32)
         npb = np.full(150, 20, np.int32)
         npb[::7] = 32
-    os.environ["BBC_RERANK_FORM"] = {"tile": "0", "tile_4bins": "0", "per_query": "1"}[form]
-    if form == "tile_4bins":
-        os.environ["BBC_RERANK_BINS"] = "4"
+    os.environ["BBC_RERANK_FORM"] = {"tile": "0", "tile_ranges": "0", "per_query": "1"}[form]
+    if form == "tile_ranges":
+        os.environ["BBC_RERANK_SORT_BINS"] = "1"
     try:
         g = make_gpu_index(bbc, ix)
     finally:
         del os.environ["BBC_RERANK_FORM"]
-        os.environ.pop("BBC_RERANK_BINS", None)
+        os.environ.pop("BBC_RERANK_SORT_BINS", None)
     print(f"[case] rerank form={form} shape={shape}", flush=True)
     tr = g.search_traced(q, k, npb, ratio=2.0, buckets=64, nsample=2)
     exp = expected_steps(ix, q, k, npb, 2.0, 64, 2)

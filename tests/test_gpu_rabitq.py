@@ -37,12 +37,13 @@ def _data(d, n, nq, nlist, metric, fp16=False, seed_index=2):
     return x, q, tr, ip, P, ix
 
 
-FORMS = {"per_query": "1", "wide": "2"}
+FORMS = {"per_query": "1", "wide": "2", "tiles": "3"}
 
 
 def _gpu_index(bbc, x, ix, eps0=0.0, form="per_query"):
     """The re-rank form (one block per query, or the exact keys of all
-    candidates by a device-wide grid first) is fixed when the index is made."""
+    candidates first, by a device-wide grid or tile-major from rows staged
+    once per group of queries) is fixed when the index is made."""
     import os
     old = os.environ.get("BBC_WALK_FORM")
     os.environ["BBC_WALK_FORM"] = FORMS[form]
@@ -135,3 +136,21 @@ def test_device_io_and_repeat(bbc):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(ids.cpu().numpy(), a[0])
     np.testing.assert_array_equal(dists.cpu().numpy(), a[1])
+
+
+@pytest.mark.parametrize("ranges", [False, True])
+def test_tile_keys_many_queries(bbc, ranges):
+    """Tile-major exact keys with more queries per list than one group of
+    pairs holds (several groups per list), one wave per candidate row; with
+    the bin counters cut to one list's tiles, each query's ranks are sorted
+    in ranges."""
+    import os
+    x, q, tr, ip, P, ix = _data(256, 5000, 200, 10, 1, True)
+    if ranges:
+        os.environ["BBC_RERANK_SORT_BINS"] = "1"
+    try:
+        g = _gpu_index(bbc, x, ix, form="tiles")
+    finally:
+        os.environ.pop("BBC_RERANK_SORT_BINS", None)
+    print(f"[case] rabitq tile keys, 200 queries, ranges={ranges}", flush=True)
+    _check_search(g, ix, q, 120, 8)
