@@ -233,11 +233,11 @@ int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out);
  * 6 the collector codebook, 4 re-rank
  * (RaBitQ: the bounded walk, after the exact keys of all candidates in the
  * wide form), 5 final top-k).  A RaBitQ batch of at most as many queries as
- * the device has compute units takes the wide form; a larger batch of rows
- * of at most 128 elements takes the wide form with the exact keys computed
- * tile-major (each tile of a list's rows staged once per group of queries),
- * other batches one block per query.  A PQ batch re-ranks tile-major where
- * the rows have at most 128 elements. */
+ * the device has compute units takes the wide form with the exact keys
+ * from a device-wide grid; a larger batch takes the wide form with the
+ * exact keys computed tile-major (each tile of a list's rows staged once per
+ * group of queries).  A PQ batch re-ranks tile-major where the rows have at
+ * most 128 elements. */
 int32_t bbc_stage_timing(int32_t enable);
 int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t reset);
 

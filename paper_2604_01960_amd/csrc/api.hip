@@ -813,10 +813,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   std::vector<int64_t> bin_off;
   int rt_shift = 0, rt_bins = 0;
   size_t rt_lds = 0;
-  // (by default only for rows of at most 32 chunks: with longer rows a tile
-  // holds few rows, and each query's short run per tile does not repay
-  // loading its query again)
-  const bool want_tiles = ix->walk_form == 3 || (ix->walk_form == 0 && nq > ix->num_cu && d / 4 <= 32);
+  const bool want_tiles = ix->walk_form == 3 || (ix->walk_form == 0 && nq > ix->num_cu);
   const bool tile_keys = want_tiles && tile_plan(ix, nq, nprobe, max_np, 256, bin_off, &rt_shift, &rt_bins, &rt_lds);
   if (!tile_keys) bin_off.assign(nq + 1, 0);
   Plan mp;
@@ -838,7 +835,8 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const bool wide = ix->walk_form == 2 || tile_keys || (ix->walk_form == 0 && nq <= ix->num_cu);
   size_t L_cpos = 0, L_wbins = 0, L_wst = 0;
   if (wide) { L_cpos = pl.add(4 * nkeys); L_wbins = pl.add(4 * 2048 * nq); L_wst = pl.add(16 * nq); }
-  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
+  const int rt_group = bbc::tile_rerank_group(d);
+  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (rt_group - 1);
   size_t L_rts = 0, L_rti = 0, L_rtb = 0, L_rtp = 0, L_rtc = 0, L_rtl = 0;
   if (tile_keys) {
     L_rts = pl.add(4 * nkeys); L_rti = pl.add(4 * nkeys); L_rtb = pl.add(4 * bin_off[nq]);
@@ -973,6 +971,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
       ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
       ta.lpairs_cap = rt_lpairs_cap;
+      ta.group = rt_group;
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
       wa.keys_ready = 1;
     }
@@ -1132,7 +1131,8 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.n_cand = pl.add(8 * nq);
   L.qorder = pl.add(4 * nq);
   // tile-major re-rank: its sort buffers
-  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (bbc::RT_G - 1);
+  const int rt_group = bbc::tile_rerank_group(d);
+  const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (rt_group - 1);
   if (tile_rr) {
     L.rt_sorted = pl.add(4 * ncand);
     L.rt_bins = pl.add(4 * bin_off[nq]);
@@ -1327,6 +1327,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.lcnt = reinterpret_cast<uint32_t*>(A + L.rt_lcnt);
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);
       ta.lpairs_cap = rt_lpairs_cap;
+      ta.group = rt_group;
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
     } else {
       if (ix->nlist <= bbc::QUERY_ORDER_MAX_LISTS && nq > 1) {

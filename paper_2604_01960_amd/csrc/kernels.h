@@ -113,7 +113,8 @@ hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 constexpr int QUERY_ORDER_MAX_LISTS = 32768;
 
 // Tile-major re-rank (rows of at most 256 four-element chunks).
-constexpr int RT_G = 128;              // (query, list) pairs per block
+constexpr int RT_G = 128;              // (query, list) pairs per block, rows of at most 32 chunks
+constexpr int RT_GW = 16;              // the same for longer rows (one pair per wave)
 constexpr int RT_TILE_BYTES = 65536;   // LDS rows per tile
 struct TileRerankArgs {
   const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;
@@ -135,9 +136,11 @@ struct TileRerankArgs {
   const int64_t* bin_off;   // [nq + 1] each query's bins in bin_beg
   uint32_t* bin_beg;        // [bin_off[nq]] bin starts within the query's candidates, then the count
   uint32_t* lcnt;           // [nlist + 1] pair counts, then cursors; [nlist] = number of groups
-  uint64_t* lpairs;         // [lpairs_cap] (query << 32 | rank) grouped by list, whole groups of RT_G
-  int64_t lpairs_cap;       // npairs + nlist * (RT_G - 1)
+  uint64_t* lpairs;         // [lpairs_cap] (query << 32 | rank) grouped by list, whole groups
+  int64_t lpairs_cap;       // npairs + nlist * (group - 1)
+  int group;                // pairs per block: tile_rerank_group(d)
 };
+int tile_rerank_group(int d);
 // log2 of the rows per tile for the row shape, or -1 where the form does not apply
 int tile_rerank_shift(int d, int fp16);
 // dynamic LDS of the candidate sort

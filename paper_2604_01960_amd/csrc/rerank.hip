@@ -243,10 +243,11 @@ __device__ void block_excl_scan(uint32_t* v, int n, uint32_t* s_w, uint32_t* tot
 __global__ __launch_bounds__(1024) void rt_pair_offsets(TileRerankArgs a) {
   __shared__ uint32_t s_w[16];
   __shared__ uint32_t s_tot;
-  for (int L = threadIdx.x; L < a.nlist; L += 1024) a.lcnt[L] = (a.lcnt[L] + RT_G - 1) / RT_G * RT_G;
+  const uint32_t G = (uint32_t)a.group;
+  for (int L = threadIdx.x; L < a.nlist; L += 1024) a.lcnt[L] = (a.lcnt[L] + G - 1) / G * G;
   __syncthreads();
   block_excl_scan<1024>(a.lcnt, a.nlist, s_w, &s_tot);
-  if (threadIdx.x == 0) a.lcnt[a.nlist] = s_tot / RT_G;
+  if (threadIdx.x == 0) a.lcnt[a.nlist] = s_tot / G;
 }
 
 __global__ __launch_bounds__(256) void rt_pair_scatter(TileRerankArgs a) {
@@ -347,8 +348,8 @@ struct RtGroup {
 
 template <int NT>
 __device__ __forceinline__ void rt_load_group(const TileRerankArgs& a, int64_t blk, RtGroup& g) {
-  if (threadIdx.x < RT_G) {
-    const uint64_t e = a.lpairs[blk * RT_G + threadIdx.x];
+  if (threadIdx.x < a.group) {
+    const uint64_t e = a.lpairs[blk * a.group + threadIdx.x];
     const int q = e == RT_NO_PAIR ? -1 : (int32_t)(e >> 32);
     g.q[threadIdx.x] = q;
     g.r[threadIdx.x] = (int32_t)(e & 0xffffffffu);
@@ -482,11 +483,14 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   }
 }
 
-// Rows of 33 to 256 chunks: one wave per candidate, lane l holding chunks
-// l, l + 64, l + 128 and l + 192 (the canonical steps of virtual lane l).
+// Rows of 33 to 256 chunks (groups of RT_GW pairs): wave w takes pair w of
+// the group and keeps its query chunks in registers over all the list's
+// tiles (lane l holds chunks l, l + 64, l + 128 and l + 192, the canonical
+// steps of virtual lane l); one candidate row at a time, from LDS.
 template <typename T>
 __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a) {
-  constexpr int NT = 1024, NW = NT / 64;
+  constexpr int NT = 1024;
+  static_assert(RT_GW == NT / 64, "one pair per wave");
   __shared__ uint4 tile[RT_TILE_BYTES / 16];
   __shared__ RtGroup g;
   const int64_t blk = blockIdx.x;
@@ -503,32 +507,32 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
   const int row_words = a.d * (int)sizeof(T) / 16;
   const T* trow = reinterpret_cast<const T*>(tile);
   const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
+  const int q = g.q[wv];
+  const int64_t co = g.co[wv], pof = g.pof[wv];
+  const uint32_t* bins = a.bin_beg + g.bbase[wv];
+  float4 qv[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int c4 = lane + 64 * st;
+    qv[st] = q >= 0 && c4 < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * a.d)[c4]
+                                   : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
   for (int t = 0; t < ntile; ++t) {
     const int64_t r0 = (int64_t)t * TR;
     const int nr = (int)min((int64_t)TR, le - lb - r0);
+    // this pair's candidates in tile t (loaded before the tile's rows)
+    const uint32_t b0 = q >= 0 ? bins[t] : 0u, b1 = q >= 0 ? bins[t + 1] : 0u;
     __syncthreads();
     rt_stage_rows<NT>(tile, src + r0 * row_words, nr * row_words);
-    if (threadIdx.x < 64) rt_runs(a, t, g);
     __syncthreads();
-    const uint32_t nrun = g.cpre[RT_G];
-    for (uint32_t c = wv; c < nrun; c += NW) {
-      const int e = rt_run_pair(g, c);
-      const uint32_t j0 = g.beg[e] + (c - g.cpre[e]) * 64;
-      const int cnt = (int)min(64u, g.end[e] - j0);
-      const int q = g.q[e];
-      const int64_t co = g.co[e], pof = g.pof[e];
+    for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
+      const int cnt = (int)min(64u, b1 - j0);
       const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
       const int64_t rl = (int64_t)pl - lb - r0;
       const bool okl = lane < cnt && rl >= 0 && rl < nr;
       const int32_t idl = okl ? a.list_ids[pl] : 0;
       const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
       const int rowl = okl ? (int)rl : -1;
-      float4 qv[4];
-#pragma unroll
-      for (int st = 0; st < 4; ++st) {
-        const int c4 = lane + 64 * st;
-        qv[st] = c4 < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * a.d)[c4] : make_float4(0.f, 0.f, 0.f, 0.f);
-      }
       float mykey = 0.0f;
       for (int jj = 0; jj < cnt; ++jj) {
         const int rr = __builtin_amdgcn_readlane(rowl, jj);
@@ -547,6 +551,8 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
     }
   }
 }
+
+int tile_rerank_group(int d) { return d / 4 > 32 ? RT_GW : RT_G; }
 
 int tile_rerank_shift(int d, int fp16) {
   if (d <= 0 || d % 4 || d / 4 > 256) return -1;
@@ -572,7 +578,7 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
   hipLaunchKernelGGL(rt_pair_offsets, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(rt_pair_scatter, pg, dim3(256), 0, s, a);
   hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
-  const int64_t groups = (a.npairs + RT_G - 1) / RT_G + a.nlist;  // bound on the padded group count
+  const int64_t groups = (a.npairs + a.group - 1) / a.group + a.nlist;  // bound on the padded group count
   const bool wide = a.d / 4 > 32;
   if (a.fp16) {
     if (wide) hipLaunchKernelGGL(rt_rerank_tile_wide<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
