@@ -627,12 +627,21 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
     algo = {"scan": S * (w.d // 8 + 16), "rerank": nv * (row_bytes + 4)}
     names = {"scan": "rabitq_scan_kernel (bounds of every scanned object)",
              "rerank": "rabitq_walk_kernel (bounded re-rank)"}
+    # batches larger than the compute-unit count take the wide form with
+    # tile-major exact keys (rows from LDS): priced by arithmetic instead
+    tile_keys = nq > 256 and os.environ.get("BBC_WALK_FORM", "0") in ("0", "3")
     entries = {}
     for name in algo:
         st = stages[name]
         if st["launches"] == 0:
             continue
         avg_ms = st["ms"] / st["launches"]
+        if name == "rerank" and tile_keys:
+            e = rerank_entry(avg_ms, nv * args.steps / st["launches"], w.d)
+            e["kernel"] = ("rt_rerank_tile_wide + rabitq_walk_kernel (exact keys of the candidate set C, "
+                           "tile-major, then the walk over them)")
+            entries[name] = e
+            continue
         bpl = algo[name] * args.steps / st["launches"]
         gbs = bpl / (avg_ms * 1e-3) / 1e9
         entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,

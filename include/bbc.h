@@ -175,7 +175,8 @@ typedef struct {
   int64_t* n_survivors;                      /* [nq] keys kept by the relaxed-threshold filter */
   int64_t* n_sample_keys;                    /* [nq] keys in the codebook sample lists */
   float* est_lb; float* est_ub;              /* RaBitQ: [sum S] bounds in the est_keys order */
-  int64_t* n_visited;                        /* RaBitQ: [nq] objects re-ranked */
+  int64_t* n_visited;                        /* RaBitQ: [nq] exact distances computed (the objects the
+                                                bounded walk visited; all of C in the wide form) */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and
@@ -294,7 +295,8 @@ typedef struct {
   int32_t status;      /* BBC_OK or the batch's error */
   int64_t latency_ns;  /* submission to completion, as seen by the worker */
   int64_t n_scanned;   /* codes scanned (S) */
-  int64_t n_reranked;  /* exact distances computed: K_c (PQ), objects the bounded walk visited (RaBitQ) */
+  int64_t n_reranked;  /* exact distances computed: K_c (PQ); RaBitQ: the objects the bounded walk
+                          visited, or all of the candidate set C in the wide form */
   int64_t batch_size;  /* requests in the batch that answered this one */
 } bbc_request_info;
 int32_t bbc_server_create(bbc_index* ix, const bbc_search_params* params, int64_t mem_budget_bytes,

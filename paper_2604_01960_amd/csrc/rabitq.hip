@@ -825,7 +825,8 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
     }
   }
   if (ok) {
-    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = nvis; }
+    // exact distances computed: the visited objects, or all of C in the wide form
+    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = a.wide ? nC : nvis; }
     return;
   }
 
@@ -906,7 +907,8 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
     have_last = true;
     __syncthreads();
   }
-  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = visited; }
+  // the item walk visits a prefix of the (lb, id) order, of which C is a prefix too
+  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = a.wide ? max(nC, visited) : visited; }
 }
 
 hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s) {
