@@ -483,6 +483,21 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   }
 }
 
+// canon_reduce64 with the last four levels as DPP: after the xor levels 32
+// and 16 every lane's value repeats with period 16, after the rotation by 8
+// with period 8, so each rotation pairs lane l with the lane the canonical
+// tree pairs it with whichever way it turns, and every lane ends with the
+// canonical sum.
+__device__ __forceinline__ float canon_reduce64_dpp(float acc) {
+  acc = acc + __shfl_xor(acc, 32);
+  acc = acc + __shfl_xor(acc, 16);
+  acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x128, 0xf, 0xf, false));  // row_ror:8
+  acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x124, 0xf, 0xf, false));  // row_ror:4
+  acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x4e, 0xf, 0xf, false));   // quad [2,3,0,1]
+  acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0xb1, 0xf, 0xf, false));   // quad [1,0,3,2]
+  return acc;
+}
+
 // Rows of 33 to 256 chunks (groups of RT_GW pairs): wave w takes pair w of
 // the group and keeps its query chunks in registers over all the list's
 // tiles (lane l holds chunks l, l + 64, l + 128 and l + 192, the canonical
@@ -544,7 +559,7 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
           const int c4 = lane + 64 * st;
           if (c4 < nchunk) acc = ip ? chunk_ip(qv[st], load4<T>(row, c4), acc) : chunk_l2(qv[st], load4<T>(row, c4), acc);
         }
-        acc = canon_reduce64(acc);  // every lane ends with the sum
+        acc = canon_reduce64_dpp(acc);  // every lane ends with the sum
         if (lane == jj) mykey = ip ? -acc : acc;
       }
       if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
