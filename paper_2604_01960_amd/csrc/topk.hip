@@ -307,7 +307,7 @@ __device__ void sort_global_unpack(const int metric, const int run, uint64_t* ou
 // IPT > 0: the candidates are loaded once into registers (IPT per thread,
 // K_c <= IPT * 1024) and every pass of the binned path runs from there.
 template <int IPT>
-__global__ __launch_bounds__(1024) void final_topk_kernel(FinalArgs a) {
+__global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_topk_kernel(FinalArgs a) {
   constexpr int NT = 1024;
   extern __shared__ __align__(16) unsigned char smem[];
   uint64_t* run_buf = reinterpret_cast<uint64_t*>(smem);  // [a.cap]
