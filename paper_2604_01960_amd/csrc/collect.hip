@@ -446,7 +446,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     for (int r = threadIdx.x; r < np; r += NT)
       for (uint32_t ch = s_pref[r]; ch < s_pref[r + 1]; ++ch) s_crank[ch] = (uint16_t)r;
   __syncthreads();
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;  // wv: wave-uniform
   constexpr int U = COLLECT_UNROLL;
   constexpr int NW = NT / 64;
   // Batches of UB chunks per wave (UB = the Unroll argument): batch(act,
