@@ -367,7 +367,7 @@ hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
 constexpr int WK_NB = 2048;       // lb bins
 constexpr int WK_RANKCAP = 2048;  // probe ranks in LDS
 constexpr int WK_CHUNK = 1024;    // items per step of the exact walk (and per bin-walk round)
-constexpr int WK_QCAP = 2048;     // objects above the k-th exact key resolved in LDS
+constexpr int WK_QCAP = 4096;     // objects above the k-th exact key resolved in LDS
 constexpr int WK_U = 2;           // loads in flight per thread in the block-wide passes
 
 template <typename T> __device__ __forceinline__ float4 ld4(const T* p, int64_t chunk);
@@ -410,9 +410,30 @@ __device__ void exact_keys4(const RabitqWalkArgs& a, const float4* qc, const int
   }
 }
 
+// The exact key of one list position, one wave, in the order of exact_keys4.
+template <typename T>
+__device__ float exact_key1(const RabitqWalkArgs& a, const float4* qc, int64_t pos) {
+  const int lane = threadIdx.x & 63;
+  const int nchunk = a.D >> 2;
+  const T* row = reinterpret_cast<const T*>(a.vectors) + pos * a.D;
+  float4 x[4];
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    const int c = lane + 64 * st;
+    x[st] = c < nchunk ? ld4<T>(row, c) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+  float acc = 0.0f;
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+    if (lane + 64 * st < nchunk)
+      acc = a.metric == 0 ? chunk_l2(qc[64 * st], x[st], acc) : chunk_ip(qc[64 * st], x[st], acc);
+  acc = canon_reduce64(acc);
+  return a.metric == 0 ? acc : -acc;
+}
+
 // Block-wide bitonic sort of keys with a payload (n a power of two).
-template <int NT>
-__device__ void lds_bitonic_sort_kv(uint64_t* key, uint64_t* val, int n) {
+template <int NT, typename V>
+__device__ void lds_bitonic_sort_kv(uint64_t* key, V* val, int n) {
   for (int size = 2; size <= n; size <<= 1) {
     for (int stride = size >> 1; stride > 0; stride >>= 1) {
       __syncthreads();
@@ -423,7 +444,7 @@ __device__ void lds_bitonic_sort_kv(uint64_t* key, uint64_t* val, int n) {
         const uint64_t ka = key[lo], kb = key[hi];
         if ((ka > kb) == up) {
           key[lo] = kb; key[hi] = ka;
-          const uint64_t v = val[lo]; val[lo] = val[hi]; val[hi] = v;
+          const V v = val[lo]; val[lo] = val[hi]; val[hi] = v;
         }
       }
     }
@@ -432,8 +453,9 @@ __device__ void lds_bitonic_sort_kv(uint64_t* key, uint64_t* val, int n) {
 }
 
 // The lb bins of a query's candidate set C = {lb <= U}, U = the k-th smallest
-// ub (every object when S <= k): C's slots grouped by bin in cbuf (and their
-// list positions in cpos when it is not NULL), hist[b] = the end of bin b.
+// ub (every object when S <= k), grouped by bin: hist[b] = the end of bin b.
+// Without cpos, cbuf holds C's slots; with it (wide form), cpos holds their
+// list positions and cbuf their lb images.
 struct WalkBins {
   uint32_t U, lmin;
   int shift;
@@ -491,8 +513,12 @@ __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float
   block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
     if (valid && b <= U) {
       const uint32_t j = atomicAdd(&hist[(b - lmin) >> shift], 1u);
-      cbuf[j] = (uint32_t)i;
-      if (cpos) cpos[j] = (int32_t)sm.pos(i);
+      if (cpos) {
+        cbuf[j] = b;
+        cpos[j] = (int32_t)sm.pos(i);
+      } else {
+        cbuf[j] = (uint32_t)i;
+      }
     }
   });
   __syncthreads();
@@ -562,9 +588,12 @@ __global__ __launch_bounds__(256) void rabitq_exact_kernel(RabitqWalkArgs a) {
   }
 }
 
+// WIDE: the exact keys of all of C are in cand_packed before the walk (the
+// wide form); then the kernel computes no exact key except in the item walk,
+// and fits two blocks per compute unit.
 constexpr int WK_NT = 1024;
-template <typename T>
-__global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
+template <typename T, bool WIDE>
+__global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(RabitqWalkArgs a) {
   constexpr int NT = WK_NT;
   constexpr int NW = NT / 64;
   __shared__ int32_t s_rbeg[WK_RANKCAP];
@@ -573,7 +602,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
   __shared__ uint32_t rhist[256];
   __shared__ __align__(8) uint32_t bc[16];
   __shared__ uint64_t chunk_v[WK_QCAP];    // (lb image, id) keys, sorted
-  __shared__ uint64_t chunk_x[WK_QCAP];    // their (exact image, id)
+  __shared__ uint32_t chunk_x[WK_QCAP];    // their exact images
 
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
@@ -616,7 +645,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
   // the bins of C: computed here, or (wide form) read back with the exact
   // keys of all of C already in pbuf
   WalkBins w;
-  if (a.wide) {
+  if constexpr (WIDE) {
     const uint32_t* st = a.wstate + 4 * qi;
     w.U = st[0]; w.lmin = st[1]; w.shift = (int)st[2]; w.nC = st[3];
     for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = a.wbins[qi * WK_NB + i];
@@ -627,6 +656,11 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
   const uint32_t U = w.U, lmin = w.lmin;
   const int shift = w.shift;
   const int64_t nC = w.nC;
+  // lb image of the object at place i of C's bin order
+  auto lb_img = [&](int64_t i) -> uint32_t {
+    if constexpr (WIDE) return cbuf[i];
+    else return key_bits(lb[cbuf[i]]);
+  };
   // hist[b] is now the end of bin b in cbuf.  Walk whole bins in order.
   auto lower_edge = [&](int b) -> uint64_t { return (uint64_t)lmin + ((uint64_t)b << shift); };
   // exact keys of cbuf[i0, i1) into pbuf, four rows per wave
@@ -648,60 +682,118 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
       }
     }
   };
-  // Z = the processed (exact, id) that can still be among the k best: all of
-  // them until k are processed, then those whose key image is at most E, the
-  // k-th smallest key image (ties at E included).
-  int64_t p = 0, nz = 0;
-  int b_end = 0;
+  int64_t p = 0;
   uint32_t Eimg = 0xffffffffu;
   bool exhausted = false;
-  // Wide form: the running k-th exact key never drops below E_C, the k-th
-  // smallest exact key image over all of C, so no stop can come before the
-  // first bin whose lower edge exceeds E_C: the first round takes every bin
-  // before it.
-  int64_t first_end = 0;
-  if (a.wide && nC > k) {
-    const uint32_t EC =
-        block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(pbuf[i] >> 32); }, nC, k - 1, rhist, bc);
-    if (EC >= lmin) {
-      const uint64_t bC = ((uint64_t)(EC - lmin) >> shift) + 1;
-      first_end = bC >= (uint64_t)WK_NB ? nC : (int64_t)hist[bC - 1];
+  if constexpr (WIDE) {
+    // The exact keys of all of C are known, so the processed set P is the
+    // shortest prefix of whole bins [0, b) after which the walk stops for
+    // certain: P holds at least k objects whose exact image lies below the
+    // lower edge of bin b, i.e. whose lb bin and exact-image bin (images
+    // below lmin in bin 0) are both below b.  A histogram of the larger of
+    // the two bins gives that count for every b in one pass over C.
+    if (S <= k) {
+      p = nC;
+      exhausted = true;
+    } else {
+      uint32_t* H = reinterpret_cast<uint32_t*>(chunk_v);  // WK_NB counters
+      for (int i = threadIdx.x; i < WK_NB; i += NT) H[i] = 0;
+      __syncthreads();
+      // each wave takes a contiguous range of C and follows the bin ends
+      const int64_t per = ((nC + NW - 1) / NW + 63) & ~(int64_t)63;
+      const int64_t w0 = (int64_t)wv * per, w1 = min(nC, w0 + per);
+      const uint32_t* ximg = reinterpret_cast<const uint32_t*>(pbuf) + 1;  // exact image of place i at 2 i
+      int bn = 0;  // the first bin whose end exceeds the lane's place
+      {
+        const int64_t i0 = w0 + lane;
+        int lo = 0, hi = WK_NB - 1;  // hist[WK_NB - 1] = nC
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if ((int64_t)hist[mid] > i0) hi = mid; else lo = mid + 1;
+        }
+        bn = lo;
+      }
+      constexpr int HU = 8;
+      for (int64_t base = w0; base < w1; base += 64 * HU) {
+        uint32_t img[HU];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) img[u] = ximg[2 * min(base + 64 * u + lane, w1 - 1)];
+#pragma unroll
+        for (int u = 0; u < HU; ++u) {
+          const int64_t i = base + 64 * u + lane;
+          const bool valid = i < w1;
+          uint32_t m = WK_NB;
+          if (valid) {
+            while ((int64_t)hist[bn] <= i) ++bn;
+            const uint32_t eb = img[u] < lmin ? 0u : (img[u] - lmin) >> shift;
+            m = max((uint32_t)bn, eb);
+          }
+          wave_hist_add(H, m, valid && m < (uint32_t)WK_NB);
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < 64) {  // the first m whose inclusive count reaches k
+        uint32_t carry = 0;
+        int found = WK_NB;
+        for (int base = 0; base < WK_NB; base += 64) {
+          const uint32_t incl = carry + wave_incl_scan(H[base + lane]);
+          const uint64_t hit = __ballot((int64_t)incl >= k);
+          if (hit) {
+            found = base + __ffsll((unsigned long long)hit) - 1;
+            break;
+          }
+          carry = __shfl(incl, 63);
+        }
+        if (lane == 0) bc[13] = (uint32_t)found;
+      }
+      __syncthreads();
+      const int found = (int)bc[13];
+      const int b = found < WK_NB ? found + 1 : WK_NB;
+      p = hist[b - 1];
+      exhausted = p >= nC;
+      Eimg = block_radix_select32<NT>([&](int64_t i) { return ximg[2 * i]; }, p, k - 1, rhist, bc);
     }
-  }
-  while (true) {
-    const int64_t target = max(p < k ? max(k, (int64_t)WK_CHUNK) : p + WK_CHUNK, first_end);
-    int b = b_end;
-    while (b < WK_NB && (int64_t)hist[b] < target) ++b;
-    if (b < WK_NB) ++b;  // the bin that reaches the target
-    const int64_t np_ = b > 0 ? (int64_t)hist[b - 1] : 0;
-    b_end = b;
-    if (!a.wide) rerank_range(p, np_);
-    if (threadIdx.x == 0) bc[13] = 0;
-    __syncthreads();
-    block_for_batched<NT, WK_U>(np_ - p, [&](int64_t j) { return pbuf[p + j]; },
-                             [&](int64_t, bool valid, uint64_t v) {
-                               const bool take = valid && (p < k || (uint32_t)(v >> 32) <= Eimg);
-                               const uint32_t slot = wave_slot(take, &bc[13]);
-                               if (take) zA[nz + slot] = v;
-                             });
-    __syncthreads();
-    nz += bc[13];
-    p = np_;
-    if (p >= k) {
-      Eimg = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
+  } else {
+    // Z = the processed (exact, id) that can still be among the k best: all
+    // of them until k are processed, then those whose key image is at most
+    // E, the k-th smallest key image (ties at E included).
+    int64_t nz = 0;
+    int b_end = 0;
+    while (true) {
+      const int64_t target = p < k ? max(k, (int64_t)WK_CHUNK) : p + WK_CHUNK;
+      int b = b_end;
+      while (b < WK_NB && (int64_t)hist[b] < target) ++b;
+      if (b < WK_NB) ++b;  // the bin that reaches the target
+      const int64_t np_ = b > 0 ? (int64_t)hist[b - 1] : 0;
+      b_end = b;
+      rerank_range(p, np_);
       if (threadIdx.x == 0) bc[13] = 0;
       __syncthreads();
-      block_for_batched<NT, WK_U>(nz, [&](int64_t i) { return zA[i]; }, [&](int64_t, bool valid, uint64_t v) {
-        const bool take = valid && (uint32_t)(v >> 32) <= Eimg;
-        const uint32_t slot = wave_slot(take, &bc[13]);
-        if (take) zB[slot] = v;
-      });
+      block_for_batched<NT, WK_U>(np_ - p, [&](int64_t j) { return pbuf[p + j]; },
+                               [&](int64_t, bool valid, uint64_t v) {
+                                 const bool take = valid && (p < k || (uint32_t)(v >> 32) <= Eimg);
+                                 const uint32_t slot = wave_slot(take, &bc[13]);
+                                 if (take) zA[nz + slot] = v;
+                               });
       __syncthreads();
-      nz = bc[13];
-      uint64_t* t = zA; zA = zB; zB = t;
+      nz += bc[13];
+      p = np_;
+      if (p >= k) {
+        Eimg = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
+        if (threadIdx.x == 0) bc[13] = 0;
+        __syncthreads();
+        block_for_batched<NT, WK_U>(nz, [&](int64_t i) { return zA[i]; }, [&](int64_t, bool valid, uint64_t v) {
+          const bool take = valid && (uint32_t)(v >> 32) <= Eimg;
+          const uint32_t slot = wave_slot(take, &bc[13]);
+          if (take) zB[slot] = v;
+        });
+        __syncthreads();
+        nz = bc[13];
+        uint64_t* t = zA; zA = zB; zB = t;
+      }
+      if (b_end >= WK_NB || p >= nC) { exhausted = true; break; }
+      if (p >= k && lower_edge(b_end) > (uint64_t)Eimg) break;
     }
-    if (b_end >= WK_NB || p >= nC) { exhausted = true; break; }
-    if (p >= k && lower_edge(b_end) > (uint64_t)Eimg) break;
   }
   const uint32_t E = Eimg;  // k-th smallest exact key image among the processed
   // The processed set P is a prefix of the (lb, id) order.  The oracle's walk
@@ -718,7 +810,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
     if (threadIdx.x == 0) { bc[7] = 0; bc[14] = 0; }
     __syncthreads();
     // (lb image, exact image) of processed object i
-    auto lb_ex = [&](int64_t i) { return make_uint2(key_bits(lb[cbuf[i]]), (uint32_t)(pbuf[i] >> 32)); };
+    auto lb_ex = [&](int64_t i) { return make_uint2(lb_img(i), (uint32_t)(pbuf[i] >> 32)); };
     {
       uint32_t nab = 0;
       bool member = false;
@@ -742,11 +834,11 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
       uint32_t thr0 = 0xffffffffu;
       if (n0 > k)
         thr0 = block_radix_select32<NT>(
-            [&](int64_t i) { return key_bits(lb[cbuf[i]]) <= E ? (uint32_t)(pbuf[i] >> 32) : 0xffffffffu; }, p,
+            [&](int64_t i) { return lb_img(i) <= E ? (uint32_t)(pbuf[i] >> 32) : 0xffffffffu; }, p,
             k - 1, rhist, bc);
       if (threadIdx.x == 0) bc[13] = 0;
       __syncthreads();
-      block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+      block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(lb_img(i), pbuf[i]); },
                                [&](int64_t, bool valid, ulonglong2 e) {
                                  const bool take = valid && e.x <= E && (uint32_t)(e.y >> 32) <= thr0;
                                  const uint32_t slot = wave_slot(take, &bc[13]);
@@ -761,16 +853,16 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
         // Q sorted in LDS by (lb image, id), with its exact (key, id)
         if (threadIdx.x == 0) bc[9] = 0;
         __syncthreads();
-        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(lb_img(i), pbuf[i]); },
                                  [&](int64_t, bool valid, ulonglong2 e) {
                                    if (valid && e.x > E) {
                                      const uint32_t j = atomicAdd(&bc[9], 1u);
                                      chunk_v[j] = (e.x << 32) | (uint64_t)(uint32_t)e.y;
-                                     chunk_x[j] = e.y;
+                                     chunk_x[j] = (uint32_t)(e.y >> 32);
                                    }
                                  });
         const int P2 = next_pow2((int)nQ);
-        for (int i = (int)nQ + threadIdx.x; i < P2; i += NT) { chunk_v[i] = ~0ull; chunk_x[i] = ~0ull; }
+        for (int i = (int)nQ + threadIdx.x; i < P2; i += NT) { chunk_v[i] = ~0ull; chunk_x[i] = ~0u; }
         lds_bitonic_sort_kv<NT>(chunk_v, chunk_x, P2);
         // first t in [lo, nQ) with lb(Q[t]) > the k-th key of Z0 and Q[0, t),
         // i.e. with at least k of those keys below lb(Q[t])
@@ -778,7 +870,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
           const int64_t t = (lo + hi) >> 1;
           const uint32_t L = (uint32_t)(chunk_v[t] >> 32);
           const int64_t below = count_below(
-              nz0 + t, [&](int64_t i) { return (uint32_t)((i < nz0 ? zB[i] : chunk_x[i - nz0]) >> 32); }, L);
+              nz0 + t, [&](int64_t i) { return i < nz0 ? (uint32_t)(zB[i] >> 32) : chunk_x[i - nz0]; }, L);
           if (below >= k) hi = t; else lo = t + 1;
         }
         if (lo < nQ) cut = chunk_v[lo];
@@ -786,7 +878,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
         // the same search with Q left in place: Q[t] by a radix select over
         // the (lb image, id) keys of Q, Q[0, t) as the keys below it
         auto qkey = [&](int64_t i, uint64_t& v) -> bool {
-          const uint32_t lbi = key_bits(lb[cbuf[i]]);
+          const uint32_t lbi = lb_img(i);
           v = ((uint64_t)lbi << 32) | (uint64_t)(uint32_t)pbuf[i];
           return lbi > E;
         };
@@ -811,7 +903,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
       if (lo < nQ) {
         if (threadIdx.x == 0) bc[13] = 0;
         __syncthreads();
-        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(key_bits(lb[cbuf[i]]), pbuf[i]); },
+        block_for_batched<NT, WK_U>(p, [&](int64_t i) { return make_ulonglong2(lb_img(i), pbuf[i]); },
                                  [&](int64_t, bool valid, ulonglong2 e) {
                                    const bool take = valid && ((e.x << 32) | (uint64_t)(uint32_t)e.y) < cut;
                                    const uint32_t slot = wave_slot(take, &bc[13]);
@@ -826,7 +918,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
   }
   if (ok) {
     // exact distances computed: the visited objects, or all of C in the wide form
-    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = a.wide ? nC : nvis; }
+    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = WIDE ? nC : nvis; }
     return;
   }
 
@@ -872,17 +964,15 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
     lds_bitonic_sort<NT>(chunk_v, P2);
     for (int i = wv; i < (int)nb; i += NW) {
       const uint32_t id = (uint32_t)chunk_v[i];
-      int64_t pos[4] = {(int64_t)a.pos_of_id[id], 0, 0, 0};
-      float ex[4];
-      exact_keys4<T>(a, qc, pos, 1, ex);
-      if (lane == 0) chunk_x[i] = pack_key_id(ex[0], id);
+      const float ex = exact_key1<T>(a, qc, (int64_t)a.pos_of_id[id]);
+      if (lane == 0) chunk_x[i] = key_bits(ex);
     }
     __syncthreads();
     if (wv == 0) {
       for (int i = 0; i < (int)nb; ++i) {
         const uint32_t lbi = (uint32_t)(chunk_v[i] >> 32);
         if (nr == k && lbi > (uint32_t)(top >> 32)) { stop = true; break; }
-        const uint64_t e = chunk_x[i];
+        const uint64_t e = ((uint64_t)chunk_x[i] << 32) | (uint32_t)chunk_v[i];
         ++visited;
         if (nr < k) {
           if (lane == 0) hstore(pbuf + nr, e);
@@ -908,7 +998,7 @@ __global__ __launch_bounds__(WK_NT) void rabitq_walk_kernel(RabitqWalkArgs a) {
     __syncthreads();
   }
   // the item walk visits a prefix of the (lb, id) order, of which C is a prefix too
-  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = a.wide ? max(nC, visited) : visited; }
+  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = WIDE ? max(nC, visited) : visited; }
 }
 
 hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s) {
@@ -925,8 +1015,14 @@ hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s) {
     if (a.fp16) hipLaunchKernelGGL(rabitq_exact_kernel<__half>, g, dim3(256), 0, s, a);
     else hipLaunchKernelGGL(rabitq_exact_kernel<float>, g, dim3(256), 0, s, a);
   }
-  if (a.fp16) hipLaunchKernelGGL(rabitq_walk_kernel<__half>, dim3((unsigned)a.nq), dim3(WK_NT), 0, s, a);
-  else hipLaunchKernelGGL(rabitq_walk_kernel<float>, dim3((unsigned)a.nq), dim3(WK_NT), 0, s, a);
+  const dim3 g((unsigned)a.nq), b(WK_NT);
+  if (a.wide) {
+    if (a.fp16) hipLaunchKernelGGL((rabitq_walk_kernel<__half, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((rabitq_walk_kernel<float, true>), g, b, 0, s, a);
+  } else {
+    if (a.fp16) hipLaunchKernelGGL((rabitq_walk_kernel<__half, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((rabitq_walk_kernel<float, false>), g, b, 0, s, a);
+  }
   return hipGetLastError();
 }
 
