@@ -175,6 +175,9 @@ struct bbc_index {
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
   int64_t rt_sort_bins = (int64_t)1 << 30;  // tile-major sort: most bin counters (BBC_RERANK_SORT_BINS)
+  // RaBitQ tile-major keys: C put in tile order by the walk's bin pass (1) or
+  // by the candidate sort (0) (BBC_WALK_PRESORT)
+  int walk_presort = 1;
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -274,6 +277,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 3) ix->walk_form = x;
+  }
+  if (const char* sv = std::getenv("BBC_WALK_PRESORT")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 1) ix->walk_presort = x;
   }
   if (const char* sv = std::getenv("BBC_RERANK_SORT_BINS")) {
     const long long x = std::atoll(sv);
@@ -833,8 +840,15 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   // the wide re-rank form when the batch alone leaves compute units idle
   // with one block per query, or when its keys come tile-major
   const bool wide = ix->walk_form == 2 || tile_keys || (ix->walk_form == 0 && nq <= ix->num_cu);
+  // tile-major keys: the walk's bin pass also writes C in tile order (when
+  // each query's probe ranks fit its LDS tables), else the candidate sort does
+  const bool presort = tile_keys && ix->walk_presort && max_np <= bbc::WALK_RANKS_LDS;
   size_t L_cpos = 0, L_wbins = 0, L_wst = 0;
-  if (wide) { L_cpos = pl.add(4 * nkeys); L_wbins = pl.add(4 * 2048 * nq); L_wst = pl.add(16 * nq); }
+  if (wide) {
+    if (!presort) L_cpos = pl.add(4 * nkeys);
+    L_wbins = pl.add(4 * 2048 * nq);
+    L_wst = pl.add(16 * nq);
+  }
   const int rt_group = bbc::tile_rerank_group(d);
   const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (rt_group - 1);
   size_t L_rts = 0, L_rti = 0, L_rtb = 0, L_rtp = 0, L_rtc = 0, L_rtl = 0;
@@ -943,9 +957,17 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   wa.wide = wide ? 1 : 0;
   wa.max_c = max_cap;
   if (wide) {
-    wa.cpos = reinterpret_cast<int32_t*>(A + L_cpos);
+    wa.cpos = presort ? nullptr : reinterpret_cast<int32_t*>(A + L_cpos);
     wa.wbins = reinterpret_cast<uint32_t*>(A + L_wbins);
     wa.wstate = reinterpret_cast<uint32_t*>(A + L_wst);
+  }
+  if (presort) {
+    wa.t_pos = reinterpret_cast<uint32_t*>(A + L_rts);
+    wa.t_idx = reinterpret_cast<uint32_t*>(A + L_rti);
+    wa.t_bins = reinterpret_cast<uint32_t*>(A + L_rtb);
+    wa.t_rank_tb = reinterpret_cast<uint32_t*>(A + L_rtp);
+    wa.t_bin_off = d_bo;
+    wa.t_shift = rt_shift;
   }
   if (wide) {
     StageScope st(s, 3);
@@ -972,6 +994,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
       ta.lpairs_cap = rt_lpairs_cap;
       ta.group = rt_group;
+      ta.presorted = presort ? 1 : 0;
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
       wa.keys_ready = 1;
     }

@@ -309,20 +309,20 @@ struct SlotMap {
   const int32_t* s_rbeg;  // LDS copies (lds = true)
   const int32_t* s_lbeg;
   bool lds;
-  __device__ int64_t pos(int64_t slot) const {
+  __device__ int64_t rbeg(int r) const { return lds ? (int64_t)s_rbeg[r] : rank_off[r]; }
+  __device__ int64_t lbeg(int r) const { return lds ? (int64_t)s_lbeg[r] : list_off[lists[r]]; }
+  // the probe rank that holds a slot
+  __device__ int rank(int64_t slot) const {
     int lo = 0, hi = np - 1;
-    if (lds) {
-      while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_rbeg[mid] <= slot) lo = mid; else hi = mid - 1;
-      }
-      return (int64_t)s_lbeg[lo] + (slot - s_rbeg[lo]);
-    }
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
-      if (rank_off[mid] <= slot) lo = mid; else hi = mid - 1;
+      if (rbeg(mid) <= slot) lo = mid; else hi = mid - 1;
     }
-    return list_off[lists[lo]] + (slot - rank_off[lo]);
+    return lo;
+  }
+  __device__ int64_t pos(int64_t slot) const {
+    const int r = rank(slot);
+    return lbeg(r) + (slot - rbeg(r));
   }
 };
 

@@ -139,6 +139,7 @@ struct TileRerankArgs {
   uint64_t* lpairs;         // [lpairs_cap] (query << 32 | rank) grouped by list, whole groups
   int64_t lpairs_cap;       // npairs + nlist * (group - 1)
   int group;                // pairs per block: tile_rerank_group(d)
+  int presorted;            // sorted_pos, sorted_idx, pair_tb and bin_beg already filled
 };
 int tile_rerank_group(int d);
 // log2 of the rows per tile for the row shape, or -1 where the form does not apply
@@ -199,12 +200,13 @@ struct RabitqScanArgs {
 };
 hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s);
 
+constexpr int WALK_RANKS_LDS = 2048;  // probe ranks per query held in the walk kernels' LDS tables
 struct RabitqWalkArgs {
   int64_t nq; const int64_t* n_scanned; const int32_t* k; const int32_t* nprobe; const int64_t* probe_off;
   const int64_t* rank_off; const int32_t* probe_lists; const int64_t* list_off; const int32_t* list_ids;
   const int32_t* pos_of_id;
   const float* lb; const float* ub; const int64_t* key_off;
-  uint32_t* cbuf;            // [sum S] scratch (slots grouped by lb bin)
+  uint32_t* cbuf;            // [sum S] C grouped by lb bin: slots, or lb images in the wide form
   const int64_t* cand_off; uint64_t* cand_packed;  // [sum S] processed (exact key, id)
   int64_t* n_cand; int64_t* n_visited;
   uint64_t* zbuf;            // [2 * sum S] scratch (the k best so far, ping-pong)
@@ -217,6 +219,15 @@ struct RabitqWalkArgs {
   uint32_t* wbins;           // [nq][2048] bin ends
   uint32_t* wstate;          // [nq][4] U, lmin, shift, |C|
   int keys_ready;            // wide form: the exact keys of C are already in cand_packed
+  // wide form with tile-major keys: C also in slot order (by probe rank, then
+  // list position, hence by tile of 2^t_shift rows), as the tile re-rank reads
+  // it (t_pos NULL: not wanted; cpos is then not written either)
+  uint32_t* t_pos;           // [sum S] list positions of C in slot order
+  uint32_t* t_idx;           // [sum S] their places in cbuf order
+  uint32_t* t_bins;          // per query from t_bin_off: start of each (rank, tile) bin, then |C|
+  uint32_t* t_rank_tb;       // [sum nprobe] first bin of each probe rank
+  const int64_t* t_bin_off;  // [nq + 1]
+  int t_shift;
 };
 // wide form: the bins of C (a no-op otherwise); then the exact keys of C
 // (wide form) and the walk

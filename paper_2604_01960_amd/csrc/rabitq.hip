@@ -365,7 +365,7 @@ hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
 
 // ---- bounded re-rank ---------------------------------------------------------------
 constexpr int WK_NB = 2048;       // lb bins
-constexpr int WK_RANKCAP = 2048;  // probe ranks in LDS
+constexpr int WK_RANKCAP = WALK_RANKS_LDS;  // probe ranks in LDS
 constexpr int WK_CHUNK = 1024;    // items per step of the exact walk (and per bin-walk round)
 constexpr int WK_QCAP = 4096;     // objects above the k-th exact key resolved in LDS
 constexpr int WK_U = 2;           // loads in flight per thread in the block-wide passes
@@ -454,17 +454,30 @@ __device__ void lds_bitonic_sort_kv(uint64_t* key, V* val, int n) {
 
 // The lb bins of a query's candidate set C = {lb <= U}, U = the k-th smallest
 // ub (every object when S <= k), grouped by bin: hist[b] = the end of bin b.
-// Without cpos, cbuf holds C's slots; with it (wide form), cpos holds their
-// list positions and cbuf their lb images.
+// In the per-query form cbuf holds C's slots; in the wide form it holds their
+// lb images, cpos (when not NULL) their list positions, and so (when so.pos
+// is not NULL) receives C in slot order.
 struct WalkBins {
   uint32_t U, lmin;
   int shift;
   int64_t nC;
 };
 
+// C in slot order: by probe rank, then list position, so grouped by tile of
+// 2^shift rows of each probed list (the order the tile-major keys read).
+struct SlotOrder {
+  uint32_t* pos;            // list positions
+  uint32_t* idx;            // places in cbuf order
+  uint32_t* bins;           // start of each (rank, tile) bin, then |C| at [nbins]
+  const uint32_t* rank_tb;  // (LDS) first bin of each probe rank
+  uint32_t nbins;
+  int shift;
+};
+
 template <int NT>
-__device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float* ub, uint32_t* cbuf, int32_t* cpos,
-                              const SlotMap& sm, uint32_t* hist, uint32_t* rhist, uint32_t* bc) {
+__device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float* ub, bool wide, uint32_t* cbuf,
+                              int32_t* cpos, const SlotOrder& so, const SlotMap& sm, uint32_t* hist, uint32_t* rhist,
+                              uint32_t* bc) {
   const int lane = threadIdx.x & 63;
   WalkBins w;
   w.U = 0xffffffffu;
@@ -510,17 +523,70 @@ __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float
     }
   }
   __syncthreads();
-  block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
-    if (valid && b <= U) {
-      const uint32_t j = atomicAdd(&hist[(b - lmin) >> shift], 1u);
-      if (cpos) {
-        cbuf[j] = b;
-        cpos[j] = (int32_t)sm.pos(i);
-      } else {
-        cbuf[j] = (uint32_t)i;
+  if (so.pos) {
+    // slot order: SPT consecutive slots per thread, rows of NT * SPT slots,
+    // a block scan of the members per row
+    constexpr int SPT = 4;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const uint32_t tmask = (1u << so.shift) - 1u;
+    uint32_t* s_w = rhist;  // wave totals of a row
+    uint32_t carry = 0;     // members in the earlier rows
+    for (int64_t row = 0; row < S; row += (int64_t)NT * SPT) {
+      const int64_t i0 = row + (int64_t)SPT * threadIdx.x;
+      uint32_t img[SPT];
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) img[u] = lb_bits(min(i0 + u, S - 1));
+      uint32_t cnt = 0;
+#pragma unroll
+      for (int u = 0; u < SPT; ++u) cnt += (i0 + u < S && img[u] <= U) ? 1u : 0u;
+      const uint32_t incl = wave_incl_scan(cnt);
+      if (lane == 63) s_w[wv] = incl;
+      __syncthreads();
+      uint32_t before = 0, tot = 0;
+      for (int w2 = 0; w2 < NT / 64; ++w2) {
+        const uint32_t t = s_w[w2];
+        before += w2 < wv ? t : 0u;
+        tot += t;
       }
+      uint32_t c = carry + before + incl - cnt;
+      if (i0 < S) {
+        int r = sm.rank(i0);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+          const int64_t i = i0 + u;
+          if (i < S) {
+            while (r + 1 < sm.np && sm.rbeg(r + 1) <= i) ++r;
+            const int64_t off = i - sm.rbeg(r);
+            if (((uint32_t)off & tmask) == 0) so.bins[so.rank_tb[r] + (uint32_t)(off >> so.shift)] = c;
+            if (img[u] <= U) {
+              const uint32_t j = atomicAdd(&hist[(img[u] - lmin) >> shift], 1u);
+              const int64_t pos = sm.lbeg(r) + off;
+              cbuf[j] = img[u];
+              if (cpos) cpos[j] = (int32_t)pos;
+              so.pos[c] = (uint32_t)pos;
+              so.idx[c] = j;
+              ++c;
+            }
+          }
+        }
+      }
+      carry += tot;
+      __syncthreads();
     }
-  });
+    if (threadIdx.x == 0) so.bins[so.nbins] = carry;
+  } else {
+    block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
+      if (valid && b <= U) {
+        const uint32_t j = atomicAdd(&hist[(b - lmin) >> shift], 1u);
+        if (wide) {
+          cbuf[j] = b;
+          if (cpos) cpos[j] = (int32_t)sm.pos(i);
+        } else {
+          cbuf[j] = (uint32_t)i;
+        }
+      }
+    });
+  }
   __syncthreads();
   return w;
 }
@@ -533,21 +599,57 @@ __global__ __launch_bounds__(1024) void rabitq_walk_prep_kernel(RabitqWalkArgs a
   constexpr int NT = 1024;
   __shared__ int32_t s_rbeg[WK_RANKCAP];
   __shared__ int32_t s_lbeg[WK_RANKCAP];
+  __shared__ uint32_t s_tb[WK_RANKCAP];
   __shared__ uint32_t hist[WK_NB];
   __shared__ uint32_t rhist[256];
   __shared__ __align__(8) uint32_t bc[16];
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
+  const int np = a.nprobe[qi];
+  const int64_t po = a.probe_off[qi];
   uint32_t* st = a.wstate + 4 * qi;
+  SlotOrder so{};
+  if (a.t_pos) {
+    // the tiles of each probed list (np <= WK_RANKCAP, checked by the host),
+    // their first bins by an exclusive scan
+    const int64_t tr = (int64_t)1 << a.t_shift;
+    for (int r = threadIdx.x; r < np; r += NT) {
+      const int L = a.probe_lists[po + r];
+      s_tb[r] = (uint32_t)((a.list_off[L + 1] - a.list_off[L] + tr - 1) >> a.t_shift);
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+      const int lane = threadIdx.x;
+      uint32_t carry = 0;
+      for (int base = 0; base < np; base += 64) {
+        const uint32_t v = base + lane < np ? s_tb[base + lane] : 0u;
+        const uint32_t incl = wave_incl_scan(v);
+        if (base + lane < np) s_tb[base + lane] = carry + incl - v;
+        carry += __shfl(incl, 63);
+      }
+      if (lane == 0) bc[12] = carry;
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < np; r += NT) a.t_rank_tb[po + r] = s_tb[r];
+    so.pos = a.t_pos + a.key_off[qi];
+    so.idx = a.t_idx + a.key_off[qi];
+    so.bins = a.t_bins + a.t_bin_off[qi];
+    so.rank_tb = s_tb;
+    so.nbins = bc[12];
+    so.shift = a.t_shift;
+  }
   if (S == 0) {
-    if (threadIdx.x == 0) { st[0] = 0; st[1] = 0; st[2] = 0; st[3] = 0; }
+    if (threadIdx.x == 0) {
+      st[0] = 0; st[1] = 0; st[2] = 0; st[3] = 0;
+      if (a.t_pos) so.bins[so.nbins] = 0;  // (every probed list is empty: no bins before)
+    }
     return;
   }
-  const int64_t po = a.probe_off[qi];
-  const SlotMap sm = slot_map_load<NT, WK_RANKCAP>(a.rank_off + po, a.probe_lists + po, a.list_off, a.nprobe[qi],
-                                                   s_rbeg, s_lbeg);
-  const WalkBins w = walk_bins<NT>(S, a.k[qi], a.lb + a.key_off[qi], a.ub + a.key_off[qi], a.cbuf + a.key_off[qi],
-                                   a.cpos + a.key_off[qi], sm, hist, rhist, bc);
+  const SlotMap sm = slot_map_load<NT, WK_RANKCAP>(a.rank_off + po, a.probe_lists + po, a.list_off, np, s_rbeg,
+                                                   s_lbeg);
+  const WalkBins w = walk_bins<NT>(S, a.k[qi], a.lb + a.key_off[qi], a.ub + a.key_off[qi], true,
+                                   a.cbuf + a.key_off[qi], a.cpos ? a.cpos + a.key_off[qi] : nullptr,
+                                   so, sm, hist, rhist, bc);
   for (int i = threadIdx.x; i < WK_NB; i += NT) a.wbins[qi * WK_NB + i] = hist[i];
   if (threadIdx.x == 0) { st[0] = w.U; st[1] = w.lmin; st[2] = (uint32_t)w.shift; st[3] = (uint32_t)w.nC; }
 }
@@ -651,7 +753,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
     for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = a.wbins[qi * WK_NB + i];
     __syncthreads();
   } else {
-    w = walk_bins<NT>(S, k, lb, ub, cbuf, nullptr, sm, hist, rhist, bc);
+    w = walk_bins<NT>(S, k, lb, ub, false, cbuf, nullptr, SlotOrder{}, sm, hist, rhist, bc);
   }
   const uint32_t U = w.U, lmin = w.lmin;
   const int shift = w.shift;

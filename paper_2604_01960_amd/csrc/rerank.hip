@@ -592,7 +592,7 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
   hipLaunchKernelGGL(rt_pair_count, pg, dim3(256), 0, s, a);
   hipLaunchKernelGGL(rt_pair_offsets, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(rt_pair_scatter, pg, dim3(256), 0, s, a);
-  hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
+  if (!a.presorted) hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
   const int64_t groups = (a.npairs + a.group - 1) / a.group + a.nlist;  // bound on the padded group count
   const bool wide = a.d / 4 > 32;
   if (a.fp16) {

@@ -138,19 +138,22 @@ def test_device_io_and_repeat(bbc):
     np.testing.assert_array_equal(dists.cpu().numpy(), a[1])
 
 
-@pytest.mark.parametrize("ranges", [False, True])
-def test_tile_keys_many_queries(bbc, ranges):
+@pytest.mark.parametrize("sort", ["walk", "cand_sort", "cand_sort_ranges"])
+def test_tile_keys_many_queries(bbc, sort):
     """Tile-major exact keys with more queries per list than one group of
-    pairs holds (several groups per list), one wave per candidate row; with
-    the bin counters cut to one list's tiles, each query's ranks are sorted
-    in ranges."""
+    pairs holds (several groups per list), one wave per candidate row.  The
+    candidates reach tile order from the walk's bin pass (slot order), or
+    from the candidate sort, with all bins counted at once or, with the bin
+    counters cut to one list's tiles, each query's ranks in ranges."""
     import os
     x, q, tr, ip, P, ix = _data(256, 5000, 200, 10, 1, True)
-    if ranges:
-        os.environ["BBC_RERANK_SORT_BINS"] = "1"
+    env = {"walk": {}, "cand_sort": {"BBC_WALK_PRESORT": "0"},
+           "cand_sort_ranges": {"BBC_WALK_PRESORT": "0", "BBC_RERANK_SORT_BINS": "1"}}[sort]
+    os.environ.update(env)
     try:
         g = _gpu_index(bbc, x, ix, form="tiles")
     finally:
-        os.environ.pop("BBC_RERANK_SORT_BINS", None)
-    print(f"[case] rabitq tile keys, 200 queries, ranges={ranges}", flush=True)
+        for v in env:
+            os.environ.pop(v, None)
+    print(f"[case] rabitq tile keys, 200 queries, sort={sort}", flush=True)
     _check_search(g, ix, q, 120, 8)
