@@ -178,6 +178,9 @@ struct bbc_index {
   // RaBitQ tile-major keys: C put in tile order by the walk's bin pass (1) or
   // by the candidate sort (0) (BBC_WALK_PRESORT)
   int walk_presort = 1;
+  // RaBitQ scan order with tile-major keys: pairs by list, a run of lists per
+  // XCD (1), or by query (0) (BBC_SCAN_BY_LIST)
+  int scan_by_list = 1;
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -277,6 +280,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 3) ix->walk_form = x;
+  }
+  if (const char* sv = std::getenv("BBC_SCAN_BY_LIST")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 1) ix->scan_by_list = x;
   }
   if (const char* sv = std::getenv("BBC_WALK_PRESORT")) {
     const int x = std::atoi(sv);
@@ -930,7 +937,24 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     StageScope st(s, 1);
     HIP_TRY(bbc::launch_rotate(dq, nq, d, ix->rot, qrot, s));
   }
+  // tile-major keys: the (query, rank) pairs grouped by list, before the scan
+  // when it takes them in that order
+  bbc::TileRerankArgs ta{};
+  if (tile_keys) {
+    ta.q = dq; ta.nq = nq; ta.d = d; ta.metric = ix->metric; ta.vectors = ix->vectors; ta.fp16 = ix->fp16;
+    ta.list_ids = ix->list_ids; ta.list_off = ix->list_off; ta.list_of_pos = ix->list_of_pos;
+    ta.nprobe = d_np; ta.probe_off = d_po; ta.probe_lists = pa.probe_lists; ta.nlist = ix->nlist;
+    ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
+    ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
+    ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
+    ta.lpairs_cap = rt_lpairs_cap;
+    ta.group = rt_group;
+  }
+  const bool scan_by_list = tile_keys && ix->scan_by_list;
   bbc::RabitqScanArgs sa{};
+  if (scan_by_list) {
+    sa.lpairs = ta.lpairs; sa.ngroups = ta.lcnt + ix->nlist; sa.group = rt_group; sa.lpairs_cap = rt_lpairs_cap;
+  }
   sa.npairs = npairs; sa.nq = nq; sa.probe_off = d_po; sa.probe_lists = pa.probe_lists; sa.probe_keys = pa.probe_keys;
   sa.rank_off = pa.rank_off; sa.key_off = d_ko; sa.q = dq; sa.qrot = qrot; sa.rot_cent = ix->rot_cent;
   sa.D = d; sa.metric = ix->metric; sa.eps0 = ix->eps0; sa.list_off = ix->list_off; sa.codes = ix->rq_codes;
@@ -942,6 +966,10 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   sa.key = tracing ? reinterpret_cast<float*>(A + L_key) : nullptr;
   {
     StageScope st(s, 2);
+    if (scan_by_list) {
+      HIP_TRY(bbc::launch_tile_pairs(ta, s));
+      ta.pairs_ready = 1;
+    }
     HIP_TRY(bbc::launch_rabitq_scan(sa, s));
   }
   bbc::RabitqWalkArgs wa{};
@@ -977,23 +1005,14 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     StageScope st(s, 4);
     if (tile_keys) {
       // the exact keys of C, tile-major, at C's indices (what the walk reads)
-      bbc::TileRerankArgs ta{};
-      ta.q = dq; ta.nq = nq; ta.d = d; ta.metric = ix->metric; ta.vectors = ix->vectors; ta.fp16 = ix->fp16;
-      ta.list_ids = ix->list_ids; ta.list_off = ix->list_off; ta.list_of_pos = ix->list_of_pos;
-      ta.nprobe = d_np; ta.probe_off = d_po; ta.probe_lists = pa.probe_lists; ta.nlist = ix->nlist;
       ta.cand_pos = reinterpret_cast<const uint32_t*>(wa.cpos); ta.pos_off = d_ko;
       ta.ncand_w = wa.wstate + 3; ta.ncand_stride = 4;
       ta.cand_off = d_ko; ta.cand_packed = wa.cand_packed;
-      ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
       ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L_rts);
       ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L_rti);
       ta.pair_tb = reinterpret_cast<uint32_t*>(A + L_rtp);
       ta.bin_off = d_bo;
       ta.bin_beg = reinterpret_cast<uint32_t*>(A + L_rtb);
-      ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
-      ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
-      ta.lpairs_cap = rt_lpairs_cap;
-      ta.group = rt_group;
       ta.presorted = presort ? 1 : 0;
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
       wa.keys_ready = 1;

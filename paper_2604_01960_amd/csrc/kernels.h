@@ -140,7 +140,10 @@ struct TileRerankArgs {
   int64_t lpairs_cap;       // npairs + nlist * (group - 1)
   int group;                // pairs per block: tile_rerank_group(d)
   int presorted;            // sorted_pos, sorted_idx, pair_tb and bin_beg already filled
+  int pairs_ready;          // lcnt and lpairs already filled (launch_tile_pairs)
 };
+// the (query, rank) pairs grouped by list into whole groups: lcnt, lpairs
+hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s);
 int tile_rerank_group(int d);
 // log2 of the rows per tile for the row shape, or -1 where the form does not apply
 int tile_rerank_shift(int d, int fp16);
@@ -197,6 +200,10 @@ struct RabitqScanArgs {
   float* lb; float* ub; float* key;  // [sum S] by slot at key_off[q]; key optional
   int max_np;               // largest nprobe of the batch (the 2-D grid's first dimension)
   int grid2d;               // set by the launcher
+  // optional: the (query << 32 | rank) pairs grouped by list, *ngroups groups
+  // of `group` entries (~0 pads), scanned so that each XCD takes a contiguous
+  // run of them (a list's code rows then stay in that XCD's L2)
+  const uint64_t* lpairs; const uint32_t* ngroups; int group; int64_t lpairs_cap;
 };
 hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s);
 

@@ -197,7 +197,18 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
   __shared__ float scal[8];
 
   int64_t p, qi;
-  if (a.grid2d) {
+  if (a.lpairs) {
+    // XCD x (blocks x, x + 8, ...) takes the x-th eighth of the pairs in order
+    const int64_t n = (int64_t)*a.ngroups * a.group;
+    const int64_t per = (n + 7) / 8;
+    const int64_t b = blockIdx.x;
+    const int64_t idx = (b & 7) * per + (b >> 3);
+    if ((b >> 3) >= per || idx >= n) return;
+    const uint64_t e = a.lpairs[idx];
+    if (e == ~0ull) return;
+    qi = (int64_t)(e >> 32);
+    p = a.probe_off[qi] + (int64_t)(uint32_t)e;
+  } else if (a.grid2d) {
     qi = blockIdx.y;
     const int64_t pb = a.probe_off[qi], pe = a.probe_off[qi + 1];
     p = pb + blockIdx.x;
@@ -358,7 +369,9 @@ hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
   if (a.D > 32 * RQ_MAXW_ROW || a.D % 64 || a.code_words > RQ_MAXW_ROW || a.code_words % 4) return hipErrorInvalidValue;
   RabitqScanArgs b = a;
   b.grid2d = a.nq <= 65535 && a.max_np >= 1;
-  const dim3 g = b.grid2d ? dim3((unsigned)a.max_np, (unsigned)a.nq) : dim3((unsigned)a.npairs);
+  if (a.lpairs && (a.lpairs_cap < 1 || a.lpairs_cap > 0x7fffffffLL)) return hipErrorInvalidValue;
+  const dim3 g = a.lpairs ? dim3((unsigned)((a.lpairs_cap + 7) / 8 * 8))
+                          : b.grid2d ? dim3((unsigned)a.max_np, (unsigned)a.nq) : dim3((unsigned)a.npairs);
   hipLaunchKernelGGL(rabitq_scan_kernel, g, dim3(256), 0, s, b);
   return hipGetLastError();
 }

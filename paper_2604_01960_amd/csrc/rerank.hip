@@ -582,7 +582,7 @@ size_t tile_rerank_sort_lds(int max_bins, int max_np, int nlist) {
   return sizeof(uint32_t) * ((size_t)max_bins + 2 * (size_t)max_np) + sizeof(uint16_t) * (size_t)nlist;
 }
 
-hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s) {
+hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s) {
   if (a.nq <= 0 || a.npairs <= 0) return hipSuccess;
   const dim3 pg((unsigned)((a.max_np + 255) / 256), (unsigned)a.nq);
   hipLaunchKernelGGL(rt_fill_u32, dim3((unsigned)std::min<int64_t>((a.nlist + 256) / 256, 1024)), dim3(256), 0, s,
@@ -592,6 +592,15 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
   hipLaunchKernelGGL(rt_pair_count, pg, dim3(256), 0, s, a);
   hipLaunchKernelGGL(rt_pair_offsets, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(rt_pair_scatter, pg, dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s) {
+  if (a.nq <= 0 || a.npairs <= 0) return hipSuccess;
+  if (!a.pairs_ready) {
+    const hipError_t e = launch_tile_pairs(a, s);
+    if (e != hipSuccess) return e;
+  }
   if (!a.presorted) hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
   const int64_t groups = (a.npairs + a.group - 1) / a.group + a.nlist;  // bound on the padded group count
   const bool wide = a.d / 4 > 32;
