@@ -214,7 +214,9 @@ __device__ __forceinline__ void wave_hist_add(uint32_t* hist, uint32_t bin, bool
 // load(i) of U consecutive strides are loaded before any is used (U loads in
 // flight per thread), then use(i, valid, v) runs for each; every lane calls
 // use() the same block-uniform number of times (valid = false past n), so
-// use() may take wave-wide collectives.
+// use() may take wave-wide collectives.  Lanes past n load element n - 1
+// (and ignore it): a load under a lane mask would be issued and waited for
+// on its own.
 template <int NT, int U, typename Load, typename Use>
 __device__ __forceinline__ void block_for_batched(int64_t n, Load load, Use use) {
   using V = decltype(load((int64_t)0));
@@ -223,7 +225,7 @@ __device__ __forceinline__ void block_for_batched(int64_t n, Load load, Use use)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int64_t i = base + (int64_t)u * NT + threadIdx.x;
-      v[u] = i < n ? load(i) : V{};
+      v[u] = load(i < n ? i : n - 1);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -236,13 +238,13 @@ __device__ __forceinline__ void block_for_batched(int64_t n, Load load, Use use)
 // Radix select over a block: value of the element of rank r (0-based,
 // ascending) among n 32-bit values produced by get(i).  hist: 256 LDS words;
 // bc: 4 LDS words for broadcast, 8-byte aligned.
-template <int NT, typename Get>
+template <int NT, int U = 4, typename Get>
 __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
   uint32_t prefix = 0, mask = 0;
   for (int shift = 24; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    block_for_batched<NT, 4>(n, get, [&](int64_t, bool valid, uint32_t v) {
+    block_for_batched<NT, U>(n, get, [&](int64_t, bool valid, uint32_t v) {
       wave_hist_add(hist, (v >> shift) & 255u, valid && (v & mask) == prefix);
     });
     __syncthreads();
@@ -257,14 +259,14 @@ __device__ uint32_t block_radix_select32(Get get, int64_t n, int64_t r, uint32_t
 }
 
 // 64-bit variant over the elements for which get(i, v) returns true.
-template <int NT, typename Get>
+template <int NT, int U = 4, typename Get>
 __device__ uint64_t block_radix_select64(Get get, int64_t n, int64_t r, uint32_t* hist, uint32_t* bc) {
   uint64_t prefix = 0, mask = 0;
   struct KV { uint64_t v; bool ok; };
   for (int shift = 56; shift >= 0; shift -= 8) {
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
     __syncthreads();
-    block_for_batched<NT, 4>(
+    block_for_batched<NT, U>(
         n,
         [&](int64_t i) {
           KV e{0, false};

@@ -381,7 +381,8 @@ constexpr int WK_NB = 2048;       // lb bins
 constexpr int WK_RANKCAP = WALK_RANKS_LDS;  // probe ranks in LDS
 constexpr int WK_CHUNK = 1024;    // items per step of the exact walk (and per bin-walk round)
 constexpr int WK_QCAP = 4096;     // objects above the k-th exact key resolved in LDS
-constexpr int WK_U = 2;           // loads in flight per thread in the block-wide passes
+constexpr int WK_U = 2;           // loads in flight per thread in the walk's block-wide passes
+constexpr int PREP_U = 8;         // and in the wide form's bin pass
 
 template <typename T> __device__ __forceinline__ float4 ld4(const T* p, int64_t chunk);
 template <> __device__ __forceinline__ float4 ld4<float>(const float* p, int64_t chunk) {
@@ -487,14 +488,14 @@ struct SlotOrder {
   int shift;
 };
 
-template <int NT>
+template <int NT, int LU>
 __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float* ub, bool wide, uint32_t* cbuf,
                               int32_t* cpos, const SlotOrder& so, const SlotMap& sm, uint32_t* hist, uint32_t* rhist,
                               uint32_t* bc) {
   const int lane = threadIdx.x & 63;
   WalkBins w;
   w.U = 0xffffffffu;
-  if (S > k) w.U = block_radix_select32<NT>([&](int64_t i) { return key_bits(ub[i]); }, S, k - 1, rhist, bc);
+  if (S > k) w.U = block_radix_select32<NT, LU>([&](int64_t i) { return key_bits(ub[i]); }, S, k - 1, rhist, bc);
   const uint32_t U = w.U;
   // C's smallest and largest lb image
   if (threadIdx.x == 0) { bc[4] = 0xffffffffu; bc[5] = 0u; bc[6] = 0u; }
@@ -502,7 +503,7 @@ __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float
   auto lb_bits = [&](int64_t i) { return key_bits(lb[i]); };
   {
     uint32_t mn = 0xffffffffu, mx = 0u, cnt = 0;
-    block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
+    block_for_batched<NT, LU>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
       if (valid && b <= U) { mn = min(mn, b); mx = max(mx, b); ++cnt; }
     });
     for (int off = 32; off >= 1; off >>= 1) {
@@ -521,7 +522,7 @@ __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float
   int shift = 0;
   while ((span >> shift) >= (uint32_t)WK_NB) ++shift;
   w.shift = shift;
-  block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
+  block_for_batched<NT, LU>(S, lb_bits, [&](int64_t, bool valid, uint32_t b) {
     const bool in = valid && b <= U;
     wave_hist_add(hist, in ? (b - lmin) >> shift : 0u, in);
   });
@@ -588,7 +589,7 @@ __device__ WalkBins walk_bins(int64_t S, int64_t k, const float* lb, const float
     }
     if (threadIdx.x == 0) so.bins[so.nbins] = carry;
   } else {
-    block_for_batched<NT, WK_U>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
+    block_for_batched<NT, LU>(S, lb_bits, [&](int64_t i, bool valid, uint32_t b) {
       if (valid && b <= U) {
         const uint32_t j = atomicAdd(&hist[(b - lmin) >> shift], 1u);
         if (wide) {
@@ -660,7 +661,7 @@ __global__ __launch_bounds__(1024) void rabitq_walk_prep_kernel(RabitqWalkArgs a
   }
   const SlotMap sm = slot_map_load<NT, WK_RANKCAP>(a.rank_off + po, a.probe_lists + po, a.list_off, np, s_rbeg,
                                                    s_lbeg);
-  const WalkBins w = walk_bins<NT>(S, a.k[qi], a.lb + a.key_off[qi], a.ub + a.key_off[qi], true,
+  const WalkBins w = walk_bins<NT, PREP_U>(S, a.k[qi], a.lb + a.key_off[qi], a.ub + a.key_off[qi], true,
                                    a.cbuf + a.key_off[qi], a.cpos ? a.cpos + a.key_off[qi] : nullptr,
                                    so, sm, hist, rhist, bc);
   for (int i = threadIdx.x; i < WK_NB; i += NT) a.wbins[qi * WK_NB + i] = hist[i];
@@ -766,7 +767,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
     for (int i = threadIdx.x; i < WK_NB; i += NT) hist[i] = a.wbins[qi * WK_NB + i];
     __syncthreads();
   } else {
-    w = walk_bins<NT>(S, k, lb, ub, false, cbuf, nullptr, SlotOrder{}, sm, hist, rhist, bc);
+    w = walk_bins<NT, WK_U>(S, k, lb, ub, false, cbuf, nullptr, SlotOrder{}, sm, hist, rhist, bc);
   }
   const uint32_t U = w.U, lmin = w.lmin;
   const int shift = w.shift;
@@ -866,7 +867,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       const int b = found < WK_NB ? found + 1 : WK_NB;
       p = hist[b - 1];
       exhausted = p >= nC;
-      Eimg = block_radix_select32<NT>([&](int64_t i) { return ximg[2 * i]; }, p, k - 1, rhist, bc);
+      Eimg = block_radix_select32<NT, WK_U>([&](int64_t i) { return ximg[2 * i]; }, p, k - 1, rhist, bc);
     }
   } else {
     // Z = the processed (exact, id) that can still be among the k best: all
@@ -894,7 +895,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       nz += bc[13];
       p = np_;
       if (p >= k) {
-        Eimg = block_radix_select32<NT>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
+        Eimg = block_radix_select32<NT, WK_U>([&](int64_t i) { return (uint32_t)(zA[i] >> 32); }, nz, k - 1, rhist, bc);
         if (threadIdx.x == 0) bc[13] = 0;
         __syncthreads();
         block_for_batched<NT, WK_U>(nz, [&](int64_t i) { return zA[i]; }, [&](int64_t, bool valid, uint64_t v) {
@@ -948,7 +949,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       const int64_t n0 = p - nQ;
       uint32_t thr0 = 0xffffffffu;
       if (n0 > k)
-        thr0 = block_radix_select32<NT>(
+        thr0 = block_radix_select32<NT, WK_U>(
             [&](int64_t i) { return lb_img(i) <= E ? (uint32_t)(pbuf[i] >> 32) : 0xffffffffu; }, p,
             k - 1, rhist, bc);
       if (threadIdx.x == 0) bc[13] = 0;
@@ -999,7 +1000,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
         };
         while (lo < hi) {
           const int64_t t = (lo + hi) >> 1;
-          const uint64_t kt = block_radix_select64<NT>(qkey, p, t, rhist, bc);
+          const uint64_t kt = block_radix_select64<NT, WK_U>(qkey, p, t, rhist, bc);
           const uint32_t L = (uint32_t)(kt >> 32);
           const int64_t below = count_below(
               nz0 + p,
@@ -1012,7 +1013,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
               L);
           if (below >= k) hi = t; else lo = t + 1;
         }
-        if (lo < nQ) cut = block_radix_select64<NT>(qkey, p, lo, rhist, bc);
+        if (lo < nQ) cut = block_radix_select64<NT, WK_U>(qkey, p, lo, rhist, bc);
       }
       // visited: P minus the objects of Q from position lo on
       if (lo < nQ) {
@@ -1061,7 +1062,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
     const int64_t rem = bc[8];
     if (rem == 0) break;
     const int64_t nb = min((int64_t)WK_CHUNK, rem);
-    const uint64_t thr = block_radix_select64<NT>(
+    const uint64_t thr = block_radix_select64<NT, WK_U>(
         [&](int64_t i, uint64_t& v) -> bool {
           v = packed_lb(i);
           return !have_last || v > last;
