@@ -483,14 +483,20 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   }
 }
 
-// canon_reduce64 with the last four levels as DPP: after the xor levels 32
-// and 16 every lane's value repeats with period 16, after the rotation by 8
-// with period 8, so each rotation pairs lane l with the lane the canonical
-// tree pairs it with whichever way it turns, and every lane ends with the
-// canonical sum.
+// canon_reduce64 without LDS permutes.  Levels 32 and 16: swapping the
+// upper half of one copy with the lower half of another (v_permlane32_swap),
+// or the odd 16-lane rows of one with the even rows of another
+// (v_permlane16_swap), leaves lane l with its own value in one output and
+// lane l ^ 32 (l ^ 16) in the other, so their sum is the tree's pair sum.
+// The last four levels as DPP: after the xor levels 32 and 16 every lane's
+// value repeats with period 16, after the rotation by 8 with period 8, so
+// each rotation pairs lane l with the lane the canonical tree pairs it with
+// whichever way it turns, and every lane ends with the canonical sum.
 __device__ __forceinline__ float canon_reduce64_dpp(float acc) {
-  acc = acc + __shfl_xor(acc, 32);
-  acc = acc + __shfl_xor(acc, 16);
+  const auto s32 = __builtin_amdgcn_permlane32_swap(__float_as_uint(acc), __float_as_uint(acc), false, false);
+  acc = __uint_as_float(s32[0]) + __uint_as_float(s32[1]);
+  const auto s16 = __builtin_amdgcn_permlane16_swap(__float_as_uint(acc), __float_as_uint(acc), false, false);
+  acc = __uint_as_float(s16[0]) + __uint_as_float(s16[1]);
   acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x128, 0xf, 0xf, false));  // row_ror:8
   acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x124, 0xf, 0xf, false));  // row_ror:4
   acc = acc + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(acc), 0x4e, 0xf, 0xf, false));   // quad [2,3,0,1]
@@ -501,8 +507,10 @@ __device__ __forceinline__ float canon_reduce64_dpp(float acc) {
 // Rows of 33 to 256 chunks (groups of RT_GW pairs): wave w takes pair w of
 // the group and keeps its query chunks in registers over all the list's
 // tiles (lane l holds chunks l, l + 64, l + 128 and l + 192, the canonical
-// steps of virtual lane l); one candidate row at a time, from LDS.
-template <typename T>
+// steps of virtual lane l); one candidate row at a time, from LDS, its four
+// chunk reads issued together (lanes past the row's chunks read its last
+// chunk and leave their sum as it is).  IP: the metric is inner product.
+template <typename T, bool IP>
 __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a) {
   constexpr int NT = 1024;
   static_assert(RT_GW == NT / 64, "one pair per wave");
@@ -518,7 +526,6 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
   const int ntile = (int)((le - lb + TR - 1) >> a.tshift);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int nchunk = a.d >> 2;
-  const bool ip = a.metric != 0;
   const int row_words = a.d * (int)sizeof(T) / 16;
   const T* trow = reinterpret_cast<const T*>(tile);
   const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
@@ -553,14 +560,17 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
         const int rr = __builtin_amdgcn_readlane(rowl, jj);
         if (rr < 0) continue;  // wave-uniform
         const T* row = trow + (int64_t)rr * a.d;
+        float4 xv[4];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) xv[st] = load4<T>(row, min(lane + 64 * st, nchunk - 1));
         float acc = 0.0f;
 #pragma unroll
         for (int st = 0; st < 4; ++st) {
-          const int c4 = lane + 64 * st;
-          if (c4 < nchunk) acc = ip ? chunk_ip(qv[st], load4<T>(row, c4), acc) : chunk_l2(qv[st], load4<T>(row, c4), acc);
+          const float nx = IP ? chunk_ip(qv[st], xv[st], acc) : chunk_l2(qv[st], xv[st], acc);
+          acc = lane + 64 * st < nchunk ? nx : acc;
         }
         acc = canon_reduce64_dpp(acc);  // every lane ends with the sum
-        if (lane == jj) mykey = ip ? -acc : acc;
+        if (lane == jj) mykey = IP ? -acc : acc;
       }
       if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
     }
@@ -604,13 +614,19 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
   if (!a.presorted) hipLaunchKernelGGL(rt_cand_sort, dim3((unsigned)a.nq), dim3(1024), sort_lds, s, a);
   const int64_t groups = (a.npairs + a.group - 1) / a.group + a.nlist;  // bound on the padded group count
   const bool wide = a.d / 4 > 32;
-  if (a.fp16) {
-    if (wide) hipLaunchKernelGGL(rt_rerank_tile_wide<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL(rt_rerank_tile<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
-  } else {
-    if (wide) hipLaunchKernelGGL(rt_rerank_tile_wide<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL(rt_rerank_tile<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  if (wide) {
+    const bool ip = a.metric != 0;
+    if (a.fp16) {
+      if (ip) hipLaunchKernelGGL((rt_rerank_tile_wide<__half, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+      else hipLaunchKernelGGL((rt_rerank_tile_wide<__half, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+    } else {
+      if (ip) hipLaunchKernelGGL((rt_rerank_tile_wide<float, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+      else hipLaunchKernelGGL((rt_rerank_tile_wide<float, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+    }
+    return hipGetLastError();
   }
+  if (a.fp16) hipLaunchKernelGGL(rt_rerank_tile<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  else hipLaunchKernelGGL(rt_rerank_tile<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 

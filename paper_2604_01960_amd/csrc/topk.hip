@@ -340,9 +340,19 @@ __global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_to
     if (!done) sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
   } else if (cnt > 0 && cnt <= a.cap) {
     const bool done = final_topk_binned(a.metric, a.cap, in, kc, cnt, oid, odist, run_buf, hist, bbuf, red, [&](auto fn) {
-      for (int64_t base = 0; base < kc; base += NT) {
-        const int64_t i = base + threadIdx.x;
-        fn(i < kc ? in[i] : ~0ull, i < kc);
+      constexpr int B = IPT == 0 ? 8 : 1;  // loads in flight per thread (registers kept for the others)
+      for (int64_t base = 0; base < kc; base += (int64_t)NT * B) {
+        uint64_t v[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+          v[u] = in[i < kc ? i : kc - 1];
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+          const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+          if (base + (int64_t)u * NT < kc) fn(i < kc ? v[u] : ~0ull, i < kc);
+        }
       }
     });
     if (!done) sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
