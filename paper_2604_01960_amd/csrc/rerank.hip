@@ -407,9 +407,13 @@ __device__ __forceinline__ int rt_run_pair(const RtGroup& g, uint32_t c) {
 }
 
 // Rows of at most 32 chunks: 8 lanes per candidate, lane p of an octet
-// holding the virtual lanes (four-element chunks) p, p + 8, p + 16 and p + 24
-// of the canonical sum.
-template <typename T>
+// holding the virtual lanes (four-element chunks) u, u + 8, u + 16 and u + 24
+// of the canonical sum, u = p for p < 4 and 11 - p otherwise, so that the
+// tree's level 4 pairs lanes p and 7 - p (a DPP half-row mirror) and levels
+// 2 and 1 stay within quads; every lane of the octet ends with the sum.  A
+// candidate's four chunk reads are issued together (clamped to the row;
+// chunks past it count as zero).  IP: the metric is inner product.
+template <typename T, bool IP>
 __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   constexpr int NT = 1024, NW = NT / 64;
   __shared__ uint4 tile[RT_TILE_BYTES / 16];
@@ -425,8 +429,9 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   const int ntile = (int)((le - lb + TR - 1) >> a.tshift);
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int oct = lane >> 3, p = lane & 7;
+  const int vb = p < 4 ? p : 11 - p;
+  const int kaddr = 4 * (8 * (lane & 7));  // byte address of lane 8 (l mod 8), which holds candidate l's sum
   const int nchunk = a.d >> 2;
-  const bool ip = a.metric != 0;
   const int row_words = a.d * (int)sizeof(T) / 16;  // 16-byte words per row
   const T* trow = reinterpret_cast<const T*>(tile);
   const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
@@ -454,29 +459,29 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
       float4 qv[4];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int v = p + 8 * i;
+        const int v = vb + 8 * i;
         qv[i] = v < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * a.d)[v] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       float mykey = 0.0f;
       for (int it = 0; it * 8 < cnt; ++it) {
-        const int rr = __shfl(rowl, it * 8 + oct);  // this octet's candidate
+        const int rr = __shfl(rowl, it * 8 + oct);  // this octet's candidate (-1: none, row 0 read)
+        const T* row = trow + (int64_t)max(rr, 0) * a.d;
         float acc[4];
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-          const int v = p + 8 * i;
-          float4 xv = make_float4(0.f, 0.f, 0.f, 0.f);
-          if (rr >= 0 && v < nchunk) xv = load4<T>(trow + (int64_t)rr * a.d, v);
-          acc[i] = ip ? chunk_ip(qv[i], xv, 0.0f) : chunk_l2(qv[i], xv, 0.0f);
+          const float4 xl = load4<T>(row, min(vb + 8 * i, nchunk - 1));
+          const float4 x = vb + 8 * i < nchunk ? xl : make_float4(0.f, 0.f, 0.f, 0.f);
+          acc[i] = IP ? chunk_ip(qv[i], x, 0.0f) : chunk_l2(qv[i], x, 0.0f);
         }
-        // levels 16 and 8 within the lane, 4 across lanes p and p + 4,
-        // 2 and 1 within quads; lane p = 0 ends with the canonical sum
+        // levels 16 and 8 within the lane, 4 across lanes p and 7 - p
+        // (half-row mirror), 2 and 1 within quads
         float sum = (acc[0] + acc[2]) + (acc[1] + acc[3]);
-        sum = sum + __shfl_xor(sum, 4);
+        sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x141, 0xf, 0xf, false));
         sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x4e, 0xf, 0xf, false));
         sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0xb1, 0xf, 0xf, false));
         // candidate it * 8 + o's sum sits in lane 8 * o
-        const float kk = __shfl(sum, 8 * (lane & 7));
-        if ((lane >> 3) == it) mykey = ip ? -kk : kk;
+        const float kk = __int_as_float(__builtin_amdgcn_ds_bpermute(kaddr, __float_as_int(sum)));
+        if ((lane >> 3) == it) mykey = IP ? -kk : kk;
       }
       if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
     }
@@ -625,8 +630,14 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
     }
     return hipGetLastError();
   }
-  if (a.fp16) hipLaunchKernelGGL(rt_rerank_tile<__half>, dim3((unsigned)groups), dim3(1024), 0, s, a);
-  else hipLaunchKernelGGL(rt_rerank_tile<float>, dim3((unsigned)groups), dim3(1024), 0, s, a);
+  const bool ip = a.metric != 0;
+  if (a.fp16) {
+    if (ip) hipLaunchKernelGGL((rt_rerank_tile<__half, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((rt_rerank_tile<__half, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+  } else {
+    if (ip) hipLaunchKernelGGL((rt_rerank_tile<float, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+    else hipLaunchKernelGGL((rt_rerank_tile<float, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
+  }
   return hipGetLastError();
 }
 
