@@ -234,7 +234,6 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
     vmin = fminf(vmin, y);
     vmax = fmaxf(vmax, y);
   }
-  for (int i = threadIdx.x; i < W; i += NT) planes4[i] = make_uint4(0u, 0u, 0u, 0u);
   for (int off = 32; off >= 1; off >>= 1) {
     vmin = fminf(vmin, __shfl_xor(vmin, off));
     vmax = fmaxf(vmax, __shfl_xor(vmax, off));
@@ -247,6 +246,8 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
   float delta = vu - vl;
   delta = delta * inv15;
   uint32_t su = 0;
+  // D is a multiple of 64: a wave quantises 64 consecutive coordinates, and
+  // the ballot of each bit plane is that plane's two 32-bit code words
   for (int i = threadIdx.x; i < D; i += NT) {
     uint32_t u = 0;
     if (delta > 0.0f) {
@@ -257,10 +258,11 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
       u = t < 0.0f ? 0u : (t > 15.0f ? 15u : (uint32_t)t);
     }
     su += u;
-    uint32_t* pw = reinterpret_cast<uint32_t*>(&planes4[i / 32]);
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-      if ((u >> b) & 1u) atomicOr(pw + b, 1u << (i % 32));
+    const uint64_t m0 = __ballot(u & 1u), m1 = __ballot(u & 2u), m2 = __ballot(u & 4u), m3 = __ballot(u & 8u);
+    if ((threadIdx.x & 63) == 0) {
+      planes4[i / 32] = make_uint4((uint32_t)m0, (uint32_t)m1, (uint32_t)m2, (uint32_t)m3);
+      planes4[i / 32 + 1] = make_uint4((uint32_t)(m0 >> 32), (uint32_t)(m1 >> 32), (uint32_t)(m2 >> 32), (uint32_t)(m3 >> 32));
+    }
   }
   for (int off = 32; off >= 1; off >>= 1) su += __shfl_xor(su, off);
   if ((threadIdx.x & 63) == 0) red_u[threadIdx.x >> 6] = su;
