@@ -295,6 +295,9 @@ __global__ __launch_bounds__(256) void rabitq_scan_kernel(RabitqScanArgs a) {
   const int64_t out0 = a.key_off[qi] + a.rank_off[p];
   const int CW = a.code_words;  // a multiple of 4, at most RQ_MAXW_ROW
   for (int64_t t0 = threadIdx.x; t0 < nobj; t0 += OBJ * NT) {
+    // the query planes are read from LDS in every pass (kept in registers
+    // across passes they take 128 VGPRs and halve the occupancy)
+    asm volatile("" ::: "memory");
     uint4 cv[OBJ][CV];
     float4 fac[OBJ];
     bool act[OBJ];
