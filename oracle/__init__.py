@@ -5,8 +5,9 @@ CPU-baseline leg use this package.  It shares no code with the GPU library
 (``paper_2604_01960_amd``) and never imports it.
 
 The arithmetic lives in ``oracle.c`` (plain C, canonical float32 order, see
-its header); this module only marshals numpy arrays through ctypes and
-composes the index build from the C steps.
+its header) and ``oracle64.c`` (O_64, the same query paths in float64, for
+distance-error reporting only); this module only marshals numpy arrays
+through ctypes and composes the index build from the C steps.
 """
 from __future__ import annotations
 
@@ -20,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
+_SRC64 = os.path.join(_HERE, "oracle64.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -32,7 +34,7 @@ def build(force: bool = True) -> str:
     """Compile oracle.c into liboracle.so (gcc, canonical float flags)."""
     if force or not os.path.exists(_LIB_PATH):
         tmp = _LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, "-lm"])
+        subprocess.check_call(["gcc", *CFLAGS, "-o", tmp, _SRC, _SRC64, "-lm"])
         os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
 
@@ -45,7 +47,8 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+                    os.path.getmtime(_SRC), os.path.getmtime(_SRC64)):
                 build()
             L = C.CDLL(_LIB_PATH)
             vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
@@ -85,6 +88,12 @@ def lib():
             L.orc_search_rabitq.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, i32, f32,
                                             vp, i64, vp, vp, vp, vp, vp, vp,
                                             vp, vp, vp, vp, vp, vp, vp, vp, vp]
+            L.orc_early_rerank.argtypes = [vp, vp, vp, i32, i64, i32, i32, i32, vp, vp, vp, vp]
+            L.orc_min_rerank.argtypes = [vp, vp, vp, vp, i64, i64, vp, vp, vp]
+            L.o64_search_pq.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, i32, vp, vp,
+                                        vp, i64, vp, vp, f64, vp, vp, vp, vp]
+            L.o64_search_rabitq.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, f64,
+                                            vp, i64, vp, vp, vp, vp, vp, vp, vp]
             L.orc_num_threads.restype = C.c_int
             _lib = L
     return _lib
@@ -190,6 +199,31 @@ def collect_bbc(keys, ids, grp_off, kc, m, nsample=8, sample_factor=2) -> Dict[s
            "collect_bbc")
     return dict(dmin=dmin[0], delta=delta[0], map=mp, tau=int(tau[0]), s=int(s[0]),
                 cand_keys=ck[:kc], cand_ids=ci[:kc], counts=counts, kc=kc)
+
+
+def early_rerank(keys, ids, grp_off, kc, m, nsample=8, sample_factor=2) -> Dict[str, int]:
+    """Early re-rank accounting of the improved IVF+PQ search (Algorithm 4):
+    predicted threshold bucket, early set size, early objects that are
+    candidates, candidates re-ranked afterwards (see oracle.c)."""
+    keys, ids, grp_off = _f32(keys), _i64(ids), _i64(grp_off)
+    ngrp = grp_off.shape[0] - 1
+    tp = np.zeros(1, np.int32)
+    out = np.zeros(3, np.int64)
+    _check(lib().orc_early_rerank(_p(keys), _p(ids), _p(grp_off), ngrp, int(kc), int(m), int(nsample),
+                                  int(sample_factor), _p(tp), _p(out[0:]), _p(out[1:]), _p(out[2:])),
+           "early_rerank")
+    return dict(tau_pred=int(tp[0]), n_early=int(out[0]), n_early_cand=int(out[1]), n_late=int(out[2]))
+
+
+def min_rerank(lb, ub, exact, ids, k):
+    """Observation 1's minimal re-rank set: (|set|, |set united with the exact
+    top-k|, Dist_k)."""
+    lb, ub, ex, ids = _f32(lb), _f32(ub), _f32(exact), _i64(ids)
+    a = np.zeros(2, np.int64)
+    dk = np.zeros(1, np.float32)
+    _check(lib().orc_min_rerank(_p(lb), _p(ub), _p(ex), _p(ids), lb.shape[0], int(k), _p(a[0:]), _p(a[1:]),
+                                _p(dk)), "min_rerank")
+    return int(a[0]), int(a[1]), dk[0]
 
 
 # --------------------------------------------------------------------------
@@ -452,6 +486,46 @@ def search_pq(index, queries, k, nprobe, ratio, debug=False):
         _p(_f32(ix["codebook"])), _p(_f32(ix["base"])), ix["metric"],
         _p(q), nq, _p(kk), _p(npb), float(ratio), _p(off), _p(ids), _p(dists), _p(counts),
         _p(pl), _p(pk), _p(poff), _p(ns), _p(nc), _p(ck), _p(ci), _p(coff)), "search_pq")
+    return res
+
+
+def search_pq64(index, queries, k, nprobe, ratio):
+    """O_64: the PQ query path in float64 (same steps as search_pq).
+    Returns dict(ids, dists (float64), counts, off)."""
+    q = _f32(queries)
+    nq = q.shape[0]
+    kk = _i32(np.broadcast_to(np.asarray(k), (nq,)))
+    npb = _i32(np.broadcast_to(np.asarray(nprobe), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    res = dict(ids=np.empty(off[-1], np.int64), dists=np.empty(off[-1], np.float64),
+               counts=np.empty(nq, np.int32), off=off)
+    ix = index
+    _check(lib().o64_search_pq(
+        ix["n"], ix["d"], ix["nlist"], _p(_f32(ix["centroids"])), _p(_i64(ix["list_off"])),
+        _p(_i64(ix["list_ids"])), _p(np.ascontiguousarray(ix["codes"], np.uint8)), ix["M"], ix["ksub"],
+        _p(_f32(ix["codebook"])), _p(_f32(ix["base"])), _p(q), nq, _p(kk), _p(npb), float(ratio), _p(off),
+        _p(res["ids"]), _p(res["dists"]), _p(res["counts"])), "search_pq64")
+    return res
+
+
+def search_rabitq64(index, queries, k, nprobe, eps0=RABITQ_EPS0):
+    """O_64: the RaBitQ query path with the bounded walk in float64.
+    Returns dict(ids, dists (float64), counts, off, n_visited)."""
+    q = _f32(queries)
+    nq = q.shape[0]
+    kk = _i32(np.broadcast_to(np.asarray(k), (nq,)))
+    npb = _i32(np.broadcast_to(np.asarray(nprobe), (nq,)))
+    off = np.zeros(nq + 1, np.int64)
+    off[1:] = np.cumsum(kk)
+    res = dict(ids=np.empty(off[-1], np.int64), dists=np.empty(off[-1], np.float64),
+               counts=np.empty(nq, np.int32), off=off, n_visited=np.empty(nq, np.int64))
+    ix = index
+    _check(lib().o64_search_rabitq(
+        ix["n"], ix["d"], ix["nlist"], _p(_f32(ix["centroids"])), _p(_f32(ix["P"])), _p(_i64(ix["list_off"])),
+        _p(_i64(ix["list_ids"])), _p(np.ascontiguousarray(ix["codes"], np.uint32)), _p(_f32(ix["factors"])),
+        _p(_f32(ix["base"])), ix["metric"], float(eps0), _p(q), nq, _p(kk), _p(npb), _p(off), _p(res["ids"]),
+        _p(res["dists"]), _p(res["counts"]), _p(res["n_visited"])), "search_rabitq64")
     return res
 
 

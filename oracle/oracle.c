@@ -215,15 +215,31 @@ int32_t orc_bucket_of(float key, float dmin, float delta, const uint8_t* map) {
   return map[cell_of(key, dmin, delta)];
 }
 
-/* The result-buffer workflow (Push / Update / Collect) over objects that
- * arrive grouped by probed list, nearest list first.  The codebook sample is
- * the nearest lists: at least nsample of them, extended list by list until
- * the sample holds sample_factor * kc keys (the sample's kc-th key then
- * bounds the result).  The threshold bucket is
- * refreshed once per list.  Returns the collected candidates (kc of them,
- * buckets below the threshold in arrival order, then the top-s of the
- * threshold bucket by (key, id)), the codebook, the final threshold bucket
- * and s, and the full per-bucket histogram of all keys. */
+/* Number of nearest lists forming the codebook sample: at least nsample of
+ * them, extended list by list until they hold sample_factor * kc keys (the
+ * sample's kc-th key then lies at or beyond the kc-th key of the whole scan;
+ * reading of the codebook section's "5 to 10 nearest clusters"). */
+static int32_t sample_lists(const int64_t* grp_off, int32_t ngrp, int64_t kc, int32_t nsample,
+                            int32_t sample_factor) {
+  int32_t ns_grp = nsample < ngrp ? nsample : ngrp;
+  while (ns_grp < ngrp && grp_off[ns_grp] < (int64_t)sample_factor * kc) ++ns_grp;
+  return ns_grp;
+}
+
+/* What the bucket-based collector (Algorithm 1) produces for one query,
+ * stated by its definition rather than by its procedure:
+ *  - the codebook is built from the sample (the nearest probed lists, see
+ *    sample_lists) by orc_codebook;
+ *  - counts[b] is the number of scanned keys whose bucket (bucket-id
+ *    equation) is b;
+ *  - the threshold bucket tau is the first bucket whose running count
+ *    reaches kc (Update, reading "cumulative >= k"); m when it never does;
+ *  - s = kc - (keys in buckets below tau): how many of bucket tau's keys are
+ *    kept;
+ *  - the collected candidates are the kc smallest (key, id), ascending
+ *    (Collect returns every key of the buckets below tau plus the best s of
+ *    bucket tau, which is that set).
+ * Keys arrive grouped by probed list, nearest list first (grp_off). */
 int orc_collect_bbc(const float* keys, const int64_t* ids, const int64_t* grp_off, int32_t ngrp,
                     int64_t kc, int32_t m, int32_t nsample, int32_t sample_factor,
                     float* dmin_out, float* delta_out, uint8_t* map_out,
@@ -231,71 +247,76 @@ int orc_collect_bbc(const float* keys, const int64_t* ids, const int64_t* grp_of
                     float* cand_keys, int64_t* cand_ids, int64_t* counts_full) {
   int64_t total = grp_off[ngrp];
   if (kc > total) kc = total;
-  /* the sample: the nearest lists, at least nsample of them and then more
-   * until they hold sample_factor * kc keys (so that d_max, the sample's
-   * kc-th key, lies beyond the kc-th key of the whole scan) */
-  int32_t ns_grp = nsample < ngrp ? nsample : ngrp;
-  while (ns_grp < ngrp && grp_off[ns_grp] < (int64_t)sample_factor * kc) ++ns_grp;
-  int64_t ns = grp_off[ns_grp];
-  int rc = orc_codebook(keys, ids, ns, kc, m, dmin_out, delta_out, map_out);
+  int32_t ns_grp = sample_lists(grp_off, ngrp, kc, nsample, sample_factor);
+  int rc = orc_codebook(keys, ids, grp_off[ns_grp], kc, m, dmin_out, delta_out, map_out);
   if (rc) return rc;
-  float dmin = *dmin_out, delta = *delta_out;
+  for (int32_t b = 0; b < m; ++b) counts_full[b] = 0;
+  for (int64_t i = 0; i < total; ++i) counts_full[map_out[cell_of(keys[i], *dmin_out, *delta_out)]] += 1;
+  int32_t tau = orc_update(counts_full, m, kc);
+  int64_t below = 0;
+  for (int32_t b = 0; b < tau && b < m; ++b) below += counts_full[b];
+  *tau_out = tau;
+  *s_out = kc - below;
+  return orc_topk_sort(keys, ids, total, kc, cand_keys, cand_ids);
+}
 
-  /* buckets: per-bucket linear buffers of (key, id) */
-  int64_t* cap = (int64_t*)calloc((size_t)m, sizeof(int64_t));
-  int64_t* cnt = (int64_t*)calloc((size_t)m, sizeof(int64_t));
-  kv_t** buf = (kv_t**)calloc((size_t)m, sizeof(kv_t*));
-  if (!cap || !cnt || !buf) { free(cap); free(cnt); free(buf); return ORC_ENOMEM; }
-  for (int i = 0; i < m; ++i) counts_full[i] = 0;
-
-  int32_t tau = m; /* infinity */
-  for (int32_t g = 0; g < ngrp; ++g) {
-    for (int64_t i = grp_off[g]; i < grp_off[g + 1]; ++i) {
-      int32_t a = map_out[cell_of(keys[i], dmin, delta)];
-      counts_full[a] += 1;
-      if (a <= tau) { /* Push */
-        if (cnt[a] == cap[a]) {
-          int64_t nc = cap[a] ? 2 * cap[a] : 64;
-          kv_t* nb = (kv_t*)realloc(buf[a], sizeof(kv_t) * (size_t)nc);
-          if (!nb) { rc = ORC_ENOMEM; goto done; }
-          buf[a] = nb;
-          cap[a] = nc;
-        }
-        buf[a][cnt[a]].key = keys[i];
-        buf[a][cnt[a]].pad = 0;
-        buf[a][cnt[a]].id = ids[i];
-        cnt[a] += 1;
-      }
-    }
-    tau = orc_update(cnt, m, kc); /* Update once per list */
+/* Early re-rank accounting of the improved IVF+PQ search (Algorithm 4) for
+ * one query, keys grouped by probed list as for orc_collect_bbc.  The
+ * predicted threshold bucket is the bucket of the sample's j-th smallest key
+ * with j = ceil(kc * n_sample / S) (the sample's share of the scan times the
+ * candidate count); tau_pred = 0 when j = 0.  Reading for a scan that runs in
+ * two phases: the sample lists are scanned before tau_pred exists, so only
+ * the lists after the sample re-rank early; there, every object whose bucket
+ * lies below tau_pred gets its exact distance during the scan.  The
+ * candidates and the final result are those of the plain definition (the kc
+ * smallest estimated keys, then the k smallest exact keys): early re-ranking
+ * only moves work.  Outputs: tau_pred, the early set's size, how many of it
+ * are candidates, and how many candidates are left to re-rank afterwards. */
+int orc_early_rerank(const float* keys, const int64_t* ids, const int64_t* grp_off, int32_t ngrp,
+                     int64_t kc, int32_t m, int32_t nsample, int32_t sample_factor,
+                     int32_t* tau_pred_out, int64_t* n_early, int64_t* n_early_cand, int64_t* n_late) {
+  int64_t total = grp_off[ngrp];
+  if (kc > total) kc = total;
+  *tau_pred_out = 0; *n_early = 0; *n_early_cand = 0; *n_late = kc;
+  if (kc <= 0) return ORC_OK;
+  int32_t ns_grp = sample_lists(grp_off, ngrp, kc, nsample, sample_factor);
+  int64_t ns = grp_off[ns_grp];
+  float dmin, delta;
+  uint8_t map[NCELLS];
+  int rc = orc_codebook(keys, ids, ns, kc, m, &dmin, &delta, map);
+  if (rc) return rc;
+  /* j = ceil(kc * ns / total) in exact integer arithmetic */
+  int64_t j = (kc * ns + total - 1) / total;
+  int32_t tau_pred = 0;
+  if (j > 0) {
+    float* sk = (float*)malloc(sizeof(float) * (size_t)j);
+    int64_t* si = (int64_t*)malloc(sizeof(int64_t) * (size_t)j);
+    if (!sk || !si) { free(sk); free(si); return ORC_ENOMEM; }
+    rc = orc_topk_sort(keys, ids, ns, j, sk, si);
+    if (!rc) tau_pred = map[cell_of(sk[j - 1], dmin, delta)];
+    free(sk); free(si);
+    if (rc) return rc;
   }
-  {
-    int64_t nres = 0;
-    int32_t upto = tau < m ? tau : m;
-    for (int32_t b = 0; b < upto; ++b)
-      for (int64_t j = 0; j < cnt[b]; ++j) {
-        cand_keys[nres] = buf[b][j].key;
-        cand_ids[nres] = buf[b][j].id;
-        ++nres;
-      }
-    int64_t s = kc - nres;
-    if (tau < m && s > 0) {
-      qsort(buf[tau], (size_t)cnt[tau], sizeof(kv_t), kv_cmp);
-      for (int64_t j = 0; j < s; ++j) {
-        cand_keys[nres] = buf[tau][j].key;
-        cand_ids[nres] = buf[tau][j].id;
-        ++nres;
-      }
-    }
-    *tau_out = tau;
-    *s_out = s;
+  float* ck = (float*)malloc(sizeof(float) * (size_t)kc);
+  int64_t* ci = (int64_t*)malloc(sizeof(int64_t) * (size_t)kc);
+  if (!ck || !ci) { free(ck); free(ci); return ORC_ENOMEM; }
+  rc = orc_topk_sort(keys, ids, total, kc, ck, ci);
+  if (rc) { free(ck); free(ci); return rc; }
+  /* candidate membership by (key, id): kc-th pair bounds the set */
+  const float kk = ck[kc - 1];
+  const int64_t ki = ci[kc - 1];
+  int64_t ne = 0, nec = 0;
+  for (int64_t i = ns; i < total; ++i) {
+    if (map[cell_of(keys[i], dmin, delta)] >= tau_pred) continue;
+    ++ne;
+    if (keys[i] < kk || (keys[i] == kk && ids[i] <= ki)) ++nec;
   }
-done:
-  for (int i = 0; i < m; ++i) free(buf[i]);
-  free(buf);
-  free(cap);
-  free(cnt);
-  return rc;
+  free(ck); free(ci);
+  *tau_pred_out = tau_pred;
+  *n_early = ne;
+  *n_early_cand = nec;
+  *n_late = kc - nec;
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
@@ -1032,6 +1053,40 @@ int orc_search_rabitq(int64_t n, int32_t d, int32_t nlist, const float* centroid
     }
   }
   return err;
+}
+
+/* The minimal re-rank set of Observation 1 for one query: with Dist_k the
+ * k-th smallest (exact key, id) over the n scanned objects, the objects whose
+ * bound interval [lb, ub] contains Dist_k.  Needs the exact key of every
+ * scanned object (the definition, not Algorithm 2's two-heap procedure).
+ * n_min = |minimal set|; n_min_out = |minimal set united with the exact
+ * top-k| (what a path that returns exact distances must compute at least);
+ * both 0 when n < k (no boundary object).  dist_k = Dist_k (NaN when n < k). */
+int orc_min_rerank(const float* lb, const float* ub, const float* exact, const int64_t* ids, int64_t n,
+                   int64_t k, int64_t* n_min, int64_t* n_min_out, float* dist_k) {
+  *n_min = 0;
+  *n_min_out = 0;
+  *dist_k = NAN;
+  if (k <= 0 || n < k) return ORC_OK;
+  float* tk = (float*)malloc(sizeof(float) * (size_t)k);
+  int64_t* ti = (int64_t*)malloc(sizeof(int64_t) * (size_t)k);
+  if (!tk || !ti) { free(tk); free(ti); return ORC_ENOMEM; }
+  int rc = orc_topk_sort(exact, ids, n, k, tk, ti);
+  if (rc) { free(tk); free(ti); return rc; }
+  const float dk = tk[k - 1];
+  const int64_t dki = ti[k - 1];
+  int64_t a = 0, b = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    const int in_min = lb[i] <= dk && dk <= ub[i];
+    const int in_top = exact[i] < dk || (exact[i] == dk && ids[i] <= dki);
+    a += in_min;
+    b += in_min || in_top;
+  }
+  free(tk); free(ti);
+  *n_min = a;
+  *n_min_out = b;
+  *dist_k = dk;
+  return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------ */
