@@ -35,6 +35,41 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_TFLOPS = 39.3
 
 
+# LDS read peak: 256 CUs x 128 bytes per clock (32 banks of 4 bytes) x 2.4 GHz
+LDS_PEAK_GBS = 256 * 128 * 2.4
+# last-level (Infinity) cache: a code array that fits is served from it once warm
+CACHE_BYTES = 256 << 20
+
+
+def scan_entry(kernel, avg_ms, code_bytes_pl, lds_bytes_pl, traffic, codes_total_bytes):
+    """Roofline entry of a PQ code scan.  Two algorithmic byte counts per
+    launch: the code bytes read (one code row per (query, object)) and the
+    table bytes gathered from LDS (4 bytes per (query, sub-space, object)).
+    When the index's code array fits in the last-level cache the codes are
+    cache-served and the scan is held against the LDS roof; otherwise the
+    bound is the roof of which the scan reaches the larger fraction.  The
+    HBM bytes the counters measured (`traffic`) are reported beside it."""
+    sec = avg_ms * 1e-3
+    code_rate = code_bytes_pl / sec / 1e9
+    lds_rate = lds_bytes_pl / sec / 1e9
+    cache_served = codes_total_bytes <= CACHE_BYTES
+    hbm_frac, lds_frac = code_rate / HBM_PEAK_GBS, lds_rate / LDS_PEAK_GBS
+    if cache_served or lds_frac >= hbm_frac:
+        bound, achieved, peak, alg = "lds", lds_rate, LDS_PEAK_GBS, lds_bytes_pl
+    else:
+        bound, achieved, peak, alg = "hbm", code_rate, HBM_PEAK_GBS, code_bytes_pl
+    e = {"kernel": kernel, "bound": bound, "achieved": round(achieved, 1), "peak": round(peak, 1), "unit": "GB/s",
+         "frac": round(achieved / peak, 4), "traffic": traffic, "avg_launch_ms": round(avg_ms, 4),
+         "algorithmic_bytes_per_launch": int(alg),
+         "code_bytes_per_launch": int(code_bytes_pl), "code_bytes_rate_gbs": round(code_rate, 1),
+         "lds_table_bytes_per_launch": int(lds_bytes_pl), "lds_frac": round(lds_frac, 4),
+         "codes_cache_served": cache_served}
+    if traffic:
+        e["hbm_traffic_rate_gbs"] = round(traffic / sec / 1e9, 1)
+        e["hbm_traffic_frac"] = round(traffic / sec / 1e9 / HBM_PEAK_GBS, 4)
+    return e
+
+
 def rerank_tile_form(d: int) -> bool:
     """Whether the PQ re-rank runs tile-major (rows of at most 32 chunks)."""
     return d % 4 == 0 and d <= 128 and os.environ.get("BBC_RERANK_FORM", "0") == "0"
@@ -99,10 +134,12 @@ def recall_at_k(ids, off, gt, k):
     return float(sum(r) / len(r))
 
 
-def ground_truth(torch, x_gpu64, q, kmax, metric=0):
+def ground_truth(torch, x_gpu64, q, kmax, metric=0, keep_on_device=False):
     """Exact float64 k nearest (evaluation only): squared L2, or the largest
-    inner products for metric 1."""
-    out = []
+    inner products for metric 1.  Returns the ids [nq, kmax] (numpy), or,
+    with keep_on_device, (ids, keys) as device tensors (keys: squared L2, or
+    -<q, x>)."""
+    ids, keys = [], []
     xn = (x_gpu64 * x_gpu64).sum(1)
     for s in range(0, q.shape[0], 50):
         qq = torch.from_numpy(q[s:s + 50]).to(x_gpu64.device, torch.float64)
@@ -110,9 +147,87 @@ def ground_truth(torch, x_gpu64, q, kmax, metric=0):
             d = xn[None, :] - 2.0 * (qq @ x_gpu64.T) + (qq * qq).sum(1)[:, None]
         else:
             d = -(qq @ x_gpu64.T)
-        out.append(torch.topk(d, kmax, dim=1, largest=False).indices.cpu().numpy())
+        t = torch.topk(d, kmax, dim=1, largest=False, sorted=True)
+        if keep_on_device:
+            ids.append(t.indices)
+            keys.append(t.values)
+        else:
+            ids.append(t.indices.cpu().numpy())
+    if keep_on_device:
+        return torch.cat(ids), torch.cat(keys)
     import numpy as np
-    return np.concatenate(out)
+    return np.concatenate(ids)
+
+
+def recall_device(torch, ids, gt_ids, k):
+    """Mean recall@k of result ids [nq * k] (device, -1 pads never match)
+    against ground-truth ids [nq, >= k] (device)."""
+    nq = gt_ids.shape[0]
+    got = ids.view(nq, k)
+    hits = 0
+    for s in range(0, nq, 256):
+        g = torch.sort(gt_ids[s:s + 256, :k], dim=1).values
+        r = got[s:s + 256]
+        pos = torch.searchsorted(g, r).clamp_(max=k - 1)
+        hits += int((torch.gather(g, 1, pos) == r).sum())
+    return hits / (nq * k)
+
+
+def distance_errors(torch, x64, q, ids, dists, k, gt_keys, metric=0):
+    """Distance error of the returned results against float64 (evaluation):
+     - fp32: |d32 - d64| / |d64| over the returned (id, distance) pairs, with
+       d64 the float64 distance of the same id (the float32 path's rounding);
+     - rel_err: the relative-error measure of the paper's experiments, the
+       mean over queries of (1/k) sum_i |D_i - D*_i| / D*_i with D_i the
+       float64 distance of the i-th returned object and D*_i that of the i-th
+       true neighbour, on non-squared L2 distances (|<q, x>| for IP).
+    ids/dists: [nq * k] device tensors; gt_keys: [nq, >= k] float64 keys."""
+    nq = gt_keys.shape[0]
+    ids = ids.view(nq, k)
+    dists = dists.view(nq, k)
+    fmax, fsum, fn, rel_q = 0.0, 0.0, 0, []
+    dev = x64.device
+    for s in range(0, nq, 16):
+        qq = torch.from_numpy(q[s:s + 16]).to(dev, torch.float64)
+        i = ids[s:s + 16]
+        valid = i >= 0
+        rows = x64[i.clamp(min=0)]
+        if metric == 0:
+            d64 = ((rows - qq[:, None, :]) ** 2).sum(-1)
+        else:
+            d64 = (rows * qq[:, None, :]).sum(-1)
+        d32 = dists[s:s + 16].to(torch.float64)
+        den = d64.abs().clamp_min(1e-300)
+        fe = ((d32 - d64).abs() / den)[valid]
+        if fe.numel():
+            fmax = max(fmax, float(fe.max()))
+            fsum += float(fe.sum())
+            fn += int(fe.numel())
+        g = gt_keys[s:s + 16, :k]
+        if metric == 0:
+            a, b = d64.clamp_min(0).sqrt(), g.clamp_min(0).sqrt()
+        else:
+            a, b = d64.abs(), g.abs()
+        r = ((a - b).abs() / b.clamp_min(1e-300))
+        r = torch.where(valid, r, torch.zeros_like(r))
+        rel_q.append(r.sum(1) / valid.sum(1).clamp_min(1))
+    rel = torch.cat(rel_q)
+    return {"fp32_vs_fp64_max": fmax, "fp32_vs_fp64_mean": fsum / max(1, fn), "rel_err_mean": float(rel.mean()),
+            "rel_err_max_query": float(rel.max())}
+
+
+def host_cpu():
+    """Host CPU model name and logical core count."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
 
 
 def main():
@@ -130,6 +245,8 @@ def main():
     ap.add_argument("--ratio", type=str, default="", help="fixed r per k, e.g. 2,2 (skips the sweep)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-queries", type=int, default=3000)
+    ap.add_argument("--cpu-queries-1t", type=int, default=200, help="oracle queries timed on one thread")
+    ap.add_argument("--o64-queries", type=int, default=100, help="queries searched by the float64 oracle O_64")
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
     ap.add_argument("--serve-qps", type=float, default=0.0, help="serving: arrival rate (default: the workload's)")
     ap.add_argument("--serve-seconds", type=float, default=None, help="serving: stream length (default: the workload's)")
@@ -195,11 +312,14 @@ def main():
     # ---- recall operating point ---------------------------------------------
     rq = q[: args.recall_queries]
     gt = None
+    x64 = torch.from_numpy(x).to(dev, torch.float64)
+    t0 = time.time()
+    # float64 exact kNN of the whole batch (evaluation: recall and distance
+    # error are computed over every query)
+    gt_full_ids, gt_full_keys = ground_truth(torch, x64, q, max(ks), keep_on_device=True)
+    log(f"float64 ground truth of {nq} queries in {time.time() - t0:.1f}s")
     if args.recall_queries > 0:
-        x64 = torch.from_numpy(x).to(dev, torch.float64)
-        gt = ground_truth(torch, x64, rq, max(ks))
-        del x64
-        torch.cuda.empty_cache()
+        gt = gt_full_ids[: args.recall_queries].cpu().numpy()
     elif not (args.nprobe and args.ratio):
         raise SystemExit("--recall-queries 0 needs a fixed operating point (--nprobe and --ratio)")
     nprobe_grid = [64, 96, 128, 160, 192, 256]
@@ -226,16 +346,25 @@ def main():
                     break
         if not cands:
             raise SystemExit(f"recall {args.target_recall} not reached for k={k}")
-        best = None
-        for c in cands:  # one timed full batch per candidate, the fastest wins
+        for c in cands:  # one timed full batch per candidate
             index.search(qd, k, c["nprobe"], ratio=c["ratio"])
             torch.cuda.synchronize()
             t = time.perf_counter()
             index.search(qd, k, c["nprobe"], ratio=c["ratio"])
             torch.cuda.synchronize()
             c["probe_ms"] = (time.perf_counter() - t) * 1e3
-            if best is None or c["probe_ms"] < best["probe_ms"]:
+        # the fastest candidate whose recall over the whole batch reaches the
+        # target (the sweep's sample only shortlists)
+        best = None
+        for c in sorted(cands, key=lambda c: c["probe_ms"]):
+            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"])
+            torch.cuda.synchronize()
+            c["recall_batch"] = recall_device(torch, o[0], gt_full_ids, k)
+            if c["recall_batch"] >= args.target_recall:
                 best = c
+                break
+        if best is None:
+            best = max(cands, key=lambda c: c["recall_batch"])
         op[k] = best
         log(f"k={k}: candidates {cands} -> {best}")
 
@@ -278,10 +407,15 @@ def main():
     per_k = {}
     for k in ks:
         arr = np.array(lat[k])
-        rec = op[k]["recall"]
-        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], recall=None if rec is None else round(rec, 4),
+        # recall and distance error of the last timed step's results, every query
+        rec = recall_device(torch, outs[k][0], gt_full_ids, k)
+        derr = distance_errors(torch, x64, q, outs[k][0], outs[k][1], k, gt_full_keys)
+        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], recall=round(rec, 4),
+                             recall_queries=nq, recall_target_reached=rec >= args.target_recall,
+                             dist_err={n: float(f"{v:.3e}") for n, v in derr.items()},
                              qps=round(nq / (arr.mean() / 1e3), 1), batch_ms_p50=round(float(np.percentile(arr, 50)), 3),
                              batch_ms_p99=round(float(np.percentile(arr, 99)), 3))
+        log(f"k={k}: recall over {nq} queries {rec:.4f}, distance error {derr}")
 
     # ---- collector comparison: same batch, same operating point ---------------
     collectors = {}
@@ -353,6 +487,11 @@ def main():
             kc_pl = sum(sizes[k]["Kc"] for k in ks) * args.steps / st["launches"]
             entries[name] = rerank_entry(avg_ms, kc_pl, d)
             continue
+        if name in ("scan", "sample_scan"):
+            entries[name] = scan_entry(kernels[name][0], avg_ms, bytes_per_launch,
+                                       bytes_per_launch / code_bytes * w.pq_m * 4,
+                                       measured_traffic(w.name, name, kernels[name][1]), w.n * code_bytes)
+            continue
         entries[name] = {"kernel": kernels[name][0], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                          "traffic": measured_traffic(w.name, name, kernels[name][1]),
@@ -362,23 +501,69 @@ def main():
     others = {n: e for n, e in entries.items() if n != dominant}
     stage_ms = {s: round(v["ms"] / max(1, args.steps), 4) for s, v in stages.items()}
 
-    # ---- oracle CPU baseline ----------------------------------------------------
+    # ---- oracle CPU baseline, and the oracle's verdict on the GPU results ------
     cpu = None
+    oracle_match = None
+    fp64_oracle = None
     if not args.no_cpu:
         import oracle
         t0 = time.time()
         oix = oracle.build_ivf_pq(x, w.nlist, w.pq_m, w.pq_bits, tr, ip, pr, pi, w.kmeans_iters)
         log(f"oracle index build {time.time() - t0:.1f}s")
+        # the oracle searches its own build; the GPU searched the GPU build:
+        # the comparison below needs them to be the same index
+        build_same = bool(np.array_equal(index.get(bbc.FIELD_CENTROIDS), oix["centroids"])
+                          and np.array_equal(index.get(bbc.FIELD_LIST_IDS), oix["list_ids"])
+                          and np.array_equal(index.get(bbc.FIELD_CODEBOOK), oix["codebook"])
+                          and np.array_equal(index.get(bbc.FIELD_CODES), oix["codes"]))
         nqc = min(args.cpu_queries, nq)
+        oracle.set_threads(0)
         t_cpu = 0.0
+        mism_ids = mism_d = 0
         for k in ks:
             t0 = time.perf_counter()
-            oracle.search_pq(oix, q[:nqc], k, op[k]["nprobe"], op[k]["ratio"])
+            ref = oracle.search_pq(oix, q[:nqc], k, op[k]["nprobe"], op[k]["ratio"])
             t_cpu += time.perf_counter() - t0
-        cpu = {"value": round(nqc * len(ks) / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(),
-               "kind": "oracle",
-               "sample": f"first {nqc} queries of the batch at each k in {ks}, same nprobe/r operating point, "
-                         f"oracle-built index; {t_cpu:.1f}s of CPU work"}
+            gi = outs[k][0][: nqc * k].cpu().numpy().reshape(nqc, k)
+            gd = outs[k][1][: nqc * k].cpu().numpy().reshape(nqc, k)
+            gc = outs[k][2][:nqc].cpu().numpy()
+            ri, rd = ref["ids"].reshape(nqc, k), ref["dists"].reshape(nqc, k)
+            mism_ids += int(np.sum(np.any(ri != gi, axis=1) | (ref["counts"] != gc)))
+            mism_d += int(np.sum(np.any(rd.view(np.uint32) != gd.view(np.uint32), axis=1)))
+        threads = oracle.num_threads()
+        # one thread, on a shorter sample
+        n1 = max(1, min(nqc, args.cpu_queries_1t))
+        oracle.set_threads(1)
+        t1 = 0.0
+        for k in ks:
+            t0 = time.perf_counter()
+            oracle.search_pq(oix, q[:n1], k, op[k]["nprobe"], op[k]["ratio"])
+            t1 += time.perf_counter() - t0
+        oracle.set_threads(0)
+        model, ncpu = host_cpu()
+        cpu = {"value": round(nqc * len(ks) / t_cpu, 2), "unit": "queries/s", "cores": threads,
+               "kind": "oracle", "value_1_thread": round(n1 * len(ks) / t1, 2), "cpu_model": model,
+               "host_logical_cpus": ncpu,
+               "sample": f"first {nqc} queries of the batch at each k in {ks} on {threads} threads ({t_cpu:.1f}s), "
+                         f"first {n1} on 1 thread ({t1:.1f}s); same nprobe/r operating point, oracle-built index"}
+        oracle_match = {"queries": nqc * len(ks), "index_build_identical": build_same,
+                        "queries_with_different_ids": mism_ids, "queries_with_different_dists": mism_d,
+                        "match": build_same and mism_ids == 0 and mism_d == 0,
+                        "what": "ids, counts and float32 distance bits of the GPU's timed-step results against "
+                                "the oracle on the same queries"}
+        log(f"oracle match {oracle_match}")
+        # O_64, the float64 shadow of the path, on a few queries
+        n64 = min(args.o64_queries, nq)
+        if n64 > 0:
+            agree = []
+            for k in ks:
+                r64 = oracle.search_pq64(oix, q[:n64], k, op[k]["nprobe"], op[k]["ratio"])
+                gi = outs[k][0][: n64 * k].cpu().numpy().reshape(n64, k)
+                i64 = r64["ids"].reshape(n64, k)
+                agree.append(float(np.mean([len(np.intersect1d(gi[j], i64[j])) / k for j in range(n64)])))
+            fp64_oracle = {"queries": n64 * len(ks), "id_overlap_per_k": dict(zip(map(str, ks), agree)),
+                           "what": "mean |GPU ids & O_64 ids| / k: the same path run in float64"}
+            log(f"O_64 {fp64_oracle}")
 
     res = {
         "metric": METRIC, "value": round(value, 1), "unit": "queries/s", "n_gpus": 1, "steps": args.steps,
@@ -396,6 +581,8 @@ def main():
         "roofline": roof,
         "roofline_other_kernels": others,
         "cpu_baseline": cpu,
+        "oracle_match": oracle_match,
+        "fp64_oracle": fp64_oracle,
         "build_s": round(build_s, 2),
     }
     print(json.dumps(res), flush=True)
@@ -510,6 +697,11 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         gbs = bpl / (avg_ms * 1e-3) / 1e9
         if name == "rerank" and rerank_tile_form(w.d):
             entries[name] = rerank_entry(avg_ms, Kc * args.steps / st["launches"], w.d)
+            continue
+        if name == "scan":
+            src = [os.path.join(CSRC, f) for f in ("pq_scan.hip", "common.h", "kernels.h")]
+            entries[name] = scan_entry(names[name], avg_ms, bpl, bpl / code_bytes * w.pq_m * 4,
+                                       measured_traffic(w.name, name, src), w.n * code_bytes)
             continue
         entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,

@@ -24,6 +24,12 @@
  *    it passes; the library copies what it keeps and holds no caller pointer
  *    after a call returns.
  *  - Floating-point inputs must be finite (BBC_EINVAL otherwise).
+ *  - One index may be searched from several threads and on several streams
+ *    at once.  The host side of each call is serialised per index; searches
+ *    without a caller workspace share the index's device workspace, and each
+ *    such search makes its stream wait for the previous one's use of it, so
+ *    they never overlap on the device (plans and servers own their
+ *    workspaces and run concurrently with them).
  */
 #ifndef BBC_H_
 #define BBC_H_
@@ -177,6 +183,15 @@ typedef struct {
   float* est_lb; float* est_ub;              /* RaBitQ: [sum S] bounds in the est_keys order */
   int64_t* n_visited;                        /* RaBitQ: [nq] exact distances computed (the objects the
                                                 bounded walk visited; all of C in the wide form) */
+  int32_t* kernel_forms;                     /* [4] kernel variants the batch ran: codebook sample slots
+                                                per thread (16, 32, 48; 0 = sample read from memory;
+                                                -1 = none), final top-k candidates per thread (8, 16,
+                                                24, 32; 0 = memory form), RaBitQ scan grid (1 = one
+                                                block per pair on a 1-D grid, 2 = 2-D grid, 3 = pairs
+                                                grouped by list; -1 = none), 0 */
+  int32_t* walk_path;                        /* RaBitQ: [nq] how the bounded walk found its exact stop
+                                                point: 0 no search, 1 in LDS, 2 in global memory,
+                                                3 item-by-item walk (a bound check failed) */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and

@@ -95,6 +95,7 @@ def lib():
             L.o64_search_rabitq.argtypes = [i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, i32, f64,
                                             vp, i64, vp, vp, vp, vp, vp, vp, vp]
             L.orc_num_threads.restype = C.c_int
+            L.orc_set_threads.argtypes = [i32]
             _lib = L
     return _lib
 
@@ -118,6 +119,11 @@ def _check(rc: int, what: str):
 
 def num_threads() -> int:
     return int(lib().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Threads of the oracle's loops over queries (n < 1: all host cores)."""
+    lib().orc_set_threads(int(n))
 
 
 # --------------------------------------------------------------------------

@@ -1128,6 +1128,15 @@ int orc_exact_knn64(const float* base, int64_t n, int32_t d, const float* querie
   return err;
 }
 
+/* Threads of the OpenMP loops over queries (n < 1: all host cores). */
+void orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+  omp_set_num_threads(n >= 1 ? n : omp_get_num_procs());
+#else
+  (void)n;
+#endif
+}
+
 int orc_num_threads(void) {
 #ifdef _OPENMP
   return omp_get_max_threads();

@@ -60,7 +60,8 @@ class SearchTrace(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
         "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off",
-        "n_sample_lists", "n_survivors", "n_sample_keys", "est_lb", "est_ub", "n_visited")]
+        "n_sample_lists", "n_survivors", "n_sample_keys", "est_lb", "est_ub", "n_visited", "kernel_forms",
+        "walk_path")]
 
 
 _lib = None
@@ -424,13 +425,16 @@ class Index:
             dmin=np.empty(nq, np.float32), delta=np.empty(nq, np.float32), map=np.empty((nq, 256), np.uint8),
             tau=np.empty(nq, np.int32), s=np.empty(nq, np.int64), bucket_counts=np.empty((nq, m), np.int32),
             n_boundary=np.empty(nq, np.int64), est_off=np.zeros(nq + 1, np.int64),
-            cand_off=np.zeros(nq + 1, np.int64))
+            cand_off=np.zeros(nq + 1, np.int64), n_sample_keys=np.zeros(nq, np.int64),
+            n_survivors=np.zeros(nq, np.int64), kernel_forms=np.full(4, -9, np.int32))
         rabitq = self.quant == QUANT_RABITQ
         if rabitq:
             r["n_visited"] = np.empty(nq, np.int64)
+            r["walk_path"] = np.full(nq, -1, np.int32)
         tr = SearchTrace(**{f: _ptr(r[f]) for f in (
             "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
-            "bucket_counts", "n_boundary", "est_off", "cand_off") + (("n_visited",) if rabitq else ())})
+            "bucket_counts", "n_boundary", "est_off", "cand_off", "n_sample_keys", "n_survivors", "kernel_forms")
+            + (("n_visited", "walk_path") if rabitq else ())})
         _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                    _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
         # second pass for the ragged arrays, now that their sizes are known

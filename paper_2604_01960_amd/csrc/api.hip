@@ -61,21 +61,25 @@ bool all_finite(const float* p, int64_t n) {
   return true;
 }
 
-// Grow-only device arena for per-call scratch.
+// Grow-only device arena for per-call scratch.  `done` is recorded on the
+// stream of each search after its last use of the arena, and the next search
+// makes its own stream wait for it, so searches on different streams never
+// overlap on the arena; growing it waits for that last use only (no
+// device-wide synchronisation).
 struct Arena {
   char* base = nullptr;
   size_t cap = 0;
-  size_t used = 0;
+  hipEvent_t done = nullptr;
   hipError_t reserve(size_t bytes) {
     if (bytes <= cap) return hipSuccess;
+    size_t want = std::max(bytes, cap + cap / 2);
     if (base) {
-      hipError_t e = hipDeviceSynchronize();
+      hipError_t e = done ? hipEventSynchronize(done) : hipDeviceSynchronize();
       if (e != hipSuccess) return e;
       hipFree(base);
       base = nullptr;
       cap = 0;
     }
-    size_t want = std::max(bytes, cap + cap / 2);
     hipError_t e = hipMalloc(reinterpret_cast<void**>(&base), want);
     if (e != hipSuccess) {
       base = nullptr;
@@ -86,6 +90,9 @@ struct Arena {
     cap = want;
     return hipSuccess;
   }
+  // order a search on stream s after the previous search's use of the arena
+  hipError_t acquire(hipStream_t s) { return done ? hipStreamWaitEvent(s, done, 0) : hipSuccess; }
+  hipError_t release(hipStream_t s) { return done ? hipEventRecord(done, s) : hipSuccess; }
 };
 
 // Simple layout planner: offsets of 256-byte aligned sub-buffers.
@@ -173,6 +180,9 @@ struct bbc_index {
   int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide, 3 wide with tile-major keys)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
+  int walk_qcap = 0;        // RaBitQ walk: objects above the k-th exact key resolved in LDS (BBC_WALK_QCAP:
+                            // a power of two, 64..4096; 0 = the LDS capacity)
+  int rq_scan_1d = 0;       // RaBitQ scan on a 1-D grid of pairs (BBC_RQ_SCAN_1D; taken anyway beyond 65535 queries)
   int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
   int64_t rt_sort_bins = (int64_t)1 << 30;  // tile-major sort: most bin counters (BBC_RERANK_SORT_BINS)
   // RaBitQ tile-major keys: C put in tile order by the walk's bin pass (1) or
@@ -209,6 +219,7 @@ void index_release(bbc_index* ix) {
   hipFree(ix->codebook); hipFree(ix->vectors);
   hipFree(ix->rq_codes); hipFree(ix->rq_factors); hipFree(ix->rot); hipFree(ix->rot_cent);
   if (ix->arena.base) hipFree(ix->arena.base);
+  if (ix->arena.done) hipEventDestroy(ix->arena.done);
   if (ix->pinned) hipHostFree(ix->pinned);
   if (ix->meta_done) hipEventDestroy(ix->meta_done);
   delete ix;
@@ -301,7 +312,13 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
     const int x = std::atoi(sv);
     if (x >= 64 && x <= 4096 && (x & (x - 1)) == 0) ix->collect_bcap = x;
   }
+  if (const char* sv = std::getenv("BBC_WALK_QCAP")) {
+    const int x = std::atoi(sv);
+    if (x >= 64 && x <= 4096 && (x & (x - 1)) == 0) ix->walk_qcap = x;
+  }
+  if (const char* sv = std::getenv("BBC_RQ_SCAN_1D")) ix->rq_scan_1d = std::atoi(sv) == 1;
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
+  HIP_TRY(hipEventCreateWithFlags(&ix->arena.done, hipEventDisableTiming));
   return BBC_OK;
 }
 
@@ -749,7 +766,39 @@ struct SearchCtx {
   int64_t* work_out = nullptr;  // [2][nq]: codes scanned, exact distances computed
   bool capture = false;
   hipGraph_t graph = nullptr;
+  // fixed pinned staging for the metadata block (allocation-free searches):
+  // used instead of the index's growable pinned buffer when set
+  char* meta_host = nullptr;
+  size_t meta_cap = 0;
+  hipEvent_t meta_ev = nullptr;
 };
+
+// Host staging of a search's metadata block: the caller-given fixed buffer,
+// or the index's pinned buffer (grown when too small).  Waits until the
+// previous upload out of that buffer is done before it is rewritten.
+int32_t stage_meta(bbc_index* ix, const SearchCtx* ctx, size_t bytes, char** H, hipEvent_t* ev) {
+  if (ctx && ctx->meta_host) {
+    if (bytes > ctx->meta_cap)
+      return fail(BBC_EINVAL, "the batch's metadata (" + std::to_string(bytes) +
+                                  " bytes) exceeds the allocation-free staging buffer (" +
+                                  std::to_string(ctx->meta_cap) + " bytes)");
+    HIP_TRY(hipEventSynchronize(ctx->meta_ev));
+    *H = ctx->meta_host;
+    *ev = ctx->meta_ev;
+    return BBC_OK;
+  }
+  HIP_TRY(hipEventSynchronize(ix->meta_done));
+  if (ix->pinned_cap < bytes) {
+    if (ix->pinned) hipHostFree(ix->pinned);
+    ix->pinned = nullptr;
+    ix->pinned_cap = 0;
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ix->pinned), bytes * 2));
+    ix->pinned_cap = bytes * 2;
+  }
+  *H = ix->pinned;
+  *ev = ix->meta_done;
+  return BBC_OK;
+}
 
 // Tile counts of the largest lists for tiles of 1 << ts rows: h_maxT[p] =
 // sum of the p largest ceil(size / 2^ts), a bound on the bins of a query
@@ -844,6 +893,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const size_t L_key = tracing ? pl.add(4 * nkeys) : 0;
   const size_t L_cbuf = pl.add(4 * nkeys), L_cp = pl.add(8 * nkeys), L_z = pl.add(16 * nkeys);
   const size_t L_nc = pl.add(8 * nq), L_nv = pl.add(8 * nq);
+  const size_t L_qp = tracing ? pl.add(4 * nq) : 0;
   // the wide re-rank form when the batch alone leaves compute units idle
   // with one block per query, or when its keys come tile-major
   const bool wide = ix->walk_form == 2 || tile_keys || (ix->walk_form == 0 && nq <= ix->num_cu);
@@ -875,17 +925,11 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   } else {
     HIP_TRY(ix->arena.reserve(pl.total));
     A = ix->arena.base;
+    HIP_TRY(ix->arena.acquire(s));
   }
-  if (ix->pinned_cap < mp.total) {
-    HIP_TRY(hipEventSynchronize(ix->meta_done));
-    if (ix->pinned) hipHostFree(ix->pinned);
-    ix->pinned = nullptr;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ix->pinned), mp.total * 2));
-    ix->pinned_cap = mp.total * 2;
-  } else {
-    HIP_TRY(hipEventSynchronize(ix->meta_done));
-  }
-  char* H = ix->pinned;
+  char* H = nullptr;
+  hipEvent_t meta_ev = nullptr;
+  if ((rc = stage_meta(ix, ctx, mp.total, &H, &meta_ev))) return rc;
   std::memcpy(H + m_k, k, 4 * nq);
   std::memcpy(H + m_np, nprobe, 4 * nq);
   std::memcpy(H + m_po, probe_off.data(), 8 * (nq + 1));
@@ -899,7 +943,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     t_capturing = true;
   } else {
     HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(ix->meta_done, s));
+    HIP_TRY(hipEventRecord(meta_ev, s));
   }
   const float* dq = queries;
   if (host_io) {
@@ -959,6 +1003,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   sa.rank_off = pa.rank_off; sa.key_off = d_ko; sa.q = dq; sa.qrot = qrot; sa.rot_cent = ix->rot_cent;
   sa.D = d; sa.metric = ix->metric; sa.eps0 = ix->eps0; sa.list_off = ix->list_off; sa.codes = ix->rq_codes;
   sa.code_words = ix->rq_words; sa.factors = ix->rq_factors;
+  sa.force_1d = ix->rq_scan_1d;
   sa.max_np = 1;
   for (int64_t i = 0; i < nq; ++i) sa.max_np = std::max(sa.max_np, (int)nprobe[i]);
   sa.lb = reinterpret_cast<float*>(A + L_lb);
@@ -984,6 +1029,8 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   wa.q = dq; wa.vectors = ix->vectors; wa.fp16 = ix->fp16; wa.D = d; wa.metric = ix->metric;
   wa.wide = wide ? 1 : 0;
   wa.max_c = max_cap;
+  wa.qcap = ix->walk_qcap;
+  wa.t_qpath = tracing ? reinterpret_cast<int32_t*>(A + L_qp) : nullptr;
   if (wide) {
     wa.cpos = presort ? nullptr : reinterpret_cast<int32_t*>(A + L_cpos);
     wa.wbins = reinterpret_cast<uint32_t*>(A + L_wbins);
@@ -1048,6 +1095,13 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     if ((rc = cp(tr->n_recheck, L_nr, 4 * nq))) return rc;
     if ((rc = cp(tr->n_cand, L_nc, 8 * nq))) return rc;
     if ((rc = cp(tr->n_visited, L_nv, 8 * nq))) return rc;
+    if ((rc = cp(tr->walk_path, L_qp, 4 * nq))) return rc;
+    if (tr->kernel_forms) {
+      tr->kernel_forms[0] = -1;
+      tr->kernel_forms[1] = bbc::final_topk_form(fa.max_kc);
+      tr->kernel_forms[2] = sa.lpairs ? 3 : (!sa.force_1d && nq <= 65535) ? 2 : 1;
+      tr->kernel_forms[3] = 0;
+    }
     std::vector<int64_t> nsc(nq);
     HIP_TRY(hipMemcpyAsync(nsc.data(), A + L_ns, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1075,6 +1129,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     HIP_TRY(hipMemcpyAsync(ctx->work_out, A + L_ns, 8 * nq, hipMemcpyDefault, s));
     HIP_TRY(hipMemcpyAsync(ctx->work_out + nq, A + L_nv, 8 * nq, hipMemcpyDefault, s));
   }
+  if (!(ctx && ctx->ws)) HIP_TRY(ix->arena.release(s));
   if (ctx && ctx->capture) {
     t_capturing = false;
     HIP_TRY(hipStreamEndCapture(s, &ctx->graph));
@@ -1201,19 +1256,13 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   } else {
     HIP_TRY(ix->arena.reserve(pl.total));
     A = ix->arena.base;
+    HIP_TRY(ix->arena.acquire(s));
   }
 
   // stage metadata through pinned memory (wait for the previous call's copy)
-  if (ix->pinned_cap < mp.total) {
-    HIP_TRY(hipEventSynchronize(ix->meta_done));
-    if (ix->pinned) hipHostFree(ix->pinned);
-    ix->pinned = nullptr;
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&ix->pinned), mp.total * 2));
-    ix->pinned_cap = mp.total * 2;
-  } else {
-    HIP_TRY(hipEventSynchronize(ix->meta_done));
-  }
-  char* H = ix->pinned;
+  char* H = nullptr;
+  hipEvent_t meta_ev = nullptr;
+  if ((rc = stage_meta(ix, ctx, mp.total, &H, &meta_ev))) return rc;
   std::memcpy(H + m_k, k, 4 * nq);
   std::memcpy(H + m_np, nprobe, 4 * nq);
   std::memcpy(H + m_po, probe_off.data(), 8 * (nq + 1));
@@ -1231,7 +1280,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     t_capturing = true;
   } else {
     HIP_TRY(hipMemcpyAsync(M, H, mp.total, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipEventRecord(ix->meta_done, s));
+    HIP_TRY(hipEventRecord(meta_ev, s));
   }
   const float* dq = queries;
   if (host_io) {
@@ -1420,6 +1469,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       if (dst) HIP_TRY(hipMemcpyAsync(dst, A + off, bytes, hipMemcpyDeviceToHost, s));
       return BBC_OK;
     };
+    if (tr->kernel_forms) {
+      tr->kernel_forms[0] = bucket ? bbc::codebook_form(ca.max_sample) : -1;
+      tr->kernel_forms[1] = bbc::final_topk_form(fa.max_kc);
+      tr->kernel_forms[2] = -1;
+      tr->kernel_forms[3] = 0;
+    }
     if ((rc = cp(tr->probe_lists, L.probe_lists, 4 * npairs))) return rc;
     if ((rc = cp(tr->probe_keys, L.probe_keys, 4 * npairs))) return rc;
     if ((rc = cp(tr->n_recheck, L.n_recheck, 4 * nq))) return rc;
@@ -1481,6 +1536,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     HIP_TRY(hipMemcpyAsync(ctx->work_out, A + L.n_scanned, 8 * nq, hipMemcpyDefault, s));
     HIP_TRY(hipMemcpyAsync(ctx->work_out + nq, A + L.n_cand, 8 * nq, hipMemcpyDefault, s));
   }
+  if (!(ctx && ctx->ws)) HIP_TRY(ix->arena.release(s));
   if (ctx && ctx->capture) {
     t_capturing = false;
     HIP_TRY(hipStreamEndCapture(s, &ctx->graph));
@@ -1496,7 +1552,7 @@ namespace bbc {
 int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
                             const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
                             int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes,
-                            int64_t* work_out) {
+                            int64_t* work_out, const MetaStaging* meta) {
   if (!p || !ws_bytes) return fail(BBC_EINVAL, "NULL argument");
   if (!p->device_io) return fail(BBC_EINVAL, "a workspace search needs device I/O");
   // a sizing pass reads no query: any non-null pointer passes validation
@@ -1506,10 +1562,17 @@ int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, con
   ctx.size_only = ws == nullptr;
   ctx.ws = ws;
   ctx.work_out = work_out;
+  if (meta) {
+    ctx.meta_host = meta->host;
+    ctx.meta_cap = meta->bytes;
+    ctx.meta_ev = meta->done;
+  }
   const int32_t rc = run_search(ix, queries, nq, k, nprobe, p, out_off, out_ids, out_dists, out_counts, nullptr, &ctx);
   if (ctx.size_only) *ws_bytes = ctx.ws_bytes;
   return rc;
 }
+
+int index_device(const bbc_index* ix) { return ix ? ix->device : -1; }
 
 }  // namespace bbc
 

@@ -694,12 +694,20 @@ hipError_t launch_codebook(const CollectArgs& a, hipStream_t s) {
   // the smallest register slot count that holds the largest sample (48
   // slots fill the 128 registers a lane of a 1024-thread block may hold)
   const dim3 g((unsigned)a.nq), b(1024);
-  const int64_t ms = a.max_sample;
-  if (ms <= 16 * 1024) hipLaunchKernelGGL(codebook_kernel<16>, g, b, 0, s, a);
-  else if (ms <= 32 * 1024) hipLaunchKernelGGL(codebook_kernel<32>, g, b, 0, s, a);
-  else if (ms <= 48 * 1024) hipLaunchKernelGGL(codebook_kernel<48>, g, b, 0, s, a);
-  else hipLaunchKernelGGL(codebook_kernel<0>, g, b, 0, s, a);
+  switch (codebook_form(a.max_sample)) {
+    case 16: hipLaunchKernelGGL(codebook_kernel<16>, g, b, 0, s, a); break;
+    case 32: hipLaunchKernelGGL(codebook_kernel<32>, g, b, 0, s, a); break;
+    case 48: hipLaunchKernelGGL(codebook_kernel<48>, g, b, 0, s, a); break;
+    default: hipLaunchKernelGGL(codebook_kernel<0>, g, b, 0, s, a); break;
+  }
   return hipGetLastError();
+}
+
+int codebook_form(int64_t ms) {
+  if (ms <= 16 * 1024) return 16;
+  if (ms <= 32 * 1024) return 32;
+  if (ms <= 48 * 1024) return 48;
+  return 0;
 }
 
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s) {

@@ -13,16 +13,29 @@ namespace bbc {
 // Records the message of a failing call (bbc_last_error) and returns code.
 int32_t set_error(int32_t code, const std::string& msg);
 
+// Fixed pinned host staging for a search's metadata block, and the event
+// recorded after each upload out of it.
+struct MetaStaging {
+  char* host;
+  size_t bytes;
+  hipEvent_t done;
+};
+
 // A search with device I/O whose scratch is the caller's `ws` (the index
 // arena is not touched, so calls on different streams with different
 // workspaces may overlap on the device).  With ws == nullptr only *ws_bytes
 // is set: the bytes the call needs.  work_out (device or pinned host, may be
 // NULL) receives [2][nq] int64 on the search stream: codes scanned, then
 // exact distances computed (K_c, or the objects the bounded walk visited).
+// meta (may be NULL): stage the metadata block there instead of in the
+// index's growable pinned buffer (the call then allocates nothing).
 int32_t search_in_workspace(bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
                             const int32_t* nprobe, const bbc_search_params* p, const int64_t* out_off,
                             int64_t* out_ids, float* out_dists, int32_t* out_counts, char* ws, size_t* ws_bytes,
-                            int64_t* work_out = nullptr);
+                            int64_t* work_out = nullptr, const MetaStaging* meta = nullptr);
+
+// Device an index lives on.
+int index_device(const bbc_index* ix);
 
 int32_t build_index_pq(int32_t device, const float* base, int64_t n, int32_t d, const bbc_build_params* p,
                        bbc_index** out);
@@ -101,6 +114,9 @@ struct CollectArgs {
   int64_t* t_nsample_keys;  // keys in the codebook sample (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
+// register slots per thread the codebook kernel takes for samples of up to
+// max_sample keys (16, 32, 48; 0 = samples read from memory in each pass)
+int codebook_form(int64_t max_sample);
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s);
 
 struct RerankArgs {
@@ -200,6 +216,7 @@ struct RabitqScanArgs {
   float* lb; float* ub; float* key;  // [sum S] by slot at key_off[q]; key optional
   int max_np;               // largest nprobe of the batch (the 2-D grid's first dimension)
   int grid2d;               // set by the launcher
+  int force_1d;             // one block per pair on a 1-D grid even where the 2-D grid fits
   // optional: the (query << 32 | rank) pairs grouped by list, *ngroups groups
   // of `group` entries (~0 pads), scanned so that each XCD takes a contiguous
   // run of them (a list's code rows then stay in that XCD's L2)
@@ -235,6 +252,9 @@ struct RabitqWalkArgs {
   uint32_t* t_rank_tb;       // [sum nprobe] first bin of each probe rank
   const int64_t* t_bin_off;  // [nq + 1]
   int t_shift;
+  int qcap;                  // objects above the k-th exact key resolved in LDS (0 = the LDS capacity)
+  int32_t* t_qpath;          // optional [nq]: how the exact stop point was found (0 no search, 1 LDS,
+                             // 2 global memory, 3 item-by-item walk)
 };
 // wide form: the bins of C (a no-op otherwise); then the exact keys of C
 // (wide form) and the walk
@@ -243,5 +263,8 @@ hipError_t launch_rabitq_walk(const RabitqWalkArgs& a, hipStream_t s);
 
 constexpr int FINAL_STATIC_LDS = 21000;  // bytes of static LDS of the final top-k kernel (upper bound)
 hipError_t launch_final_topk(const FinalArgs& a, hipStream_t s);
+// candidates per thread the final top-k kernel holds in registers for at most
+// max_kc candidates per query (8, 16, 24, 32; 0 = memory form)
+int final_topk_form(int64_t max_kc);
 
 }  // namespace bbc

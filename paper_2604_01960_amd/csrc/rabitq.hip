@@ -373,7 +373,7 @@ hipError_t launch_rabitq_scan(const RabitqScanArgs& a, hipStream_t s) {
   if (a.npairs <= 0) return hipSuccess;
   if (a.D > 32 * RQ_MAXW_ROW || a.D % 64 || a.code_words > RQ_MAXW_ROW || a.code_words % 4) return hipErrorInvalidValue;
   RabitqScanArgs b = a;
-  b.grid2d = a.nq <= 65535 && a.max_np >= 1;
+  b.grid2d = !a.force_1d && a.nq <= 65535 && a.max_np >= 1;
   if (a.lpairs && (a.lpairs_cap < 1 || a.lpairs_cap > 0x7fffffffLL)) return hipErrorInvalidValue;
   const dim3 g = a.lpairs ? dim3((unsigned)((a.lpairs_cap + 7) / 8 * 8))
                           : b.grid2d ? dim3((unsigned)a.max_np, (unsigned)a.nq) : dim3((unsigned)a.npairs);
@@ -730,7 +730,11 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
   const int64_t k = a.k[qi];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   if (S == 0) {
-    if (threadIdx.x == 0) { a.n_cand[qi] = 0; if (a.n_visited) a.n_visited[qi] = 0; }
+    if (threadIdx.x == 0) {
+      a.n_cand[qi] = 0;
+      if (a.n_visited) a.n_visited[qi] = 0;
+      if (a.t_qpath) a.t_qpath[qi] = 0;
+    }
     return;
   }
   const int64_t po = a.probe_off[qi];
@@ -926,6 +930,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
   // a predicate monotone in t, found by binary search.
   bool ok = true;
   int64_t nvis = p;
+  int qpath = 0;
   if (S > k) {
     if (exhausted && p < S && E > U) ok = false;
     if (threadIdx.x == 0) { bc[7] = 0; bc[14] = 0; }
@@ -970,7 +975,8 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       const int64_t kz = min(k, n0);  // objects of R that Z0 provides
       int64_t lo = max((int64_t)0, k - kz), hi = nQ;
       uint64_t cut = ~0ull;
-      if (nQ <= WK_QCAP) {
+      qpath = nQ <= (a.qcap > 0 && a.qcap < WK_QCAP ? a.qcap : WK_QCAP) ? 1 : 2;
+      if (qpath == 1) {
         // Q sorted in LDS by (lb image, id), with its exact (key, id)
         if (threadIdx.x == 0) bc[9] = 0;
         __syncthreads();
@@ -1039,7 +1045,11 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
   }
   if (ok) {
     // exact distances computed: the visited objects, or all of C in the wide form
-    if (threadIdx.x == 0) { a.n_cand[qi] = nvis; if (a.n_visited) a.n_visited[qi] = WIDE ? nC : nvis; }
+    if (threadIdx.x == 0) {
+      a.n_cand[qi] = nvis;
+      if (a.n_visited) a.n_visited[qi] = WIDE ? nC : nvis;
+      if (a.t_qpath) a.t_qpath[qi] = qpath;
+    }
     return;
   }
 
@@ -1119,7 +1129,11 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
     __syncthreads();
   }
   // the item walk visits a prefix of the (lb, id) order, of which C is a prefix too
-  if (threadIdx.x == 0) { a.n_cand[qi] = nr; if (a.n_visited) a.n_visited[qi] = WIDE ? max(nC, visited) : visited; }
+  if (threadIdx.x == 0) {
+    a.n_cand[qi] = nr;
+    if (a.n_visited) a.n_visited[qi] = WIDE ? max(nC, visited) : visited;
+    if (a.t_qpath) a.t_qpath[qi] = 3;
+  }
 }
 
 hipError_t launch_rabitq_walk_prep(const RabitqWalkArgs& a, hipStream_t s) {

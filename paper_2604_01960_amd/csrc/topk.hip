@@ -385,17 +385,23 @@ __global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_to
 hipError_t launch_final_topk(const FinalArgs& a, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
   size_t lds = sizeof(uint64_t) * (size_t)a.cap;
-  if (a.max_kc <= 8 * 1024)
-    hipLaunchKernelGGL((final_topk_kernel<8>), dim3((unsigned)a.nq), dim3(1024), lds, s, a);
-  else if (a.max_kc <= 16 * 1024)
-    hipLaunchKernelGGL((final_topk_kernel<16>), dim3((unsigned)a.nq), dim3(1024), lds, s, a);
-  else if (a.max_kc <= 24 * 1024)
-    hipLaunchKernelGGL((final_topk_kernel<24>), dim3((unsigned)a.nq), dim3(1024), lds, s, a);
-  else if (a.max_kc <= 32 * 1024)
-    hipLaunchKernelGGL((final_topk_kernel<32>), dim3((unsigned)a.nq), dim3(1024), lds, s, a);
-  else
-    hipLaunchKernelGGL((final_topk_kernel<0>), dim3((unsigned)a.nq), dim3(1024), lds, s, a);
+  const dim3 g((unsigned)a.nq), b(1024);
+  switch (final_topk_form(a.max_kc)) {
+    case 8: hipLaunchKernelGGL((final_topk_kernel<8>), g, b, lds, s, a); break;
+    case 16: hipLaunchKernelGGL((final_topk_kernel<16>), g, b, lds, s, a); break;
+    case 24: hipLaunchKernelGGL((final_topk_kernel<24>), g, b, lds, s, a); break;
+    case 32: hipLaunchKernelGGL((final_topk_kernel<32>), g, b, lds, s, a); break;
+    default: hipLaunchKernelGGL((final_topk_kernel<0>), g, b, lds, s, a); break;
+  }
   return hipGetLastError();
+}
+
+int final_topk_form(int64_t max_kc) {
+  if (max_kc <= 8 * 1024) return 8;
+  if (max_kc <= 16 * 1024) return 16;
+  if (max_kc <= 24 * 1024) return 24;
+  if (max_kc <= 32 * 1024) return 32;
+  return 0;
 }
 
 }  // namespace bbc

@@ -1,7 +1,8 @@
 """Captured plans (the batched uneven form): a HIP graph replay of a batch
-with per-query k and nprobe gives the eager search's results, on every
-replay, with eager work and synchronisation between replays; autotuning
-changes nothing in the results."""
+with per-query k and nprobe gives the oracle's results (ids and distances
+bit for bit) and the eager search's, on every replay, with eager work and
+synchronisation between replays; autotuning changes nothing in the
+results."""
 import numpy as np
 import pytest
 
@@ -30,8 +31,12 @@ def test_pq_plan_replays_match_eager(bbc, autotune):
     w, ix, q = oracle_pq_index("ivfpq4_10m_d96", 20000, 50, 48, 4, 64)
     g = make_gpu_index(bbc, ix)
     k, npb = synth.uneven_k_nprobe(64, (100, 5000), (4, 50), seed=7)
+    import oracle
     qd = torch.from_numpy(q).cuda()
+    orc = oracle.search_pq(ix, q, k, npb, 2.0)
     ref = g.search(q, k, npb, ratio=2.0)
+    np.testing.assert_array_equal(ref[0], orc["ids"])
+    np.testing.assert_array_equal(ref[1], orc["dists"])
     out = _bufs(torch, k)
     print(f"[case] pq plan autotune={autotune}", flush=True)
     plan = g.plan(qd, k, npb, out, ratio=2.0, autotune=autotune)
@@ -42,9 +47,9 @@ def test_pq_plan_replays_match_eager(bbc, autotune):
             t.fill_(-7)
         plan.execute()
         torch.cuda.synchronize()
-        np.testing.assert_array_equal(out[0].cpu().numpy(), ref[0], err_msg=f"replay {rep}")
-        np.testing.assert_array_equal(out[1].cpu().numpy(), ref[1])
-        np.testing.assert_array_equal(out[2].cpu().numpy(), ref[2])
+        np.testing.assert_array_equal(out[0].cpu().numpy(), orc["ids"], err_msg=f"replay {rep}")
+        np.testing.assert_array_equal(out[1].cpu().numpy(), orc["dists"])
+        np.testing.assert_array_equal(out[2].cpu().numpy(), orc["counts"])
         # eager work on the same index between replays
         again = g.search(q[:5], 300, 7, ratio=2.0)
         assert again[2].shape == (5,)
@@ -53,8 +58,9 @@ def test_pq_plan_replays_match_eager(bbc, autotune):
     qd.copy_(torch.from_numpy(q2))
     plan.execute()
     torch.cuda.synchronize()
-    ref2 = g.search(q2, k, npb, ratio=2.0)
-    np.testing.assert_array_equal(out[0].cpu().numpy(), ref2[0])
+    orc2 = oracle.search_pq(ix, q2, k, npb, 2.0)
+    np.testing.assert_array_equal(out[0].cpu().numpy(), orc2["ids"])
+    np.testing.assert_array_equal(out[1].cpu().numpy(), orc2["dists"])
     plan.free()
 
 
