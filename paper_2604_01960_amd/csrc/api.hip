@@ -181,7 +181,7 @@ struct bbc_index {
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide, 3 wide with tile-major keys)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   int walk_qcap = 0;        // RaBitQ walk: objects above the k-th exact key resolved in LDS (BBC_WALK_QCAP:
-                            // a power of two, 64..4096; 0 = the LDS capacity)
+                            // a power of two, 2..4096; 0 = the LDS capacity)
   int rq_scan_1d = 0;       // RaBitQ scan on a 1-D grid of pairs (BBC_RQ_SCAN_1D; taken anyway beyond 65535 queries)
   int rerank_form = 0;      // PQ re-rank form (BBC_RERANK_FORM: 0 tile-major where it applies, 1 per query)
   int64_t rt_sort_bins = (int64_t)1 << 30;  // tile-major sort: most bin counters (BBC_RERANK_SORT_BINS)
@@ -314,7 +314,7 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   }
   if (const char* sv = std::getenv("BBC_WALK_QCAP")) {
     const int x = std::atoi(sv);
-    if (x >= 64 && x <= 4096 && (x & (x - 1)) == 0) ix->walk_qcap = x;
+    if (x >= 2 && x <= 4096 && (x & (x - 1)) == 0) ix->walk_qcap = x;
   }
   if (const char* sv = std::getenv("BBC_RQ_SCAN_1D")) ix->rq_scan_1d = std::atoi(sv) == 1;
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));

@@ -89,13 +89,15 @@ def _check_rabitq(tr, ix, q, k, nprobe):
 @pytest.mark.parametrize("form", ["1", "2"])
 def test_rabitq_walk_stop_point_outside_lds(bbc, form):
     """With the walk's LDS capacity for the objects above the k-th exact key
-    cut to 64, queries with more of them resolve the exact stop point with
+    cut to 2, queries with more of them resolve the exact stop point with
     radix selects in global memory; results equal the oracle's, and the
-    default capacity resolves the same queries in LDS."""
-    x, q, ix = _rabitq_data(128, 20000, 12, 16)
+    default capacity resolves the same queries in LDS.  (The wide form's
+    processed prefix is the shortest one, so few of its objects lie above
+    the k-th key: the capacity is cut below that count.)"""
+    x, q, ix = _rabitq_data(128, 20000, 24, 16)
     k, nprobe = 2500, 16
-    print(f"[case] rabitq walk qcap=64 form={form}", flush=True)
-    g = _rabitq_index(bbc, x, ix, {"BBC_WALK_QCAP": "64", "BBC_WALK_FORM": form})
+    print(f"[case] rabitq walk qcap=2 form={form}", flush=True)
+    g = _rabitq_index(bbc, x, ix, {"BBC_WALK_QCAP": "2", "BBC_WALK_FORM": form})
     tr = g.search_traced(q, k, nprobe)
     assert np.any(tr["walk_path"] == 2), tr["walk_path"]
     _check_rabitq(tr, ix, q, k, nprobe)
