@@ -157,6 +157,29 @@ int32_t bbc_search(const bbc_index* ix, const float* queries, int64_t nq, const 
                    const int32_t* nprobe, const bbc_search_params* params, const int64_t* out_offsets,
                    int64_t* out_ids, float* out_dists, int32_t* out_counts);
 
+/* Allocation-free search, for callers that cannot allocate memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation).  Same arguments, results and errors as bbc_search with
+ * params->device_io = 1 (queries and outputs are device pointers on
+ * params->stream; k, nprobe and out_offsets are host arrays), but the
+ * workspace is a fixed device array of BBC_NOALLOC_MAX_BYTES held by each
+ * GPU the library runs on until the process ends, and the metadata block is
+ * staged through a fixed host buffer: the call makes no hipMalloc, hipFree
+ * or other allocating call.  Errors: BBC_EINVAL when device_io is 0 (and as
+ * bbc_search); BBC_ENOMEM, before anything is enqueued, when the batch needs
+ * more workspace than BBC_NOALLOC_MAX_BYTES (bbc_query_bytes bounds each
+ * query's share; split such batches).  Every allocation-free call on one GPU
+ * shares that GPU's array and the array keeps the last call's contents:
+ * calls that overlap on the device (different streams, or different indexes
+ * on the same GPU) race, so order them on one stream or by events.  The
+ * host side of these calls is serialised process-wide.  Only the 256-byte
+ * aligned sub-buffers the search lays out are used; what must start at zero
+ * is cleared by its kernels. */
+#define BBC_NOALLOC_MAX_BYTES ((size_t)128 << 20)
+int32_t bbc_search_noalloc(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                           const int32_t* nprobe, const bbc_search_params* params, const int64_t* out_offsets,
+                           int64_t* out_ids, float* out_dists, int32_t* out_counts);
+
 /* Intermediate state of a search, for checking every step (host arrays;
  * any pointer may be NULL).  Ragged arrays use the prefix sums given:
  * probe_*: by nprobe; cand_*: by cand_cap[q] = the per-query candidate

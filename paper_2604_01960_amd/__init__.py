@@ -94,6 +94,8 @@ def load(path: Optional[str] = None):
     L.bbc_search.restype = i32
     L.bbc_search.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.bbc_search_traced.restype = i32
+    L.bbc_search_noalloc.restype = i32
+    L.bbc_search_noalloc.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp]
     L.bbc_search_traced.argtypes = [vp, vp, i64, vp, vp, C.POINTER(SearchParams), vp, vp, vp, vp,
                                     C.POINTER(SearchTrace)]
     L.bbc_query_bytes.restype = i64
@@ -330,6 +332,29 @@ class Index:
         p = self._params(ratio, collector, buckets, nsample, 0, stream)
         _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                  _ptr(ids), _ptr(dists), _ptr(counts)))
+        return ids, dists, counts, off
+
+    def search_noalloc(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
+                       nsample: int = 0, stream=None):
+        """bbc_search_noalloc: torch GPU queries and preallocated (ids, dists, counts)
+        torch tensors; enqueued on `stream` (default: torch's current stream).  The
+        workspace is the library's fixed per-GPU array (BBC_NOALLOC_MAX_BYTES)."""
+        import torch
+        nq = int(queries.shape[0])
+        kk = _per_query(k, nq, "k")
+        npb = _per_query(nprobe, nq, "nprobe")
+        off = np.zeros(nq + 1, np.int64)
+        off[1:] = np.cumsum(kk)
+        if not _is_torch_gpu(queries) or queries.dtype != torch.float32 or not queries.is_contiguous():
+            raise ValueError("queries must be a contiguous float32 GPU tensor")
+        if stream is None:
+            stream = torch.cuda.current_stream(queries.device).cuda_stream
+        ids, dists, counts = out
+        if ids.numel() < int(off[-1]) or dists.numel() < int(off[-1]) or counts.numel() < nq:
+            raise ValueError("output tensors are too small")
+        p = self._params(ratio, collector, buckets, nsample, 1, stream)
+        _check(load().bbc_search_noalloc(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
+                                         _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_counts(self, queries, k, nprobe, ratio: float = 2.0, buckets: int = 0, nsample: int = 0):

@@ -1595,6 +1595,81 @@ int32_t bbc_search_traced(const bbc_index* ix, const float* queries, int64_t nq,
                     out_dists, out_counts, trace);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// allocation-free search: the workspace is a fixed device array
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr size_t NOALLOC_SCRATCH_BYTES = BBC_NOALLOC_MAX_BYTES;  // device scratch per GPU
+constexpr size_t NOALLOC_META_BYTES = (size_t)1 << 20;       // host staging of the metadata block
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+}  // namespace
+
+// The allocation-free search's workspace.  In host code this name stands for
+// the array but is not its device address: kernels get the address that
+// hipGetSymbolAddress returns for the current device (each GPU holds its own
+// copy, at its own address, until the process ends).
+static __device__ __align__(256) char scratch[NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+struct NoAllocDevice {
+  char* ptr = nullptr;             // device address of this GPU's copy of `scratch`
+  hipEvent_t meta_done = nullptr;  // recorded after each metadata upload out of g_noalloc_meta
+};
+std::mutex g_noalloc_mu;  // serialises the host side of every allocation-free call
+NoAllocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+alignas(256) char g_noalloc_meta[NOALLOC_META_BYTES];
+
+// Once per device, with that device current: the device address of its copy
+// of `scratch` and the staging buffer's event.
+int32_t noalloc_setup(int dev) {
+  NoAllocDevice& nd = g_noalloc[dev];
+  if (nd.ptr) return BBC_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(BBC_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  hipEvent_t ev = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+  nd.meta_done = ev;
+  nd.ptr = static_cast<char*>(ptr);
+  return BBC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bbc_search_noalloc(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
+                           const int32_t* nprobe, const bbc_search_params* params, const int64_t* out_offsets,
+                           int64_t* out_ids, float* out_dists, int32_t* out_counts) {
+  if (!ix) return fail(BBC_EINVAL, "index is NULL");
+  if (!params) return fail(BBC_EINVAL, "params is NULL");
+  if (!params->device_io) return fail(BBC_EINVAL, "the allocation-free search needs device I/O (device_io = 1)");
+  const int dev = ix->device;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(BBC_EUNSUPPORTED, "device ordinal out of range");
+  std::lock_guard<std::mutex> guard(g_noalloc_mu);
+  int32_t rc = set_device(dev);
+  if (rc) return rc;
+  if ((rc = noalloc_setup(dev))) return rc;
+  bbc_index* mix = const_cast<bbc_index*>(ix);
+  size_t need = 0;
+  rc = bbc::search_in_workspace(mix, queries, nq, k, nprobe, params, out_offsets, out_ids, out_dists, out_counts,
+                                nullptr, &need);
+  if (rc || nq == 0) return rc;
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(BBC_ENOMEM, "the batch needs " + std::to_string(need) +
+                                " bytes of workspace, above the allocation-free maximum of " +
+                                std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes: split it into smaller batches");
+  const bbc::MetaStaging ms{g_noalloc_meta, NOALLOC_META_BYTES, g_noalloc[dev].meta_done};
+  return bbc::search_in_workspace(mix, queries, nq, k, nprobe, params, out_offsets, out_ids, out_dists, out_counts,
+                                  g_noalloc[dev].ptr, &need, nullptr, &ms);
+}
+
 struct bbc_plan {
   bbc_index* ix = nullptr;
   int64_t nq = 0;

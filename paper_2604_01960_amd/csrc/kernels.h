@@ -13,8 +13,8 @@ namespace bbc {
 // Records the message of a failing call (bbc_last_error) and returns code.
 int32_t set_error(int32_t code, const std::string& msg);
 
-// Fixed pinned host staging for a search's metadata block, and the event
-// recorded after each upload out of it.
+// Fixed host staging for a search's metadata block (pinned, or a static
+// pageable buffer), and the event recorded after each upload out of it.
 struct MetaStaging {
   char* host;
   size_t bytes;
