@@ -71,6 +71,9 @@ def lib():
             L.orc_pq_key.restype = f32
             L.orc_pq_key.argtypes = [vp, vp, i32, i32]
             L.orc_pq_keys.argtypes = [vp, vp, i64, i32, i32, vp]
+            L.orc_pq_lut_u8.argtypes = [vp, i32, i32, vp, vp, vp]
+            L.orc_pq_key_u8.restype = f32
+            L.orc_pq_key_u8.argtypes = [vp, vp, i32, i32, f32, f32]
             L.orc_kmeans_assign.argtypes = [vp, vp, i64, i32, vp, i32, vp]
             L.orc_kmeans_update.argtypes = [vp, vp, i64, i32, vp, i32, vp]
             L.orc_kmeans_train.argtypes = [vp, i32, vp, i64, vp, i32, i32, vp]
@@ -78,7 +81,7 @@ def lib():
             L.orc_pq_encode.argtypes = [vp, i64, i32, i32, i32, vp, vp]
             L.orc_residuals.argtypes = [vp, vp, i64, i32, vp, vp, vp]
             L.orc_search_pq.argtypes = [i64, i32, i32, vp, vp, vp, vp, i32, i32, vp, vp, i32,
-                                        vp, i64, vp, vp, f64, vp, vp, vp, vp,
+                                        vp, i64, vp, vp, f64, i32, vp, vp, vp, vp,
                                         vp, vp, vp, vp, vp, vp, vp, vp]
             L.orc_exact_knn64.argtypes = [vp, i64, i32, vp, i64, i32, i32, vp, vp]
             L.orc_rotate.argtypes = [vp, i32, vp, i64, vp]
@@ -254,6 +257,26 @@ def pq_lut(q, centroid, codebook_arr, M, ksub):
     lut = np.empty((M, ksub), np.float32)
     lib().orc_pq_lut(_p(q), _p(c), q.shape[0], M, ksub, _p(cb), _p(lut))
     return lut
+
+
+def pq_lut_u8(lut):
+    """One-byte table of a float32 table [M, ksub]: (u8 [M, ksub], base, delta)."""
+    lut = _f32(lut)
+    M, ksub = lut.shape
+    u = np.empty((M, ksub), np.uint8)
+    b = np.zeros(1, np.float32)
+    dl = np.zeros(1, np.float32)
+    lib().orc_pq_lut_u8(_p(lut), M, ksub, _p(u), _p(b), _p(dl))
+    return u, b[0], dl[0]
+
+
+def pq_keys_u8(u, base, delta, codes):
+    """Estimated keys of the rows of codes [n, M] against one one-byte table."""
+    u = np.ascontiguousarray(u, dtype=np.uint8)
+    codes = np.ascontiguousarray(codes, dtype=np.uint8)
+    M, ksub = u.shape
+    return np.array([lib().orc_pq_key_u8(_p(u), _p(codes[i]), M, ksub, float(base), float(delta))
+                     for i in range(codes.shape[0])], np.float32)
 
 
 def pq_keys(lut, codes):
@@ -458,8 +481,9 @@ def search_rabitq(index, queries, k, nprobe, eps0=RABITQ_EPS0, debug=False):
 # search
 # --------------------------------------------------------------------------
 
-def search_pq(index, queries, k, nprobe, ratio, debug=False):
-    """Full PQ query path.  Returns dict(ids, dists, counts, off[, debug...])."""
+def search_pq(index, queries, k, nprobe, ratio, debug=False, lut_u8=False):
+    """Full PQ query path (lut_u8: one-byte tables with integer sums).
+    Returns dict(ids, dists, counts, off[, debug...])."""
     q = _f32(queries)
     nq = q.shape[0]
     kk = _i32(np.broadcast_to(np.asarray(k), (nq,)))
@@ -490,7 +514,7 @@ def search_pq(index, queries, k, nprobe, ratio, debug=False):
         ix["n"], ix["d"], ix["nlist"], _p(_f32(ix["centroids"])), _p(_i64(ix["list_off"])),
         _p(_i64(ix["list_ids"])), _p(np.ascontiguousarray(ix["codes"], np.uint8)), ix["M"], ix["ksub"],
         _p(_f32(ix["codebook"])), _p(_f32(ix["base"])), ix["metric"],
-        _p(q), nq, _p(kk), _p(npb), float(ratio), _p(off), _p(ids), _p(dists), _p(counts),
+        _p(q), nq, _p(kk), _p(npb), float(ratio), int(bool(lut_u8)), _p(off), _p(ids), _p(dists), _p(counts),
         _p(pl), _p(pk), _p(poff), _p(ns), _p(nc), _p(ck), _p(ci), _p(coff)), "search_pq")
     return res
 

@@ -393,6 +393,61 @@ void orc_pq_keys(const float* lut, const uint8_t* codes, int64_t n, int32_t M, i
   for (int64_t i = 0; i < n; ++i) out[i] = orc_pq_key(lut, codes + i * M, M, ksub);
 }
 
+/* One-byte table with integer sums (row f2; the paper counts one byte per
+ * table entry for its 4-bit fast-scan codes, and sums of small integers are
+ * exact in any order).  Reading, one scale per (query, list) table so that
+ * the sub-space codes add up as integers:
+ *   lo_m  = min over b of lut[m][b]
+ *   span  = max over m of (max_b lut[m][b] - lo_m)      (float32 subtraction)
+ *   delta = span / 255, or 1 when that is not positive; inv = 1 / delta
+ *   u[m][b] = min(255, floor(((lut[m][b] - lo_m) * inv) + 0.5))
+ *             (float32 subtract, multiply, add in that order; the value is
+ *             never negative, so floor is truncation)
+ *   base  = lo_0 + lo_1 + ... + lo_{M-1}, sequential from +0.
+ * A code's estimated key is base + K * delta with K = sum_m u[m][code_m]
+ * (an exact integer; K * delta rounded once, then the add rounded once). */
+void orc_pq_lut_u8(const float* lut, int32_t M, int32_t ksub, uint8_t* u, float* base_out,
+                   float* delta_out) {
+  float span = 0.0f, base = 0.0f;
+  for (int32_t m = 0; m < M; ++m) {
+    const float* row = lut + (int64_t)m * ksub;
+    float lo = row[0], hi = row[0];
+    for (int32_t b = 1; b < ksub; ++b) {
+      if (row[b] < lo) lo = row[b];
+      if (row[b] > hi) hi = row[b];
+    }
+    const float w = hi - lo;
+    if (w > span) span = w;
+    base = base + lo;
+  }
+  float delta = span / 255.0f;
+  if (!(delta > 0.0f)) delta = 1.0f;
+  const float inv = 1.0f / delta;
+  for (int32_t m = 0; m < M; ++m) {
+    const float* row = lut + (int64_t)m * ksub;
+    float lo = row[0];
+    for (int32_t b = 1; b < ksub; ++b)
+      if (row[b] < lo) lo = row[b];
+    for (int32_t b = 0; b < ksub; ++b) {
+      float t = row[b] - lo;
+      t = t * inv;
+      t = t + 0.5f;
+      uint32_t v = (uint32_t)t;
+      u[(int64_t)m * ksub + b] = (uint8_t)(v > 255u ? 255u : v);
+    }
+  }
+  *base_out = base;
+  *delta_out = delta;
+}
+
+float orc_pq_key_u8(const uint8_t* u, const uint8_t* code, int32_t M, int32_t ksub, float base,
+                    float delta) {
+  uint32_t K = 0;
+  for (int32_t m = 0; m < M; ++m) K += u[(int64_t)m * ksub + code[m]];
+  const float t = (float)K * delta;
+  return base + t;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Index build: IVF k-means and PQ                                           */
 /* ------------------------------------------------------------------------ */
@@ -570,6 +625,7 @@ typedef struct {
   const float* codebook;       /* [M][ksub][d/M] */
   const float* base;           /* [n][d] original row order */
   int32_t metric;              /* 0 = L2 (PQ path supports L2 only) */
+  int32_t lut_u8;              /* 1: one-byte tables with integer sums (orc_pq_lut_u8) */
 } orc_pq_index;
 
 /* Optional per-query intermediate outputs (any pointer may be NULL). */
@@ -591,9 +647,13 @@ static int search_pq_one(const orc_pq_index* ix, const float* q, int32_t k, int3
   int32_t* lists = (int32_t*)malloc(sizeof(int32_t) * (size_t)nprobe);
   float* lkeys = (float*)malloc(sizeof(float) * (size_t)nprobe);
   float* lut = (float*)malloc(sizeof(float) * (size_t)ix->M * ix->ksub);
-  if (!lists || !lkeys || !lut) { free(lists); free(lkeys); free(lut); return ORC_ENOMEM; }
+  uint8_t* lut8 = (uint8_t*)malloc((size_t)ix->M * ix->ksub);
+  if (!lists || !lkeys || !lut || !lut8) {
+    free(lists); free(lkeys); free(lut); free(lut8);
+    return ORC_ENOMEM;
+  }
   int rc = probe_one(q, ix->centroids, ix->nlist, d, ix->metric, nprobe, lists, lkeys);
-  if (rc) { free(lists); free(lkeys); free(lut); return rc; }
+  if (rc) { free(lists); free(lkeys); free(lut); free(lut8); return rc; }
   if (dbg && dbg->probe_lists)
     for (int32_t i = 0; i < nprobe; ++i) dbg->probe_lists[dbg->probe_off[qi] + i] = lists[i];
   if (dbg && dbg->probe_keys)
@@ -602,13 +662,16 @@ static int search_pq_one(const orc_pq_index* ix, const float* q, int32_t k, int3
   int64_t S = 0;
   for (int32_t i = 0; i < nprobe; ++i) S += ix->list_off[lists[i] + 1] - ix->list_off[lists[i]];
   kv_t* est = (kv_t*)malloc(sizeof(kv_t) * (size_t)(S > 0 ? S : 1));
-  if (!est) { free(lists); free(lkeys); free(lut); return ORC_ENOMEM; }
+  if (!est) { free(lists); free(lkeys); free(lut); free(lut8); return ORC_ENOMEM; }
   int64_t w = 0;
   for (int32_t i = 0; i < nprobe; ++i) {
     int32_t j = lists[i];
     orc_pq_lut(q, ix->centroids + (int64_t)j * d, d, ix->M, ix->ksub, ix->codebook, lut);
+    float base = 0.0f, delta = 1.0f;
+    if (ix->lut_u8) orc_pq_lut_u8(lut, ix->M, ix->ksub, lut8, &base, &delta);
     for (int64_t p = ix->list_off[j]; p < ix->list_off[j + 1]; ++p) {
-      est[w].key = orc_pq_key(lut, ix->codes + p * ix->M, ix->M, ix->ksub);
+      est[w].key = ix->lut_u8 ? orc_pq_key_u8(lut8, ix->codes + p * ix->M, ix->M, ix->ksub, base, delta)
+                              : orc_pq_key(lut, ix->codes + p * ix->M, ix->M, ix->ksub);
       est[w].pad = 0;
       est[w].id = ix->list_ids[p];
       ++w;
@@ -646,6 +709,7 @@ static int search_pq_one(const orc_pq_index* ix, const float* q, int32_t k, int3
   free(lists);
   free(lkeys);
   free(lut);
+  free(lut8);
   return ORC_OK;
 }
 
@@ -653,12 +717,13 @@ int orc_search_pq(int64_t n, int32_t d, int32_t nlist, const float* centroids,
                   const int64_t* list_off, const int64_t* list_ids, const uint8_t* codes,
                   int32_t M, int32_t ksub, const float* codebook, const float* base, int32_t metric,
                   const float* queries, int64_t nq, const int32_t* k, const int32_t* nprobe,
-                  double ratio, const int64_t* out_off, int64_t* out_ids, float* out_dists,
-                  int32_t* out_counts,
+                  double ratio, int32_t lut_u8, const int64_t* out_off, int64_t* out_ids,
+                  float* out_dists, int32_t* out_counts,
                   int32_t* dbg_probe_lists, float* dbg_probe_keys, const int64_t* dbg_probe_off,
                   int64_t* dbg_n_scanned, int64_t* dbg_n_cand,
                   float* dbg_cand_keys, int64_t* dbg_cand_ids, const int64_t* dbg_cand_off) {
-  orc_pq_index ix = {n, d, nlist, centroids, list_off, list_ids, codes, M, ksub, codebook, base, metric};
+  orc_pq_index ix = {n, d, nlist, centroids, list_off, list_ids, codes, M, ksub, codebook, base, metric,
+                     lut_u8};
   orc_pq_debug dbg = {dbg_probe_lists, dbg_probe_keys, dbg_probe_off, dbg_n_scanned, dbg_n_cand,
                       dbg_cand_keys, dbg_cand_ids, dbg_cand_off};
   int err = ORC_OK;
