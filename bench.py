@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--cpu-queries-1t", type=int, default=200, help="oracle queries timed on one thread")
     ap.add_argument("--o64-queries", type=int, default=100, help="queries searched by the float64 oracle O_64")
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
+    ap.add_argument("--lut-u8", action="store_true",
+                    help="PQ: one-byte distance tables with integer sums (fast-scan table accounting)")
     ap.add_argument("--serve-qps", type=float, default=0.0, help="serving: arrival rate (default: the workload's)")
     ap.add_argument("--serve-seconds", type=float, default=None, help="serving: stream length (default: the workload's)")
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving: workspace bytes in flight")
@@ -332,14 +334,14 @@ def main():
         if fixed_np and fixed_r:
             rec = None
             if gt is not None:
-                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki])
+                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki], lut_u8=args.lut_u8)
                 rec = recall_at_k(ids, off, gt, k)
             op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=rec)
             continue
         cands = []
         for npb in nprobe_grid:
             for r in ratio_grid:
-                ids, _, _, off = index.search(rq, k, npb, ratio=r)
+                ids, _, _, off = index.search(rq, k, npb, ratio=r, lut_u8=args.lut_u8)
                 rec = recall_at_k(ids, off, gt, k)
                 if rec >= args.target_recall:
                     cands.append(dict(nprobe=npb, ratio=r, recall=rec))
@@ -347,17 +349,17 @@ def main():
         if not cands:
             raise SystemExit(f"recall {args.target_recall} not reached for k={k}")
         for c in cands:  # one timed full batch per candidate
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"])
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"])
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
             torch.cuda.synchronize()
             c["probe_ms"] = (time.perf_counter() - t) * 1e3
         # the fastest candidate whose recall over the whole batch reaches the
         # target (the sweep's sample only shortlists)
         best = None
         for c in sorted(cands, key=lambda c: c["probe_ms"]):
-            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"])
+            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
             torch.cuda.synchronize()
             c["recall_batch"] = recall_device(torch, o[0], gt_full_ids, k)
             if c["recall_batch"] >= args.target_recall:
@@ -378,7 +380,7 @@ def main():
         for k in ks:
             if per_k_events is not None:
                 per_k_events[k][0].record()
-            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k])
+            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k], lut_u8=args.lut_u8)
             if per_k_events is not None:
                 per_k_events[k][1].record()
 
@@ -425,13 +427,13 @@ def main():
             ref = None
             for col in ("bucket", "heap", "sort"):
                 o = (torch.empty_like(outs[k][0]), torch.empty_like(outs[k][1]), torch.empty_like(outs[k][2]))
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o)
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8)
                 torch.cuda.synchronize()
                 bbc.stage_times(reset=True)
                 bbc.stage_timing(True)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o)
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8)
                 e1.record()
                 torch.cuda.synchronize()
                 bbc.stage_timing(False)
@@ -449,7 +451,7 @@ def main():
     # ---- sizes for the algorithmic byte counts ---------------------------------
     sizes = {}
     for k in ks:
-        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"])
+        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"], lut_u8=args.lut_u8)
         sizes[k] = dict(S=int(c["n_scanned"].sum()), Kc=int(c["n_cand"].sum()),
                         sample_keys=int(c["n_sample_keys"].sum()),
                         recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()),
@@ -489,7 +491,7 @@ def main():
             continue
         if name in ("scan", "sample_scan"):
             entries[name] = scan_entry(kernels[name][0], avg_ms, bytes_per_launch,
-                                       bytes_per_launch / code_bytes * w.pq_m * 4,
+                                       bytes_per_launch / code_bytes * w.pq_m * (1 if args.lut_u8 else 4),
                                        measured_traffic(w.name, name, kernels[name][1]), w.n * code_bytes)
             continue
         entries[name] = {"kernel": kernels[name][0], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -522,7 +524,7 @@ def main():
         mism_ids = mism_d = 0
         for k in ks:
             t0 = time.perf_counter()
-            ref = oracle.search_pq(oix, q[:nqc], k, op[k]["nprobe"], op[k]["ratio"])
+            ref = oracle.search_pq(oix, q[:nqc], k, op[k]["nprobe"], op[k]["ratio"], lut_u8=args.lut_u8)
             t_cpu += time.perf_counter() - t0
             gi = outs[k][0][: nqc * k].cpu().numpy().reshape(nqc, k)
             gd = outs[k][1][: nqc * k].cpu().numpy().reshape(nqc, k)
@@ -537,7 +539,7 @@ def main():
         t1 = 0.0
         for k in ks:
             t0 = time.perf_counter()
-            oracle.search_pq(oix, q[:n1], k, op[k]["nprobe"], op[k]["ratio"])
+            oracle.search_pq(oix, q[:n1], k, op[k]["nprobe"], op[k]["ratio"], lut_u8=args.lut_u8)
             t1 += time.perf_counter() - t0
         oracle.set_threads(0)
         model, ncpu = host_cpu()
@@ -570,7 +572,8 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "pq": f"{w.pq_m}x{w.pq_bits}",
-                   "nq": nq, "k": ks, "collector": "bucket", "buckets": 256, "nsample": 8},
+                   "nq": nq, "k": ks, "collector": "bucket", "buckets": 256, "nsample": 8,
+                   "tables": "u8" if args.lut_u8 else "f32"},
         "per_k": per_k,
         "latency_ms": {"p50": round(float(np.percentile(sum(lat.values(), []), 50)), 3),
                        "p99": round(float(np.percentile(sum(lat.values(), []), 99)), 3),
@@ -623,7 +626,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         ratio = float(args.ratio.split(",")[0])
         rec = None
         if gt is not None:
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio, lut_u8=args.lut_u8)
             rec = mean_recall(ids, off)
     else:
         # nprobe is fixed per query by the workload, so a query with few
@@ -632,7 +635,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         # smallest r within 0.005 of the best recall)
         ratio, rec, curve = None, None, []
         for r in (1.5, 2.0, 3.0, 4.0, 6.0, 8.0):
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r, lut_u8=args.lut_u8)
             rr = mean_recall(ids, off)
             log(f"ratio {r}: mean recall {rr:.4f}")
             curve.append((r, rr))
@@ -670,18 +673,18 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
             bbc.stage_timing(False)
         return el, np.array([a.elapsed_time(b) for a, b in ev])
 
-    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out), stage_timing=True)
+    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out, lut_u8=args.lut_u8), stage_timing=True)
     stages = bbc.stage_times(reset=True)
     t0 = time.time()
-    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True)
+    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True, lut_u8=args.lut_u8)
     plan_s = time.time() - t0
     info = plan.info()
     graph_s, graph_ms = timed(lambda: plan.execute())
     ids_g = out[0].cpu().numpy()
-    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"])
+    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"], lut_u8=args.lut_u8)
     same = bool(np.array_equal(ids_g, ref[0]))
     value = nq * args.steps / graph_s
-    sz = index.search_counts(q, k, npb, ratio=ratio)
+    sz = index.search_counts(q, k, npb, ratio=ratio, lut_u8=args.lut_u8)
     S, Kc, nsurv = int(sz["n_scanned"].sum()), int(sz["n_cand"].sum()), int(sz["n_survivors"].sum())
     nsk = int(sz["n_sample_keys"].sum())
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2
@@ -700,7 +703,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
             continue
         if name == "scan":
             src = [os.path.join(CSRC, f) for f in ("pq_scan.hip", "common.h", "kernels.h")]
-            entries[name] = scan_entry(names[name], avg_ms, bpl, bpl / code_bytes * w.pq_m * 4,
+            entries[name] = scan_entry(names[name], avg_ms, bpl, bpl / code_bytes * w.pq_m * (1 if args.lut_u8 else 4),
                                        measured_traffic(w.name, name, src), w.n * code_bytes)
             continue
         entries[name] = {"kernel": names[name], "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
@@ -715,7 +718,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
                    list_ids=index.get(bbc.FIELD_LIST_IDS), codes=index.get(bbc.FIELD_CODES),
                    codebook=index.get(bbc.FIELD_CODEBOOK), base=x)
         per_call = max(8, oracle.num_threads())
-        nqc, t_cpu = oracle_sample(lambda lo, hi: oracle.search_pq(oix, q[lo:hi], k[lo:hi], npb[lo:hi], ratio),
+        nqc, t_cpu = oracle_sample(lambda lo, hi: oracle.search_pq(oix, q[lo:hi], k[lo:hi], npb[lo:hi], ratio, lut_u8=args.lut_u8),
                                    min(args.cpu_queries, nq), args.cpu_seconds, per_call)
         cpu = {"value": round(nqc / t_cpu, 2), "unit": "queries/s", "cores": oracle.num_threads(), "kind": "oracle",
                "sample": f"first {nqc} queries of the batch (their own k and nprobe), same r, {per_call} per "
@@ -728,7 +731,8 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         "ms_per_step": round(graph_s / args.steps * 1e3, 3), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "pq": f"{w.pq_m}x{w.pq_bits}",
-                   "nq": nq, "k_mean": float(k.mean()), "nprobe_mean": float(npb.mean()), "ratio": ratio},
+                   "nq": nq, "k_mean": float(k.mean()), "nprobe_mean": float(npb.mean()), "ratio": ratio,
+                   "tables": "u8" if args.lut_u8 else "f32"},
         "recall": None if rec is None else round(rec, 4),
         "recall_target_reached": rec is not None and rec >= args.target_recall,
         "graph": {"qps": round(value, 1), "batch_ms_p50": round(float(np.percentile(graph_ms, 50)), 3),

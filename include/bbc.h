@@ -147,6 +147,14 @@ typedef struct {
                           call returns once the work is enqueued; 0: host pointers, the
                           call returns when the results are in place */
   void* stream;        /* hipStream_t; NULL = the default stream */
+  int32_t lut_u8;      /* PQ only, 1: one-byte distance tables with integer sums (row f2 of the
+                          fast-scan accounting).  Per (query, list) table: lo_m = the smallest
+                          entry of sub-space m, span = the largest (max - lo_m) over m, delta =
+                          span / 255 (1 if not positive), u = min(255, floor((entry - lo_m) *
+                          (1 / delta) + 0.5)); key = sum_m lo_m + K * delta with K the integer
+                          sum of u over the code's sub-spaces (float32 steps in that order).
+                          Candidates follow these keys; exact re-rank unchanged.  Supported for
+                          the grouped scan shapes (8-bit M=16 or 32, 4-bit M=32 or 48) */
 } bbc_search_params;
 
 /* Search nq queries [nq][d] float32.  k[nq] and nprobe[nq] are host arrays

@@ -74,6 +74,7 @@ def lib():
             L.orc_pq_lut_u8.argtypes = [vp, i32, i32, vp, vp, vp]
             L.orc_pq_key_u8.restype = f32
             L.orc_pq_key_u8.argtypes = [vp, vp, i32, i32, f32, f32]
+            L.orc_pq_keys_u8.argtypes = [vp, vp, i64, i32, i32, f32, f32, vp]
             L.orc_kmeans_assign.argtypes = [vp, vp, i64, i32, vp, i32, vp]
             L.orc_kmeans_update.argtypes = [vp, vp, i64, i32, vp, i32, vp]
             L.orc_kmeans_train.argtypes = [vp, i32, vp, i64, vp, i32, i32, vp]
@@ -275,8 +276,9 @@ def pq_keys_u8(u, base, delta, codes):
     u = np.ascontiguousarray(u, dtype=np.uint8)
     codes = np.ascontiguousarray(codes, dtype=np.uint8)
     M, ksub = u.shape
-    return np.array([lib().orc_pq_key_u8(_p(u), _p(codes[i]), M, ksub, float(base), float(delta))
-                     for i in range(codes.shape[0])], np.float32)
+    out = np.empty(codes.shape[0], np.float32)
+    lib().orc_pq_keys_u8(_p(u), _p(codes), codes.shape[0], M, ksub, float(base), float(delta), _p(out))
+    return out
 
 
 def pq_keys(lut, codes):

@@ -448,6 +448,11 @@ float orc_pq_key_u8(const uint8_t* u, const uint8_t* code, int32_t M, int32_t ks
   return base + t;
 }
 
+void orc_pq_keys_u8(const uint8_t* u, const uint8_t* codes, int64_t n, int32_t M, int32_t ksub, float base,
+                    float delta, float* out) {
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_pq_key_u8(u, codes + i * M, M, ksub, base, delta);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Index build: IVF k-means and PQ                                           */
 /* ------------------------------------------------------------------------ */

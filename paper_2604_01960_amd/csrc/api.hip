@@ -740,6 +740,10 @@ int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, c
   if (p->sample_factor < 0 || p->sample_factor > 64) return fail(BBC_EINVAL, "sample_factor must be in [0, 64]");
   if (p->collector != BBC_COLLECT_BUCKET && p->collector != BBC_COLLECT_HEAP && p->collector != BBC_COLLECT_SORT)
     return fail(BBC_EINVAL, "unknown collector");
+  if (p->lut_u8 != 0 && p->lut_u8 != 1) return fail(BBC_EINVAL, "lut_u8 must be 0 or 1");
+  if (p->lut_u8 && ix->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "lut_u8 applies to PQ indexes only");
+  if (p->lut_u8 && !bbc::pq_scan_grouped_shape(ix->bits, ix->M, ix->d))
+    return fail(BBC_EUNSUPPORTED, "one-byte tables need a grouped scan shape (8-bit M=16 or 32, 4-bit M=32 or 48)");
   if (out_off[0] != 0) return fail(BBC_EINVAL, "out_offsets[0] must be 0");
   for (int64_t i = 0; i < nq; ++i) {
     if (k[i] < 1) return fail(BBC_EINVAL, "k must be >= 1");
@@ -1334,6 +1338,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   sa.key_off = d_ko;
   sa.nlist = ix->nlist; sa.npairs = npairs; sa.num_cu = ix->num_cu; sa.nxcd = ix->nxcd;
   sa.scan_variant = ix->scan_variant;
+  sa.lut_u8 = p->lut_u8;
   sa.pair_cnt = reinterpret_cast<uint32_t*>(A + L.pair_cnt);
   sa.sorted_pairs = reinterpret_cast<uint32_t*>(A + L.sorted_pairs);
   sa.sorted_q = reinterpret_cast<uint32_t*>(A + L.sorted_q);

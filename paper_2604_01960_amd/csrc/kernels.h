@@ -89,8 +89,14 @@ struct PqScanArgs {
   float* surv_key; uint32_t* surv_pos; const int64_t* surv_off; uint32_t* pair_nsurv; uint32_t* n_rejected;
   float* trace_keys;        // optional: every key by slot (key_off regions)
   int scan_variant;         // grouped-scan block geometry: 0 (512 threads, 2 codes each), 1 (512, 1), 2 (1024, 1)
+  int lut_u8;               // one-byte tables with integer sums (grouped shapes only)
 };
-constexpr int SCAN_GROUP = 4;  // queries of one list scanned together
+// Shapes the grouped scan (and so the one-byte tables) supports.
+bool pq_scan_grouped_shape(int bits, int M, int d);
+constexpr int SCAN_GROUP = 4;  // queries of one list scanned together (float tables)
+constexpr int SCAN_GROUP_MAX = 8;
+// queries per scan group: one-byte tables of 4-bit codes take 8, the rest 4
+__host__ __device__ constexpr int scan_group_of(bool u8, int bits) { return u8 && bits == 4 ? 8 : 4; }
 int64_t pair_slots(int64_t npairs, int nlist);  // sorted_pairs capacity
 // Counting sort of the (query, rank) pairs by (rank >= nsample, list).
 hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s);

@@ -54,10 +54,10 @@ __global__ void pair_count_kernel(PqScanArgs a) {
 }
 
 // In place: per-bin counts -> exclusive prefix of the counts rounded up to a
-// multiple of SCAN_GROUP (one block).  Also records the start of the second
+// multiple of the scan's group size (one block).  Also records the start of the second
 // phase (bin nlist) and the padded total in split[0], split[1].
 __global__ __launch_bounds__(1024) void pair_offsets_kernel(uint32_t* __restrict__ cnt_fill, int nbins, int nlist,
-                                                            uint32_t* __restrict__ split) {
+                                                            int group, uint32_t* __restrict__ split) {
   __shared__ uint32_t carry_s;
   __shared__ uint32_t wsum[16];
   if (threadIdx.x == 0) carry_s = 0;
@@ -65,7 +65,7 @@ __global__ __launch_bounds__(1024) void pair_offsets_kernel(uint32_t* __restrict
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int base = 0; base < nbins; base += 1024) {
     const int j = base + threadIdx.x;
-    uint32_t v = j < nbins ? (cnt_fill[j] + SCAN_GROUP - 1) / SCAN_GROUP * SCAN_GROUP : 0u;
+    uint32_t v = j < nbins ? (cnt_fill[j] + group - 1) / group * group : 0u;
     uint32_t incl = v;
     for (int off = 1; off < 64; off <<= 1) {
       uint32_t o = __shfl_up(incl, off);
@@ -188,9 +188,22 @@ struct PairOut {
 // interleaved, to keep more table reads in flight per wave.  Block geometries
 // (threads NT, codes per thread O) are compiled as variants: (512, 2), the
 // default, (512, 1) and (1024, 1).
-template <int MODE, int BITS, int M, int DSUB, int NT, int O>
+//
+// One-byte tables (U8): after the float table is built, each (query,
+// sub-space) gets its minimum lo_m and each query one step delta = (largest
+// max - lo_m over the sub-spaces) / 255 and base = sum of lo_m; every entry
+// becomes u = min(255, floor((entry - lo_m) * (1 / delta) + 0.5)).  An
+// entry's row holds the group's codes in 16-bit halves of 32-bit words
+// (queries 2h and 2h+1 in word h), so one 32-bit integer add accumulates two
+// queries (sums stay below 2^16 for M < 257); the key is base + K * delta.
+// Rows are written in place over the float rows (a one-byte row is half the
+// size of a float row, so row e's bytes land inside float rows below e: each
+// round of NT rows is read before a barrier and written after it).  4-bit
+// shapes scan 8 queries per group (one 16-byte read per code serves all 8),
+// 8-bit shapes 4 (their float staging table would not fit twice as wide).
+template <int MODE, int BITS, int M, int DSUB, int NT, int O, bool U8>
 __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
-  constexpr int G = SCAN_GROUP;
+  constexpr int G = scan_group_of(U8, BITS);
   constexpr int KSUB = 1 << BITS;
   constexpr int NENT = M * KSUB;
   constexpr int EPT = (NENT + NT - 1) / NT;   // table entries owned by each thread
@@ -198,10 +211,17 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   constexpr int D = M * DSUB;
   constexpr int CODE_BYTES = BITS == 8 ? M : (M + 1) / 2;
   constexpr int NVEC = (CODE_BYTES + 15) / 16;
-  static_assert(G == 4, "the table rows are float4");
-  extern __shared__ __align__(16) float4 lut4[];   // [NENT]: entry e for the group's 4 queries
+  constexpr int NW = NT / 64;
+  constexpr int FR = G / 4;                   // float4 rows per table entry (float staging)
+  constexpr int UW = G / 2;                   // 32-bit words per one-byte row
+  static_assert(G == 4 || (U8 && G == 8), "float rows serve 4 queries, one-byte rows 4 or 8");
+  static_assert(!U8 || M * 255 < 65536, "16-bit partial sums");
+  extern __shared__ __align__(16) float4 lut4[];   // [NENT * FR]: entry e for the group's queries
   __shared__ __align__(16) float res[G][D];
   __shared__ uint32_t wcnt[2][G][NT / 64];
+  __shared__ float u8_lo[U8 ? M : 1][G];      // per (sub-space, query) minimum
+  __shared__ float u8_wspan[U8 ? NW : 1][G];  // per wave: largest range seen
+  __shared__ float u8_par[3][G];              // per query: base, delta, 1 / delta
 
   // the codebook is the same for every group: the owned codewords are loaded once
   float creg[REGCB ? EPT : 1][DSUB];
@@ -351,12 +371,121 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
           }
           out[g] = acc;
         }
-        lut4[e] = make_float4(out[0], out[1], out[2], out[3]);
+#pragma unroll
+        for (int h = 0; h < FR; ++h)
+          lut4[e * FR + h] = make_float4(out[4 * h], out[4 * h + 1], out[4 * h + 2], out[4 * h + 3]);
       }
       asm volatile("" ::: "memory");  // one entry's LDS reads at a time
     }
     __syncthreads();
     if (c + nw < hi) fetch_places();
+    float kbase[G], kdelta[G];
+    if constexpr (U8) {
+      const int wv = threadIdx.x >> 6;
+      float wspan[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) wspan[g] = 0.0f;
+      // minimum and maximum of each (sub-space, query): a wave per sub-space
+      // (four sub-spaces per wave at a time for 16-entry sub-spaces)
+      constexpr int SPW = KSUB >= 64 ? 1 : 64 / KSUB;
+      constexpr int LPS = KSUB >= 64 ? 64 : KSUB;  // lanes per sub-space
+      auto row_vals = [&](int e, float* v) {
+#pragma unroll
+        for (int h = 0; h < FR; ++h) {
+          const float4 f = lut4[e * FR + h];
+          v[4 * h] = f.x; v[4 * h + 1] = f.y; v[4 * h + 2] = f.z; v[4 * h + 3] = f.w;
+        }
+      };
+      for (int m0 = wv * SPW; m0 < M; m0 += NW * SPW) {
+        const int m = m0 + lane / LPS;
+        const bool okm = m < M;
+        float lo[G], hv[G];
+        row_vals((okm ? m : 0) * KSUB + lane % LPS, lo);
+#pragma unroll
+        for (int g = 0; g < G; ++g) hv[g] = lo[g];
+        for (int b = lane % LPS + LPS; b < KSUB; b += LPS) {
+          float f[G];
+          row_vals((okm ? m : 0) * KSUB + b, f);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            lo[g] = fminf(lo[g], f[g]);
+            hv[g] = fmaxf(hv[g], f[g]);
+          }
+        }
+#pragma unroll
+        for (int off = LPS / 2; off >= 1; off >>= 1)
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            lo[g] = fminf(lo[g], __shfl_xor(lo[g], off));
+            hv[g] = fmaxf(hv[g], __shfl_xor(hv[g], off));
+          }
+        if (okm) {
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            if (lane % LPS == 0) u8_lo[m][g] = lo[g];
+            wspan[g] = fmaxf(wspan[g], hv[g] - lo[g]);
+          }
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1)
+#pragma unroll
+        for (int g = 0; g < G; ++g) wspan[g] = fmaxf(wspan[g], __shfl_xor(wspan[g], off));
+      if (lane == 0) {
+#pragma unroll
+        for (int g = 0; g < G; ++g) u8_wspan[wv][g] = wspan[g];
+      }
+      __syncthreads();
+      if (threadIdx.x < G) {
+        const int g = threadIdx.x;
+        float span = 0.0f;
+        for (int w2 = 0; w2 < NW; ++w2) span = fmaxf(span, u8_wspan[w2][g]);
+        float dl = span / 255.0f;
+        if (!(dl > 0.0f)) dl = 1.0f;
+        float base = 0.0f;
+        for (int m = 0; m < M; ++m) base = base + u8_lo[m][g];
+        u8_par[0][g] = base;
+        u8_par[1][g] = dl;
+        u8_par[2][g] = 1.0f / dl;
+      }
+      __syncthreads();
+      float inv[G];
+#pragma unroll
+      for (int g = 0; g < G; ++g) inv[g] = u8_par[2][g];
+      uint32_t* lut32 = reinterpret_cast<uint32_t*>(lut4);
+#pragma unroll
+      for (int i = 0; i < EPT; ++i) {
+        const int e = threadIdx.x + i * NT;
+        uint32_t row[UW];
+#pragma unroll
+        for (int h = 0; h < UW; ++h) row[h] = 0u;
+        if (e < NENT) {
+          const int m = e / KSUB;
+          float fv[G];
+          row_vals(e, fv);
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            float t = fv[g] - u8_lo[m][g];
+            t = t * inv[g];
+            t = t + 0.5f;
+            uint32_t u = (uint32_t)t;
+            u = u > 255u ? 255u : u;
+            row[g >> 1] |= u << (16 * (g & 1));
+          }
+        }
+        __syncthreads();  // every float row this round overwrites has been read
+        if (e < NENT) {
+#pragma unroll
+          for (int h = 0; h < UW; ++h) lut32[e * UW + h] = row[h];
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        kbase[g] = u8_par[0][g];
+        kdelta[g] = u8_par[1][g];
+      }
+    }
     const int64_t lbeg = uniform(a.list_off[j]);
     const int64_t nobj = uniform(a.list_off[j + 1]) - lbeg;
     BlockCompactor<G, NT, O> comp;
@@ -382,6 +511,41 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
       for (int o = 0; o < O; ++o)
 #pragma unroll
         for (int g = 0; g < G; ++g) acc[o][g] = 0.0f;
+      if constexpr (U8) {
+        const uint32_t* lut32 = reinterpret_cast<const uint32_t*>(lut4);
+        uint32_t acc16[O][UW];  // word h: 16-bit sums of queries 2h (low) and 2h+1 (high)
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+#pragma unroll
+          for (int h = 0; h < UW; ++h) acc16[o][h] = 0u;
+        if (active[0])
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+          if (m % (4 / O) == 0 && m) asm volatile("" ::: "memory");
+#pragma unroll
+          for (int o = 0; o < O; ++o) {
+            uint32_t code;
+            if (BITS == 8) code = (w[o][m >> 2] >> (8 * (m & 3))) & 0xffu;
+            else code = (w[o][m >> 3] >> (4 * (m & 7))) & 0xfu;
+            const uint32_t* row = lut32 + (m * KSUB + code) * UW;
+            if constexpr (UW == 4) {
+              const uint4 v = *reinterpret_cast<const uint4*>(row);
+              acc16[o][0] += v.x; acc16[o][1] += v.y; acc16[o][2] += v.z; acc16[o][3] += v.w;
+            } else {
+              const uint2 v = *reinterpret_cast<const uint2*>(row);
+              acc16[o][0] += v.x; acc16[o][1] += v.y;
+            }
+          }
+        }
+#pragma unroll
+        for (int o = 0; o < O; ++o)
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            const uint32_t K = (acc16[o][g >> 1] >> (16 * (g & 1))) & 0xffffu;
+            const float t = (float)K * kdelta[g];
+            acc[o][g] = kbase[g] + t;
+          }
+      } else {
       if (active[0])  // waves past the end of the list skip the table reads
 #pragma unroll
       for (int m = 0; m < M; ++m) {
@@ -398,6 +562,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
           acc[o][2] = acc[o][2] + v.z;
           acc[o][3] = acc[o][3] + v.w;
         }
+      }
       }
       if (base == 0 && c + nw < hi) fetch_inputs();
 #pragma unroll
@@ -530,12 +695,24 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   }
 }
 
+template <int BITS, int M, int DSUB, int NT, int O, bool U8>
+static void launch_grouped_t(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
+  if (a.mode == 0)
+    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8>), dim3(blocks), dim3(NT), lds, s, a);
+  else
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, U8>), dim3(blocks), dim3(NT), lds, s, a);
+}
+
 template <int BITS, int M, int DSUB, int NT, int O>
 static void launch_grouped(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
-  if (a.mode == 0)
-    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O>), dim3(blocks), dim3(NT), lds, s, a);
-  else
-    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O>), dim3(blocks), dim3(NT), lds, s, a);
+  if (a.lut_u8) launch_grouped_t<BITS, M, DSUB, NT, O, true>(a, blocks, lds, s);
+  else launch_grouped_t<BITS, M, DSUB, NT, O, false>(a, blocks, lds, s);
+}
+
+// Pairs per scan group of this search: the grouped kernel's group for a
+// grouped shape, SCAN_GROUP for the generic one-pair-per-block kernel.
+static int pair_group(const PqScanArgs& a) {
+  return pq_scan_grouped_shape(a.bits, a.M, a.d) ? scan_group_of(a.lut_u8 != 0, a.bits) : SCAN_GROUP;
 }
 
 template <int BITS, int M, int DSUB>
@@ -543,7 +720,7 @@ static bool try_grouped(const PqScanArgs& a, hipStream_t s) {
   if (a.bits != BITS || a.M != M || a.d != M * DSUB) return false;
   int blocks = (a.num_cu / a.nxcd) * a.nxcd;
   if (blocks < a.nxcd) blocks = a.nxcd;
-  const size_t lds = sizeof(float4) * (size_t)M * (1 << BITS);
+  const size_t lds = sizeof(float) * (size_t)scan_group_of(a.lut_u8 != 0, BITS) * M * (1 << BITS);
   switch (a.scan_variant) {
     case 1: launch_grouped<BITS, M, DSUB, 512, 1>(a, blocks, lds, s); break;
     case 2: launch_grouped<BITS, M, DSUB, 1024, 1>(a, blocks, lds, s); break;
@@ -552,7 +729,12 @@ static bool try_grouped(const PqScanArgs& a, hipStream_t s) {
   return true;
 }
 
-int64_t pair_slots(int64_t npairs, int nlist) { return npairs + 2 * (int64_t)nlist * (SCAN_GROUP - 1); }
+bool pq_scan_grouped_shape(int bits, int M, int d) {
+  return (bits == 8 && M == 32 && d == 128) || (bits == 8 && M == 16 && d == 128) ||
+         (bits == 4 && M == 48 && d == 96) || (bits == 4 && M == 32 && d == 128);
+}
+
+int64_t pair_slots(int64_t npairs, int nlist) { return npairs + 2 * (int64_t)nlist * (SCAN_GROUP_MAX - 1); }
 
 hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s) {
   if (a.npairs <= 0) return hipSuccess;
@@ -563,7 +745,8 @@ hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s) {
                      a.sorted_pairs, slots, NO_PAIR);
   const unsigned g = (unsigned)std::min<int64_t>((a.npairs + 255) / 256, 4096);
   hipLaunchKernelGGL(pair_count_kernel, dim3(g), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, a.pair_split);
+  hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, pair_group(a),
+                     a.pair_split);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(g), dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -35,12 +35,13 @@ def make_gpu_index(bbc, ix):
                                ix["base"])
 
 
-def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2):
-    """Per query, everything the GPU trace reports, from the oracle alone."""
+def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2, lut_u8=False):
+    """Per query, everything the GPU trace reports, from the oracle alone
+    (lut_u8: one-byte tables with integer sums)."""
     nq = q.shape[0]
     kk = np.broadcast_to(np.asarray(k), (nq,)).astype(np.int64)
     npb = np.broadcast_to(np.asarray(nprobe), (nq,)).astype(np.int64)
-    res = oracle.search_pq(ix, q, kk, npb, ratio, debug=True)
+    res = oracle.search_pq(ix, q, kk, npb, ratio, debug=True, lut_u8=lut_u8)
     out = []
     for i in range(nq):
         lists = res["probe_lists"][res["probe_off"][i]:res["probe_off"][i + 1]]
@@ -48,7 +49,10 @@ def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2):
         for j in lists:
             lut = oracle.pq_lut(q[i], ix["centroids"][j], ix["codebook"], ix["M"], ix["ksub"])
             sl = slice(ix["list_off"][j], ix["list_off"][j + 1])
-            keys.append(oracle.pq_keys(lut, ix["codes"][sl]))
+            if lut_u8:
+                keys.append(oracle.pq_keys_u8(*oracle.pq_lut_u8(lut), ix["codes"][sl]))
+            else:
+                keys.append(oracle.pq_keys(lut, ix["codes"][sl]))
             ids.append(ix["list_ids"][sl])
             sizes.append(sl.stop - sl.start)
         keys = np.concatenate(keys) if keys else np.zeros(0, np.float32)

@@ -155,3 +155,68 @@ def test_rerank_forms(bbc, form, shape):
     tr = g.search_traced(q, k, npb, ratio=2.0, buckets=64, nsample=2)
     exp = expected_steps(ix, q, k, npb, 2.0, 64, 2)
     check_trace(tr, exp, 64)
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2"])
+@pytest.mark.parametrize("cfg", [
+    # (base workload, n, nlist, M, bits, nq, k, nprobe, ratio, m, nsample)
+    ("ivfpq_100k_d128", 20000, 64, 16, 8, 12, 300, 12, 2.0, 64, 8),
+    ("ivfpq_1m_d128", 24000, 60, 32, 8, 10, 700, 9, 1.5, 256, 3),
+    ("ivfpq4_10m_d96", 20000, 50, 48, 4, 10, 400, 10, 2.5, 80, 8),
+])
+def test_one_byte_tables_match_oracle(bbc, cfg, variant):
+    """One-byte tables with integer sums: estimated keys (base + K * delta),
+    codebook, threshold bucket, candidates and results equal the oracle's
+    one-byte path, in each scan block shape."""
+    import os
+    base, n, nlist, M, bits, nq, k, nprobe, ratio, m, ns = cfg
+    w, ix, q = oracle_pq_index(base, n, nlist, M, bits, nq)
+    print(f"[case] u8 tables {base} n={n} M={M} bits={bits} k={k} nprobe={nprobe} variant={variant}", flush=True)
+    old = os.environ.get("BBC_SCAN_VARIANT")
+    os.environ["BBC_SCAN_VARIANT"] = variant
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        if old is None:
+            os.environ.pop("BBC_SCAN_VARIANT")
+        else:
+            os.environ["BBC_SCAN_VARIANT"] = old
+    rng = np.random.default_rng(int(variant) + 3)
+    kk = rng.integers(1, 2 * k, nq).astype(np.int32)
+    npb = rng.integers(1, nprobe + 1, nq).astype(np.int32)
+    for kq, nq_probe in ((k, nprobe), (kk, npb)):
+        tr = g.search_traced(q, kq, nq_probe, ratio=ratio, buckets=m, nsample=ns, lut_u8=True)
+        exp = expected_steps(ix, q, kq, nq_probe, ratio, m, ns, lut_u8=True)
+        check_trace(tr, exp, m)
+    # the device-I/O search returns the same as the traced one
+    import torch
+    ids, dists, counts, off = g.search(torch.from_numpy(q).to("cuda:0"), kk, npb, ratio=ratio, buckets=m,
+                                       nsample=ns, lut_u8=True)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(ids.cpu().numpy(), tr["ids"])
+    np.testing.assert_array_equal(dists.cpu().numpy(), tr["dists"])
+    g.free()
+
+
+def test_one_byte_tables_refused_where_unsupported(bbc):
+    """A scan shape without the grouped kernel refuses one-byte tables
+    (BBC_EUNSUPPORTED); so does a RaBitQ index (BBC_EINVAL)."""
+    import oracle
+    import synth
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 4000, 8, 8, 8, 3)
+    g = make_gpu_index(bbc, ix)
+    with pytest.raises(bbc.BBCError) as e:
+        g.search(q, 10, 2, lut_u8=True)
+    assert e.value.code == bbc.EUNSUPPORTED
+    g.free()
+    d, n, nlist = 64, 2000, 4
+    w = synth.small_workload("ivfrabitq_1m_d960", n=n, nlist=nlist, nq=2, d=d, seed_index=2)
+    x = synth.base_vectors(w)
+    tr, ip = synth.kmeans_draws(n, nlist, 64 * nlist, 0)
+    rix = oracle.build_ivf_rabitq(x, nlist, tr, ip, synth.rotation_orthogonal(d, 302))
+    g = bbc.Index.create_rabitq(rix["centroids"], rix["list_off"], rix["list_ids"], rix["P"], rix["codes"],
+                                rix["factors"], x, metric=rix["metric"])
+    with pytest.raises(bbc.BBCError) as e:
+        g.search(synth.query_vectors(w), 10, 2, lut_u8=True)
+    assert e.value.code == bbc.EINVAL
+    g.free()
