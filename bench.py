@@ -248,6 +248,8 @@ def main():
     ap.add_argument("--cpu-queries-1t", type=int, default=200, help="oracle queries timed on one thread")
     ap.add_argument("--o64-queries", type=int, default=100, help="queries searched by the float64 oracle O_64")
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
+    ap.add_argument("--early-rerank", action="store_true",
+                    help="PQ: early re-rank during the scan (Algorithm 4)")
     ap.add_argument("--lut-u8", action="store_true",
                     help="PQ: one-byte distance tables with integer sums (fast-scan table accounting)")
     ap.add_argument("--serve-qps", type=float, default=0.0, help="serving: arrival rate (default: the workload's)")
@@ -334,14 +336,14 @@ def main():
         if fixed_np and fixed_r:
             rec = None
             if gt is not None:
-                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki], lut_u8=args.lut_u8)
+                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
                 rec = recall_at_k(ids, off, gt, k)
             op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=rec)
             continue
         cands = []
         for npb in nprobe_grid:
             for r in ratio_grid:
-                ids, _, _, off = index.search(rq, k, npb, ratio=r, lut_u8=args.lut_u8)
+                ids, _, _, off = index.search(rq, k, npb, ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
                 rec = recall_at_k(ids, off, gt, k)
                 if rec >= args.target_recall:
                     cands.append(dict(nprobe=npb, ratio=r, recall=rec))
@@ -349,17 +351,17 @@ def main():
         if not cands:
             raise SystemExit(f"recall {args.target_recall} not reached for k={k}")
         for c in cands:  # one timed full batch per candidate
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             torch.cuda.synchronize()
             c["probe_ms"] = (time.perf_counter() - t) * 1e3
         # the fastest candidate whose recall over the whole batch reaches the
         # target (the sweep's sample only shortlists)
         best = None
         for c in sorted(cands, key=lambda c: c["probe_ms"]):
-            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8)
+            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             torch.cuda.synchronize()
             c["recall_batch"] = recall_device(torch, o[0], gt_full_ids, k)
             if c["recall_batch"] >= args.target_recall:
@@ -380,7 +382,7 @@ def main():
         for k in ks:
             if per_k_events is not None:
                 per_k_events[k][0].record()
-            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k], lut_u8=args.lut_u8)
+            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             if per_k_events is not None:
                 per_k_events[k][1].record()
 
@@ -427,13 +429,15 @@ def main():
             ref = None
             for col in ("bucket", "heap", "sort"):
                 o = (torch.empty_like(outs[k][0]), torch.empty_like(outs[k][1]), torch.empty_like(outs[k][2]))
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8)
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8,
+                             early_rerank=args.early_rerank and col == "bucket")
                 torch.cuda.synchronize()
                 bbc.stage_times(reset=True)
                 bbc.stage_timing(True)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8)
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8,
+                             early_rerank=args.early_rerank and col == "bucket")
                 e1.record()
                 torch.cuda.synchronize()
                 bbc.stage_timing(False)
@@ -451,12 +455,14 @@ def main():
     # ---- sizes for the algorithmic byte counts ---------------------------------
     sizes = {}
     for k in ks:
-        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"], lut_u8=args.lut_u8)
+        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
         sizes[k] = dict(S=int(c["n_scanned"].sum()), Kc=int(c["n_cand"].sum()),
                         sample_keys=int(c["n_sample_keys"].sum()),
                         recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()),
                         sample_lists_mean=float(c["n_sample_lists"].mean()),
                         survivors_mean=float(c["n_survivors"].mean()))
+        if args.early_rerank:
+            sizes[k].update(early_mean=float(c["n_early"].mean()), early_used_mean=float(c["n_early_used"].mean()))
     d = w.d
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2
     # algorithmic bytes per step of the kernels that dominate their stage
@@ -573,7 +579,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "pq": f"{w.pq_m}x{w.pq_bits}",
                    "nq": nq, "k": ks, "collector": "bucket", "buckets": 256, "nsample": 8,
-                   "tables": "u8" if args.lut_u8 else "f32"},
+                   "tables": "u8" if args.lut_u8 else "f32", "early_rerank": bool(args.early_rerank)},
         "per_k": per_k,
         "latency_ms": {"p50": round(float(np.percentile(sum(lat.values(), []), 50)), 3),
                        "p99": round(float(np.percentile(sum(lat.values(), []), 99)), 3),
@@ -626,7 +632,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         ratio = float(args.ratio.split(",")[0])
         rec = None
         if gt is not None:
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio, lut_u8=args.lut_u8)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             rec = mean_recall(ids, off)
     else:
         # nprobe is fixed per query by the workload, so a query with few
@@ -635,7 +641,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         # smallest r within 0.005 of the best recall)
         ratio, rec, curve = None, None, []
         for r in (1.5, 2.0, 3.0, 4.0, 6.0, 8.0):
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r, lut_u8=args.lut_u8)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
             rr = mean_recall(ids, off)
             log(f"ratio {r}: mean recall {rr:.4f}")
             curve.append((r, rr))
@@ -673,18 +679,18 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
             bbc.stage_timing(False)
         return el, np.array([a.elapsed_time(b) for a, b in ev])
 
-    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out, lut_u8=args.lut_u8), stage_timing=True)
+    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out, lut_u8=args.lut_u8, early_rerank=args.early_rerank), stage_timing=True)
     stages = bbc.stage_times(reset=True)
     t0 = time.time()
-    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True, lut_u8=args.lut_u8)
+    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
     plan_s = time.time() - t0
     info = plan.info()
     graph_s, graph_ms = timed(lambda: plan.execute())
     ids_g = out[0].cpu().numpy()
-    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"], lut_u8=args.lut_u8)
+    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
     same = bool(np.array_equal(ids_g, ref[0]))
     value = nq * args.steps / graph_s
-    sz = index.search_counts(q, k, npb, ratio=ratio, lut_u8=args.lut_u8)
+    sz = index.search_counts(q, k, npb, ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
     S, Kc, nsurv = int(sz["n_scanned"].sum()), int(sz["n_cand"].sum()), int(sz["n_survivors"].sum())
     nsk = int(sz["n_sample_keys"].sum())
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2
@@ -732,7 +738,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "nlist": w.nlist, "pq": f"{w.pq_m}x{w.pq_bits}",
                    "nq": nq, "k_mean": float(k.mean()), "nprobe_mean": float(npb.mean()), "ratio": ratio,
-                   "tables": "u8" if args.lut_u8 else "f32"},
+                   "tables": "u8" if args.lut_u8 else "f32", "early_rerank": bool(args.early_rerank)},
         "recall": None if rec is None else round(rec, 4),
         "recall_target_reached": rec is not None and rec >= args.target_recall,
         "graph": {"qps": round(value, 1), "batch_ms_p50": round(float(np.percentile(graph_ms, 50)), 3),

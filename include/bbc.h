@@ -155,6 +155,14 @@ typedef struct {
                           sum of u over the code's sub-spaces (float32 steps in that order).
                           Candidates follow these keys; exact re-rank unchanged.  Supported for
                           the grouped scan shapes (8-bit M=16 or 32, 4-bit M=32 or 48) */
+  int32_t early_rerank; /* PQ with the bucket collector, 1: the early re-rank of Algorithm 4 (the
+                          improved IVF+PQ search).  The codebook also predicts the threshold
+                          bucket tau_pred = the bucket of the sample's j-th smallest key,
+                          j = ceil(K_c * (sample keys) / S); while the lists after the sample are
+                          scanned, every object whose bucket is below tau_pred gets its exact
+                          distance at once, and a candidate among them is not re-ranked again.
+                          Results are identical to the plain search.  Needs float32 tables, a
+                          grouped scan shape and float32 rows (BBC_EUNSUPPORTED otherwise) */
 } bbc_search_params;
 
 /* Search nq queries [nq][d] float32.  k[nq] and nprobe[nq] are host arrays
@@ -223,6 +231,11 @@ typedef struct {
   int32_t* walk_path;                        /* RaBitQ: [nq] how the bounded walk found its exact stop
                                                 point: 0 no search, 1 in LDS, 2 in global memory,
                                                 3 item-by-item walk (a bound check failed) */
+  int32_t* tau_pred;                         /* early re-rank: [nq] predicted threshold bucket */
+  int64_t* n_early;                          /* early re-rank: [nq] exact distances computed during the
+                                                scan (objects after the sample below tau_pred) */
+  int64_t* n_early_used;                     /* early re-rank: [nq] candidates whose early exact key was
+                                                used (all early candidates of buckets below tau) */
 } bbc_search_trace;
 
 /* bbc_search with host I/O that also fills `trace` (est_keys, cand_ids and

@@ -40,7 +40,7 @@ class BBCError(RuntimeError):
 class SearchParams(C.Structure):
     _fields_ = [("ncand_ratio", C.c_double), ("collector", C.c_int32), ("buckets", C.c_int32),
                 ("nsample", C.c_int32), ("sample_factor", C.c_int32), ("device_io", C.c_int32),
-                ("stream", C.c_void_p), ("lut_u8", C.c_int32)]
+                ("stream", C.c_void_p), ("lut_u8", C.c_int32), ("early_rerank", C.c_int32)]
 
 
 class BuildParams(C.Structure):
@@ -61,7 +61,7 @@ class SearchTrace(C.Structure):
         "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
         "bucket_counts", "n_boundary", "est_keys", "est_off", "cand_ids", "cand_exact", "cand_off",
         "n_sample_lists", "n_survivors", "n_sample_keys", "est_lb", "est_ub", "n_visited", "kernel_forms",
-        "walk_path")]
+        "walk_path", "tau_pred", "n_early", "n_early_used")]
 
 
 _lib = None
@@ -296,13 +296,14 @@ class Index:
         return int(v)
 
     # -- search --------------------------------------------------------------
-    def _params(self, ratio, collector, buckets, nsample, device_io, stream, sample_factor=0, lut_u8=False):
+    def _params(self, ratio, collector, buckets, nsample, device_io, stream, sample_factor=0, lut_u8=False,
+                early_rerank=False):
         return SearchParams(float(ratio), COLLECT[collector] if isinstance(collector, str) else int(collector),
                             int(buckets), int(nsample), int(sample_factor), int(device_io), stream,
-                            int(bool(lut_u8)))
+                            int(bool(lut_u8)), int(bool(early_rerank)))
 
     def search(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-               nsample: int = 0, out=None, stream=None, lut_u8: bool = False):
+               nsample: int = 0, out=None, stream=None, lut_u8: bool = False, early_rerank: bool = False):
         """Search a batch.  numpy queries: blocking, returns (ids, dists, counts, offsets)
         as numpy.  torch GPU queries: enqueued on `stream` (default: torch's current
         stream); `out` may hold preallocated (ids, dists, counts) torch tensors."""
@@ -322,7 +323,7 @@ class Index:
                        torch.empty(int(off[-1]), dtype=torch.float32, device=queries.device),
                        torch.empty(nq, dtype=torch.int32, device=queries.device))
             ids, dists, counts = out
-            p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8)
+            p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank)
             _check(load().bbc_search(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                      _ptr(ids), _ptr(dists), _ptr(counts)))
             return ids, dists, counts, off
@@ -330,13 +331,13 @@ class Index:
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
-        p = self._params(ratio, collector, buckets, nsample, 0, stream, lut_u8=lut_u8)
+        p = self._params(ratio, collector, buckets, nsample, 0, stream, lut_u8=lut_u8, early_rerank=early_rerank)
         _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                  _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_noalloc(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                       nsample: int = 0, stream=None, lut_u8: bool = False):
+                       nsample: int = 0, stream=None, lut_u8: bool = False, early_rerank: bool = False):
         """bbc_search_noalloc: torch GPU queries and preallocated (ids, dists, counts)
         torch tensors; enqueued on `stream` (default: torch's current stream).  The
         workspace is the library's fixed per-GPU array (BBC_NOALLOC_MAX_BYTES)."""
@@ -353,13 +354,13 @@ class Index:
         ids, dists, counts = out
         if ids.numel() < int(off[-1]) or dists.numel() < int(off[-1]) or counts.numel() < nq:
             raise ValueError("output tensors are too small")
-        p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8)
+        p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank)
         _check(load().bbc_search_noalloc(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                          _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_counts(self, queries, k, nprobe, ratio: float = 2.0, buckets: int = 0, nsample: int = 0,
-                      lut_u8: bool = False):
+                      lut_u8: bool = False, early_rerank: bool = False):
         """Host search returning only per-query sizes: S, K_c, rechecked lists,
         threshold-bucket size."""
         q = _np(queries, np.float32)
@@ -371,17 +372,20 @@ class Index:
         r = dict(n_scanned=np.empty(nq, np.int64), n_cand=np.empty(nq, np.int64), n_recheck=np.empty(nq, np.int32),
                  n_boundary=np.empty(nq, np.int64), n_sample_lists=np.empty(nq, np.int32),
                  n_survivors=np.empty(nq, np.int64), n_sample_keys=np.empty(nq, np.int64))
+        if early_rerank:
+            r.update(tau_pred=np.empty(nq, np.int32), n_early=np.empty(nq, np.int64),
+                     n_early_used=np.empty(nq, np.int64))
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
         tr = SearchTrace(**{f: _ptr(v) for f, v in r.items()})
-        p = self._params(ratio, "bucket", buckets, nsample, 0, None, lut_u8=lut_u8)
+        p = self._params(ratio, "bucket", buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
         _check(load().bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                         _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
         return r
 
     def plan(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-             nsample: int = 0, autotune: bool = False, lut_u8: bool = False) -> Plan:
+             nsample: int = 0, autotune: bool = False, lut_u8: bool = False, early_rerank: bool = False) -> Plan:
         """Capture the search of a fixed device batch (torch queries and
         `out` = (ids, dists, counts) torch buffers) into a replayable plan."""
         import torch
@@ -392,7 +396,7 @@ class Index:
         off[1:] = np.cumsum(kk)
         ids, dists, counts = out
         assert ids.numel() == off[-1] and dists.numel() == off[-1] and counts.numel() == nq
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(load().bbc_plan_create(self._h, nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(queries), _ptr(off),
@@ -400,15 +404,15 @@ class Index:
         return Plan(h.value, self, (queries, ids, dists, counts))
 
     def server(self, mem_budget: int, max_slots: int = 1024, lanes: int = 2, ratio: float = 2.0,
-               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False) -> "Server":
+               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False) -> "Server":
         """A continuous-batching server over this index (bbc_server_*)."""
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank)
         h = C.c_void_p()
         _check(load().bbc_server_create(self._h, C.byref(p), int(mem_budget), int(max_slots), int(lanes),
                                         C.byref(h)))
         return Server(h.value, self)
 
-    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False) -> Dict[str, np.ndarray]:
+    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False, early_rerank: bool = False) -> Dict[str, np.ndarray]:
         """Host search returning per-query sizes only: S (n_scanned), the
         candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
         RaBitQ) and, for RaBitQ, n_visited."""
@@ -424,7 +428,7 @@ class Index:
             r["n_visited"] = np.empty(nq, np.int64)
             fields.append("n_visited")
         tr = SearchTrace(**{f: _ptr(r[f]) for f in fields})
-        p = self._params(ratio, "bucket", 0, 0, 0, None, lut_u8=lut_u8)
+        p = self._params(ratio, "bucket", 0, 0, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
@@ -433,7 +437,7 @@ class Index:
         return r
 
     def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                      nsample: int = 0, lut_u8: bool = False) -> Dict[str, np.ndarray]:
+                      nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False) -> Dict[str, np.ndarray]:
         """Host search that also returns every intermediate of the path."""
         q = _np(queries, np.float32)
         nq = q.shape[0]
@@ -443,7 +447,7 @@ class Index:
         off = np.zeros(nq + 1, np.int64)
         off[1:] = np.cumsum(kk)
         L = load()
-        p = self._params(ratio, collector, buckets, nsample, 0, None, lut_u8=lut_u8)
+        p = self._params(ratio, collector, buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
         r = dict(
             ids=np.empty(int(off[-1]), np.int64), dists=np.empty(int(off[-1]), np.float32),
             counts=np.empty(nq, np.int32), off=off,
@@ -458,10 +462,15 @@ class Index:
         if rabitq:
             r["n_visited"] = np.empty(nq, np.int64)
             r["walk_path"] = np.full(nq, -1, np.int32)
+        if early_rerank:
+            r["tau_pred"] = np.full(nq, -1, np.int32)
+            r["n_early"] = np.full(nq, -1, np.int64)
+            r["n_early_used"] = np.full(nq, -1, np.int64)
         tr = SearchTrace(**{f: _ptr(r[f]) for f in (
             "probe_lists", "probe_keys", "n_scanned", "n_cand", "n_recheck", "dmin", "delta", "map", "tau", "s",
             "bucket_counts", "n_boundary", "est_off", "cand_off", "n_sample_keys", "n_survivors", "kernel_forms")
-            + (("n_visited", "walk_path") if rabitq else ())})
+            + (("n_visited", "walk_path") if rabitq else ())
+            + (("tau_pred", "n_early", "n_early_used") if early_rerank else ())})
         _check(L.bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                    _ptr(r["ids"]), _ptr(r["dists"]), _ptr(r["counts"]), C.byref(tr)))
         # second pass for the ragged arrays, now that their sizes are known

@@ -725,6 +725,7 @@ struct Layout {
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb, qorder, rt_sorted, rt_bins, rt_ptb, rt_lcnt, rt_lpairs;
+  size_t surv_exact, n_early, n_used, rt_sidx, t_tpred;  // early re-rank
 };
 
 int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, const int32_t* k,
@@ -744,6 +745,13 @@ int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, c
   if (p->lut_u8 && ix->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "lut_u8 applies to PQ indexes only");
   if (p->lut_u8 && !bbc::pq_scan_grouped_shape(ix->bits, ix->M, ix->d))
     return fail(BBC_EUNSUPPORTED, "one-byte tables need a grouped scan shape (8-bit M=16 or 32, 4-bit M=32 or 48)");
+  if (p->early_rerank != 0 && p->early_rerank != 1) return fail(BBC_EINVAL, "early_rerank must be 0 or 1");
+  if (p->early_rerank) {
+    if (ix->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "early_rerank applies to PQ indexes only");
+    if (p->collector != BBC_COLLECT_BUCKET) return fail(BBC_EINVAL, "early_rerank needs the bucket collector");
+    if (p->lut_u8 || ix->fp16 || !bbc::pq_scan_grouped_shape(ix->bits, ix->M, ix->d))
+      return fail(BBC_EUNSUPPORTED, "early_rerank needs float32 tables, float32 rows and a grouped scan shape");
+  }
   if (out_off[0] != 0) return fail(BBC_EINVAL, "out_offsets[0] must be 0");
   for (int64_t i = 0; i < nq; ++i) {
     if (k[i] < 1) return fail(BBC_EINVAL, "k must be >= 1");
@@ -1231,10 +1239,18 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
   L.qorder = pl.add(4 * nq);
+  const bool early = bucket && p->early_rerank;
+  if (early) {
+    L.surv_exact = pl.add(4 * surv_off[nq]);
+    L.n_early = pl.add(4 * nq);
+    L.n_used = pl.add(4 * nq);
+    L.t_tpred = pl.add(4 * nq);
+  }
   // tile-major re-rank: its sort buffers
   const int rt_group = bbc::tile_rerank_group(d);
   const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (rt_group - 1);
   if (tile_rr) {
+    if (early) L.rt_sidx = pl.add(4 * ncand);  // results at the candidates' own places
     L.rt_sorted = pl.add(4 * ncand);
     L.rt_bins = pl.add(4 * bin_off[nq]);
     L.rt_ptb = pl.add(4 * npairs);
@@ -1347,6 +1363,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   sa.surv_key = surv_key; sa.surv_pos = surv_pos; sa.surv_off = d_vo; sa.pair_nsurv = pair_nsurv;
   sa.n_rejected = n_rejected;
   sa.trace_keys = tracing ? reinterpret_cast<float*>(A + L.keys) : nullptr;
+  sa.early = early;
+  sa.metric = ix->metric;
+  sa.vectors = reinterpret_cast<const float*>(ix->vectors);
+  sa.surv_exact = early ? reinterpret_cast<float*>(A + L.surv_exact) : nullptr;
+  sa.n_early = early ? reinterpret_cast<uint32_t*>(A + L.n_early) : nullptr;
 
   bbc::CollectArgs ca{};
   ca.nq = nq; ca.n_scanned = pa.n_scanned; ca.nprobe = d_np;
@@ -1367,6 +1388,8 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     ca.t_nboundary = reinterpret_cast<int64_t*>(A + L.t_nb);
     ca.t_nsample_keys = reinterpret_cast<int64_t*>(A + L.t_nsk);
   }
+  ca.early = early;
+  ca.t_tau_pred = early ? reinterpret_cast<int32_t*>(A + L.t_tpred) : nullptr;
 
   // scan of the sample lists, codebook, scan of the rest through the filter,
   // then the collector over the survivors
@@ -1384,11 +1407,22 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     {
       StageScope st(s, 2);
       sa.mode = 1;
+      if (early) HIP_TRY(bbc::launch_zero_u32(sa.n_early, nq, s));
       HIP_TRY(bbc::launch_pq_scan(sa, s));
     }
     {
       StageScope st(s, 3);
       HIP_TRY(bbc::launch_collect_bucket(ca, s));
+    }
+    if (early) {  // candidates re-ranked during the scan: (exact key, id) in place
+      StageScope st(s, 4);
+      bbc::EarlyFillArgs ea{};
+      ea.nq = nq; ea.n_cand = ca.n_cand; ea.cand_off = d_co; ea.cand_pos = ca.cand_pos; ea.surv_off = d_vo;
+      ea.surv_pos = surv_pos; ea.surv_exact = sa.surv_exact; ea.list_ids = ix->list_ids;
+      ea.cand_packed = reinterpret_cast<uint64_t*>(A + L.cand_packed);
+      ea.n_used = reinterpret_cast<uint32_t*>(A + L.n_used);
+      HIP_TRY(bbc::launch_zero_u32(ea.n_used, nq, s));
+      HIP_TRY(bbc::launch_early_fill(ea, max_kc, s));
     }
   } else {
     bbc::CompareArgs xa{};
@@ -1424,6 +1458,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);
       ta.lpairs_cap = rt_lpairs_cap;
       ta.group = rt_group;
+      if (early) ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L.rt_sidx);
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
     } else {
       if (ix->nlist <= bbc::QUERY_ORDER_MAX_LISTS && nq > 1) {
@@ -1496,6 +1531,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       if ((rc = cp(tr->n_sample_keys, L.t_nsk, 8 * nq))) return rc;
       HIP_TRY(hipMemcpyAsync(nsurv.data(), A + L.surv_total, 4 * nq, hipMemcpyDeviceToHost, s));
     }
+    std::vector<uint32_t> nearly(nq, 0), nused(nq, 0);
+    if (early) {
+      if ((rc = cp(tr->tau_pred, L.t_tpred, 4 * nq))) return rc;
+      HIP_TRY(hipMemcpyAsync(nearly.data(), A + L.n_early, 4 * nq, hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipMemcpyAsync(nused.data(), A + L.n_used, 4 * nq, hipMemcpyDeviceToHost, s));
+    }
     std::vector<int64_t> nsc(nq);
     HIP_TRY(hipMemcpyAsync(nsc.data(), A + L.n_scanned, 8 * nq, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(n_cand_h.data(), A + L.n_cand, 8 * nq, hipMemcpyDeviceToHost, s));
@@ -1504,6 +1545,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     if (tr->n_cand) std::memcpy(tr->n_cand, n_cand_h.data(), 8 * nq);
     if (tr->n_survivors && bucket)
       for (int64_t i = 0; i < nq; ++i) tr->n_survivors[i] = nsurv[i];
+    if (early) {
+      for (int64_t i = 0; i < nq; ++i) {
+        if (tr->n_early) tr->n_early[i] = nearly[i];
+        if (tr->n_early_used) tr->n_early_used[i] = nused[i];
+      }
+    }
     if (tr->est_off) {
       tr->est_off[0] = 0;
       for (int64_t i = 0; i < nq; ++i) tr->est_off[i + 1] = tr->est_off[i] + nsc[i];

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   __shared__ __align__(8) uint32_t bc[8];
   __shared__ uint32_t s_wred[2][NW];
   __shared__ float fbc[2];
+  __shared__ int32_t s_cpred;  // early re-rank: cell of the sample's jp-th smallest key (-1: none)
 
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
@@ -276,6 +277,11 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
       const int64_t below_dmax = __shfl(incl, 63);
       const int cmax = cell_of(dmax, dmin, delta);
       int64_t below = incl - sum;
+      // early re-rank (Algorithm 4): jp = ceil(K_c * (sample keys) / S); the
+      // sample's jp-th smallest key lies in the first cell whose running
+      // count of the T smallest reaches jp (jp <= T)
+      const int64_t jp = a.early && S > 0 ? (kc * Ts + S - 1) / S : 0;
+      uint32_t n_before = 0;  // cells whose running count stays below jp
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int e = 4 * lane + j;
@@ -283,7 +289,10 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
         const int64_t b = ((int64_t)m * be) / T;
         cmap[e] = (uint8_t)(b < m - 1 ? b : m - 1);
         below += h[j];
+        n_before += (below + (e + 1 > cmax ? T - below_dmax : 0)) < jp ? 1u : 0u;
       }
+      for (int off = 32; off >= 1; off >>= 1) n_before += __shfl_xor(n_before, off);
+      if (lane == 0) s_cpred = jp > 0 ? (int32_t)n_before : -1;
       if (lane == 0) {
         fbc[0] = dmin;
         fbc[1] = delta;
@@ -297,6 +306,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     fbc[0] = 0.0f;
     fbc[1] = 1.0f;
     bc[5] = 0u;
+    s_cpred = -1;
   }
   if (threadIdx.x == 0) { bc[6] = 0; bc[7] = 0; }
   __syncthreads();
@@ -307,6 +317,29 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     book->delta = fbc[1];
     book->dmax_bits = dmax_b;
     book->prune = prune;
+    // early re-rank: tau_pred = the bucket of that cell; a key is re-ranked
+    // early when its bucket is below tau_pred, i.e. its cell is below the
+    // first cell mapped to tau_pred or above, i.e. its image is below the
+    // smallest image of a key in that cell (binary search over the images
+    // of -inf .. +inf, on which the cell is monotone)
+    int32_t tp = 0;
+    uint32_t ebits = 0u;
+    if (s_cpred >= 0) {
+      tp = cmap[s_cpred];
+      if (tp > 0) {
+        int ep = 0;
+        while (ep < 255 && (int)cmap[ep] < tp) ++ep;
+        uint32_t lo = key_bits(-INFINITY), hi = key_bits(INFINITY);
+        while (hi - lo > 1u) {
+          const uint32_t mid = lo + (hi - lo) / 2u;
+          if (cell_of(bits_key(mid), fbc[0], fbc[1]) >= ep) hi = mid; else lo = mid;
+        }
+        ebits = hi;
+      }
+    }
+    book->tau_pred = tp;
+    book->early_bits = ebits;
+    if (a.t_tau_pred) a.t_tau_pred[qi] = tp;
   }
   // the sample's keys through the relaxed-threshold filter
   float* skey = a.surv_key + a.surv_off[qi];
@@ -593,7 +626,9 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     const uint64_t lt = (1ull << lane) - 1ull;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (b[u] < tau) cand[basec + (uint32_t)__popcll(mc[u] & lt)] = pv[u];
+      if (b[u] < tau)  // a survivor re-ranked early is handed on by its slot
+        cand[basec + (uint32_t)__popcll(mc[u] & lt)] =
+            (pv[u] & EARLY_FLAG) ? (EARLY_FLAG | (uint32_t)idx[u]) : pv[u];
       if (b[u] == tau) {
         const uint32_t bs = baseb + (uint32_t)__popcll(mb[u] & lt);
         const uint64_t pk = (uint64_t)idx[u];  // survivor slot, resolved below
@@ -610,7 +645,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     // members: survivor slot -> (key, id)
     for (int i = threadIdx.x; i < (int)nb; i += NT) {
       const int64_t x = (int64_t)bbuf[i];
-      bbuf[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x]]);
+      bbuf[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x] & EARLY_MASK]);
     }
     const int P = next_pow2((int)nb);
     for (int i = (int)nb + threadIdx.x; i < P; i += NT) bbuf[i] = ~0ull;
@@ -623,7 +658,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     // slots -> (key, id), radix select of the s-th, one pass over them
     for (int64_t i = threadIdx.x; i < nb; i += NT) {
       const int64_t x = (int64_t)bnd[i];
-      bnd[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x]]);
+      bnd[i] = pack_key_id(skey[x], (uint32_t)a.list_ids[spos[x] & EARLY_MASK]);
     }
     __syncthreads();
     const uint64_t thr =
@@ -639,7 +674,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     // 64-bit radix select over its members, then one pass to collect them
     auto get = [&](int64_t i, uint64_t& v) -> bool {
       if ((int)sbkt[i] != tau) return false;
-      v = pack_key_id(skey[i], (uint32_t)a.list_ids[spos[i]]);
+      v = pack_key_id(skey[i], (uint32_t)a.list_ids[spos[i] & EARLY_MASK]);
       return true;
     };
     uint64_t prefix = 0, mask = 0;
@@ -672,7 +707,8 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
     __syncthreads();
     for_each([&](int64_t i) {
       uint64_t v;
-      if (get(i, v) && v <= prefix) cand[nbelow + atomicAdd(&bc[3], 1u)] = spos[i];
+      if (get(i, v) && v <= prefix)
+        cand[nbelow + atomicAdd(&bc[3], 1u)] = (spos[i] & EARLY_FLAG) ? (EARLY_FLAG | (uint32_t)i) : spos[i];
     });
   }
   if (threadIdx.x == 0) {
@@ -687,6 +723,32 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
   }
   if (a.t_map) for (int e = threadIdx.x; e < 256; e += NT) a.t_map[qi * 256 + e] = cmap[e];
   if (a.t_counts) for (int b = threadIdx.x; b < m; b += NT) a.t_counts[qi * m + b] = (int32_t)counts[b];
+}
+
+// Candidates that reuse an early exact key: (exact key, id) at their place.
+// One block per query.
+__global__ __launch_bounds__(256) void early_fill_kernel(EarlyFillArgs a) {
+  const int64_t qi = blockIdx.x;
+  const int64_t kc = a.n_cand[qi];
+  const int64_t co = a.cand_off[qi], so = a.surv_off[qi];
+  uint32_t nused = 0;
+  for (int64_t i = threadIdx.x; i < kc; i += 256) {
+    const uint32_t c = a.cand_pos[co + i];
+    if (c & EARLY_FLAG) {
+      const int64_t slot = so + (c & EARLY_MASK);
+      const uint32_t pos = a.surv_pos[slot] & EARLY_MASK;
+      a.cand_packed[co + i] = pack_key_id(a.surv_exact[slot], (uint32_t)a.list_ids[pos]);
+      ++nused;
+    }
+  }
+  for (int off = 32; off >= 1; off >>= 1) nused += __shfl_xor(nused, off);
+  if ((threadIdx.x & 63) == 0 && nused) atomicAdd(&a.n_used[qi], nused);
+}
+
+hipError_t launch_early_fill(const EarlyFillArgs& a, int64_t max_kc, hipStream_t s) {
+  if (a.nq <= 0 || max_kc <= 0) return hipSuccess;
+  hipLaunchKernelGGL(early_fill_kernel, dim3((unsigned)a.nq), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s) {

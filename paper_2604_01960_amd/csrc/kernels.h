@@ -65,7 +65,19 @@ struct QueryBook {
   uint32_t dmax_bits;  // key image of d_max
   uint32_t prune;      // 1: keys above d_max are rejected at the scan
   uint8_t map[256];    // equal-width cell -> bucket
+  // early re-rank (Algorithm 4): the predicted threshold bucket and the
+  // smallest key image whose bucket reaches it (keys with a smaller image are
+  // re-ranked during the scan of the lists after the sample; 0: none)
+  int32_t tau_pred;
+  uint32_t early_bits;
 };
+
+// Early re-rank marks: a survivor re-ranked during the scan carries this bit
+// in its list position (positions are below 2^31); a candidate that reuses
+// such an exact key holds this bit and its survivor slot instead of its list
+// position.
+constexpr uint32_t EARLY_FLAG = 0x80000000u;
+constexpr uint32_t EARLY_MASK = 0x7fffffffu;
 
 struct PqScanArgs {
   const float* q; int64_t nq; int d; const float* cent;
@@ -90,9 +102,16 @@ struct PqScanArgs {
   float* trace_keys;        // optional: every key by slot (key_off regions)
   int scan_variant;         // grouped-scan block geometry: 0 (512 threads, 2 codes each), 1 (512, 1), 2 (1024, 1)
   int lut_u8;               // one-byte tables with integer sums (grouped shapes only)
+  // early re-rank (mode 1, grouped shapes, float32 rows): survivors whose key
+  // image is below their query's book->early_bits get their exact key now
+  int early; int metric; const float* vectors;   // rows in list-slot order
+  float* surv_exact;        // exact key by survivor slot (early survivors only)
+  uint32_t* n_early;        // [nq] survivors re-ranked during the scan (atomic adds)
 };
 // Shapes the grouped scan (and so the one-byte tables) supports.
 bool pq_scan_grouped_shape(int bits, int M, int d);
+// p[0, n) = 0 (a kernel, so that graph capture records no memset)
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s);
 constexpr int SCAN_GROUP = 4;  // queries of one list scanned together (float tables)
 constexpr int SCAN_GROUP_MAX = 8;
 // queries per scan group: one-byte tables of 4-bit codes take 8, the rest 4
@@ -118,12 +137,24 @@ struct CollectArgs {
   float* t_dmin; float* t_delta; uint8_t* t_map; int32_t* t_tau; int64_t* t_s; int32_t* t_counts;
   int64_t* t_nboundary;
   int64_t* t_nsample_keys;  // keys in the codebook sample (codebook kernel)
+  int early;                // codebook: also the predicted threshold of the early re-rank
+  int32_t* t_tau_pred;      // trace: the predicted threshold bucket (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
 // register slots per thread the codebook kernel takes for samples of up to
 // max_sample keys (16, 32, 48; 0 = samples read from memory in each pass)
 int codebook_form(int64_t max_sample);
 hipError_t launch_collect_bucket(const CollectArgs& a, hipStream_t s);
+
+// Early re-rank: each candidate that reuses an exact key computed during the
+// scan (cand_pos holds EARLY_FLAG | survivor slot) gets its (exact key, id)
+// at its own place in cand_packed; n_used[q] counts them.
+struct EarlyFillArgs {
+  int64_t nq; const int64_t* n_cand; const int64_t* cand_off; const uint32_t* cand_pos;
+  const int64_t* surv_off; const uint32_t* surv_pos; const float* surv_exact; const int32_t* list_ids;
+  uint64_t* cand_packed; uint32_t* n_used;
+};
+hipError_t launch_early_fill(const EarlyFillArgs& a, int64_t max_kc, hipStream_t s);
 
 struct RerankArgs {
   const float* q; int64_t nq; int d; int metric; const void* vectors; int fp16;

@@ -157,8 +157,9 @@ struct PairOut {
   float* sample_out;
   float* skey;
   uint32_t* spos;
+  float* sexact;   // early re-rank: exact keys by survivor slot
   float* trace_out;
-  uint32_t prune, dmax_bits;
+  uint32_t prune, dmax_bits, early_bits;
   // loads only (everything a pair's output needs), so that a group's outputs
   // can be fetched while the previous group is being scanned
   __device__ __forceinline__ void init(const PqScanArgs& a, int mode, int64_t qi, int64_t p) {
@@ -172,9 +173,11 @@ struct PairOut {
       const QueryBook* b = a.books + qi;
       prune = uniform(b->prune);
       dmax_bits = uniform(b->dmax_bits);
+      early_bits = a.early ? uniform(b->early_bits) : 0u;
       const int64_t so = uniform(a.surv_off[qi]) + ro;
       skey = a.surv_key + so;
       spos = a.surv_pos + so;
+      sexact = a.surv_exact ? a.surv_exact + so : nullptr;
     }
   }
   __device__ __forceinline__ bool keep(float key) const { return !prune || key_bits(key) <= dmax_bits; }
@@ -201,7 +204,16 @@ struct PairOut {
 // round of NT rows is read before a barrier and written after it).  4-bit
 // shapes scan 8 queries per group (one 16-byte read per code serves all 8),
 // 8-bit shapes 4 (their float staging table would not fit twice as wide).
-template <int MODE, int BITS, int M, int DSUB, int NT, int O, bool U8>
+//
+// Early re-rank (EARLY, mode 1; Algorithm 4's improved IVF+PQ search): a
+// survivor whose key image lies below its query's early_bits (its bucket is
+// below the predicted threshold bucket) gets its exact key in the scan, right
+// after its code: each wave takes its early (object, query) items two at a
+// time (one per 32-lane half, chunk hl of the row on lane hl, the canonical
+// lane order), four items per half per round so that their row loads are in
+// flight together.  The survivor's list position carries EARLY_FLAG and its
+// exact key goes to surv_exact at its slot.
+template <int MODE, int BITS, int M, int DSUB, int NT, int O, bool U8, bool EARLY>
 __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   constexpr int G = scan_group_of(U8, BITS);
   constexpr int KSUB = 1 << BITS;
@@ -222,6 +234,8 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   __shared__ float u8_lo[U8 ? M : 1][G];      // per (sub-space, query) minimum
   __shared__ float u8_wspan[U8 ? NW : 1][G];  // per wave: largest range seen
   __shared__ float u8_par[3][G];              // per query: base, delta, 1 / delta
+  __shared__ uint32_t s_early[EARLY ? G : 1];  // per query of the group: items re-ranked early
+  static_assert(!EARLY || (MODE == 1 && D <= 128 && D % 4 == 0), "early re-rank: filter scan, rows of <= 32 chunks");
 
   // the codebook is the same for every group: the owned codewords are loaded once
   float creg[REGCB ? EPT : 1][DSUB];
@@ -252,7 +266,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   // values after its first scan pass.
   const int lane = threadIdx.x & 63;
   constexpr int RPT = (G * D + NT - 1) / NT;  // residual inputs per thread
-  uint32_t f_pp = NO_PAIR, f_prune = 0, f_dmax = 0;
+  uint32_t f_pp = NO_PAIR, f_prune = 0, f_dmax = 0, f_ebits = 0;
   int64_t f_qq = 0, f_ro = 0, f_base = 0, f_tr = 0;
   int32_t f_j = 0;
   float f_q[RPT], f_c[RPT];
@@ -272,6 +286,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
         f_base = a.surv_off[f_qq];
         f_prune = a.books[f_qq].prune;
         f_dmax = a.books[f_qq].dmax_bits;
+        if (EARLY) f_ebits = a.books[f_qq].early_bits;
       }
     }
   };
@@ -298,6 +313,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
       }
     }
   };
+  if (EARLY && threadIdx.x < G) s_early[threadIdx.x] = 0u;
   const int64_t c0 = lo + wid;
   if (c0 < hi) {
     fetch_pairs(c0);
@@ -324,8 +340,10 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
         } else {
           out[g].prune = lane_value(f_prune, g);
           out[g].dmax_bits = lane_value(f_dmax, g);
+          out[g].early_bits = EARLY ? lane_value(f_ebits, g) : 0u;
           out[g].skey = a.surv_key + base + ro;
           out[g].spos = a.surv_pos + base + ro;
+          out[g].sexact = EARLY ? a.surv_exact + base + ro : nullptr;
         }
       }
     }
@@ -585,25 +603,74 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
 #pragma unroll
           for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && out[g].keep(acc[o][g]);
         comp.step(keep, slot, wcnt);
+        bool ear[O * G];
 #pragma unroll
         for (int o = 0; o < O; ++o) {
           const int64_t i = base + o * NT + threadIdx.x;
 #pragma unroll
-          for (int g = 0; g < G; ++g)
+          for (int g = 0; g < G; ++g) {
+            ear[o * G + g] = EARLY && keep[o * G + g] && key_bits(acc[o][g]) < out[g].early_bits;
             if (keep[o * G + g]) {
               out[g].skey[slot[o * G + g]] = acc[o][g];
-              out[g].spos[slot[o * G + g]] = (uint32_t)(lbeg + i);
+              out[g].spos[slot[o * G + g]] = (uint32_t)(lbeg + i) | (ear[o * G + g] ? EARLY_FLAG : 0u);
             }
+          }
+        }
+        if constexpr (EARLY) {
+          constexpr int NCH = D / 4;
+          constexpr int EU = 4;  // items per half-wave per round
+          const int hl = lane & 31, half = lane >> 5;
+          const int64_t wbase = base + (int64_t)(threadIdx.x & ~63);  // object of lane 0, o = 0
+          const float4* vec4 = reinterpret_cast<const float4*>(a.vectors);
+          const float4* q4 = reinterpret_cast<const float4*>(a.q);
+#pragma unroll
+          for (int og = 0; og < O * G; ++og) {
+            const int o = og / G, g = og % G;
+            uint64_t em = __ballot(ear[og]);
+            if (lane == 0 && em) atomicAdd(&s_early[g], (uint32_t)__popcll(em));
+            while (em) {  // wave-uniform
+              int src[EU];
+#pragma unroll
+              for (int u = 0; u < EU; ++u) {
+                const int a0 = em ? __ffsll((unsigned long long)em) - 1 : -1;
+                if (em) em &= em - 1;
+                const int a1 = em ? __ffsll((unsigned long long)em) - 1 : -1;
+                if (em) em &= em - 1;
+                src[u] = half ? a1 : a0;
+              }
+              float4 xv[EU], qv[EU];
+              uint32_t sl[EU];
+#pragma unroll
+              for (int u = 0; u < EU; ++u) {
+                const int sr = src[u] < 0 ? 0 : src[u];
+                sl[u] = __shfl(slot[og], sr);
+                const bool ok = src[u] >= 0 && hl < NCH;
+                const int64_t row = lbeg + wbase + o * NT + sr;
+                xv[u] = ok ? vec4[row * NCH + hl] : make_float4(0.f, 0.f, 0.f, 0.f);
+                qv[u] = ok ? q4[qq[g] * NCH + hl] : make_float4(0.f, 0.f, 0.f, 0.f);
+              }
+#pragma unroll
+              for (int u = 0; u < EU; ++u) {
+                float e = a.metric ? chunk_ip(qv[u], xv[u], 0.0f) : chunk_l2(qv[u], xv[u], 0.0f);
+                e = canon_reduce32(e);
+                if (src[u] >= 0 && hl == 0) out[g].sexact[sl[u]] = a.metric ? -e : e;
+              }
+            }
+          }
         }
       }
     }
+    if (EARLY) __syncthreads();  // the group's early counts are complete
     if (MODE == 1 && threadIdx.x == 0) {
 #pragma unroll
-      for (int g = 0; g < G; ++g)
+      for (int g = 0; g < G; ++g) {
         if (valid[g]) {
           a.pair_nsurv[pp[g]] = comp.total[g];
           if (nobj > comp.total[g]) atomicAdd(a.n_rejected + qq[g], (uint32_t)(nobj - comp.total[g]));
+          if (EARLY && s_early[g]) atomicAdd(a.n_early + qq[g], s_early[g]);
         }
+        if (EARLY) s_early[g] = 0u;
+      }
     }
   }
 }
@@ -698,9 +765,11 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
 template <int BITS, int M, int DSUB, int NT, int O, bool U8>
 static void launch_grouped_t(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
   if (a.mode == 0)
-    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8>), dim3(blocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8, false>), dim3(blocks), dim3(NT), lds, s, a);
+  else if (!U8 && a.early)
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, false, true>), dim3(blocks), dim3(NT), lds, s, a);
   else
-    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, U8>), dim3(blocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, U8, false>), dim3(blocks), dim3(NT), lds, s, a);
 }
 
 template <int BITS, int M, int DSUB, int NT, int O>
@@ -732,6 +801,12 @@ static bool try_grouped(const PqScanArgs& a, hipStream_t s) {
 bool pq_scan_grouped_shape(int bits, int M, int d) {
   return (bits == 8 && M == 32 && d == 128) || (bits == 8 && M == 16 && d == 128) ||
          (bits == 4 && M == 48 && d == 96) || (bits == 4 && M == 32 && d == 128);
+}
+
+hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((unsigned)std::min<int64_t>((n + 255) / 256, 4096)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
 }
 
 int64_t pair_slots(int64_t npairs, int nlist) { return npairs + 2 * (int64_t)nlist * (SCAN_GROUP_MAX - 1); }

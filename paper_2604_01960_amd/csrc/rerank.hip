@@ -59,16 +59,17 @@ __global__ __launch_bounds__(256) void rerank_half_kernel(RerankArgs a) {
 #pragma unroll
     for (int u = 0; u < RR_UNROLL; ++u) {
       int64_t r = base + u;
-      pos[u] = r < row_end ? cpos[r] : 0u;
+      pos[u] = r < row_end ? cpos[r] : EARLY_FLAG;
       xv[u] = make_float4(0.f, 0.f, 0.f, 0.f);
-      if (r < row_end && hl < nchunk) xv[u] = load4<T>(vec + (int64_t)pos[u] * a.d, hl);
+      // candidates re-ranked during the scan (EARLY_FLAG) are skipped
+      if (!(pos[u] & EARLY_FLAG) && hl < nchunk) xv[u] = load4<T>(vec + (int64_t)pos[u] * a.d, hl);
     }
 #pragma unroll
     for (int u = 0; u < RR_UNROLL; ++u) {
       float acc = ip ? chunk_ip(qc, xv[u], 0.0f) : chunk_l2(qc, xv[u], 0.0f);
       acc = canon_reduce32(acc);
       int64_t r = base + u;
-      if (hl == 0 && r < row_end) {
+      if (hl == 0 && !(pos[u] & EARLY_FLAG)) {
         float key = ip ? -acc : acc;
         outp[r] = pack_key_id(key, (uint32_t)a.list_ids[pos[u]]);
       }
@@ -103,12 +104,12 @@ __global__ __launch_bounds__(256) void rerank_full_kernel(RerankArgs a) {
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
       int64_t r = base + u;
-      pos[u] = r < row_end ? cpos[r] : 0u;
+      pos[u] = r < row_end ? cpos[r] : EARLY_FLAG;
 #pragma unroll
       for (int st = 0; st < 4; ++st) {
         int c = lane + 64 * st;
         xv[u][st] = make_float4(0.f, 0.f, 0.f, 0.f);
-        if (r < row_end && c < nchunk) xv[u][st] = load4<T>(vec + (int64_t)pos[u] * a.d, c);
+        if (!(pos[u] & EARLY_FLAG) && c < nchunk) xv[u][st] = load4<T>(vec + (int64_t)pos[u] * a.d, c);
       }
     }
 #pragma unroll
@@ -121,7 +122,7 @@ __global__ __launch_bounds__(256) void rerank_full_kernel(RerankArgs a) {
       }
       acc = canon_reduce64(acc);
       int64_t r = base + u;
-      if (lane == 0 && r < row_end) {
+      if (lane == 0 && !(pos[u] & EARLY_FLAG)) {
         float key = ip ? -acc : acc;
         outp[r] = pack_key_id(key, (uint32_t)a.list_ids[pos[u]]);
       }
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
     for (uint32_t i = threadIdx.x; i < b1 - b0; i += NT) cnt[i] = 0;
     __syncthreads();
     block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t, bool valid, uint32_t pos) {
-      if (!valid) return;
+      if (!valid || (pos & EARLY_FLAG)) return;  // re-ranked during the scan
       const int r = rank_at(pos);
       if (r >= rlo && r < rhi) atomicAdd(&cnt[s_tb[r] - b0 + ((pos - (uint32_t)s_lbeg[r]) >> a.tshift)], 1u);
     });
@@ -321,7 +322,7 @@ __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
     }
     __syncthreads();
     block_for_batched<NT, 4>(kc, [&](int64_t i) { return cpos[i]; }, [&](int64_t i, bool valid, uint32_t pos) {
-      if (!valid) return;
+      if (!valid || (pos & EARLY_FLAG)) return;
       const int r = rank_at(pos);
       if (r >= rlo && r < rhi) {
         const uint32_t slot = atomicAdd(&cnt[s_tb[r] - b0 + ((pos - (uint32_t)s_lbeg[r]) >> a.tshift)], 1u);
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
     rlo = rhi;
     __syncthreads();
   }
-  if (threadIdx.x == 0) bb[nb] = (uint32_t)kc;
+  if (threadIdx.x == 0) bb[nb] = base;  // the candidates placed (all but those re-ranked early)
 }
 
 // Shared by both tile kernels: the block's pairs, the rows of tile t in LDS,

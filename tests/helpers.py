@@ -61,13 +61,15 @@ def expected_steps(ix, q, k, nprobe, ratio, m, nsample, sample_factor=2, lut_u8=
         goff[1:] = np.cumsum(sizes)
         kc_t = int(np.ceil(ratio * float(kk[i])))
         col = oracle.collect_bbc(keys, ids, goff, kc_t, m, nsample, sample_factor) if len(keys) else None
+        early = oracle.early_rerank(keys, ids, goff, kc_t, m, nsample, sample_factor) if len(keys) else None
         kc = int(res["n_cand"][i])
         cand = res["cand_ids"][res["cand_off"][i]:res["cand_off"][i] + kc]
         exact = np.array([oracle.canon_l2(q[i], ix["base"][c]) for c in cand], np.float32)
         s = slice(res["off"][i], res["off"][i + 1])
         out.append(dict(probe_lists=lists, probe_keys=res["probe_keys"][res["probe_off"][i]:res["probe_off"][i + 1]],
                         est_keys=keys, est_ids=ids, n_scanned=int(res["n_scanned"][i]), n_cand=kc,
-                        collect=col, cand_ids=cand, cand_exact=exact, ids=res["ids"][s], dists=res["dists"][s],
+                        collect=col, early=early, cand_ids=cand, cand_exact=exact, ids=res["ids"][s],
+                        dists=res["dists"][s],
                         count=int(res["counts"][i])))
     return out
 
