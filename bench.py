@@ -247,7 +247,11 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=3000)
     ap.add_argument("--cpu-queries-1t", type=int, default=200, help="oracle queries timed on one thread")
     ap.add_argument("--o64-queries", type=int, default=100, help="queries searched by the float64 oracle O_64")
+    ap.add_argument("--f4-queries", type=int, default=8,
+                    help="RaBitQ: queries whose re-rank sizes are set against the minimal re-rank set")
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
+    ap.add_argument("--small-k", type=str, default="100,1000",
+                    help="small k values (nprobe 64, r 2) at which the collectors are also compared")
     ap.add_argument("--early-rerank", action="store_true",
                     help="PQ: early re-rank during the scan (Algorithm 4)")
     ap.add_argument("--lut-u8", action="store_true",
@@ -427,17 +431,21 @@ def main():
         for k in ks:
             res_k = {}
             ref = None
-            for col in ("bucket", "heap", "sort"):
+            # "bucket": the production path (the scan keeps only keys at or
+            # below the relaxed threshold d_max); "bucket_all_keys": every
+            # scanned key reaches the collector, as for heap and sort
+            for name in ("bucket", "bucket_all_keys", "heap", "heap_lds", "sort"):
+                col = "bucket" if name.startswith("bucket") else name
+                kw = dict(collector=col, lut_u8=args.lut_u8, early_rerank=args.early_rerank and col == "bucket",
+                          keep_all_keys=name == "bucket_all_keys")
                 o = (torch.empty_like(outs[k][0]), torch.empty_like(outs[k][1]), torch.empty_like(outs[k][2]))
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8,
-                             early_rerank=args.early_rerank and col == "bucket")
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=o, **kw)
                 torch.cuda.synchronize()
                 bbc.stage_times(reset=True)
                 bbc.stage_timing(True)
                 e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 e0.record()
-                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], collector=col, out=o, lut_u8=args.lut_u8,
-                             early_rerank=args.early_rerank and col == "bucket")
+                index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=o, **kw)
                 e1.record()
                 torch.cuda.synchronize()
                 bbc.stage_timing(False)
@@ -446,11 +454,38 @@ def main():
                     ref = o
                 same = bool(torch.equal(o[0], ref[0]) and torch.equal(o[1], ref[1]) and torch.equal(o[2], ref[2]))
                 scan_ms = st["sample_scan"]["ms"] + st["scan"]["ms"]
-                res_k[col] = dict(batch_ms=round(e0.elapsed_time(e1), 3), collector_ms=round(st["collect"]["ms"], 3),
-                                  scan_ms=round(scan_ms, 3), qps=round(nq / (e0.elapsed_time(e1) / 1e3), 1),
-                                  identical_to_bucket=same)
-                log(f"k={k} collector {col}: {res_k[col]}")
+                res_k[name] = dict(batch_ms=round(e0.elapsed_time(e1), 3), collector_ms=round(st["collect"]["ms"], 3),
+                                   scan_ms=round(scan_ms, 3), qps=round(nq / (e0.elapsed_time(e1) / 1e3), 1),
+                                   identical_to_bucket=same)
+                log(f"k={k} collector {name}: {res_k[name]}")
             collectors[str(k)] = res_k
+
+    # ---- small k: the bucket collector must not slow it down -------------------
+    small_k = {}
+    if not args.no_compare and args.small_k:
+        for k in [int(v) for v in args.small_k.split(",")]:
+            res_k, ref = {}, None
+            o = (torch.empty(nq * k, dtype=torch.int64, device=dev), torch.empty(nq * k, dtype=torch.float32, device=dev),
+                 torch.empty(nq, dtype=torch.int32, device=dev))
+            for col in ("bucket", "heap", "sort"):
+                index.search(qd, k, 64, ratio=2.0, collector=col, out=o)
+                torch.cuda.synchronize()
+                ms = []
+                for _ in range(3):
+                    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    e0.record()
+                    index.search(qd, k, 64, ratio=2.0, collector=col, out=o)
+                    e1.record()
+                    torch.cuda.synchronize()
+                    ms.append(e0.elapsed_time(e1))
+                cur = [t.clone() for t in o]
+                if ref is None:
+                    ref = cur
+                same = all(bool(torch.equal(a_, b_)) for a_, b_ in zip(cur, ref))
+                res_k[col] = dict(batch_ms=round(float(np.median(ms)), 3), qps=round(nq / (np.median(ms) / 1e3), 1),
+                                  identical_to_bucket=same)
+            small_k[str(k)] = res_k
+            log(f"small k={k}: {res_k}")
 
     # ---- sizes for the algorithmic byte counts ---------------------------------
     sizes = {}
@@ -586,6 +621,7 @@ def main():
                        "what": "device time of one 10,000-query batch"},
         "stage_ms_per_step": stage_ms,
         "collectors": collectors,
+        "collectors_small_k": small_k,
         "sizes": sizes,
         "roofline": roof,
         "roofline_other_kernels": others,
@@ -851,13 +887,19 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
                          "avg_launch_ms": round(avg_ms, 4), "algorithmic_bytes_per_launch": int(bpl)}
     dominant = max(entries, key=lambda s: stages[s]["ms"])
     cpu = None
+    f4 = None
+    oix = dict(kind="rabitq", n=w.n, d=w.d, nlist=w.nlist, metric=metric,
+               centroids=index.get(bbc.FIELD_CENTROIDS), rot_centroids=index.get(bbc.FIELD_ROT_CENTROIDS),
+               P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
+               codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
+               base=x)
+    if args.f4_queries > 0:
+        nf = min(args.f4_queries, nq)
+        f4 = rerank_report(oix, q[:nf], k, npb, sz["n_visited"][:nf])
+        log(f"re-rank sizes {f4}")
     if not args.no_cpu:
         import oracle
-        oix = dict(kind="rabitq", n=w.n, d=w.d, nlist=w.nlist, metric=metric,
-                   centroids=index.get(bbc.FIELD_CENTROIDS), rot_centroids=index.get(bbc.FIELD_ROT_CENTROIDS),
-                   P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
-                   codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
-                   base=np.ascontiguousarray(x, dtype=np.float32))
+        oix["base"] = np.ascontiguousarray(x, dtype=np.float32)
         per_call = max(8, oracle.num_threads())
         nqc, t_cpu = oracle_sample(lambda lo, hi: oracle.search_rabitq(oix, q[lo:hi], k, npb),
                                    min(args.cpu_queries, nq), args.cpu_seconds, per_call)
@@ -878,12 +920,32 @@ def run_rabitq(args, w, np, torch, bbc, synth, dev):
                        "what": f"device time of one {nq}-query batch"},
         "stage_ms_per_step": {s: round(v["ms"] / max(1, args.steps), 4) for s, v in stages.items()},
         "sizes": {"S_mean": S / nq, "reranked_mean": nv / nq},
+        "rerank_vs_minimal": f4,
         "roofline": entries[dominant],
         "roofline_other_kernels": {n: e for n, e in entries.items() if n != dominant},
         "cpu_baseline": cpu,
         "build_s": round(build_s, 2),
     }
     print(json.dumps(res), flush=True)
+
+
+def rerank_report(oix, qs, ks, npbs, gpu_exact):
+    """Row f4: re-rank sizes on a sample of queries, against Observation 1's
+    minimum (oracle.rerank_counts), beside the exact distances the GPU
+    computed for the same queries."""
+    import numpy as np
+    import oracle
+    c = oracle.rerank_counts(oix, qs, ks, npbs)
+    mn = np.maximum(c["min"], 1)
+    g = np.asarray(gpu_exact, np.float64)
+    return {"queries": int(len(qs)), "S_mean": float(c["S"].mean()),
+            "gpu_exact_mean": float(g.mean()), "walk_visited_mean": float(c["visited"].mean()),
+            "C_mean": float(c["C"].mean()), "minimal_mean": float(c["min"].mean()),
+            "minimal_with_topk_mean": float(c["min_out"].mean()),
+            "gpu_over_minimal": float(np.mean(g / mn)), "walk_over_minimal": float(np.mean(c["visited"] / mn)),
+            "what": "per query: S scanned; exact distances the GPU computed (all of C = {lb <= k-th ub} in the "
+                    "wide form); the oracle's bounded walk; |C|; Observation 1's minimal set (bound interval holds "
+                    "the k-th exact key) and that set with the exact top-k"}
 
 
 def recall_each(ids, off, gt, ks):
@@ -1056,13 +1118,19 @@ def run_serving(args, w, np, torch, bbc, synth, dev):
     dominant = max(entries, key=lambda s_: stages[s_]["ms"])
 
     cpu = None
-    if not args.no_cpu:
-        import oracle
+    f4 = None
+    if args.f4_queries > 0 or not args.no_cpu:
         oix = dict(kind="rabitq", n=w.n, d=w.d, nlist=w.nlist, metric=metric,
                    centroids=index.get(bbc.FIELD_CENTROIDS), rot_centroids=index.get(bbc.FIELD_ROT_CENTROIDS),
                    P=P, list_off=index.get(bbc.FIELD_LIST_OFF), list_ids=index.get(bbc.FIELD_LIST_IDS),
                    codes=index.get(bbc.FIELD_RABITQ_CODES), factors=index.get(bbc.FIELD_RABITQ_FACTORS),
                    base=np.ascontiguousarray(x, dtype=np.float32))
+    if args.f4_queries > 0:
+        nf = min(args.f4_queries, n)
+        f4 = rerank_report(oix, pool[qi[:nf]], ks[:nf], npr[:nf], [f["n_reranked"] for f in infos[:nf]])
+        log(f"re-rank sizes {f4}")
+    if not args.no_cpu:
+        import oracle
         per_call = max(8, oracle.num_threads())
         done_n, t_cpu = oracle_sample(
             lambda lo, hi: oracle.search_rabitq(oix, pool[qi[lo:hi]], ks[lo:hi], npr[lo:hi]), n, args.cpu_seconds,
@@ -1103,6 +1171,7 @@ def run_serving(args, w, np, torch, bbc, synth, dev):
         "sizes": {"S_mean": S / n, "reranked_mean": nv / n},
         "roofline": entries[dominant],
         "roofline_other_kernels": {k_: e for k_, e in entries.items() if k_ != dominant},
+        "rerank_vs_minimal": f4,
         "cpu_baseline": cpu,
         "build_s": round(build_s, 2),
     }

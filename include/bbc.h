@@ -62,12 +62,17 @@ extern "C" {
  *          the rest, all buckets below the threshold bucket plus the best s
  *          of the threshold bucket;
  *  HEAP    comparator: every scanned key offered to a bounded max-heap of
- *          K_c (key, id) per query (one wave per query, 64-ary heap);
+ *          K_c (key, id) per query (one wave per query, 64-ary heap in
+ *          global memory, many waves per compute unit);
  *  SORT    comparator: exact selection over every scanned key (radix
- *          select of the K_c-th key, ties by id). */
+ *          select of the K_c-th key, ties by id);
+ *  HEAP_LDS the heap comparator with each query's heap in LDS (when the
+ *          batch's largest K_c fits in 152 KiB, else as HEAP): one wave per
+ *          compute unit at large K_c. */
 #define BBC_COLLECT_BUCKET 0
 #define BBC_COLLECT_HEAP 1
 #define BBC_COLLECT_SORT 2
+#define BBC_COLLECT_HEAP_LDS 3
 
 typedef struct bbc_index bbc_index; /* opaque; owns its device memory */
 
@@ -163,6 +168,10 @@ typedef struct {
                           distance at once, and a candidate among them is not re-ranked again.
                           Results are identical to the plain search.  Needs float32 tables, a
                           grouped scan shape and float32 rows (BBC_EUNSUPPORTED otherwise) */
+  int32_t keep_all_keys; /* bucket collector, 1: the scan keeps every key (no relaxed-threshold
+                          filter at d_max), so the collector reads every scanned key, as the heap
+                          and sort collectors do: a like-for-like collector comparison.  Results
+                          are identical */
 } bbc_search_params;
 
 /* Search nq queries [nq][d] float32.  k[nq] and nprobe[nq] are host arrays

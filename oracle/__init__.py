@@ -57,6 +57,7 @@ def lib():
             L.orc_canon_ip.restype = f32
             L.orc_canon_ip.argtypes = [vp, vp, i32]
             L.orc_canon_l2_batch.argtypes = [vp, vp, i64, i32, vp]
+            L.orc_canon_ip_batch.argtypes = [vp, vp, i64, i32, vp]
             L.orc_topk_sort.argtypes = [vp, vp, i64, i64, vp, vp]
             L.orc_update.restype = i32
             L.orc_update.argtypes = [vp, i32, i64]
@@ -148,6 +149,13 @@ def canon_l2_batch(q, x) -> np.ndarray:
     q, x = _f32(q), _f32(x)
     out = np.empty(x.shape[0], dtype=np.float32)
     lib().orc_canon_l2_batch(_p(q), _p(x), x.shape[0], x.shape[1], _p(out))
+    return out
+
+
+def canon_ip_batch(q, x) -> np.ndarray:
+    q, x = _f32(q), _f32(x)
+    out = np.empty(x.shape[0], dtype=np.float32)
+    lib().orc_canon_ip_batch(_p(q), _p(x), x.shape[0], x.shape[1], _p(out))
     return out
 
 
@@ -570,3 +578,37 @@ def exact_knn64(base, queries, k, metric=0):
     _check(lib().orc_exact_knn64(_p(b), b.shape[0], b.shape[1], _p(q), nq, int(k), int(metric),
                                  _p(ids), _p(dists)), "exact_knn64")
     return ids, dists
+
+
+def rerank_counts(index, queries, k, nprobe, eps0=RABITQ_EPS0):
+    """Re-rank sizes of the RaBitQ path per query (row f4): S (objects
+    scanned), the bounded walk's visited objects, |C| = objects whose lower
+    bound is at most the k-th smallest upper bound, and Observation 1's
+    minimal set (objects whose bound interval holds the k-th exact key) and
+    that set united with the exact top-k.  Exact keys of every scanned object
+    by the canonical float32 order (negated inner product for IP)."""
+    q = _f32(queries)
+    nq = q.shape[0]
+    kk = np.broadcast_to(np.asarray(k), (nq,)).astype(np.int64)
+    npb = np.broadcast_to(np.asarray(nprobe), (nq,)).astype(np.int64)
+    res = search_rabitq(index, q, kk, npb, eps0=eps0, debug=True)
+    out = {f: np.zeros(nq, np.int64) for f in ("S", "visited", "C", "min", "min_out")}
+    base = index["base"]
+    for i in range(nq):
+        lists = res["probe_lists"][res["probe_off"][i]:res["probe_off"][i + 1]]
+        ids = np.concatenate([index["list_ids"][index["list_off"][j]:index["list_off"][j + 1]] for j in lists])
+        sl = slice(res["est_off"][i], res["est_off"][i + 1])
+        lb, ub = res["est_lb"][sl], res["est_ub"][sl]
+        rows = np.asarray(base[ids], np.float32)
+        ex = canon_l2_batch(q[i], rows) if index["metric"] == 0 else -canon_ip_batch(q[i], rows)
+        S = len(ids)
+        out["S"][i] = S
+        out["visited"][i] = res["n_visited"][i]
+        if S > kk[i]:
+            U = np.partition(ub, kk[i] - 1)[kk[i] - 1]
+            out["C"][i] = int(np.sum(lb <= U))
+        else:
+            out["C"][i] = S
+        a, b, _ = min_rerank(lb, ub, ex, ids, int(kk[i]))
+        out["min"][i], out["min_out"][i] = a, b
+    return out

@@ -102,6 +102,11 @@ void orc_canon_l2_batch(const float* q, const float* x, int64_t n, int32_t d, fl
   for (int64_t i = 0; i < n; ++i) out[i] = orc_canon_l2(q, x + i * (int64_t)d, d);
 }
 
+void orc_canon_ip_batch(const float* q, const float* x, int64_t n, int32_t d, float* out) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = orc_canon_ip(q, x + i * (int64_t)d, d);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Total order on (key, id)                                                  */
 /* ------------------------------------------------------------------------ */

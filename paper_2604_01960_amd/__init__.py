@@ -24,7 +24,7 @@ HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "bbc.h")
 OK, EINVAL, ENOMEM, EDEVICE, EUNSUPPORTED, EBUSY = 0, -1, -2, -3, -4, -6
 METRIC_L2, METRIC_IP = 0, 1
 QUANT_PQ, QUANT_RABITQ = 0, 1
-COLLECT = {"bucket": 0, "heap": 1, "sort": 2}
+COLLECT = {"bucket": 0, "heap": 1, "sort": 2, "heap_lds": 3}
 FIELD_CENTROIDS, FIELD_LIST_OFF, FIELD_LIST_IDS, FIELD_CODES, FIELD_CODEBOOK = 0, 1, 2, 3, 4
 FIELD_RABITQ_CODES, FIELD_RABITQ_FACTORS, FIELD_ROT_CENTROIDS, FIELD_ROTATION, FIELD_BASE = 5, 6, 7, 8, 9
 STORAGE_FP32, STORAGE_FP16 = 0, 1
@@ -40,7 +40,8 @@ class BBCError(RuntimeError):
 class SearchParams(C.Structure):
     _fields_ = [("ncand_ratio", C.c_double), ("collector", C.c_int32), ("buckets", C.c_int32),
                 ("nsample", C.c_int32), ("sample_factor", C.c_int32), ("device_io", C.c_int32),
-                ("stream", C.c_void_p), ("lut_u8", C.c_int32), ("early_rerank", C.c_int32)]
+                ("stream", C.c_void_p), ("lut_u8", C.c_int32), ("early_rerank", C.c_int32),
+                ("keep_all_keys", C.c_int32)]
 
 
 class BuildParams(C.Structure):
@@ -297,13 +298,13 @@ class Index:
 
     # -- search --------------------------------------------------------------
     def _params(self, ratio, collector, buckets, nsample, device_io, stream, sample_factor=0, lut_u8=False,
-                early_rerank=False):
+                early_rerank=False, keep_all_keys=False):
         return SearchParams(float(ratio), COLLECT[collector] if isinstance(collector, str) else int(collector),
                             int(buckets), int(nsample), int(sample_factor), int(device_io), stream,
-                            int(bool(lut_u8)), int(bool(early_rerank)))
+                            int(bool(lut_u8)), int(bool(early_rerank)), int(bool(keep_all_keys)))
 
     def search(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-               nsample: int = 0, out=None, stream=None, lut_u8: bool = False, early_rerank: bool = False):
+               nsample: int = 0, out=None, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
         """Search a batch.  numpy queries: blocking, returns (ids, dists, counts, offsets)
         as numpy.  torch GPU queries: enqueued on `stream` (default: torch's current
         stream); `out` may hold preallocated (ids, dists, counts) torch tensors."""
@@ -323,7 +324,7 @@ class Index:
                        torch.empty(int(off[-1]), dtype=torch.float32, device=queries.device),
                        torch.empty(nq, dtype=torch.int32, device=queries.device))
             ids, dists, counts = out
-            p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank)
+            p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
             _check(load().bbc_search(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                      _ptr(ids), _ptr(dists), _ptr(counts)))
             return ids, dists, counts, off
@@ -331,13 +332,13 @@ class Index:
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
-        p = self._params(ratio, collector, buckets, nsample, 0, stream, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, collector, buckets, nsample, 0, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                  _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_noalloc(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                       nsample: int = 0, stream=None, lut_u8: bool = False, early_rerank: bool = False):
+                       nsample: int = 0, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
         """bbc_search_noalloc: torch GPU queries and preallocated (ids, dists, counts)
         torch tensors; enqueued on `stream` (default: torch's current stream).  The
         workspace is the library's fixed per-GPU array (BBC_NOALLOC_MAX_BYTES)."""
@@ -354,13 +355,13 @@ class Index:
         ids, dists, counts = out
         if ids.numel() < int(off[-1]) or dists.numel() < int(off[-1]) or counts.numel() < nq:
             raise ValueError("output tensors are too small")
-        p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search_noalloc(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                          _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_counts(self, queries, k, nprobe, ratio: float = 2.0, buckets: int = 0, nsample: int = 0,
-                      lut_u8: bool = False, early_rerank: bool = False):
+                      lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
         """Host search returning only per-query sizes: S, K_c, rechecked lists,
         threshold-bucket size."""
         q = _np(queries, np.float32)
@@ -379,13 +380,13 @@ class Index:
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
         tr = SearchTrace(**{f: _ptr(v) for f, v in r.items()})
-        p = self._params(ratio, "bucket", buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, "bucket", buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                         _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
         return r
 
     def plan(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-             nsample: int = 0, autotune: bool = False, lut_u8: bool = False, early_rerank: bool = False) -> Plan:
+             nsample: int = 0, autotune: bool = False, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Plan:
         """Capture the search of a fixed device batch (torch queries and
         `out` = (ids, dists, counts) torch buffers) into a replayable plan."""
         import torch
@@ -396,7 +397,7 @@ class Index:
         off[1:] = np.cumsum(kk)
         ids, dists, counts = out
         assert ids.numel() == off[-1] and dists.numel() == off[-1] and counts.numel() == nq
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(load().bbc_plan_create(self._h, nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(queries), _ptr(off),
@@ -404,15 +405,15 @@ class Index:
         return Plan(h.value, self, (queries, ids, dists, counts))
 
     def server(self, mem_budget: int, max_slots: int = 1024, lanes: int = 2, ratio: float = 2.0,
-               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False) -> "Server":
+               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> "Server":
         """A continuous-batching server over this index (bbc_server_*)."""
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         h = C.c_void_p()
         _check(load().bbc_server_create(self._h, C.byref(p), int(mem_budget), int(max_slots), int(lanes),
                                         C.byref(h)))
         return Server(h.value, self)
 
-    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False, early_rerank: bool = False) -> Dict[str, np.ndarray]:
+    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Dict[str, np.ndarray]:
         """Host search returning per-query sizes only: S (n_scanned), the
         candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
         RaBitQ) and, for RaBitQ, n_visited."""
@@ -428,7 +429,7 @@ class Index:
             r["n_visited"] = np.empty(nq, np.int64)
             fields.append("n_visited")
         tr = SearchTrace(**{f: _ptr(r[f]) for f in fields})
-        p = self._params(ratio, "bucket", 0, 0, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, "bucket", 0, 0, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
@@ -437,7 +438,7 @@ class Index:
         return r
 
     def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                      nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False) -> Dict[str, np.ndarray]:
+                      nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Dict[str, np.ndarray]:
         """Host search that also returns every intermediate of the path."""
         q = _np(queries, np.float32)
         nq = q.shape[0]
@@ -447,7 +448,7 @@ class Index:
         off = np.zeros(nq + 1, np.int64)
         off[1:] = np.cumsum(kk)
         L = load()
-        p = self._params(ratio, collector, buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank)
+        p = self._params(ratio, collector, buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         r = dict(
             ids=np.empty(int(off[-1]), np.int64), dists=np.empty(int(off[-1]), np.float32),
             counts=np.empty(nq, np.int32), off=off,

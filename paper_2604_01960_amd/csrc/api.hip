@@ -739,13 +739,15 @@ int32_t validate_search(const bbc_index* ix, const float* queries, int64_t nq, c
   if (p->buckets < 0 || p->buckets > 256) return fail(BBC_EINVAL, "buckets must be in [0, 256]");
   if (p->nsample < 0) return fail(BBC_EINVAL, "nsample must be >= 0");
   if (p->sample_factor < 0 || p->sample_factor > 64) return fail(BBC_EINVAL, "sample_factor must be in [0, 64]");
-  if (p->collector != BBC_COLLECT_BUCKET && p->collector != BBC_COLLECT_HEAP && p->collector != BBC_COLLECT_SORT)
+  if (p->collector != BBC_COLLECT_BUCKET && p->collector != BBC_COLLECT_HEAP && p->collector != BBC_COLLECT_SORT &&
+      p->collector != BBC_COLLECT_HEAP_LDS)
     return fail(BBC_EINVAL, "unknown collector");
   if (p->lut_u8 != 0 && p->lut_u8 != 1) return fail(BBC_EINVAL, "lut_u8 must be 0 or 1");
   if (p->lut_u8 && ix->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "lut_u8 applies to PQ indexes only");
   if (p->lut_u8 && !bbc::pq_scan_grouped_shape(ix->bits, ix->M, ix->d))
     return fail(BBC_EUNSUPPORTED, "one-byte tables need a grouped scan shape (8-bit M=16 or 32, 4-bit M=32 or 48)");
   if (p->early_rerank != 0 && p->early_rerank != 1) return fail(BBC_EINVAL, "early_rerank must be 0 or 1");
+  if (p->keep_all_keys != 0 && p->keep_all_keys != 1) return fail(BBC_EINVAL, "keep_all_keys must be 0 or 1");
   if (p->early_rerank) {
     if (ix->quant != BBC_QUANT_PQ) return fail(BBC_EINVAL, "early_rerank applies to PQ indexes only");
     if (p->collector != BBC_COLLECT_BUCKET) return fail(BBC_EINVAL, "early_rerank needs the bucket collector");
@@ -1389,6 +1391,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     ca.t_nsample_keys = reinterpret_cast<int64_t*>(A + L.t_nsk);
   }
   ca.early = early;
+  ca.keep_all = p->keep_all_keys != 0;
   ca.t_tau_pred = early ? reinterpret_cast<int32_t*>(A + L.t_tpred) : nullptr;
 
   // scan of the sample lists, codebook, scan of the rest through the filter,
@@ -1432,6 +1435,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     xa.keys = reinterpret_cast<const float*>(A + L.sample_keys); xa.key_off = d_so;
     xa.cand_off = d_co; xa.cand_pos = ca.cand_pos; xa.n_cand = ca.n_cand;
     xa.heap = reinterpret_cast<uint64_t*>(A + L.cand_packed);
+    xa.max_kc = max_kc;
     StageScope st(s, 3);
     HIP_TRY(bbc::launch_compare_collect(xa, p->collector, s));
   }

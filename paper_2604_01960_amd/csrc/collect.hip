@@ -298,7 +298,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
         fbc[1] = delta;
         // reject above d_max only when the sample alone holds K_c keys and the
         // cells are proper (then every key above d_max is in cell 255)
-        bc[5] = (Ts >= kc && dmax > dmin) ? 1u : 0u;
+        bc[5] = (Ts >= kc && dmax > dmin && !a.keep_all) ? 1u : 0u;
       }
     }
   } else if (threadIdx.x == 0) {

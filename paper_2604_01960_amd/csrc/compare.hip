@@ -8,7 +8,8 @@
 //    over all S keys, then a compaction pass; ties on the threshold key are
 //    cut by id with a second radix select over the tied ids;
 //  - heap: one wave per query keeps a 64-ary max-heap of packed (key, id)
-//    of size K_c in global memory.  Its first K_c keys are heapified; every
+//    of size K_c in global memory (collector 1), or in LDS when the batch's
+//    largest K_c fits (collector 3).  Its first K_c keys are heapified; every
 //    later key below the heap's top replaces the top and sifts down (each
 //    level: the 64 children are read by the 64 lanes and reduced).
 #include "common.h"
@@ -20,6 +21,7 @@ namespace {
 
 constexpr int CMP_RANKCAP = 2048;      // probe ranks held in LDS (sort collector)
 constexpr int CMP_RANKCAP_HEAP = 256;  // (heap collector: small blocks, many per CU)
+constexpr size_t CMP_HEAP_LDS_MAX = 152 * 1024;  // heaps of up to 19,456 entries live in LDS
 
 template <int NT, int CAP>
 __device__ SlotMap load_slot_map(const CompareArgs& a, int64_t qi, int32_t* s_rbeg, int32_t* s_lbeg) {
@@ -92,10 +94,53 @@ __global__ __launch_bounds__(1024) void sort_collect_kernel(CompareArgs a) {
   }
 }
 
+// The heap's storage: global memory (agent-scope atomic loads and stores, so
+// that lane 0's stores are seen by the wave's later loads) or LDS.
+template <bool LDSH>
+__device__ __forceinline__ uint64_t hp_load(const uint64_t* p) {
+  if constexpr (LDSH) return *reinterpret_cast<const volatile uint64_t*>(p);
+  else return hload(p);
+}
+template <bool LDSH>
+__device__ __forceinline__ void hp_store(uint64_t* p, uint64_t v) {
+  if constexpr (LDSH) *reinterpret_cast<volatile uint64_t*>(p) = v;
+  else hstore(p, v);
+}
+
+// One wave: sift v down from node i of the 64-ary max-heap h[0, n).
+template <bool LDSH>
+__device__ void hp_sift_down(uint64_t* h, int64_t n, int64_t i, uint64_t v) {
+  const int lane = threadIdx.x & 63;
+  while (true) {
+    const int64_t c0 = 64 * i + 1;
+    if (c0 >= n) break;
+    const int64_t cj = c0 + lane;
+    const bool ok = cj < n;
+    const uint64_t cv = ok ? hp_load<LDSH>(h + cj) : 0ull;
+    uint64_t mx = cv;
+    for (int off = 32; off >= 1; off >>= 1) {
+      const uint64_t o = __shfl_xor(mx, off);
+      mx = o > mx ? o : mx;
+    }
+    if (mx <= v) break;
+    const uint64_t at = __ballot(ok && cv == mx);
+    const int j = __ffsll((unsigned long long)at) - 1;
+    if (lane == 0) hp_store<LDSH>(h + i, mx);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    i = c0 + j;
+  }
+  if (lane == 0) hp_store<LDSH>(h + i, v);
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+}
+
+// LDSH: the heap lives in LDS (dynamic, K_c entries of 8 bytes), for batches
+// whose largest K_c fits.
+template <bool LDSH>
 __global__ __launch_bounds__(64) void heap_collect_kernel(CompareArgs a) {
   constexpr int NT = 64;
   __shared__ int32_t s_rbeg[CMP_RANKCAP_HEAP];
   __shared__ int32_t s_lbeg[CMP_RANKCAP_HEAP];
+  extern __shared__ __align__(16) uint64_t s_heap[];
   const int lane = threadIdx.x;
 
   const int64_t qi = blockIdx.x;
@@ -111,15 +156,15 @@ __global__ __launch_bounds__(64) void heap_collect_kernel(CompareArgs a) {
     for (int64_t i = lane; i < S; i += NT) cand[i] = (uint32_t)sm.pos(i);
     return;
   }
-  uint64_t* h = a.heap + a.cand_off[qi];
+  uint64_t* h = LDSH ? s_heap : a.heap + a.cand_off[qi];
   auto packed = [&](int64_t i) -> uint64_t {
     return pack_key_id(keys[i], (uint32_t)a.list_ids[sm.pos(i)]);
   };
   // the first kc keys, then heapify bottom-up
-  for (int64_t i = lane; i < kc; i += NT) hstore(h + i, packed(i));
+  for (int64_t i = lane; i < kc; i += NT) hp_store<LDSH>(h + i, packed(i));
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
-  for (int64_t node = (kc - 2) / 64; node >= 0; --node) heap_sift_down(h, kc, node, hload(h + node));
-  uint64_t top = hload(h);
+  for (int64_t node = (kc - 2) / 64; node >= 0; --node) hp_sift_down<LDSH>(h, kc, node, hp_load<LDSH>(h + node));
+  uint64_t top = hp_load<LDSH>(h);
   for (int64_t base = kc; base < S; base += NT) {
     const int64_t i = base + lane;
     uint64_t v = ~0ull;
@@ -131,18 +176,20 @@ __global__ __launch_bounds__(64) void heap_collect_kernel(CompareArgs a) {
       mask &= mask - 1;
       const uint64_t x = __shfl(v, j);
       if (x < top) {  // the top only decreases
-        heap_sift_down(h, kc, 0, x);
-        top = hload(h);
+        hp_sift_down<LDSH>(h, kc, 0, x);
+        top = hp_load<LDSH>(h);
       }
     }
   }
-  for (int64_t i = lane; i < kc; i += NT) cand[i] = (uint32_t)a.pos_of_id[packed_id(hload(h + i))];
+  for (int64_t i = lane; i < kc; i += NT) cand[i] = (uint32_t)a.pos_of_id[packed_id(hp_load<LDSH>(h + i))];
 }
 
 hipError_t launch_compare_collect(const CompareArgs& a, int collector, hipStream_t s) {
   if (a.nq <= 0) return hipSuccess;
-  if (collector == 1)
-    hipLaunchKernelGGL(heap_collect_kernel, dim3((unsigned)a.nq), dim3(64), 0, s, a);
+  if (collector == 3 && a.max_kc > 0 && (size_t)a.max_kc * 8 <= CMP_HEAP_LDS_MAX)
+    hipLaunchKernelGGL(heap_collect_kernel<true>, dim3((unsigned)a.nq), dim3(64), (size_t)a.max_kc * 8, s, a);
+  else if (collector == 1 || collector == 3)
+    hipLaunchKernelGGL(heap_collect_kernel<false>, dim3((unsigned)a.nq), dim3(64), 0, s, a);
   else
     hipLaunchKernelGGL(sort_collect_kernel, dim3((unsigned)a.nq), dim3(1024), 0, s, a);
   return hipGetLastError();

@@ -138,6 +138,7 @@ struct CollectArgs {
   int64_t* t_nboundary;
   int64_t* t_nsample_keys;  // keys in the codebook sample (codebook kernel)
   int early;                // codebook: also the predicted threshold of the early re-rank
+  int keep_all;             // codebook: no relaxed-threshold filter (every key survives)
   int32_t* t_tau_pred;      // trace: the predicted threshold bucket (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
@@ -222,8 +223,9 @@ struct CompareArgs {
   const float* keys; const int64_t* key_off;   // every scanned key of query q at keys[key_off[q] + slot]
   const int64_t* cand_off; uint32_t* cand_pos; int64_t* n_cand;
   uint64_t* heap;                              // [sum K_c] heap storage (heap collector)
+  int64_t max_kc;                              // largest K_c of the batch (LDS heap when it fits)
 };
-// collector: 1 heap, 2 sort
+// collector: 1 heap, 2 sort, 3 heap in LDS
 hipError_t launch_compare_collect(const CompareArgs& a, int collector, hipStream_t s);
 
 // ---- RaBitQ -------------------------------------------------------------------

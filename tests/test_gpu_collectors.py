@@ -16,7 +16,7 @@ def bbc():
     return b
 
 
-@pytest.mark.parametrize("collector", ["heap", "sort"])
+@pytest.mark.parametrize("collector", ["heap", "sort", "heap_lds"])
 @pytest.mark.parametrize("cfg", [
     # (base workload, n, nlist, M, bits, nq, k, nprobe, ratio)
     ("ivfpq_100k_d128", 20000, 64, 16, 8, 10, 300, 12, 2.0),
@@ -41,7 +41,7 @@ def test_comparators_uneven_and_ties(bbc):
     g = make_gpu_index(bbc, ix)
     k = np.array([1, 5, 300, 2000, 12000, 50, 7, 999, 64, 3], np.int32)
     npb = np.array([1, 40, 3, 7, 40, 2, 1, 11, 5, 39], np.int32)
-    for collector in ("heap", "sort"):
+    for collector in ("heap", "sort", "heap_lds"):
         print(f"[case] uneven {collector}", flush=True)
         tr = g.search_traced(q, k, npb, ratio=1.7, collector=collector)
         check_trace(tr, expected_steps(ix, q, k, npb, 1.7, 256, 8), 256, bucket=False)
@@ -61,7 +61,7 @@ def test_comparators_uneven_and_ties(bbc):
     tq = rng.integers(0, 3, (6, d)).astype(np.float32)
     tg = make_gpu_index(bbc, tix)
     exp = expected_steps(tix, tq, 700, 4, 2.0, 16, 2)
-    for collector in ("heap", "sort"):
+    for collector in ("heap", "sort", "heap_lds"):
         print(f"[case] integer ties {collector}", flush=True)
         tr = tg.search_traced(tq, 700, 4, ratio=2.0, collector=collector)
         check_trace(tr, exp, 16, bucket=False)
@@ -78,3 +78,21 @@ def test_collectors_agree_at_scale(bbc):
         got = g.search(q, 5000, 32, ratio=2.0, collector=collector)
         for x, y in zip(got[:3], ref[:3]):
             np.testing.assert_array_equal(x, y)
+
+
+def test_heap_in_global_memory_and_keep_all_keys(bbc):
+    """K_c above the LDS heap's capacity (19,456) takes the global-memory
+    heap; the bucket collector with every key kept (no relaxed-threshold
+    filter: all S keys reach it, as for heap and sort) returns the same, and
+    every step of it equals the oracle."""
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 100_000, 64, 16, 8, 4)
+    print("[case] global heap, K_c = 24000", flush=True)
+    g = make_gpu_index(bbc, ix)
+    ref = g.search(q, 16000, 48, ratio=1.5, collector="bucket")
+    for kw in (dict(collector="heap"), dict(collector="heap_lds"), dict(collector="bucket", keep_all_keys=True)):
+        got = g.search(q, 16000, 48, ratio=1.5, **kw)
+        for x, y in zip(got[:3], ref[:3]):
+            np.testing.assert_array_equal(x, y)
+    tr = g.search_traced(q, 3000, 20, ratio=2.0, keep_all_keys=True)
+    check_trace(tr, expected_steps(ix, q, 3000, 20, 2.0, 256, 8), 256)
+    np.testing.assert_array_equal(tr["n_survivors"], tr["n_scanned"])

@@ -201,3 +201,22 @@ def test_collect_definition_matches_paper_workflow(m):
             tau, s, cand = _replay_result_buffer(keys, ids, off, min(kc, n), col, m)
             assert (tau, s) == (col["tau"], col["s"])
             np.testing.assert_array_equal(cand, np.sort(col["cand_ids"]))
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_rerank_counts_relations(metric):
+    """The re-rank size report (minimal set <= minimal set with the top-k,
+    minimal set <= visited <= S, and the visited prefix inside |C| when the
+    walk's k-th exact key is at most U) on a small index, L2 and IP."""
+    d, n, nlist, nq, k = 64, 2000, 4, 6, 50
+    w = synth.small_workload("ivfrabitq_1m_d960", n=n, nlist=nlist, nq=nq, d=d, seed_index=4)
+    x, q = synth.base_vectors(w), synth.query_vectors(w)
+    if metric:
+        q = (q / np.linalg.norm(q, axis=1, keepdims=True)).astype(np.float32)
+    tr, ip = synth.kmeans_draws(n, nlist, 64 * nlist, 0)
+    ix = oracle.build_ivf_rabitq(x, nlist, tr, ip, synth.rotation_orthogonal(d, 331), metric=metric)
+    c = oracle.rerank_counts(ix, q, k, 3)
+    assert np.all(c["min"] <= c["min_out"])
+    assert np.all(c["min"] <= c["visited"]) and np.all(c["visited"] <= c["S"])
+    assert np.all(c["C"] <= c["S"]) and np.all(c["min"] >= 1)
+    assert np.mean(c["visited"] <= c["C"]) >= 0.8
