@@ -256,6 +256,8 @@ def main():
                     help="PQ: early re-rank during the scan (Algorithm 4)")
     ap.add_argument("--lut-u8", action="store_true",
                     help="PQ: one-byte distance tables with integer sums (fast-scan table accounting)")
+    ap.add_argument("--tables", choices=["f32", "u8"], default=None,
+                    help="PQ distance tables (default: u8 for the 4-bit fast-scan workload, f32 otherwise)")
     ap.add_argument("--serve-qps", type=float, default=0.0, help="serving: arrival rate (default: the workload's)")
     ap.add_argument("--serve-seconds", type=float, default=None, help="serving: stream length (default: the workload's)")
     ap.add_argument("--serve-budget", type=int, default=16 << 30, help="serving: workspace bytes in flight")
@@ -296,6 +298,10 @@ def main():
     dev = torch.device("cuda:0")
     bbc.load()
     w = synth.workload(args.workload)
+    if args.tables:
+        args.lut_u8 = args.tables == "u8"
+    elif not args.lut_u8:
+        args.lut_u8 = w.quant == "pq" and w.pq_bits == 4  # fast-scan codes: one-byte tables
     if args.n:
         w = synth.small_workload(args.workload, n=args.n, nlist=max(16, args.n // 1221), nq=w.nq)
     if w.arrival_qps:

@@ -97,6 +97,29 @@ def counter_per_dispatch(db: str, counter: str, regex: str) -> Tuple[float, int]
     return sum(per.values()) / len(per), len(per)
 
 
+def counter_by_grid(db: str, counter: str, regex: str) -> List[Tuple]:
+    """Per grid shape of the matching dispatches: (grid, dispatches, mean of
+    the counter's per-dispatch total).  The grid columns are taken from the
+    counter table when it has them."""
+    c = sqlite3.connect(db)
+    cols = [r[1] for r in c.execute("pragma table_info(counters_collection)").fetchall()]
+    gcols = [x for x in ("grid_size_x", "grid_size_y", "grid_size", "workgroup_size") if x in cols]
+    sel = ", ".join(["kernel_name", "dispatch_id", "counter_name", "value"] + gcols)
+    rx = re.compile(regex)
+    per: Dict[int, float] = collections.defaultdict(float)
+    grid: Dict[int, Tuple] = {}
+    for row in c.execute(f"select {sel} from counters_collection"):
+        name, disp, cname, val = row[:4]
+        if cname != counter or not rx.search(_short(name)):
+            continue
+        per[disp] += float(val)
+        grid[disp] = tuple(row[4:])
+    g: Dict[Tuple, List[float]] = collections.defaultdict(list)
+    for d, v in per.items():
+        g[grid[d]].append(v)
+    return [(k, len(v), sum(v) / len(v)) for k, v in sorted(g.items())]
+
+
 def sources_sha256(paths: List[str]) -> str:
     h = hashlib.sha256()
     for p in paths:
@@ -127,6 +150,7 @@ def main(argv=None):
     c.add_argument("db")
     c.add_argument("counter")
     c.add_argument("--regex", required=True)
+    c.add_argument("--by-grid", action="store_true", help="one line per grid shape")
     t = sub.add_parser("traffic")
     for a in ("--fetch", "--write", "--cal-fetch", "--cal-write", "--regex", "--cal-regex", "--out", "--command"):
         t.add_argument(a, required=True)
@@ -135,6 +159,9 @@ def main(argv=None):
     args = ap.parse_args(argv)
     if args.cmd == "stats":
         print(stats_markdown(args.db, args.regex, args.by_name, args.since))
+    elif args.cmd == "counter" and args.by_grid:
+        for grid, n, v in counter_by_grid(args.db, args.counter, args.regex):
+            print(f"{args.counter} grid {grid}: {v:.1f} per dispatch over {n} dispatches")
     elif args.cmd == "counter":
         v, n = counter_per_dispatch(args.db, args.counter, args.regex)
         print(f"{args.counter}: {v:.1f} per dispatch over {n} dispatches")
