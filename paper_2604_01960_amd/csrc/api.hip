@@ -191,6 +191,10 @@ struct bbc_index {
   // RaBitQ scan order with tile-major keys: pairs by list, a run of lists per
   // XCD (1), or by query (0) (BBC_SCAN_BY_LIST)
   int scan_by_list = 1;
+  // RaBitQ wide form: the first round's keys reach this fraction of the way
+  // from the k-th smallest lb's bin to U's bin (BBC_WALK_ALPHA; >= 1: one
+  // round over all of C)
+  float walk_alpha = 0.8f;
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -317,6 +321,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
     if (x >= 2 && x <= 4096 && (x & (x - 1)) == 0) ix->walk_qcap = x;
   }
   if (const char* sv = std::getenv("BBC_RQ_SCAN_1D")) ix->rq_scan_1d = std::atoi(sv) == 1;
+  if (const char* sv = std::getenv("BBC_WALK_ALPHA")) {
+    const float x = std::strtof(sv, nullptr);
+    if (x >= 0.0f && x <= 64.0f) ix->walk_alpha = x;
+  }
   HIP_TRY(hipEventCreateWithFlags(&ix->meta_done, hipEventDisableTiming));
   HIP_TRY(hipEventCreateWithFlags(&ix->arena.done, hipEventDisableTiming));
   return BBC_OK;
@@ -914,11 +922,15 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   // tile-major keys: the walk's bin pass also writes C in tile order (when
   // each query's probe ranks fit its LDS tables), else the candidate sort does
   const bool presort = tile_keys && ix->walk_presort && max_np <= bbc::WALK_RANKS_LDS;
-  size_t L_cpos = 0, L_wbins = 0, L_wst = 0;
+  size_t L_cpos = 0, L_wbins = 0, L_wst = 0, L_wround = 0;
+  const bool rounds = wide && ix->walk_alpha < 1.0f;  // the wide form's keys in two rounds
   if (wide) {
-    if (!presort) L_cpos = pl.add(4 * nkeys);
+    // C's list positions in place order: the grid keys' input (also the
+    // second round's when the first round's keys come tile-major)
+    if (!presort || rounds) L_cpos = pl.add(4 * nkeys);
     L_wbins = pl.add(4 * 2048 * nq);
     L_wst = pl.add(16 * nq);
+    if (rounds) L_wround = pl.add(16 * nq);
   }
   const int rt_group = bbc::tile_rerank_group(d);
   const int64_t rt_lpairs_cap = npairs + (int64_t)ix->nlist * (rt_group - 1);
@@ -1046,9 +1058,13 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   wa.qcap = ix->walk_qcap;
   wa.t_qpath = tracing ? reinterpret_cast<int32_t*>(A + L_qp) : nullptr;
   if (wide) {
-    wa.cpos = presort ? nullptr : reinterpret_cast<int32_t*>(A + L_cpos);
+    wa.cpos = presort && !rounds ? nullptr : reinterpret_cast<int32_t*>(A + L_cpos);
     wa.wbins = reinterpret_cast<uint32_t*>(A + L_wbins);
     wa.wstate = reinterpret_cast<uint32_t*>(A + L_wst);
+    if (rounds) {
+      wa.wround = reinterpret_cast<uint32_t*>(A + L_wround);
+      wa.round1_alpha = ix->walk_alpha;
+    }
   }
   if (presort) {
     wa.t_pos = reinterpret_cast<uint32_t*>(A + L_rts);
@@ -1064,21 +1080,30 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   }
   {
     StageScope st(s, 4);
-    if (tile_keys) {
-      // the exact keys of C, tile-major, at C's indices (what the walk reads)
-      ta.cand_pos = reinterpret_cast<const uint32_t*>(wa.cpos); ta.pos_off = d_ko;
-      ta.ncand_w = wa.wstate + 3; ta.ncand_stride = 4;
-      ta.cand_off = d_ko; ta.cand_packed = wa.cand_packed;
-      ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L_rts);
-      ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L_rti);
-      ta.pair_tb = reinterpret_cast<uint32_t*>(A + L_rtp);
-      ta.bin_off = d_bo;
-      ta.bin_beg = reinterpret_cast<uint32_t*>(A + L_rtb);
-      ta.presorted = presort ? 1 : 0;
-      HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
-      wa.keys_ready = 1;
+    // the wide form's keys in two rounds: C's first bins, a walk that settles
+    // most queries, then the rest of C for the others and a second walk
+    for (int round = rounds ? 1 : 0; round <= (rounds ? 2 : 0); ++round) {
+      wa.round = round;
+      wa.keys_ready = 0;  // round 2: C's other keys by the device-wide grid
+      if (tile_keys && round < 2) {
+        // the exact keys of C, tile-major, at C's indices (what the walk reads)
+        ta.cand_pos = reinterpret_cast<const uint32_t*>(wa.cpos); ta.pos_off = d_ko;
+        ta.ncand_w = wa.wstate + 3; ta.ncand_stride = 4;
+        ta.cand_off = d_ko; ta.cand_packed = wa.cand_packed;
+        ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L_rts);
+        ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L_rti);
+        ta.pair_tb = reinterpret_cast<uint32_t*>(A + L_rtp);
+        ta.bin_off = d_bo;
+        ta.bin_beg = reinterpret_cast<uint32_t*>(A + L_rtb);
+        ta.presorted = presort ? 1 : 0;
+        ta.round = round;
+        ta.wround = wa.wround;
+        HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));
+        ta.pairs_ready = 1;
+        wa.keys_ready = 1;
+      }
+      HIP_TRY(bbc::launch_rabitq_walk(wa, s));
     }
-    HIP_TRY(bbc::launch_rabitq_walk(wa, s));
   }
   const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
   const int cap = (int)std::min(max_cnt, cap_max);

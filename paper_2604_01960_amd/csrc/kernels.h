@@ -194,6 +194,9 @@ struct TileRerankArgs {
   int64_t lpairs_cap;       // npairs + nlist * (group - 1)
   int group;                // pairs per block: tile_rerank_group(d)
   int presorted;            // sorted_pos, sorted_idx, pair_tb and bin_beg already filled
+  // RaBitQ wide form in two rounds: round 1 computes only the candidates
+  // placed below wround[4q + 1] (sorted_idx = their places); 0: every one
+  int round; const uint32_t* wround;
   int pairs_ready;          // lcnt and lpairs already filled (launch_tile_pairs)
 };
 // the (query, rank) pairs grouped by list into whole groups: lcnt, lpairs
@@ -294,6 +297,15 @@ struct RabitqWalkArgs {
   int qcap;                  // objects above the k-th exact key resolved in LDS (0 = the LDS capacity)
   int32_t* t_qpath;          // optional [nq]: how the exact stop point was found (0 no search, 1 LDS,
                              // 2 global memory, 3 item-by-item walk)
+  // wide form in two rounds (round 1, then 2; 0 = one pass over all of C):
+  // round 1 computes the exact keys of C's first bins only (places below
+  // wround[4q + 1], bins below wround[4q]: the lb bins up to an estimate of
+  // the walk's stop point) and walks them; a query whose stop point lies
+  // beyond them is marked (wround[4q + 2] = 1) and round 2 computes the rest
+  // of its keys and walks again
+  int round;
+  uint32_t* wround;          // [nq][4] first-round bins, first-round places, second round needed, 0
+  float round1_alpha;        // prep: the first round's bins reach lb bin(k-th lb) + alpha * (bin(U) - that)
 };
 // wide form: the bins of C (a no-op otherwise); then the exact keys of C
 // (wide form) and the walk

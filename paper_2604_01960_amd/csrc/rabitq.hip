@@ -661,6 +661,10 @@ __global__ __launch_bounds__(1024) void rabitq_walk_prep_kernel(RabitqWalkArgs a
     if (threadIdx.x == 0) {
       st[0] = 0; st[1] = 0; st[2] = 0; st[3] = 0;
       if (a.t_pos) so.bins[so.nbins] = 0;  // (every probed list is empty: no bins before)
+      if (a.wround) {
+        uint32_t* wr = a.wround + 4 * qi;
+        wr[0] = WK_NB; wr[1] = 0; wr[2] = 0; wr[3] = 0;
+      }
     }
     return;
   }
@@ -671,6 +675,26 @@ __global__ __launch_bounds__(1024) void rabitq_walk_prep_kernel(RabitqWalkArgs a
                                    so, sm, hist, rhist, bc);
   for (int i = threadIdx.x; i < WK_NB; i += NT) a.wbins[qi * WK_NB + i] = hist[i];
   if (threadIdx.x == 0) { st[0] = w.U; st[1] = w.lmin; st[2] = (uint32_t)w.shift; st[3] = (uint32_t)w.nC; }
+  if (a.wround && threadIdx.x == 0) {
+    // first-round bins: up to the bin of the k-th smallest lb (the walk's
+    // k-th exact key lies above it) plus alpha of the way to U's bin (the
+    // k-th exact key lies below U when the bounds hold); everything when
+    // S <= k
+    const int64_t k = a.k[qi];
+    int b1 = WK_NB;
+    if (S > k) {
+      int kb = 0;
+      while (kb < WK_NB - 1 && (int64_t)hist[kb] < k) ++kb;
+      const int ub = (int)min((uint32_t)(WK_NB - 1), (w.U - w.lmin) >> w.shift);
+      const int ext = ub > kb ? (int)ceilf(a.round1_alpha * (float)(ub - kb)) : 0;
+      b1 = min(WK_NB, kb + 1 + ext);
+    }
+    uint32_t* wr = a.wround + 4 * qi;
+    wr[0] = (uint32_t)b1;
+    wr[1] = b1 >= WK_NB ? (uint32_t)w.nC : hist[b1 - 1];
+    wr[2] = 0u;
+    wr[3] = 0u;
+  }
 }
 
 // Wide form, step 2: exact (key, id) of every object of C, in cbuf order,
@@ -679,8 +703,15 @@ constexpr int EX_ROWS = 64;
 template <typename T>
 __global__ __launch_bounds__(256) void rabitq_exact_kernel(RabitqWalkArgs a) {
   const int64_t qi = blockIdx.y;
-  const int64_t nC = a.wstate[4 * qi + 3];
-  const int64_t i0 = (int64_t)blockIdx.x * EX_ROWS;
+  // places of C whose keys this launch computes: all, or one round's
+  int64_t lo = 0, nC = a.wstate[4 * qi + 3];
+  if (a.round) {
+    const uint32_t* wr = a.wround + 4 * qi;
+    if (a.round == 1) nC = min(nC, (int64_t)wr[1]);
+    else if (wr[2] == 0) return;
+    else lo = wr[1];
+  }
+  const int64_t i0 = lo + (int64_t)blockIdx.x * EX_ROWS;
   if (i0 >= nC) return;  // block-uniform
   __shared__ float4 s_qc[256];
   const float* q = a.q + qi * a.D;
@@ -729,6 +760,9 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
   const int64_t S = a.n_scanned[qi];
   const int64_t k = a.k[qi];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // two rounds (wide form): round 2 walks only the queries round 1 marked
+  uint32_t* wr = WIDE && a.round ? a.wround + 4 * qi : nullptr;
+  if (WIDE && a.round == 2 && wr[2] == 0) return;  // block-uniform
   if (S == 0) {
     if (threadIdx.x == 0) {
       a.n_cand[qi] = 0;
@@ -824,9 +858,13 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       uint32_t* H = reinterpret_cast<uint32_t*>(chunk_v);  // WK_NB counters
       for (int i = threadIdx.x; i < WK_NB; i += NT) H[i] = 0;
       __syncthreads();
+      // round 1 knows the keys of C's first bins only (places below
+      // lim): the counts of every b up to those bins are exact, since an
+      // object of a later bin counts for no b up to its own bin
+      const int64_t lim = a.round == 1 ? (int64_t)wr[1] : nC;
       // each wave takes a contiguous range of C and follows the bin ends
-      const int64_t per = ((nC + NW - 1) / NW + 63) & ~(int64_t)63;
-      const int64_t w0 = (int64_t)wv * per, w1 = min(nC, w0 + per);
+      const int64_t per = ((lim + NW - 1) / NW + 63) & ~(int64_t)63;
+      const int64_t w0 = (int64_t)wv * per, w1 = min(lim, w0 + per);
       const uint32_t* ximg = reinterpret_cast<const uint32_t*>(pbuf) + 1;  // exact image of place i at 2 i
       int bn = 0;  // the first bin whose end exceeds the lane's place
       {
@@ -874,6 +912,14 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       __syncthreads();
       const int found = (int)bc[13];
       const int b = found < WK_NB ? found + 1 : WK_NB;
+      if (a.round == 1 && (found >= WK_NB || b > (int)wr[0]) && lim < nC) {
+        // the stop point lies beyond the first round's bins: round 2
+        if (threadIdx.x == 0) {
+          wr[2] = 1u;
+          if (a.n_visited) a.n_visited[qi] = nC;
+        }
+        return;
+      }
       p = hist[b - 1];
       exhausted = p >= nC;
       Eimg = block_radix_select32<NT, WK_U>([&](int64_t i) { return ximg[2 * i]; }, p, k - 1, rhist, bc);
@@ -1043,11 +1089,13 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
       }
     }
   }
+  // exact distances computed: the visited objects; in the wide form all of
+  // C, or of the first round's bins when round 1 settled the query
+  const int64_t n_exact = !WIDE ? nvis : (a.round == 1 ? (int64_t)wr[1] : nC);
   if (ok) {
-    // exact distances computed: the visited objects, or all of C in the wide form
     if (threadIdx.x == 0) {
       a.n_cand[qi] = nvis;
-      if (a.n_visited) a.n_visited[qi] = WIDE ? nC : nvis;
+      if (a.n_visited) a.n_visited[qi] = n_exact;
       if (a.t_qpath) a.t_qpath[qi] = qpath;
     }
     return;
@@ -1131,7 +1179,7 @@ __global__ __launch_bounds__(WK_NT, WIDE ? 8 : 1) void rabitq_walk_kernel(Rabitq
   // the item walk visits a prefix of the (lb, id) order, of which C is a prefix too
   if (threadIdx.x == 0) {
     a.n_cand[qi] = nr;
-    if (a.n_visited) a.n_visited[qi] = WIDE ? max(nC, visited) : visited;
+    if (a.n_visited) a.n_visited[qi] = WIDE ? max(n_exact, visited) : visited;
     if (a.t_qpath) a.t_qpath[qi] = 3;
   }
 }

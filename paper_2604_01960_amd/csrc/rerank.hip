@@ -337,6 +337,13 @@ __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
   if (threadIdx.x == 0) bb[nb] = base;  // the candidates placed (all but those re-ranked early)
 }
 
+// Two-round RaBitQ keys: whether candidate place `place` of query q is
+// computed in the first round (the second round's keys are gathered by the
+// device-wide grid of the wide form, not tile-major).
+__device__ __forceinline__ bool rt_round_keep(const TileRerankArgs& a, int q, uint32_t place) {
+  return a.round != 1 || place < a.wround[4 * (int64_t)q + 1];
+}
+
 // Shared by both tile kernels: the block's pairs, the rows of tile t in LDS,
 // and the tile's work cut into runs of up to 64 candidates of one pair.
 struct RtGroup {
@@ -453,9 +460,10 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
       // lane l: candidate l's position, id, output index and row in the tile (-1: none)
       const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
       const int64_t rl = (int64_t)pl - lb - r0;
-      const bool okl = lane < cnt && rl >= 0 && rl < nr;
-      const int32_t idl = okl ? a.list_ids[pl] : 0;
+      bool okl = lane < cnt && rl >= 0 && rl < nr;
       const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
+      okl = okl && rt_round_keep(a, q, oil);
+      const int32_t idl = okl ? a.list_ids[pl] : 0;
       const int rowl = okl ? (int)rl : -1;
       float4 qv[4];
 #pragma unroll
@@ -557,9 +565,10 @@ __global__ __launch_bounds__(1024, 4) void rt_rerank_tile_wide(TileRerankArgs a)
       const int cnt = (int)min(64u, b1 - j0);
       const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
       const int64_t rl = (int64_t)pl - lb - r0;
-      const bool okl = lane < cnt && rl >= 0 && rl < nr;
-      const int32_t idl = okl ? a.list_ids[pl] : 0;
+      bool okl = lane < cnt && rl >= 0 && rl < nr;
       const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
+      okl = okl && rt_round_keep(a, q, oil);
+      const int32_t idl = okl ? a.list_ids[pl] : 0;
       const int rowl = okl ? (int)rl : -1;
       float mykey = 0.0f;
       for (int jj = 0; jj < cnt; ++jj) {

@@ -157,3 +157,49 @@ def test_tile_keys_many_queries(bbc, sort):
             os.environ.pop(v, None)
     print(f"[case] rabitq tile keys, 200 queries, sort={sort}", flush=True)
     _check_search(g, ix, q, 120, 8)
+
+
+@pytest.mark.parametrize("alpha", ["0", "0.8", "1"])
+@pytest.mark.parametrize("form", ["wide", "tiles"])
+@pytest.mark.parametrize("d,metric", [(128, 0), (256, 1)])
+def test_wide_form_two_rounds(bbc, alpha, form, d, metric):
+    """The wide form's exact keys in two rounds: the first round computes C's
+    lower-bound bins up to alpha of the way from the k-th lb to U, the walk
+    settles the queries whose stop point lies inside them, and the others get
+    the rest of C and a second walk.  Results equal the oracle's for every
+    alpha (0: the first round holds only the bins up to the k-th lb, so most
+    queries take the second round; 1: one round over all of C), and the keys
+    computed never exceed |C| (fewer than |C| for most queries at 0.8: on
+    this data the stop point lies 0.45 to 0.76 of the way, in bins)."""
+    import os
+    x, q, tr, ip, P, ix = _data(d, 12000, 16, 16, metric)
+    print(f"[case] two rounds d={d} metric={metric} form={form} alpha={alpha}", flush=True)
+    old = os.environ.get("BBC_WALK_ALPHA")
+    os.environ["BBC_WALK_ALPHA"] = alpha
+    try:
+        g = _gpu_index(bbc, x, ix, eps0=oracle.RABITQ_EPS0, form=form)
+    finally:
+        if old is None:
+            del os.environ["BBC_WALK_ALPHA"]
+        else:
+            os.environ["BBC_WALK_ALPHA"] = old
+    rng = np.random.default_rng(int(float(alpha) * 10) + d)
+    k = rng.integers(1, 3000, q.shape[0]).astype(np.int32)
+    npb = rng.integers(1, 17, q.shape[0]).astype(np.int32)
+    tr_ = g.search_traced(q, k, npb)
+    ref = oracle.search_rabitq(ix, q, k, npb, debug=True)
+    np.testing.assert_array_equal(tr_["counts"], ref["counts"])
+    np.testing.assert_array_equal(tr_["ids"], ref["ids"])
+    np.testing.assert_array_equal(tr_["dists"], ref["dists"])
+    # keys computed against |C| = objects with lb <= the k-th smallest ub
+    nC = np.zeros(q.shape[0], np.int64)
+    for i in range(q.shape[0]):
+        sl = slice(ref["est_off"][i], ref["est_off"][i + 1])
+        lb, ub = ref["est_lb"][sl], ref["est_ub"][sl]
+        nC[i] = len(lb) if len(lb) <= k[i] else int(np.sum(lb <= np.partition(ub, k[i] - 1)[k[i] - 1]))
+    assert np.all(tr_["n_visited"] <= nC)
+    if alpha == "1":
+        np.testing.assert_array_equal(tr_["n_visited"], nC)
+    if alpha == "0.8":
+        assert np.mean(tr_["n_visited"] < nC) >= 0.5
+    g.free()
