@@ -252,6 +252,8 @@ def main():
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
     ap.add_argument("--small-k", type=str, default="100,1000",
                     help="small k values (nprobe 64, r 2) at which the collectors are also compared")
+    ap.add_argument("--sample-factor", type=int, default=0,
+                    help="PQ: the codebook sample holds at least this many times K_c keys (0 = the library's 2)")
     ap.add_argument("--early-rerank", action="store_true",
                     help="PQ: early re-rank during the scan (Algorithm 4)")
     ap.add_argument("--lut-u8", action="store_true",
@@ -346,14 +348,14 @@ def main():
         if fixed_np and fixed_r:
             rec = None
             if gt is not None:
-                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+                ids, _, _, off = index.search(rq, k, fixed_np[ki], ratio=fixed_r[ki], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
                 rec = recall_at_k(ids, off, gt, k)
-            op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=rec)
+            op[k] = dict(nprobe=fixed_np[ki], ratio=fixed_r[ki], recall=rec, sample_factor=args.sample_factor or 2)
             continue
         cands = []
         for npb in nprobe_grid:
             for r in ratio_grid:
-                ids, _, _, off = index.search(rq, k, npb, ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+                ids, _, _, off = index.search(rq, k, npb, ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
                 rec = recall_at_k(ids, off, gt, k)
                 if rec >= args.target_recall:
                     cands.append(dict(nprobe=npb, ratio=r, recall=rec))
@@ -361,17 +363,17 @@ def main():
         if not cands:
             raise SystemExit(f"recall {args.target_recall} not reached for k={k}")
         for c in cands:  # one timed full batch per candidate
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
             torch.cuda.synchronize()
             t = time.perf_counter()
-            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
             torch.cuda.synchronize()
             c["probe_ms"] = (time.perf_counter() - t) * 1e3
         # the fastest candidate whose recall over the whole batch reaches the
         # target (the sweep's sample only shortlists)
         best = None
         for c in sorted(cands, key=lambda c: c["probe_ms"]):
-            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            o = index.search(qd, k, c["nprobe"], ratio=c["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
             torch.cuda.synchronize()
             c["recall_batch"] = recall_device(torch, o[0], gt_full_ids, k)
             if c["recall_batch"] >= args.target_recall:
@@ -380,6 +382,24 @@ def main():
         if best is None:
             best = max(cands, key=lambda c: c["recall_batch"])
         op[k] = best
+        # the codebook sample's size (a tighter relaxed threshold against a
+        # costlier codebook; results are identical): the fastest of 2, 3, 4
+        # times K_c on the whole batch, unless given
+        if args.sample_factor:
+            best["sample_factor"] = args.sample_factor
+        else:
+            sf_ms = {}
+            for f in (2, 3, 4):
+                index.search(qd, k, best["nprobe"], ratio=best["ratio"], lut_u8=args.lut_u8,
+                             early_rerank=args.early_rerank, sample_factor=f)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                index.search(qd, k, best["nprobe"], ratio=best["ratio"], lut_u8=args.lut_u8,
+                             early_rerank=args.early_rerank, sample_factor=f)
+                torch.cuda.synchronize()
+                sf_ms[f] = (time.perf_counter() - t) * 1e3
+            best["sample_factor"] = min(sf_ms, key=sf_ms.get)
+            log(f"k={k}: sample factor times {sf_ms}")
         log(f"k={k}: candidates {cands} -> {best}")
 
     # ---- timed steps ------------------------------------------------------------
@@ -392,7 +412,7 @@ def main():
         for k in ks:
             if per_k_events is not None:
                 per_k_events[k][0].record()
-            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=outs[k], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=op[k]["sample_factor"])
             if per_k_events is not None:
                 per_k_events[k][1].record()
 
@@ -424,7 +444,8 @@ def main():
         # recall and distance error of the last timed step's results, every query
         rec = recall_device(torch, outs[k][0], gt_full_ids, k)
         derr = distance_errors(torch, x64, q, outs[k][0], outs[k][1], k, gt_full_keys)
-        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], recall=round(rec, 4),
+        per_k[str(k)] = dict(nprobe=op[k]["nprobe"], ratio=op[k]["ratio"], sample_factor=op[k]["sample_factor"],
+                             recall=round(rec, 4),
                              recall_queries=nq, recall_target_reached=rec >= args.target_recall,
                              dist_err={n: float(f"{v:.3e}") for n, v in derr.items()},
                              qps=round(nq / (arr.mean() / 1e3), 1), batch_ms_p50=round(float(np.percentile(arr, 50)), 3),
@@ -443,6 +464,7 @@ def main():
             for name in ("bucket", "bucket_all_keys", "heap", "heap_lds", "sort"):
                 col = "bucket" if name.startswith("bucket") else name
                 kw = dict(collector=col, lut_u8=args.lut_u8, early_rerank=args.early_rerank and col == "bucket",
+                          sample_factor=op[k]["sample_factor"],
                           keep_all_keys=name == "bucket_all_keys")
                 o = (torch.empty_like(outs[k][0]), torch.empty_like(outs[k][1]), torch.empty_like(outs[k][2]))
                 index.search(qd, k, op[k]["nprobe"], ratio=op[k]["ratio"], out=o, **kw)
@@ -496,7 +518,7 @@ def main():
     # ---- sizes for the algorithmic byte counts ---------------------------------
     sizes = {}
     for k in ks:
-        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+        c = index.search_counts(q, k, op[k]["nprobe"], ratio=op[k]["ratio"], lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=op[k]["sample_factor"])
         sizes[k] = dict(S=int(c["n_scanned"].sum()), Kc=int(c["n_cand"].sum()),
                         sample_keys=int(c["n_sample_keys"].sum()),
                         recheck_mean=float(c["n_recheck"].mean()), boundary_mean=float(c["n_boundary"].mean()),
@@ -674,7 +696,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         ratio = float(args.ratio.split(",")[0])
         rec = None
         if gt is not None:
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
             rec = mean_recall(ids, off)
     else:
         # nprobe is fixed per query by the workload, so a query with few
@@ -683,7 +705,7 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
         # smallest r within 0.005 of the best recall)
         ratio, rec, curve = None, None, []
         for r in (1.5, 2.0, 3.0, 4.0, 6.0, 8.0):
-            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+            ids, _, _, off = index.search(q[rsel], k[rsel], npb[rsel], ratio=r, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
             rr = mean_recall(ids, off)
             log(f"ratio {r}: mean recall {rr:.4f}")
             curve.append((r, rr))
@@ -721,18 +743,19 @@ def run_uneven(args, w, np, torch, bbc, synth, dev):
             bbc.stage_timing(False)
         return el, np.array([a.elapsed_time(b) for a, b in ev])
 
-    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out, lut_u8=args.lut_u8, early_rerank=args.early_rerank), stage_timing=True)
+    eager_s, eager_ms = timed(lambda: index.search(qd, k, npb, ratio=ratio, out=out, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor), stage_timing=True)
     stages = bbc.stage_times(reset=True)
     t0 = time.time()
-    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+    plan = index.plan(qd, k, npb, out, ratio=ratio, autotune=True, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
     plan_s = time.time() - t0
     info = plan.info()
     graph_s, graph_ms = timed(lambda: plan.execute())
     ids_g = out[0].cpu().numpy()
-    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"], lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+    ref = index.search(q, k, npb, ratio=ratio, buckets=info["buckets"], lut_u8=args.lut_u8,
+                       early_rerank=args.early_rerank, sample_factor=info["sample_factor"])
     same = bool(np.array_equal(ids_g, ref[0]))
     value = nq * args.steps / graph_s
-    sz = index.search_counts(q, k, npb, ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank)
+    sz = index.search_counts(q, k, npb, ratio=ratio, lut_u8=args.lut_u8, early_rerank=args.early_rerank, sample_factor=args.sample_factor)
     S, Kc, nsurv = int(sz["n_scanned"].sum()), int(sz["n_cand"].sum()), int(sz["n_survivors"].sum())
     nsk = int(sz["n_sample_keys"].sum())
     code_bytes = w.pq_m if w.pq_bits == 8 else (w.pq_m + 1) // 2

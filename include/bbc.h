@@ -317,15 +317,19 @@ int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t 
  * working meanwhile).  params->device_io must be 1; queries, outputs and
  * out_offsets are fixed at creation: each execution searches whatever the
  * query buffer holds then and overwrites the outputs.  With autotune = 1
- * (PQ, bucket collector) the scan block geometry and the bucket count are
- * chosen by timing each candidate on the batch once (the choice is read
- * back by bbc_plan_info).  Results are identical for every choice. */
+ * (PQ, bucket collector) the scan block geometry (3 shapes), the bucket
+ * count (64, 128, 256), the codebook sample's size (2, 3 or 4 times K_c
+ * keys) and the collector's LDS budget for sorting the threshold bucket
+ * (1024 or 4096 members) are chosen by a coordinate search, two passes,
+ * each candidate timed on the batch itself (the choice is read back by
+ * bbc_plan_info).  Results are identical for every choice. */
 typedef struct bbc_plan bbc_plan;
 int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32_t* nprobe,
                         const bbc_search_params* params, const float* queries, const int64_t* out_offsets,
                         int64_t* out_ids, float* out_dists, int32_t* out_counts, int32_t autotune, bbc_plan** out);
 int32_t bbc_plan_execute(bbc_plan* plan, void* stream);
-int32_t bbc_plan_info(const bbc_plan* plan, int32_t* scan_variant, int32_t* buckets, int64_t* workspace_bytes);
+int32_t bbc_plan_info(const bbc_plan* plan, int32_t* scan_variant, int32_t* buckets, int32_t* sample_factor,
+                      int32_t* bcap, int64_t* workspace_bytes);
 void bbc_plan_free(bbc_plan* plan);
 
 /* Serving form (continuous batching; a request loop with admission by the

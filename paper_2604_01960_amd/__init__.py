@@ -116,7 +116,7 @@ def load(path: Optional[str] = None):
     L.bbc_plan_execute.restype = i32
     L.bbc_plan_execute.argtypes = [vp, vp]
     L.bbc_plan_info.restype = i32
-    L.bbc_plan_info.argtypes = [vp, vp, vp, vp]
+    L.bbc_plan_info.argtypes = [vp, vp, vp, vp, vp, vp]
     L.bbc_plan_free.restype = None
     L.bbc_plan_free.argtypes = [vp]
     L.bbc_server_create.restype = i32
@@ -304,7 +304,7 @@ class Index:
                             int(bool(lut_u8)), int(bool(early_rerank)), int(bool(keep_all_keys)))
 
     def search(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-               nsample: int = 0, out=None, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
+               nsample: int = 0, out=None, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0):
         """Search a batch.  numpy queries: blocking, returns (ids, dists, counts, offsets)
         as numpy.  torch GPU queries: enqueued on `stream` (default: torch's current
         stream); `out` may hold preallocated (ids, dists, counts) torch tensors."""
@@ -324,7 +324,7 @@ class Index:
                        torch.empty(int(off[-1]), dtype=torch.float32, device=queries.device),
                        torch.empty(nq, dtype=torch.int32, device=queries.device))
             ids, dists, counts = out
-            p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+            p = self._params(ratio, collector, buckets, nsample, 1, stream, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
             _check(load().bbc_search(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                      _ptr(ids), _ptr(dists), _ptr(counts)))
             return ids, dists, counts, off
@@ -332,13 +332,13 @@ class Index:
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
-        p = self._params(ratio, collector, buckets, nsample, 0, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, collector, buckets, nsample, 0, stream, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                  _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_noalloc(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                       nsample: int = 0, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
+                       nsample: int = 0, stream=None, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0):
         """bbc_search_noalloc: torch GPU queries and preallocated (ids, dists, counts)
         torch tensors; enqueued on `stream` (default: torch's current stream).  The
         workspace is the library's fixed per-GPU array (BBC_NOALLOC_MAX_BYTES)."""
@@ -355,13 +355,13 @@ class Index:
         ids, dists, counts = out
         if ids.numel() < int(off[-1]) or dists.numel() < int(off[-1]) or counts.numel() < nq:
             raise ValueError("output tensors are too small")
-        p = self._params(ratio, collector, buckets, nsample, 1, stream, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, collector, buckets, nsample, 1, stream, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search_noalloc(self._h, _ptr(queries), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                          _ptr(ids), _ptr(dists), _ptr(counts)))
         return ids, dists, counts, off
 
     def search_counts(self, queries, k, nprobe, ratio: float = 2.0, buckets: int = 0, nsample: int = 0,
-                      lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False):
+                      lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0):
         """Host search returning only per-query sizes: S, K_c, rechecked lists,
         threshold-bucket size."""
         q = _np(queries, np.float32)
@@ -380,13 +380,13 @@ class Index:
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
         tr = SearchTrace(**{f: _ptr(v) for f, v in r.items()})
-        p = self._params(ratio, "bucket", buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, "bucket", buckets, nsample, 0, None, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         _check(load().bbc_search_traced(self._h, _ptr(q), nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(off),
                                         _ptr(ids), _ptr(dists), _ptr(counts), C.byref(tr)))
         return r
 
     def plan(self, queries, k, nprobe, out, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-             nsample: int = 0, autotune: bool = False, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Plan:
+             nsample: int = 0, autotune: bool = False, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0) -> Plan:
         """Capture the search of a fixed device batch (torch queries and
         `out` = (ids, dists, counts) torch buffers) into a replayable plan."""
         import torch
@@ -397,7 +397,7 @@ class Index:
         off[1:] = np.cumsum(kk)
         ids, dists, counts = out
         assert ids.numel() == off[-1] and dists.numel() == off[-1] and counts.numel() == nq
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         h = C.c_void_p()
         torch.cuda.synchronize()
         _check(load().bbc_plan_create(self._h, nq, _ptr(kk), _ptr(npb), C.byref(p), _ptr(queries), _ptr(off),
@@ -405,15 +405,15 @@ class Index:
         return Plan(h.value, self, (queries, ids, dists, counts))
 
     def server(self, mem_budget: int, max_slots: int = 1024, lanes: int = 2, ratio: float = 2.0,
-               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> "Server":
+               collector="bucket", buckets: int = 0, nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0) -> "Server":
         """A continuous-batching server over this index (bbc_server_*)."""
-        p = self._params(ratio, collector, buckets, nsample, 1, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, collector, buckets, nsample, 1, None, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         h = C.c_void_p()
         _check(load().bbc_server_create(self._h, C.byref(p), int(mem_budget), int(max_slots), int(lanes),
                                         C.byref(h)))
         return Server(h.value, self)
 
-    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Dict[str, np.ndarray]:
+    def search_sizes(self, queries, k, nprobe, ratio: float = 2.0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0) -> Dict[str, np.ndarray]:
         """Host search returning per-query sizes only: S (n_scanned), the
         candidates re-ranked (n_cand: K_c for PQ, the objects re-ranked for
         RaBitQ) and, for RaBitQ, n_visited."""
@@ -429,7 +429,7 @@ class Index:
             r["n_visited"] = np.empty(nq, np.int64)
             fields.append("n_visited")
         tr = SearchTrace(**{f: _ptr(r[f]) for f in fields})
-        p = self._params(ratio, "bucket", 0, 0, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, "bucket", 0, 0, 0, None, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         ids = np.empty(int(off[-1]), np.int64)
         dists = np.empty(int(off[-1]), np.float32)
         counts = np.empty(nq, np.int32)
@@ -438,7 +438,7 @@ class Index:
         return r
 
     def search_traced(self, queries, k, nprobe, ratio: float = 2.0, collector="bucket", buckets: int = 0,
-                      nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False) -> Dict[str, np.ndarray]:
+                      nsample: int = 0, lut_u8: bool = False, early_rerank: bool = False, keep_all_keys: bool = False, sample_factor: int = 0) -> Dict[str, np.ndarray]:
         """Host search that also returns every intermediate of the path."""
         q = _np(queries, np.float32)
         nq = q.shape[0]
@@ -448,7 +448,7 @@ class Index:
         off = np.zeros(nq + 1, np.int64)
         off[1:] = np.cumsum(kk)
         L = load()
-        p = self._params(ratio, collector, buckets, nsample, 0, None, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
+        p = self._params(ratio, collector, buckets, nsample, 0, None, sample_factor=sample_factor, lut_u8=lut_u8, early_rerank=early_rerank, keep_all_keys=keep_all_keys)
         r = dict(
             ids=np.empty(int(off[-1]), np.int64), dists=np.empty(int(off[-1]), np.float32),
             counts=np.empty(nq, np.int32), off=off,
@@ -507,9 +507,10 @@ class Plan:
         _check(load().bbc_plan_execute(self._h, C.c_void_p(int(s.cuda_stream))))
 
     def info(self) -> Dict[str, int]:
-        v, b, w = C.c_int32(), C.c_int32(), C.c_int64()
-        _check(load().bbc_plan_info(self._h, C.byref(v), C.byref(b), C.byref(w)))
-        return dict(scan_variant=v.value, buckets=b.value, workspace_bytes=w.value)
+        v, b, f, c, w = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32(), C.c_int64()
+        _check(load().bbc_plan_info(self._h, C.byref(v), C.byref(b), C.byref(f), C.byref(c), C.byref(w)))
+        return dict(scan_variant=v.value, buckets=b.value, sample_factor=f.value, bcap=c.value,
+                    workspace_bytes=w.value)
 
     def free(self):
         if self._h and self._h.value:

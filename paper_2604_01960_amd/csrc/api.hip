@@ -1759,7 +1759,7 @@ struct bbc_plan {
   hipStream_t stream = nullptr;  // capture stream
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  int32_t scan_variant = 0, buckets = 0;
+  int32_t scan_variant = 0, buckets = 0, sample_factor = 0, bcap = 0;
 };
 
 static void plan_release(bbc_plan* pl) {
@@ -1792,38 +1792,74 @@ int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32
     return fail(BBC_EDEVICE, "hipStreamCreateWithFlags failed");
   }
   prm.stream = pl->stream;
-  const int saved_variant = ix->scan_variant;
+  const int saved_variant = ix->scan_variant, saved_bcap = ix->collect_bcap;
   pl->scan_variant = ix->scan_variant;
   pl->buckets = prm.buckets;
-  // autotune (PQ): scan block geometry x bucket count, each timed on the batch
+  pl->sample_factor = prm.sample_factor;
+  pl->bcap = ix->collect_bcap;
+  // autotune (PQ, bucket collector): a coordinate search, timed on the batch
+  // itself, over the scan block geometry, the bucket count, the codebook
+  // sample's size (a larger sample gives a tighter relaxed threshold and
+  // fewer survivors but a costlier codebook) and the collector's LDS budget
+  // for sorting the threshold bucket; two passes over the four.  Every
+  // choice returns the same results.
   if (autotune && ix->quant == BBC_QUANT_PQ && prm.collector == BBC_COLLECT_BUCKET) {
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipEventCreate(&e0);
     hipEventCreate(&e1);
-    float best = 1e30f;
-    const int variants[3] = {0, 1, 2};
-    const int buckets[3] = {64, 128, 256};
-    for (int vi = 0; vi < 3; ++vi)
-      for (int bi = 0; bi < 3; ++bi) {
-        ix->scan_variant = variants[vi];
-        prm.buckets = buckets[bi];
-        float ms = 0.0f;
-        for (int rep = 0; rep < 2 && rc == BBC_OK; ++rep) {
-          hipEventRecord(e0, pl->stream);
-          rc = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts, nullptr);
-          hipEventRecord(e1, pl->stream);
-          hipEventSynchronize(e1);
-          hipEventElapsedTime(&ms, e0, e1);
-        }
-        if (rc) break;
-        if (ms < best) { best = ms; pl->scan_variant = variants[vi]; pl->buckets = buckets[bi]; }
+    int cur[4] = {ix->scan_variant, prm.buckets ? prm.buckets : 256, prm.sample_factor ? prm.sample_factor : 2,
+                  ix->collect_bcap};
+    const std::vector<int> choices[4] = {{0, 1, 2}, {64, 128, 256}, {2, 3, 4}, {1024, 4096}};
+    auto time_of = [&](const int* c, float* out_ms) -> int32_t {
+      ix->scan_variant = c[0];
+      prm.buckets = c[1];
+      prm.sample_factor = c[2];
+      ix->collect_bcap = c[3];
+      float ms = 0.0f;
+      for (int rep = 0; rep < 2; ++rep) {
+        hipEventRecord(e0, pl->stream);
+        const int32_t r = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts,
+                                     nullptr);
+        if (r) return r;
+        hipEventRecord(e1, pl->stream);
+        hipEventSynchronize(e1);
+        hipEventElapsedTime(&ms, e0, e1);
       }
+      *out_ms = ms;
+      return BBC_OK;
+    };
+    float best = 1e30f;
+    rc = time_of(cur, &best);
+    for (int pass = 0; pass < 2 && rc == BBC_OK; ++pass)
+      for (int dim = 0; dim < 4 && rc == BBC_OK; ++dim)
+        for (int v : choices[dim]) {
+          if (v == cur[dim]) continue;
+          int trial[4] = {cur[0], cur[1], cur[2], cur[3]};
+          trial[dim] = v;
+          float ms = 0.0f;
+          if ((rc = time_of(trial, &ms))) break;
+          if (ms < best) {
+            best = ms;
+            cur[dim] = v;
+          }
+        }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    if (rc) { ix->scan_variant = saved_variant; plan_release(pl); return rc; }
+    if (rc) {
+      ix->scan_variant = saved_variant;
+      ix->collect_bcap = saved_bcap;
+      plan_release(pl);
+      return rc;
+    }
+    pl->scan_variant = cur[0];
+    pl->buckets = cur[1];
+    pl->sample_factor = cur[2];
+    pl->bcap = cur[3];
   }
   ix->scan_variant = pl->scan_variant;
+  ix->collect_bcap = pl->bcap;
   prm.buckets = pl->buckets;
+  prm.sample_factor = pl->sample_factor;
   SearchCtx sz;
   sz.size_only = true;
   rc = run_search(ix, queries, nq, k, nprobe, &prm, out_offsets, out_ids, out_dists, out_counts, nullptr, &sz);
@@ -1843,6 +1879,7 @@ int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32
     }
   }
   ix->scan_variant = saved_variant;
+  ix->collect_bcap = saved_bcap;
   pl->graph = cap.graph;
   if (rc == BBC_OK && HIP_FAILED(hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0)))
     rc = fail(BBC_EDEVICE, "hipGraphInstantiate failed");
@@ -1859,10 +1896,13 @@ int32_t bbc_plan_execute(bbc_plan* pl, void* stream) {
   return BBC_OK;
 }
 
-int32_t bbc_plan_info(const bbc_plan* pl, int32_t* scan_variant, int32_t* buckets, int64_t* workspace_bytes) {
+int32_t bbc_plan_info(const bbc_plan* pl, int32_t* scan_variant, int32_t* buckets, int32_t* sample_factor,
+                      int32_t* bcap, int64_t* workspace_bytes) {
   if (!pl) return fail(BBC_EINVAL, "plan is NULL");
   if (scan_variant) *scan_variant = pl->scan_variant;
   if (buckets) *buckets = pl->buckets;
+  if (sample_factor) *sample_factor = pl->sample_factor;
+  if (bcap) *bcap = pl->bcap;
   if (workspace_bytes) *workspace_bytes = (int64_t)pl->ws_bytes;
   return BBC_OK;
 }

@@ -42,6 +42,9 @@ def test_pq_plan_replays_match_eager(bbc, autotune):
     plan = g.plan(qd, k, npb, out, ratio=2.0, autotune=autotune)
     info = plan.info()
     assert info["workspace_bytes"] > 0 and info["scan_variant"] in (0, 1, 2)
+    if autotune:
+        assert info["buckets"] in (64, 128, 256) and info["sample_factor"] in (2, 3, 4)
+        assert info["bcap"] in (1024, 4096)
     for rep in range(4):
         for t in out:
             t.fill_(-7)
