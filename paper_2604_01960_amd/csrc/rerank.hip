@@ -420,8 +420,10 @@ __device__ __forceinline__ int rt_run_pair(const RtGroup& g, uint32_t c) {
 // tree's level 4 pairs lanes p and 7 - p (a DPP half-row mirror) and levels
 // 2 and 1 stay within quads; every lane of the octet ends with the sum.  A
 // candidate's four chunk reads are issued together (clamped to the row;
-// chunks past it count as zero).  IP: the metric is inner product.
-template <typename T, bool IP>
+// chunks past it count as zero).  IP: the metric is inner product.  NC: the
+// row's chunk count when fixed at compile time (32 or 24: no clamps and no
+// selects, constant row stride), 0 for any count up to 32.
+template <typename T, bool IP, int NC>
 __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   constexpr int NT = 1024, NW = NT / 64;
   __shared__ uint4 tile[RT_TILE_BYTES / 16];
@@ -439,8 +441,10 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   const int oct = lane >> 3, p = lane & 7;
   const int vb = p < 4 ? p : 11 - p;
   const int kaddr = 4 * (8 * (lane & 7));  // byte address of lane 8 (l mod 8), which holds candidate l's sum
-  const int nchunk = a.d >> 2;
-  const int row_words = a.d * (int)sizeof(T) / 16;  // 16-byte words per row
+  static_assert(NC == 0 || NC == 32 || NC == 24, "fixed chunk counts");
+  const int nchunk = NC ? NC : a.d >> 2;
+  const int d = 4 * nchunk;
+  const int row_words = d * (int)sizeof(T) / 16;  // 16-byte words per row
   const T* trow = reinterpret_cast<const T*>(tile);
   const uint4* src = reinterpret_cast<const uint4*>(a.vectors) + lb * row_words;
   for (int t = 0; t < ntile; ++t) {
@@ -469,18 +473,34 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int v = vb + 8 * i;
-        qv[i] = v < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * a.d)[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        qv[i] = v < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * d)[v] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
       float mykey = 0.0f;
       for (int it = 0; it * 8 < cnt; ++it) {
         const int rr = __shfl(rowl, it * 8 + oct);  // this octet's candidate (-1: none, row 0 read)
-        const T* row = trow + (int64_t)max(rr, 0) * a.d;
+        const T* row = trow + max(rr, 0) * d;
         float acc[4];
+        if (NC == 32) {
+          float4 x[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-          const float4 xl = load4<T>(row, min(vb + 8 * i, nchunk - 1));
-          const float4 x = vb + 8 * i < nchunk ? xl : make_float4(0.f, 0.f, 0.f, 0.f);
-          acc[i] = IP ? chunk_ip(qv[i], x, 0.0f) : chunk_l2(qv[i], x, 0.0f);
+          for (int i = 0; i < 4; ++i) x[i] = load4<T>(row, vb + 8 * i);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2(qv[i], x[i], 0.0f);
+        } else if (NC == 24) {
+          // virtual lanes 24..31 hold no chunk: their sums are +0
+          float4 x[3];
+#pragma unroll
+          for (int i = 0; i < 3; ++i) x[i] = load4<T>(row, vb + 8 * i);
+#pragma unroll
+          for (int i = 0; i < 3; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2(qv[i], x[i], 0.0f);
+          acc[3] = 0.0f;
+        } else {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const float4 xl = load4<T>(row, min(vb + 8 * i, nchunk - 1));
+            const float4 x = vb + 8 * i < nchunk ? xl : make_float4(0.f, 0.f, 0.f, 0.f);
+            acc[i] = IP ? chunk_ip(qv[i], x, 0.0f) : chunk_l2(qv[i], x, 0.0f);
+          }
         }
         // levels 16 and 8 within the lane, 4 across lanes p and 7 - p
         // (half-row mirror), 2 and 1 within quads
@@ -620,6 +640,19 @@ hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
+template <typename T>
+static void launch_rt_tile(bool ip, int nc, dim3 grid, dim3 block, hipStream_t s, const TileRerankArgs& a) {
+  if (ip) {
+    if (nc == 32) hipLaunchKernelGGL((rt_rerank_tile<T, true, 32>), grid, block, 0, s, a);
+    else if (nc == 24) hipLaunchKernelGGL((rt_rerank_tile<T, true, 24>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((rt_rerank_tile<T, true, 0>), grid, block, 0, s, a);
+  } else {
+    if (nc == 32) hipLaunchKernelGGL((rt_rerank_tile<T, false, 32>), grid, block, 0, s, a);
+    else if (nc == 24) hipLaunchKernelGGL((rt_rerank_tile<T, false, 24>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((rt_rerank_tile<T, false, 0>), grid, block, 0, s, a);
+  }
+}
+
 hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStream_t s) {
   if (a.nq <= 0 || a.npairs <= 0) return hipSuccess;
   if (!a.pairs_ready) {
@@ -641,13 +674,10 @@ hipError_t launch_tile_rerank(const TileRerankArgs& a, size_t sort_lds, hipStrea
     return hipGetLastError();
   }
   const bool ip = a.metric != 0;
-  if (a.fp16) {
-    if (ip) hipLaunchKernelGGL((rt_rerank_tile<__half, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL((rt_rerank_tile<__half, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
-  } else {
-    if (ip) hipLaunchKernelGGL((rt_rerank_tile<float, true>), dim3((unsigned)groups), dim3(1024), 0, s, a);
-    else hipLaunchKernelGGL((rt_rerank_tile<float, false>), dim3((unsigned)groups), dim3(1024), 0, s, a);
-  }
+  const int nc = a.d / 4 == 32 ? 32 : a.d / 4 == 24 ? 24 : 0;
+  const dim3 grid((unsigned)groups), block(1024);
+  if (a.fp16) launch_rt_tile<__half>(ip, nc, grid, block, s, a);
+  else launch_rt_tile<float>(ip, nc, grid, block, s, a);
   return hipGetLastError();
 }
 
