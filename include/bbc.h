@@ -317,7 +317,10 @@ int32_t bbc_stage_times(double* ms, int64_t* launches, int32_t nstages, int32_t 
  * working meanwhile).  params->device_io must be 1; queries, outputs and
  * out_offsets are fixed at creation: each execution searches whatever the
  * query buffer holds then and overwrites the outputs.  With autotune = 1
- * (PQ, bucket collector) the scan block geometry (3 shapes), the bucket
+ * (PQ, bucket collector) the scan block geometry (5 shapes: one block per
+ * CU of 512 threads with 2 or 1 codes per pass or of 1024 threads, two
+ * blocks per CU of 512 threads with 2 or 1 codes, their float tables of
+ * 8-bit codes over 32 sub-spaces in two slices), the bucket
  * count (64, 128, 256), the codebook sample's size (2, 3 or 4 times K_c
  * keys) and the collector's LDS budget for sorting the threshold bucket
  * (1024 or 4096 members) are chosen by a coordinate search, two passes,

@@ -177,7 +177,7 @@ struct bbc_index {
   int max_lds = 65536;
   int num_cu = 256;
   int nxcd = 8;
-  int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0, 1 or 2)
+  int scan_variant = 0;  // grouped PQ scan block geometry (BBC_SCAN_VARIANT: 0 .. 4)
   int walk_form = 0;     // RaBitQ re-rank form (BBC_WALK_FORM: 0 by batch size, 1 per query, 2 wide, 3 wide with tile-major keys)
   int collect_bcap = 4096;  // threshold-bucket members sorted in LDS (BBC_COLLECT_BCAP: a power of two, 64..4096)
   int walk_qcap = 0;        // RaBitQ walk: objects above the k-th exact key resolved in LDS (BBC_WALK_QCAP:
@@ -290,7 +290,7 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
     ix->nxcd = v;
   if (const char* sv = std::getenv("BBC_SCAN_VARIANT")) {
     const int x = std::atoi(sv);
-    if (x >= 0 && x <= 2) ix->scan_variant = x;
+    if (x >= 0 && x <= 4) ix->scan_variant = x;
   }
   if (const char* sv = std::getenv("BBC_WALK_FORM")) {
     const int x = std::atoi(sv);
@@ -1809,7 +1809,7 @@ int32_t bbc_plan_create(bbc_index* ix, int64_t nq, const int32_t* k, const int32
     hipEventCreate(&e1);
     int cur[4] = {ix->scan_variant, prm.buckets ? prm.buckets : 256, prm.sample_factor ? prm.sample_factor : 2,
                   ix->collect_bcap};
-    const std::vector<int> choices[4] = {{0, 1, 2}, {64, 128, 256}, {2, 3, 4}, {1024, 4096}};
+    const std::vector<int> choices[4] = {{0, 1, 2, 3, 4}, {64, 128, 256}, {2, 3, 4}, {1024, 4096}};
     auto time_of = [&](const int* c, float* out_ms) -> int32_t {
       ix->scan_variant = c[0];
       prm.buckets = c[1];

@@ -213,13 +213,25 @@ struct PairOut {
 // lane order), four items per half per round so that their row loads are in
 // flight together.  The survivor's list position carries EARLY_FLAG and its
 // exact key goes to surv_exact at its slot.
-template <int MODE, int BITS, int M, int DSUB, int NT, int O, bool U8, bool EARLY>
-__global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
+//
+// Sliced tables (SL = 2, 8-bit codes, float rows): the table holds the
+// entries of M / SL sub-spaces at a time (64 KB for 32 sub-spaces), so two
+// blocks share a CU and one's table build overlaps the other's lookups.  A
+// group's codes are taken in chunks of up to PMAX passes; for each chunk the
+// slices are built in sub-space order and every pass of the chunk adds the
+// slice's entries to its running sums in registers, so each key is still
+// summed over m = 0 .. M-1 in order.  Lists longer than one chunk rebuild
+// the slices per chunk.
+//
+// BPC: blocks per CU (two: registers capped so that both fit).
+template <int MODE, int BITS, int M, int DSUB, int NT, int O, bool U8, bool EARLY, int SL = 1, int PMAX = 1,
+          int BPC = 1>
+__global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs a) {
   constexpr int G = scan_group_of(U8, BITS);
   constexpr int KSUB = 1 << BITS;
   constexpr int NENT = M * KSUB;
   constexpr int EPT = (NENT + NT - 1) / NT;   // table entries owned by each thread
-  constexpr bool REGCB = EPT * DSUB <= 64;    // owned codewords held in registers
+  constexpr bool REGCB = BPC == 1 && EPT * DSUB <= 64;  // owned codewords held in registers
   constexpr int D = M * DSUB;
   constexpr int CODE_BYTES = BITS == 8 ? M : (M + 1) / 2;
   constexpr int NVEC = (CODE_BYTES + 15) / 16;
@@ -236,6 +248,12 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
   __shared__ float u8_par[3][G];              // per query: base, delta, 1 / delta
   __shared__ uint32_t s_early[EARLY ? G : 1];  // per query of the group: items re-ranked early
   static_assert(!EARLY || (MODE == 1 && D <= 128 && D % 4 == 0), "early re-rank: filter scan, rows of <= 32 chunks");
+  static_assert(SL == 1 || (!U8 && !EARLY && BITS == 8 && (M / SL) % 16 == 0 && NENT % (SL * NT) == 0),
+                "sliced tables: float rows, 8-bit codes, whole 16-byte code words and owned entries per slice");
+  static_assert(SL > 1 || PMAX == 1, "one pass per chunk without slices");
+  constexpr int MS = M / SL;            // sub-spaces per slice
+  constexpr int NVS = NVEC / SL;        // 16-byte code words per slice
+  constexpr int EPS = EPT / SL;         // owned entries per slice
 
   // the codebook is the same for every group: the owned codewords are loaded once
   float creg[REGCB ? EPT : 1][DSUB];
@@ -366,35 +384,41 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
       }
     }
     __syncthreads();
+    // the entries of slice sl (all of them without slices) into the table
+    auto build_slice = [&](int sl) {
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-      const int e = threadIdx.x + i * NT;
-      if (e < NENT) {
-        const int m = e / KSUB;
-        float cw[DSUB];
-#pragma unroll
-        for (int t = 0; t < DSUB; ++t) {
-          if constexpr (REGCB) cw[t] = creg[i][t];
-          else cw[t] = a.codebook[e * DSUB + t];
-        }
-        float out[G];
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-          float acc = 0.0f;
+      for (int i = 0; i < EPT; ++i) {
+        if (i / EPS != sl) continue;
+        const int e = threadIdx.x + i * NT;
+        if (e < NENT) {
+          const int m = e / KSUB;
+          float cw[DSUB];
 #pragma unroll
           for (int t = 0; t < DSUB; ++t) {
-            float u = res[g][m * DSUB + t] - cw[t];
-            u = u * u;
-            acc = acc + u;
+            if constexpr (REGCB) cw[t] = creg[i][t];
+            else cw[t] = a.codebook[e * DSUB + t];
           }
-          out[g] = acc;
-        }
+          float out[G];
 #pragma unroll
-        for (int h = 0; h < FR; ++h)
-          lut4[e * FR + h] = make_float4(out[4 * h], out[4 * h + 1], out[4 * h + 2], out[4 * h + 3]);
+          for (int g = 0; g < G; ++g) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = 0; t < DSUB; ++t) {
+              float u = res[g][m * DSUB + t] - cw[t];
+              u = u * u;
+              acc = acc + u;
+            }
+            out[g] = acc;
+          }
+          const int el = e - sl * (NENT / SL);
+#pragma unroll
+          for (int h = 0; h < FR; ++h)
+            lut4[el * FR + h] = make_float4(out[4 * h], out[4 * h + 1], out[4 * h + 2], out[4 * h + 3]);
+        }
+        asm volatile("" ::: "memory");  // one entry's LDS reads at a time
       }
-      asm volatile("" ::: "memory");  // one entry's LDS reads at a time
-    }
+    };
+    build_slice(0);
     __syncthreads();
     if (c + nw < hi) fetch_places();
     float kbase[G], kdelta[G];
@@ -509,26 +533,42 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
     BlockCompactor<G, NT, O> comp;
     comp.reset();
     const uint8_t* codes = a.codes + lbeg * (NVEC * 16);
-    // block-uniform trip count: every thread takes part in the compaction
-    for (int64_t base = 0; base < nobj; base += NT * O) {
-      bool active[O];
+    // block-uniform trip counts: every thread takes part in the compaction
+    for (int64_t cb = 0; cb < nobj; cb += (int64_t)PMAX * NT * O) {
+    float acc_c[PMAX][O][G];
+    bool active_c[PMAX][O];
+#pragma unroll
+    for (int pp2 = 0; pp2 < PMAX; ++pp2)
+#pragma unroll
+      for (int o = 0; o < O; ++o) {
+        active_c[pp2][o] = cb + pp2 * NT * O + o * NT + threadIdx.x < nobj;
+#pragma unroll
+        for (int g = 0; g < G; ++g) acc_c[pp2][o][g] = 0.0f;
+      }
+#pragma unroll
+    for (int sl = 0; sl < SL; ++sl) {
+      if (sl > 0 || (SL > 1 && cb > 0)) {
+        __syncthreads();  // the previous slice's lookups are done
+        build_slice(sl);
+        __syncthreads();
+      }
+#pragma unroll
+    for (int ps = 0; ps < PMAX; ++ps) {
+      const int64_t base = cb + (int64_t)ps * NT * O;
+      if (base >= nobj) break;  // block-uniform
+      const bool* active = active_c[ps];
       uint32_t w[O][NVEC * 4];
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         const int64_t i = base + o * NT + threadIdx.x;
-        active[o] = i < nobj;
         const uint4* row = reinterpret_cast<const uint4*>(codes + (active[o] ? i : 0) * (NVEC * 16));
 #pragma unroll
-        for (int cc = 0; cc < NVEC; ++cc) {
+        for (int cc = sl * NVS; cc < (sl + 1) * NVS; ++cc) {
           uint4 v = active[o] ? row[cc] : make_uint4(0u, 0u, 0u, 0u);
           w[o][4 * cc + 0] = v.x; w[o][4 * cc + 1] = v.y; w[o][4 * cc + 2] = v.z; w[o][4 * cc + 3] = v.w;
         }
       }
-      float acc[O][G];
-#pragma unroll
-      for (int o = 0; o < O; ++o)
-#pragma unroll
-        for (int g = 0; g < G; ++g) acc[o][g] = 0.0f;
+      float (*acc)[G] = acc_c[ps];
       if constexpr (U8) {
         const uint32_t* lut32 = reinterpret_cast<const uint32_t*>(lut4);
         uint32_t acc16[O][UW];  // word h: 16-bit sums of queries 2h (low) and 2h+1 (high)
@@ -566,15 +606,15 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
       } else {
       if (active[0])  // waves past the end of the list skip the table reads
 #pragma unroll
-      for (int m = 0; m < M; ++m) {
+      for (int m = sl * MS; m < (sl + 1) * MS; ++m) {
         // bounds the table reads in flight: nothing moves across this fence
-        if (m % (4 / O) == 0 && m) asm volatile("" ::: "memory");
+        if (m % (4 / O) == 0 && m > sl * MS) asm volatile("" ::: "memory");
 #pragma unroll
         for (int o = 0; o < O; ++o) {
           uint32_t code;
           if (BITS == 8) code = (w[o][m >> 2] >> (8 * (m & 3))) & 0xffu;
           else code = (w[o][m >> 3] >> (4 * (m & 7))) & 0xfu;
-          const float4 v = lut4[m * KSUB + code];
+          const float4 v = lut4[(m - sl * MS) * KSUB + code];
           acc[o][0] = acc[o][0] + v.x;
           acc[o][1] = acc[o][1] + v.y;
           acc[o][2] = acc[o][2] + v.z;
@@ -582,7 +622,15 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
         }
       }
       }
-      if (base == 0 && c + nw < hi) fetch_inputs();
+    }
+    }
+    if (cb == 0 && c + nw < hi) fetch_inputs();
+#pragma unroll
+    for (int ps = 0; ps < PMAX; ++ps) {
+      const int64_t base = cb + (int64_t)ps * NT * O;
+      if (base >= nobj) break;  // block-uniform
+      const bool* active = active_c[ps];
+      float (*acc)[G] = acc_c[ps];
 #pragma unroll
       for (int o = 0; o < O; ++o) {
         const int64_t i = base + o * NT + threadIdx.x;
@@ -659,6 +707,7 @@ __global__ __launch_bounds__(NT) void pq_scan_grouped(PqScanArgs a) {
           }
         }
       }
+    }
     }
     if (EARLY) __syncthreads();  // the group's early counts are complete
     if (MODE == 1 && threadIdx.x == 0) {
@@ -762,20 +811,23 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   }
 }
 
-template <int BITS, int M, int DSUB, int NT, int O, bool U8>
-static void launch_grouped_t(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
+template <int BITS, int M, int DSUB, int NT, int O, bool U8, int SL, int PMAX, int BPC>
+static void launch_grouped_t(const PqScanArgs& a, int blocks, hipStream_t s) {
+  constexpr int G = scan_group_of(U8, BITS);
+  const size_t lds = sizeof(float) * (size_t)G * (M / SL) * (1 << BITS);
+  const dim3 grid(BPC * blocks), block(NT);
   if (a.mode == 0)
-    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8, false>), dim3(blocks), dim3(NT), lds, s, a);
-  else if (!U8 && a.early)
-    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, false, true>), dim3(blocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8, false, SL, PMAX, BPC>), grid, block, lds, s, a);
+  else if (!U8 && SL == 1 && BPC == 1 && a.early)
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, false, true>), grid, block, lds, s, a);
   else
-    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, U8, false>), dim3(blocks), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((pq_scan_grouped<1, BITS, M, DSUB, NT, O, U8, false, SL, PMAX, BPC>), grid, block, lds, s, a);
 }
 
-template <int BITS, int M, int DSUB, int NT, int O>
-static void launch_grouped(const PqScanArgs& a, int blocks, size_t lds, hipStream_t s) {
-  if (a.lut_u8) launch_grouped_t<BITS, M, DSUB, NT, O, true>(a, blocks, lds, s);
-  else launch_grouped_t<BITS, M, DSUB, NT, O, false>(a, blocks, lds, s);
+template <int BITS, int M, int DSUB, int NT, int O, int SL, int PMAX, int BPC>
+static void launch_grouped(const PqScanArgs& a, int blocks, hipStream_t s) {
+  if (a.lut_u8) launch_grouped_t<BITS, M, DSUB, NT, O, true, 1, 1, BPC>(a, blocks, s);
+  else launch_grouped_t<BITS, M, DSUB, NT, O, false, SL, PMAX, BPC>(a, blocks, s);
 }
 
 // Pairs per scan group of this search: the grouped kernel's group for a
@@ -784,16 +836,37 @@ static int pair_group(const PqScanArgs& a) {
   return pq_scan_grouped_shape(a.bits, a.M, a.d) ? scan_group_of(a.lut_u8 != 0, a.bits) : SCAN_GROUP;
 }
 
+// Block shapes (scan_variant):
+//   0  two blocks of 512 threads per CU, 2 codes per thread and pass (float
+//      tables of 8-bit codes over 32 sub-spaces: in two slices); early
+//      re-rank runs shape 3
+//   1  one block of 512 threads per CU, 1 code per thread and pass
+//   2  one block of 1024 threads per CU, 1 code
+//   3  one block of 512 threads per CU, 2 codes
+//   4  two blocks of 512 threads per CU, 1 code (sliced as shape 0)
 template <int BITS, int M, int DSUB>
 static bool try_grouped(const PqScanArgs& a, hipStream_t s) {
   if (a.bits != BITS || a.M != M || a.d != M * DSUB) return false;
   int blocks = (a.num_cu / a.nxcd) * a.nxcd;
   if (blocks < a.nxcd) blocks = a.nxcd;
-  const size_t lds = sizeof(float) * (size_t)scan_group_of(a.lut_u8 != 0, BITS) * M * (1 << BITS);
+  // float tables that fit twice in LDS need no slices
+  constexpr int SL = (size_t)SCAN_GROUP * M * (1 << BITS) * sizeof(float) > 65536 ? 2 : 1;
+  // two blocks per CU: float tables (sliced when needed), and one-byte
+  // tables whose float staging fits twice; early re-rank keeps one
+  constexpr bool U8_TWO = (size_t)scan_group_of(true, BITS) * M * (1 << BITS) * sizeof(float) <= 65536;
+  const bool two = a.lut_u8 ? U8_TWO : !a.early;
   switch (a.scan_variant) {
-    case 1: launch_grouped<BITS, M, DSUB, 512, 1>(a, blocks, lds, s); break;
-    case 2: launch_grouped<BITS, M, DSUB, 1024, 1>(a, blocks, lds, s); break;
-    default: launch_grouped<BITS, M, DSUB, 512, 2>(a, blocks, lds, s); break;
+    case 1: launch_grouped<BITS, M, DSUB, 512, 1, 1, 1, 1>(a, blocks, s); break;
+    case 2: launch_grouped<BITS, M, DSUB, 1024, 1, 1, 1, 1>(a, blocks, s); break;
+    case 3: launch_grouped<BITS, M, DSUB, 512, 2, 1, 1, 1>(a, blocks, s); break;
+    case 4:
+      if (two) launch_grouped<BITS, M, DSUB, 512, 1, SL, SL == 1 ? 1 : 4, 2>(a, blocks, s);
+      else launch_grouped<BITS, M, DSUB, 512, 2, 1, 1, 1>(a, blocks, s);
+      break;
+    default:
+      if (two) launch_grouped<BITS, M, DSUB, 512, 2, SL, SL == 1 ? 1 : 2, 2>(a, blocks, s);
+      else launch_grouped<BITS, M, DSUB, 512, 2, 1, 1, 1>(a, blocks, s);
+      break;
   }
   return true;
 }

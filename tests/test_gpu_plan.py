@@ -41,7 +41,7 @@ def test_pq_plan_replays_match_eager(bbc, autotune):
     print(f"[case] pq plan autotune={autotune}", flush=True)
     plan = g.plan(qd, k, npb, out, ratio=2.0, autotune=autotune)
     info = plan.info()
-    assert info["workspace_bytes"] > 0 and info["scan_variant"] in (0, 1, 2)
+    assert info["workspace_bytes"] > 0 and info["scan_variant"] in (0, 1, 2, 3, 4)
     if autotune:
         assert info["buckets"] in (64, 128, 256) and info["sample_factor"] in (2, 3, 4)
         assert info["bcap"] in (1024, 4096)

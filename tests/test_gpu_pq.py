@@ -157,7 +157,7 @@ def test_rerank_forms(bbc, form, shape):
     check_trace(tr, exp, 64)
 
 
-@pytest.mark.parametrize("variant", ["0", "1", "2"])
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
 @pytest.mark.parametrize("cfg", [
     # (base workload, n, nlist, M, bits, nq, k, nprobe, ratio, m, nsample)
     ("ivfpq_100k_d128", 20000, 64, 16, 8, 12, 300, 12, 2.0, 64, 8),
@@ -195,6 +195,36 @@ def test_one_byte_tables_match_oracle(bbc, cfg, variant):
     torch.cuda.synchronize()
     np.testing.assert_array_equal(ids.cpu().numpy(), tr["ids"])
     np.testing.assert_array_equal(dists.cpu().numpy(), tr["dists"])
+    g.free()
+
+
+@pytest.mark.parametrize("variant", ["0", "1", "2", "3", "4"])
+def test_scan_block_shapes_match_oracle(bbc, variant):
+    """Every block shape of the float-table scan of 8-bit codes, among them
+    the sliced tables (variants 0 and 4: two 16-sub-space slices, two blocks
+    per CU).  Lists of about 3000 codes take the sliced scan through more than
+    one chunk of passes (the slices rebuilt per chunk), short lists through
+    one; per-query k and nprobe."""
+    import os
+    w, ix, q = oracle_pq_index("ivfpq_1m_d128", 24000, 8, 32, 8, 8)
+    sizes = np.diff(ix["list_off"])
+    assert sizes.max() > 2048 and sizes.min() < 2048
+    print(f"[case] scan shape variant={variant} lists {sizes.min()}..{sizes.max()}", flush=True)
+    old = os.environ.get("BBC_SCAN_VARIANT")
+    os.environ["BBC_SCAN_VARIANT"] = variant
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        if old is None:
+            os.environ.pop("BBC_SCAN_VARIANT")
+        else:
+            os.environ["BBC_SCAN_VARIANT"] = old
+    rng = np.random.default_rng(int(variant) + 11)
+    kk = rng.integers(1, 3000, q.shape[0]).astype(np.int32)
+    npb = rng.integers(1, 9, q.shape[0]).astype(np.int32)
+    for kq, nq_probe, ns in ((900, 5, 2), (kk, npb, 3)):
+        tr = g.search_traced(q, kq, nq_probe, ratio=1.5, buckets=256, nsample=ns)
+        check_trace(tr, expected_steps(ix, q, kq, nq_probe, 1.5, 256, ns), 256)
     g.free()
 
 
