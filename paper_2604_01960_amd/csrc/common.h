@@ -68,6 +68,16 @@ __device__ __forceinline__ float chunk_l2(float4 a, float4 b, float acc) {
   t = a.w - b.w; t = t * t; acc = acc + t;
   return acc;
 }
+// chunk_l2(a, b, 0.0f) without its first addition: 0 + t is t for every
+// square t (never -0), so the result is the same bit for bit
+__device__ __forceinline__ float chunk_l2_0(float4 a, float4 b) {
+  float t, acc;
+  t = a.x - b.x; acc = t * t;
+  t = a.y - b.y; t = t * t; acc = acc + t;
+  t = a.z - b.z; t = t * t; acc = acc + t;
+  t = a.w - b.w; t = t * t; acc = acc + t;
+  return acc;
+}
 __device__ __forceinline__ float chunk_ip(float4 a, float4 b, float acc) {
   float t;
   t = a.x * b.x; acc = acc + t;

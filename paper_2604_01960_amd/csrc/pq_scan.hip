@@ -401,12 +401,14 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
           float out[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) {
+            // the sum from 0 in t order; its first term alone (0 + u is u
+            // for a square)
             float acc = 0.0f;
 #pragma unroll
             for (int t = 0; t < DSUB; ++t) {
               float u = res[g][m * DSUB + t] - cw[t];
               u = u * u;
-              acc = acc + u;
+              acc = t == 0 ? u : acc + u;
             }
             out[g] = acc;
           }
@@ -604,21 +606,42 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
             acc[o][g] = kbase[g] + t;
           }
       } else {
-      if (active[0])  // waves past the end of the list skip the table reads
+      if (active[0]) {  // waves past the end of the list skip the table reads
+        // the table reads of MB sub-spaces are issued together (the fences
+        // keep them apart from the additions), then added in m order; the
+        // first term of a key replaces its 0 + (an entry is a sum of squares,
+        // never -0)
+        constexpr int MB = 4 / O;
 #pragma unroll
-      for (int m = sl * MS; m < (sl + 1) * MS; ++m) {
-        // bounds the table reads in flight: nothing moves across this fence
-        if (m % (4 / O) == 0 && m > sl * MS) asm volatile("" ::: "memory");
+        for (int m0 = sl * MS; m0 < (sl + 1) * MS; m0 += MB) {
+          float4 v[MB][O];
 #pragma unroll
-        for (int o = 0; o < O; ++o) {
-          uint32_t code;
-          if (BITS == 8) code = (w[o][m >> 2] >> (8 * (m & 3))) & 0xffu;
-          else code = (w[o][m >> 3] >> (4 * (m & 7))) & 0xfu;
-          const float4 v = lut4[(m - sl * MS) * KSUB + code];
-          acc[o][0] = acc[o][0] + v.x;
-          acc[o][1] = acc[o][1] + v.y;
-          acc[o][2] = acc[o][2] + v.z;
-          acc[o][3] = acc[o][3] + v.w;
+          for (int mm = 0; mm < MB; ++mm)
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+              const int m = m0 + mm;
+              uint32_t code;
+              if (BITS == 8) code = (w[o][m >> 2] >> (8 * (m & 3))) & 0xffu;
+              else code = (w[o][m >> 3] >> (4 * (m & 7))) & 0xfu;
+              v[mm][o] = lut4[(m - sl * MS) * KSUB + code];
+            }
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int mm = 0; mm < MB; ++mm)
+#pragma unroll
+            for (int o = 0; o < O; ++o) {
+              if (m0 + mm == 0) {
+                acc[o][0] = v[mm][o].x;
+                acc[o][1] = v[mm][o].y;
+                acc[o][2] = v[mm][o].z;
+                acc[o][3] = v[mm][o].w;
+              } else {
+                acc[o][0] = acc[o][0] + v[mm][o].x;
+                acc[o][1] = acc[o][1] + v[mm][o].y;
+                acc[o][2] = acc[o][2] + v[mm][o].z;
+                acc[o][3] = acc[o][3] + v[mm][o].w;
+              }
+            }
         }
       }
       }

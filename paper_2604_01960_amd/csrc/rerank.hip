@@ -485,14 +485,14 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
 #pragma unroll
           for (int i = 0; i < 4; ++i) x[i] = load4<T>(row, vb + 8 * i);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2(qv[i], x[i], 0.0f);
+          for (int i = 0; i < 4; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
         } else if (NC == 24) {
           // virtual lanes 24..31 hold no chunk: their sums are +0
           float4 x[3];
 #pragma unroll
           for (int i = 0; i < 3; ++i) x[i] = load4<T>(row, vb + 8 * i);
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2(qv[i], x[i], 0.0f);
+          for (int i = 0; i < 3; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
           acc[3] = 0.0f;
         } else {
 #pragma unroll
@@ -504,7 +504,8 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
         }
         // levels 16 and 8 within the lane, 4 across lanes p and 7 - p
         // (half-row mirror), 2 and 1 within quads
-        float sum = (acc[0] + acc[2]) + (acc[1] + acc[3]);
+        // (rows of 24 chunks, L2: acc[3] is +0 and acc[1] never -0)
+        float sum = (acc[0] + acc[2]) + (NC == 24 && !IP ? acc[1] : acc[1] + acc[3]);
         sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x141, 0xf, 0xf, false));
         sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x4e, 0xf, 0xf, false));
         sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0xb1, 0xf, 0xf, false));
