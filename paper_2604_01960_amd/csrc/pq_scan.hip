@@ -339,31 +339,21 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     fetch_inputs();
   }
   for (int64_t c = c0; c < hi; c += nw) {
-    uint32_t pp[G];
-    int64_t qq[G];
+    // per pair g of the group: its first output slot (sample keys in phase
+    // 0, survivors in phase 1) and the largest key image it keeps (all keys
+    // when the query does not reject); the pairs, queries and trace offsets
+    // stay in vector registers (lane g), read back where they are needed
     bool valid[G];
-    PairOut out[G];
+    int64_t ooff[G];
+    uint32_t dmax[G], ebits[G];
+    const uint32_t cur_pp = f_pp;
+    const int64_t cur_qq = f_qq, cur_tr = f_tr + f_ro;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
-      pp[g] = lane_value(f_pp, g);
-      qq[g] = lane_value(f_qq, g);
-      valid[g] = pp[g] != NO_PAIR;
-      if (valid[g]) {
-        const int64_t ro = lane_value(f_ro, g), base = lane_value(f_base, g);
-        out[g].trace_out = a.trace_keys ? a.trace_keys + lane_value(f_tr, g) + ro : nullptr;
-        if (MODE == 0) {
-          out[g].sample_out = a.sample_keys + base + ro;
-          out[g].prune = 0;
-          out[g].dmax_bits = 0;
-        } else {
-          out[g].prune = lane_value(f_prune, g);
-          out[g].dmax_bits = lane_value(f_dmax, g);
-          out[g].early_bits = EARLY ? lane_value(f_ebits, g) : 0u;
-          out[g].skey = a.surv_key + base + ro;
-          out[g].spos = a.surv_pos + base + ro;
-          out[g].sexact = EARLY ? a.surv_exact + base + ro : nullptr;
-        }
-      }
+      valid[g] = lane_value(f_pp, g) != NO_PAIR;
+      ooff[g] = valid[g] ? lane_value(f_base, g) + lane_value(f_ro, g) : 0;
+      dmax[g] = MODE == 1 && valid[g] && lane_value(f_prune, g) ? lane_value(f_dmax, g) : 0xffffffffu;
+      ebits[g] = EARLY && valid[g] ? lane_value(f_ebits, g) : 0u;
     }
     const int j = lane_value(f_j, 0);
     float rq[RPT];
@@ -654,17 +644,23 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
       if (base >= nobj) break;  // block-uniform
       const bool* active = active_c[ps];
       float (*acc)[G] = acc_c[ps];
+      if (a.trace_keys) {
+        // (lanes are read in converged code only: a lane's value may be
+        // stale where the lane is inactive)
 #pragma unroll
-      for (int o = 0; o < O; ++o) {
-        const int64_t i = base + o * NT + threadIdx.x;
+        for (int g = 0; g < G; ++g) {
+          const int64_t t0 = lane_value(cur_tr, g) + base + threadIdx.x;
 #pragma unroll
-        for (int g = 0; g < G; ++g)
-          if (valid[g] && active[o] && out[g].trace_out) out[g].trace_out[i] = acc[o][g];
-        if (MODE == 0) {
+          for (int o = 0; o < O; ++o)
+            if (valid[g] && active[o]) a.trace_keys[t0 + o * NT] = acc[o][g];
+        }
+      }
+      if (MODE == 0) {
+#pragma unroll
+        for (int o = 0; o < O; ++o)
 #pragma unroll
           for (int g = 0; g < G; ++g)
-            if (valid[g] && active[o]) out[g].sample_out[i] = acc[o][g];
-        }
+            if (valid[g] && active[o]) a.sample_keys[ooff[g] + base + o * NT + threadIdx.x] = acc[o][g];
       }
       if (MODE == 1) {
         bool keep[O * G];
@@ -672,7 +668,7 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
 #pragma unroll
         for (int o = 0; o < O; ++o)
 #pragma unroll
-          for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && out[g].keep(acc[o][g]);
+          for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && key_bits(acc[o][g]) <= dmax[g];
         comp.step(keep, slot, wcnt);
         bool ear[O * G];
 #pragma unroll
@@ -680,10 +676,10 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
           const int64_t i = base + o * NT + threadIdx.x;
 #pragma unroll
           for (int g = 0; g < G; ++g) {
-            ear[o * G + g] = EARLY && keep[o * G + g] && key_bits(acc[o][g]) < out[g].early_bits;
+            ear[o * G + g] = EARLY && keep[o * G + g] && key_bits(acc[o][g]) < ebits[g];
             if (keep[o * G + g]) {
-              out[g].skey[slot[o * G + g]] = acc[o][g];
-              out[g].spos[slot[o * G + g]] = (uint32_t)(lbeg + i) | (ear[o * G + g] ? EARLY_FLAG : 0u);
+              a.surv_key[ooff[g] + slot[o * G + g]] = acc[o][g];
+              a.surv_pos[ooff[g] + slot[o * G + g]] = (uint32_t)(lbeg + i) | (ear[o * G + g] ? EARLY_FLAG : 0u);
             }
           }
         }
@@ -697,6 +693,7 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
 #pragma unroll
           for (int og = 0; og < O * G; ++og) {
             const int o = og / G, g = og % G;
+            const int64_t qrow = lane_value(cur_qq, g) * NCH;
             uint64_t em = __ballot(ear[og]);
             if (lane == 0 && em) atomicAdd(&s_early[g], (uint32_t)__popcll(em));
             while (em) {  // wave-uniform
@@ -718,13 +715,13 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
                 const bool ok = src[u] >= 0 && hl < NCH;
                 const int64_t row = lbeg + wbase + o * NT + sr;
                 xv[u] = ok ? vec4[row * NCH + hl] : make_float4(0.f, 0.f, 0.f, 0.f);
-                qv[u] = ok ? q4[qq[g] * NCH + hl] : make_float4(0.f, 0.f, 0.f, 0.f);
+                qv[u] = ok ? q4[qrow + hl] : make_float4(0.f, 0.f, 0.f, 0.f);
               }
 #pragma unroll
               for (int u = 0; u < EU; ++u) {
                 float e = a.metric ? chunk_ip(qv[u], xv[u], 0.0f) : chunk_l2(qv[u], xv[u], 0.0f);
                 e = canon_reduce32(e);
-                if (src[u] >= 0 && hl == 0) out[g].sexact[sl[u]] = a.metric ? -e : e;
+                if (src[u] >= 0 && hl == 0) a.surv_exact[ooff[g] + sl[u]] = a.metric ? -e : e;
               }
             }
           }
@@ -733,13 +730,21 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     }
     }
     if (EARLY) __syncthreads();  // the group's early counts are complete
+    uint32_t pg[G];
+    int64_t qgs[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {  // converged: every lane active
+      pg[g] = lane_value(cur_pp, g);
+      qgs[g] = lane_value(cur_qq, g);
+    }
     if (MODE == 1 && threadIdx.x == 0) {
 #pragma unroll
       for (int g = 0; g < G; ++g) {
         if (valid[g]) {
-          a.pair_nsurv[pp[g]] = comp.total[g];
-          if (nobj > comp.total[g]) atomicAdd(a.n_rejected + qq[g], (uint32_t)(nobj - comp.total[g]));
-          if (EARLY && s_early[g]) atomicAdd(a.n_early + qq[g], s_early[g]);
+          const int64_t qg = qgs[g];
+          a.pair_nsurv[pg[g]] = comp.total[g];
+          if (nobj > comp.total[g]) atomicAdd(a.n_rejected + qg, (uint32_t)(nobj - comp.total[g]));
+          if (EARLY && s_early[g]) atomicAdd(a.n_early + qg, s_early[g]);
         }
         if (EARLY) s_early[g] = 0u;
       }
