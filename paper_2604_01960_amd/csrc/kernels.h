@@ -167,7 +167,7 @@ hipError_t launch_rerank(const RerankArgs& a, int64_t max_kc, hipStream_t s);
 constexpr int QUERY_ORDER_MAX_LISTS = 32768;
 
 // Tile-major re-rank (rows of at most 256 four-element chunks).
-constexpr int RT_G = 128;              // (query, list) pairs per block, rows of at most 32 chunks
+constexpr int RT_G = 256;              // (query, list) pairs per block, rows of at most 32 chunks
 constexpr int RT_GW = 16;              // the same for longer rows (one pair per wave)
 constexpr int RT_TILE_BYTES = 65536;   // LDS rows per tile
 struct TileRerankArgs {
