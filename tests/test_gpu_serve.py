@@ -73,7 +73,12 @@ def test_admission_bounds_what_is_in_flight(bbc):
         res = _collect(srv, tickets)
         st = srv.stats()
         # a request bigger than the whole budget is refused at submission
-        if budget < (1 << 32):
+        # (the budget of one request: any larger one; the others: when the
+        # largest request this index allows is bigger still)
+        big = g.query_bytes(20 * k, 50, ratio=2.0)
+        if budget == one:
+            assert big > budget
+        if big > budget:
             with pytest.raises(bbc.BBCError) as e:
                 srv.submit(q[0], 20 * k, 50)
             assert e.value.code == bbc.ENOMEM
