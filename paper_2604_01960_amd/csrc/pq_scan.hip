@@ -103,10 +103,16 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v)
 // of the block calls step() with the keep flags of its O elements
 // (keep[o * G + g]); each kept element gets the next slot of its stream, in
 // (wave, element, lane) order within a call and call order across calls.  One
-// barrier per call; the per-wave counts are double buffered so consecutive
-// calls need no second barrier.
+// barrier per call: each wave posts its counts packed two streams to a word
+// (16 bits each: a call keeps at most NT * O < 65536 per stream), and lanes
+// 0 .. NW-1 of every wave then read one wave's words each and scan them
+// across lanes (DPP shifts within the first row).  The words are double
+// buffered so consecutive calls need no second barrier.
 template <int G, int NT, int O = 1>
 struct BlockCompactor {
+  static constexpr int NW = NT / 64;
+  static constexpr int NPK = (G + 1) / 2;
+  static_assert(NW <= 16 && NT * O < 65536, "one DPP row of waves, 16-bit counts");
   uint32_t total[G];
   int parity;
   __device__ __forceinline__ void reset() {
@@ -114,10 +120,13 @@ struct BlockCompactor {
     for (int g = 0; g < G; ++g) total[g] = 0;
     parity = 0;
   }
-  __device__ __forceinline__ void step(const bool* keep, uint32_t* slot, uint32_t (*wc)[G][NT / 64]) {
+  __device__ __forceinline__ void step(const bool* keep, uint32_t* slot, uint32_t (*wc)[NW][NPK]) {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const uint64_t below = (1ull << lane) - 1ull;
     uint64_t mask[O][G];
+    uint32_t pk[NPK];
+#pragma unroll
+    for (int j = 0; j < NPK; ++j) pk[j] = 0u;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       uint32_t n = 0;
@@ -126,24 +135,37 @@ struct BlockCompactor {
         mask[o][g] = __ballot(keep[o * G + g]);
         n += (uint32_t)__popcll(mask[o][g]);
       }
-      if (lane == 0) wc[parity][g][w] = n;
+      pk[g >> 1] |= n << (16 * (g & 1));
+    }
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < NPK; ++j) wc[parity][w][j] = pk[j];
     }
     __syncthreads();
 #pragma unroll
-    for (int g = 0; g < G; ++g) {
-      uint32_t off = total[g], sum = 0;
+    for (int j = 0; j < NPK; ++j) {
+      // inclusive scan of the waves' words over lanes 0 .. NW-1
+      uint32_t v = lane < NW ? wc[parity][lane][j] : 0u;
+      // row_shr:1, 2, 4, 8 (zero from before the row's start)
+      v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, true);
+      if (NW > 2) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, true);
+      if (NW > 4) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, true);
+      if (NW > 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, true);
+      const uint32_t ex = w ? (uint32_t)__builtin_amdgcn_readlane((int)v, w - 1) : 0u;
+      const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)v, NW - 1);
 #pragma unroll
-      for (int ww = 0; ww < NT / 64; ++ww) {
-        const uint32_t c = wc[parity][g][ww];
-        if (ww < w) off += c;
-        sum += c;
-      }
+      for (int h = 0; h < 2; ++h) {
+        const int g = 2 * j + h;
+        if (g < G) {
+          uint32_t off = total[g] + ((ex >> (16 * h)) & 0xffffu);
 #pragma unroll
-      for (int o = 0; o < O; ++o) {
-        slot[o * G + g] = off + (uint32_t)__popcll(mask[o][g] & below);
-        off += (uint32_t)__popcll(mask[o][g]);
+          for (int o = 0; o < O; ++o) {
+            slot[o * G + g] = off + (uint32_t)__popcll(mask[o][g] & below);
+            off += (uint32_t)__popcll(mask[o][g]);
+          }
+          total[g] += (tot >> (16 * h)) & 0xffffu;
+        }
       }
-      total[g] += sum;
     }
     parity ^= 1;
   }
@@ -242,7 +264,7 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
   static_assert(!U8 || M * 255 < 65536, "16-bit partial sums");
   extern __shared__ __align__(16) float4 lut4[];   // [NENT * FR]: entry e for the group's queries
   __shared__ __align__(16) float res[G][D];
-  __shared__ uint32_t wcnt[2][G][NT / 64];
+  __shared__ uint32_t wcnt[2][NT / 64][(G + 1) / 2];
   __shared__ float u8_lo[U8 ? M : 1][G];      // per (sub-space, query) minimum
   __shared__ float u8_wspan[U8 ? NW : 1][G];  // per wave: largest range seen
   __shared__ float u8_par[3][G];              // per query: base, delta, 1 / delta
@@ -792,7 +814,7 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   const int64_t nobj = a.list_off[j + 1] - lbeg;
   PairOut out;
   out.init(a, MODE, qi, p);
-  __shared__ uint32_t wcnt[2][1][NT / 64];
+  __shared__ uint32_t wcnt[2][NT / 64][1];
   BlockCompactor<1, NT> comp;
   comp.reset();
   const int stride = a.code_stride;  // bytes per code row, multiple of 16
