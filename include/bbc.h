@@ -278,14 +278,18 @@ void bbc_index_free(bbc_index* ix);
 
 /* Index files: bbc_index_save writes the index's host-side image (what the
  * create calls take) to `path`; bbc_index_load reads one and creates the
- * index on `device` (BBC_EINVAL for a missing, foreign, truncated or
- * inconsistent file).  Layout, little-endian, arrays packed in this order:
- *   char[8] "BBCIDX1\0"; int32 quant, metric, storage, d, nlist, pq_m,
+ * index on `device` (BBC_EINVAL for a missing, foreign, truncated,
+ * inconsistent or altered file).  Layout, little-endian, arrays packed in
+ * this order:
+ *   char[8] "BBCIDX2\0"; int32 quant, metric, storage, d, nlist, pq_m,
  *   pq_bits, 0; int64 n; float32 eps0; int32 0            (56 bytes)
  *   float32 centroids [nlist][d]; int64 list_off [nlist+1]; int64 list_ids [n]
  *   PQ:     float32 codebook [pq_m][2^pq_bits][d/pq_m]; uint8 codes [n][pq_m]
  *   RaBitQ: float32 rotation [d][d]; uint32 codes [n][d/32]; float32 factors [n][4]
  *   base [n][d] float32, or float16 when storage = BBC_STORAGE_FP16, row-id order
+ *   uint64 checksum: FNV-1a over the bytes after the header taken as
+ *     little-endian 64-bit words (the last one zero-padded): h = 0xcbf29ce484222325,
+ *     then h = (h ^ word) * 0x100000001b3 (mod 2^64) for each word
  * The caller owns `path`; the file holds the whole base (about n*d*4 bytes). */
 int32_t bbc_index_save(const bbc_index* ix, const char* path);
 int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out);

@@ -47,10 +47,15 @@ def lib():
     global _lib
     with _lock:
         if _lib is None:
-            if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
-                    os.path.getmtime(_SRC), os.path.getmtime(_SRC64)):
-                build()
-            L = C.CDLL(_LIB_PATH)
+            # ORACLE_LIB: another build of the same sources (the sanitizer
+            # test loads an instrumented one)
+            path = os.environ.get("ORACLE_LIB")
+            if not path:
+                path = _LIB_PATH
+                if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(
+                        os.path.getmtime(_SRC), os.path.getmtime(_SRC64)):
+                    build()
+            L = C.CDLL(path)
             vp, i32, i64, f32, f64 = C.c_void_p, C.c_int32, C.c_int64, C.c_float, C.c_double
             L.orc_canon_l2.restype = f32
             L.orc_canon_l2.argtypes = [vp, vp, i32]

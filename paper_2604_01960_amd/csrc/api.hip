@@ -590,7 +590,46 @@ void bbc_index_free(bbc_index* ix) { index_release(ix); }
 
 namespace {
 
-constexpr char kIndexMagic[8] = {'B', 'B', 'C', 'I', 'D', 'X', '1', '\0'};
+constexpr char kIndexMagic[8] = {'B', 'B', 'C', 'I', 'D', 'X', '2', '\0'};
+
+// Checksum of an index file's arrays: FNV-1a over little-endian 64-bit words
+// of the bytes after the header (the last word zero-padded), the FNV-1a
+// 64-bit offset basis and prime; fed section by section.
+struct WordFnv64 {
+  uint64_t h = 0xcbf29ce484222325ull;
+  uint8_t carry[8] = {};
+  int nc = 0;
+  void word(uint64_t w) { h = (h ^ w) * 0x100000001b3ull; }
+  void add(const void* data, size_t n) {
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    while (n && nc) {  // complete a carried word
+      carry[nc++] = *p++;
+      --n;
+      if (nc == 8) {
+        uint64_t w;
+        std::memcpy(&w, carry, 8);
+        word(w);
+        nc = 0;
+      }
+    }
+    for (; n >= 8; n -= 8, p += 8) {
+      uint64_t w;
+      std::memcpy(&w, p, 8);
+      word(w);
+    }
+    while (n--) carry[nc++] = *p++;
+  }
+  uint64_t final() {
+    if (nc) {
+      std::memset(carry + nc, 0, (size_t)(8 - nc));
+      uint64_t w;
+      std::memcpy(&w, carry, 8);
+      word(w);
+      nc = 0;
+    }
+    return h;
+  }
+};
 
 struct IndexFileHeader {
   char magic[8];
@@ -640,12 +679,16 @@ int32_t bbc_index_save(const bbc_index* ix, const char* path) {
   std::unique_ptr<FILE, FileCloser> f(std::fopen(path, "wb"));
   if (!f) return fail(BBC_EINVAL, std::string("cannot open for writing: ") + path);
   if (std::fwrite(&h, sizeof(h), 1, f.get()) != 1) return fail(BBC_EINVAL, "write failed");
+  WordFnv64 sum;
   for (size_t i = 0; i < sec.size(); ++i) {
     std::vector<char> buf((size_t)sec[i]);
     const int32_t rc = bbc_index_get(ix, fields[i], buf.data(), sec[i]);
     if (rc) return rc;
+    sum.add(buf.data(), buf.size());
     if (sec[i] && std::fwrite(buf.data(), 1, buf.size(), f.get()) != buf.size()) return fail(BBC_EINVAL, "write failed");
   }
+  const uint64_t cs = sum.final();
+  if (std::fwrite(&cs, sizeof(cs), 1, f.get()) != 1) return fail(BBC_EINVAL, "write failed");
   if (std::fflush(f.get()) != 0) return fail(BBC_EINVAL, "write failed");
   return BBC_OK;
 }
@@ -665,18 +708,23 @@ int32_t bbc_index_load(int32_t device, const char* path, bbc_index** out) {
       (pq && (h.pq_m < 1 || h.d % h.pq_m || (h.pq_bits != 4 && h.pq_bits != 8))) || (!pq && h.d % 64))
     return fail(BBC_EINVAL, "index file header out of range");
   const std::vector<int64_t> sec = index_file_sections(h);
-  int64_t total = (int64_t)sizeof(h);
+  int64_t total = (int64_t)sizeof(h) + (int64_t)sizeof(uint64_t);  // header, arrays, checksum
   for (int64_t b : sec) total += b;
   if (std::fseek(f.get(), 0, SEEK_END) != 0 || std::ftell(f.get()) != total)
     return fail(BBC_EINVAL, "index file size does not match its header");
   std::fseek(f.get(), (long)sizeof(h), SEEK_SET);
   std::vector<std::vector<char>> a(sec.size());
+  WordFnv64 sum;
   for (size_t i = 0; i < sec.size(); ++i) {
     a[i].resize((size_t)sec[i]);
     if (sec[i] && std::fread(a[i].data(), 1, a[i].size(), f.get()) != a[i].size())
       return fail(BBC_EINVAL, "index file read failed");
+    sum.add(a[i].data(), a[i].size());
   }
+  uint64_t cs = 0;
+  if (std::fread(&cs, sizeof(cs), 1, f.get()) != 1) return fail(BBC_EINVAL, "index file read failed");
   f.reset();
+  if (cs != sum.final()) return fail(BBC_EINVAL, "index file checksum mismatch (the arrays were altered)");
   const float* cent = reinterpret_cast<const float*>(a[0].data());
   const int64_t* list_off = reinterpret_cast<const int64_t*>(a[1].data());
   const int64_t* list_ids = reinterpret_cast<const int64_t*>(a[2].data());

@@ -111,13 +111,24 @@ def check_trace(tr, exp, m, bucket=True):
         np.testing.assert_array_equal(tr["dists"][os_], e["dists"], err_msg=f"dists q{i}")
 
 
+def word_fnv64(body: bytes) -> int:
+    """The index file checksum as documented: FNV-1a over little-endian
+    64-bit words of `body` (the last zero-padded)."""
+    pad = (-len(body)) % 8
+    words = np.frombuffer(body + b"\0" * pad, "<u8")
+    h, mask = 0xcbf29ce484222325, (1 << 64) - 1
+    for w in words.tolist():
+        h = ((h ^ w) * 0x100000001b3) & mask
+    return h
+
+
 def read_index_file(path):
     """Arrays of an index file, parsed from its documented layout (a 56-byte
     header of int32 quant, metric, storage, d, nlist, pq_m, pq_bits, 0, int64
-    n, float32 eps0, then the packed arrays); checks that the sizes add up
-    to the file size."""
+    n, float32 eps0, then the packed arrays and a 64-bit checksum); checks
+    that the sizes add up to the file size and the checksum."""
     raw = np.fromfile(path, np.uint8)
-    assert raw[:8].tobytes() == b"BBCIDX1\0"
+    assert raw[:8].tobytes() == b"BBCIDX2\0"
     quant, metric, storage, d, nlist, pq_m, pq_bits, _ = (int(v) for v in raw[8:40].view(np.int32))
     n = int(raw[40:48].view(np.int64)[0])
     eps0 = float(raw[48:52].view(np.float32)[0])
@@ -142,5 +153,6 @@ def read_index_file(path):
         f["codes"] = take(np.uint32, (n, d // 32))
         f["factors"] = take(np.float32, (n, 4))
     f["base"] = take(np.float16 if storage == 1 else np.float32, (n, d))
-    assert off == raw.size
+    assert off + 8 == raw.size
+    assert int(raw[off:].view("<u8")[0]) == word_fnv64(raw[56:off].tobytes())
     return f

@@ -71,6 +71,27 @@ def test_rabitq_fp16_file_round_trip(bbc, tmp_path):
     np.testing.assert_array_equal(got[1], ref["dists"])
 
 
+def test_altered_file_is_refused(bbc, tmp_path):
+    """One flipped bit anywhere in a saved file's arrays fails the load with
+    BBC_EINVAL (checksum mismatch); the untouched file still loads."""
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 4000, 8, 16, 8, 2)
+    g = make_gpu_index(bbc, ix)
+    path = str(tmp_path / "flip.bbc")
+    print("[case] altered index file", flush=True)
+    g.save(path)
+    raw = np.fromfile(path, np.uint8)
+    for pos in (56, raw.size // 2, raw.size - 9):
+        bad = raw.copy()
+        bad[pos] ^= 0x10
+        bp = str(tmp_path / f"flip_{pos}.bbc")
+        bad.tofile(bp)
+        with pytest.raises(bbc.BBCError) as e:
+            bbc.Index.load(bp)
+        assert e.value.code == bbc.EINVAL and "checksum" in str(e.value)
+    h = bbc.Index.load(path)
+    _same_search(g, h, q, 50, 3)
+
+
 def test_gpu_built_index_round_trip(bbc, tmp_path):
     w = synth.small_workload("ivfpq4_10m_d96", n=30000, nlist=40, nq=8, pq_m=48, pq_bits=4)
     x = synth.base_vectors(w)

@@ -1,5 +1,5 @@
-"""Index files without a GPU: loading a missing, foreign, truncated or
-inconsistent file fails with BBC_EINVAL before any device work."""
+"""Index files without a GPU: loading a missing, foreign, truncated,
+inconsistent or altered file fails with BBC_EINVAL before any device work."""
 import numpy as np
 import pytest
 
@@ -13,7 +13,7 @@ def bbc():
 
 def _header(quant=0, metric=0, storage=0, d=8, nlist=2, pq_m=2, pq_bits=8, n=4, eps0=0.0):
     h = np.zeros(56, np.uint8)
-    h[:8] = np.frombuffer(b"BBCIDX1\0", np.uint8)
+    h[:8] = np.frombuffer(b"BBCIDX2\0", np.uint8)
     h[8:40] = np.array([quant, metric, storage, d, nlist, pq_m, pq_bits, 0], np.int32).view(np.uint8)
     h[40:48] = np.array([n], np.int64).view(np.uint8)
     h[48:52] = np.array([eps0], np.float32).view(np.uint8)
@@ -51,5 +51,29 @@ def test_size_must_match_the_header(bbc, tmp_path):
     np.concatenate([_header(), np.zeros(body - 1, np.uint8)]).tofile(p)
     assert _load_rc(bbc, p)[0] == bbc.EINVAL
     assert "size" in bbc.load().bbc_last_error().decode()
-    np.concatenate([_header(), np.zeros(body + 8, np.uint8)]).tofile(p)
+    np.concatenate([_header(), np.zeros(body + 16, np.uint8)]).tofile(p)
     assert _load_rc(bbc, p)[0] == bbc.EINVAL
+    # the arrays without their checksum
+    np.concatenate([_header(), np.zeros(body, np.uint8)]).tofile(p)
+    assert _load_rc(bbc, p)[0] == bbc.EINVAL
+    assert "size" in bbc.load().bbc_last_error().decode()
+
+
+def test_checksum_of_the_arrays(bbc, tmp_path):
+    """A file of the right size whose checksum does not match its arrays is
+    refused; the checksum routine itself is pinned to FNV-1a's published
+    64-bit test values (the empty input gives the offset basis; one word
+    of zeros gives basis * prime mod 2^64)."""
+    from helpers import word_fnv64
+    assert word_fnv64(b"") == 0xcbf29ce484222325
+    assert word_fnv64(b"\0") == (0xcbf29ce484222325 * 0x100000001b3) % (1 << 64)
+    assert word_fnv64(b"\x01") == ((0xcbf29ce484222325 ^ 1) * 0x100000001b3) % (1 << 64)
+    n, d, nlist, m, bits = 4, 8, 2, 2, 8
+    body = 4 * nlist * d + 8 * (nlist + 1) + 8 * n + 4 * m * (1 << bits) * (d // m) + n * m + 4 * n * d
+    arrays = np.random.default_rng(0).integers(0, 255, body).astype(np.uint8)
+    arrays[4 * nlist * d:4 * nlist * d + 8 * (nlist + 1)] = 0  # list_off all zero: consistent only if checked later
+    good = word_fnv64(arrays.tobytes())
+    p = tmp_path / "altered.bbc"
+    np.concatenate([_header(), arrays, np.array([good ^ 1], "<u8").view(np.uint8)]).tofile(p)
+    assert _load_rc(bbc, p)[0] == bbc.EINVAL
+    assert "checksum" in bbc.load().bbc_last_error().decode()
