@@ -843,6 +843,55 @@ struct SearchCtx {
   hipEvent_t meta_ev = nullptr;
 };
 
+// The final top-k's launches: queries grouped by the kernel form their
+// candidate capacity selects (register-resident forms for small sets, the
+// memory form for large ones), each group with the LDS its own largest
+// min(k, K_c) needs, so that a few large queries do not set the form and the
+// LDS of a whole batch.  order lists the queries group by group.
+struct FinalGroups {
+  std::vector<int32_t> order;
+  struct G { int64_t beg = 0, n = 0, max_kc = 0, max_cnt = 1; };
+  std::vector<G> groups;
+};
+
+void final_groups(int64_t nq, const int32_t* k, const std::vector<int64_t>& cap_of, FinalGroups& fg) {
+  const int forms[5] = {8, 16, 24, 32, 0};
+  fg.order.resize((size_t)nq);
+  fg.groups.clear();
+  int64_t at = 0;
+  for (int f : forms) {
+    FinalGroups::G g;
+    g.beg = at;
+    for (int64_t i = 0; i < nq; ++i) {
+      if (bbc::final_topk_form(cap_of[(size_t)i]) != f) continue;
+      fg.order[(size_t)at++] = (int32_t)i;
+      g.max_kc = std::max(g.max_kc, cap_of[(size_t)i]);
+      g.max_cnt = std::max(g.max_cnt, std::min<int64_t>(k[i], cap_of[(size_t)i]));
+    }
+    g.n = at - g.beg;
+    if (g.n) fg.groups.push_back(g);
+  }
+}
+
+// One launch per group (a group's form from its largest K_c, its LDS from its
+// largest min(k, K_c)).
+int32_t launch_final_groups(bbc_index* ix, const FinalGroups& fg, const int32_t* d_order, bbc::FinalArgs fa,
+                            hipStream_t s) {
+  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
+  for (const auto& g : fg.groups) {
+    const int cap = (int)std::min(g.max_cnt, cap_max);
+    int run = 1;
+    while (2 * run <= cap) run *= 2;
+    fa.nq = g.n;
+    fa.qmap = d_order + g.beg;
+    fa.cap = cap;
+    fa.run = run;
+    fa.max_kc = g.max_kc;
+    HIP_TRY(bbc::launch_final_topk(fa, s));
+  }
+  return BBC_OK;
+}
+
 // Host staging of a search's metadata block: the caller-given fixed buffer,
 // or the index's pinned buffer (grown when too small).  Waits until the
 // previous upload out of that buffer is done before it is rewritten.
@@ -949,9 +998,16 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   const bool want_tiles = ix->walk_form == 3 || (ix->walk_form == 0 && nq > ix->num_cu);
   const bool tile_keys = want_tiles && tile_plan(ix, nq, nprobe, max_np, 256, bin_off, &rt_shift, &rt_bins, &rt_lds);
   if (!tile_keys) bin_off.assign(nq + 1, 0);
+  FinalGroups fg;
+  {
+    std::vector<int64_t> cap_of((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) cap_of[(size_t)i] = key_off[i + 1] - key_off[i];
+    final_groups(nq, k, cap_of, fg);
+  }
   Plan mp;
   const size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)),
-               m_ko = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1));
+               m_ko = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1)),
+               m_fq = mp.add(4 * nq);
   Plan pl;
   const size_t L_meta = pl.add(mp.total);
   const size_t L_q = host_io ? pl.add(sizeof(float) * nq * d) : 0;
@@ -1010,6 +1066,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   std::memcpy(H + m_ko, key_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_oo, out_off, 8 * (nq + 1));
   std::memcpy(H + m_bo, bin_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_fq, fg.order.data(), 4 * nq);
   char* M = A + L_meta;
   if (ctx && ctx->capture) {
     HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
@@ -1153,20 +1210,14 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
       HIP_TRY(bbc::launch_rabitq_walk(wa, s));
     }
   }
-  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
-  const int cap = (int)std::min(max_cnt, cap_max);
-  int run = 1;
-  while (2 * run <= cap) run *= 2;
   bbc::FinalArgs fa{};
-  fa.nq = nq; fa.k = d_k; fa.n_cand = wa.n_cand; fa.cand_off = d_ko; fa.cand_packed = wa.cand_packed;
+  fa.k = d_k; fa.n_cand = wa.n_cand; fa.cand_off = d_ko; fa.cand_packed = wa.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
-  fa.cap = cap;
-  fa.run = run;
-  fa.max_kc = max_cap;
   {
     StageScope st(s, 5);
-    HIP_TRY(bbc::launch_final_topk(fa, s));
+    if ((rc = launch_final_groups(ix, fg, reinterpret_cast<const int32_t*>(M + m_fq), fa, s))) return rc;
   }
+  fa.max_kc = max_cap;
   if (host_io) {
     HIP_TRY(hipMemcpyAsync(out_ids, d_oid, 8 * nout, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(out_dists, d_odist, 4 * nout, hipMemcpyDeviceToHost, s));
@@ -1282,10 +1333,17 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   if (!tile_rr) bin_off.assign(nq + 1, 0);
 
   // metadata block (one upload): k, nprobe, then the prefix arrays
+  FinalGroups fg;
+  {
+    std::vector<int64_t> cap_of((size_t)nq);
+    for (int64_t i = 0; i < nq; ++i) cap_of[(size_t)i] = cand_off[i + 1] - cand_off[i];
+    final_groups(nq, k, cap_of, fg);
+  }
   Plan mp;
   size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),
          m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)),
-         m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1));
+         m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1)),
+         m_fq = mp.add(4 * nq);
   Plan pl;
   Layout L{};
   L.meta = pl.add(mp.total);
@@ -1368,6 +1426,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::memcpy(H + m_so, sample_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_vo, surv_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_bo, bin_off.data(), 8 * (nq + 1));
+  std::memcpy(H + m_fq, fg.order.data(), 4 * nq);
   char* M = A + L.meta;
   if (ctx && ctx->capture) {
     HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
@@ -1559,22 +1618,14 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
 
   // final top-k LDS: `cap` packed items (dynamic; the largest min(k, K_c) of
   // the batch when it fits) + the kernel's static tables
-  int64_t max_cnt = 1;
-  for (int64_t i = 0; i < nq; ++i) max_cnt = std::max(max_cnt, std::min<int64_t>(k[i], cand_off[i + 1] - cand_off[i]));
-  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
-  const int cap = (int)std::min(max_cnt, cap_max);
-  int run = 1;
-  while (2 * run <= cap) run *= 2;
   bbc::FinalArgs fa{};
-  fa.nq = nq; fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
+  fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
-  fa.cap = cap;
-  fa.run = run;
-  fa.max_kc = max_kc;
   {
     StageScope st(s, 5);
-    HIP_TRY(bbc::launch_final_topk(fa, s));
+    if ((rc = launch_final_groups(ix, fg, reinterpret_cast<const int32_t*>(M + m_fq), fa, s))) return rc;
   }
+  fa.max_kc = max_kc;
 
   if (host_io) {
     HIP_TRY(hipMemcpyAsync(out_ids, d_oid, 8 * nout, hipMemcpyDeviceToHost, s));

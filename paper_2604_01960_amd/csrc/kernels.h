@@ -216,7 +216,8 @@ struct FinalArgs {
   const int64_t* out_off; int64_t* out_ids; float* out_dists; int32_t* out_counts; int metric;
   int cap;                  // packed items in the dynamic LDS buffer (queries with min(k, K_c) <= cap use the binned path)
   int run;                  // largest power of two <= cap: LDS sort run of the global sort
-  int64_t max_kc;           // largest K_c of the batch (selects the register-resident variant)
+  int64_t max_kc;           // largest K_c of the launch's queries (selects the register-resident variant)
+  const int32_t* qmap;      // the launch's queries: block b takes query qmap[b] (nullptr: query b)
 };
 // ---- comparator collectors (heap, sort) over every scanned key ----------------
 struct CompareArgs {

@@ -316,7 +316,7 @@ __global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_to
   __shared__ __align__(8) uint32_t red[12];
   uint32_t* bc = red;
 
-  const int64_t qi = blockIdx.x;
+  const int64_t qi = a.qmap ? (int64_t)a.qmap[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t kc = a.n_cand[qi];
   const int64_t k = a.k[qi];
   const int64_t cnt = kc < k ? kc : k;
