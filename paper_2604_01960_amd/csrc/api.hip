@@ -193,8 +193,10 @@ struct bbc_index {
   int scan_by_list = 1;
   // RaBitQ wide form: the first round's keys reach this fraction of the way
   // from the k-th smallest lb's bin to U's bin (BBC_WALK_ALPHA; >= 1: one
-  // round over all of C)
-  float walk_alpha = 0.8f;
+  // round over all of C).  Unset (< 0): 0.8 with tile-major keys (large
+  // batches), one round with the grid's keys (small batches, where a second
+  // round's launches cost more latency than the keys they save)
+  float walk_alpha = -1.0f;
   // per-call state
   Arena arena;
   char* pinned = nullptr;
@@ -854,16 +856,21 @@ struct FinalGroups {
   std::vector<G> groups;
 };
 
-void final_groups(int64_t nq, const int32_t* k, const std::vector<int64_t>& cap_of, FinalGroups& fg) {
+void final_groups(int64_t nq, const int32_t* k, const std::vector<int64_t>& cap_of, int64_t split_from,
+                  FinalGroups& fg) {
+  // batches smaller than split_from queries take one launch (for them the
+  // launches cost more than the forms save)
+  const bool split = nq >= split_from;
   const int forms[5] = {8, 16, 24, 32, 0};
   fg.order.resize((size_t)nq);
   fg.groups.clear();
   int64_t at = 0;
   for (int f : forms) {
+    if (!split && f != 0) continue;
     FinalGroups::G g;
     g.beg = at;
     for (int64_t i = 0; i < nq; ++i) {
-      if (bbc::final_topk_form(cap_of[(size_t)i]) != f) continue;
+      if (split && bbc::final_topk_form(cap_of[(size_t)i]) != f) continue;
       fg.order[(size_t)at++] = (int32_t)i;
       g.max_kc = std::max(g.max_kc, cap_of[(size_t)i]);
       g.max_cnt = std::max(g.max_cnt, std::min<int64_t>(k[i], cap_of[(size_t)i]));
@@ -1002,7 +1009,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   {
     std::vector<int64_t> cap_of((size_t)nq);
     for (int64_t i = 0; i < nq; ++i) cap_of[(size_t)i] = key_off[i + 1] - key_off[i];
-    final_groups(nq, k, cap_of, fg);
+    final_groups(nq, k, cap_of, ix->num_cu, fg);
   }
   Plan mp;
   const size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)),
@@ -1027,7 +1034,8 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   // each query's probe ranks fit its LDS tables), else the candidate sort does
   const bool presort = tile_keys && ix->walk_presort && max_np <= bbc::WALK_RANKS_LDS;
   size_t L_cpos = 0, L_wbins = 0, L_wst = 0, L_wround = 0;
-  const bool rounds = wide && ix->walk_alpha < 1.0f;  // the wide form's keys in two rounds
+  // the wide form's keys in two rounds
+  const bool rounds = wide && (ix->walk_alpha < 0.0f ? tile_keys : ix->walk_alpha < 1.0f);
   if (wide) {
     // C's list positions in place order: the grid keys' input (also the
     // second round's when the first round's keys come tile-major)
@@ -1168,7 +1176,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     wa.wstate = reinterpret_cast<uint32_t*>(A + L_wst);
     if (rounds) {
       wa.wround = reinterpret_cast<uint32_t*>(A + L_wround);
-      wa.round1_alpha = ix->walk_alpha;
+      wa.round1_alpha = ix->walk_alpha < 0.0f ? 0.8f : ix->walk_alpha;
     }
   }
   if (presort) {
@@ -1337,7 +1345,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   {
     std::vector<int64_t> cap_of((size_t)nq);
     for (int64_t i = 0; i < nq; ++i) cap_of[(size_t)i] = cand_off[i + 1] - cand_off[i];
-    final_groups(nq, k, cap_of, fg);
+    final_groups(nq, k, cap_of, ix->num_cu, fg);
   }
   Plan mp;
   size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),

@@ -54,6 +54,26 @@ def test_large_k_variants_match_oracle(bbc, cfg):
     g.free()
 
 
+def test_final_topk_groups_match_oracle(bbc):
+    """A batch above the size from which the final top-k runs one launch per
+    kernel form (256 queries, one per CU): per-query k spread so that the
+    queries' candidate sets select every form (8, 16, 24 and 32 items per
+    thread and the memory form); ids and distances equal the oracle's."""
+    nq = 300
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 100_000, 64, 16, 8, nq)
+    ks = np.array([500, 3000, 6000, 8000, 12000, 16000], np.int32)
+    k = ks[np.arange(nq) % len(ks)]
+    print(f"[case] final top-k groups nq={nq}", flush=True)
+    g = make_gpu_index(bbc, ix)
+    got = g.search(q, k, 48, ratio=2.5)
+    ref = oracle.search_pq(ix, q, k.astype(np.int64), np.full(nq, 48, np.int64), 2.5)
+    np.testing.assert_array_equal(got[3], ref["off"])
+    np.testing.assert_array_equal(got[0], ref["ids"])
+    np.testing.assert_array_equal(got[1], ref["dists"])
+    np.testing.assert_array_equal(got[2], ref["counts"])
+    g.free()
+
+
 def _rabitq_data(d, n, nq, nlist):
     w = synth.small_workload("ivfrabitq_1m_d960", n=n, nlist=nlist, nq=nq, d=d, seed_index=2)
     x, q = synth.base_vectors(w), synth.query_vectors(w)
