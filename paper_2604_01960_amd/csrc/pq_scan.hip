@@ -367,14 +367,20 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     // stay in vector registers (lane g), read back where they are needed
     bool valid[G];
     int64_t ooff[G];
-    uint32_t dmax[G], ebits[G];
+    uint32_t ebits[G];
+    // the largest kept key as a float: keys are sums of non-negative table
+    // entries, so comparing them with d_max as floats orders them as their
+    // images do (+inf: keep all; a negative d_max keeps none)
+    float dmaxf[G];
     const uint32_t cur_pp = f_pp;
     const int64_t cur_qq = f_qq, cur_tr = f_tr + f_ro;
 #pragma unroll
     for (int g = 0; g < G; ++g) {
       valid[g] = lane_value(f_pp, g) != NO_PAIR;
       ooff[g] = valid[g] ? lane_value(f_base, g) + lane_value(f_ro, g) : 0;
-      dmax[g] = MODE == 1 && valid[g] && lane_value(f_prune, g) ? lane_value(f_dmax, g) : 0xffffffffu;
+      const uint32_t db = lane_value(f_dmax, g);
+      dmaxf[g] = !(MODE == 1 && valid[g] && lane_value(f_prune, g)) ? __builtin_inff()
+                 : (db & 0x80000000u) ? __uint_as_float(db & 0x7fffffffu) : -1.0f;
       ebits[g] = EARLY && valid[g] ? lane_value(f_ebits, g) : 0u;
     }
     const int j = lane_value(f_j, 0);
@@ -690,7 +696,7 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
 #pragma unroll
         for (int o = 0; o < O; ++o)
 #pragma unroll
-          for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && key_bits(acc[o][g]) <= dmax[g];
+          for (int g = 0; g < G; ++g) keep[o * G + g] = valid[g] && active[o] && acc[o][g] <= dmaxf[g];
         comp.step(keep, slot, wcnt);
         bool ear[O * G];
 #pragma unroll
@@ -700,8 +706,9 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
           for (int g = 0; g < G; ++g) {
             ear[o * G + g] = EARLY && keep[o * G + g] && key_bits(acc[o][g]) < ebits[g];
             if (keep[o * G + g]) {
-              a.surv_key[ooff[g] + slot[o * G + g]] = acc[o][g];
-              a.surv_pos[ooff[g] + slot[o * G + g]] = (uint32_t)(lbeg + i) | (ear[o * G + g] ? EARLY_FLAG : 0u);
+              // uniform bases, 32-bit lane offsets
+              (a.surv_key + ooff[g])[slot[o * G + g]] = acc[o][g];
+              (a.surv_pos + ooff[g])[slot[o * G + g]] = (uint32_t)(lbeg + i) | (ear[o * G + g] ? EARLY_FLAG : 0u);
             }
           }
         }
