@@ -250,6 +250,8 @@ def main():
     ap.add_argument("--f4-queries", type=int, default=8,
                     help="RaBitQ: queries whose re-rank sizes are set against the minimal re-rank set")
     ap.add_argument("--no-compare", action="store_true", help="skip the heap / sort collector comparison")
+    ap.add_argument("--graph", action="store_true",
+                    help="batch workloads: also time the steps as captured plans (serial and concurrent)")
     ap.add_argument("--small-k", type=str, default="100,1000",
                     help="small k values (nprobe 64, r 2) at which the collectors are also compared")
     ap.add_argument("--sample-factor", type=int, default=0,
@@ -452,6 +454,48 @@ def main():
                              batch_ms_p99=round(float(np.percentile(arr, 99)), 3))
         log(f"k={k}: recall over {nq} queries {rec:.4f}, distance error {derr}")
 
+    # ---- the same steps replayed as captured plans (one per k, the operating
+    # point above): in turn on one stream, and the k batches on streams of
+    # their own at once (each plan has its own workspace); results equal the
+    # eager step's --------------------------------------------------------------
+    graph = None
+    if args.graph:
+        outs_g = {k: tuple(torch.empty_like(t) for t in outs[k]) for k in ks}
+        plans = {k: index.plan(qd, k, op[k]["nprobe"], outs_g[k], ratio=op[k]["ratio"], lut_u8=args.lut_u8,
+                               early_rerank=args.early_rerank, sample_factor=op[k]["sample_factor"]) for k in ks}
+        streams = {k: torch.cuda.Stream() for k in ks}
+
+        def gstep_serial():
+            for k in ks:
+                plans[k].execute()
+
+        def gstep_concurrent():
+            cur = torch.cuda.current_stream()
+            for k in ks:
+                streams[k].wait_stream(cur)
+                plans[k].execute(streams[k])
+            for k in ks:
+                cur.wait_stream(streams[k])
+
+        graph = {}
+        for name, fn in (("serial", gstep_serial), ("concurrent", gstep_concurrent)):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                fn()
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            same = all(bool(torch.equal(outs_g[k][0], outs[k][0])) and bool(torch.equal(outs_g[k][1], outs[k][1]))
+                       for k in ks)
+            graph[name] = dict(qps=round(total_q / el, 1), ms_per_step=round(el / args.steps * 1e3, 3),
+                               identical_to_eager=same)
+            log(f"graph {name}: {graph[name]}")
+        for pl in plans.values():
+            pl.free()
+        del plans
+
     # ---- collector comparison: same batch, same operating point ---------------
     collectors = {}
     if not args.no_compare:
@@ -648,6 +692,7 @@ def main():
                        "p99": round(float(np.percentile(sum(lat.values(), []), 99)), 3),
                        "what": "device time of one 10,000-query batch"},
         "stage_ms_per_step": stage_ms,
+        "graph": graph,
         "collectors": collectors,
         "collectors_small_k": small_k,
         "sizes": sizes,
