@@ -169,6 +169,14 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   if (a.t_nsample_keys && threadIdx.x == 0) a.t_nsample_keys[qi] = Ts;
   const int64_t T = kc < Ts ? kc : Ts;
   uint32_t dmax_b = 0;
+  // the sample's keys through the relaxed-threshold filter go to rank 0's
+  // survivor run; with the sample read from memory this happens in the pass
+  // of the cell histogram (one pass less over the sample)
+  float* skey = a.surv_key + a.surv_off[qi];
+  uint32_t* spos = a.surv_pos + a.surv_off[qi];
+  int rk = 0;
+  bool filtered = false;
+  if (threadIdx.x == 0) { bc[6] = 0; bc[7] = 0; }
   if (T > 0) {
     // smallest and largest image of the sample
     uint32_t mn = 0xffffffffu, mx = 0u;
@@ -259,9 +267,29 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     float delta = (dmax - dmin) / 256.0f;
     if (!(delta > 0.0f)) delta = 1.0f;
     const float rdelta = __builtin_amdgcn_rcpf(delta);
-    each([&](int64_t, bool valid, uint32_t v) {
-      wave_hist_add(hist, (uint32_t)cell_fast(bits_key(v), dmin, delta, rdelta), valid && v < dmax_b);
-    });
+    if (in_regs) {
+      each([&](int64_t, bool valid, uint32_t v) {
+        wave_hist_add(hist, (uint32_t)cell_fast(bits_key(v), dmin, delta, rdelta), valid && v < dmax_b);
+      });
+    } else {
+      // (the same rule as the prune flag set below)
+      const bool prune_f = Ts >= kc && dmax > dmin && !a.keep_all;
+      uint32_t n_rej = 0;
+      each([&](int64_t i, bool valid, uint32_t v) {
+        wave_hist_add(hist, (uint32_t)cell_fast(bits_key(v), dmin, delta, rdelta), valid && v < dmax_b);
+        const bool keep = valid && (!prune_f || v <= dmax_b);
+        const uint32_t slot = wave_slot(keep, &bc[6]);
+        if (keep) {
+          skey[slot] = bits_key(v);
+          spos[slot] = (uint32_t)pos_at(i, rk);
+        } else if (valid) {
+          ++n_rej;
+        }
+      });
+      for (int off = 32; off >= 1; off >>= 1) n_rej += __shfl_xor(n_rej, off);
+      if (lane == 0 && n_rej) atomicAdd(&bc[7], n_rej);
+      filtered = true;
+    }
     __syncthreads();
     if (threadIdx.x < 64) {
       // cell counts of the sample's T smallest keys: the keys below d_max as
@@ -308,7 +336,6 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     bc[5] = 0u;
     s_cpred = -1;
   }
-  if (threadIdx.x == 0) { bc[6] = 0; bc[7] = 0; }
   __syncthreads();
   const uint32_t prune = bc[5];
   for (int e = threadIdx.x; e < 256; e += NT) book->map[e] = cmap[e];
@@ -341,12 +368,10 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     book->early_bits = ebits;
     if (a.t_tau_pred) a.t_tau_pred[qi] = tp;
   }
-  // the sample's keys through the relaxed-threshold filter
-  float* skey = a.surv_key + a.surv_off[qi];
-  uint32_t* spos = a.surv_pos + a.surv_off[qi];
+  // the sample's keys through the relaxed-threshold filter (unless done)
   const uint64_t lt = (1ull << lane) - 1ull;
-  int rk = 0;
-  if (in_regs) {
+  if (filtered) {
+  } else if (in_regs) {
     // slots from a count of each wave's kept keys (registers are read twice)
     uint32_t nkeep = 0, nrej = 0;
     each([&](int64_t, bool valid, uint32_t v) {
