@@ -70,6 +70,10 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   constexpr int NT = 1024, NW = NT / 64;
   constexpr int SEL_BITS = 12;  // bits of the key image resolved per select pass
   __shared__ uint32_t hist[1 << SEL_BITS];
+  // memory form: the keys of the bin the first select pass picks, when they
+  // fit, for the remaining passes
+  constexpr int GCAP = R == 0 ? 4096 : 1;
+  __shared__ uint32_t gkeys[GCAP];
   __shared__ uint8_t cmap[256];
   __shared__ __align__(8) uint32_t bc[8];
   __shared__ uint32_t s_wred[2][NW];
@@ -209,6 +213,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     int sh = span ? 32 - __clz(span) : 0;  // bits of v - mn still to resolve
     uint32_t pref = 0;                     // the resolved high bits of v - mn
     int64_t rr = T - 1;
+    int ng = -1;                           // keys gathered into gkeys (-1: none)
     for (bool first = true; sh > 0; first = false) {
       const int w = sh < SEL_BITS ? sh : SEL_BITS;
       const int nsh = sh - w;
@@ -218,10 +223,17 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
       // mn read again after the barrier: v - mn is then formed in the pass
       // rather than kept for every register slot across the passes
       const uint32_t mnp = bc[4];
-      each([&](int64_t, bool valid, uint32_t v) {
-        const uint32_t d = v - mnp;
-        if (valid && (first || (d >> sh) == pref)) atomicAdd(&hist[(d >> nsh) & dmask], 1u);
-      });
+      if (ng >= 0) {
+        for (int i = threadIdx.x; i < ng; i += NT) {
+          const uint32_t d = gkeys[i] - mnp;
+          if ((d >> sh) == pref) atomicAdd(&hist[(d >> nsh) & dmask], 1u);
+        }
+      } else {
+        each([&](int64_t, bool valid, uint32_t v) {
+          const uint32_t d = v - mnp;
+          if (valid && (first || (d >> sh) == pref)) atomicAdd(&hist[(d >> nsh) & dmask], 1u);
+        });
+      }
       __syncthreads();
       {
         // the bin holding rank rr: 4 bins per thread, a block-wide scan
@@ -250,6 +262,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
             rem -= h[j];
           }
           bc[0] = 4 * threadIdx.x + j;
+          bc[1] = h[j];
           *reinterpret_cast<int64_t*>(bc + 2) = rem;
         }
       }
@@ -257,7 +270,20 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
       pref = (pref << w) | bc[0];
       rr = *reinterpret_cast<const int64_t*>(bc + 2);
       sh = nsh;
+      const uint32_t nbin = bc[1];
       __syncthreads();
+      if (R == 0 && ng < 0 && sh > 0 && nbin <= (uint32_t)GCAP) {
+        // gather the picked bin's keys (its prefix pref) for the next passes
+        if (threadIdx.x == 0) bc[1] = 0;
+        __syncthreads();
+        each([&](int64_t, bool valid, uint32_t v) {
+          const bool in_bin = valid && ((v - mnp) >> sh) == pref;
+          const uint32_t slot = wave_slot(in_bin, &bc[1]);
+          if (in_bin) gkeys[slot] = v;
+        });
+        __syncthreads();
+        ng = (int)nbin;
+      }
     }
     dmax_b = mn + pref;
     for (int i = threadIdx.x; i < 256; i += NT) hist[i] = 0;
