@@ -884,6 +884,8 @@ void final_groups(int64_t nq, const int32_t* k, const std::vector<int64_t>& cap_
 // largest min(k, K_c)).
 int32_t launch_final_groups(bbc_index* ix, const FinalGroups& fg, const int32_t* d_order, bbc::FinalArgs fa,
                             hipStream_t s) {
+  // the LDS buffer: the group's largest result set when it fits (larger ones
+  // group their winners in the scratch buffer and sort in memory)
   const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
   for (const auto& g : fg.groups) {
     const int cap = (int)std::min(g.max_cnt, cap_max);
@@ -1053,6 +1055,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   }
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
+  const size_t L_fs = pl.add(8 * nout);  // final top-k: winners grouped by bin
   if (ctx && ctx->size_only) {
     ctx->ws_bytes = pl.total;
     return BBC_OK;
@@ -1221,6 +1224,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
   bbc::FinalArgs fa{};
   fa.k = d_k; fa.n_cand = wa.n_cand; fa.cand_off = d_ko; fa.cand_packed = wa.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
+  fa.scratch = reinterpret_cast<uint64_t*>(A + L_fs);
   {
     StageScope st(s, 5);
     if ((rc = launch_final_groups(ix, fg, reinterpret_cast<const int32_t*>(M + m_fq), fa, s))) return rc;
@@ -1403,6 +1407,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     L.out_dists = pl.add(4 * nout);
     L.out_counts = pl.add(4 * nq);
   }
+  const size_t L_fs = pl.add(8 * nout);  // final top-k: winners grouped by bin
   if (tracing) {
     L.t_dmin = pl.add(4 * nq); L.t_delta = pl.add(4 * nq); L.t_map = pl.add(256 * nq);
     L.t_tau = pl.add(4 * nq); L.t_s = pl.add(8 * nq); L.t_counts = pl.add(4 * nq * m); L.t_nb = pl.add(8 * nq); L.t_nsk = pl.add(8 * nq);
@@ -1629,6 +1634,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   bbc::FinalArgs fa{};
   fa.k = d_k; fa.n_cand = ca.n_cand; fa.cand_off = d_co; fa.cand_packed = ra.cand_packed;
   fa.out_off = d_oo; fa.out_ids = d_oid; fa.out_dists = d_odist; fa.out_counts = d_ocnt; fa.metric = ix->metric;
+  fa.scratch = reinterpret_cast<uint64_t*>(A + L_fs);
   {
     StageScope st(s, 5);
     if ((rc = launch_final_groups(ix, fg, reinterpret_cast<const int32_t*>(M + m_fq), fa, s))) return rc;

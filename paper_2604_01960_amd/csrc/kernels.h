@@ -218,6 +218,7 @@ struct FinalArgs {
   int run;                  // largest power of two <= cap: LDS sort run of the global sort
   int64_t max_kc;           // largest K_c of the launch's queries (selects the register-resident variant)
   const int32_t* qmap;      // the launch's queries: block b takes query qmap[b] (nullptr: query b)
+  uint64_t* scratch;        // k slots per query at out_off: the winners grouped by bin
 };
 // ---- comparator collectors (heap, sort) over every scanned key ----------------
 struct CompareArgs {

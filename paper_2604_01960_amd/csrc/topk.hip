@@ -121,11 +121,15 @@ __device__ void ft_prefix(uint32_t* hist, int lg, int64_t cnt, uint32_t* red) {
 // block-uniform number of calls (fn may use wave-wide collectives); the
 // candidates stay readable at in[0, kc) for the rare exact-select path.
 // LDS: hist[FT_NB2], bbuf[FT_BCAP], red[12] and obuf (cap items) from the kernel.
-template <class Items>
+// IN_LDS: the winners grouped by bin go to the LDS buffer (cnt <= cap), else
+// to the query's slots of the scratch buffer (a compile-time choice, so that
+// each form addresses one memory).
+template <bool IN_LDS, class Items>
 __device__ bool final_topk_binned(const int metric, const int cap, const uint64_t* in, int64_t kc, int64_t cnt, int64_t* oid,
-                                  float* odist, uint64_t* obuf, uint32_t* hist, uint64_t* bbuf, uint32_t* red,
-                                  Items items) {
+                                  float* odist, uint64_t* gbuf_mem, uint64_t* obuf, uint32_t* hist, uint64_t* bbuf,
+                                  uint32_t* red, Items items) {
   constexpr int NT = 1024;
+  uint64_t* gbuf = IN_LDS ? obuf : gbuf_mem;
   static_assert(FT_NB == 64 * 32 && FT_NB2 == 64 * 64, "one wave forms the prefix");
   if (threadIdx.x == 0) { red[0] = 0xffffffffu; red[1] = 0u; red[2] = 0u; }
   for (int i = threadIdx.x; i < FT_NB; i += NT) hist[i] = 0;
@@ -186,7 +190,7 @@ __device__ bool final_topk_binned(const int metric, const int cap, const uint64_
   items([&](uint64_t v, bool ok) {
     const int b = bins((uint32_t)(v >> 32));
     if (ok && b < bstar) {
-      obuf[atomicAdd(&hist[ft_slot(b, lg)], 1u)] = v;
+      gbuf[atomicAdd(&hist[ft_slot(b, lg)], 1u)] = v;
     } else if (ok && b == bstar) {
       uint32_t bs = atomicAdd(&red[2], 1u);
       if (bs < (uint32_t)FT_BCAP) bbuf[bs] = v;
@@ -219,11 +223,11 @@ __device__ bool final_topk_binned(const int metric, const int cap, const uint64_
       }
     }
     for (int64_t p = threadIdx.x; p < nbelow; p += NT) {
-      const uint64_t v = obuf[p];
+      const uint64_t v = gbuf[p];
       const int b = bins((uint32_t)(v >> 32));
       const int beg = b ? (int)hist[ft_slot(b - 1, lg)] : 0, end = (int)hist[ft_slot(b, lg)];
       int rank = 0;
-      for (int j = beg; j < end; ++j) rank += obuf[j] < v;
+      for (int j = beg; j < end; ++j) rank += gbuf[j] < v;
       oid[beg + rank] = (int64_t)packed_id(v);
       odist[beg + rank] = sgn * packed_key(v);
     }
@@ -233,7 +237,7 @@ __device__ bool final_topk_binned(const int metric, const int cap, const uint64_
     const int P = next_pow2((int)nb);
     for (int i = (int)nb + threadIdx.x; i < P; i += NT) bbuf[i] = ~0ull;
     lds_bitonic_sort<NT>(bbuf, P);
-    for (int64_t r = threadIdx.x; r < s; r += NT) obuf[nbelow + r] = bbuf[r];
+    for (int64_t r = threadIdx.x; r < s; r += NT) gbuf[nbelow + r] = bbuf[r];
   } else {
     auto get = [&](int64_t i, uint64_t& v) -> bool {
       v = in[i];
@@ -244,7 +248,7 @@ __device__ bool final_topk_binned(const int metric, const int cap, const uint64_
     __syncthreads();
     for (int64_t i = threadIdx.x; i < kc; i += NT) {
       uint64_t v;
-      if (get(i, v) && v <= thr) obuf[nbelow + atomicAdd(&red[2], 1u)] = v;
+      if (get(i, v) && v <= thr) gbuf[nbelow + atomicAdd(&red[2], 1u)] = v;
     }
   }
   __syncthreads();
@@ -252,11 +256,15 @@ __device__ bool final_topk_binned(const int metric, const int cap, const uint64_
   if (P > cap) {
     // the winners do not fit a power-of-two LDS sort: hand them over unsorted
     uint64_t* outp = reinterpret_cast<uint64_t*>(oid);
-    for (int64_t i = threadIdx.x; i < cnt; i += NT) outp[i] = obuf[i];
+    for (int64_t i = threadIdx.x; i < cnt; i += NT) outp[i] = gbuf[i];
     __syncthreads();
     return false;
   }
-  for (int i = (int)cnt + threadIdx.x; i < P; i += NT) obuf[i] = ~0ull;
+  if constexpr (!IN_LDS) {
+    for (int i = threadIdx.x; i < P; i += NT) obuf[i] = i < cnt ? gbuf[i] : ~0ull;
+  } else {
+    for (int i = (int)cnt + threadIdx.x; i < P; i += NT) obuf[i] = ~0ull;
+  }
   lds_bitonic_sort<NT>(obuf, P);
   for (int64_t i = threadIdx.x; i < cnt; i += NT) {
     const uint64_t v = obuf[i];
@@ -304,6 +312,39 @@ __device__ void sort_global_unpack(const int metric, const int run, uint64_t* ou
   }
 }
 
+// The candidates read from memory: the memory form, or a register form's
+// query whose result set does not fit the LDS buffer (SCRATCH_ONLY: then the
+// winners always go to the scratch buffer, and only that form is compiled
+// into the register kernels).
+template <bool SCRATCH_ONLY>
+__device__ __forceinline__ void final_topk_mem(const FinalArgs& a, uint64_t* in, int64_t kc, int64_t cnt,
+                                               int64_t* oid, float* odist, uint64_t* outp, uint64_t* gbuf,
+                                               uint64_t* run_buf, uint32_t* hist, uint64_t* bbuf, uint32_t* red) {
+  constexpr int NT = 1024;
+  auto items = [&](auto fn) {
+    constexpr int B = SCRATCH_ONLY ? 1 : 8;  // loads in flight per thread (registers kept for the others)
+    for (int64_t base = 0; base < kc; base += (int64_t)NT * B) {
+      uint64_t v[B];
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+        v[u] = in[i < kc ? i : kc - 1];
+      }
+#pragma unroll
+      for (int u = 0; u < B; ++u) {
+        const int64_t i = base + (int64_t)u * NT + threadIdx.x;
+        if (base + (int64_t)u * NT < kc) fn(i < kc ? v[u] : ~0ull, i < kc);
+      }
+    }
+  };
+  bool done;
+  if (SCRATCH_ONLY || cnt > a.cap)
+    done = final_topk_binned<false>(a.metric, a.cap, in, kc, cnt, oid, odist, gbuf, run_buf, hist, bbuf, red, items);
+  else
+    done = final_topk_binned<true>(a.metric, a.cap, in, kc, cnt, oid, odist, gbuf, run_buf, hist, bbuf, red, items);
+  if (!done) sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
+}
+
 // IPT > 0: the candidates are loaded once into registers (IPT per thread,
 // K_c <= IPT * 1024) and every pass of the binned path runs from there.
 template <int IPT>
@@ -324,6 +365,7 @@ __global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_to
   int64_t* oid = a.out_ids + a.out_off[qi];
   float* odist = a.out_dists + a.out_off[qi];
   uint64_t* outp = reinterpret_cast<uint64_t*>(oid);
+  uint64_t* gbuf = a.scratch + a.out_off[qi];  // k slots: the winners grouped by bin
 
   if (IPT > 0 && cnt > 0 && cnt <= a.cap && kc <= (int64_t)IPT * NT) {
     uint64_t v[IPT > 0 ? IPT : 1];
@@ -332,47 +374,16 @@ __global__ __launch_bounds__(1024, (IPT > 0 && IPT <= 16) ? 8 : 1) void final_to
       const int64_t i = (int64_t)u * NT + threadIdx.x;
       v[u] = i < kc ? in[i] : ~0ull;
     }
-    const bool done = final_topk_binned(a.metric, a.cap, in, kc, cnt, oid, odist, run_buf, hist, bbuf, red, [&](auto fn) {
+    auto items = [&](auto fn) {
 #pragma unroll
       for (int u = 0; u < IPT; ++u)
         if ((int64_t)u * NT < kc) fn(v[u], (int64_t)u * NT + threadIdx.x < kc);
-    });
-    if (!done) sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
-  } else if (cnt > 0 && cnt <= a.cap) {
-    const bool done = final_topk_binned(a.metric, a.cap, in, kc, cnt, oid, odist, run_buf, hist, bbuf, red, [&](auto fn) {
-      constexpr int B = IPT == 0 ? 8 : 1;  // loads in flight per thread (registers kept for the others)
-      for (int64_t base = 0; base < kc; base += (int64_t)NT * B) {
-        uint64_t v[B];
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          const int64_t i = base + (int64_t)u * NT + threadIdx.x;
-          v[u] = in[i < kc ? i : kc - 1];
-        }
-#pragma unroll
-        for (int u = 0; u < B; ++u) {
-          const int64_t i = base + (int64_t)u * NT + threadIdx.x;
-          if (base + (int64_t)u * NT < kc) fn(i < kc ? v[u] : ~0ull, i < kc);
-        }
-      }
-    });
+    };
+    const bool done =
+        final_topk_binned<true>(a.metric, a.cap, in, kc, cnt, oid, odist, gbuf, run_buf, hist, bbuf, red, items);
     if (!done) sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
   } else if (cnt > 0) {
-    uint64_t thr = ~0ull;
-    if (cnt < kc) {
-      thr = block_radix_select64<NT>([&](int64_t i, uint64_t& v) { v = in[i]; return true; }, kc, cnt - 1,
-                                     hist, bc);
-    }
-    if (threadIdx.x == 0) bc[2] = 0;
-    __syncthreads();
-    for (int64_t i = threadIdx.x; i < kc; i += NT) {
-      uint64_t v = in[i];
-      if (v <= thr) {
-        uint32_t slot = atomicAdd(&bc[2], 1u);
-        outp[slot] = v;
-      }
-    }
-    __syncthreads();
-    sort_global_unpack(a.metric, a.run, outp, in, cnt, run_buf, oid, odist);
+    final_topk_mem<(IPT > 0)>(a, in, kc, cnt, oid, odist, outp, gbuf, run_buf, hist, bbuf, red);
   }
   const float pad = a.metric == 0 ? __builtin_inff() : -__builtin_inff();
   for (int64_t i = cnt + threadIdx.x; i < k; i += NT) {
