@@ -191,6 +191,9 @@ struct bbc_index {
   // RaBitQ scan order with tile-major keys: pairs by list, a run of lists per
   // XCD (1), or by query (0) (BBC_SCAN_BY_LIST)
   int scan_by_list = 1;
+  // pair sorts by list: per-block LDS histograms (1) or device-wide atomics
+  // (0) (BBC_PAIR_SORT)
+  int pair_sort_lds = 1;
   // RaBitQ wide form: the first round's keys reach this fraction of the way
   // from the k-th smallest lb's bin to U's bin (BBC_WALK_ALPHA; >= 1: one
   // round over all of C).  Unset (< 0): 0.8 with tile-major keys (large
@@ -301,6 +304,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_SCAN_BY_LIST")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 1) ix->scan_by_list = x;
+  }
+  if (const char* sv = std::getenv("BBC_PAIR_SORT")) {
+    const int x = std::atoi(sv);
+    if (x >= 0 && x <= 1) ix->pair_sort_lds = x;
   }
   if (const char* sv = std::getenv("BBC_WALK_PRESORT")) {
     const int x = std::atoi(sv);
@@ -779,7 +786,7 @@ namespace {
 
 struct Layout {
   // offsets into the arena
-  size_t nsample_q, pair_cnt, pair_split, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
+  size_t nsample_q, pair_cnt, pair_split, bs_table, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb, qorder, rt_sorted, rt_bins, rt_ptb, rt_lcnt, rt_lpairs;
@@ -1053,6 +1060,8 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     L_rts = pl.add(4 * nkeys); L_rti = pl.add(4 * nkeys); L_rtb = pl.add(4 * bin_off[nq]);
     L_rtp = pl.add(4 * npairs); L_rtc = pl.add(4 * ((int64_t)ix->nlist + 1)); L_rtl = pl.add(8 * rt_lpairs_cap);
   }
+  const int64_t bs_words = ix->pair_sort_lds && tile_keys ? bbc::pair_sort_table_words(nq, ix->nlist) : 0;
+  const size_t L_bst = bs_words ? pl.add(4 * bs_words) : 0;
   size_t L_oid = 0, L_od = 0, L_oc = 0;
   if (host_io) { L_oid = pl.add(8 * nout); L_od = pl.add(4 * nout); L_oc = pl.add(4 * nq); }
   const size_t L_fs = pl.add(8 * nout);  // final top-k: winners grouped by bin
@@ -1133,6 +1142,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
     ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
     ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
+    ta.bs_table = bs_words ? reinterpret_cast<uint32_t*>(A + L_bst) : nullptr;
     ta.lpairs_cap = rt_lpairs_cap;
     ta.group = rt_group;
   }
@@ -1380,6 +1390,10 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   L.sorted_pairs = pl.add(4 * bbc::pair_slots(npairs, ix->nlist));
   L.sorted_q = pl.add(4 * bbc::pair_slots(npairs, ix->nlist));
   L.pair_split = pl.add(8);
+  // pair sorts' per-block counts: the scan's (2 * nlist bins) then the
+  // re-rank's (nlist) reuse it
+  const int64_t bs_words = ix->pair_sort_lds ? bbc::pair_sort_table_words(nq, 2 * ix->nlist) : 0;
+  L.bs_table = bs_words ? pl.add(4 * bs_words) : 0;
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
@@ -1506,6 +1520,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   sa.sorted_pairs = reinterpret_cast<uint32_t*>(A + L.sorted_pairs);
   sa.sorted_q = reinterpret_cast<uint32_t*>(A + L.sorted_q);
   sa.pair_split = reinterpret_cast<uint32_t*>(A + L.pair_split);
+  sa.bs_table = bs_words ? reinterpret_cast<uint32_t*>(A + L.bs_table) : nullptr;
   sa.nsample_q = pa.nsample_q; sa.sample_keys = sample_keys; sa.sample_off = d_so; sa.books = books;
   sa.surv_key = surv_key; sa.surv_pos = surv_pos; sa.surv_off = d_vo; sa.pair_nsurv = pair_nsurv;
   sa.n_rejected = n_rejected;
@@ -1606,6 +1621,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.lcnt = reinterpret_cast<uint32_t*>(A + L.rt_lcnt);
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);
       ta.lpairs_cap = rt_lpairs_cap;
+      ta.bs_table = bs_words ? reinterpret_cast<uint32_t*>(A + L.bs_table) : nullptr;
       ta.group = rt_group;
       if (early) ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L.rt_sidx);
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));

@@ -92,6 +92,7 @@ struct PqScanArgs {
   // [split, total) for mode 1, with pair_split = {split, total} (bins padded
   // to SCAN_GROUP entries with NO_PAIR)
   uint32_t* pair_split;
+  uint32_t* bs_table;       // pair sort's per-block counts (bs_table_words(nq, 2 * nlist)); NULL: global atomics
   int mode;                 // 0: sample lists -> sample_keys by slot; 1: the rest -> filter + survivors
   const int32_t* nsample_q; // per-query sample size (probe ranks below it are the sample)
   float* sample_keys; const int64_t* sample_off;
@@ -120,6 +121,9 @@ int64_t pair_slots(int64_t npairs, int nlist);  // sorted_pairs capacity
 // Counting sort of the (query, rank) pairs by (rank >= nsample, list).
 hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s);
 hipError_t launch_pq_scan(const PqScanArgs& a, hipStream_t s);
+// words of the pair sorts' per-block count table for nq queries over nbins
+// bins (0: too many bins for it, the sorts then use global atomics)
+int64_t pair_sort_table_words(int64_t nq, int nbins);
 
 struct CollectArgs {
   int64_t nq; const float* keys; const int64_t* key_off; const int64_t* n_scanned;
@@ -198,6 +202,7 @@ struct TileRerankArgs {
   // placed below wround[4q + 1] (sorted_idx = their places); 0: every one
   int round; const uint32_t* wround;
   int pairs_ready;          // lcnt and lpairs already filled (launch_tile_pairs)
+  uint32_t* bs_table;       // pair sort's per-block counts (bs_table_words(nq, nlist)); NULL: global atomics
 };
 // the (query, rank) pairs grouped by list into whole groups: lcnt, lpairs
 hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s);

@@ -21,6 +21,7 @@
 #include <algorithm>
 
 #include "common.h"
+#include "bin_sort.h"
 #include "kernels.h"
 
 namespace bbc {
@@ -94,6 +95,20 @@ __global__ void pair_scatter_kernel(PqScanArgs a) {
     a.sorted_q[slot] = (uint32_t)qi;
   }
 }
+
+// the pair sort's binner: bin (rank >= nsample, list); slot -> (pair, query)
+struct ScanPairBins {
+  const int64_t* probe_off; const int32_t* probe_lists; const int32_t* nsample_q; int nlist;
+  uint32_t* sorted_pairs; uint32_t* sorted_q;
+  __device__ int64_t count(int64_t q) const { return probe_off[q + 1] - probe_off[q]; }
+  __device__ int bin(int64_t q, int r, int64_t p) const {
+    return (r >= nsample_q[q] ? nlist : 0) + probe_lists[p];
+  }
+  __device__ void put(uint32_t slot, int64_t q, int, int64_t p) const {
+    sorted_pairs[slot] = (uint32_t)p;
+    sorted_q[slot] = (uint32_t)q;
+  }
+};
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) p[i] = v;
@@ -939,15 +954,25 @@ hipError_t launch_zero_u32(uint32_t* p, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+int64_t pair_sort_table_words(int64_t nq, int nbins) { return bs_table_words(nq, nbins); }
+
 int64_t pair_slots(int64_t npairs, int nlist) { return npairs + 2 * (int64_t)nlist * (SCAN_GROUP_MAX - 1); }
 
 hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s) {
   if (a.npairs <= 0) return hipSuccess;
   const int nb = 2 * a.nlist;
   const int64_t slots = pair_slots(a.npairs, a.nlist);
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.pair_cnt, (int64_t)nb);
   hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)std::min<int64_t>((slots + 255) / 256, 4096)), dim3(256), 0, s,
                      a.sorted_pairs, slots, NO_PAIR);
+  if (a.bs_table && nb <= BS_MAX_BINS) {
+    const ScanPairBins f{a.probe_off, a.probe_lists, a.nsample_q, a.nlist, a.sorted_pairs, a.sorted_q};
+    bs_sort(f, nb, a.nq, a.probe_off, a.bs_table, a.pair_cnt, [&] {
+      hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, pair_group(a),
+                         a.pair_split);
+    }, s);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((nb + 255) / 256), dim3(256), 0, s, a.pair_cnt, (int64_t)nb);
   const unsigned g = (unsigned)std::min<int64_t>((a.npairs + 255) / 256, 4096);
   hipLaunchKernelGGL(pair_count_kernel, dim3(g), dim3(256), 0, s, a);
   hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, pair_group(a),

@@ -74,6 +74,45 @@ def test_final_topk_groups_match_oracle(bbc):
     g.free()
 
 
+@pytest.mark.parametrize("sort", ["1", "0"])
+def test_pair_sort_forms_match_oracle(bbc, sort):
+    """The (query, rank) pairs sorted by list with per-block LDS histograms
+    (1, the default) or device-wide atomics (0): a ragged batch of 70
+    queries (blocks of 32 queries, the last one partial) with per-query k
+    and nprobe, PQ (the scan's sort by (phase, list) and the re-rank's by
+    list) and RaBitQ with tile-major keys (the scan's and re-rank's sort by
+    list); ids and distances equal the oracle's."""
+    nq = 70
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 20_000, 64, 16, 8, nq)
+    rng = np.random.default_rng(17)
+    k = rng.integers(1, 1500, nq).astype(np.int32)
+    npb = rng.integers(1, 33, nq).astype(np.int32)
+    print(f"[case] pair sort form {sort}: pq nq={nq}", flush=True)
+    old = os.environ.get("BBC_PAIR_SORT")
+    os.environ["BBC_PAIR_SORT"] = sort
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        if old is None:
+            os.environ.pop("BBC_PAIR_SORT")
+        else:
+            os.environ["BBC_PAIR_SORT"] = old
+    got = g.search(q, k, npb, ratio=2.0)
+    ref = oracle.search_pq(ix, q, k.astype(np.int64), npb.astype(np.int64), 2.0)
+    np.testing.assert_array_equal(got[3], ref["off"])
+    np.testing.assert_array_equal(got[0], ref["ids"])
+    np.testing.assert_array_equal(got[1], ref["dists"])
+    g.free()
+    x, q, ix = _rabitq_data(128, 12000, nq, 24)
+    print(f"[case] pair sort form {sort}: rabitq tile keys nq={nq}", flush=True)
+    g = _rabitq_index(bbc, x, ix, {"BBC_PAIR_SORT": sort, "BBC_WALK_FORM": "3"})
+    k = rng.integers(1, 800, nq).astype(np.int32)
+    npb = rng.integers(1, 25, nq).astype(np.int32)
+    tr = g.search_traced(q, k, npb)
+    _check_rabitq(tr, ix, q, k, npb)
+    g.free()
+
+
 def _rabitq_data(d, n, nq, nlist):
     w = synth.small_workload("ivfrabitq_1m_d960", n=n, nlist=nlist, nq=nq, d=d, seed_index=2)
     x, q = synth.base_vectors(w), synth.query_vectors(w)
