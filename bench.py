@@ -30,9 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak for plain (non-FMA, non-packed) adds and multiplies: 256
-# CUs x 4 SIMDs x 16 lanes x 2.4 GHz, one operation per lane per clock
-VALU_PEAK_TFLOPS = 39.3
+# FP32 vector issue peak (non-packed): 256 CUs x 4 SIMDs x 16 lanes x
+# 2.4 GHz, one operation (an add, a multiply or a fused multiply-add) per
+# lane per clock
+VALU_PEAK_TOPS = 39.3
 
 
 # LDS read peak: 256 CUs x 128 bytes per clock (32 banks of 4 bytes) x 2.4 GHz
@@ -77,13 +78,14 @@ def rerank_tile_form(d: int) -> bool:
 
 def rerank_entry(ms_per_launch: float, kc_per_launch: float, d: int) -> dict:
     """Roofline entry of the tile-major PQ re-rank stage: each candidate row is
-    staged once per group of queries, so the stage is bound by the 3 d
-    arithmetic operations (subtract, multiply, add) of each candidate."""
-    tf = kc_per_launch * 3 * d / (ms_per_launch * 1e-3) / 1e12
+    staged once per group of queries, so the stage is bound by the 2 d vector
+    operations (a subtract and a fused multiply-add per element) of each
+    candidate."""
+    tops = kc_per_launch * 2 * d / (ms_per_launch * 1e-3) / 1e12
     return {"kernel": "rt_rerank_tile (tile-major re-rank stage, with its pair and candidate sorts)",
-            "bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": None, "avg_launch_ms": round(ms_per_launch, 4),
-            "algorithmic_flops_per_launch": int(kc_per_launch * 3 * d)}
+            "bound": "alu", "achieved": round(tops, 2), "peak": VALU_PEAK_TOPS, "unit": "TOP/s",
+            "frac": round(tops / VALU_PEAK_TOPS, 4), "traffic": None, "avg_launch_ms": round(ms_per_launch, 4),
+            "algorithmic_ops_per_launch": int(kc_per_launch * 2 * d)}
 CSRC = os.path.join(ROOT, "paper_2604_01960_amd", "csrc")
 PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SCAN = "pq_scan_grouped<1, ...> (scan through the relaxed threshold)"

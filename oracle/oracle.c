@@ -9,19 +9,21 @@
  * independent queries (or independent rows of the index build) in parallel;
  * inside one query everything is sequential.
  *
- * Arithmetic is IEEE binary32 with round-to-nearest-even, no contraction
- * (built with -ffp-contract=off, no fast-math), in the fixed operation order
- * below.  The GPU path implements the same order independently; that is what
- * makes bit-exact ids possible when thousands of neighbours sit within a
- * relative distance band of 1e-6 of each other.
+ * Arithmetic is IEEE binary32 with round-to-nearest-even, in the fixed
+ * operation order below; the compiler contracts nothing (built with
+ * -ffp-contract=off, no fast-math), and a fused multiply-add appears only
+ * where written as fmaf (one rounding of a*b + c).  The GPU path implements
+ * the same order independently; that is what makes bit-exact ids possible
+ * when thousands of neighbours sit within a relative distance band of 1e-6
+ * of each other.
  *
  *   canon_l2(a,b): vectors padded with zeros to a multiple of 256; 4-element
  *     chunk c goes to virtual lane c%64 at step c/64; each lane starts at +0
- *     and for each step and element e=0..3 does  t=(a-b); t=t*t; acc=acc+t;
+ *     and for each step and element e=0..3 does  t=(a-b); acc=fmaf(t,t,acc);
  *     lanes are combined by acc[l] = acc[l] + acc[l+off] for off=32,16,..,1.
- *   canon_ip: same with t = a*b.
+ *   canon_ip: same with acc = fmaf(a,b,acc).
  *   PQ table entry: r = q - c (once per element), then sequentially over the
- *     sub-vector elements  t = r - C; t = t*t; acc = acc + t.
+ *     sub-vector elements  t = r - C; acc = fmaf(t,t,acc), from acc = +0.
  *   PQ key: acc = +0; acc = acc + LUT[m][code_m] for m = 0..M-1.
  *   Total order: (key, id) with numeric key comparison, ties by smaller id.
  */
@@ -58,8 +60,7 @@ float orc_canon_l2(const float* a, const float* b, int32_t d) {
       float av = i < d ? a[i] : 0.0f;
       float bv = i < d ? b[i] : 0.0f;
       float t = av - bv;
-      t = t * t;
-      acc[lane] = acc[lane] + t;
+      acc[lane] = fmaf(t, t, acc[lane]);
     }
   }
   for (int off = NLANES / 2; off >= 1; off /= 2)
@@ -77,8 +78,7 @@ float orc_canon_ip(const float* a, const float* b, int32_t d) {
       int i = 4 * c + e;
       float av = i < d ? a[i] : 0.0f;
       float bv = i < d ? b[i] : 0.0f;
-      float t = av * bv;
-      acc[lane] = acc[lane] + t;
+      acc[lane] = fmaf(av, bv, acc[lane]);
     }
   }
   for (int off = NLANES / 2; off >= 1; off /= 2)
@@ -91,8 +91,7 @@ static float seq_l2(const float* a, const float* b, int32_t n) {
   float acc = 0.0f;
   for (int e = 0; e < n; ++e) {
     float t = a[e] - b[e];
-    t = t * t;
-    acc = acc + t;
+    acc = fmaf(t, t, acc);
   }
   return acc;
 }

@@ -41,8 +41,8 @@ __global__ void gather_rows_kernel(const float* __restrict__ x, const int64_t* _
 }
 
 // Code of each (row, sub-space): blockIdx.y = sub-space m, the sub-space's
-// codebook in LDS; residual element r = x - c(x), then t = r - C; t = t*t;
-// acc = acc + t sequentially; ties to the smaller codeword.
+// codebook in LDS; residual element r = x - c(x), then t = r - C and
+// acc = fma(t, t, acc) sequentially from +0; ties to the smaller codeword.
 __global__ __launch_bounds__(256) void pq_assign_kernel(const float* __restrict__ x, const int64_t* __restrict__ rows,
                                                         int64_t nrows, const int32_t* __restrict__ assign_of_row,
                                                         const float* __restrict__ cent, const float* __restrict__ codebook,
@@ -63,9 +63,8 @@ __global__ __launch_bounds__(256) void pq_assign_kernel(const float* __restrict_
     for (int b = 0; b < ksub; ++b) {
       float acc = 0.0f;
       for (int e = 0; e < dsub; ++e) {
-        float t = r[e] - cbm[b * dsub + e];
-        t = t * t;
-        acc = acc + t;
+        const float t = r[e] - cbm[b * dsub + e];
+        acc = __builtin_fmaf(t, t, acc);
       }
       if (b == 0 || acc < bk) { bk = acc; best = b; }
     }

@@ -60,30 +60,33 @@ __device__ __forceinline__ float canon_reduce32(float acc) {
   return acc;
 }
 
+// One four-element chunk of the canonical sums: per element a difference
+// (L2) and a fused multiply-add into the running sum (one rounding of
+// t * t + acc, or a * b + acc).
 __device__ __forceinline__ float chunk_l2(float4 a, float4 b, float acc) {
   float t;
-  t = a.x - b.x; t = t * t; acc = acc + t;
-  t = a.y - b.y; t = t * t; acc = acc + t;
-  t = a.z - b.z; t = t * t; acc = acc + t;
-  t = a.w - b.w; t = t * t; acc = acc + t;
+  t = a.x - b.x; acc = __builtin_fmaf(t, t, acc);
+  t = a.y - b.y; acc = __builtin_fmaf(t, t, acc);
+  t = a.z - b.z; acc = __builtin_fmaf(t, t, acc);
+  t = a.w - b.w; acc = __builtin_fmaf(t, t, acc);
   return acc;
 }
-// chunk_l2(a, b, 0.0f) without its first addition: 0 + t is t for every
-// square t (never -0), so the result is the same bit for bit
+// chunk_l2(a, b, 0.0f) with its first step a plain square: t * t + 0 rounds
+// to the rounded square for every t (never -0), so the result is the same
+// bit for bit
 __device__ __forceinline__ float chunk_l2_0(float4 a, float4 b) {
   float t, acc;
   t = a.x - b.x; acc = t * t;
-  t = a.y - b.y; t = t * t; acc = acc + t;
-  t = a.z - b.z; t = t * t; acc = acc + t;
-  t = a.w - b.w; t = t * t; acc = acc + t;
+  t = a.y - b.y; acc = __builtin_fmaf(t, t, acc);
+  t = a.z - b.z; acc = __builtin_fmaf(t, t, acc);
+  t = a.w - b.w; acc = __builtin_fmaf(t, t, acc);
   return acc;
 }
 __device__ __forceinline__ float chunk_ip(float4 a, float4 b, float acc) {
-  float t;
-  t = a.x * b.x; acc = acc + t;
-  t = a.y * b.y; acc = acc + t;
-  t = a.z * b.z; acc = acc + t;
-  t = a.w * b.w; acc = acc + t;
+  acc = __builtin_fmaf(a.x, b.x, acc);
+  acc = __builtin_fmaf(a.y, b.y, acc);
+  acc = __builtin_fmaf(a.z, b.z, acc);
+  acc = __builtin_fmaf(a.w, b.w, acc);
   return acc;
 }
 

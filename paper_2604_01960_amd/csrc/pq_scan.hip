@@ -277,7 +277,10 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
   constexpr int UW = G / 2;                   // 32-bit words per one-byte row
   static_assert(G == 4 || (U8 && G == 8), "float rows serve 4 queries, one-byte rows 4 or 8");
   static_assert(!U8 || M * 255 < 65536, "16-bit partial sums");
-  extern __shared__ __align__(16) float4 lut4[];   // [NENT * FR]: entry e for the group's queries
+  // [NENT / SL * FR]: entry e for the group's queries.  A static array, so
+  // that its address is a constant: a table read is then the code byte
+  // times 16 (one shift of the selected byte) plus an immediate offset.
+  __shared__ __align__(16) float4 lut4[NENT / SL * FR];
   __shared__ __align__(16) float res[G][D];
   __shared__ uint32_t wcnt[2][NT / 64][(G + 1) / 2];
   __shared__ float u8_lo[U8 ? M : 1][G];      // per (sub-space, query) minimum
@@ -434,14 +437,13 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
           float out[G];
 #pragma unroll
           for (int g = 0; g < G; ++g) {
-            // the sum from 0 in t order; its first term alone (0 + u is u
-            // for a square)
+            // the sum from 0 in t order by fused multiply-adds; its first
+            // term a plain square (u * u + 0 rounds to the rounded square)
             float acc = 0.0f;
 #pragma unroll
             for (int t = 0; t < DSUB; ++t) {
-              float u = res[g][m * DSUB + t] - cw[t];
-              u = u * u;
-              acc = t == 0 ? u : acc + u;
+              const float u = res[g][m * DSUB + t] - cw[t];
+              acc = t == 0 ? u * u : __builtin_fmaf(u, u, acc);
             }
             out[g] = acc;
           }
@@ -825,9 +827,8 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
     const float* rr = res + m * dsub;
     float acc = 0.0f;
     for (int t = 0; t < dsub; ++t) {
-      float u = rr[t] - cw[t];
-      u = u * u;
-      acc = acc + u;
+      const float u = rr[t] - cw[t];
+      acc = __builtin_fmaf(u, u, acc);
     }
     lut[e] = acc;
   }
@@ -885,8 +886,7 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
 
 template <int BITS, int M, int DSUB, int NT, int O, bool U8, int SL, int PMAX, int BPC>
 static void launch_grouped_t(const PqScanArgs& a, int blocks, hipStream_t s) {
-  constexpr int G = scan_group_of(U8, BITS);
-  const size_t lds = sizeof(float) * (size_t)G * (M / SL) * (1 << BITS);
+  const size_t lds = 0;  // the tables are static LDS
   const dim3 grid(BPC * blocks), block(NT);
   if (a.mode == 0)
     hipLaunchKernelGGL((pq_scan_grouped<0, BITS, M, DSUB, NT, O, U8, false, SL, PMAX, BPC>), grid, block, lds, s, a);
@@ -898,7 +898,10 @@ static void launch_grouped_t(const PqScanArgs& a, int blocks, hipStream_t s) {
 
 template <int BITS, int M, int DSUB, int NT, int O, int SL, int PMAX, int BPC>
 static void launch_grouped(const PqScanArgs& a, int blocks, hipStream_t s) {
-  if (a.lut_u8) launch_grouped_t<BITS, M, DSUB, NT, O, true, 1, 1, BPC>(a, blocks, s);
+  // one-byte tables take two blocks per CU only when their float staging
+  // fits twice in LDS (the callers ask for one block otherwise)
+  constexpr bool U8_BPC = BPC == 1 || (size_t)scan_group_of(true, BITS) * M * (1 << BITS) * sizeof(float) <= 65536;
+  if (a.lut_u8) launch_grouped_t<BITS, M, DSUB, NT, O, true, 1, 1, U8_BPC ? BPC : 1>(a, blocks, s);
   else launch_grouped_t<BITS, M, DSUB, NT, O, false, SL, PMAX, BPC>(a, blocks, s);
 }
 
