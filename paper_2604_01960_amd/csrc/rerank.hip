@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include "common.h"
+#include "bin_sort.h"
 #include "kernels.h"
 
 namespace bbc {
@@ -344,14 +345,18 @@ __device__ __forceinline__ bool rt_round_keep(const TileRerankArgs& a, int q, ui
   return a.round != 1 || place < a.wround[4 * (int64_t)q + 1];
 }
 
-// Shared by both tile kernels: the block's pairs, the rows of tile t in LDS,
-// and the tile's work cut into runs of up to 64 candidates of one pair.
+// Shared by both tile kernels: the block's pairs (their queries, output and
+// position offsets and first bins), loaded once per group.
 struct RtGroup {
   int32_t q[RT_G], r[RT_G];
   int64_t co[RT_G], pof[RT_G];   // output and position offsets of the pair's query
   int64_t bbase[RT_G];           // the pair's first bin in bin_beg
-  uint32_t beg[RT_G], end[RT_G];  // the pair's candidates in this tile's bin
-  uint32_t cpre[RT_G + 1];       // runs before each pair (this tile)
+};
+// Per tile of rt_rerank_tile: each pair's candidates in the tile, and the
+// next unclaimed pair.
+struct RtTileBins {
+  uint32_t beg[RT_G], end[RT_G];
+  uint32_t next;
 };
 
 template <int NT>
@@ -379,41 +384,6 @@ __device__ __forceinline__ void rt_stage_rows(uint4* tile, const uint4* sw, int 
   }
 }
 
-// by lanes 0..63 of wave 0: each pair's bin for tile t, cut into 64-candidate runs
-__device__ __forceinline__ void rt_runs(const TileRerankArgs& a, int t, RtGroup& g) {
-  constexpr int EPL = RT_G / 64;
-  uint32_t nc[EPL], tot = 0;
-#pragma unroll
-  for (int h = 0; h < EPL; ++h) {
-    const int e = EPL * (int)threadIdx.x + h;
-    uint32_t b0 = 0, b1 = 0;
-    if (g.q[e] >= 0) {
-      const uint32_t* bb = a.bin_beg + g.bbase[e] + t;
-      b0 = bb[0];
-      b1 = bb[1];
-    }
-    g.beg[e] = b0;
-    g.end[e] = b1;
-    nc[h] = (b1 - b0 + 63) / 64;
-    tot += nc[h];
-  }
-  uint32_t run = wave_incl_scan(tot) - tot;
-#pragma unroll
-  for (int h = 0; h < EPL; ++h) {
-    g.cpre[EPL * threadIdx.x + h] = run;
-    run += nc[h];
-  }
-  if (threadIdx.x == 63) g.cpre[RT_G] = run;
-}
-
-__device__ __forceinline__ int rt_run_pair(const RtGroup& g, uint32_t c) {
-  int e = 0;
-#pragma unroll
-  for (int step = RT_G / 2; step >= 1; step >>= 1)
-    if (g.cpre[e + step] <= c) e += step;
-  return e;
-}
-
 // Rows of at most 32 chunks: 8 lanes per candidate, lane p of an octet
 // holding the virtual lanes (four-element chunks) u, u + 8, u + 16 and u + 24
 // of the canonical sum, u = p for p < 4 and 11 - p otherwise, so that the
@@ -423,11 +393,19 @@ __device__ __forceinline__ int rt_run_pair(const RtGroup& g, uint32_t c) {
 // chunks past it count as zero).  IP: the metric is inner product.  NC: the
 // row's chunk count when fixed at compile time (32 or 24: no clamps and no
 // selects, constant row stride), 0 for any count up to 32.
+//
+// Per tile, wave 0 reads every pair's bin bounds (one batch of loads), then
+// each wave claims the group's pairs one at a time (an LDS counter, the next
+// claim issued before the current pair's work) and takes the pair's
+// candidates in this tile in runs of 64: the pair, its query row and its
+// bin bounds are wave-uniform (scalar registers), and the query row is
+// loaded once per pair and tile.
 template <typename T, bool IP, int NC>
 __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
-  constexpr int NT = 1024, NW = NT / 64;
+  constexpr int NT = 1024;
   __shared__ uint4 tile[RT_TILE_BYTES / 16];
   __shared__ RtGroup g;
+  __shared__ RtTileBins tb;
   const int64_t blk = blockIdx.x;
   if (blk >= (int64_t)a.lcnt[a.nlist]) return;
   rt_load_group<NT>(a, blk, g);
@@ -437,7 +415,12 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   const int64_t lb = a.list_off[L], le = a.list_off[L + 1];
   const int TR = 1 << a.tshift;
   const int ntile = (int)((le - lb + TR - 1) >> a.tshift);
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63;
+  auto claim = [&]() {
+    uint32_t c = 0u;
+    if (lane == 0) c = atomicAdd(&tb.next, 1u);
+    return (int)uniform(__shfl(c, 0));
+  };
   const int oct = lane >> 3, p = lane & 7;
   const int vb = p < 4 ? p : 11 - p;
   const int kaddr = 4 * (8 * (lane & 7));  // byte address of lane 8 (l mod 8), which holds candidate l's sum
@@ -450,70 +433,99 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   for (int t = 0; t < ntile; ++t) {
     const int64_t r0 = (int64_t)t * TR;
     const int nr = (int)min((int64_t)TR, le - lb - r0);
-    __syncthreads();  // the previous tile is no longer read
+    const uint32_t pbase = (uint32_t)(lb + r0);  // list position of the tile's first row
+    __syncthreads();  // the previous tile is no longer read, nor its bins and counter
+    if (threadIdx.x < 64) {
+      constexpr int EPL = RT_G / 64;
+      uint32_t b0[EPL], b1[EPL];
+#pragma unroll
+      for (int h = 0; h < EPL; ++h) {
+        const int e = EPL * (int)threadIdx.x + h;
+        b0[h] = b1[h] = 0u;
+        if (g.q[e] >= 0) {
+          const uint32_t* bb = a.bin_beg + g.bbase[e] + t;
+          b0[h] = bb[0];
+          b1[h] = bb[1];
+        }
+      }
+#pragma unroll
+      for (int h = 0; h < EPL; ++h) {
+        tb.beg[EPL * threadIdx.x + h] = b0[h];
+        tb.end[EPL * threadIdx.x + h] = b1[h];
+      }
+      if (threadIdx.x == 0) tb.next = 0u;
+    }
     rt_stage_rows<NT>(tile, src + r0 * row_words, nr * row_words);
-    if (threadIdx.x < 64) rt_runs(a, t, g);
     __syncthreads();
-    const uint32_t nrun = g.cpre[RT_G];
-    for (uint32_t c = wv; c < nrun; c += NW) {
-      const int e = rt_run_pair(g, c);
-      const uint32_t j0 = g.beg[e] + (c - g.cpre[e]) * 64;
-      const int cnt = (int)min(64u, g.end[e] - j0);
-      const int q = g.q[e];
-      const int64_t co = g.co[e], pof = g.pof[e];
-      // lane l: candidate l's position, id, output index and row in the tile (-1: none)
-      const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
-      const int64_t rl = (int64_t)pl - lb - r0;
-      bool okl = lane < cnt && rl >= 0 && rl < nr;
-      const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
-      okl = okl && rt_round_keep(a, q, oil);
-      const int32_t idl = okl ? a.list_ids[pl] : 0;
-      const int rowl = okl ? (int)rl : -1;
+    for (int e = claim(); e < RT_G;) {
+      const int q = uniform(g.q[e]);
+      if (q < 0) break;  // padding ends the group
+      const uint32_t b0 = uniform(tb.beg[e]), b1 = uniform(tb.end[e]);
+      const int e_next = claim();
+      if (b0 >= b1) {
+        e = e_next;
+        continue;
+      }
+      const int64_t co = uniform(g.co[e]), pof = uniform(g.pof[e]);
+      const uint32_t keep_below = a.round == 1 ? uniform(a.wround[4 * (int64_t)q + 1]) : 0xffffffffu;
       float4 qv[4];
+      const float4* qrow = reinterpret_cast<const float4*>(a.q + (int64_t)q * d);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int v = vb + 8 * i;
-        qv[i] = v < nchunk ? reinterpret_cast<const float4*>(a.q + (int64_t)q * d)[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        qv[i] = v < nchunk ? qrow[v] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      float mykey = 0.0f;
-      for (int it = 0; it * 8 < cnt; ++it) {
-        const int rr = __shfl(rowl, it * 8 + oct);  // this octet's candidate (-1: none, row 0 read)
-        const T* row = trow + max(rr, 0) * d;
-        float acc[4];
-        if (NC == 32) {
-          float4 x[4];
+      for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
+        const int cnt = (int)min(64u, b1 - j0);
+        // lane l: candidate l's position, id, output index and row in the tile (-1: none)
+        const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
+        const uint32_t rl = pl - pbase;
+        bool okl = lane < cnt && rl < (uint32_t)nr;
+        const uint32_t oil = !okl ? 0u : (a.sorted_idx ? a.sorted_idx[pof + j0 + lane] : j0 + lane);
+        okl = okl && oil < keep_below;
+        const int32_t idl = okl ? a.list_ids[pl] : 0;
+        const int rowl = okl ? (int)rl : -1;
+        float mykey = 0.0f;
+        for (int it = 0; it * 8 < cnt; ++it) {
+          const int rr = __shfl(rowl, it * 8 + oct);  // this octet's candidate (-1: none, row 0 read)
+          const T* row = trow + max(rr, 0) * d;
+          float acc[4];
+          if (NC == 32) {
+            float4 x[4];
 #pragma unroll
-          for (int i = 0; i < 4; ++i) x[i] = load4<T>(row, vb + 8 * i);
+            for (int i = 0; i < 4; ++i) x[i] = load4<T>(row, vb + 8 * i);
 #pragma unroll
-          for (int i = 0; i < 4; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
-        } else if (NC == 24) {
-          // virtual lanes 24..31 hold no chunk: their sums are +0
-          float4 x[3];
+            for (int i = 0; i < 4; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
+          } else if (NC == 24) {
+            // virtual lanes 24..31 hold no chunk: their sums are +0
+            float4 x[3];
 #pragma unroll
-          for (int i = 0; i < 3; ++i) x[i] = load4<T>(row, vb + 8 * i);
+            for (int i = 0; i < 3; ++i) x[i] = load4<T>(row, vb + 8 * i);
 #pragma unroll
-          for (int i = 0; i < 3; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
-          acc[3] = 0.0f;
-        } else {
+            for (int i = 0; i < 3; ++i) acc[i] = IP ? chunk_ip(qv[i], x[i], 0.0f) : chunk_l2_0(qv[i], x[i]);
+            acc[3] = 0.0f;
+          } else {
 #pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const float4 xl = load4<T>(row, min(vb + 8 * i, nchunk - 1));
-            const float4 x = vb + 8 * i < nchunk ? xl : make_float4(0.f, 0.f, 0.f, 0.f);
-            acc[i] = IP ? chunk_ip(qv[i], x, 0.0f) : chunk_l2(qv[i], x, 0.0f);
+            for (int i = 0; i < 4; ++i) {
+              const float4 xl = load4<T>(row, min(vb + 8 * i, nchunk - 1));
+              const float4 x = vb + 8 * i < nchunk ? xl : make_float4(0.f, 0.f, 0.f, 0.f);
+              acc[i] = IP ? chunk_ip(qv[i], x, 0.0f) : chunk_l2(qv[i], x, 0.0f);
+            }
           }
+          // levels 16 and 8 within the lane, 4 across lanes p and 7 - p
+          // (half-row mirror), 2 and 1 within quads
+          // (rows of 24 chunks, L2: acc[3] is +0 and acc[1] never -0)
+          float sum = (acc[0] + acc[2]) + (NC == 24 && !IP ? acc[1] : acc[1] + acc[3]);
+          sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x141, 0xf, 0xf, false));
+          sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x4e, 0xf, 0xf, false));
+          sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0xb1, 0xf, 0xf, false));
+          // candidate it * 8 + o's sum sits in lane 8 * o
+          const float kk = __int_as_float(__builtin_amdgcn_ds_bpermute(kaddr, __float_as_int(sum)));
+          if ((lane >> 3) == it) mykey = IP ? -kk : kk;
         }
-        // levels 16 and 8 within the lane, 4 across lanes p and 7 - p
-        // (half-row mirror), 2 and 1 within quads
-        // (rows of 24 chunks, L2: acc[3] is +0 and acc[1] never -0)
-        float sum = (acc[0] + acc[2]) + (NC == 24 && !IP ? acc[1] : acc[1] + acc[3]);
-        sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x141, 0xf, 0xf, false));
-        sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0x4e, 0xf, 0xf, false));
-        sum = sum + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(sum), 0xb1, 0xf, 0xf, false));
-        // candidate it * 8 + o's sum sits in lane 8 * o
-        const float kk = __int_as_float(__builtin_amdgcn_ds_bpermute(kaddr, __float_as_int(sum)));
-        if ((lane >> 3) == it) mykey = IP ? -kk : kk;
+        if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
       }
-      if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
+      e = e_next;
     }
   }
 }
@@ -628,13 +640,30 @@ size_t tile_rerank_sort_lds(int max_bins, int max_np, int nlist) {
   return sizeof(uint32_t) * ((size_t)max_bins + 2 * (size_t)max_np) + sizeof(uint16_t) * (size_t)nlist;
 }
 
+// the list sort's binner: bin = list; slot -> (query << 32 | rank)
+struct TilePairBins {
+  const int32_t* nprobe; const int32_t* probe_lists; uint64_t* lpairs;
+  __device__ int64_t count(int64_t q) const { return nprobe[q]; }
+  __device__ int bin(int64_t, int, int64_t p) const { return probe_lists[p]; }
+  __device__ void put(uint32_t slot, int64_t q, int r, int64_t) const {
+    lpairs[slot] = ((uint64_t)q << 32) | (uint32_t)r;
+  }
+};
+
 hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s) {
   if (a.nq <= 0 || a.npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(rt_fill_u64, dim3((unsigned)std::min<int64_t>((a.lpairs_cap + 255) / 256, 4096)), dim3(256), 0,
+                     s, a.lpairs, a.lpairs_cap, RT_NO_PAIR);
+  if (a.bs_table && a.nlist <= BS_MAX_BINS) {
+    const TilePairBins f{a.nprobe, a.probe_lists, a.lpairs};
+    bs_sort(f, a.nlist, a.nq, a.probe_off, a.bs_table, a.lcnt, [&] {
+      hipLaunchKernelGGL(rt_pair_offsets, dim3(1), dim3(1024), 0, s, a);
+    }, s);
+    return hipGetLastError();
+  }
   const dim3 pg((unsigned)((a.max_np + 255) / 256), (unsigned)a.nq);
   hipLaunchKernelGGL(rt_fill_u32, dim3((unsigned)std::min<int64_t>((a.nlist + 256) / 256, 1024)), dim3(256), 0, s,
                      a.lcnt, (int64_t)a.nlist + 1, 0u);
-  hipLaunchKernelGGL(rt_fill_u64, dim3((unsigned)std::min<int64_t>((a.lpairs_cap + 255) / 256, 4096)), dim3(256), 0,
-                     s, a.lpairs, a.lpairs_cap, RT_NO_PAIR);
   hipLaunchKernelGGL(rt_pair_count, pg, dim3(256), 0, s, a);
   hipLaunchKernelGGL(rt_pair_offsets, dim3(1), dim3(1024), 0, s, a);
   hipLaunchKernelGGL(rt_pair_scatter, pg, dim3(256), 0, s, a);
