@@ -294,6 +294,10 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
   constexpr int MS = M / SL;            // sub-spaces per slice
   constexpr int NVS = NVEC / SL;        // 16-byte code words per slice
   constexpr int EPS = EPT / SL;         // owned entries per slice
+  // sliced tables: each thread builds entries of one sub-space (TPM threads
+  // per sub-space of the slice)
+  constexpr int TPM = NT / MS;
+  constexpr bool SUBM = SL > 1 && !REGCB && NT % MS == 0 && KSUB % TPM == 0;
 
   // the codebook is the same for every group: the owned codewords are loaded once
   float creg[REGCB ? EPT : 1][DSUB];
@@ -422,6 +426,39 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     __syncthreads();
     // the entries of slice sl (all of them without slices) into the table
     auto build_slice = [&](int sl) {
+      if constexpr (SUBM) {
+        // thread t builds entries j = t % TPM + TPM * i of sub-space t / TPM
+        // of the slice: the sub-space's residuals are read from LDS once
+        const int ml = threadIdx.x / TPM, m = sl * MS + ml;
+        float rg[G][DSUB];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+          for (int t = 0; t < DSUB; ++t) rg[g][t] = res[g][m * DSUB + t];
+#pragma unroll
+        for (int i = 0; i < KSUB / TPM; ++i) {
+          const int jj = threadIdx.x % TPM + TPM * i;
+          const float* cwp = a.codebook + ((int64_t)m * KSUB + jj) * DSUB;
+          float cw[DSUB];
+#pragma unroll
+          for (int t = 0; t < DSUB; ++t) cw[t] = cwp[t];
+          float out[G];
+#pragma unroll
+          for (int g = 0; g < G; ++g) {
+            float acc = 0.0f;
+#pragma unroll
+            for (int t = 0; t < DSUB; ++t) {
+              const float u = rg[g][t] - cw[t];
+              acc = t == 0 ? u * u : __builtin_fmaf(u, u, acc);
+            }
+            out[g] = acc;
+          }
+#pragma unroll
+          for (int h = 0; h < FR; ++h)
+            lut4[(ml * KSUB + jj) * FR + h] = make_float4(out[4 * h], out[4 * h + 1], out[4 * h + 2], out[4 * h + 3]);
+        }
+        return;
+      }
 #pragma unroll
       for (int i = 0; i < EPT; ++i) {
         if (i / EPS != sl) continue;
