@@ -194,6 +194,9 @@ struct bbc_index {
   // pair sorts by list: per-block LDS histograms (1) or device-wide atomics
   // (0) (BBC_PAIR_SORT)
   int pair_sort_lds = 1;
+  // final top-k: most results ranked in LDS (BBC_FINAL_LDS_CAP; 0: as many
+  // as the LDS holds); larger result sets group their winners in memory
+  int64_t final_lds_cap = 0;
   // RaBitQ wide form: the first round's keys reach this fraction of the way
   // from the k-th smallest lb's bin to U's bin (BBC_WALK_ALPHA; >= 1: one
   // round over all of C).  Unset (< 0): 0.8 with tile-major keys (large
@@ -304,6 +307,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
   if (const char* sv = std::getenv("BBC_SCAN_BY_LIST")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 1) ix->scan_by_list = x;
+  }
+  if (const char* sv = std::getenv("BBC_FINAL_LDS_CAP")) {
+    const long long x = std::atoll(sv);
+    if (x >= 1024) ix->final_lds_cap = x;
   }
   if (const char* sv = std::getenv("BBC_PAIR_SORT")) {
     const int x = std::atoi(sv);
@@ -893,7 +900,8 @@ int32_t launch_final_groups(bbc_index* ix, const FinalGroups& fg, const int32_t*
                             hipStream_t s) {
   // the LDS buffer: the group's largest result set when it fits (larger ones
   // group their winners in the scratch buffer and sort in memory)
-  const int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
+  int64_t cap_max = std::max<int64_t>(1024, (ix->max_lds - bbc::FINAL_STATIC_LDS) / 8);
+  if (ix->final_lds_cap > 0) cap_max = std::min(cap_max, ix->final_lds_cap);
   for (const auto& g : fg.groups) {
     const int cap = (int)std::min(g.max_cnt, cap_max);
     int run = 1;

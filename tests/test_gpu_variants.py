@@ -54,17 +54,29 @@ def test_large_k_variants_match_oracle(bbc, cfg):
     g.free()
 
 
-def test_final_topk_groups_match_oracle(bbc):
+@pytest.mark.parametrize("lds_cap", ["", "1024"])
+def test_final_topk_groups_match_oracle(bbc, lds_cap):
     """A batch above the size from which the final top-k runs one launch per
     kernel form (256 queries, one per CU): per-query k spread so that the
     queries' candidate sets select every form (8, 16, 24 and 32 items per
-    thread and the memory form); ids and distances equal the oracle's."""
+    thread and the memory form); ids and distances equal the oracle's.  With
+    the LDS buffer cut to 1024 results, every result set above it groups its
+    winners by bin in the scratch buffer."""
     nq = 300
     w, ix, q = oracle_pq_index("ivfpq_100k_d128", 100_000, 64, 16, 8, nq)
     ks = np.array([500, 3000, 6000, 8000, 12000, 16000], np.int32)
     k = ks[np.arange(nq) % len(ks)]
-    print(f"[case] final top-k groups nq={nq}", flush=True)
-    g = make_gpu_index(bbc, ix)
+    print(f"[case] final top-k groups nq={nq} lds_cap={lds_cap or 'default'}", flush=True)
+    old = os.environ.get("BBC_FINAL_LDS_CAP")
+    if lds_cap:
+        os.environ["BBC_FINAL_LDS_CAP"] = lds_cap
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        if old is None:
+            os.environ.pop("BBC_FINAL_LDS_CAP", None)
+        else:
+            os.environ["BBC_FINAL_LDS_CAP"] = old
     got = g.search(q, k, 48, ratio=2.5)
     ref = oracle.search_pq(ix, q, k.astype(np.int64), np.full(nq, 48, np.int64), 2.5)
     np.testing.assert_array_equal(got[3], ref["off"])
