@@ -352,11 +352,15 @@ struct RtGroup {
   int64_t co[RT_G], pof[RT_G];   // output and position offsets of the pair's query
   int64_t bbase[RT_G];           // the pair's first bin in bin_beg
 };
-// Per tile of rt_rerank_tile: each pair's candidates in the tile, and the
-// next unclaimed pair.
+// Per tile of rt_rerank_tile: each pair's candidates in the tile, the runs
+// before each pair, the tile's 64-candidate runs (pair * 64 + run within
+// the pair) when they fit the list, their number and the next unclaimed run.
+constexpr int RT_RUNCAP = 1024;
 struct RtTileBins {
   uint32_t beg[RT_G], end[RT_G];
-  uint32_t next;
+  uint32_t rpre[RT_G + 1];
+  uint16_t run[RT_RUNCAP];
+  uint32_t next, nrun;
 };
 
 template <int NT>
@@ -394,12 +398,14 @@ __device__ __forceinline__ void rt_stage_rows(uint4* tile, const uint4* sw, int 
 // row's chunk count when fixed at compile time (32 or 24: no clamps and no
 // selects, constant row stride), 0 for any count up to 32.
 //
-// Per tile, wave 0 reads every pair's bin bounds (one batch of loads), then
-// each wave claims the group's pairs one at a time (an LDS counter, the next
-// claim issued before the current pair's work) and takes the pair's
-// candidates in this tile in runs of 64: the pair, its query row and its
-// bin bounds are wave-uniform (scalar registers), and the query row is
-// loaded once per pair and tile.
+// Per tile, wave 0 reads every pair's bin bounds (one batch of loads) and
+// lists the tile's runs of up to 64 candidates of one pair; each wave then
+// claims runs one at a time (an LDS counter, the next claim issued before
+// the current run's work), so that a pair with many candidates in the tile
+// spreads over several waves.  The run's pair, query row and bin bounds are
+// wave-uniform (scalar registers).  A tile with more runs than the list
+// holds finds each claimed run's pair by a binary search over the runs
+// before each pair.
 template <typename T, bool IP, int NC>
 __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
   constexpr int NT = 1024;
@@ -437,7 +443,7 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
     __syncthreads();  // the previous tile is no longer read, nor its bins and counter
     if (threadIdx.x < 64) {
       constexpr int EPL = RT_G / 64;
-      uint32_t b0[EPL], b1[EPL];
+      uint32_t b0[EPL], b1[EPL], nrh[EPL], tot = 0u;
 #pragma unroll
       for (int h = 0; h < EPL; ++h) {
         const int e = EPL * (int)threadIdx.x + h;
@@ -452,31 +458,51 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
       for (int h = 0; h < EPL; ++h) {
         tb.beg[EPL * threadIdx.x + h] = b0[h];
         tb.end[EPL * threadIdx.x + h] = b1[h];
+        nrh[h] = b1[h] > b0[h] ? (b1[h] - b0[h] + 63u) / 64u : 0u;
+        tot += nrh[h];
       }
-      if (threadIdx.x == 0) tb.next = 0u;
+      const uint32_t incl = wave_incl_scan(tot);
+      const uint32_t total = __shfl(incl, 63);
+      {
+        uint32_t at = incl - tot;
+#pragma unroll
+        for (int h = 0; h < EPL; ++h) {
+          tb.rpre[EPL * threadIdx.x + h] = at;
+          at += nrh[h];
+        }
+        if (threadIdx.x == 63) tb.rpre[RT_G] = at;
+      }
+      if (total <= (uint32_t)RT_RUNCAP) {
+        uint32_t at = incl - tot;
+#pragma unroll
+        for (int h = 0; h < EPL; ++h) {
+          const uint32_t u0 = (EPL * threadIdx.x + h) * 64;
+#pragma nounroll
+          for (uint32_t k = 0; k < nrh[h]; ++k) tb.run[at + k] = (uint16_t)(u0 + k);
+          at += nrh[h];
+        }
+      }
+      if (threadIdx.x == 0) {
+        tb.next = 0u;
+        tb.nrun = total;
+      }
     }
     rt_stage_rows<NT>(tile, src + r0 * row_words, nr * row_words);
     __syncthreads();
-    for (int e = claim(); e < RT_G;) {
-      const int q = uniform(g.q[e]);
-      if (q < 0) break;  // padding ends the group
-      const uint32_t b0 = uniform(tb.beg[e]), b1 = uniform(tb.end[e]);
-      const int e_next = claim();
-      if (b0 >= b1) {
-        e = e_next;
-        continue;
-      }
-      const int64_t co = uniform(g.co[e]), pof = uniform(g.pof[e]);
-      const uint32_t keep_below = a.round == 1 ? uniform(a.wround[4 * (int64_t)q + 1]) : 0xffffffffu;
-      float4 qv[4];
+    // this lane's chunks of query q's row
+    auto load_q = [&](int q, float4 (&qv)[4]) {
       const float4* qrow = reinterpret_cast<const float4*>(a.q + (int64_t)q * d);
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int v = vb + 8 * i;
         qv[i] = v < nchunk ? qrow[v] : make_float4(0.f, 0.f, 0.f, 0.f);
       }
-      for (uint32_t j0 = b0; j0 < b1; j0 += 64) {
-        const int cnt = (int)min(64u, b1 - j0);
+    };
+    // the candidates [j0, j0 + cnt) of pair e (query q), cnt <= 64
+    auto run = [&](int e, int q, uint32_t j0, int cnt, const float4 (&qv)[4]) {
+      const int64_t co = uniform(g.co[e]), pof = uniform(g.pof[e]);
+      const uint32_t keep_below = a.round == 1 ? uniform(a.wround[4 * (int64_t)q + 1]) : 0xffffffffu;
+      {
         // lane l: candidate l's position, id, output index and row in the tile (-1: none)
         const uint32_t pl = lane < cnt ? a.sorted_pos[pof + j0 + lane] : 0u;
         const uint32_t rl = pl - pbase;
@@ -525,7 +551,30 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
         }
         if (okl) a.cand_packed[co + oil] = pack_key_id(mykey, (uint32_t)idl);
       }
-      e = e_next;
+    };
+    const uint32_t nrun = uniform(tb.nrun);
+    const bool listed = nrun <= (uint32_t)RT_RUNCAP;
+    for (int c = claim(); c < (int)nrun;) {
+      const int c_next = claim();
+      int e;
+      uint32_t k;
+      if (listed) {
+        const uint32_t u = uniform((uint32_t)tb.run[c]);
+        e = (int)(u >> 6);
+        k = u & 63u;
+      } else {
+        e = 0;
+#pragma unroll
+        for (int step = RT_G / 2; step >= 1; step >>= 1)
+          if (uniform(tb.rpre[e + step]) <= (uint32_t)c) e += step;
+        k = (uint32_t)c - uniform(tb.rpre[e]);
+      }
+      const int q = uniform(g.q[e]);
+      const uint32_t j0 = uniform(tb.beg[e]) + 64u * k, b1 = uniform(tb.end[e]);
+      float4 qv[4];
+      load_q(q, qv);
+      run(e, q, j0, (int)min(64u, b1 - j0), qv);
+      c = c_next;
     }
   }
 }
