@@ -194,6 +194,9 @@ struct bbc_index {
   // pair sorts by list: per-block LDS histograms (1) or device-wide atomics
   // (0) (BBC_PAIR_SORT)
   int pair_sort_lds = 1;
+  // tile-major re-rank: runs found by binary search instead of the tile's
+  // run list (BBC_RERANK_RUN_LIST=0; for tests of that path)
+  int no_run_list = 0;
   // final top-k: most results ranked in LDS (BBC_FINAL_LDS_CAP; 0: as many
   // as the LDS holds); larger result sets group their winners in memory
   int64_t final_lds_cap = 0;
@@ -312,6 +315,7 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
     const long long x = std::atoll(sv);
     if (x >= 1024) ix->final_lds_cap = x;
   }
+  if (const char* sv = std::getenv("BBC_RERANK_RUN_LIST")) ix->no_run_list = std::atoi(sv) == 0;
   if (const char* sv = std::getenv("BBC_PAIR_SORT")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 1) ix->pair_sort_lds = x;
@@ -1151,6 +1155,7 @@ int32_t run_search_rabitq(bbc_index* ix, const float* queries, int64_t nq, const
     ta.lcnt = reinterpret_cast<uint32_t*>(A + L_rtc);
     ta.lpairs = reinterpret_cast<uint64_t*>(A + L_rtl);
     ta.bs_table = bs_words ? reinterpret_cast<uint32_t*>(A + L_bst) : nullptr;
+    ta.no_run_list = ix->no_run_list;
     ta.lpairs_cap = rt_lpairs_cap;
     ta.group = rt_group;
   }
@@ -1630,6 +1635,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.lpairs = reinterpret_cast<uint64_t*>(A + L.rt_lpairs);
       ta.lpairs_cap = rt_lpairs_cap;
       ta.bs_table = bs_words ? reinterpret_cast<uint32_t*>(A + L.bs_table) : nullptr;
+      ta.no_run_list = ix->no_run_list;
       ta.group = rt_group;
       if (early) ta.sorted_idx = reinterpret_cast<uint32_t*>(A + L.rt_sidx);
       HIP_TRY(bbc::launch_tile_rerank(ta, rt_lds, s));

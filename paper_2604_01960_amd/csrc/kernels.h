@@ -203,6 +203,7 @@ struct TileRerankArgs {
   int round; const uint32_t* wround;
   int pairs_ready;          // lcnt and lpairs already filled (launch_tile_pairs)
   uint32_t* bs_table;       // pair sort's per-block counts (bs_table_words(nq, nlist)); NULL: global atomics
+  int no_run_list;          // tile re-rank: find each run's pair by binary search even when the runs fit the list
 };
 // the (query, rank) pairs grouped by list into whole groups: lcnt, lpairs
 hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s);

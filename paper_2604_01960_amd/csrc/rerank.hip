@@ -553,7 +553,7 @@ __global__ __launch_bounds__(1024, 8) void rt_rerank_tile(TileRerankArgs a) {
       }
     };
     const uint32_t nrun = uniform(tb.nrun);
-    const bool listed = nrun <= (uint32_t)RT_RUNCAP;
+    const bool listed = nrun <= (uint32_t)RT_RUNCAP && !a.no_run_list;
     for (int c = claim(); c < (int)nrun;) {
       const int c_next = claim();
       int e;

@@ -74,6 +74,32 @@ def _check_search(g, ix, q, k, nprobe, eps0=oracle.RABITQ_EPS0):
     return tr, ref
 
 
+@pytest.mark.parametrize("run_list", ["1", "0"])
+def test_tile_runs_listed_or_searched(bbc, run_list):
+    """Tile-major exact keys with half-precision rows of 64 dimensions (512
+    rows per tile, so a pair holds up to 8 runs of 64 candidates in a tile):
+    300 queries over 6 lists of about 2000 rows with large k put more than
+    1024 runs in most tiles.  The waves claim runs from the tile's list when
+    they fit it and otherwise find each run's pair by binary search;
+    BBC_RERANK_RUN_LIST=0 takes the search for every tile.  Results equal
+    the oracle's either way."""
+    import os
+    x, q, tr, ip, P, ix = _data(64, 12000, 300, 6, 0, True)
+    print(f"[case] rabitq tile runs d=64 fp16 nq=300 run_list={run_list}", flush=True)
+    old = os.environ.get("BBC_RERANK_RUN_LIST")
+    os.environ["BBC_RERANK_RUN_LIST"] = run_list
+    try:
+        g = _gpu_index(bbc, x, ix, form="tiles")
+    finally:
+        if old is None:
+            os.environ.pop("BBC_RERANK_RUN_LIST")
+        else:
+            os.environ["BBC_RERANK_RUN_LIST"] = old
+    rng = np.random.default_rng(5)
+    k = rng.integers(2000, 6000, 300).astype(np.int32)
+    _check_search(g, ix, q, k, 6)
+
+
 @pytest.mark.parametrize("d", [128, 960])
 def test_gpu_build_matches_oracle(bbc, d):
     n = 6000 if d == 128 else 2500
