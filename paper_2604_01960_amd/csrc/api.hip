@@ -197,6 +197,11 @@ struct bbc_index {
   // tile-major re-rank: runs found by binary search instead of the tile's
   // run list (BBC_RERANK_RUN_LIST=0; for tests of that path)
   int no_run_list = 0;
+  // PQ float-table searches: the lists after the sample are filtered at the
+  // upper edge of the first cell by which the sample's running count reaches
+  // this fraction of K_c (BBC_FILTER_FRACTION; 0 or >= 1: at d_max), with a
+  // rescan at d_max for a query it leaves short of K_c keys
+  float filt_fraction = 0.0f;
   // final top-k: most results ranked in LDS (BBC_FINAL_LDS_CAP; 0: as many
   // as the LDS holds); larger result sets group their winners in memory
   int64_t final_lds_cap = 0;
@@ -316,6 +321,10 @@ int32_t upload_ivf_common(bbc_index* ix, const float* centroids, const int64_t* 
     if (x >= 1024) ix->final_lds_cap = x;
   }
   if (const char* sv = std::getenv("BBC_RERANK_RUN_LIST")) ix->no_run_list = std::atoi(sv) == 0;
+  if (const char* sv = std::getenv("BBC_FILTER_FRACTION")) {
+    const float x = std::strtof(sv, nullptr);
+    if (x >= 0.0f && x <= 1.0f) ix->filt_fraction = x;
+  }
   if (const char* sv = std::getenv("BBC_PAIR_SORT")) {
     const int x = std::atoi(sv);
     if (x >= 0 && x <= 1) ix->pair_sort_lds = x;
@@ -797,7 +806,7 @@ namespace {
 
 struct Layout {
   // offsets into the arena
-  size_t nsample_q, pair_cnt, pair_split, bs_table, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
+  size_t nsample_q, pair_cnt, pair_split, bs_table, rescan_q, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb, qorder, rt_sorted, rt_bins, rt_ptb, rt_lcnt, rt_lpairs;
@@ -1407,6 +1416,11 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   // re-rank's (nlist) reuse it
   const int64_t bs_words = ix->pair_sort_lds ? bbc::pair_sort_table_words(nq, 2 * ix->nlist) : 0;
   L.bs_table = bs_words ? pl.add(4 * bs_words) : 0;
+  // the tighter filter of the lists after the sample (float tables only: its
+  // rescan runs the generic float-table kernel)
+  const bool tight = bucket && !p->early_rerank && !p->lut_u8 && !p->keep_all_keys && ix->filt_fraction > 0.0f &&
+                     ix->filt_fraction < 1.0f;
+  L.rescan_q = tight ? pl.add(4 * nq) : 0;
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
@@ -1565,6 +1579,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   }
   ca.early = early;
   ca.keep_all = p->keep_all_keys != 0;
+  ca.filt_fraction = tight ? ix->filt_fraction : 0.0f;
   ca.t_tau_pred = early ? reinterpret_cast<int32_t*>(A + L.t_tpred) : nullptr;
 
   // scan of the sample lists, codebook, scan of the rest through the filter,
@@ -1585,6 +1600,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       sa.mode = 1;
       if (early) HIP_TRY(bbc::launch_zero_u32(sa.n_early, nq, s));
       HIP_TRY(bbc::launch_pq_scan(sa, s));
+      if (tight) HIP_TRY(bbc::launch_filter_rescan(sa, d_kt, reinterpret_cast<uint32_t*>(A + L.rescan_q), s));
     }
     {
       StageScope st(s, 3);

@@ -79,6 +79,8 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   __shared__ uint32_t s_wred[2][NW];
   __shared__ float fbc[2];
   __shared__ int32_t s_cpred;  // early re-rank: cell of the sample's jp-th smallest key (-1: none)
+  __shared__ int32_t s_cfilt;  // tighter filter: its last cell (-1: none)
+  __shared__ uint32_t s_nfilt; // and the sample keys in cells up to it
 
   const int64_t qi = blockIdx.x;
   const int64_t S = a.n_scanned[qi];
@@ -347,6 +349,34 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
       }
       for (int off = 32; off >= 1; off >>= 1) n_before += __shfl_xor(n_before, off);
       if (lane == 0) s_cpred = jp > 0 ? (int32_t)n_before : -1;
+      // tighter filter for the lists after the sample: the first cell by
+      // which the running count of the sample's keys reaches jf, if it lies
+      // below d_max's cell (its keys are then all below d_max and counted)
+      const bool tight = Ts >= kc && dmax > dmin && !a.keep_all && !a.early && a.filt_fraction > 0.0f &&
+                         a.filt_fraction < 1.0f;
+      const int64_t jf = tight ? (int64_t)ceilf(a.filt_fraction * (float)kc) : 0;
+      int cf = 256;
+      uint32_t ncf = 0;
+      {
+        int64_t run = incl - sum;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          run += h[j];
+          const int e = 4 * lane + j;
+          if (cf == 256 && jf > 0 && run >= jf) {
+            cf = e;
+            ncf = (uint32_t)run;
+          }
+        }
+      }
+      const uint64_t got = __ballot(cf < 256);
+      const int first = got ? __ffsll((unsigned long long)got) - 1 : 0;
+      const int cf0 = __shfl(cf, first);
+      const uint32_t ncf0 = __shfl(ncf, first);
+      if (lane == 0) {
+        s_cfilt = got && cf0 < cmax ? cf0 : -1;
+        s_nfilt = ncf0;
+      }
       if (lane == 0) {
         fbc[0] = dmin;
         fbc[1] = delta;
@@ -362,13 +392,31 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
     bc[5] = 0u;
     s_cpred = -1;
   }
+  if (T <= 0 && threadIdx.x == 0) s_cfilt = -1;
   __syncthreads();
   const uint32_t prune = bc[5];
   for (int e = threadIdx.x; e < 256; e += NT) book->map[e] = cmap[e];
   if (threadIdx.x == 0) {
     book->dmin = fbc[0];
     book->delta = fbc[1];
-    book->dmax_bits = dmax_b;
+    // the scan's bound: the largest image whose cell is at most s_cfilt
+    // (binary search over the images of -inf .. +inf, on which the cell is
+    // monotone), else d_max
+    uint32_t fb = dmax_b, nf = 0u;
+    if (prune && s_cfilt >= 0) {
+      uint32_t lo = key_bits(-INFINITY), hi = key_bits(INFINITY);
+      while (hi - lo > 1u) {
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (cell_of(bits_key(mid), fbc[0], fbc[1]) > s_cfilt) hi = mid; else lo = mid;
+      }
+      if (lo < dmax_b) {
+        fb = lo;
+        nf = s_nfilt;
+      }
+    }
+    book->dmax_bits = fb;
+    book->dmax_full = dmax_b;
+    book->filt_count = nf;
     book->prune = prune;
     // early re-rank: tau_pred = the bucket of that cell; a key is re-ranked
     // early when its bucket is below tau_pred, i.e. its cell is below the

@@ -62,8 +62,12 @@ size_t probe_select_lds(int nlist);
 struct QueryBook {
   float dmin;
   float delta;
-  uint32_t dmax_bits;  // key image of d_max
-  uint32_t prune;      // 1: keys above d_max are rejected at the scan
+  uint32_t dmax_bits;  // key image of the scan's filter bound (d_max, or the tighter d_f)
+  uint32_t prune;      // 1: keys above the filter bound are rejected at the scan
+  // tighter filter: d_max's image, and the number of sample keys at or below
+  // the bound (filt_count = 0: the bound is d_max itself)
+  uint32_t dmax_full;
+  uint32_t filt_count;
   uint8_t map[256];    // equal-width cell -> bucket
   // early re-rank (Algorithm 4): the predicted threshold bucket and the
   // smallest key image whose bucket reaches it (keys with a smaller image are
@@ -108,6 +112,8 @@ struct PqScanArgs {
   int early; int metric; const float* vectors;   // rows in list-slot order
   float* surv_exact;        // exact key by survivor slot (early survivors only)
   uint32_t* n_early;        // [nq] survivors re-ranked during the scan (atomic adds)
+  // mode 1, generic kernel: only the pairs of queries with rescan_q[q] != 0
+  const uint32_t* rescan_q;
 };
 // Shapes the grouped scan (and so the one-byte tables) supports.
 bool pq_scan_grouped_shape(int bits, int M, int d);
@@ -121,6 +127,12 @@ int64_t pair_slots(int64_t npairs, int nlist);  // sorted_pairs capacity
 // Counting sort of the (query, rank) pairs by (rank >= nsample, list).
 hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s);
 hipError_t launch_pq_scan(const PqScanArgs& a, hipStream_t s);
+// After the filter scan at the tighter bound d_f: a query whose sample keys
+// and later survivors at or below d_f number fewer than K_c has its bound
+// reset to d_max, its later lists' rejected count taken back and its flag
+// set (flags: [nq]); then those queries' later lists are scanned again at
+// d_max (the generic one-pair-per-block kernel, other pairs return at once).
+hipError_t launch_filter_rescan(PqScanArgs a, const int64_t* kc_target, uint32_t* flags, hipStream_t s);
 // words of the pair sorts' per-block count table for nq queries over nbins
 // bins (0: too many bins for it, the sorts then use global atomics)
 int64_t pair_sort_table_words(int64_t nq, int nbins);
@@ -143,6 +155,10 @@ struct CollectArgs {
   int64_t* t_nsample_keys;  // keys in the codebook sample (codebook kernel)
   int early;                // codebook: also the predicted threshold of the early re-rank
   int keep_all;             // codebook: no relaxed-threshold filter (every key survives)
+  // codebook: the lists after the sample are filtered at d_f, the upper edge
+  // of the first cell by which the sample's running count reaches
+  // filt_fraction * K_c (0 or >= 1: at d_max)
+  float filt_fraction;
   int32_t* t_tau_pred;      // trace: the predicted threshold bucket (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);

@@ -851,6 +851,7 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
   if (pv == NO_PAIR) return;
   const int64_t p = pv;
   const int64_t qi = a.sorted_q[it];
+  if (MODE == 1 && a.rescan_q && !a.rescan_q[qi]) return;
   const int j = a.probe_lists[p];
   const float* qv = a.q + qi * a.d;
   const float* cv = a.cent + (int64_t)j * a.d;
@@ -1018,6 +1019,53 @@ hipError_t launch_pair_sort(const PqScanArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(pair_offsets_kernel, dim3(1), dim3(1024), 0, s, a.pair_cnt, nb, a.nlist, pair_group(a),
                      a.pair_split);
   hipLaunchKernelGGL(pair_scatter_kernel, dim3(g), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+// One wave per query: the check of the tighter filter (see launch_filter_rescan).
+__global__ __launch_bounds__(256) void filter_check_kernel(PqScanArgs a, const int64_t* __restrict__ kc_target,
+                                                           uint32_t* __restrict__ flags) {
+  const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (q >= a.nq) return;
+  const int lane = threadIdx.x & 63;
+  QueryBook* book = const_cast<QueryBook*>(a.books) + q;
+  const uint32_t nf = book->filt_count;
+  uint32_t flag = 0u;
+  if (nf > 0u) {
+    const int64_t po = a.probe_off[q], np = a.probe_off[q + 1] - po;
+    uint64_t kept = 0, rej = 0;
+    for (int64_t r = a.nsample_q[q] + lane; r < np; r += 64) {
+      const int j = a.probe_lists[po + r];
+      const uint32_t ns = a.pair_nsurv[po + r];
+      kept += ns;
+      rej += (uint64_t)(a.list_off[j + 1] - a.list_off[j]) - ns;
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+      kept += __shfl_xor(kept, off);
+      rej += __shfl_xor(rej, off);
+    }
+    if ((int64_t)(nf + kept) < kc_target[q]) {
+      flag = 1u;
+      if (lane == 0) {
+        book->dmax_bits = book->dmax_full;
+        book->filt_count = 0u;
+        a.n_rejected[q] -= (uint32_t)rej;
+      }
+    }
+  }
+  if (lane == 0) flags[q] = flag;
+}
+
+hipError_t launch_filter_rescan(PqScanArgs a, const int64_t* kc_target, uint32_t* flags, hipStream_t s) {
+  if (a.nq <= 0 || a.npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(filter_check_kernel, dim3((unsigned)((a.nq + 3) / 4)), dim3(256), 0, s, a, kc_target, flags);
+  a.mode = 1;
+  a.rescan_q = flags;
+  a.early = 0;
+  const int64_t n = pair_slots(a.npairs, a.nlist);  // covers the slots of the second phase
+  const size_t lds = sizeof(float) * ((size_t)a.M * (1 << a.bits) + a.d);
+  if (a.bits == 8) hipLaunchKernelGGL((pq_scan_kernel<1, 8>), dim3((unsigned)n), dim3(256), lds, s, a);
+  else hipLaunchKernelGGL((pq_scan_kernel<1, 4>), dim3((unsigned)n), dim3(256), lds, s, a);
   return hipGetLastError();
 }
 

@@ -86,6 +86,41 @@ def test_final_topk_groups_match_oracle(bbc, lds_cap):
     g.free()
 
 
+@pytest.mark.parametrize("fraction", ["0.6", "0.3", "0.02"])
+def test_tighter_filter_matches_oracle(bbc, fraction):
+    """The lists after the sample filtered at the upper edge of the cell by
+    which the sample's running count reaches fraction * K_c: a query left
+    short of K_c keys at or below that bound is scanned again at d_max (at
+    0.02 nearly every query is).  Estimated keys, codebook, threshold
+    bucket, candidates and results equal the oracle's, for equal and for
+    per-query k and nprobe."""
+    nq = 24
+    w, ix, q = oracle_pq_index("ivfpq_100k_d128", 40_000, 64, 32, 8, nq)
+    print(f"[case] tighter filter fraction={fraction} nq={nq}", flush=True)
+    old = os.environ.get("BBC_FILTER_FRACTION")
+    os.environ["BBC_FILTER_FRACTION"] = fraction
+    try:
+        g = make_gpu_index(bbc, ix)
+    finally:
+        if old is None:
+            os.environ.pop("BBC_FILTER_FRACTION")
+        else:
+            os.environ["BBC_FILTER_FRACTION"] = old
+    rng = np.random.default_rng(11)
+    kk = rng.integers(50, 3000, nq).astype(np.int32)
+    npb = rng.integers(4, 33, nq).astype(np.int32)
+    for k, nprobe in ((1500, 24), (kk, npb)):
+        tr = g.search_traced(q, k, nprobe, ratio=2.0, buckets=256, nsample=3)
+        exp = expected_steps(ix, q, k, nprobe, 2.0, 256, 3)
+        check_trace(tr, exp, 256)
+        got = g.search(q, k, nprobe, ratio=2.0)
+        ref = oracle.search_pq(ix, q, np.broadcast_to(np.asarray(k, np.int64), (nq,)),
+                               np.broadcast_to(np.asarray(nprobe, np.int64), (nq,)), 2.0)
+        np.testing.assert_array_equal(got[0], ref["ids"])
+        np.testing.assert_array_equal(got[1], ref["dists"])
+    g.free()
+
+
 @pytest.mark.parametrize("sort", ["1", "0"])
 def test_pair_sort_forms_match_oracle(bbc, sort):
     """The (query, rank) pairs sorted by list with per-block LDS histograms
