@@ -24,6 +24,17 @@
  *    it passes; the library copies what it keeps and holds no caller pointer
  *    after a call returns.
  *  - Floating-point inputs must be finite (BBC_EINVAL otherwise).
+ *  - Environment switches, read when an index is made (bbc_index_*), select
+ *    kernel forms for tuning and tests; unless noted, results are the same
+ *    bit for bit under every setting: BBC_SCAN_VARIANT (PQ scan block
+ *    shape 0..4), BBC_PAIR_SORT (0: pair sorts with device-wide atomics),
+ *    BBC_RERANK_FORM (1: per-query PQ re-rank), BBC_RERANK_SORT_BINS,
+ *    BBC_RERANK_RUN_LIST (0: tile re-rank runs found by binary search),
+ *    BBC_COLLECT_BCAP, BBC_FINAL_LDS_CAP, BBC_FILTER_FRACTION (tighter
+ *    filter of the lists after the codebook sample, with a rescan),
+ *    BBC_WALK_FORM, BBC_WALK_PRESORT, BBC_WALK_QCAP, BBC_WALK_ALPHA,
+ *    BBC_SCAN_BY_LIST, BBC_RQ_SCAN_1D (RaBitQ forms).  Out-of-range values
+ *    are ignored.
  *  - One index may be searched from several threads and on several streams
  *    at once.  The host side of each call is serialised per index; searches
  *    without a caller workspace share the index's device workspace, and each
