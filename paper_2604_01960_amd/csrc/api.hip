@@ -806,7 +806,7 @@ namespace {
 
 struct Layout {
   // offsets into the arena
-  size_t nsample_q, pair_cnt, pair_split, bs_table, rescan_q, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
+  size_t nsample_q, pair_cnt, pair_split, bs_table, rescan_q, sminmax, sorted_pairs, sorted_q, sample_keys, surv_key, surv_pos, pair_nsurv, surv_total, surv_bucket, n_rejected, books;
   size_t q, meta, dprime, probe_lists, probe_keys, rank_off, n_scanned, n_recheck, keys, cand_pos,
       cand_packed, n_cand, out_ids, out_dists, out_counts, t_dmin, t_delta, t_map, t_tau, t_s, t_counts, t_nsk,
       t_nb, qorder, rt_sorted, rt_bins, rt_ptb, rt_lcnt, rt_lpairs;
@@ -1421,6 +1421,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   const bool tight = bucket && !p->early_rerank && !p->lut_u8 && !p->keep_all_keys && ix->filt_fraction > 0.0f &&
                      ix->filt_fraction < 1.0f;
   L.rescan_q = tight ? pl.add(4 * nq) : 0;
+  L.sminmax = bucket ? pl.add(8 * nq) : 0;  // the sample's smallest and largest key image
   L.cand_pos = pl.add(4 * ncand);
   L.cand_packed = pl.add(8 * ncand);
   L.n_cand = pl.add(8 * nq);
@@ -1580,6 +1581,12 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ca.early = early;
   ca.keep_all = p->keep_all_keys != 0;
   ca.filt_fraction = tight ? ix->filt_fraction : 0.0f;
+  if (bucket) {
+    sa.smin = reinterpret_cast<uint32_t*>(A + L.sminmax);
+    sa.smax = sa.smin + nq;
+    ca.smin = sa.smin;
+    ca.smax = sa.smax;
+  }
   ca.t_tau_pred = early ? reinterpret_cast<int32_t*>(A + L.t_tpred) : nullptr;
 
   // scan of the sample lists, codebook, scan of the rest through the filter,
@@ -1589,6 +1596,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
     HIP_TRY(bbc::launch_pair_sort(sa, s));
     sa.mode = 0;
     HIP_TRY(bbc::launch_pq_scan(sa, s));
+    sa.smin = sa.smax = nullptr;  // the filter scan keeps no extremes
   }
   if (bucket) {
     {

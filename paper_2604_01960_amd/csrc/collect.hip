@@ -184,28 +184,34 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   bool filtered = false;
   if (threadIdx.x == 0) { bc[6] = 0; bc[7] = 0; }
   if (T > 0) {
-    // smallest and largest image of the sample
+    // smallest and largest image of the sample (kept by the sample scan when
+    // it has them: one pass less over the sample)
     uint32_t mn = 0xffffffffu, mx = 0u;
-    each([&](int64_t, bool valid, uint32_t v) {
-      if (valid) {
-        mn = min(mn, v);
-        mx = max(mx, v);
+    if (a.smin) {
+      mn = a.smin[qi];
+      mx = a.smax[qi];
+    } else {
+      each([&](int64_t, bool valid, uint32_t v) {
+        if (valid) {
+          mn = min(mn, v);
+          mx = max(mx, v);
+        }
+      });
+      for (int off = 32; off >= 1; off >>= 1) {
+        mn = min(mn, __shfl_xor(mn, off));
+        mx = max(mx, __shfl_xor(mx, off));
       }
-    });
-    for (int off = 32; off >= 1; off >>= 1) {
-      mn = min(mn, __shfl_xor(mn, off));
-      mx = max(mx, __shfl_xor(mx, off));
-    }
-    if (lane == 0) {
-      s_wred[0][wv] = mn;
-      s_wred[1][wv] = mx;
-    }
-    __syncthreads();
-    mn = 0xffffffffu;
-    mx = 0u;
-    for (int w = 0; w < NW; ++w) {
-      mn = min(mn, s_wred[0][w]);
-      mx = max(mx, s_wred[1][w]);
+      if (lane == 0) {
+        s_wred[0][wv] = mn;
+        s_wred[1][wv] = mx;
+      }
+      __syncthreads();
+      mn = 0xffffffffu;
+      mx = 0u;
+      for (int w = 0; w < NW; ++w) {
+        mn = min(mn, s_wred[0][w]);
+        mx = max(mx, s_wred[1][w]);
+      }
     }
     if (threadIdx.x == 0) bc[4] = mn;
     __syncthreads();

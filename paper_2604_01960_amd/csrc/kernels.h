@@ -112,6 +112,9 @@ struct PqScanArgs {
   int early; int metric; const float* vectors;   // rows in list-slot order
   float* surv_exact;        // exact key by survivor slot (early survivors only)
   uint32_t* n_early;        // [nq] survivors re-ranked during the scan (atomic adds)
+  // mode 0: the smallest and largest key image of each query's sample
+  // (atomic min / max; launch_pq_scan sets them to +inf / 0 first); NULL: not kept
+  uint32_t* smin; uint32_t* smax;
   // mode 1, generic kernel: only the pairs of queries with rescan_q[q] != 0
   const uint32_t* rescan_q;
 };
@@ -159,6 +162,9 @@ struct CollectArgs {
   // of the first cell by which the sample's running count reaches
   // filt_fraction * K_c (0 or >= 1: at d_max)
   float filt_fraction;
+  // codebook: the sample's smallest and largest key images from the sample
+  // scan (NULL: the codebook finds them itself)
+  const uint32_t* smin; const uint32_t* smax;
   int32_t* t_tau_pred;      // trace: the predicted threshold bucket (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);

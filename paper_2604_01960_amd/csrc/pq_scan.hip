@@ -186,6 +186,28 @@ struct BlockCompactor {
   }
 };
 
+// Smallest and largest value over the 64 lanes of a wave, in every lane:
+// lanes l and l ^ 32, l ^ 16 by lane swaps, then rotations by 8 and 4 within
+// rows and the two quad steps, all without LDS.
+__device__ __forceinline__ void wave_minmax(uint32_t& mn, uint32_t& mx) {
+  auto s = __builtin_amdgcn_permlane32_swap(mn, mn, false, false);
+  mn = min((uint32_t)s[0], (uint32_t)s[1]);
+  s = __builtin_amdgcn_permlane32_swap(mx, mx, false, false);
+  mx = max((uint32_t)s[0], (uint32_t)s[1]);
+  s = __builtin_amdgcn_permlane16_swap(mn, mn, false, false);
+  mn = min((uint32_t)s[0], (uint32_t)s[1]);
+  s = __builtin_amdgcn_permlane16_swap(mx, mx, false, false);
+  mx = max((uint32_t)s[0], (uint32_t)s[1]);
+  mn = min(mn, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mn, 0x128, 0xf, 0xf, false));  // row_ror:8
+  mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x128, 0xf, 0xf, false));
+  mn = min(mn, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mn, 0x124, 0xf, 0xf, false));  // row_ror:4
+  mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x124, 0xf, 0xf, false));
+  mn = min(mn, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mn, 0x4e, 0xf, 0xf, false));   // quad [2,3,0,1]
+  mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0x4e, 0xf, 0xf, false));
+  mn = min(mn, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mn, 0xb1, 0xf, 0xf, false));   // quad [1,0,3,2]
+  mx = max(mx, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)mx, 0xb1, 0xf, 0xf, false));
+}
+
 // Per-query output of one scanned pair.  Phase 0 (sample lists) writes every
 // key by slot; phase 1 keeps the keys at or below the query's relaxed
 // threshold (all keys when the query does not reject) and writes them,
@@ -287,6 +309,7 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
   __shared__ float u8_wspan[U8 ? NW : 1][G];  // per wave: largest range seen
   __shared__ float u8_par[3][G];              // per query: base, delta, 1 / delta
   __shared__ uint32_t s_early[EARLY ? G : 1];  // per query of the group: items re-ranked early
+  __shared__ uint32_t s_kmm[2][MODE == 0 ? NT / 64 : 1][G];  // sample scan: per wave, smallest and largest key image
   static_assert(!EARLY || (MODE == 1 && D <= 128 && D % 4 == 0), "early re-rank: filter scan, rows of <= 32 chunks");
   static_assert(SL == 1 || (!U8 && !EARLY && BITS == 8 && (M / SL) % 16 == 0 && NENT % (SL * NT) == 0),
                 "sliced tables: float rows, 8-bit codes, whole 16-byte code words and owned entries per slice");
@@ -394,6 +417,14 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     // entries, so comparing them with d_max as floats orders them as their
     // images do (+inf: keep all; a negative d_max keeps none)
     float dmaxf[G];
+    // mode 0: this thread's smallest and largest key per pair (keys are
+    // sums of non-negative entries, so they order as their images do)
+    float kmn[G], kmx[G];
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+      kmn[g] = __builtin_inff();
+      kmx[g] = 0.0f;
+    }
     const uint32_t cur_pp = f_pp;
     const int64_t cur_qq = f_qq, cur_tr = f_tr + f_ro;
 #pragma unroll
@@ -742,7 +773,11 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
         for (int o = 0; o < O; ++o)
 #pragma unroll
           for (int g = 0; g < G; ++g)
-            if (valid[g] && active[o]) a.sample_keys[ooff[g] + base + o * NT + threadIdx.x] = acc[o][g];
+            if (valid[g] && active[o]) {
+              a.sample_keys[ooff[g] + base + o * NT + threadIdx.x] = acc[o][g];
+              kmn[g] = fminf(kmn[g], acc[o][g]);
+              kmx[g] = fmaxf(kmx[g], acc[o][g]);
+            }
       }
       if (MODE == 1) {
         bool keep[O * G];
@@ -819,6 +854,42 @@ __global__ __launch_bounds__(NT, BPC * NT / 256) void pq_scan_grouped(PqScanArgs
     for (int g = 0; g < G; ++g) {  // converged: every lane active
       pg[g] = lane_value(cur_pp, g);
       qgs[g] = lane_value(cur_qq, g);
+    }
+    if (MODE == 0 && a.smin) {
+      // per wave, then across the block's waves, then one atomic per query
+      // and group (device-wide atomics per wave cost more than the scan's
+      // last barrier)
+      const int wv = threadIdx.x >> 6;
+#pragma unroll
+      for (int g = 0; g < G; ++g) {
+        uint32_t mn = key_bits(kmn[g]), mx = key_bits(kmx[g]);
+        wave_minmax(mn, mx);
+        if (lane == 0) {
+          s_kmm[0][wv][g] = mn;
+          s_kmm[1][wv][g] = mx;
+        }
+      }
+      __syncthreads();
+      if (threadIdx.x < G) {
+        const int g = threadIdx.x;
+        uint32_t mn = 0xffffffffu, mx = 0u;
+        for (int w = 0; w < NT / 64; ++w) {
+          mn = min(mn, s_kmm[0][w][g]);
+          mx = max(mx, s_kmm[1][w][g]);
+        }
+        bool vg = false;
+        int64_t qg = 0;
+#pragma unroll
+        for (int h = 0; h < G; ++h)
+          if (h == g) {
+            vg = valid[h];
+            qg = qgs[h];
+          }
+        if (vg && mn <= mx) {
+          atomicMin(a.smin + qg, mn);
+          atomicMax(a.smax + qg, mx);
+        }
+      }
     }
     if (MODE == 1 && threadIdx.x == 0) {
 #pragma unroll
@@ -906,6 +977,14 @@ __global__ __launch_bounds__(256) void pq_scan_kernel(PqScanArgs a) {
     if (active && out.trace_out) out.trace_out[i] = key;
     if (MODE == 0) {
       if (active) out.sample_out[i] = key;
+      if (a.smin) {
+        uint32_t mn = active ? key_bits(key) : 0xffffffffu, mx = active ? key_bits(key) : 0u;
+        wave_minmax(mn, mx);
+        if ((threadIdx.x & 63) == 0 && mn <= mx) {
+          atomicMin(a.smin + qi, mn);
+          atomicMax(a.smax + qi, mx);
+        }
+      }
     } else {
       bool keep[1] = {active && out.keep(key)};
       uint32_t slot[1];
@@ -1071,6 +1150,11 @@ hipError_t launch_filter_rescan(PqScanArgs a, const int64_t* kc_target, uint32_t
 
 hipError_t launch_pq_scan(const PqScanArgs& a, hipStream_t s) {
   if (a.npairs <= 0) return hipSuccess;
+  if (a.mode == 0 && a.smin) {
+    const unsigned g = (unsigned)std::min<int64_t>((a.nq + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(g), dim3(256), 0, s, a.smin, a.nq, 0xffffffffu);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(g), dim3(256), 0, s, a.smax, a.nq, 0u);
+  }
   if (try_grouped<8, 32, 4>(a, s) || try_grouped<8, 16, 8>(a, s) || try_grouped<4, 48, 2>(a, s) ||
       try_grouped<4, 32, 4>(a, s))
     return hipGetLastError();
