@@ -903,6 +903,10 @@ void final_groups(int64_t nq, const int32_t* k, const std::vector<int64_t>& cap_
       g.max_cnt = std::max(g.max_cnt, std::min<int64_t>(k[i], cap_of[(size_t)i]));
     }
     g.n = at - g.beg;
+    // largest candidate sets first, so that the launch does not end on a
+    // few long blocks while the other CUs idle
+    std::stable_sort(fg.order.begin() + g.beg, fg.order.begin() + at,
+                     [&](int32_t x, int32_t y) { return cap_of[(size_t)x] > cap_of[(size_t)y]; });
     if (g.n) fg.groups.push_back(g);
   }
 }
