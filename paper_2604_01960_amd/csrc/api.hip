@@ -1382,16 +1382,22 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
 
   // metadata block (one upload): k, nprobe, then the prefix arrays
   FinalGroups fg;
+  // the per-query kernels (codebook, collector, candidate sort) take the
+  // queries largest candidate set first
+  std::vector<int32_t> big_first((size_t)nq);
   {
     std::vector<int64_t> cap_of((size_t)nq);
     for (int64_t i = 0; i < nq; ++i) cap_of[(size_t)i] = cand_off[i + 1] - cand_off[i];
     final_groups(nq, k, cap_of, ix->num_cu, fg);
+    for (int64_t i = 0; i < nq; ++i) big_first[(size_t)i] = (int32_t)i;
+    std::stable_sort(big_first.begin(), big_first.end(),
+                     [&](int32_t x, int32_t y) { return cap_of[(size_t)x] > cap_of[(size_t)y]; });
   }
   Plan mp;
   size_t m_k = mp.add(4 * nq), m_np = mp.add(4 * nq), m_po = mp.add(8 * (nq + 1)), m_ko = mp.add(8 * (nq + 1)),
          m_kt = mp.add(8 * nq), m_co = mp.add(8 * (nq + 1)), m_oo = mp.add(8 * (nq + 1)),
          m_so = mp.add(8 * (nq + 1)), m_vo = mp.add(8 * (nq + 1)), m_bo = mp.add(8 * (nq + 1)),
-         m_fq = mp.add(4 * nq);
+         m_fq = mp.add(4 * nq), m_bq = mp.add(4 * nq);
   Plan pl;
   Layout L{};
   L.meta = pl.add(mp.total);
@@ -1486,6 +1492,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   std::memcpy(H + m_vo, surv_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_bo, bin_off.data(), 8 * (nq + 1));
   std::memcpy(H + m_fq, fg.order.data(), 4 * nq);
+  std::memcpy(H + m_bq, big_first.data(), 4 * nq);
   char* M = A + L.meta;
   if (ctx && ctx->capture) {
     HIP_TRY(hipMemcpy(M, H, mp.total, hipMemcpyHostToDevice));
@@ -1585,6 +1592,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
   ca.early = early;
   ca.keep_all = p->keep_all_keys != 0;
   ca.filt_fraction = tight ? ix->filt_fraction : 0.0f;
+  ca.qorder = reinterpret_cast<const int32_t*>(M + m_bq);
   if (bucket) {
     sa.smin = reinterpret_cast<uint32_t*>(A + L.sminmax);
     sa.smax = sa.smin + nq;
@@ -1655,6 +1663,7 @@ int32_t run_search(bbc_index* ix, const float* queries, int64_t nq, const int32_
       ta.cand_pos = ca.cand_pos; ta.pos_off = d_co; ta.n_cand = ca.n_cand;
       ta.cand_off = d_co; ta.cand_packed = ra.cand_packed;
       ta.npairs = npairs; ta.max_np = max_np; ta.tshift = rt_shift; ta.max_bins = rt_bins;
+      ta.qorder = reinterpret_cast<const int32_t*>(M + m_bq);
       ta.sorted_pos = reinterpret_cast<uint32_t*>(A + L.rt_sorted);
       ta.pair_tb = reinterpret_cast<uint32_t*>(A + L.rt_ptb);
       ta.bin_off = d_bo;

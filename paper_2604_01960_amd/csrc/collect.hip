@@ -82,7 +82,7 @@ __global__ __launch_bounds__(1024, R == 0 ? 8 : 1) void codebook_kernel(CollectA
   __shared__ int32_t s_cfilt;  // tighter filter: its last cell (-1: none)
   __shared__ uint32_t s_nfilt; // and the sample keys in cells up to it
 
-  const int64_t qi = blockIdx.x;
+  const int64_t qi = a.qorder ? (int64_t)a.qorder[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t S = a.n_scanned[qi];
   int64_t kc = a.kc_target[qi];
   if (kc > S) kc = S;
@@ -521,7 +521,7 @@ __global__ __launch_bounds__(1024, 8) void collect_bucket_kernel(CollectArgs a) 
   __shared__ __align__(8) uint32_t bc[8];
   __shared__ int64_t s_rem;
 
-  const int64_t qi = blockIdx.x;
+  const int64_t qi = a.qorder ? (int64_t)a.qorder[blockIdx.x] : (int64_t)blockIdx.x;
   const int64_t S = a.n_scanned[qi];
   int64_t kc = a.kc_target[qi];
   if (kc > S) kc = S;

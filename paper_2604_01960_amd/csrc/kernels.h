@@ -165,6 +165,10 @@ struct CollectArgs {
   // codebook: the sample's smallest and largest key images from the sample
   // scan (NULL: the codebook finds them itself)
   const uint32_t* smin; const uint32_t* smax;
+  // codebook and collector: query of each block (NULL: the block index),
+  // largest candidate sets first so that a launch does not end on a few
+  // long blocks
+  const int32_t* qorder;
   int32_t* t_tau_pred;      // trace: the predicted threshold bucket (codebook kernel)
 };
 hipError_t launch_codebook(const CollectArgs& a, hipStream_t s);
@@ -226,6 +230,7 @@ struct TileRerankArgs {
   int pairs_ready;          // lcnt and lpairs already filled (launch_tile_pairs)
   uint32_t* bs_table;       // pair sort's per-block counts (bs_table_words(nq, nlist)); NULL: global atomics
   int no_run_list;          // tile re-rank: find each run's pair by binary search even when the runs fit the list
+  const int32_t* qorder;    // candidate sort: query of each block (NULL: the block index)
 };
 // the (query, rank) pairs grouped by list into whole groups: lcnt, lpairs
 hipError_t launch_tile_pairs(const TileRerankArgs& a, hipStream_t s);

@@ -275,7 +275,7 @@ __global__ __launch_bounds__(1024) void rt_cand_sort(TileRerankArgs a) {
   extern __shared__ __align__(16) uint32_t sm[];
   __shared__ uint32_t s_w[16];
   __shared__ uint32_t s_tot, s_nb;
-  const int64_t q = blockIdx.x;
+  const int64_t q = a.qorder ? (int64_t)a.qorder[blockIdx.x] : (int64_t)blockIdx.x;
   const int np = a.nprobe[q];
   const int64_t po = a.probe_off[q], pof = a.pos_off[q];
   const int64_t kc = rt_ncand(a, q);
